@@ -1,0 +1,521 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: numbers the
+paper prints (tests/golden/paper_facts.json), closed forms, brute-force sums,
+invariances, finite differences and exhaustive searches.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import basis as ob
+from oracle import mtp as om
+from oracle import neighbors as onb
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_facts.json")))
+
+
+def _bcc(reps=(2, 2, 2), a=3.3, sigma=0.1, seed=0):
+    base = np.array([[0, 0, 0], [0.5, 0.5, 0.5]])
+    g = np.array([[i, j, k] for i in range(reps[0]) for j in range(reps[1]) for k in range(reps[2])])
+    pos = (g[:, None, :] + base[None]).reshape(-1, 3) * a
+    pos = pos + np.random.default_rng(seed).normal(0, sigma, pos.shape)
+    return pos, np.diag(np.asarray(reps, float) * a)
+
+
+def _name(bf):
+    parts = []
+    for g in bf.factors:
+        if g.n == 1:
+            parts.append("M%d%d" % g.labels[0])
+        elif g.n == 2 and g.edges == (1,):
+            parts.append("M%d%d.M%d%d" % (g.labels[0] + g.labels[1]))
+        else:
+            parts.append(str(g))
+    out = []
+    for p, grp in itertools.groupby(parts):
+        k = len(list(grp))
+        out.append(p if k == 1 else f"{p}^{k}")
+    return "*".join(out)
+
+
+# ---------------------------------------------------------------- basis ----
+def test_moment_level_examples():
+    for mu, nu, lev in GOLD["moment_level_examples"]["values"]:
+        assert ob.moment_level(mu, nu) == lev
+
+
+def test_level6_basis_matches_paper():
+    names = sorted(_name(b) for b in ob.basis(6))
+    assert names == sorted(GOLD["level6_basis"]["functions"])
+    assert len(ob.basis(6)) == GOLD["level6_basis"]["n_lin"]
+    assert ob.n_rad(6) == GOLD["level6_basis"]["n_rad"]
+
+
+def test_parameter_counts_match_paper():
+    for lev, n in GOLD["n_params_one_species"]["values"].items():
+        assert ob.n_params(int(lev), 1) == n
+
+
+def test_contraction_examples_are_basis_members():
+    for ex in GOLD["contraction_examples"]["graphs"]:
+        labels = tuple(tuple(l) for l in ex["labels"])
+        lev = sum(ob.moment_level(*l) for l in labels)
+        found = [g for g in ob.connected_graphs(lev) if g.labels == labels]
+        want = sorted((p, q, m) for p, q, m in ex["edges"])
+        assert any(sorted(g.edge_list()) == want for g in found), ex
+        # and it is absent one level below
+        assert not any(g.labels == labels for g in ob.connected_graphs(lev - 1))
+
+
+def test_basis_closed_under_isomorphism_dedup():
+    # a graph and a relabelled copy must not both occur
+    for g in ob.connected_graphs(16):
+        assert g.edges == ob._canonical(g.labels, g.edges)
+    keys = [b.key() for b in ob.basis(16)]
+    assert len(keys) == len(set(keys))
+
+
+# --------------------------------------------------------------- radial ----
+def test_chebyshev_is_cos_k_t():
+    t = torch.linspace(0.0, math.pi, 37, dtype=torch.float64)
+    T = om.chebyshev(torch.cos(t), 8)
+    for k in range(8):
+        assert torch.allclose(T[:, k], torch.cos(k * t), atol=1e-13)
+
+
+def test_radial_vanishes_smoothly_at_cutoff():
+    pot = om.Potential(8, 2, 2.0, 5.0)
+    c = torch.as_tensor(np.random.default_rng(1).normal(size=(pot.n_rad, 2, 2, 8)))
+    r = torch.tensor([5.0, 5.0 - 1e-6], dtype=torch.float64)
+    f = om.radial_functions(pot, c, r, torch.tensor([0, 1]), torch.tensor([1, 1]))
+    assert torch.all(f[0] == 0)
+    assert torch.all(f[1].abs() < 1e-10)        # quadratic zero: f ~ (R_cut - r)^2
+
+
+def test_radial_at_rmin_is_plain_sum():
+    # at r = R_min, x = -1 and T_k(-1) = (-1)^k, so f = (R_cut - R_min)^2 sum_b c_b (-1)^(b-1)
+    pot = om.Potential(8, 1, 2.0, 5.0)
+    c = torch.as_tensor(np.random.default_rng(2).normal(size=(pot.n_rad, 1, 1, 8)))
+    f = om.radial_functions(pot, c, torch.tensor([2.0], dtype=torch.float64), torch.tensor([0]), torch.tensor([0]))
+    sign = torch.tensor([(-1.0) ** k for k in range(8)], dtype=torch.float64)
+    want = 9.0 * (c[:, 0, 0, :] * sign).sum(-1)
+    assert torch.allclose(f[0], want, rtol=1e-13)
+
+
+# --------------------------------------------------------- contractions ----
+def _pair_sum_value(g, f, R):
+    """val(G) = sum over one neighbor per node of prod f * prod (r_p . r_q)^e."""
+    n = len(R)
+    total = 0.0
+    for js in itertools.product(range(n), repeat=g.n):
+        v = 1.0
+        for p, (mu, _) in enumerate(g.labels):
+            v *= f[js[p], mu]
+        for p, q, m in g.edge_list():
+            v *= float(np.dot(R[js[p]], R[js[q]])) ** m
+        total += v
+    return total
+
+
+@pytest.mark.parametrize("level", [16])
+def test_graph_values_equal_brute_force_pair_sums(level):
+    rng = np.random.default_rng(3)
+    R = rng.normal(size=(3, 3))
+    f = rng.normal(size=(3, 4))
+    Rt = torch.as_tensor(R)
+    ft = torch.as_tensor(f)
+    M = {}
+    for mu in range(4):
+        M[(mu, 0)] = ft[:, mu].sum()[None]
+        M[(mu, 1)] = torch.einsum("p,pa->a", ft[:, mu], Rt)[None]
+        M[(mu, 2)] = torch.einsum("p,pa,pb->ab", ft[:, mu], Rt, Rt)[None]
+        M[(mu, 3)] = torch.einsum("p,pa,pb,pc->abc", ft[:, mu], Rt, Rt, Rt)[None]
+    for g in ob.connected_graphs(level):
+        got = float(om.graph_value(g, M)[0])
+        want = _pair_sum_value(g, f, R)
+        assert abs(got - want) <= 1e-11 * max(1.0, abs(want)), str(g)
+
+
+def test_closed_forms():
+    rng = np.random.default_rng(4)
+    R = torch.as_tensor(rng.normal(size=(5, 3)))
+    f = torch.as_tensor(rng.normal(size=5))
+    M01 = (f[:, None] * R).sum(0)[None]
+    M02 = torch.einsum("p,pa,pb->ab", f, R, R)[None]
+    g11 = [g for g in ob.connected_graphs(6) if g.labels == ((0, 1), (0, 1))][0]
+    g22 = [g for g in ob.connected_graphs(8) if g.labels == ((0, 2), (0, 2))][0]
+    g222 = [g for g in ob.connected_graphs(12) if g.labels == ((0, 2),) * 3][0]
+    M = {(0, 1): M01, (0, 2): M02}
+    assert torch.allclose(om.graph_value(g11, M), (M01 ** 2).sum(), rtol=1e-13)
+    G = R @ R.T
+    assert torch.allclose(om.graph_value(g22, M), (f[:, None] * f[None] * G ** 2).sum(), rtol=1e-12)
+    assert torch.allclose(om.graph_value(g222, M), torch.trace(M02[0] @ M02[0] @ M02[0]), rtol=1e-12)
+
+
+# -------------------------------------------------------------- energy -----
+def _nbrs(pos, cell, pbc=(1, 1, 1), rc=5.0):
+    return onb.neighbors(pos, cell, pbc, rc)
+
+
+def test_level2_is_pair_potential():
+    pos, cell = _bcc()
+    pot = om.Potential(2, 1, 2.0, 5.0)
+    theta = np.random.default_rng(5).normal(0, 0.1, pot.n_theta)
+    pairs = _nbrs(pos, cell)
+    E, F, S, V = om.energy_forces_stress(pot, theta, pos, np.zeros(len(pos), int), cell, pairs)
+    xi0, xi, c = theta[0], theta[1], theta[2:]
+    want = 0.0
+    for i in range(len(pos)):
+        vi = xi0
+        for p in np.where(pairs.i == i)[0]:
+            r = np.linalg.norm(pos[pairs.j[p]] + pairs.shift[p] @ cell - pos[i])
+            x = (2 * r - 7.0) / 3.0
+            T = [math.cos(k * math.acos(x)) if abs(x) <= 1 else math.cosh(k * math.acosh(abs(x))) * (np.sign(x) ** k)
+                 for k in range(8)]
+            vi += xi * sum(c[b] * T[b] for b in range(8)) * (5.0 - r) ** 2
+        want += vi
+    assert abs(E - want) <= 1e-11 * abs(want)
+
+
+def test_level4_is_quadratic_embedding():
+    pos, cell = _bcc(sigma=0.05)
+    pot = om.Potential(4, 1, 2.0, 5.0)
+    theta = np.random.default_rng(6).normal(0, 0.1, pot.n_theta)
+    pairs = _nbrs(pos, cell)
+    E, F, S, V = om.energy_forces_stress(pot, theta, pos, np.zeros(len(pos), int), cell, pairs)
+    c = torch.as_tensor(theta[3:]).reshape(1, 1, 1, 8)
+    rv = torch.as_tensor(pos[pairs.j] + pairs.shift @ cell - pos[pairs.i])
+    f = om.radial_functions(pot, c, torch.linalg.norm(rv, dim=1), torch.zeros(len(rv), dtype=torch.long),
+                            torch.zeros(len(rv), dtype=torch.long))[:, 0].numpy()
+    rho = np.bincount(pairs.i, weights=f, minlength=len(pos))
+    want = theta[0] + theta[1] * rho + theta[2] * rho ** 2
+    assert np.allclose(V, want, rtol=1e-12, atol=1e-12)
+
+
+def _setup(level=8, n_types=2, seed=7, reps=(2, 2, 2), sigma=0.1):
+    pos, cell = _bcc(reps, sigma=sigma, seed=seed)
+    types = np.random.default_rng(seed + 1).integers(0, n_types, len(pos))
+    pot = om.Potential(level, n_types, 2.0, 5.0)
+    theta = np.random.default_rng(seed + 2).normal(0, 0.1, pot.n_theta)
+    return pot, theta, pos, types, cell
+
+
+def _random_rotation(seed):
+    q, r = np.linalg.qr(np.random.default_rng(seed).normal(size=(3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def test_invariances_translation_rotation_permutation():
+    pot, theta, pos, types, cell = _setup(level=12)
+    E0, F0, S0, V0 = om.energy_forces_stress(pot, theta, pos, types, cell, _nbrs(pos, cell))
+    # translation
+    p1 = pos + np.array([0.37, -1.2, 2.5])
+    E1, F1, _, V1 = om.energy_forces_stress(pot, theta, p1, types, cell, _nbrs(p1, cell))
+    assert abs(E1 - E0) <= 1e-10 * abs(E0) and np.allclose(F1, F0, atol=1e-9 * np.abs(F0).max())
+    # rotation of positions and cell together
+    Q = _random_rotation(11)
+    p2, c2 = pos @ Q.T, cell @ Q.T
+    E2, F2, S2, _ = om.energy_forces_stress(pot, theta, p2, types, c2, _nbrs(p2, c2))
+    assert abs(E2 - E0) <= 1e-10 * abs(E0)
+    assert np.allclose(F2, F0 @ Q.T, atol=1e-9 * np.abs(F0).max())
+    assert np.allclose(S2, Q @ S0 @ Q.T, atol=1e-9 * np.abs(S0).max())
+    # permutation of atoms
+    perm = np.random.default_rng(12).permutation(len(pos))
+    p3, t3 = pos[perm], types[perm]
+    E3, F3, _, V3 = om.energy_forces_stress(pot, theta, p3, t3, cell, _nbrs(p3, cell))
+    assert abs(E3 - E0) <= 1e-10 * abs(E0)
+    assert np.allclose(F3, F0[perm], atol=1e-9 * np.abs(F0).max())
+    assert np.allclose(V3, V0[perm], rtol=1e-10, atol=1e-10 * np.abs(V0).max())
+
+
+def test_additivity_of_separated_clusters():
+    pot = om.Potential(12, 1, 2.0, 5.0)
+    theta = np.random.default_rng(13).normal(0, 0.1, pot.n_theta)
+    rng = np.random.default_rng(14)
+    a = rng.normal(0, 1.5, (5, 3))
+    b = rng.normal(0, 1.5, (4, 3)) + np.array([40.0, 0, 0])
+    cell = np.eye(3) * 100.0
+    pbc = (0, 0, 0)
+    t = np.zeros(9, int)
+    Ea = om.energy_forces_stress(pot, theta, a, t[:5], cell, onb.neighbors(a, cell, pbc, 5.0))[0]
+    Eb = om.energy_forces_stress(pot, theta, b, t[:4], cell, onb.neighbors(b, cell, pbc, 5.0))[0]
+    ab = np.vstack([a, b])
+    Eab = om.energy_forces_stress(pot, theta, ab, t, cell, onb.neighbors(ab, cell, pbc, 5.0))[0]
+    assert abs(Eab - (Ea + Eb)) <= 1e-12 * (abs(Ea) + abs(Eb))
+
+
+# ------------------------------------------------------ forces / stress ----
+def test_forces_and_stress_match_finite_differences():
+    pot, theta, pos, types, cell = _setup(level=12, sigma=0.12)
+    pairs = _nbrs(pos, cell)
+    E, F, S, _ = om.energy_forces_stress(pot, theta, pos, types, cell, pairs)
+    assert np.abs(F.sum(0)).max() <= 1e-10 * np.abs(F).max()
+    assert np.allclose(S, S.T, atol=1e-10 * np.abs(S).max())
+    h = 1e-5
+    for (i, k) in [(0, 0), (3, 1), (7, 2), (12, 0)]:
+        # the pair set does not change for this small step (no pair sits at R_cut)
+        pp, pm = pos.copy(), pos.copy()
+        pp[i, k] += h
+        pm[i, k] -= h
+        Ep = om.energy_forces_stress(pot, theta, pp, types, cell, pairs)[0]
+        Em = om.energy_forces_stress(pot, theta, pm, types, cell, pairs)[0]
+        fd = -(Ep - Em) / (2 * h)
+        assert abs(fd - F[i, k]) <= 1e-7 * np.abs(F).max(), (i, k, fd, F[i, k])
+    hs = 1e-6
+    for (a, b) in [(0, 0), (0, 1), (2, 1), (2, 2)]:
+        D = np.zeros((3, 3))
+        D[a, b] = hs
+        Ep = om.energy_forces_stress(pot, theta, pos @ (np.eye(3) + D).T, types, cell @ (np.eye(3) + D).T, pairs)[0]
+        Em = om.energy_forces_stress(pot, theta, pos @ (np.eye(3) - D).T, types, cell @ (np.eye(3) - D).T, pairs)[0]
+        fd = -(Ep - Em) / (2 * hs)
+        assert abs(fd - S[a, b]) <= 1e-6 * np.abs(S).max(), (a, b, fd, S[a, b])
+
+
+# -------------------------------------------------------------- b rows -----
+def _n_factors_moments(pot):
+    return np.array([sum(g.n for g in bf.factors) for bf in pot.basis])
+
+
+def test_b_rows_match_finite_differences_and_euler_identity():
+    pot, theta, pos, types, cell = _setup(level=8)
+    pairs = _nbrs(pos, cell)
+    b = om.b_rows(pot, theta, pos, types, cell, pairs)
+    h = 1e-6
+    for p in [0, 1, 2, 5, pot.n_types + pot.n_lin, pot.n_theta - 1]:
+        tp, tm = theta.copy(), theta.copy()
+        tp[p] += h
+        tm[p] -= h
+        Vp = om.energy_forces_stress(pot, tp, pos, types, cell, pairs)[3]
+        Vm = om.energy_forces_stress(pot, tm, pos, types, cell, pairs)[3]
+        assert np.allclose((Vp - Vm) / (2 * h), b[:, p], atol=1e-6 * np.abs(b[:, p]).max() + 1e-9)
+    # Euler: B_alpha is homogeneous of degree P_alpha (number of moment factors) in c
+    _, _, V = om.energy_forces_stress(pot, theta, pos, types, cell, pairs)[1:]
+    lin = om.linear_rows(pot, theta, pos, types, cell, pairs)
+    B = lin[:, pot.n_types:]
+    xi0, xi = theta[:pot.n_types], theta[pot.n_types:pot.n_types + pot.n_lin]
+    want = xi0[types] + B @ ((1 + _n_factors_moments(pot)) * xi)
+    assert np.allclose(b @ theta, want, rtol=1e-11, atol=1e-11 * np.abs(want).max())
+    assert np.allclose(xi0[types] + B @ xi, V, rtol=1e-12, atol=1e-12 * np.abs(V).max())
+
+
+def _null_vectors(pot, theta):
+    """w_{mu mu'}: remix f_mu += t f_mu' (mu' <= mu), compensated by xi."""
+    T, L = pot.n_types, pot.n_lin
+    c = theta[T + L:].reshape(pot.n_rad, -1)
+    out = []
+    for mu in range(pot.n_rad):
+        for mup in range(mu + 1):
+            w = np.zeros(pot.n_theta)
+            w[T + L + mu * c.shape[1]: T + L + (mu + 1) * c.shape[1]] = c[mup]
+            for a, bf in enumerate(pot.basis):
+                # each occurrence of a mu-moment turns into a mu'-moment: the
+                # resulting product is again a basis function, whose xi absorbs it
+                for gi, g in enumerate(bf.factors):
+                    for ni, (m, nu) in enumerate(g.labels):
+                        if m != mu:
+                            continue
+                        labels = list(g.labels)
+                        labels[ni] = (mup, nu)
+                        tgt = _find_basis(pot, bf, gi, ni, mup)
+                        w[T + tgt] -= theta[T + a]
+            out.append(w)
+    return np.array(out)
+
+
+def _find_basis(pot, bf, gi, ni, mup):
+    g = bf.factors[gi]
+    labels = list(g.labels)
+    labels[ni] = (mup, labels[ni][1])
+    # canonicalise the relabelled graph by brute force over all node orders
+    n = g.n
+    mat = np.zeros((n, n), int)
+    for p, q, m in g.edge_list():
+        mat[p, q] = mat[q, p] = m
+    best = None
+    for perm in itertools.permutations(range(n)):
+        lab = tuple(labels[k] for k in perm)
+        if list(lab) != sorted(lab):
+            continue
+        e = tuple(mat[perm[p], perm[q]] for p in range(n) for q in range(p + 1, n))
+        if best is None or e < best[1]:
+            best = (lab, e)
+    newg = ob.Graph(best[0], best[1])
+    factors = list(bf.factors)
+    factors[gi] = newg
+    key = ob.BasisFunction(tuple(sorted(factors, key=ob.Graph.key))).key()
+    keys = [b.key() for b in pot.basis]
+    return keys.index(key)
+
+
+def test_b_rows_null_space_and_rank():
+    pot, theta, pos, types, cell = _setup(level=8, n_types=2, reps=(3, 3, 3))
+    rows = []
+    for seed in range(3):
+        p, _ = _bcc((3, 3, 3), sigma=0.25, seed=100 + seed)
+        rows.append(om.b_rows(pot, theta, p, types, cell, _nbrs(p, cell)))
+    b = np.vstack(rows)
+    W = _null_vectors(pot, theta)
+    assert W.shape[0] == pot.n_rad * (pot.n_rad + 1) // 2
+    assert np.abs(b @ W.T).max() <= 1e-11 * np.abs(b).max() * np.abs(W).max()
+    sv = np.linalg.svd(b / np.abs(b).max(0), compute_uv=False)
+    rank = int((sv > 1e-9 * sv[0]).sum())
+    assert rank == pot.n_theta - W.shape[0]
+    # gauge-fixed columns have full rank
+    keep = om.kept_columns(pot, theta)
+    sv2 = np.linalg.svd(b[:, keep] / np.abs(b[:, keep]).max(0), compute_uv=False)
+    assert sv2[-1] > 1e-9 * sv2[0]
+
+
+# -------------------------------------------------------------- grades -----
+def _active_case(level=8, n_types=1, reps=(3, 3, 3), seed=21):
+    pot, theta, pos, types, cell = _setup(level=level, n_types=n_types, reps=reps, seed=seed)
+    pairs = _nbrs(pos, cell)
+    keep = om.kept_columns(pot, theta)
+    b = om.b_rows(pot, theta, pos, types, cell, pairs)[:, keep]
+    act = om.initial_active_set(b)
+    return pot, theta, pos, types, cell, pairs, keep, b, act
+
+
+def test_gamma_is_one_on_active_rows_and_scale_invariant():
+    pot, theta, pos, types, cell, pairs, keep, b, act = _active_case()
+    A = b[act]
+    g, am, _ = om.grades(A, A)
+    assert np.allclose(g, 1.0, atol=1e-12)
+    assert np.array_equal(am, np.arange(len(act)))
+    D = np.diag(np.random.default_rng(22).uniform(0.1, 10, A.shape[1]))
+    g1, _, _ = om.grades(b, A)
+    g2, _, _ = om.grades(b @ D, A @ D)
+    assert np.allclose(g1, g2, rtol=1e-9)
+
+
+def test_gamma_independent_of_gauge_choice():
+    pot, theta, pos, types, cell = _setup(level=8, n_types=1, reps=(3, 3, 3), seed=23)
+    pairs = _nbrs(pos, cell)
+    full = om.b_rows(pot, theta, pos, types, cell, pairs)
+    keep1 = om.kept_columns(pot, theta)
+    # another valid gauge: drop different columns of each c block
+    T, L = pot.n_types, pot.n_lin
+    c = theta[T + L:].reshape(pot.n_rad, -1)
+    drop2 = []
+    for mu in range(pot.n_rad):
+        cols = list(range(c.shape[1] - 1, -1, -1))[: mu + 1]
+        assert abs(np.linalg.det(c[: mu + 1][:, cols])) > 1e-8
+        drop2 += [T + L + mu * c.shape[1] + k for k in cols]
+    keep2 = [k for k in range(pot.n_theta) if k not in drop2]
+    assert keep1 != keep2
+    act = om.initial_active_set(full[:, keep1])
+    g1, _, _ = om.grades(full[:, keep1], full[act][:, keep1])
+    g2, _, _ = om.grades(full[:, keep2], full[act][:, keep2])
+    assert np.allclose(g1, g2, rtol=1e-7)
+
+
+def test_gamma_rotation_invariant():
+    pot, theta, pos, types, cell, pairs, keep, b, act = _active_case(seed=24)
+    Q = _random_rotation(25)
+    p2, c2 = pos @ Q.T, cell @ Q.T
+    b2 = om.b_rows(pot, theta, p2, types, c2, _nbrs(p2, c2))[:, keep]
+    g1, _, _ = om.grades(b, b[act])
+    g2, _, _ = om.grades(b2, b2[act])
+    assert np.allclose(g1, g2, rtol=1e-8)
+
+
+def test_linear_mode_reproduces_site_energies():
+    # with the active set as training set, V_i = sum_j c_ij V(n_j^act) (linear case)
+    pot, theta, pos, types, cell = _setup(level=8, n_types=2, reps=(3, 3, 3), seed=26)
+    pairs = _nbrs(pos, cell)
+    lin = om.linear_rows(pot, theta, pos, types, cell, pairs)
+    V = om.energy_forces_stress(pot, theta, pos, types, cell, pairs)[3]
+    act = om.initial_active_set(lin)
+    _, _, C = om.grades(lin, lin[act])
+    assert np.allclose(C @ V[act], V, rtol=1e-9, atol=1e-9 * np.abs(V).max())
+
+
+# -------------------------------------------------------------- maxvol -----
+def test_maxvol_det_ratios_and_local_optimality_exhaustive():
+    rng = np.random.default_rng(27)
+    rows = rng.normal(size=(8, 3))
+    A0 = rows[:3]
+    cand = rows[3:]
+    A, cand2, swaps = om.maxvol(A0, cand, threshold=1.0 + 1e-12)
+    d = abs(np.linalg.det(A0))
+    Acur, ccur = A0.copy(), cand.copy()
+    for i, j, g in swaps:
+        Acur[j], ccur[i] = ccur[i].copy(), Acur[j].copy()
+        dn = abs(np.linalg.det(Acur))
+        assert abs(dn / d - g) <= 1e-10 * g
+        d = dn
+    assert np.allclose(A, Acur)
+    # no single swap increases |det A|
+    for i in range(len(cand2)):
+        for j in range(3):
+            B = A.copy()
+            B[j] = cand2[i]
+            assert abs(np.linalg.det(B)) <= abs(np.linalg.det(A)) * (1 + 1e-9)
+    # and the result is within the MaxVol bound of the exhaustive best
+    best = max(abs(np.linalg.det(rows[list(s)])) for s in itertools.combinations(range(8), 3))
+    assert abs(np.linalg.det(A)) >= best / 3 ** 1.5 - 1e-12
+
+
+def test_sherman_morrison_matches_fresh_inverse():
+    rng = np.random.default_rng(28)
+    A = rng.normal(size=(6, 6))
+    r = rng.normal(size=6)
+    Ainv = np.linalg.inv(A)
+    c = r @ Ainv
+    j = int(np.argmax(np.abs(c)))
+    e = np.zeros(6)
+    e[j] = 1
+    upd = Ainv - np.outer(Ainv[:, j], c - e) / c[j]
+    A2 = A.copy()
+    A2[j] = r
+    assert np.allclose(upd, np.linalg.inv(A2), rtol=1e-12, atol=1e-12 * np.abs(upd).max())
+
+
+# ----------------------------------------------------------- neighbors -----
+@pytest.mark.parametrize("case", ["cubic", "triclinic_small", "slab"])
+def test_neighbors_c_matches_python(case):
+    rng = np.random.default_rng(29)
+    if case == "cubic":
+        pos, cell = _bcc((2, 2, 2))
+        pbc = (1, 1, 1)
+    elif case == "triclinic_small":
+        cell = np.array([[3.1, 0, 0], [0.9, 2.9, 0], [0.4, -0.7, 3.3]])
+        pos = rng.random((3, 3)) @ cell + rng.normal(0, 0.5, (3, 3))
+        pbc = (1, 1, 1)
+    else:
+        cell = np.diag([6.0, 6.5, 20.0])
+        pos = rng.random((10, 3)) @ cell
+        pbc = (1, 1, 0)
+    a = onb.neighbors(pos, cell, pbc, 5.0)
+    b = onb.neighbors_py(pos, cell, pbc, 5.0)
+    assert np.array_equal(np.c_[a.i, a.j, a.shift], np.c_[b.i, b.j, b.shift])
+    # symmetry: (i, j, n) present iff (j, i, -n) present
+    s = set(map(tuple, np.c_[a.i, a.j, a.shift]))
+    assert all((j, i, -x, -y, -z) in s for i, j, x, y, z in s)
+
+
+# ------------------------------------------------------------- fitting -----
+def test_loss_gradient_matches_finite_differences():
+    pot, theta, pos, types, cell = _setup(level=8, n_types=2, seed=30)
+    pairs = _nbrs(pos, cell)
+    rng = np.random.default_rng(31)
+    cfgs = [(pos, types, cell, pairs)]
+    tgt = [(rng.normal() * 10, rng.normal(size=pos.shape), rng.normal(size=(3, 3)))]
+    L0, g = om.loss_and_grad(pot, theta, cfgs, tgt, 1.0, 0.01, 0.001)
+    h = 1e-6
+    for p in [0, 1, 4, pot.n_types + pot.n_lin + 3, pot.n_theta - 1]:
+        tp, tm = theta.copy(), theta.copy()
+        tp[p] += h
+        tm[p] -= h
+        fd = (om.loss_and_grad(pot, tp, cfgs, tgt, 1.0, 0.01, 0.001)[0]
+              - om.loss_and_grad(pot, tm, cfgs, tgt, 1.0, 0.01, 0.001)[0]) / (2 * h)
+        assert abs(fd - g[p]) <= 1e-6 * np.abs(g).max(), (p, fd, g[p])
