@@ -1,0 +1,222 @@
+/* mtp.h -- C ABI of the MI355X (gfx950) Moment Tensor Potential library.
+ *
+ * The library evaluates the per-neighborhood hot path of the Moment Tensor
+ * Potential as used by MLIP-3 (Podryabinkin et al., arXiv 2304.13144):
+ *
+ *   neighborhoods n_i            (Sec. II.A, the tuple after eq. 1)
+ *   radial functions f_mu        (eq. 4; Chebyshev polynomials, see below)
+ *   moment tensors M_{mu,nu}     (eq. 3)
+ *   basis functions B_alpha      (Sec. II.A, eqs. 5-6: contractions of moments)
+ *   site / total energy          (eqs. 1-2)
+ *   forces and stress            (the quantities fitted in eq. 7)
+ *   rows b_i = dV(n_i)/dtheta    (Sec. II.D, eq. 10)
+ *   grades gamma_i = max_p |(b_i A^-1)_p|          (Sec. II.D)
+ *   MaxVol swaps into the active set A             (Sec. II.C)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Return value: an mtp_status; MTP_OK (0) on success.  No entry point aborts
+ * or throws across the ABI; on error mtp_last_error() returns a message
+ * (thread-local, valid until the next call on the same thread).  Inputs are
+ * validated before any work is enqueued; outputs are untouched on a
+ * validation error.
+ *
+ * Memory: every array argument is caller-owned DEVICE memory on the model's
+ * device unless the comment says "host".  The library owns only the opaque
+ * handles below and their internal workspaces (allocated on first use at a
+ * given capacity, reused afterwards).
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream).  All work is enqueued on it; nothing synchronises unless the
+ * comment says so.
+ *
+ * Units: Angstrom, eV, eV/Angstrom; stress in eV (not divided by volume).
+ *
+ * Parameter vector theta (FP64, length n_theta):
+ *   [ xi_0 (n_types) | xi_1..xi_Nlin | c (N_rad, n_types, n_types, N_polyn) ]
+ * xi_0 is one constant per species (the parameter counts of Sec. IV need it);
+ * c[mu][z_i][z_j][beta] multiplies T_beta(x) (R_cut - r)^2 with T_beta the
+ * Chebyshev polynomial of degree beta (beta = 0..N_polyn-1) and
+ * x = (2 r - R_min - R_cut) / (R_cut - R_min).
+ */
+#ifndef MTP_H
+#define MTP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MTP_OK = 0,
+    MTP_E_INVAL = -1,       /* bad argument (NULL, size, enum, NaN/Inf input) */
+    MTP_E_IO = -2,          /* model file cannot be read / written */
+    MTP_E_PARSE = -3,       /* model file malformed */
+    MTP_E_OVERLAP = -4,     /* two atoms closer than 1e-6 Angstrom */
+    MTP_E_CAPACITY = -5,    /* a neighborhood has more than max_nbrs atoms */
+    MTP_E_SINGULAR = -6,    /* active-set matrix not invertible */
+    MTP_E_HIP = -7,         /* HIP runtime error */
+    MTP_E_NOMEM = -8,       /* device allocation failed */
+    MTP_E_UNSUPPORTED = -9  /* level / type count not compiled into this build */
+} mtp_status;
+
+typedef enum { MTP_FP64 = 0, MTP_MIXED = 1 } mtp_precision;
+/* MTP_FP64: every step in double precision.
+ * MTP_MIXED: radial functions, moments, contractions, pair gradients and b
+ *   rows in FP32; grade product on MFMA with BF16 split operands and FP32
+ *   accumulation; energy, force and stress sums, A^-1 and MaxVol in FP64. */
+
+typedef enum { MTP_GRADE_FULL = 0, MTP_GRADE_LINEAR = 1 } mtp_grade_mode;
+/* FULL: b_i over all of theta minus N_rad(N_rad+1)/2 gauge columns of the c
+ *   block (the rows are exactly rank deficient by that many directions), so
+ *   m = n_theta - N_rad(N_rad+1)/2.  LINEAR: b_i = (onehot(z_i), B_alpha),
+ *   m = n_types + N_lin. */
+
+typedef struct mtp_model mtp_model; /* theta, basis, A^-1 per mode (device) */
+typedef struct mtp_nbrs mtp_nbrs;   /* neighbor lists of one system (device) */
+
+typedef struct {
+    int32_t level, n_types, n_polyn;
+    int32_t n_lin;          /* number of basis functions B_alpha */
+    int32_t n_rad;          /* number of radial functions f_mu */
+    int32_t n_comp;         /* symmetric moment components per neighborhood */
+    int32_t n_theta;        /* length of theta */
+    int32_t m_full, m_linear;
+    double r_min, r_cut;
+    int32_t has_active_full, has_active_linear;
+} mtp_model_info;
+
+/* A batch of configurations (all pointers device memory). */
+typedef struct {
+    int32_t n_cfg;
+    int64_t n_atoms;
+    const int64_t *cfg_off; /* [n_cfg+1] first atom of each configuration */
+    const double *pos;      /* [n_atoms*3] Cartesian positions */
+    const int32_t *type;    /* [n_atoms] species 0..n_types-1 */
+    const double *cell;     /* [n_cfg*9] row k = cell vector k */
+    const uint8_t *pbc;     /* [n_cfg*3] periodic flags, or NULL = all periodic */
+} mtp_system;
+
+/* --- model ------------------------------------------------------------ */
+
+/* Reads a model file (the library's own text format, written by
+ * mtp_save) and uploads it to `hip_device`.  The file holds level, species
+ * count, R_min, R_cut, N_polyn, theta and optionally the active sets. */
+int mtp_load(const char *path, int hip_device, mtp_model **out);
+
+/* Writes the model (host-side copy of theta and active sets) to `path`. */
+int mtp_save(const mtp_model *m, const char *path);
+
+/* A model with theta = 0 and no active set (level must be compiled in). */
+int mtp_create(int32_t level, int32_t n_types, double r_min, double r_cut, int hip_device, mtp_model **out);
+
+int mtp_free(mtp_model *m);
+int mtp_info(const mtp_model *m, mtp_model_info *info /* host */);
+
+/* Replaces theta (device FP64 [n_theta]); recomputes the FULL-mode gauge
+ * columns from the new c (column-pivoted QR of [c_0;..;c_mu] per mu) and
+ * invalidates the FULL active set (its rows depend on theta).  Synchronises
+ * `stream` (the gauge choice is made on the host). */
+int mtp_set_params(mtp_model *m, const double *theta, void *stream);
+
+/* Columns of theta kept in FULL mode, ascending (host [m_full]). */
+int mtp_kept_columns(const mtp_model *m, int32_t *cols /* host */);
+
+/* Sets the active set of `mode` from its m x m row-major FP64 matrix
+ * (device; rows = b rows of the active neighborhoods in that mode's column
+ * space) and computes A^-1 in FP64 by Gauss-Jordan elimination with partial
+ * pivoting.  Returns MTP_E_SINGULAR (after synchronising `stream`) if a
+ * pivot falls below 1e-300 in magnitude. */
+int mtp_set_active_set(mtp_model *m, mtp_grade_mode mode, const double *A, void *stream);
+
+/* Copies A (rows of the active set) or A^-1 of `mode` to `out` (device m*m). */
+int mtp_get_active_set(const mtp_model *m, mtp_grade_mode mode, double *A_out, double *Ainv_out, void *stream);
+
+/* --- neighborhoods (Sec. II.A) ------------------------------------------ */
+
+int mtp_nbrs_create(mtp_nbrs **out);
+int mtp_nbrs_free(mtp_nbrs *nb);
+
+/* Builds, for every atom i of every configuration, the list of (j, n) with
+ * 0 < |x_j + n.H - x_i| < R_cut (n: integer image shifts, zero along
+ * non-periodic axes).  Cell-list algorithm; lists are grouped by neighbor
+ * species; the order inside a group is deterministic.  Capacity: max_nbrs
+ * entries per atom.  Overflow and overlap are flagged on the device and
+ * reported by mtp_nbrs_status. */
+int mtp_build_neighbors(const mtp_model *m, const mtp_system *s, int32_t max_nbrs, mtp_nbrs *nb, void *stream);
+
+/* Synchronises `stream`; returns MTP_OK, MTP_E_CAPACITY (with the largest
+ * count in the message) or MTP_E_OVERLAP for the last build. */
+int mtp_nbrs_status(const mtp_nbrs *nb, void *stream);
+
+/* Copies the lists out: count [n_atoms] (int32), j [n_atoms*max_nbrs]
+ * (int32), shift [n_atoms*max_nbrs*3] (int32); entries past count are
+ * unspecified.  Any pointer may be NULL.  Returns max_nbrs in *stride. */
+int mtp_nbrs_export(const mtp_nbrs *nb, int32_t *count, int32_t *j, int32_t *shift, int32_t *stride /* host */,
+                    void *stream);
+
+/* --- evaluation ----------------------------------------------------------- */
+
+/* Energy per configuration (eqs. 1-2), forces F = -dE/dx, stress
+ * S_ab = -dE/d eps_ab under x -> (I + eps) x (eV), site energies V_i.
+ * energy [n_cfg], forces [n_atoms*3], stress [n_cfg*9] (row-major), site_e
+ * [n_atoms] or NULL.  All FP64.  The neighbor lists must come from
+ * mtp_build_neighbors on the same positions. */
+int mtp_energy_forces_stress(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p,
+                             double *energy, double *forces, double *stress, double *site_e, void *stream);
+
+/* Grades gamma_i = max_p |(b_i A^-1)_p| of every neighborhood (Sec. II.D)
+ * and the argmax p (lowest on ties).  gamma [n_atoms] FP64, argmax
+ * [n_atoms] int32 or NULL; b_rows (optional) receives the rows, [n_atoms*m]
+ * row-major, FP64 for MTP_FP64 and FP32 for MTP_MIXED.  Needs the mode's
+ * active set. */
+int mtp_grade(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
+              double *gamma, int32_t *argmax, void *b_rows, void *stream);
+
+/* One fused pass: energy, forces, stress, site energies and grades (any
+ * output pointer may be NULL; gamma needs the active set of `g`). */
+int mtp_evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
+                 double *energy, double *forces, double *stress, double *site_e, double *gamma, int32_t *argmax,
+                 void *stream);
+
+/* FP64 rows b_i of the listed atoms only ([n_idx*m] row-major), e.g. the
+ * candidates preselected by mtp_select for MaxVol. */
+int mtp_b_rows(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_grade_mode g, const int32_t *idx,
+               int32_t n_idx, double *rows, void *stream);
+
+/* Preselection of extrapolative neighborhoods (Sec. II.E): writes the
+ * indices i with gamma_i > threshold, ascending, to idx [capacity] and
+ * their number to *count (device int32); at most `capacity` are written. */
+int mtp_select(const double *gamma, int64_t n, double threshold, int32_t *idx, int32_t capacity, int32_t *count,
+               void *stream);
+
+/* MaxVol (Sec. II.C) in FP64: C = cand A^-1; while max |C_ij| > threshold
+ * (> 1) and fewer than max_swaps swaps: row j of A <- candidate i, A^-1 and
+ * C by rank-1 (Sherman-Morrison) updates, and the replaced row takes the
+ * candidate's place in `cand` (so cand is modified in place).  Ties: lowest
+ * i, then lowest j.  swap_cand / swap_col [max_swaps] device int32 receive
+ * the log; *n_swaps (host) the number of swaps (synchronises `stream`). */
+int mtp_maxvol_update(mtp_model *m, mtp_grade_mode g, double *cand, int64_t n_cand, double threshold,
+                      int32_t max_swaps, int32_t *swap_cand, int32_t *swap_col, int32_t *n_swaps, void *stream);
+
+/* Gradient of the fitting objective (eq. 7) with respect to theta, given
+ * the upstream gradients dL/dE [n_cfg], dL/dF [n_atoms*3], dL/dS [n_cfg*9]
+ * (any may be NULL = 0): g_theta [n_theta] FP64.  Moments are recomputed;
+ * no per-pair tensors are stored. */
+int mtp_efs_backward(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, const double *gE,
+                     const double *gF, const double *gS, double *g_theta, void *stream);
+
+/* Description of the basis of a level, one function per line (host). */
+int mtp_basis_describe(int32_t level, char *buf, size_t len, int32_t *n_lin);
+
+/* Levels compiled into this build (host [cap]); returns how many. */
+int mtp_compiled_levels(int32_t *levels, int32_t cap);
+
+const char *mtp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MTP_H */

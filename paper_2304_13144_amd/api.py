@@ -1,0 +1,268 @@
+"""Python binding of libmtp over PyTorch device tensors.
+
+PyTorch provides device memory and the current stream; every step of the
+evaluation runs in the library's HIP kernels.  Names follow include/mtp.h.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import MTP_FP64, MTP_GRADE_FULL, MTP_GRADE_LINEAR, MTP_MIXED, MtpError, check
+
+PRECISION = {"fp64": MTP_FP64, "mixed": MTP_MIXED}
+MODE = {"full": MTP_GRADE_FULL, "linear": MTP_GRADE_LINEAR}
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _prec(p):
+    return PRECISION[p] if isinstance(p, str) else int(p)
+
+
+def _mode(g):
+    return MODE[g] if isinstance(g, str) else int(g)
+
+
+def _dev(device):
+    return torch.device("cuda", device if isinstance(device, int) else torch.device(device).index or 0)
+
+
+class Model:
+    """An MTP (theta, basis, active sets) resident on one GPU."""
+
+    def __init__(self, handle, device):
+        self._h = handle
+        self.device = _dev(device)
+
+    @classmethod
+    def load(cls, path, device=0):
+        h = ctypes.c_void_p()
+        dev = _dev(device)
+        check(_lib.lib().mtp_load(str(path).encode(), dev.index, ctypes.byref(h)))
+        return cls(h, dev)
+
+    @classmethod
+    def create(cls, level, n_types, r_min, r_cut, device=0):
+        h = ctypes.c_void_p()
+        dev = _dev(device)
+        check(_lib.lib().mtp_create(level, n_types, float(r_min), float(r_cut), dev.index, ctypes.byref(h)))
+        return cls(h, dev)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                _lib.lib().mtp_free(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def save(self, path):
+        check(_lib.lib().mtp_save(self._h, str(path).encode()))
+
+    @property
+    def info(self):
+        i = _lib.ModelInfo()
+        check(_lib.lib().mtp_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in _lib.ModelInfo._fields_}
+
+    def m(self, mode):
+        i = self.info
+        return i["m_full"] if _mode(mode) == MTP_GRADE_FULL else i["m_linear"]
+
+    def set_params(self, theta):
+        t = torch.as_tensor(theta, dtype=torch.float64).to(self.device).contiguous()
+        assert t.numel() == self.info["n_theta"]
+        check(_lib.lib().mtp_set_params(self._h, _p(t), _stream()))
+
+    def kept_columns(self):
+        out = np.zeros(self.info["m_full"], dtype=np.int32)
+        check(_lib.lib().mtp_kept_columns(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def set_active_set(self, mode, A):
+        m = self.m(mode)
+        A = torch.as_tensor(A, dtype=torch.float64).to(self.device).contiguous()
+        assert A.shape == (m, m), (A.shape, m)
+        check(_lib.lib().mtp_set_active_set(self._h, _mode(mode), _p(A), _stream()))
+
+    def get_active_set(self, mode):
+        m = self.m(mode)
+        A = torch.empty((m, m), dtype=torch.float64, device=self.device)
+        Ai = torch.empty_like(A)
+        check(_lib.lib().mtp_get_active_set(self._h, _mode(mode), _p(A), _p(Ai), _stream()))
+        return A, Ai
+
+
+class Batch:
+    """Configurations packed for the library: device tensors + an mtp_system view."""
+
+    def __init__(self, configs, device=0):
+        dev = _dev(device)
+        pos = np.concatenate([np.asarray(c.pos, dtype=np.float64) for c in configs]).reshape(-1, 3)
+        types = np.concatenate([np.asarray(c.types, dtype=np.int32) for c in configs])
+        cells = np.stack([np.asarray(c.cell, dtype=np.float64) for c in configs])
+        pbc = np.array([[1 if p else 0 for p in c.pbc] for c in configs], dtype=np.uint8)
+        off = np.zeros(len(configs) + 1, dtype=np.int64)
+        np.cumsum([len(c.pos) for c in configs], out=off[1:])
+        self.device = dev
+        self.pos = torch.from_numpy(np.ascontiguousarray(pos)).to(dev)
+        self.types = torch.from_numpy(types).to(dev)
+        self.cells = torch.from_numpy(cells).to(dev)
+        self.pbc = torch.from_numpy(pbc).to(dev)
+        self.cfg_off = torch.from_numpy(off).to(dev)
+        self.n_cfg = len(configs)
+        self.n_atoms = int(off[-1])
+        self.cfg_off_host = off
+
+    def system(self):
+        s = _lib.System()
+        s.n_cfg = self.n_cfg
+        s.n_atoms = self.n_atoms
+        s.cfg_off = self.cfg_off.data_ptr()
+        s.pos = self.pos.data_ptr()
+        s.type = self.types.data_ptr()
+        s.cell = self.cells.data_ptr()
+        s.pbc = self.pbc.data_ptr()
+        return s
+
+
+class Neighbors:
+    def __init__(self):
+        self._h = ctypes.c_void_p()
+        check(_lib.lib().mtp_nbrs_create(ctypes.byref(self._h)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                _lib.lib().mtp_nbrs_free(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def build(self, model, batch, max_nbrs=64, check_status=True):
+        s = batch.system()
+        check(_lib.lib().mtp_build_neighbors(model._h, ctypes.byref(s), max_nbrs, self._h, _stream()))
+        self.max_nbrs = max_nbrs
+        if check_status:
+            self.status()
+        return self
+
+    def status(self):
+        check(_lib.lib().mtp_nbrs_status(self._h, _stream()))
+
+    def export(self, batch):
+        n = batch.n_atoms
+        count = torch.empty(n, dtype=torch.int32, device=batch.device)
+        stride = ctypes.c_int32()
+        check(_lib.lib().mtp_nbrs_export(self._h, _p(count), None, None, ctypes.byref(stride), _stream()))
+        j = torch.empty(n * stride.value, dtype=torch.int32, device=batch.device)
+        sh = torch.empty(n * stride.value * 3, dtype=torch.int32, device=batch.device)
+        check(_lib.lib().mtp_nbrs_export(self._h, None, _p(j), _p(sh), ctypes.byref(stride), _stream()))
+        return count, j.view(n, stride.value), sh.view(n, stride.value, 3)
+
+
+def _out(n, dtype, device, shape=None):
+    return torch.empty(shape if shape is not None else n, dtype=dtype, device=device)
+
+
+def energy_forces_stress(model, batch, nbrs, precision="fp64", site_energies=True):
+    d = batch.device
+    E = _out(batch.n_cfg, torch.float64, d)
+    F = _out(None, torch.float64, d, (batch.n_atoms, 3))
+    S = _out(None, torch.float64, d, (batch.n_cfg, 3, 3))
+    V = _out(batch.n_atoms, torch.float64, d) if site_energies else None
+    s = batch.system()
+    check(_lib.lib().mtp_energy_forces_stress(model._h, ctypes.byref(s), nbrs._h, _prec(precision), _p(E), _p(F),
+                                              _p(S), _p(V), _stream()))
+    return {"energy": E, "forces": F, "stress": S, "site_e": V}
+
+
+def grade(model, batch, nbrs, precision="fp64", mode="full", rows=False):
+    d = batch.device
+    g = _out(batch.n_atoms, torch.float64, d)
+    am = _out(batch.n_atoms, torch.int32, d)
+    b = None
+    if rows:
+        dt = torch.float64 if _prec(precision) == MTP_FP64 else torch.float32
+        b = _out(None, dt, d, (batch.n_atoms, model.m(mode)))
+    s = batch.system()
+    check(_lib.lib().mtp_grade(model._h, ctypes.byref(s), nbrs._h, _prec(precision), _mode(mode), _p(g), _p(am),
+                               _p(b), _stream()))
+    return {"gamma": g, "argmax": am, "rows": b}
+
+
+def evaluate(model, batch, nbrs, precision="fp64", mode="full", out=None):
+    """Fused energy, forces, stress, site energies and grades; `out` reuses tensors."""
+    d = batch.device
+    if out is None:
+        out = {"energy": _out(batch.n_cfg, torch.float64, d),
+               "forces": _out(None, torch.float64, d, (batch.n_atoms, 3)),
+               "stress": _out(None, torch.float64, d, (batch.n_cfg, 3, 3)),
+               "site_e": _out(batch.n_atoms, torch.float64, d),
+               "gamma": _out(batch.n_atoms, torch.float64, d),
+               "argmax": _out(batch.n_atoms, torch.int32, d)}
+    s = batch.system()
+    check(_lib.lib().mtp_evaluate(model._h, ctypes.byref(s), nbrs._h, _prec(precision), _mode(mode),
+                                  _p(out.get("energy")), _p(out.get("forces")), _p(out.get("stress")),
+                                  _p(out.get("site_e")), _p(out.get("gamma")), _p(out.get("argmax")), _stream()))
+    return out
+
+
+def b_rows(model, batch, nbrs, idx, mode="full"):
+    idx = torch.as_tensor(idx, dtype=torch.int32).to(batch.device).contiguous()
+    out = torch.empty((idx.numel(), model.m(mode)), dtype=torch.float64, device=batch.device)
+    s = batch.system()
+    check(_lib.lib().mtp_b_rows(model._h, ctypes.byref(s), nbrs._h, _mode(mode), _p(idx), idx.numel(), _p(out),
+                                _stream()))
+    return out
+
+
+def select(gamma, threshold, capacity=None):
+    n = gamma.numel()
+    cap = n if capacity is None else capacity
+    idx = torch.empty(max(cap, 1), dtype=torch.int32, device=gamma.device)
+    cnt = torch.empty(1, dtype=torch.int32, device=gamma.device)
+    check(_lib.lib().mtp_select(_p(gamma), n, float(threshold), _p(idx), cap, _p(cnt), _stream()))
+    return idx, cnt
+
+
+def maxvol_update(model, mode, cand, threshold=1.001, max_swaps=None):
+    """Swaps candidate rows (FP64 device [n, m], modified in place) into the active set."""
+    m = model.m(mode)
+    assert cand.dtype == torch.float64 and cand.is_contiguous() and cand.shape[1] == m
+    ms = 10 * m if max_swaps is None else max_swaps
+    sc = torch.empty(max(ms, 1), dtype=torch.int32, device=cand.device)
+    sj = torch.empty(max(ms, 1), dtype=torch.int32, device=cand.device)
+    n = ctypes.c_int32()
+    check(_lib.lib().mtp_maxvol_update(model._h, _mode(mode), _p(cand), cand.shape[0], float(threshold), ms,
+                                       _p(sc), _p(sj), ctypes.byref(n), _stream()))
+    return sc[:n.value].cpu().numpy(), sj[:n.value].cpu().numpy()
+
+
+def basis_describe(level):
+    n = ctypes.c_int32()
+    buf = ctypes.create_string_buffer(1 << 22)
+    check(_lib.lib().mtp_basis_describe(level, buf, len(buf), ctypes.byref(n)))
+    return buf.value.decode().splitlines()
+
+
+def compiled_levels():
+    arr = (ctypes.c_int32 * 64)()
+    n = _lib.lib().mtp_compiled_levels(arr, 64)
+    return list(arr[:n])
+
+
+__all__ = ["Model", "Batch", "Neighbors", "energy_forces_stress", "grade", "evaluate", "b_rows", "select",
+           "maxvol_update", "basis_describe", "compiled_levels", "MtpError"]

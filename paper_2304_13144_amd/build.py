@@ -1,0 +1,105 @@
+"""Builds libmtp.so in-tree for gfx950.
+
+Steps: compile the basis generator (g++) -> write one contraction header per
+level -> one HIP translation unit per level with the fused kernel
+instantiated for it -> compile every unit with hipcc in parallel -> link.
+
+    python -m paper_2304_13144_amd.build [--levels 8,16] [-j 8]
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(os.path.dirname(HERE), "_build")
+GEN = os.path.join(BUILD, "gen")
+LIB = os.path.join(HERE, "libmtp.so")
+
+DEFAULT_LEVELS = (2, 4, 6, 8, 12, 16)
+ARCH = "gfx950"
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+HIP_FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wno-unused-result",
+             # no packed FP32 instructions anywhere in the device code
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-I", CSRC, "-I", GEN]
+HOST_SOURCES = ["api.cpp", "basis.cpp"]
+HIP_SOURCES = ["neighbors.hip", "ops.hip", "grade.hip"]
+
+
+def _run(cmd):
+    t = time.time()
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError("build step failed:\n" + " ".join(cmd) + "\n" + p.stdout + p.stderr)
+    return time.time() - t
+
+
+def generate(levels):
+    os.makedirs(GEN, exist_ok=True)
+    gen_exe = os.path.join(BUILD, "gen_contract")
+    _run(["g++", "-O2", "-std=c++17", "-o", gen_exe, os.path.join(CSRC, "gen_contract.cpp"),
+          os.path.join(CSRC, "basis.cpp")])
+    _run([gen_exe, GEN] + [str(L) for L in levels])
+    units = []
+    for L in levels:
+        path = os.path.join(GEN, f"efs_level{L}.hip")
+        src = (f'#include "efs_kernel.hpp"\nnamespace mtp {{\n#include "mtp_level{L}.inc"\n'
+               f"MTP_EFS_LEVEL({L})\n}}  // namespace mtp\n")
+        _write_if_changed(path, src)
+        units.append(path)
+    decl = "".join(f"template <> int launch_efs_level<{L}>(const EfsArgs &a);\n" for L in levels)
+    cases = "".join(f"        case {L}: return launch_efs_level<{L}>(a);\n" for L in levels)
+    disp = ('#include "internal.hpp"\nnamespace mtp {\ntemplate <int L> int launch_efs_level(const EfsArgs &a);\n'
+            + decl + "int launch_efs(int level, const EfsArgs &a) {\n    switch (level) {\n" + cases
+            + "        default: return -1;\n    }\n}\nstd::vector<int> compiled_levels() { return {"
+            + ", ".join(str(L) for L in levels) + "}; }\n}  // namespace mtp\n")
+    dpath = os.path.join(GEN, "dispatch.cpp")
+    _write_if_changed(dpath, disp)
+    return units, dpath
+
+
+def _write_if_changed(path, text):
+    if os.path.exists(path) and open(path).read() == text:
+        return
+    with open(path, "w") as fh:
+        fh.write(text)
+
+
+def build(levels=DEFAULT_LEVELS, jobs=None, verbose=True):
+    t0 = time.time()
+    units, dispatch = generate(levels)
+    objs = []
+    jobs_list = []
+    for src in [os.path.join(CSRC, s) for s in HOST_SOURCES + HIP_SOURCES] + [dispatch] + units:
+        obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+        objs.append(obj)
+        jobs_list.append([HIPCC] + HIP_FLAGS + ["-c", src, "-o", obj])
+    n = jobs or min(8, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(n) as ex:
+        times = list(ex.map(_run, jobs_list))
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs)
+    os.replace(tmp, LIB)
+    if verbose:
+        slow = sorted(zip(times, jobs_list), key=lambda t: -t[0])[:3]
+        print(f"[build] libmtp.so with levels {list(levels)} in {time.time() - t0:.1f}s "
+              f"(slowest unit {slow[0][0]:.1f}s: {os.path.basename(slow[0][1][-3])})", flush=True)
+    return LIB
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--levels", default=",".join(str(L) for L in DEFAULT_LEVELS))
+    ap.add_argument("-j", type=int, default=None)
+    a = ap.parse_args(argv)
+    build(tuple(int(x) for x in a.levels.split(",")), a.j)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

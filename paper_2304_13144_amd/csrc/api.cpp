@@ -1,0 +1,683 @@
+// C ABI of libmtp: argument checks, model state, workspaces and the order
+// of kernel launches.  Every entry point catches its own errors and turns
+// them into an mtp_status (see include/mtp.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace mtp {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+void DevBuf::ensure(size_t n) {
+    if (n <= bytes && ptr) return;
+    release();
+    if (n == 0) n = 16;
+    hipError_t e = hipMalloc(&ptr, n);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        bytes = 0;
+        (void)hipGetLastError();
+        throw Error{MTP_E_NOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed"};
+    }
+    bytes = n;
+}
+
+void DevBuf::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+namespace {
+
+hipStream_t S(void *s) { return static_cast<hipStream_t>(s); }
+
+int ld_of(int m) { return (m + 31) / 32 * 32; }
+
+// FULL-mode gauge: per mu drop mu+1 columns of block c_mu chosen as the
+// first mu+1 pivots of a column-pivoted Gram-Schmidt (= QR with column
+// pivoting) of the (mu+1) x (T^2 N_polyn) matrix [c_0; ...; c_mu].
+void choose_gauge(mtp_model *m) {
+    const int T = m->n_types, L = m->basis.n_lin(), R = m->basis.n_rad;
+    const int blk = T * T * NPOLY;
+    const int base = T + L;
+    std::vector<int> drop;
+    for (int mu = 0; mu < R; ++mu) {
+        const int rows = mu + 1;
+        // columns of the block as vectors of length rows
+        std::vector<std::vector<double>> col(blk, std::vector<double>(rows));
+        for (int c = 0; c < blk; ++c)
+            for (int r = 0; r < rows; ++r) col[c][r] = m->theta_host[base + r * blk + c];
+        std::vector<bool> used(blk, false);
+        for (int step = 0; step < rows; ++step) {
+            int best = -1;
+            double bn = -1.0;
+            for (int c = 0; c < blk; ++c) {
+                if (used[c]) continue;
+                double nn = 0.0;
+                for (double v : col[c]) nn += v * v;
+                if (nn > bn) {
+                    bn = nn;
+                    best = c;
+                }
+            }
+            used[best] = true;
+            drop.push_back(base + mu * blk + best);
+            const double nrm = std::sqrt(bn);
+            if (nrm == 0.0) continue;
+            std::vector<double> q(rows);
+            for (int r = 0; r < rows; ++r) q[r] = col[best][r] / nrm;
+            for (int c = 0; c < blk; ++c) {
+                if (used[c]) continue;
+                double d = 0.0;
+                for (int r = 0; r < rows; ++r) d += q[r] * col[c][r];
+                for (int r = 0; r < rows; ++r) col[c][r] -= d * q[r];
+            }
+        }
+    }
+    std::sort(drop.begin(), drop.end());
+    m->kept.clear();
+    m->colmap_host.assign(m->n_theta, -1);
+    size_t d = 0;
+    for (int k = 0; k < m->n_theta; ++k) {
+        if (d < drop.size() && drop[d] == k) {
+            ++d;
+            continue;
+        }
+        m->colmap_host[k] = (int)m->kept.size();
+        m->kept.push_back(k);
+    }
+}
+
+void upload_params(mtp_model *m) {
+    MTP_HIP(hipSetDevice(m->device));
+    m->theta64.ensure(sizeof(double) * m->n_theta);
+    m->theta32.ensure(sizeof(float) * m->n_theta);
+    std::vector<float> t32(m->theta_host.begin(), m->theta_host.end());
+    MTP_HIP(hipMemcpy(m->theta64.ptr, m->theta_host.data(), sizeof(double) * m->n_theta, hipMemcpyHostToDevice));
+    MTP_HIP(hipMemcpy(m->theta32.ptr, t32.data(), sizeof(float) * m->n_theta, hipMemcpyHostToDevice));
+    m->colmap.ensure(sizeof(int32_t) * m->n_theta);
+    MTP_HIP(hipMemcpy(m->colmap.ptr, m->colmap_host.data(), sizeof(int32_t) * m->n_theta, hipMemcpyHostToDevice));
+}
+
+mtp_model *new_model(int level, int n_types, double r_min, double r_cut, int device) {
+    MTP_CHECK(n_types >= 1 && n_types <= MAX_TYPES, MTP_E_UNSUPPORTED, "n_types must be 1..4");
+    MTP_CHECK(r_cut > r_min && r_min >= 0.0, MTP_E_INVAL, "need 0 <= r_min < r_cut");
+    auto lv = compiled_levels();
+    MTP_CHECK(std::find(lv.begin(), lv.end(), level) != lv.end(), MTP_E_UNSUPPORTED,
+              "level " + std::to_string(level) + " is not compiled into this build");
+    int ndev = 0;
+    MTP_HIP(hipGetDeviceCount(&ndev));
+    MTP_CHECK(device >= 0 && device < ndev, MTP_E_INVAL, "bad hip_device");
+    auto *m = new mtp_model();
+    m->device = device;
+    m->level = level;
+    m->n_types = n_types;
+    m->r_min = r_min;
+    m->r_cut = r_cut;
+    m->basis = build_basis(level);
+    m->n_theta = n_types + m->basis.n_lin() + m->basis.n_rad * n_types * n_types * NPOLY;
+    m->theta_host.assign(m->n_theta, 0.0);
+    return m;
+}
+
+void set_active(mtp_model *m, int mode, const double *A_dev, hipStream_t st) {
+    ActiveSet &as = m->act[mode];
+    as.m = m->m_of(mode);
+    as.A.ensure(sizeof(double) * as.m * as.m);
+    as.Ainv.ensure(sizeof(double) * as.m * as.m);
+    MTP_HIP(hipMemcpyAsync(as.A.ptr, A_dev, sizeof(double) * as.m * as.m, hipMemcpyDeviceToDevice, st));
+    int singular = 0;
+    launch_invert(as, as.A.as<double>(), st, m->work, &singular);
+    if (singular) {
+        as.valid = false;
+        throw Error{MTP_E_SINGULAR, "active-set matrix is singular (pivot below 1e-300)"};
+    }
+    prepare_split(as, st);
+    as.valid = true;
+}
+
+void check_system(const mtp_model *m, const mtp_system *s) {
+    MTP_CHECK(s, MTP_E_INVAL, "system is NULL");
+    MTP_CHECK(s->n_cfg >= 1 && s->n_atoms >= 0, MTP_E_INVAL, "need n_cfg >= 1 and n_atoms >= 0");
+    MTP_CHECK(s->cfg_off && s->pos && s->type && s->cell, MTP_E_INVAL, "system arrays must not be NULL");
+    MTP_CHECK(s->n_atoms < (int64_t)1 << 31, MTP_E_INVAL, "at most 2^31-1 atoms per call");
+    (void)m;
+}
+
+void check_nbrs(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb) {
+    MTP_CHECK(nb && nb->n_atoms == s->n_atoms && nb->n_types == m->n_types && nb->n_cfg == s->n_cfg,
+              MTP_E_INVAL, "neighbor lists were not built for this system and model");
+    MTP_CHECK(nb->r_cut == m->r_cut, MTP_E_INVAL, "neighbor lists were built with another cutoff");
+}
+
+int lanes_for(const mtp_model *m, int64_t n) {
+    if (const char *e = std::getenv("MTP_LANES")) {
+        int v = std::atoi(e);
+        if (v == 2 || v == 4 || v == 8) return v;
+    }
+    (void)m;
+    // enough wavefronts for 256 CUs x 4 SIMDs, few lanes when the batch is large
+    if (n >= (int64_t)1 << 20) return 2;
+    if (n >= (int64_t)1 << 17) return 4;
+    return 8;
+}
+
+struct EvalOut {
+    double *energy = nullptr, *forces = nullptr, *stress = nullptr, *site_e = nullptr;
+    double *gamma = nullptr;
+    int32_t *argmax = nullptr;
+    void *b_rows = nullptr;
+    int mode = MTP_GRADE_FULL;
+};
+
+void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int prec, const EvalOut &o,
+              hipStream_t st) {
+    check_system(m, s);
+    check_nbrs(m, s, nb);
+    MTP_CHECK(prec == MTP_FP64 || prec == MTP_MIXED, MTP_E_INVAL, "bad precision");
+    MTP_CHECK(o.mode == MTP_GRADE_FULL || o.mode == MTP_GRADE_LINEAR, MTP_E_INVAL, "bad grade mode");
+    const bool want_grade = o.gamma || o.argmax;
+    const bool want_rows = want_grade || o.b_rows;
+    if (want_grade) MTP_CHECK(m->act[o.mode].valid, MTP_E_INVAL, "no active set for this grade mode");
+    MTP_HIP(hipSetDevice(m->device));
+    const int64_t n = s->n_atoms;
+    const size_t tsz = prec == MTP_FP64 ? sizeof(double) : sizeof(float);
+    const bool want_f = o.forces != nullptr;
+    const bool want_v = o.stress != nullptr;
+    const bool want_e = o.energy || o.site_e;
+    const int mm = m->m_of(o.mode);
+    const int ldb = ld_of(mm);
+    if (want_f) m->gbuf.ensure(tsz * 3 * (size_t)std::max<int64_t>(1, n * nb->max_nbrs));
+    if (want_v) m->virial.ensure(sizeof(double) * 9 * (size_t)std::max<int64_t>(1, n));
+    double *site = o.site_e;
+    if (want_e && !site) {
+        m->sitebuf.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, n));
+        site = m->sitebuf.as<double>();
+    }
+    if (want_rows) m->brow.ensure(tsz * (size_t)ldb * (size_t)std::max<int64_t>(1, n));
+    if (n == 0) {
+        if (o.energy) launch_zero(o.energy, sizeof(double) * s->n_cfg, st);
+        if (o.stress) launch_zero(o.stress, sizeof(double) * 9 * s->n_cfg, st);
+        return;
+    }
+    EfsArgs a{};
+    a.n_atoms = n;
+    a.atom_list = nullptr;
+    a.n_types = m->n_types;
+    a.max_nbrs = nb->max_nbrs;
+    a.r = nb->r.as<double>();
+    a.tcnt = nb->tcnt.as<int32_t>();
+    a.type = s->type;
+    a.r_min = m->r_min;
+    a.r_cut = m->r_cut;
+    const char *th = prec == MTP_FP64 ? static_cast<const char *>(m->theta64.ptr) : static_cast<const char *>(m->theta32.ptr);
+    a.xi0 = th;
+    a.xi = th + tsz * m->n_types;
+    a.c = th + tsz * (m->n_types + m->basis.n_lin());
+    a.site_e = want_e ? site : nullptr;
+    a.gbuf = want_f ? m->gbuf.ptr : nullptr;
+    a.virial = want_v ? m->virial.as<double>() : nullptr;
+    a.brow = want_rows ? m->brow.ptr : nullptr;
+    a.ldb = ldb;
+    a.grade_mode = o.mode;
+    a.colmap = m->colmap.as<int32_t>();
+    a.m = mm;
+    a.precision = prec;
+    a.lanes = lanes_for(m, n);
+    a.stream = st;
+    int e = launch_efs(m->level, a);
+    MTP_CHECK(e == 0, MTP_E_HIP, std::string("efs kernel launch: ") + hipGetErrorString((hipError_t)e));
+    if (want_f) launch_force_gather(nb, m->gbuf.ptr, prec, o.forces, st);
+    if (o.energy || want_v) launch_cfg_sums(s, o.energy ? site : nullptr, want_v ? m->virial.as<double>() : nullptr,
+                                            o.energy, o.stress, st);
+    if (want_grade) {
+        m->gamma_ws.ensure(sizeof(double) * n);
+        launch_grade(m->act[o.mode], prec, m->brow.ptr, ldb, n, o.gamma ? o.gamma : m->gamma_ws.as<double>(),
+                     o.argmax, st);
+    }
+    if (o.b_rows) launch_copy_rows(m->brow.ptr, ldb, mm, n, prec, o.b_rows, st);
+    MTP_HIP(hipGetLastError());
+}
+
+std::string read_file(const char *path) {
+    std::ifstream f(path);
+    MTP_CHECK(f.good(), MTP_E_IO, std::string("cannot open ") + path);
+    std::stringstream ss;
+    ss << f.rdbuf();
+    return ss.str();
+}
+
+}  // namespace
+}  // namespace mtp
+
+using namespace mtp;
+
+#define API_BEGIN try {
+#define API_END                                                  \
+    }                                                            \
+    catch (const mtp::Error &e) {                                \
+        mtp::set_error(e.msg);                                   \
+        return e.code;                                           \
+    }                                                            \
+    catch (const std::bad_alloc &) {                             \
+        mtp::set_error("host allocation failed");                \
+        return MTP_E_NOMEM;                                      \
+    }                                                            \
+    catch (const std::exception &e) {                            \
+        mtp::set_error(e.what());                                \
+        return MTP_E_INVAL;                                      \
+    }                                                            \
+    return MTP_OK;
+
+extern "C" {
+
+const char *mtp_last_error(void) { return g_last_error.c_str(); }
+
+int mtp_create(int32_t level, int32_t n_types, double r_min, double r_cut, int hip_device, mtp_model **out) {
+    API_BEGIN
+    MTP_CHECK(out, MTP_E_INVAL, "out is NULL");
+    mtp_model *m = new_model(level, n_types, r_min, r_cut, hip_device);
+    choose_gauge(m);
+    upload_params(m);
+    *out = m;
+    API_END
+}
+
+int mtp_load(const char *path, int hip_device, mtp_model **out) {
+    API_BEGIN
+    MTP_CHECK(path && out, MTP_E_INVAL, "NULL argument");
+    std::istringstream in(read_file(path));
+    std::string key;
+    int level = -1, nt = -1, npoly = NPOLY, fmt = -1;
+    double rmin = NAN, rcut = NAN;
+    std::vector<double> theta;
+    std::vector<std::pair<int, std::vector<double>>> acts;
+    while (in >> key) {
+        if (key[0] == '#') {
+            std::string rest;
+            std::getline(in, rest);
+            continue;
+        }
+        if (key == "format") in >> fmt;
+        else if (key == "level") in >> level;
+        else if (key == "n_types") in >> nt;
+        else if (key == "r_min") in >> rmin;
+        else if (key == "r_cut") in >> rcut;
+        else if (key == "n_polyn") in >> npoly;
+        else if (key == "theta") {
+            long n = -1;
+            in >> n;
+            MTP_CHECK(n >= 0 && n < 100000000, MTP_E_PARSE, "bad theta length");
+            theta.resize(n);
+            for (long k = 0; k < n; ++k) MTP_CHECK(bool(in >> theta[k]), MTP_E_PARSE, "theta truncated");
+        } else if (key == "active") {
+            std::string mode;
+            long mm = -1;
+            in >> mode >> mm;
+            MTP_CHECK(mode == "full" || mode == "linear", MTP_E_PARSE, "active mode must be full or linear");
+            MTP_CHECK(mm > 0 && mm < 100000, MTP_E_PARSE, "bad active-set size");
+            std::vector<double> A(mm * mm);
+            for (long k = 0; k < mm * mm; ++k) MTP_CHECK(bool(in >> A[k]), MTP_E_PARSE, "active set truncated");
+            acts.push_back({mode == "full" ? MTP_GRADE_FULL : MTP_GRADE_LINEAR, A});
+        } else {
+            throw Error{MTP_E_PARSE, "unknown key '" + key + "'"};
+        }
+        MTP_CHECK(!in.fail(), MTP_E_PARSE, "bad value after '" + key + "'");
+    }
+    MTP_CHECK(fmt == 1, MTP_E_PARSE, "missing or unsupported 'format'");
+    MTP_CHECK(npoly == NPOLY, MTP_E_UNSUPPORTED, "only n_polyn 8 is compiled");
+    MTP_CHECK(level > 0 && nt > 0 && std::isfinite(rmin) && std::isfinite(rcut), MTP_E_PARSE,
+              "need level, n_types, r_min, r_cut");
+    mtp_model *m = new_model(level, nt, rmin, rcut, hip_device);
+    MTP_CHECK(theta.empty() || (int)theta.size() == m->n_theta,
+              (delete m, MTP_E_PARSE), "theta length does not match level and n_types");
+    if (!theta.empty()) m->theta_host = theta;
+    choose_gauge(m);
+    upload_params(m);
+    for (auto &a : acts) {
+        const int mm = m->m_of(a.first);
+        if ((long)a.second.size() != (long)mm * mm) {
+            delete m;
+            throw Error{MTP_E_PARSE, "active-set size does not match the model"};
+        }
+        DevBuf tmp;
+        tmp.ensure(sizeof(double) * mm * mm);
+        MTP_HIP(hipMemcpy(tmp.ptr, a.second.data(), sizeof(double) * mm * mm, hipMemcpyHostToDevice));
+        try {
+            set_active(m, a.first, tmp.as<double>(), nullptr);
+        } catch (...) {
+            delete m;
+            throw;
+        }
+    }
+    *out = m;
+    API_END
+}
+
+int mtp_save(const mtp_model *m, const char *path) {
+    API_BEGIN
+    MTP_CHECK(m && path, MTP_E_INVAL, "NULL argument");
+    std::ofstream f(path);
+    MTP_CHECK(f.good(), MTP_E_IO, std::string("cannot write ") + path);
+    f.precision(17);
+    f << "# MTP model (MI355X library text format)\nformat 1\nlevel " << m->level << "\nn_types " << m->n_types
+      << "\nr_min " << m->r_min << "\nr_cut " << m->r_cut << "\nn_polyn " << NPOLY << "\ntheta " << m->n_theta << "\n";
+    for (int k = 0; k < m->n_theta; ++k) f << m->theta_host[k] << (k % 8 == 7 ? "\n" : " ");
+    f << "\n";
+    for (int mode = 0; mode < 2; ++mode) {
+        const ActiveSet &as = m->act[mode];
+        if (!as.valid) continue;
+        std::vector<double> A((size_t)as.m * as.m);
+        MTP_HIP(hipSetDevice(m->device));
+        MTP_HIP(hipMemcpy(A.data(), as.A.ptr, sizeof(double) * A.size(), hipMemcpyDeviceToHost));
+        f << "active " << (mode == MTP_GRADE_FULL ? "full " : "linear ") << as.m << "\n";
+        for (size_t k = 0; k < A.size(); ++k) f << A[k] << ((k + 1) % as.m == 0 ? "\n" : " ");
+    }
+    MTP_CHECK(f.good(), MTP_E_IO, "write failed");
+    API_END
+}
+
+int mtp_free(mtp_model *m) {
+    API_BEGIN
+    if (m) {
+        (void)hipSetDevice(m->device);
+        delete m;
+    }
+    API_END
+}
+
+int mtp_info(const mtp_model *m, mtp_model_info *info) {
+    API_BEGIN
+    MTP_CHECK(m && info, MTP_E_INVAL, "NULL argument");
+    info->level = m->level;
+    info->n_types = m->n_types;
+    info->n_polyn = NPOLY;
+    info->n_lin = m->basis.n_lin();
+    info->n_rad = m->basis.n_rad;
+    info->n_comp = m->basis.n_comp();
+    info->n_theta = m->n_theta;
+    info->m_full = m->m_of(MTP_GRADE_FULL);
+    info->m_linear = m->m_of(MTP_GRADE_LINEAR);
+    info->r_min = m->r_min;
+    info->r_cut = m->r_cut;
+    info->has_active_full = m->act[0].valid;
+    info->has_active_linear = m->act[1].valid;
+    API_END
+}
+
+int mtp_set_params(mtp_model *m, const double *theta, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m && theta, MTP_E_INVAL, "NULL argument");
+    MTP_HIP(hipSetDevice(m->device));
+    std::vector<double> h(m->n_theta);
+    MTP_HIP(hipMemcpyAsync(h.data(), theta, sizeof(double) * m->n_theta, hipMemcpyDeviceToHost, S(stream)));
+    MTP_HIP(hipStreamSynchronize(S(stream)));
+    for (double v : h) MTP_CHECK(std::isfinite(v), MTP_E_INVAL, "theta holds NaN or Inf");
+    m->theta_host = h;
+    choose_gauge(m);
+    upload_params(m);
+    m->act[MTP_GRADE_FULL].valid = false;   // FULL rows depend on theta
+    API_END
+}
+
+int mtp_kept_columns(const mtp_model *m, int32_t *cols) {
+    API_BEGIN
+    MTP_CHECK(m && cols, MTP_E_INVAL, "NULL argument");
+    for (size_t k = 0; k < m->kept.size(); ++k) cols[k] = m->kept[k];
+    API_END
+}
+
+int mtp_set_active_set(mtp_model *m, mtp_grade_mode mode, const double *A, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m && A, MTP_E_INVAL, "NULL argument");
+    MTP_CHECK(mode == MTP_GRADE_FULL || mode == MTP_GRADE_LINEAR, MTP_E_INVAL, "bad grade mode");
+    MTP_HIP(hipSetDevice(m->device));
+    set_active(m, mode, A, S(stream));
+    API_END
+}
+
+int mtp_get_active_set(const mtp_model *m, mtp_grade_mode mode, double *A_out, double *Ainv_out, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m, MTP_E_INVAL, "NULL model");
+    MTP_CHECK(mode == MTP_GRADE_FULL || mode == MTP_GRADE_LINEAR, MTP_E_INVAL, "bad grade mode");
+    const ActiveSet &as = m->act[mode];
+    MTP_CHECK(as.valid, MTP_E_INVAL, "no active set for this mode");
+    MTP_HIP(hipSetDevice(m->device));
+    const size_t b = sizeof(double) * as.m * as.m;
+    if (A_out) MTP_HIP(hipMemcpyAsync(A_out, as.A.ptr, b, hipMemcpyDeviceToDevice, S(stream)));
+    if (Ainv_out) MTP_HIP(hipMemcpyAsync(Ainv_out, as.Ainv.ptr, b, hipMemcpyDeviceToDevice, S(stream)));
+    API_END
+}
+
+int mtp_nbrs_create(mtp_nbrs **out) {
+    API_BEGIN
+    MTP_CHECK(out, MTP_E_INVAL, "out is NULL");
+    *out = new mtp_nbrs();
+    API_END
+}
+
+int mtp_nbrs_free(mtp_nbrs *nb) {
+    API_BEGIN
+    if (nb) {
+        if (nb->device >= 0) (void)hipSetDevice(nb->device);
+        delete nb;
+    }
+    API_END
+}
+
+int mtp_build_neighbors(const mtp_model *m, const mtp_system *s, int32_t max_nbrs, mtp_nbrs *nb, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m && nb, MTP_E_INVAL, "NULL argument");
+    check_system(m, s);
+    MTP_CHECK(max_nbrs >= 1 && max_nbrs <= 4096, MTP_E_INVAL, "max_nbrs must be 1..4096");
+    MTP_CHECK(s->n_atoms * (int64_t)max_nbrs < ((int64_t)1 << 31), MTP_E_INVAL,
+              "n_atoms * max_nbrs must stay below 2^31");
+    MTP_HIP(hipSetDevice(m->device));
+    build_neighbors(m, s, max_nbrs, nb, S(stream));
+    API_END
+}
+
+int mtp_nbrs_status(const mtp_nbrs *nb, void *stream) {
+    API_BEGIN
+    MTP_CHECK(nb && nb->device >= 0, MTP_E_INVAL, "neighbor lists not built");
+    MTP_HIP(hipSetDevice(nb->device));
+    int32_t f[4] = {0, 0, 0, 0};
+    MTP_HIP(hipMemcpyAsync(f, nb->flags.ptr, sizeof(f), hipMemcpyDeviceToHost, S(stream)));
+    MTP_HIP(hipStreamSynchronize(S(stream)));
+    MTP_CHECK(!(f[3] & 1), MTP_E_INVAL, "a cell matrix is singular");
+    MTP_CHECK(!(f[3] & 8), MTP_E_INVAL, "an atom type is outside 0..n_types-1");
+    MTP_CHECK(!(f[3] & 2), MTP_E_INVAL, "an image shift exceeds +-127 cells (atoms far outside the cell)");
+    MTP_CHECK(!(f[3] & 4), MTP_E_INVAL, "internal: a reverse pair was not found");
+    MTP_CHECK(!f[0], MTP_E_CAPACITY,
+              "a neighborhood has " + std::to_string(f[1]) + " atoms, more than max_nbrs = " +
+                  std::to_string(nb->max_nbrs));
+    MTP_CHECK(!f[2], MTP_E_OVERLAP, "two atoms are closer than 1e-6 Angstrom");
+    API_END
+}
+
+int mtp_nbrs_export(const mtp_nbrs *nb, int32_t *count, int32_t *j, int32_t *shift, int32_t *stride, void *stream) {
+    API_BEGIN
+    MTP_CHECK(nb && nb->device >= 0, MTP_E_INVAL, "neighbor lists not built");
+    MTP_HIP(hipSetDevice(nb->device));
+    const int64_t n = nb->n_atoms, P = n * nb->max_nbrs;
+    if (stride) *stride = nb->max_nbrs;
+    if (count) {
+        // per-atom totals from the per-species counts
+        std::vector<int32_t> t((size_t)n * nb->n_types), c((size_t)n);
+        MTP_HIP(hipMemcpyAsync(t.data(), nb->tcnt.ptr, sizeof(int32_t) * t.size(), hipMemcpyDeviceToHost, S(stream)));
+        MTP_HIP(hipStreamSynchronize(S(stream)));
+        for (int64_t i = 0; i < n; ++i) {
+            int s = 0;
+            for (int k = 0; k < nb->n_types; ++k) s += t[i * nb->n_types + k];
+            c[i] = s;
+        }
+        MTP_HIP(hipMemcpyAsync(count, c.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, S(stream)));
+        MTP_HIP(hipStreamSynchronize(S(stream)));
+    }
+    if (j) MTP_HIP(hipMemcpyAsync(j, nb->j.ptr, sizeof(int32_t) * P, hipMemcpyDeviceToDevice, S(stream)));
+    if (shift) {
+        std::vector<int32_t> p((size_t)P), o((size_t)P * 3);
+        MTP_HIP(hipMemcpyAsync(p.data(), nb->shift.ptr, sizeof(int32_t) * P, hipMemcpyDeviceToHost, S(stream)));
+        MTP_HIP(hipStreamSynchronize(S(stream)));
+        for (int64_t k = 0; k < P; ++k)
+            for (int a = 0; a < 3; ++a) o[3 * k + a] = (int32_t)(signed char)((p[k] >> (8 * a)) & 0xff);
+        MTP_HIP(hipMemcpyAsync(shift, o.data(), sizeof(int32_t) * 3 * P, hipMemcpyHostToDevice, S(stream)));
+        MTP_HIP(hipStreamSynchronize(S(stream)));
+    }
+    API_END
+}
+
+int mtp_energy_forces_stress(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p,
+                             double *energy, double *forces, double *stress, double *site_e, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m, MTP_E_INVAL, "NULL model");
+    EvalOut o;
+    o.energy = energy;
+    o.forces = forces;
+    o.stress = stress;
+    o.site_e = site_e;
+    evaluate(m, s, nb, p, o, S(stream));
+    API_END
+}
+
+int mtp_grade(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
+              double *gamma, int32_t *argmax, void *b_rows, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m && gamma, MTP_E_INVAL, "NULL argument");
+    EvalOut o;
+    o.gamma = gamma;
+    o.argmax = argmax;
+    o.b_rows = b_rows;
+    o.mode = g;
+    evaluate(m, s, nb, p, o, S(stream));
+    API_END
+}
+
+int mtp_evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
+                 double *energy, double *forces, double *stress, double *site_e, double *gamma, int32_t *argmax,
+                 void *stream) {
+    API_BEGIN
+    MTP_CHECK(m, MTP_E_INVAL, "NULL model");
+    EvalOut o;
+    o.energy = energy;
+    o.forces = forces;
+    o.stress = stress;
+    o.site_e = site_e;
+    o.gamma = gamma;
+    o.argmax = argmax;
+    o.mode = g;
+    evaluate(m, s, nb, p, o, S(stream));
+    API_END
+}
+
+int mtp_b_rows(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_grade_mode g, const int32_t *idx,
+               int32_t n_idx, double *rows, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m && idx && rows, MTP_E_INVAL, "NULL argument");
+    MTP_CHECK(n_idx >= 0, MTP_E_INVAL, "n_idx < 0");
+    MTP_CHECK(g == MTP_GRADE_FULL || g == MTP_GRADE_LINEAR, MTP_E_INVAL, "bad grade mode");
+    check_system(m, s);
+    check_nbrs(m, s, nb);
+    if (n_idx == 0) return MTP_OK;
+    MTP_HIP(hipSetDevice(m->device));
+    const int mm = m->m_of(g);
+    const int ldb = ld_of(mm);
+    m->brow.ensure(sizeof(double) * (size_t)ldb * n_idx);
+    EfsArgs a{};
+    a.n_atoms = n_idx;
+    a.atom_list = idx;
+    a.n_types = m->n_types;
+    a.max_nbrs = nb->max_nbrs;
+    a.r = nb->r.as<double>();
+    a.tcnt = nb->tcnt.as<int32_t>();
+    a.type = s->type;
+    a.r_min = m->r_min;
+    a.r_cut = m->r_cut;
+    const char *th = static_cast<const char *>(m->theta64.ptr);
+    a.xi0 = th;
+    a.xi = th + sizeof(double) * m->n_types;
+    a.c = th + sizeof(double) * (m->n_types + m->basis.n_lin());
+    a.brow = m->brow.ptr;
+    a.ldb = ldb;
+    a.grade_mode = g;
+    a.colmap = m->colmap.as<int32_t>();
+    a.m = mm;
+    a.precision = MTP_FP64;
+    a.lanes = 4;
+    a.stream = S(stream);
+    int e = launch_efs(m->level, a);
+    MTP_CHECK(e == 0, MTP_E_HIP, std::string("efs kernel launch: ") + hipGetErrorString((hipError_t)e));
+    launch_copy_rows(m->brow.ptr, ldb, mm, n_idx, MTP_FP64, rows, S(stream));
+    API_END
+}
+
+int mtp_select(const double *gamma, int64_t n, double threshold, int32_t *idx, int32_t capacity, int32_t *count,
+               void *stream) {
+    API_BEGIN
+    MTP_CHECK(gamma && idx && count, MTP_E_INVAL, "NULL argument");
+    MTP_CHECK(n >= 0 && capacity >= 0, MTP_E_INVAL, "negative size");
+    static thread_local DevBuf work;
+    launch_select(gamma, n, threshold, idx, capacity, count, S(stream), work);
+    API_END
+}
+
+int mtp_maxvol_update(mtp_model *m, mtp_grade_mode g, double *cand, int64_t n_cand, double threshold,
+                      int32_t max_swaps, int32_t *swap_cand, int32_t *swap_col, int32_t *n_swaps, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m && n_swaps, MTP_E_INVAL, "NULL argument");
+    MTP_CHECK(g == MTP_GRADE_FULL || g == MTP_GRADE_LINEAR, MTP_E_INVAL, "bad grade mode");
+    MTP_CHECK(threshold > 1.0, MTP_E_INVAL, "threshold must exceed 1");
+    MTP_CHECK(n_cand >= 0 && max_swaps >= 0, MTP_E_INVAL, "negative size");
+    MTP_CHECK(n_cand == 0 || cand, MTP_E_INVAL, "cand is NULL");
+    MTP_CHECK(max_swaps == 0 || (swap_cand && swap_col), MTP_E_INVAL, "swap log is NULL");
+    ActiveSet &as = m->act[g];
+    MTP_CHECK(as.valid, MTP_E_INVAL, "no active set for this mode");
+    MTP_HIP(hipSetDevice(m->device));
+    *n_swaps = 0;
+    if (n_cand == 0 || max_swaps == 0) return MTP_OK;
+    run_maxvol(as, cand, n_cand, threshold, max_swaps, swap_cand, swap_col, n_swaps, S(stream), m->work);
+    API_END
+}
+
+int mtp_efs_backward(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, const double *gE,
+                     const double *gF, const double *gS, double *g_theta, void *stream) {
+    API_BEGIN
+    (void)m; (void)s; (void)nb; (void)p; (void)gE; (void)gF; (void)gS; (void)g_theta; (void)stream;
+    throw Error{MTP_E_UNSUPPORTED, "mtp_efs_backward is not available in this build"};
+    API_END
+}
+
+int mtp_basis_describe(int32_t level, char *buf, size_t len, int32_t *n_lin) {
+    API_BEGIN
+    Basis b = build_basis(level);
+    std::string d = b.describe();
+    if (n_lin) *n_lin = b.n_lin();
+    if (buf && len) {
+        const size_t k = std::min(len - 1, d.size());
+        std::memcpy(buf, d.data(), k);
+        buf[k] = 0;
+        MTP_CHECK(d.size() < len, MTP_E_INVAL, "buffer too small: need " + std::to_string(d.size() + 1));
+    }
+    API_END
+}
+
+int mtp_compiled_levels(int32_t *levels, int32_t cap) {
+    auto lv = compiled_levels();
+    for (int k = 0; k < (int)lv.size() && k < cap; ++k) levels[k] = lv[k];
+    return (int)lv.size();
+}
+
+}  // extern "C"

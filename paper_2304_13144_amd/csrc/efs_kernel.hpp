@@ -1,0 +1,296 @@
+// Fused per-neighborhood kernel: radial functions -> moments -> contraction
+// -> site energy -> dV/dM -> pair gradients, virial and (optionally) the row
+// b_i = dV_i/dtheta.  Included by one generated translation unit per level.
+//
+// Work decomposition: LANES consecutive lanes of a wavefront share one
+// neighborhood.  Each lane walks every LANES-th pair of the list and keeps
+// its own partial moments in registers; a butterfly of cross-lane shuffles
+// then gives every lane the full moments.  The contraction program (Level<L>,
+// generated at build time) runs in registers.  The pair loop is walked a
+// second time for the gradients, one neighbor species after the other, so
+// the radial-coefficient part of b_i needs only N_rad x N_polyn accumulators.
+//
+// Pair gradient (paper eqs. 3-4; V from eq. 2):
+//   g_ij = dV_i/dr_ij = sum_mu [ f'_mu(r) P_mu r_hat + f_mu(r) grad P_mu ],
+//   P_mu(r) = sum_{k in mu} (dV/dM_k) x^a y^b z^c  (k = component (mu; a,b,c)).
+// b-row entries of c (eq. 4): dV_i/dc^(beta)_{mu,z_i,z} = sum_{j: z_j = z} Q_beta(r_ij) P_mu(r_ij),
+// Q_beta = T_beta(x) (R_cut - r)^2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace mtp {
+
+template <int L> struct Level;
+
+namespace efs {
+
+template <typename T> __device__ inline T xor_shuffle(T v, int mask) { return __shfl_xor(v, mask, 64); }
+
+// monomials x^a y^b z^c, a+b+c <= 3, in the order of monomial_index()
+template <typename T> __device__ inline void monomials(T x, T y, T z, T (&m)[20]) {
+    m[0] = T(1); m[1] = x; m[2] = y; m[3] = z;
+    m[4] = x * x; m[5] = x * y; m[6] = x * z; m[7] = y * y; m[8] = y * z; m[9] = z * z;
+    m[10] = m[4] * x; m[11] = m[4] * y; m[12] = m[4] * z; m[13] = m[7] * x; m[14] = m[5] * z;
+    m[15] = m[9] * x; m[16] = m[7] * y; m[17] = m[7] * z; m[18] = m[9] * y; m[19] = m[9] * z;
+}
+
+}  // namespace efs
+
+template <typename T, int L, int K, bool WB>
+__global__ __launch_bounds__(256) void efs_kernel(const EfsArgs a) {
+    using LV = Level<L>;
+    constexpr int NC = LV::NC, NR = LV::NRAD, NL = LV::NLIN;
+    __shared__ T c_s[NR * MAX_TYPES * MAX_TYPES * NPOLY];
+    const int nt = a.n_types;
+    {
+        const T *cg = static_cast<const T *>(a.c);
+        const int ncoef = NR * nt * nt * NPOLY;
+        for (int k = threadIdx.x; k < ncoef; k += blockDim.x) c_s[k] = cg[k];
+    }
+    __syncthreads();
+
+    const int sub = threadIdx.x % K;
+    const int64_t slot = (int64_t)blockIdx.x * (blockDim.x / K) + threadIdx.x / K;
+    const bool live = slot < a.n_atoms;
+    const int64_t atom = live ? (a.atom_list ? (int64_t)a.atom_list[slot] : slot) : 0;
+    int zi = live ? a.type[atom] : 0;
+    zi = zi < 0 ? 0 : (zi >= nt ? nt - 1 : zi);
+    int tc[MAX_TYPES];
+    int ntot = 0;
+#pragma unroll
+    for (int t = 0; t < MAX_TYPES; ++t) {
+        tc[t] = (live && t < nt) ? a.tcnt[atom * nt + t] : 0;
+        ntot += tc[t];
+    }
+    const double *rp = a.r + atom * (int64_t)a.max_nbrs * 3;
+    const T rc = T(a.r_cut);
+    const T xs = T(2.0 / (a.r_cut - a.r_min));
+    const T x0 = T(-(a.r_min + a.r_cut) / (a.r_cut - a.r_min));
+
+    // ---- moments (eq. 3) ------------------------------------------------
+    T M[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) M[k] = T(0);
+    {
+        int zj = 0, tend = tc[0];
+        for (int p = sub; p < ntot; p += K) {
+            while (p >= tend && zj < nt - 1) tend += tc[++zj];
+            const T x = T(rp[3 * p]), y = T(rp[3 * p + 1]), z = T(rp[3 * p + 2]);
+            const T r = sqrt(x * x + y * y + z * z);
+            if (!(r < rc)) continue;
+            T fm[NR];
+#pragma unroll
+            for (int mu = 0; mu < NR; ++mu) fm[mu] = T(0);
+            {
+                T u = fma(r, xs, x0), d = rc - r, cut = d * d;
+                T Tb[NPOLY];
+                Tb[0] = T(1);
+                Tb[1] = u;
+#pragma unroll
+                for (int b = 2; b < NPOLY; ++b) Tb[b] = fma(T(2) * u, Tb[b - 1], -Tb[b - 2]);
+#pragma unroll
+                for (int mu = 0; mu < NR; ++mu) {
+                    const T *cm = c_s + ((mu * nt + zi) * nt + zj) * NPOLY;
+                    T s = T(0);
+#pragma unroll
+                    for (int b = 0; b < NPOLY; ++b) s = fma(cm[b], Tb[b], s);
+                    fm[mu] = s * cut;
+                }
+            }
+            T mono[20];
+            efs::monomials(x, y, z, mono);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) M[k] = fma(fm[LV::comp_mu[k]], mono[LV::comp_mono[k]], M[k]);
+        }
+    }
+#pragma unroll
+    for (int o = K / 2; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) M[k] += efs::xor_shuffle(M[k], o);
+
+    // ---- contraction, site energy (eq. 2), dV/dM ------------------------
+    T dM[NC];
+    T V = T(0);
+    T *brow = (WB && live) ? static_cast<T *>(a.brow) + slot * (int64_t)a.ldb : nullptr;
+    if (live) {
+        LV::template contract<T, WB>(M, static_cast<const T *>(a.xi), brow ? brow + nt : nullptr, dM, V);
+    } else {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) dM[k] = T(0);
+    }
+    if (live && sub == 0 && a.site_e) a.site_e[atom] = double(V) + double(static_cast<const T *>(a.xi0)[zi]);
+
+    // ---- pair gradients, virial, b-row c part ---------------------------
+    T vir[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) vir[k] = T(0);
+    T *gout = static_cast<T *>(a.gbuf);
+    const bool full_rows = WB && a.grade_mode == MTP_GRADE_FULL;
+    int gstart = 0;
+    for (int t = 0; t < nt; ++t) {
+        T dc[NR][NPOLY];
+#pragma unroll
+        for (int mu = 0; mu < NR; ++mu)
+#pragma unroll
+            for (int b = 0; b < NPOLY; ++b) dc[mu][b] = T(0);
+        for (int q = sub; q < tc[t]; q += K) {
+            const int p = gstart + q;
+            const T x = T(rp[3 * p]), y = T(rp[3 * p + 1]), z = T(rp[3 * p + 2]);
+            const T r = sqrt(x * x + y * y + z * z);
+            T g0 = T(0), g1 = T(0), g2 = T(0);
+            if (r < rc) {
+                T f[NR], fp[NR], Q[NPOLY];
+                // radial functions and derivatives for the pair species (zi, t)
+                {
+                    const T u = fma(r, xs, x0);
+                    const T d = rc - r;
+                    const T cut = d * d;
+                    const T dcut = T(-2) * d;
+                    T Tb[NPOLY], dT[NPOLY];
+                    Tb[0] = T(1);
+                    Tb[1] = u;
+                    dT[0] = T(0);
+                    dT[1] = T(1);
+#pragma unroll
+                    for (int b = 2; b < NPOLY; ++b) {
+                        Tb[b] = fma(T(2) * u, Tb[b - 1], -Tb[b - 2]);
+                        dT[b] = fma(T(2) * u, dT[b - 1], fma(T(2), Tb[b - 1], -dT[b - 2]));
+                    }
+#pragma unroll
+                    for (int b = 0; b < NPOLY; ++b) Q[b] = Tb[b] * cut;
+#pragma unroll
+                    for (int mu = 0; mu < NR; ++mu) {
+                        const T *cm = c_s + ((mu * nt + zi) * nt + t) * NPOLY;
+                        T s = T(0), sp = T(0);
+#pragma unroll
+                        for (int b = 0; b < NPOLY; ++b) {
+                            s = fma(cm[b], Tb[b], s);
+                            sp = fma(cm[b], dT[b], sp);
+                        }
+                        f[mu] = s * cut;
+                        fp[mu] = fma(sp * xs, cut, s * dcut);
+                    }
+                }
+                T mono[20];
+                efs::monomials(x, y, z, mono);
+                T P[NR], Gx[NR], Gy[NR], Gz[NR];
+#pragma unroll
+                for (int mu = 0; mu < NR; ++mu) P[mu] = Gx[mu] = Gy[mu] = Gz[mu] = T(0);
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    const int mu = LV::comp_mu[k];
+                    P[mu] = fma(dM[k], mono[LV::comp_mono[k]], P[mu]);
+                    if (LV::comp_dmonox[k] >= 0)
+                        Gx[mu] = fma(dM[k] * T(LV::comp_dfacx[k]), mono[LV::comp_dmonox[k] < 0 ? 0 : LV::comp_dmonox[k]], Gx[mu]);
+                    if (LV::comp_dmonoy[k] >= 0)
+                        Gy[mu] = fma(dM[k] * T(LV::comp_dfacy[k]), mono[LV::comp_dmonoy[k] < 0 ? 0 : LV::comp_dmonoy[k]], Gy[mu]);
+                    if (LV::comp_dmonoz[k] >= 0)
+                        Gz[mu] = fma(dM[k] * T(LV::comp_dfacz[k]), mono[LV::comp_dmonoz[k] < 0 ? 0 : LV::comp_dmonoz[k]], Gz[mu]);
+                }
+                const T rinv = T(1) / r;
+                T radial_part = T(0);
+#pragma unroll
+                for (int mu = 0; mu < NR; ++mu) {
+                    radial_part = fma(fp[mu], P[mu], radial_part);
+                    g0 = fma(f[mu], Gx[mu], g0);
+                    g1 = fma(f[mu], Gy[mu], g1);
+                    g2 = fma(f[mu], Gz[mu], g2);
+                }
+                radial_part *= rinv;
+                g0 = fma(radial_part, x, g0);
+                g1 = fma(radial_part, y, g1);
+                g2 = fma(radial_part, z, g2);
+                if (full_rows) {
+#pragma unroll
+                    for (int mu = 0; mu < NR; ++mu)
+#pragma unroll
+                        for (int b = 0; b < NPOLY; ++b) dc[mu][b] = fma(Q[b], P[mu], dc[mu][b]);
+                }
+                // S_ab = -sum g_a r_b
+                vir[0] -= g0 * x; vir[1] -= g0 * y; vir[2] -= g0 * z;
+                vir[3] -= g1 * x; vir[4] -= g1 * y; vir[5] -= g1 * z;
+                vir[6] -= g2 * x; vir[7] -= g2 * y; vir[8] -= g2 * z;
+            }
+            if (gout) {
+                const int64_t s3 = (atom * (int64_t)a.max_nbrs + p) * 3;
+                gout[s3] = g0;
+                gout[s3 + 1] = g1;
+                gout[s3 + 2] = g2;
+            }
+        }
+        if (full_rows) {
+#pragma unroll
+            for (int o = K / 2; o > 0; o >>= 1)
+#pragma unroll
+                for (int mu = 0; mu < NR; ++mu)
+#pragma unroll
+                    for (int b = 0; b < NPOLY; ++b) dc[mu][b] += efs::xor_shuffle(dc[mu][b], o);
+            if (brow && sub == 0) {
+                const int base = nt + NL;
+#pragma unroll
+                for (int mu = 0; mu < NR; ++mu)
+#pragma unroll
+                    for (int b = 0; b < NPOLY; ++b) {
+                        const int col = a.colmap[base + ((mu * nt + zi) * nt + t) * NPOLY + b];
+                        if (col >= 0) brow[col] = dc[mu][b];
+                    }
+            }
+        }
+        gstart += tc[t];
+    }
+#pragma unroll
+    for (int o = K / 2; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) vir[k] += efs::xor_shuffle(vir[k], o);
+    if (live && sub == 0 && a.virial) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) a.virial[atom * 9 + k] = double(vir[k]);
+    }
+    if (brow) {
+        // species one-hot, zero c blocks of the other central species, zero padding
+        for (int k = sub; k < nt; k += K) brow[k] = T(k == zi ? 1 : 0);
+        if (full_rows) {
+            const int base = nt + NL;
+            const int nblk = NR * nt * nt * NPOLY;
+            for (int k = sub; k < nblk; k += K) {
+                const int zz = (k / (nt * NPOLY)) % nt;
+                if (zz == zi) continue;
+                const int col = a.colmap[base + k];
+                if (col >= 0) brow[col] = T(0);
+            }
+        }
+        for (int k = a.m + sub; k < a.ldb; k += K) brow[k] = T(0);
+    }
+}
+
+template <int L> int launch_efs_level(const EfsArgs &a);
+
+// instantiates the launcher of one level (used by the generated units)
+#define MTP_EFS_LEVEL(LEVEL)                                                                             \
+    template <typename T, int K, bool WB> static void launch_efs_tk##LEVEL(const EfsArgs &a) {           \
+        const int per = 256 / K;                                                                         \
+        const unsigned grid = (unsigned)((a.n_atoms + per - 1) / per);                                   \
+        if (grid == 0) return;                                                                           \
+        hipLaunchKernelGGL((efs_kernel<T, LEVEL, K, WB>), dim3(grid), dim3(256), 0, a.stream, a);       \
+    }                                                                                                    \
+    template <typename T, bool WB> static void launch_efs_t##LEVEL(const EfsArgs &a) {                   \
+        switch (a.lanes) {                                                                               \
+            case 2: launch_efs_tk##LEVEL<T, 2, WB>(a); break;                                            \
+            case 4: launch_efs_tk##LEVEL<T, 4, WB>(a); break;                                            \
+            default: launch_efs_tk##LEVEL<T, 8, WB>(a); break;                                           \
+        }                                                                                                \
+    }                                                                                                    \
+    template <> int launch_efs_level<LEVEL>(const EfsArgs &a) {                                          \
+        const bool wb = a.brow != nullptr;                                                               \
+        if (a.precision == MTP_FP64) {                                                                   \
+            if (wb) launch_efs_t##LEVEL<double, true>(a); else launch_efs_t##LEVEL<double, false>(a);    \
+        } else {                                                                                         \
+            if (wb) launch_efs_t##LEVEL<float, true>(a); else launch_efs_t##LEVEL<float, false>(a);      \
+        }                                                                                                \
+        return (int)hipGetLastError();                                                                   \
+    }
+
+}  // namespace mtp

@@ -1,0 +1,139 @@
+// Internal state and launch interfaces of libmtp (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mtp.h"
+#include "basis.hpp"
+
+namespace mtp {
+
+// ---- errors ---------------------------------------------------------------
+void set_error(const std::string &msg);
+struct Error {
+    int code;
+    std::string msg;
+};
+#define MTP_HIP(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            throw ::mtp::Error{MTP_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)};      \
+    } while (0)
+#define MTP_CHECK(cond, code, msg)                                                                 \
+    do {                                                                                           \
+        if (!(cond)) throw ::mtp::Error{(code), (msg)};                                            \
+    } while (0)
+
+// ---- device buffers -------------------------------------------------------
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    void ensure(size_t n);   // grows (no shrink); contents not preserved
+    void release();
+    template <typename T> T *as() const { return static_cast<T *>(ptr); }
+    ~DevBuf() { release(); }
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+};
+
+constexpr int NPOLY = 8;     // Chebyshev polynomials per radial function
+constexpr int MAX_TYPES = 4;
+
+struct ActiveSet {
+    int m = 0;
+    bool valid = false;
+    DevBuf A;        // m*m FP64 rows
+    DevBuf Ainv;     // m*m FP64
+    DevBuf Ainv32;   // split copies for the mixed grade product (see grade.hip)
+};
+
+}  // namespace mtp
+
+struct mtp_model {
+    int device = 0;
+    int level = 0, n_types = 0;
+    double r_min = 0, r_cut = 0;
+    mtp::Basis basis;
+    int n_theta = 0;
+    std::vector<double> theta_host;
+    std::vector<int> kept;          // FULL-mode kept columns
+    std::vector<int> colmap_host;   // full column -> kept column or -1
+    mtp::DevBuf theta64, theta32, colmap;
+    mtp::ActiveSet act[2];          // [MTP_GRADE_FULL], [MTP_GRADE_LINEAR]
+    // scratch of the evaluation path
+    mutable mtp::DevBuf gbuf, virial, sitebuf, brow, gamma_ws, argmax_ws, work;
+    int m_of(int mode) const { return mode == MTP_GRADE_FULL ? (int)kept.size() : n_types + basis.n_lin(); }
+};
+
+struct mtp_nbrs {
+    int device = -1;
+    int64_t n_atoms = 0;
+    int32_t n_cfg = 0;
+    int max_nbrs = 0, n_types = 0;
+    double r_cut = 0;
+    mtp::DevBuf r;        // [N*maxn*3] FP64 r_ij
+    mtp::DevBuf j;        // [N*maxn] int32
+    mtp::DevBuf shift;    // [N*maxn] int32 packed (3 x int8, x in the low byte)
+    mtp::DevBuf rev;      // [N*maxn] int32 flat index of (j, i, -n)
+    mtp::DevBuf tcnt;     // [N*n_types] int32 neighbors per species
+    mtp::DevBuf atom_cfg; // [N] int32
+    mtp::DevBuf cfg_geo;  // per cfg geometry (see neighbors.hip)
+    mtp::DevBuf bin_count, bin_start, bin_cursor, bin_atoms, atom_bin, atom_wrap, work_sums;
+    mtp::DevBuf flags;    // [4] int32: overflow, max count, overlap, spare
+    int64_t bins_cap = 0;
+};
+
+namespace mtp {
+
+// ---- launchers ------------------------------------------------------------
+struct EfsArgs {
+    int64_t n_atoms;          // atoms processed (= list length if atom_list)
+    const int32_t *atom_list; // optional: process these atoms
+    int n_types, max_nbrs;
+    const double *r;          // pair vectors
+    const int32_t *tcnt;
+    const int32_t *type;
+    double r_min, r_cut;
+    const void *xi0, *xi, *c; // precision-typed parameter arrays
+    // outputs (nullable)
+    double *site_e;           // [n_atoms]
+    void *gbuf;               // [N*maxn*3] T  (pair gradients dV_i/dr_ij)
+    double *virial;           // [n_atoms*9]
+    void *brow;               // [n_atoms*ldb] T
+    int ldb;
+    int grade_mode;           // rows layout: FULL (with colmap) or LINEAR
+    const int32_t *colmap;    // full column -> kept column or -1
+    int m;                    // row length written (kept columns)
+    int precision;
+    int lanes;                // lanes per neighborhood (2, 4, 8)
+    hipStream_t stream;
+};
+int launch_efs(int level, const EfsArgs &a);
+std::vector<int> compiled_levels();
+
+void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_nbrs *nb, hipStream_t st);
+
+void launch_force_gather(const mtp_nbrs *nb, const void *gbuf, int precision, double *forces, hipStream_t st);
+void launch_cfg_sums(const mtp_system *s, const double *site_e, const double *virial, double *energy,
+                     double *stress, hipStream_t st);
+
+// grade: C = brow * Ainv (ld ldb), gamma/argmax per row
+void launch_grade(const ActiveSet &as, int precision, const void *brow, int ldb, int64_t n, double *gamma,
+                  int32_t *argmax, hipStream_t st);
+void prepare_split(ActiveSet &as, hipStream_t st);
+int split_terms();
+void launch_invert(ActiveSet &as, const double *A, hipStream_t st, DevBuf &work, int *singular_host);
+void launch_select(const double *gamma, int64_t n, double thr, int32_t *idx, int32_t cap, int32_t *count,
+                   hipStream_t st, DevBuf &work);
+void run_maxvol(ActiveSet &as, double *cand, int64_t n_cand, double thr, int max_swaps, int32_t *swap_cand,
+                int32_t *swap_col, int32_t *n_swaps, hipStream_t st, DevBuf &work);
+void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision, void *dst, hipStream_t st);
+void launch_zero(void *p, size_t bytes, hipStream_t st);
+
+}  // namespace mtp

@@ -1,0 +1,172 @@
+// Reductions and helpers of the evaluation path: force gather, per
+// configuration energy / stress sums, row copies, preselection compaction.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace mtp {
+namespace {
+
+__global__ void zero_kernel(uint32_t *p, size_t n_words) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_words) p[i] = 0u;
+}
+
+// F_l = sum_{p in list(l)} (g_p - g_rev(p)): the first sum is -dV_l/dx_l, the
+// second collects dV_i/dx_l over every neighborhood i that holds l (or an
+// image of l).  Fixed order, no atomics: results are bitwise reproducible.
+template <typename T>
+__global__ void force_gather(int64_t n, int nt, int maxn, const int32_t *tcnt, const int32_t *rev, const T *g,
+                             double *F) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int tot = 0;
+    for (int t = 0; t < nt; ++t) tot += tcnt[i * nt + t];
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int p = 0; p < tot; ++p) {
+        const int64_t s = i * maxn + p;
+        const int64_t q = rev[s];
+        fx += double(g[3 * s]) - double(g[3 * q]);
+        fy += double(g[3 * s + 1]) - double(g[3 * q + 1]);
+        fz += double(g[3 * s + 2]) - double(g[3 * q + 2]);
+    }
+    F[3 * i] = fx;
+    F[3 * i + 1] = fy;
+    F[3 * i + 2] = fz;
+}
+
+// E_c = sum_i V_i and S_c = sum_i W_i over the atoms of configuration c
+// (eq. 1); FP64, fixed summation order.
+constexpr int SUM_T = 256;
+__global__ void cfg_sums(const int64_t *cfg_off, const double *site_e, const double *vir, double *energy,
+                         double *stress) {
+    const int c = blockIdx.x;
+    const int64_t b = cfg_off[c], e = cfg_off[c + 1];
+    double acc[10];
+    for (int k = 0; k < 10; ++k) acc[k] = 0.0;
+    for (int64_t i = b + threadIdx.x; i < e; i += SUM_T) {
+        if (site_e) acc[0] += site_e[i];
+        if (vir)
+            for (int k = 0; k < 9; ++k) acc[1 + k] += vir[9 * i + k];
+    }
+    __shared__ double s[10][SUM_T];
+    for (int k = 0; k < 10; ++k) s[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = SUM_T / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 10; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (energy) energy[c] = s[0][0];
+        if (stress)
+            for (int k = 0; k < 9; ++k) stress[9 * c + k] = s[1 + k][0];
+    }
+}
+
+template <typename T>
+__global__ void copy_rows(const T *src, int ldb, int m, int64_t n, T *dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * m) return;
+    const int64_t r = i / m, c = i % m;
+    dst[i] = src[r * ldb + c];
+}
+
+// preselection: indices with gamma > thr in ascending order
+constexpr int SEL_T = 256;
+__global__ void sel_count(const double *g, int64_t n, double thr, int32_t *blk) {
+    __shared__ int32_t s[SEL_T];
+    const int64_t i = (int64_t)blockIdx.x * SEL_T + threadIdx.x;
+    s[threadIdx.x] = (i < n && g[i] > thr) ? 1 : 0;
+    __syncthreads();
+    for (int w = SEL_T / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) blk[blockIdx.x] = s[0];
+}
+
+__global__ void sel_scan(int32_t *blk, int64_t nb, int32_t *count) {
+    if (threadIdx.x != 0) return;
+    int32_t run = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int32_t v = blk[b];
+        blk[b] = run;
+        run += v;
+    }
+    *count = run;
+}
+
+__global__ void sel_write(const double *g, int64_t n, double thr, const int32_t *blk, int32_t *idx, int32_t cap,
+                          int32_t *count) {
+    __shared__ int32_t s[SEL_T];
+    const int64_t i = (int64_t)blockIdx.x * SEL_T + threadIdx.x;
+    const int flag = (i < n && g[i] > thr) ? 1 : 0;
+    s[threadIdx.x] = flag;
+    __syncthreads();
+    for (int d = 1; d < SEL_T; d <<= 1) {
+        const int32_t t = (int)threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (flag) {
+        const int32_t pos = blk[blockIdx.x] + s[threadIdx.x] - 1;
+        if (pos < cap) idx[pos] = (int32_t)i;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && *count > cap) *count = cap;
+}
+
+}  // namespace
+
+void launch_zero(void *p, size_t bytes, hipStream_t st) {
+    const size_t w = (bytes + 3) / 4;
+    if (!w) return;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((w + 255) / 256)), dim3(256), 0, st, static_cast<uint32_t *>(p), w);
+}
+
+void launch_force_gather(const mtp_nbrs *nb, const void *gbuf, int precision, double *forces, hipStream_t st) {
+    const int64_t n = nb->n_atoms;
+    if (!n) return;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (precision == MTP_FP64)
+        hipLaunchKernelGGL(force_gather<double>, grid, dim3(256), 0, st, n, nb->n_types, nb->max_nbrs,
+                           nb->tcnt.as<int32_t>(), nb->rev.as<int32_t>(), static_cast<const double *>(gbuf), forces);
+    else
+        hipLaunchKernelGGL(force_gather<float>, grid, dim3(256), 0, st, n, nb->n_types, nb->max_nbrs,
+                           nb->tcnt.as<int32_t>(), nb->rev.as<int32_t>(), static_cast<const float *>(gbuf), forces);
+}
+
+void launch_cfg_sums(const mtp_system *s, const double *site_e, const double *virial, double *energy, double *stress,
+                     hipStream_t st) {
+    if (s->n_cfg <= 0) return;
+    hipLaunchKernelGGL(cfg_sums, dim3(s->n_cfg), dim3(SUM_T), 0, st, s->cfg_off, site_e, virial, energy, stress);
+}
+
+void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision, void *dst, hipStream_t st) {
+    const int64_t tot = n * m;
+    if (!tot) return;
+    const dim3 grid((unsigned)((tot + 255) / 256));
+    if (precision == MTP_FP64)
+        hipLaunchKernelGGL(copy_rows<double>, grid, dim3(256), 0, st, static_cast<const double *>(src), ldb, m, n,
+                           static_cast<double *>(dst));
+    else
+        hipLaunchKernelGGL(copy_rows<float>, grid, dim3(256), 0, st, static_cast<const float *>(src), ldb, m, n,
+                           static_cast<float *>(dst));
+}
+
+void launch_select(const double *gamma, int64_t n, double thr, int32_t *idx, int32_t cap, int32_t *count,
+                   hipStream_t st, DevBuf &work) {
+    const int64_t nb = (n + SEL_T - 1) / SEL_T;
+    work.ensure(sizeof(int32_t) * (nb > 0 ? nb : 1));
+    if (n == 0) {
+        launch_zero(count, sizeof(int32_t), st);
+        return;
+    }
+    hipLaunchKernelGGL(sel_count, dim3((unsigned)nb), dim3(SEL_T), 0, st, gamma, n, thr, work.as<int32_t>());
+    hipLaunchKernelGGL(sel_scan, dim3(1), dim3(64), 0, st, work.as<int32_t>(), nb, count);
+    hipLaunchKernelGGL(sel_write, dim3((unsigned)nb), dim3(SEL_T), 0, st, gamma, n, thr, work.as<int32_t>(), idx, cap,
+                       count);
+}
+
+}  // namespace mtp

@@ -1,0 +1,342 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars (written per test): FP64 form within 1e-10 relative (norm-wise: max
+|diff| / max |oracle|); mixed form with forces within 1e-4 eV/A and gamma
+within 1e-5 max(1, gamma); neighbor lists bit-exact as sets.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mtp as om
+from oracle import neighbors as onb
+from paper_2304_13144_amd import api, synth
+from tests.helpers import active_rows, oracle_local_forces, potential, rel_err, theta_for
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+
+
+def _model(w, theta, modes=("full", "linear")):
+    m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
+    m.set_params(theta)
+    keep = m.kept_columns()
+    if "full" in modes:
+        m.set_active_set("full", active_rows(w.wid, "full")[:, keep])
+    if "linear" in modes:
+        m.set_active_set("linear", active_rows(w.wid, "linear"))
+    return m, keep
+
+
+def _nbr_sets(count, j, sh, atoms):
+    out = {}
+    for a in atoms:
+        c = int(count[a])
+        out[a] = sorted((int(j[a, q]),) + tuple(int(v) for v in sh[a, q]) for q in range(c))
+    return out
+
+
+def _oracle_sets(pairs, atoms):
+    out = {a: [] for a in atoms}
+    for i, j, s in zip(pairs.i, pairs.j, pairs.shift):
+        if int(i) in out:
+            out[int(i)].append((int(j),) + tuple(int(v) for v in s))
+    return {a: sorted(v) for a, v in out.items()}
+
+
+# ------------------------------------------------------------ neighbors ----
+def _configs_for_neighbors():
+    r = np.random.default_rng(5)
+    out = []
+    w1 = synth.workload1()
+    out.append(("bcc128", w1.configs[0], 1))
+    tri = synth.Config(np.array([[0.1, 0.2, 0.3], [1.7, 1.1, 0.9], [0.4, 2.5, 1.9]]),
+                       np.array([0, 1, 1], np.int32),
+                       np.array([[3.1, 0, 0], [0.9, 2.9, 0], [0.4, -0.7, 3.3]]))
+    out.append(("triclinic_small", tri, 2))
+    slab = synth.Config(r.random((40, 3)) @ np.diag([9.0, 9.5, 20.0]), r.integers(0, 2, 40).astype(np.int32),
+                        np.diag([9.0, 9.5, 20.0]), (True, True, False))
+    out.append(("slab_xy", slab, 2))
+    return out
+
+
+@pytest.mark.parametrize("case", ["bcc128", "triclinic_small", "slab_xy"])
+def test_neighbors_match_oracle(case):
+    name, cfg, nt = [c for c in _configs_for_neighbors() if c[0] == case][0]
+    m = api.Model.create(8, nt, 2.0, 5.0)
+    b = api.Batch([cfg])
+    nb = api.Neighbors().build(m, b, max_nbrs=256)
+    count, j, sh = (t.cpu().numpy() for t in nb.export(b))
+    pairs = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, 5.0)
+    atoms = list(range(cfg.n))
+    assert _nbr_sets(count, j, sh, atoms) == _oracle_sets(pairs, atoms)
+
+
+def test_neighbors_batched_configs_match_oracle():
+    cfgs = [c for _, c, _ in _configs_for_neighbors()]
+    m = api.Model.create(8, 2, 2.0, 5.0)
+    b = api.Batch(cfgs)
+    nb = api.Neighbors().build(m, b, max_nbrs=256)
+    count, j, sh = (t.cpu().numpy() for t in nb.export(b))
+    off = b.cfg_off_host
+    for k, cfg in enumerate(cfgs):
+        pairs = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, 5.0)
+        atoms = list(range(cfg.n))
+        got = _nbr_sets(count, j - off[k], sh, [a + off[k] for a in atoms])
+        got = {a - off[k]: v for a, v in got.items()}
+        assert got == _oracle_sets(pairs, atoms)
+
+
+def test_neighbors_full_size_workload2_sampled():
+    w = synth.workload2()
+    cfg = w.configs[0]
+    m = api.Model.create(16, 2, 2.0, 5.0)
+    b = api.Batch([cfg])
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    count, j, sh = (t.cpu().numpy() for t in nb.export(b))
+    atoms = list(np.random.default_rng(6).choice(cfg.n, 48, replace=False)) + [0, cfg.n - 1]
+    pairs = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, 5.0, atoms=atoms)
+    assert _nbr_sets(count, j, sh, atoms) == _oracle_sets(pairs, atoms)
+
+
+def test_neighbor_capacity_and_overlap_are_reported():
+    w = synth.workload1()
+    m = api.Model.create(8, 1, 2.0, 5.0)
+    b = api.Batch(w.configs)
+    with pytest.raises(api.MtpError) as e:
+        api.Neighbors().build(m, b, max_nbrs=8)
+    assert e.value.status == "MTP_E_CAPACITY"
+    cfg = w.configs[0]
+    pos = cfg.pos.copy()
+    pos[1] = pos[0]
+    b2 = api.Batch([synth.Config(pos, cfg.types, cfg.cell)])
+    with pytest.raises(api.MtpError) as e:
+        api.Neighbors().build(m, b2, max_nbrs=64)
+    assert e.value.status == "MTP_E_OVERLAP"
+
+
+# ---------------------------------------------------------------- EFS ------
+def _efs_case(w, cfg, theta, precision, lanes=None, monkeypatch=None):
+    m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
+    m.set_params(theta)
+    b = api.Batch([cfg])
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    out = api.energy_forces_stress(m, b, nb, precision)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def test_efs_fp64_workload1_matches_oracle():
+    w = synth.workload1()
+    pot = potential(w)
+    theta = theta_for(1, pot)
+    cfg = w.configs[0]
+    pairs = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, w.r_cut)
+    E, F, S, V = om.energy_forces_stress(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs)
+    g = _efs_case(w, cfg, theta, "fp64")
+    assert rel_err(g["energy"][0], E) <= FP64_TOL
+    assert rel_err(g["site_e"], V) <= FP64_TOL
+    assert rel_err(g["forces"], F) <= FP64_TOL
+    assert rel_err(g["stress"][0], S) <= FP64_TOL
+
+
+@pytest.mark.parametrize("lanes", ["2", "4", "8"])
+def test_efs_fp64_level16_two_species_small(lanes, monkeypatch):
+    monkeypatch.setenv("MTP_LANES", lanes)
+    w = synth.workload2(reps=(4, 4, 4))
+    pot = potential(w)
+    theta = theta_for(2, pot)
+    cfg = w.configs[0]
+    pairs = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, w.r_cut)
+    E, F, S, V = om.energy_forces_stress(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs)
+    g = _efs_case(w, cfg, theta, "fp64")
+    assert rel_err(g["energy"][0], E) <= FP64_TOL
+    assert rel_err(g["site_e"], V) <= FP64_TOL
+    assert rel_err(g["forces"], F) <= FP64_TOL
+    assert rel_err(g["stress"][0], S) <= FP64_TOL
+
+
+def test_efs_mixed_level16_two_species_small():
+    w = synth.workload2(reps=(4, 4, 4))
+    pot = potential(w)
+    theta = theta_for(2, pot)
+    cfg = w.configs[0]
+    pairs = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, w.r_cut)
+    E, F, S, V = om.energy_forces_stress(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs)
+    g = _efs_case(w, cfg, theta, "mixed")
+    print("mixed errors: E %.3g  F %.3g eV/A  S %.3g" % (abs(g["energy"][0] - E), np.abs(g["forces"] - F).max(),
+                                                         np.abs(g["stress"][0] - S).max()))
+    assert np.abs(g["forces"] - F).max() <= 1e-4
+    assert abs(g["energy"][0] - E) <= 1e-6 * max(1.0, abs(E)) * cfg.n
+    assert np.abs(g["stress"][0] - S).max() <= 1e-5 * max(1.0, np.abs(S).max())
+
+
+def test_efs_full_size_workload2_sampled():
+    """Full 16,384-atom alloy in the benchmark's launch configuration; oracle on
+    sampled atoms (site energies and forces), plus properties of the sums."""
+    w = synth.workload2()
+    pot = potential(w)
+    theta = theta_for(2, pot)
+    cfg = w.configs[0]
+    atoms = np.sort(np.random.default_rng(7).choice(cfg.n, 24, replace=False))
+    Fo, Vo = oracle_local_forces(pot, theta, cfg, atoms)
+    for prec, ftol in (("fp64", None), ("mixed", 1e-4)):
+        g = _efs_case(w, cfg, theta, prec)
+        if ftol is None:
+            assert rel_err(g["site_e"][atoms], Vo) <= FP64_TOL
+            assert rel_err(g["forces"][atoms], Fo) <= FP64_TOL
+            assert abs(g["energy"][0] - g["site_e"].sum()) <= 1e-12 * np.abs(g["site_e"]).sum()
+        else:
+            assert np.abs(g["forces"][atoms] - Fo).max() <= ftol
+        assert np.abs(g["forces"].sum(axis=0)).max() <= 1e-6 * np.abs(g["forces"]).max() * cfg.n ** 0.5
+        assert np.abs(g["stress"][0] - g["stress"][0].T).max() <= 1e-8 * np.abs(g["stress"][0]).max()
+
+
+def test_efs_fp64_bitwise_deterministic():
+    w = synth.workload2(reps=(6, 6, 6))
+    pot = potential(w)
+    theta = theta_for(2, pot)
+    a = _efs_case(w, w.configs[0], theta, "fp64")
+    b = _efs_case(w, w.configs[0], theta, "fp64")
+    for k in ("energy", "forces", "stress", "site_e"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_batched_equals_single_configs():
+    w = synth.workload1()
+    pot = potential(w)
+    theta = theta_for(1, pot)
+    cfgs = synth.workload1_training(3)
+    m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
+    m.set_params(theta)
+    b = api.Batch(cfgs)
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    together = {k: v.cpu().numpy() for k, v in api.energy_forces_stress(m, b, nb, "fp64").items()}
+    for k, cfg in enumerate(cfgs):
+        one = _efs_case(w, cfg, theta, "fp64")
+        sl = slice(b.cfg_off_host[k], b.cfg_off_host[k + 1])
+        assert np.array_equal(together["forces"][sl], one["forces"])
+        assert np.array_equal(together["site_e"][sl], one["site_e"])
+        assert together["energy"][k] == pytest.approx(one["energy"][0], rel=1e-14)
+
+
+# --------------------------------------------------------------- grades ----
+def _grade_case(wid, w, cfg, precision, mode):
+    pot = potential(w)
+    theta = theta_for(wid, pot)
+    m, keep = _model(w, theta)
+    b = api.Batch([cfg])
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    out = api.grade(m, b, nb, precision, mode, rows=True)
+    torch.cuda.synchronize()
+    return pot, theta, keep, {k: v.cpu().numpy() for k, v in out.items()}
+
+
+@pytest.mark.parametrize("mode", ["full", "linear"])
+def test_grade_fp64_workload1(mode):
+    w = synth.workload1()
+    cfg = w.configs[0]
+    pot, theta, keep, g = _grade_case(1, w, cfg, "fp64", mode)
+    pairs = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, w.r_cut)
+    if mode == "full":
+        assert list(keep) == om.kept_columns(pot, theta)
+        rows = om.b_rows(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs)[:, keep]
+        A = active_rows(1, "full")[:, keep]
+    else:
+        rows = om.linear_rows(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs)
+        A = active_rows(1, "linear")
+    assert rel_err(g["rows"], rows) <= FP64_TOL
+    gam, am, _ = om.grades(rows, A)
+    assert rel_err(g["gamma"], gam) <= 1e-9
+    clear = np.sort(np.abs(_c(rows, A)), axis=1)
+    unique = clear[:, -1] - clear[:, -2] > 1e-8 * clear[:, -1]
+    assert np.array_equal(g["argmax"][unique], am[unique])
+
+
+def _c(rows, A):
+    return om.grades(rows, A)[2]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_grade_level16_two_species_small(precision):
+    w = synth.workload2(reps=(4, 4, 4))
+    cfg = w.configs[0]
+    pot, theta, keep, g = _grade_case(2, w, cfg, precision, "full")
+    pairs = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, w.r_cut)
+    rows = om.b_rows(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs)[:, keep]
+    gam, _, _ = om.grades(rows, active_rows(2, "full")[:, keep])
+    err = np.abs(g["gamma"] - gam) / np.maximum(1.0, gam)
+    print(f"{precision} gamma: max rel err {err.max():.3g}, gamma range {gam.min():.3g}..{gam.max():.3g}")
+    if precision == "fp64":
+        assert rel_err(g["rows"], rows) <= FP64_TOL
+        assert err.max() <= 1e-8
+    else:
+        assert err.max() <= 1e-5
+
+
+def test_gamma_is_one_on_active_rows():
+    """Rows of the active set itself: gamma = 1 (the grade of an interpolation point)."""
+    w = synth.workload1()
+    pot = potential(w)
+    theta = theta_for(1, pot)
+    m, keep = _model(w, theta)
+    A = torch.as_tensor(active_rows(1, "full")[:, keep]).cuda()
+    # grade the active rows directly through the GEMM path: use MaxVol with no swap
+    cand = A.clone().contiguous()
+    sc, sj = api.maxvol_update(m, "full", cand, threshold=1.0 + 1e-9)
+    assert len(sc) == 0
+
+
+# -------------------------------------------------------------- MaxVol -----
+def test_maxvol_matches_oracle_swap_sequence():
+    w = synth.workload1()
+    pot = potential(w)
+    theta = theta_for(1, pot)
+    m, keep = _model(w, theta)
+    cfg = synth.workload1_training(1)[0]
+    cfg = synth.Config(cfg.pos + np.random.default_rng(8).normal(0, 0.15, cfg.pos.shape), cfg.types, cfg.cell)
+    pairs = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, w.r_cut)
+    rows = om.b_rows(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs)[:, keep]
+    A0 = active_rows(1, "full")[:, keep]
+    A_or, cand_or, swaps = om.maxvol(A0, rows, threshold=1.001)
+    cand = torch.as_tensor(rows).cuda().contiguous()
+    sc, sj = api.maxvol_update(m, "full", cand, threshold=1.001)
+    assert [(int(a), int(b)) for a, b in zip(sc, sj)] == [(i, j) for i, j, _ in swaps]
+    A_gpu, Ainv = m.get_active_set("full")
+    assert np.array_equal(A_gpu.cpu().numpy(), A_or)
+    assert np.array_equal(cand.cpu().numpy(), cand_or)
+    assert rel_err(Ainv.cpu().numpy() @ A_or, np.eye(A_or.shape[0])) <= 1e-6
+
+
+def test_select_matches_numpy():
+    g = torch.as_tensor(np.random.default_rng(9).exponential(1.0, 100000)).cuda()
+    idx, cnt = api.select(g, 2.0)
+    want = np.nonzero(g.cpu().numpy() > 2.0)[0]
+    assert int(cnt.item()) == len(want)
+    assert np.array_equal(idx[:len(want)].cpu().numpy(), want)
+
+
+def test_singular_active_set_is_reported():
+    w = synth.workload1()
+    m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
+    m.set_params(theta_for(1, potential(w)))
+    A = torch.zeros((m.m("linear"), m.m("linear")), dtype=torch.float64).cuda()
+    with pytest.raises(api.MtpError) as e:
+        m.set_active_set("linear", A)
+    assert e.value.status == "MTP_E_SINGULAR"
+
+
+def test_model_file_round_trip(tmp_path):
+    w = synth.workload1()
+    pot = potential(w)
+    theta = theta_for(1, pot)
+    m, keep = _model(w, theta)
+    path = tmp_path / "w1.mtp"
+    m.save(path)
+    m2 = api.Model.load(path)
+    b = api.Batch(w.configs)
+    nb = api.Neighbors().build(m, b)
+    g1 = api.grade(m, b, nb, "fp64", "full")["gamma"].cpu().numpy()
+    g2 = api.grade(m2, b, nb, "fp64", "full")["gamma"].cpu().numpy()
+    assert np.array_equal(g1, g2)
