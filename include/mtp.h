@@ -86,6 +86,7 @@ typedef struct {
     int32_t m_full, m_linear;
     double r_min, r_cut;
     int32_t has_active_full, has_active_linear;
+    int64_t contraction_flops;  /* flops of the contraction program per neighborhood */
 } mtp_model_info;
 
 /* A batch of configurations (all pointers device memory). */
@@ -207,6 +208,14 @@ int mtp_maxvol_update(mtp_model *m, mtp_grade_mode g, double *cand, int64_t n_ca
  * no per-pair tensors are stored. */
 int mtp_efs_backward(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, const double *gE,
                      const double *gF, const double *gS, double *g_theta, void *stream);
+
+/* Kernel timing: while enabled, every library kernel group ("neighbors",
+ * "efs", "force_gather", "cfg_sums", "grade", "select", "maxvol") is
+ * bracketed by HIP events on its stream.  mtp_profile_read synchronises the
+ * recorded events of `kernel`, returns their summed duration (ms) and count
+ * and forgets them.  Host-side bookkeeping only; results are unaffected. */
+int mtp_profile_enable(int on);
+int mtp_profile_read(const char *kernel, double *total_ms /* host */, int64_t *launches /* host */);
 
 /* Description of the basis of a level, one function per line (host). */
 int mtp_basis_describe(int32_t level, char *buf, size_t len, int32_t *n_lin);

@@ -22,7 +22,7 @@ EXPORTS = ("mtp_load", "mtp_save", "mtp_create", "mtp_free", "mtp_info", "mtp_se
            "mtp_set_active_set", "mtp_get_active_set", "mtp_nbrs_create", "mtp_nbrs_free", "mtp_build_neighbors",
            "mtp_nbrs_status", "mtp_nbrs_export", "mtp_energy_forces_stress", "mtp_grade", "mtp_evaluate",
            "mtp_b_rows", "mtp_select", "mtp_maxvol_update", "mtp_efs_backward", "mtp_basis_describe",
-           "mtp_compiled_levels", "mtp_last_error")
+           "mtp_compiled_levels", "mtp_last_error", "mtp_profile_enable", "mtp_profile_read")
 
 
 class MtpError(RuntimeError):
@@ -37,7 +37,8 @@ class ModelInfo(ctypes.Structure):
                 ("n_lin", ctypes.c_int32), ("n_rad", ctypes.c_int32), ("n_comp", ctypes.c_int32),
                 ("n_theta", ctypes.c_int32), ("m_full", ctypes.c_int32), ("m_linear", ctypes.c_int32),
                 ("r_min", ctypes.c_double), ("r_cut", ctypes.c_double),
-                ("has_active_full", ctypes.c_int32), ("has_active_linear", ctypes.c_int32)]
+                ("has_active_full", ctypes.c_int32), ("has_active_linear", ctypes.c_int32),
+                ("contraction_flops", ctypes.c_int64)]
 
 
 class System(ctypes.Structure):
@@ -84,6 +85,8 @@ def lib():
         "mtp_efs_backward": [P, ctypes.POINTER(System), P, ctypes.c_int, P, P, P, P, P],
         "mtp_basis_describe": [I32, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(I32)],
         "mtp_compiled_levels": [ctypes.POINTER(I32), I32],
+        "mtp_profile_enable": [ctypes.c_int],
+        "mtp_profile_read": [ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I64)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)

@@ -28,7 +28,7 @@ HIP_FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wno-unuse
              # no packed FP32 instructions anywhere in the device code
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", CSRC, "-I", GEN]
-HOST_SOURCES = ["api.cpp", "basis.cpp"]
+HOST_SOURCES = ["api.cpp", "basis.cpp", "prof.cpp"]
 HIP_SOURCES = ["neighbors.hip", "ops.hip", "grade.hip"]
 
 
@@ -46,6 +46,10 @@ def generate(levels):
     _run(["g++", "-O2", "-std=c++17", "-o", gen_exe, os.path.join(CSRC, "gen_contract.cpp"),
           os.path.join(CSRC, "basis.cpp")])
     _run([gen_exe, GEN] + [str(L) for L in levels])
+    flops = {}
+    for L in levels:
+        txt = open(os.path.join(GEN, f"mtp_level{L}.inc")).read()
+        flops[L] = sum(int(txt.split(f"FLOPS_{k} = ")[1].split(";")[0]) for k in ("GRAPHS", "TRIE", "REVERSE"))
     units = []
     for L in levels:
         path = os.path.join(GEN, f"efs_level{L}.hip")
@@ -58,7 +62,9 @@ def generate(levels):
     disp = ('#include "internal.hpp"\nnamespace mtp {\ntemplate <int L> int launch_efs_level(const EfsArgs &a);\n'
             + decl + "int launch_efs(int level, const EfsArgs &a) {\n    switch (level) {\n" + cases
             + "        default: return -1;\n    }\n}\nstd::vector<int> compiled_levels() { return {"
-            + ", ".join(str(L) for L in levels) + "}; }\n}  // namespace mtp\n")
+            + ", ".join(str(L) for L in levels) + "}; }\nlong contraction_flops(int level) {\n    switch (level) {\n"
+            + "".join(f"        case {L}: return {flops[L]};\n" for L in levels)
+            + "        default: return 0;\n    }\n}\n}  // namespace mtp\n")
     dpath = os.path.join(GEN, "dispatch.cpp")
     _write_if_changed(dpath, disp)
     return units, dpath

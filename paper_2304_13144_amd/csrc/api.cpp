@@ -238,13 +238,28 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     a.precision = prec;
     a.lanes = lanes_for(m, n);
     a.stream = st;
-    int e = launch_efs(m->level, a);
+    m->mbuf.ensure(tsz * m->basis.n_comp() * (size_t)n);
+    m->dmbuf.ensure(tsz * m->basis.n_comp() * (size_t)n);
+    a.mbuf = m->mbuf.ptr;
+    a.dmbuf = m->dmbuf.ptr;
+    int e;
+    {
+        ProfScope ps("efs", st);
+        e = launch_efs(m->level, a);
+    }
     MTP_CHECK(e == 0, MTP_E_HIP, std::string("efs kernel launch: ") + hipGetErrorString((hipError_t)e));
-    if (want_f) launch_force_gather(nb, m->gbuf.ptr, prec, o.forces, st);
-    if (o.energy || want_v) launch_cfg_sums(s, o.energy ? site : nullptr, want_v ? m->virial.as<double>() : nullptr,
-                                            o.energy, o.stress, st);
+    if (want_f) {
+        ProfScope ps("force_gather", st);
+        launch_force_gather(nb, m->gbuf.ptr, prec, o.forces, st);
+    }
+    if (o.energy || want_v) {
+        ProfScope ps("cfg_sums", st);
+        launch_cfg_sums(s, o.energy ? site : nullptr, want_v ? m->virial.as<double>() : nullptr, o.energy, o.stress,
+                        st, m->sums);
+    }
     if (want_grade) {
         m->gamma_ws.ensure(sizeof(double) * n);
+        ProfScope ps("grade", st);
         launch_grade(m->act[o.mode], prec, m->brow.ptr, ldb, n, o.gamma ? o.gamma : m->gamma_ws.as<double>(),
                      o.argmax, st);
     }
@@ -415,6 +430,7 @@ int mtp_info(const mtp_model *m, mtp_model_info *info) {
     info->r_cut = m->r_cut;
     info->has_active_full = m->act[0].valid;
     info->has_active_linear = m->act[1].valid;
+    info->contraction_flops = contraction_flops(m->level);
     API_END
 }
 
@@ -486,6 +502,7 @@ int mtp_build_neighbors(const mtp_model *m, const mtp_system *s, int32_t max_nbr
     MTP_CHECK(s->n_atoms * (int64_t)max_nbrs < ((int64_t)1 << 31), MTP_E_INVAL,
               "n_atoms * max_nbrs must stay below 2^31");
     MTP_HIP(hipSetDevice(m->device));
+    ProfScope ps("neighbors", S(stream));
     build_neighbors(m, s, max_nbrs, nb, S(stream));
     API_END
 }
@@ -500,10 +517,10 @@ int mtp_nbrs_status(const mtp_nbrs *nb, void *stream) {
     MTP_CHECK(!(f[3] & 1), MTP_E_INVAL, "a cell matrix is singular");
     MTP_CHECK(!(f[3] & 8), MTP_E_INVAL, "an atom type is outside 0..n_types-1");
     MTP_CHECK(!(f[3] & 2), MTP_E_INVAL, "an image shift exceeds +-127 cells (atoms far outside the cell)");
-    MTP_CHECK(!(f[3] & 4), MTP_E_INVAL, "internal: a reverse pair was not found");
     MTP_CHECK(!f[0], MTP_E_CAPACITY,
               "a neighborhood has " + std::to_string(f[1]) + " atoms, more than max_nbrs = " +
                   std::to_string(nb->max_nbrs));
+    MTP_CHECK(!(f[3] & 4), MTP_E_INVAL, "internal: a reverse pair was not found");
     MTP_CHECK(!f[2], MTP_E_OVERLAP, "two atoms are closer than 1e-6 Angstrom");
     API_END
 }
@@ -618,6 +635,10 @@ int mtp_b_rows(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_
     a.precision = MTP_FP64;
     a.lanes = 4;
     a.stream = S(stream);
+    m->mbuf.ensure(sizeof(double) * m->basis.n_comp() * (size_t)n_idx);
+    m->dmbuf.ensure(sizeof(double) * m->basis.n_comp() * (size_t)n_idx);
+    a.mbuf = m->mbuf.ptr;
+    a.dmbuf = m->dmbuf.ptr;
     int e = launch_efs(m->level, a);
     MTP_CHECK(e == 0, MTP_E_HIP, std::string("efs kernel launch: ") + hipGetErrorString((hipError_t)e));
     launch_copy_rows(m->brow.ptr, ldb, mm, n_idx, MTP_FP64, rows, S(stream));
@@ -630,6 +651,7 @@ int mtp_select(const double *gamma, int64_t n, double threshold, int32_t *idx, i
     MTP_CHECK(gamma && idx && count, MTP_E_INVAL, "NULL argument");
     MTP_CHECK(n >= 0 && capacity >= 0, MTP_E_INVAL, "negative size");
     static thread_local DevBuf work;
+    ProfScope ps("select", S(stream));
     launch_select(gamma, n, threshold, idx, capacity, count, S(stream), work);
     API_END
 }
@@ -648,7 +670,10 @@ int mtp_maxvol_update(mtp_model *m, mtp_grade_mode g, double *cand, int64_t n_ca
     MTP_HIP(hipSetDevice(m->device));
     *n_swaps = 0;
     if (n_cand == 0 || max_swaps == 0) return MTP_OK;
-    run_maxvol(as, cand, n_cand, threshold, max_swaps, swap_cand, swap_col, n_swaps, S(stream), m->work);
+    {
+        ProfScope ps("maxvol", S(stream));
+        run_maxvol(as, cand, n_cand, threshold, max_swaps, swap_cand, swap_col, n_swaps, S(stream), m->work);
+    }
     API_END
 }
 

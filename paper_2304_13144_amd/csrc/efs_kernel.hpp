@@ -39,91 +39,142 @@ template <typename T> __device__ inline void monomials(T x, T y, T z, T (&m)[20]
 
 }  // namespace efs
 
-template <typename T, int L, int K, bool WB>
-__global__ __launch_bounds__(256) void efs_kernel(const EfsArgs a) {
-    using LV = Level<L>;
-    constexpr int NC = LV::NC, NR = LV::NRAD, NL = LV::NLIN;
-    __shared__ T c_s[NR * MAX_TYPES * MAX_TYPES * NPOLY];
-    const int nt = a.n_types;
-    {
-        const T *cg = static_cast<const T *>(a.c);
-        const int ncoef = NR * nt * nt * NPOLY;
-        for (int k = threadIdx.x; k < ncoef; k += blockDim.x) c_s[k] = cg[k];
-    }
-    __syncthreads();
-
-    const int sub = threadIdx.x % K;
-    const int64_t slot = (int64_t)blockIdx.x * (blockDim.x / K) + threadIdx.x / K;
-    const bool live = slot < a.n_atoms;
-    const int64_t atom = live ? (a.atom_list ? (int64_t)a.atom_list[slot] : slot) : 0;
-    int zi = live ? a.type[atom] : 0;
-    zi = zi < 0 ? 0 : (zi >= nt ? nt - 1 : zi);
+// Per-neighborhood context shared by the pair kernels.
+struct AtomCtx {
+    bool live;
+    int64_t slot, atom;
+    int zi, ntot;
     int tc[MAX_TYPES];
-    int ntot = 0;
+    const double *rp;
+};
+
+template <int K> __device__ inline AtomCtx atom_ctx(const EfsArgs &a) {
+    AtomCtx c;
+    const int nt = a.n_types;
+    c.slot = (int64_t)blockIdx.x * (blockDim.x / K) + threadIdx.x / K;
+    c.live = c.slot < a.n_atoms;
+    c.atom = c.live ? (a.atom_list ? (int64_t)a.atom_list[c.slot] : c.slot) : 0;
+    int zi = c.live ? a.type[c.atom] : 0;
+    c.zi = zi < 0 ? 0 : (zi >= nt ? nt - 1 : zi);
+    c.ntot = 0;
 #pragma unroll
     for (int t = 0; t < MAX_TYPES; ++t) {
-        tc[t] = (live && t < nt) ? a.tcnt[atom * nt + t] : 0;
-        ntot += tc[t];
+        c.tc[t] = (c.live && t < nt) ? a.tcnt[c.atom * nt + t] : 0;
+        c.ntot += c.tc[t];
     }
-    const double *rp = a.r + atom * (int64_t)a.max_nbrs * 3;
+    c.rp = a.r + c.atom * (int64_t)a.max_nbrs * 3;
+    return c;
+}
+
+template <typename T, int NR> __device__ inline void load_coefs(const EfsArgs &a, T *c_s) {
+    const T *cg = static_cast<const T *>(a.c);
+    const int ncoef = NR * a.n_types * a.n_types * NPOLY;
+    for (int k = threadIdx.x; k < ncoef; k += blockDim.x) c_s[k] = cg[k];
+    __syncthreads();
+}
+
+// ---- kernel 1: moments (eq. 3), LANES lanes per neighborhood -------------
+template <typename T, int L, int K>
+__global__ __launch_bounds__(256) void efs_moments(const EfsArgs a) {
+    using LV = Level<L>;
+    constexpr int NC = LV::NC, NR = LV::NRAD;
+    __shared__ T c_s[NR * MAX_TYPES * MAX_TYPES * NPOLY];
+    load_coefs<T, NR>(a, c_s);
+    const int nt = a.n_types;
+    const int sub = threadIdx.x % K;
+    const AtomCtx c = atom_ctx<K>(a);
     const T rc = T(a.r_cut);
     const T xs = T(2.0 / (a.r_cut - a.r_min));
     const T x0 = T(-(a.r_min + a.r_cut) / (a.r_cut - a.r_min));
-
-    // ---- moments (eq. 3) ------------------------------------------------
     T M[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) M[k] = T(0);
-    {
-        int zj = 0, tend = tc[0];
-        for (int p = sub; p < ntot; p += K) {
-            while (p >= tend && zj < nt - 1) tend += tc[++zj];
-            const T x = T(rp[3 * p]), y = T(rp[3 * p + 1]), z = T(rp[3 * p + 2]);
-            const T r = sqrt(x * x + y * y + z * z);
-            if (!(r < rc)) continue;
-            T fm[NR];
+    int zj = 0, tend = c.tc[0];
+    for (int p = sub; p < c.ntot; p += K) {
+        while (p >= tend && zj < nt - 1) tend += c.tc[++zj];
+        const T x = T(c.rp[3 * p]), y = T(c.rp[3 * p + 1]), z = T(c.rp[3 * p + 2]);
+        const T r = sqrt(x * x + y * y + z * z);
+        if (!(r < rc)) continue;
+        T fm[NR];
+        {
+            const T u = fma(r, xs, x0), d = rc - r, cut = d * d;
+            T Tb[NPOLY];
+            Tb[0] = T(1);
+            Tb[1] = u;
 #pragma unroll
-            for (int mu = 0; mu < NR; ++mu) fm[mu] = T(0);
-            {
-                T u = fma(r, xs, x0), d = rc - r, cut = d * d;
-                T Tb[NPOLY];
-                Tb[0] = T(1);
-                Tb[1] = u;
+            for (int b = 2; b < NPOLY; ++b) Tb[b] = fma(T(2) * u, Tb[b - 1], -Tb[b - 2]);
 #pragma unroll
-                for (int b = 2; b < NPOLY; ++b) Tb[b] = fma(T(2) * u, Tb[b - 1], -Tb[b - 2]);
+            for (int mu = 0; mu < NR; ++mu) {
+                const T *cm = c_s + ((mu * nt + c.zi) * nt + zj) * NPOLY;
+                T s = T(0);
 #pragma unroll
-                for (int mu = 0; mu < NR; ++mu) {
-                    const T *cm = c_s + ((mu * nt + zi) * nt + zj) * NPOLY;
-                    T s = T(0);
-#pragma unroll
-                    for (int b = 0; b < NPOLY; ++b) s = fma(cm[b], Tb[b], s);
-                    fm[mu] = s * cut;
-                }
+                for (int b = 0; b < NPOLY; ++b) s = fma(cm[b], Tb[b], s);
+                fm[mu] = s * cut;
             }
-            T mono[20];
-            efs::monomials(x, y, z, mono);
-#pragma unroll
-            for (int k = 0; k < NC; ++k) M[k] = fma(fm[LV::comp_mu[k]], mono[LV::comp_mono[k]], M[k]);
         }
+        T mono[20];
+        efs::monomials(x, y, z, mono);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) M[k] = fma(fm[LV::comp_mu[k]], mono[LV::comp_mono[k]], M[k]);
     }
 #pragma unroll
     for (int o = K / 2; o > 0; o >>= 1)
 #pragma unroll
         for (int k = 0; k < NC; ++k) M[k] += efs::xor_shuffle(M[k], o);
-
-    // ---- contraction, site energy (eq. 2), dV/dM ------------------------
-    T dM[NC];
-    T V = T(0);
-    T *brow = (WB && live) ? static_cast<T *>(a.brow) + slot * (int64_t)a.ldb : nullptr;
-    if (live) {
-        LV::template contract<T, WB>(M, static_cast<const T *>(a.xi), brow ? brow + nt : nullptr, dM, V);
-    } else {
+    if (c.live) {
+        T *out = static_cast<T *>(a.mbuf);
 #pragma unroll
-        for (int k = 0; k < NC; ++k) dM[k] = T(0);
+        for (int k = 0; k < NC; ++k)
+            if (k % K == sub) out[(int64_t)k * a.n_atoms + c.slot] = M[k];
     }
-    if (live && sub == 0 && a.site_e) a.site_e[atom] = double(V) + double(static_cast<const T *>(a.xi0)[zi]);
+}
 
-    // ---- pair gradients, virial, b-row c part ---------------------------
+// ---- kernel 2: contraction, site energy (eq. 2), dV/dM; one lane each ----
+template <typename T, int L, bool WB>
+__global__ __launch_bounds__(256) void efs_contract(const EfsArgs a) {
+    using LV = Level<L>;
+    constexpr int NC = LV::NC;
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= a.n_atoms) return;
+    const int64_t atom = a.atom_list ? (int64_t)a.atom_list[slot] : slot;
+    const int nt = a.n_types;
+    const T *min = static_cast<const T *>(a.mbuf);
+    T M[NC], dM[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) M[k] = min[(int64_t)k * a.n_atoms + slot];
+    T V = T(0);
+    T *brow = WB ? static_cast<T *>(a.brow) + slot * (int64_t)a.ldb : nullptr;
+    LV::template contract<T, WB>(M, static_cast<const T *>(a.xi), WB ? brow + nt : nullptr, dM, V);
+    T *dout = static_cast<T *>(a.dmbuf);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) dout[(int64_t)k * a.n_atoms + slot] = dM[k];
+    if (a.site_e) {
+        int zi = a.type[atom];
+        zi = zi < 0 ? 0 : (zi >= nt ? nt - 1 : zi);
+        a.site_e[atom] = double(V) + double(static_cast<const T *>(a.xi0)[zi]);
+    }
+}
+
+// ---- kernel 3: pair gradients, virial, b-row c part; LANES per atom -------
+template <typename T, int L, int K, bool WB>
+__global__ __launch_bounds__(256) void efs_forces(const EfsArgs a) {
+    using LV = Level<L>;
+    constexpr int NC = LV::NC, NR = LV::NRAD, NL = LV::NLIN;
+    __shared__ T c_s[NR * MAX_TYPES * MAX_TYPES * NPOLY];
+    load_coefs<T, NR>(a, c_s);
+    const int nt = a.n_types;
+    const int sub = threadIdx.x % K;
+    const AtomCtx c = atom_ctx<K>(a);
+    const T rc = T(a.r_cut);
+    const T xs = T(2.0 / (a.r_cut - a.r_min));
+    const T x0 = T(-(a.r_min + a.r_cut) / (a.r_cut - a.r_min));
+    T dM[NC];
+    {
+        const T *din = static_cast<const T *>(a.dmbuf);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) dM[k] = c.live ? din[(int64_t)k * a.n_atoms + c.slot] : T(0);
+    }
+    T *brow = (WB && c.live) ? static_cast<T *>(a.brow) + c.slot * (int64_t)a.ldb : nullptr;
     T vir[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) vir[k] = T(0);
@@ -136,14 +187,13 @@ __global__ __launch_bounds__(256) void efs_kernel(const EfsArgs a) {
         for (int mu = 0; mu < NR; ++mu)
 #pragma unroll
             for (int b = 0; b < NPOLY; ++b) dc[mu][b] = T(0);
-        for (int q = sub; q < tc[t]; q += K) {
+        for (int q = sub; q < c.tc[t]; q += K) {
             const int p = gstart + q;
-            const T x = T(rp[3 * p]), y = T(rp[3 * p + 1]), z = T(rp[3 * p + 2]);
+            const T x = T(c.rp[3 * p]), y = T(c.rp[3 * p + 1]), z = T(c.rp[3 * p + 2]);
             const T r = sqrt(x * x + y * y + z * z);
             T g0 = T(0), g1 = T(0), g2 = T(0);
             if (r < rc) {
                 T f[NR], fp[NR], Q[NPOLY];
-                // radial functions and derivatives for the pair species (zi, t)
                 {
                     const T u = fma(r, xs, x0);
                     const T d = rc - r;
@@ -163,7 +213,7 @@ __global__ __launch_bounds__(256) void efs_kernel(const EfsArgs a) {
                     for (int b = 0; b < NPOLY; ++b) Q[b] = Tb[b] * cut;
 #pragma unroll
                     for (int mu = 0; mu < NR; ++mu) {
-                        const T *cm = c_s + ((mu * nt + zi) * nt + t) * NPOLY;
+                        const T *cm = c_s + ((mu * nt + c.zi) * nt + t) * NPOLY;
                         T s = T(0), sp = T(0);
 #pragma unroll
                         for (int b = 0; b < NPOLY; ++b) {
@@ -182,13 +232,14 @@ __global__ __launch_bounds__(256) void efs_kernel(const EfsArgs a) {
 #pragma unroll
                 for (int k = 0; k < NC; ++k) {
                     const int mu = LV::comp_mu[k];
-                    P[mu] = fma(dM[k], mono[LV::comp_mono[k]], P[mu]);
+                    const T dmk = dM[k];
+                    P[mu] = fma(dmk, mono[LV::comp_mono[k]], P[mu]);
                     if (LV::comp_dmonox[k] >= 0)
-                        Gx[mu] = fma(dM[k] * T(LV::comp_dfacx[k]), mono[LV::comp_dmonox[k] < 0 ? 0 : LV::comp_dmonox[k]], Gx[mu]);
+                        Gx[mu] = fma(dmk * T(LV::comp_dfacx[k]), mono[LV::comp_dmonox[k] < 0 ? 0 : LV::comp_dmonox[k]], Gx[mu]);
                     if (LV::comp_dmonoy[k] >= 0)
-                        Gy[mu] = fma(dM[k] * T(LV::comp_dfacy[k]), mono[LV::comp_dmonoy[k] < 0 ? 0 : LV::comp_dmonoy[k]], Gy[mu]);
+                        Gy[mu] = fma(dmk * T(LV::comp_dfacy[k]), mono[LV::comp_dmonoy[k] < 0 ? 0 : LV::comp_dmonoy[k]], Gy[mu]);
                     if (LV::comp_dmonoz[k] >= 0)
-                        Gz[mu] = fma(dM[k] * T(LV::comp_dfacz[k]), mono[LV::comp_dmonoz[k] < 0 ? 0 : LV::comp_dmonoz[k]], Gz[mu]);
+                        Gz[mu] = fma(dmk * T(LV::comp_dfacz[k]), mono[LV::comp_dmonoz[k] < 0 ? 0 : LV::comp_dmonoz[k]], Gz[mu]);
                 }
                 const T rinv = T(1) / r;
                 T radial_part = T(0);
@@ -215,7 +266,7 @@ __global__ __launch_bounds__(256) void efs_kernel(const EfsArgs a) {
                 vir[6] -= g2 * x; vir[7] -= g2 * y; vir[8] -= g2 * z;
             }
             if (gout) {
-                const int64_t s3 = (atom * (int64_t)a.max_nbrs + p) * 3;
+                const int64_t s3 = (c.atom * (int64_t)a.max_nbrs + p) * 3;
                 gout[s3] = g0;
                 gout[s3 + 1] = g1;
                 gout[s3 + 2] = g2;
@@ -228,36 +279,38 @@ __global__ __launch_bounds__(256) void efs_kernel(const EfsArgs a) {
                 for (int mu = 0; mu < NR; ++mu)
 #pragma unroll
                     for (int b = 0; b < NPOLY; ++b) dc[mu][b] += efs::xor_shuffle(dc[mu][b], o);
-            if (brow && sub == 0) {
+            if (brow) {
                 const int base = nt + NL;
 #pragma unroll
                 for (int mu = 0; mu < NR; ++mu)
 #pragma unroll
                     for (int b = 0; b < NPOLY; ++b) {
-                        const int col = a.colmap[base + ((mu * nt + zi) * nt + t) * NPOLY + b];
+                        if ((mu * NPOLY + b) % K != sub) continue;
+                        const int col = a.colmap[base + ((mu * nt + c.zi) * nt + t) * NPOLY + b];
                         if (col >= 0) brow[col] = dc[mu][b];
                     }
             }
         }
-        gstart += tc[t];
+        gstart += c.tc[t];
     }
 #pragma unroll
     for (int o = K / 2; o > 0; o >>= 1)
 #pragma unroll
         for (int k = 0; k < 9; ++k) vir[k] += efs::xor_shuffle(vir[k], o);
-    if (live && sub == 0 && a.virial) {
+    if (c.live && a.virial) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) a.virial[atom * 9 + k] = double(vir[k]);
+        for (int k = 0; k < 9; ++k)
+            if (k % K == sub) a.virial[c.atom * 9 + k] = double(vir[k]);
     }
     if (brow) {
         // species one-hot, zero c blocks of the other central species, zero padding
-        for (int k = sub; k < nt; k += K) brow[k] = T(k == zi ? 1 : 0);
+        for (int k = sub; k < nt; k += K) brow[k] = T(k == c.zi ? 1 : 0);
         if (full_rows) {
             const int base = nt + NL;
             const int nblk = NR * nt * nt * NPOLY;
             for (int k = sub; k < nblk; k += K) {
                 const int zz = (k / (nt * NPOLY)) % nt;
-                if (zz == zi) continue;
+                if (zz == c.zi) continue;
                 const int col = a.colmap[base + k];
                 if (col >= 0) brow[col] = T(0);
             }
@@ -268,13 +321,25 @@ __global__ __launch_bounds__(256) void efs_kernel(const EfsArgs a) {
 
 template <int L> int launch_efs_level(const EfsArgs &a);
 
-// instantiates the launcher of one level (used by the generated units)
+// instantiates the launchers of one level (used by the generated units)
 #define MTP_EFS_LEVEL(LEVEL)                                                                             \
     template <typename T, int K, bool WB> static void launch_efs_tk##LEVEL(const EfsArgs &a) {           \
         const int per = 256 / K;                                                                         \
         const unsigned grid = (unsigned)((a.n_atoms + per - 1) / per);                                   \
+        const unsigned grid1 = (unsigned)((a.n_atoms + 255) / 256);                                      \
         if (grid == 0) return;                                                                           \
-        hipLaunchKernelGGL((efs_kernel<T, LEVEL, K, WB>), dim3(grid), dim3(256), 0, a.stream, a);       \
+        {                                                                                                \
+            ProfScope ps("efs_moments", a.stream);                                                       \
+            hipLaunchKernelGGL((efs_moments<T, LEVEL, K>), dim3(grid), dim3(256), 0, a.stream, a);       \
+        }                                                                                                \
+        {                                                                                                \
+            ProfScope ps("efs_contract", a.stream);                                                      \
+            hipLaunchKernelGGL((efs_contract<T, LEVEL, WB>), dim3(grid1), dim3(256), 0, a.stream, a);    \
+        }                                                                                                \
+        {                                                                                                \
+            ProfScope ps("efs_forces", a.stream);                                                        \
+            hipLaunchKernelGGL((efs_forces<T, LEVEL, K, WB>), dim3(grid), dim3(256), 0, a.stream, a);    \
+        }                                                                                                \
     }                                                                                                    \
     template <typename T, bool WB> static void launch_efs_t##LEVEL(const EfsArgs &a) {                   \
         switch (a.lanes) {                                                                               \

@@ -58,40 +58,78 @@ __device__ inline void finish_rows(double (&best)[4], int (&bidx)[4], int64_t ro
     }
 }
 
+// FP64: a block owns 64 rows; the columns are taken in super-tiles of 256
+// (16 MFMA column blocks per wavefront, accumulators in registers) and the
+// k dimension in chunks of 16 staged through LDS: the 64 x 16 slab of b and
+// the 16 x 256 slab of A^-1 are loaded once per chunk by the whole block.
+constexpr int GF_ROWS = 64, GF_KC = 16, GF_CT = 256;
 __global__ __launch_bounds__(256) void grade_f64(const double *__restrict__ brow, int ldb, int64_t n,
                                                  const double *__restrict__ Ainv, int m, double *gamma,
                                                  int32_t *argmax) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ double sA[GF_ROWS][GF_KC + 1];
+    __shared__ double sB[GF_KC][GF_CT];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
-    const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
-    const int64_t arow = row0 + lr;
-    const bool arow_ok = arow < n;
-    const double *ap = brow + (arow_ok ? arow : 0) * (int64_t)ldb;
+    const int64_t row0 = (int64_t)blockIdx.x * GF_ROWS;
     double best[4] = {-1.0, -1.0, -1.0, -1.0};
     int bidx[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
-    for (int col0 = 0; col0 < m; col0 += 64) {
-        doublex4 acc[4];
+    for (int ct0 = 0; ct0 < m; ct0 += GF_CT) {
+        const int ncb = min(GF_CT, m - ct0 + 15) / 16;   // column blocks holding real columns
+        doublex4 acc[GF_CT / 16];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) acc[cb] = doublex4{0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < m; k0 += 4) {
-            const int k = k0 + lk;
-            const double av = (arow_ok && k < m) ? ap[k] : 0.0;
+        for (int cb = 0; cb < GF_CT / 16; ++cb) acc[cb] = doublex4{0.0, 0.0, 0.0, 0.0};
+        // register-staged double buffering: the next chunk's global loads are
+        // in flight while the MFMAs consume the current chunk from LDS
+        constexpr int RA = GF_ROWS * GF_KC / 256, RB = GF_KC * GF_CT / 256;
+        double ra[RA], rb[RB];
+        auto fetch = [&](int k0) {
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
-                const int col = col0 + cb * 16 + lr;
-                const double bv = (k < m && col < m) ? Ainv[(int64_t)k * m + col] : 0.0;
-                acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[cb], 0, 0, 0);
+            for (int q = 0; q < RA; ++q) {
+                const int e = tid + 256 * q;
+                const int r = e / GF_KC, k = e % GF_KC;
+                const int64_t row = row0 + r;
+                ra[q] = (row < n && k0 + k < m) ? brow[row * ldb + k0 + k] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                const int e = tid + 256 * q;
+                const int k = e / GF_CT, c = e % GF_CT;
+                rb[q] = (k0 + k < m && ct0 + c < m) ? Ainv[(int64_t)(k0 + k) * m + ct0 + c] : 0.0;
+            }
+        };
+        fetch(0);
+        for (int k0 = 0; k0 < m; k0 += GF_KC) {
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < RA; ++q) {
+                const int e = tid + 256 * q;
+                sA[e / GF_KC][e % GF_KC] = ra[q];
+            }
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                const int e = tid + 256 * q;
+                sB[e / GF_CT][e % GF_CT] = rb[q];
+            }
+            __syncthreads();
+            if (k0 + GF_KC < m) fetch(k0 + GF_KC);
+#pragma unroll
+            for (int kk = 0; kk < GF_KC; kk += 4) {
+                const double av = sA[wave * 16 + lr][kk + lk];
+#pragma unroll
+                for (int cb = 0; cb < GF_CT / 16; ++cb)
+                    if (cb < ncb) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sB[kk + lk][cb * 16 + lr], acc[cb], 0, 0, 0);
             }
         }
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            const int col = col0 + cb * 16 + lr;
-            if (col < m)
+        for (int cb = 0; cb < GF_CT / 16; ++cb) {
+            const int col = ct0 + cb * 16 + lr;
+            if (cb < ncb && col < m)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) better(fabs(acc[cb][r]), col, best[r], bidx[r]);
         }
     }
-    finish_rows<true>(best, bidx, row0, lane, n, gamma, argmax);
+    finish_rows<true>(best, bidx, row0 + wave * 16, lane, n, gamma, argmax);
 }
 
 // split of x into NS BF16 terms (round to nearest even at every step)

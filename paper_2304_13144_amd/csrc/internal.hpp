@@ -67,7 +67,7 @@ struct mtp_model {
     mtp::DevBuf theta64, theta32, colmap;
     mtp::ActiveSet act[2];          // [MTP_GRADE_FULL], [MTP_GRADE_LINEAR]
     // scratch of the evaluation path
-    mutable mtp::DevBuf gbuf, virial, sitebuf, brow, gamma_ws, argmax_ws, work;
+    mutable mtp::DevBuf gbuf, virial, sitebuf, brow, gamma_ws, argmax_ws, work, sums, mbuf, dmbuf;
     int m_of(int mode) const { return mode == MTP_GRADE_FULL ? (int)kept.size() : n_types + basis.n_lin(); }
 };
 
@@ -112,16 +112,27 @@ struct EfsArgs {
     int m;                    // row length written (kept columns)
     int precision;
     int lanes;                // lanes per neighborhood (2, 4, 8)
+    void *mbuf, *dmbuf;       // [NC][n_atoms] T: moments and dV/dM between the kernels
     hipStream_t stream;
 };
 int launch_efs(int level, const EfsArgs &a);
 std::vector<int> compiled_levels();
+long contraction_flops(int level);   // per neighborhood, from the generated program
+
+// Optional timing of library kernels with HIP events (see mtp_profile_enable).
+void prof_mark(const char *name, bool begin, hipStream_t st);
+struct ProfScope {
+    const char *name;
+    hipStream_t st;
+    ProfScope(const char *n, hipStream_t s) : name(n), st(s) { prof_mark(name, true, st); }
+    ~ProfScope() { prof_mark(name, false, st); }
+};
 
 void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_nbrs *nb, hipStream_t st);
 
 void launch_force_gather(const mtp_nbrs *nb, const void *gbuf, int precision, double *forces, hipStream_t st);
 void launch_cfg_sums(const mtp_system *s, const double *site_e, const double *virial, double *energy,
-                     double *stress, hipStream_t st);
+                     double *stress, hipStream_t st, DevBuf &work);
 
 // grade: C = brow * Ainv (ld ldb), gamma/argmax per row
 void launch_grade(const ActiveSet &as, int precision, const void *brow, int ldb, int64_t n, double *gamma,

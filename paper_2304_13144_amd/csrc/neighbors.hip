@@ -15,6 +15,8 @@
 // force gather.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace mtp {
@@ -76,6 +78,7 @@ __global__ void geo_kernel(int n_cfg, const int64_t *cfg_off, const double *cell
         off += g.nbins;
         geo[c] = g;
     }
+    flags[4] = (int)off;   // bins in use (<= the host-side capacity n_atoms + n_cfg)
 }
 
 __global__ void bin_kernel(int64_t n, int n_cfg, const int64_t *cfg_off, const double *pos, const CfgGeo *geo,
@@ -115,8 +118,9 @@ __global__ void bin_kernel(int64_t n, int n_cfg, const int64_t *cfg_off, const d
 // exclusive scan, three kernels (block scan, scan of block sums, add)
 constexpr int SCAN_B = 1024;
 
-__global__ void scan_block(const int32_t *in, int32_t *out, int32_t *sums, int64_t n) {
+__global__ void scan_block(const int32_t *in, int32_t *out, int32_t *sums, const int32_t *n_dev) {
     __shared__ int32_t s[SCAN_B];
+    const int64_t n = *n_dev;
     const int64_t i = (int64_t)blockIdx.x * SCAN_B + threadIdx.x;
     int32_t v = i < n ? in[i] : 0;
     s[threadIdx.x] = v;
@@ -155,9 +159,14 @@ __global__ void scan_sums(int32_t *sums, int64_t nb) {
     }
 }
 
-__global__ void scan_add(int32_t *out, const int32_t *sums, int64_t n) {
+__global__ void scan_add(int32_t *out, const int32_t *sums, const int32_t *n_dev, int32_t *copy) {
+    const int64_t n = *n_dev;
     const int64_t i = (int64_t)blockIdx.x * SCAN_B + threadIdx.x;
-    if (i < n) out[i] += sums[blockIdx.x];
+    if (i < n) {
+        const int32_t v = out[i] + sums[blockIdx.x];
+        out[i] = v;
+        copy[i] = v;
+    }
 }
 
 __global__ void fill_bins(int64_t n, const int32_t *atom_bin, int32_t *cursor, int32_t *bin_atoms) {
@@ -167,147 +176,265 @@ __global__ void fill_bins(int64_t n, const int32_t *atom_bin, int32_t *cursor, i
     bin_atoms[slot] = (int32_t)i;
 }
 
-__global__ void sort_bins(int64_t nbins, const int32_t *start, const int32_t *count, int32_t *bin_atoms) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nbins) return;
-    int32_t *a = bin_atoms + start[b];
-    const int c = count[b];
-    for (int x = 1; x < c; ++x) {
-        int32_t v = a[x];
-        int y = x - 1;
-        while (y >= 0 && a[y] > v) {
-            a[y + 1] = a[y];
-            --y;
+// One wavefront per bin: the bin's atoms (filled in arbitrary order by
+// atomics) are put in ascending index order, which makes every later step
+// deterministic.  Ranks come from all-pairs comparisons across the lanes.
+__device__ inline void sort_one_bin(int32_t *a, int c, int lane) {
+    if (c <= 1) return;
+    if (c <= 64) {
+        const int v = lane < c ? a[lane] : 0x7fffffff;
+        int rank = 0;
+        for (int k = 0; k < c; ++k) rank += __shfl(v, k, 64) < v ? 1 : 0;
+        if (lane < c) a[rank] = v;
+    } else if (lane == 0) {
+        for (int x = 1; x < c; ++x) {
+            const int32_t v = a[x];
+            int y = x - 1;
+            while (y >= 0 && a[y] > v) {
+                a[y + 1] = a[y];
+                --y;
+            }
+            a[y + 1] = v;
         }
-        a[y + 1] = v;
     }
+}
+
+__global__ __launch_bounds__(256) void sort_bins(const int32_t *flags, const int32_t *start, const int32_t *count,
+                                                 int32_t *bin_atoms) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nbins = flags[4];
+    for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nbins; b += (int64_t)gridDim.x * 4)
+        sort_one_bin(bin_atoms + start[b], count[b], lane);
 }
 
 __device__ inline int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
-// FILL = false: count per species; FILL = true: write the lists
-template <bool FILL>
-__global__ void search_kernel(int64_t n, int n_types, int max_nbrs, double rc, const double *pos, const int32_t *type,
-                              const CfgGeo *geo, const int32_t *atom_cfg, const int32_t *atom_bin,
-                              const int32_t *atom_wrap, const int32_t *bin_start, const int32_t *bin_count,
-                              const int32_t *bin_atoms, int32_t *tcnt, double *rout, int32_t *jout,
-                              int32_t *shout, int32_t *flags) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const CfgGeo &g = geo[atom_cfg[i]];
-    const int local = (int)(atom_bin[i] - g.bin_off);
-    const int bx = local % g.n[0], by = (local / g.n[0]) % g.n[1], bz = local / (g.n[0] * g.n[1]);
-    const int wi[3] = {atom_wrap[3 * i], atom_wrap[3 * i + 1], atom_wrap[3 * i + 2]};
-    const double xi[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
-    int cnt[MAX_TYPES] = {0, 0, 0, 0};
-    int base[MAX_TYPES] = {0, 0, 0, 0}, cap[MAX_TYPES] = {0, 0, 0, 0};
-    if (FILL) {
-        int off = 0;
-        for (int t = 0; t < n_types; ++t) {
-            int want = tcnt[i * n_types + t];
-            int room = max_nbrs - off;
-            cap[t] = want < room ? want : room;
-            base[t] = off;
-            off += cap[t];
-        }
-    }
+// One block per bin.  The atoms of the bins around it (all periodic images
+// that can hold a neighbor) are staged in LDS in chunks, each as its image
+// position x_j + (q - w_j).H, so that r_ij = staged + w_i.H - x_i.  Each
+// wavefront then tests one of the bin's atoms against the chunk, 64
+// candidates at a time; ballots per neighbor species give every accepted pair
+// its slot, so the order (bin offset, then atom index in the bin) is
+// deterministic.  Pass 0 counts per species, pass 1 writes the lists
+// (clamped to max_nbrs).
+constexpr int BS_T = 256, BS_CAP = 1024, BS_ATOMS = 64;
+
+__device__ inline int pack_q(int x, int y, int z) { return (x + 512) | ((y + 512) << 10) | ((z + 512) << 20); }
+
+__global__ __launch_bounds__(BS_T) void bin_search(const int32_t *nbins_dev, int n_cfg, int n_types, int max_nbrs, double rc,
+                                                   const double *pos, const int32_t *type, const CfgGeo *geo,
+                                                   const int32_t *atom_wrap, const int32_t *bin_start,
+                                                   const int32_t *bin_count, const int32_t *bin_atoms, int32_t *tcnt,
+                                                   double *rout, int32_t *jout, int32_t *shout, int32_t *flags) {
+    __shared__ double cx[BS_CAP], cy[BS_CAP], cz[BS_CAP];
+    __shared__ int cj[BS_CAP], cs[BS_CAP], ct[BS_CAP];
+    __shared__ int o_start[BS_T], o_pre[BS_T + 1], o_q[BS_T];
+    __shared__ int a_cnt[BS_ATOMS][MAX_TYPES], a_base[BS_ATOMS][MAX_TYPES], a_cap[BS_ATOMS][MAX_TYPES];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     bool overlap = false, wide = false, bad_type = false;
-    for (int dz = -g.s[2]; dz <= g.s[2]; ++dz) {
-        int uz = bz + dz, qz = 0;
-        if (g.pbc[2]) { qz = floordiv(uz, g.n[2]); uz -= qz * g.n[2]; }
-        else if (uz < 0 || uz >= g.n[2]) continue;
-        for (int dy = -g.s[1]; dy <= g.s[1]; ++dy) {
-            int uy = by + dy, qy = 0;
-            if (g.pbc[1]) { qy = floordiv(uy, g.n[1]); uy -= qy * g.n[1]; }
-            else if (uy < 0 || uy >= g.n[1]) continue;
-            for (int dx = -g.s[0]; dx <= g.s[0]; ++dx) {
-                int ux = bx + dx, qx = 0;
-                if (g.pbc[0]) { qx = floordiv(ux, g.n[0]); ux -= qx * g.n[0]; }
-                else if (ux < 0 || ux >= g.n[0]) continue;
-                const long long bin = g.bin_off + ((long long)uz * g.n[1] + uy) * g.n[0] + ux;
-                const int st = bin_start[bin], c = bin_count[bin];
-                for (int q = 0; q < c; ++q) {
-                    const int j = bin_atoms[st + q];
-                    const int sh0 = qx - atom_wrap[3 * j] + wi[0];
-                    const int sh1 = qy - atom_wrap[3 * j + 1] + wi[1];
-                    const int sh2 = qz - atom_wrap[3 * j + 2] + wi[2];
-                    if (j == i && sh0 == 0 && sh1 == 0 && sh2 == 0) continue;
-                    double r[3];
-                    for (int k = 0; k < 3; ++k)
-                        r[k] = pos[3 * j + k] + sh0 * g.H[k] + sh1 * g.H[3 + k] + sh2 * g.H[6 + k] - xi[k];
-                    const double d = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-                    if (!(d < rc)) continue;
-                    if (d < 1e-6) overlap = true;
-                    const int t = type[j];
-                    if (t < 0 || t >= n_types) {
-                        bad_type = true;
-                        continue;
+    const int64_t nbins = *nbins_dev;
+    for (int64_t bin = blockIdx.x; bin < nbins; bin += gridDim.x) {
+    const int my_cnt = bin_count[bin];
+    if (my_cnt == 0) continue;   // uniform per block
+    int lo = 0, hi = n_cfg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (geo[mid].bin_off <= bin) lo = mid; else hi = mid - 1;
+    }
+    const CfgGeo g = geo[lo];
+    const int local = (int)(bin - g.bin_off);
+    const int bx = local % g.n[0], by = (local / g.n[0]) % g.n[1], bz = local / (g.n[0] * g.n[1]);
+    const int ox = 2 * g.s[0] + 1, oy = 2 * g.s[1] + 1, oz = 2 * g.s[2] + 1;
+    const int n_off = ox * oy * oz;
+    const int my_start = bin_start[bin];
+    for (int a0 = 0; a0 < my_cnt; a0 += BS_ATOMS) {
+        const int na = my_cnt - a0 < BS_ATOMS ? my_cnt - a0 : BS_ATOMS;
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 0) {
+                for (int k = tid; k < BS_ATOMS * MAX_TYPES; k += BS_T) a_cnt[k / MAX_TYPES][k % MAX_TYPES] = 0;
+            } else {
+                for (int aa = tid; aa < na; aa += BS_T) {
+                    int off = 0, tot = 0;
+                    for (int t = 0; t < n_types; ++t) {
+                        const int c = a_cnt[aa][t];
+                        tot += c;
+                        const int room = max_nbrs - off;
+                        a_cap[aa][t] = c < room ? c : room;
+                        a_base[aa][t] = off;
+                        off += a_cap[aa][t];
+                        a_cnt[aa][t] = 0;
                     }
-                    if (FILL) {
-                        if (cnt[t] < cap[t]) {
-                            const int64_t slot = i * max_nbrs + base[t] + cnt[t];
-                            rout[3 * slot] = r[0];
-                            rout[3 * slot + 1] = r[1];
-                            rout[3 * slot + 2] = r[2];
-                            jout[slot] = j;
-                            if (sh0 < -127 || sh0 > 127 || sh1 < -127 || sh1 > 127 || sh2 < -127 || sh2 > 127)
-                                wide = true;
-                            shout[slot] = (sh0 & 0xff) | ((sh1 & 0xff) << 8) | ((sh2 & 0xff) << 16);
-                        }
-                    }
-                    cnt[t]++;
+                    if (tot > max_nbrs) atomicOr(&flags[0], 1);
+                    atomicMax(&flags[1], tot);
                 }
             }
+            __syncthreads();
+            for (int og = 0; og < n_off; og += BS_T) {
+                {
+                    const int o = og + tid;
+                    int start = 0, c = 0, qp = pack_q(0, 0, 0);
+                    if (o < n_off) {
+                        const int dx = o % ox - g.s[0], dy = (o / ox) % oy - g.s[1], dz = o / (ox * oy) - g.s[2];
+                        int ux = bx + dx, uy = by + dy, uz = bz + dz, qx = 0, qy = 0, qz = 0;
+                        bool ok = true;
+                        if (g.pbc[0]) { qx = floordiv(ux, g.n[0]); ux -= qx * g.n[0]; } else ok = ok && ux >= 0 && ux < g.n[0];
+                        if (g.pbc[1]) { qy = floordiv(uy, g.n[1]); uy -= qy * g.n[1]; } else ok = ok && uy >= 0 && uy < g.n[1];
+                        if (g.pbc[2]) { qz = floordiv(uz, g.n[2]); uz -= qz * g.n[2]; } else ok = ok && uz >= 0 && uz < g.n[2];
+                        if (ok) {
+                            const long long nb = g.bin_off + ((long long)uz * g.n[1] + uy) * g.n[0] + ux;
+                            start = bin_start[nb];
+                            c = bin_count[nb];
+                            qp = pack_q(qx, qy, qz);
+                        }
+                    }
+                    o_start[tid] = start;
+                    o_q[tid] = qp;
+                    o_pre[tid + 1] = c;
+                    if (tid == 0) o_pre[0] = 0;
+                }
+                __syncthreads();
+                for (int d = 1; d < BS_T; d <<= 1) {   // inclusive scan of o_pre[1..BS_T]
+                    const int t = tid >= d ? o_pre[tid + 1 - d] : 0;
+                    __syncthreads();
+                    o_pre[tid + 1] += t;
+                    __syncthreads();
+                }
+                const int total = o_pre[BS_T];
+                for (int v0 = 0; v0 < total; v0 += BS_CAP) {
+                    const int nchunk = total - v0 < BS_CAP ? total - v0 : BS_CAP;
+                    for (int v = v0 + tid; v < v0 + nchunk; v += BS_T) {
+                        int L = 0;
+                        for (int step = BS_T / 2; step >= 1; step >>= 1)
+                            if (o_pre[L + step] <= v) L += step;
+                        const int j = bin_atoms[o_start[L] + v - o_pre[L]];
+                        const int q = o_q[L];
+                        const int sx = ((q & 1023) - 512) - atom_wrap[3 * j];
+                        const int sy = (((q >> 10) & 1023) - 512) - atom_wrap[3 * j + 1];
+                        const int sz = (((q >> 20) & 1023) - 512) - atom_wrap[3 * j + 2];
+                        const int e = v - v0;
+                        cx[e] = pos[3 * j] + sx * g.H[0] + sy * g.H[3] + sz * g.H[6];
+                        cy[e] = pos[3 * j + 1] + sx * g.H[1] + sy * g.H[4] + sz * g.H[7];
+                        cz[e] = pos[3 * j + 2] + sx * g.H[2] + sy * g.H[5] + sz * g.H[8];
+                        cj[e] = j;
+                        cs[e] = pack_q(sx, sy, sz);
+                        const int t = type[j];
+                        ct[e] = (t < 0 || t >= n_types) ? -1 : t;
+                    }
+                    __syncthreads();
+                    for (int aa = wave; aa < na; aa += BS_T / 64) {
+                        const int i = bin_atoms[my_start + a0 + aa];
+                        const int wi0 = atom_wrap[3 * i], wi1 = atom_wrap[3 * i + 1], wi2 = atom_wrap[3 * i + 2];
+                        // r_ij = staged + w_i.H - x_i
+                        const double bx0 = wi0 * g.H[0] + wi1 * g.H[3] + wi2 * g.H[6] - pos[3 * i];
+                        const double bx1 = wi0 * g.H[1] + wi1 * g.H[4] + wi2 * g.H[7] - pos[3 * i + 1];
+                        const double bx2 = wi0 * g.H[2] + wi1 * g.H[5] + wi2 * g.H[8] - pos[3 * i + 2];
+                        int cnt_t[MAX_TYPES], cap_t[MAX_TYPES], base_t[MAX_TYPES];
+#pragma unroll
+                        for (int t = 0; t < MAX_TYPES; ++t) {
+                            cnt_t[t] = a_cnt[aa][t];
+                            cap_t[t] = pass ? a_cap[aa][t] : 0;
+                            base_t[t] = pass ? a_base[aa][t] : 0;
+                        }
+                        for (int e0 = 0; e0 < nchunk; e0 += 64) {
+                            const int e = e0 + lane;
+                            bool ok = false;
+                            int t = -1, sh0 = 0, sh1 = 0, sh2 = 0, j = 0;
+                            double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+                            if (e < nchunk) {
+                                j = cj[e];
+                                const int q = cs[e];
+                                sh0 = ((q & 1023) - 512) + wi0;
+                                sh1 = (((q >> 10) & 1023) - 512) + wi1;
+                                sh2 = (((q >> 20) & 1023) - 512) + wi2;
+                                if (!(j == i && sh0 == 0 && sh1 == 0 && sh2 == 0)) {
+                                    r0 = cx[e] + bx0;
+                                    r1 = cy[e] + bx1;
+                                    r2 = cz[e] + bx2;
+                                    const double d = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+                                    if (d < rc) {
+                                        t = ct[e];
+                                        if (t < 0) {
+                                            bad_type = true;
+                                        } else {
+                                            ok = true;
+                                            if (d < 1e-6) overlap = true;
+                                        }
+                                    }
+                                }
+                            }
+                            for (int tt = 0; tt < n_types; ++tt) {
+                                const bool mine = ok && t == tt;
+                                const unsigned long long mk = __ballot(mine);
+                                if (pass == 1 && mine) {
+                                    const int slot_in = cnt_t[tt] + __popcll(mk & ((1ull << lane) - 1ull));
+                                    if (slot_in < cap_t[tt]) {
+                                        const int64_t slot = (int64_t)i * max_nbrs + base_t[tt] + slot_in;
+                                        rout[3 * slot] = r0;
+                                        rout[3 * slot + 1] = r1;
+                                        rout[3 * slot + 2] = r2;
+                                        jout[slot] = j;
+                                        if (sh0 < -127 || sh0 > 127 || sh1 < -127 || sh1 > 127 || sh2 < -127 ||
+                                            sh2 > 127)
+                                            wide = true;
+                                        shout[slot] = (sh0 & 0xff) | ((sh1 & 0xff) << 8) | ((sh2 & 0xff) << 16);
+                                    }
+                                }
+                                cnt_t[tt] += __popcll(mk);
+                            }
+                        }
+                        if (lane == 0)
+                            for (int t = 0; t < MAX_TYPES; ++t) a_cnt[aa][t] = cnt_t[t];
+                    }
+                    __syncthreads();
+                }
+            }
+            __syncthreads();
         }
-    }
-    if (!FILL) {
-        int tot = 0;
-        for (int t = 0; t < n_types; ++t) {
-            tcnt[i * n_types + t] = cnt[t];
-            tot += cnt[t];
+        for (int aa = tid; aa < na; aa += BS_T) {
+            const int i = bin_atoms[my_start + a0 + aa];
+            for (int t = 0; t < n_types; ++t) tcnt[(int64_t)i * n_types + t] = a_cap[aa][t];
         }
-        if (tot > max_nbrs) atomicOr(&flags[0], 1);
-        atomicMax(&flags[1], tot);
-        if (overlap) atomicOr(&flags[2], 1);
-        if (bad_type) atomicOr(&flags[3], 8);
-    } else {
-        for (int t = 0; t < n_types; ++t) tcnt[i * n_types + t] = cap[t];
-        if (wide) atomicOr(&flags[3], 2);
+        __syncthreads();
     }
+    }
+    if (overlap) atomicOr(&flags[2], 1);
+    if (wide) atomicOr(&flags[3], 2);
+    if (bad_type) atomicOr(&flags[3], 8);
 }
 
 __device__ inline int sx8(int v) { return (int)(signed char)(v & 0xff); }
 
-__global__ void reverse_kernel(int64_t n, int n_types, int max_nbrs, const int32_t *type, const int32_t *tcnt,
-                               const int32_t *jl, const int32_t *sh, int32_t *rev, int32_t *flags) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// one thread per list slot: find the slot of (j, i, -n) in j's list
+__global__ void reverse_pairs(int64_t n, int n_types, int max_nbrs, const int32_t *type, const int32_t *tcnt,
+                              const int32_t *jl, const int32_t *sh, int32_t *rev, int32_t *flags) {
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= n * max_nbrs) return;
+    const int64_t i = slot / max_nbrs;
+    const int p = (int)(slot % max_nbrs);
     int tot = 0;
     for (int t = 0; t < n_types; ++t) tot += tcnt[i * n_types + t];
+    if (p >= tot) return;
     const int zi = type[i];
     if (zi < 0 || zi >= n_types) return;
-    for (int p = 0; p < tot; ++p) {
-        const int64_t slot = i * max_nbrs + p;
-        const int j = jl[slot];
-        const int s = sh[slot];
-        const int want = ((-sx8(s)) & 0xff) | ((-sx8(s >> 8)) & 0xff) << 8 | ((-sx8(s >> 16)) & 0xff) << 16;
-        int start = 0;
-        for (int t = 0; t < zi; ++t) start += tcnt[(int64_t)j * n_types + t];
-        const int cnt = tcnt[(int64_t)j * n_types + zi];
-        int found = -1;
-        for (int q = start; q < start + cnt; ++q) {
-            const int64_t s2 = (int64_t)j * max_nbrs + q;
-            if (jl[s2] == (int)i && sh[s2] == want) {
-                found = (int)s2;
-                break;
-            }
+    const int j = jl[slot];
+    const int s = sh[slot];
+    const int want = ((-sx8(s)) & 0xff) | ((-sx8(s >> 8)) & 0xff) << 8 | ((-sx8(s >> 16)) & 0xff) << 16;
+    int start = 0;
+    for (int t = 0; t < zi; ++t) start += tcnt[(int64_t)j * n_types + t];
+    const int cnt = tcnt[(int64_t)j * n_types + zi];
+    int found = -1;
+    for (int q = start; q < start + cnt; ++q) {
+        const int64_t s2 = (int64_t)j * max_nbrs + q;
+        if (jl[s2] == (int)i && sh[s2] == want) {
+            found = (int)s2;
+            break;
         }
-        if (found < 0) {
-            atomicOr(&flags[3], 4);
-            found = (int)slot;   // keeps the gather in bounds; status reports the fault
-        }
-        rev[slot] = found;
     }
+    if (found < 0) {
+        atomicOr(&flags[3], 4);
+        found = (int)slot;   // keeps the gather in bounds; the status call reports the fault
+    }
+    rev[slot] = found;
 }
 
 }  // namespace
@@ -338,9 +465,9 @@ void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_
     const int64_t nscan = (bins + SCAN_B - 1) / SCAN_B;
     nb->work_sums.ensure(sizeof(int32_t) * (nscan > 0 ? nscan : 1));
     nb->bin_atoms.ensure(sizeof(int32_t) * (n > 0 ? n : 1));
-    nb->flags.ensure(sizeof(int32_t) * 4);
+    nb->flags.ensure(sizeof(int32_t) * 8);
     nb->bins_cap = bins;
-    launch_zero(nb->flags.ptr, sizeof(int32_t) * 4, st);
+    launch_zero(nb->flags.ptr, sizeof(int32_t) * 8, st);
     launch_zero(nb->bin_count.ptr, sizeof(int32_t) * bins, st);
     if (n == 0) return;
     auto *geo = nb->cfg_geo.as<CfgGeo>();
@@ -353,27 +480,22 @@ void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_
                        nb->atom_cfg.as<int32_t>(), nb->atom_bin.as<int32_t>(), nb->atom_wrap.as<int32_t>(),
                        nb->bin_count.as<int32_t>());
     hipLaunchKernelGGL(scan_block, dim3((unsigned)nscan), dim3(SCAN_B), 0, st, nb->bin_count.as<int32_t>(),
-                       nb->bin_start.as<int32_t>(), nb->work_sums.as<int32_t>(), bins);
+                       nb->bin_start.as<int32_t>(), nb->work_sums.as<int32_t>(), flags + 4);
     hipLaunchKernelGGL(scan_sums, dim3(1), dim3(SCAN_B), 0, st, nb->work_sums.as<int32_t>(), nscan);
     hipLaunchKernelGGL(scan_add, dim3((unsigned)nscan), dim3(SCAN_B), 0, st, nb->bin_start.as<int32_t>(),
-                       nb->work_sums.as<int32_t>(), bins);
-    MTP_HIP(hipMemcpyAsync(nb->bin_cursor.ptr, nb->bin_start.ptr, sizeof(int32_t) * bins, hipMemcpyDeviceToDevice,
-                           st));
+                       nb->work_sums.as<int32_t>(), flags + 4, nb->bin_cursor.as<int32_t>());
     hipLaunchKernelGGL(fill_bins, ga, dim3(TB), 0, st, n, nb->atom_bin.as<int32_t>(), nb->bin_cursor.as<int32_t>(),
                        nb->bin_atoms.as<int32_t>());
-    hipLaunchKernelGGL(sort_bins, dim3((unsigned)((bins + TB - 1) / TB)), dim3(TB), 0, st, bins,
+    const unsigned gbins = (unsigned)std::min<int64_t>((bins + 3) / 4, 2048);
+    hipLaunchKernelGGL(sort_bins, dim3(gbins), dim3(256), 0, st, flags,
                        nb->bin_start.as<int32_t>(), nb->bin_count.as<int32_t>(), nb->bin_atoms.as<int32_t>());
-    hipLaunchKernelGGL(search_kernel<false>, ga, dim3(TB), 0, st, n, nt, max_nbrs, m->r_cut, s->pos, s->type, geo,
-                       nb->atom_cfg.as<int32_t>(), nb->atom_bin.as<int32_t>(), nb->atom_wrap.as<int32_t>(),
-                       nb->bin_start.as<int32_t>(), nb->bin_count.as<int32_t>(), nb->bin_atoms.as<int32_t>(),
-                       nb->tcnt.as<int32_t>(), nullptr, nullptr, nullptr, flags);
-    hipLaunchKernelGGL(search_kernel<true>, ga, dim3(TB), 0, st, n, nt, max_nbrs, m->r_cut, s->pos, s->type, geo,
-                       nb->atom_cfg.as<int32_t>(), nb->atom_bin.as<int32_t>(), nb->atom_wrap.as<int32_t>(),
-                       nb->bin_start.as<int32_t>(), nb->bin_count.as<int32_t>(), nb->bin_atoms.as<int32_t>(),
-                       nb->tcnt.as<int32_t>(), nb->r.as<double>(), nb->j.as<int32_t>(), nb->shift.as<int32_t>(),
+    hipLaunchKernelGGL(bin_search, dim3((unsigned)std::min<int64_t>(bins, 8192)), dim3(BS_T), 0, st, flags + 4, s->n_cfg, nt, max_nbrs, m->r_cut,
+                       s->pos, s->type, geo, nb->atom_wrap.as<int32_t>(), nb->bin_start.as<int32_t>(),
+                       nb->bin_count.as<int32_t>(), nb->bin_atoms.as<int32_t>(), nb->tcnt.as<int32_t>(),
+                       nb->r.as<double>(), nb->j.as<int32_t>(), nb->shift.as<int32_t>(), flags);
+    hipLaunchKernelGGL(reverse_pairs, dim3((unsigned)((P + TB - 1) / TB)), dim3(TB), 0, st, n, nt, max_nbrs, s->type,
+                       nb->tcnt.as<int32_t>(), nb->j.as<int32_t>(), nb->shift.as<int32_t>(), nb->rev.as<int32_t>(),
                        flags);
-    hipLaunchKernelGGL(reverse_kernel, ga, dim3(TB), 0, st, n, nt, max_nbrs, s->type, nb->tcnt.as<int32_t>(),
-                       nb->j.as<int32_t>(), nb->shift.as<int32_t>(), nb->rev.as<int32_t>(), flags);
     MTP_HIP(hipGetLastError());
 }
 

@@ -14,53 +14,75 @@ __global__ void zero_kernel(uint32_t *p, size_t n_words) {
 
 // F_l = sum_{p in list(l)} (g_p - g_rev(p)): the first sum is -dV_l/dx_l, the
 // second collects dV_i/dx_l over every neighborhood i that holds l (or an
-// image of l).  Fixed order, no atomics: results are bitwise reproducible.
+// image of l).  FG_LANES lanes per atom, a fixed shuffle tree at the end, no
+// atomics: results are bitwise reproducible.
+constexpr int FG_LANES = 8;
 template <typename T>
-__global__ void force_gather(int64_t n, int nt, int maxn, const int32_t *tcnt, const int32_t *rev, const T *g,
-                             double *F) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__global__ __launch_bounds__(256) void force_gather(int64_t n, int nt, int maxn, const int32_t *tcnt,
+                                                    const int32_t *rev, const T *g, double *F) {
+    const int sub = threadIdx.x % FG_LANES;
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / FG_LANES;
+    const bool live = i < n;
     int tot = 0;
-    for (int t = 0; t < nt; ++t) tot += tcnt[i * nt + t];
+    if (live)
+        for (int t = 0; t < nt; ++t) tot += tcnt[i * nt + t];
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int p = 0; p < tot; ++p) {
+    for (int p = sub; p < tot; p += FG_LANES) {
         const int64_t s = i * maxn + p;
         const int64_t q = rev[s];
         fx += double(g[3 * s]) - double(g[3 * q]);
         fy += double(g[3 * s + 1]) - double(g[3 * q + 1]);
         fz += double(g[3 * s + 2]) - double(g[3 * q + 2]);
     }
-    F[3 * i] = fx;
-    F[3 * i + 1] = fy;
-    F[3 * i + 2] = fz;
+#pragma unroll
+    for (int o = FG_LANES / 2; o > 0; o >>= 1) {
+        fx += __shfl_xor(fx, o, 64);
+        fy += __shfl_xor(fy, o, 64);
+        fz += __shfl_xor(fz, o, 64);
+    }
+    if (live && sub == 0) {
+        F[3 * i] = fx;
+        F[3 * i + 1] = fy;
+        F[3 * i + 2] = fz;
+    }
 }
 
 // E_c = sum_i V_i and S_c = sum_i W_i over the atoms of configuration c
-// (eq. 1); FP64, fixed summation order.
-constexpr int SUM_T = 256;
-__global__ void cfg_sums(const int64_t *cfg_off, const double *site_e, const double *vir, double *energy,
-                         double *stress) {
-    const int c = blockIdx.x;
+// (eq. 1) in FP64.  Block (c, s) sums every SUM_S-th chunk of 256 atoms of
+// configuration c; a second kernel adds the SUM_S partials in order.
+constexpr int SUM_T = 256, SUM_S = 32;
+__global__ __launch_bounds__(SUM_T) void cfg_partial(const int64_t *cfg_off, const double *site_e, const double *vir,
+                                                     double *part) {
+    const int c = blockIdx.x / SUM_S, s = blockIdx.x % SUM_S;
     const int64_t b = cfg_off[c], e = cfg_off[c + 1];
     double acc[10];
     for (int k = 0; k < 10; ++k) acc[k] = 0.0;
-    for (int64_t i = b + threadIdx.x; i < e; i += SUM_T) {
+    for (int64_t i = b + (int64_t)s * SUM_T + threadIdx.x; i < e; i += (int64_t)SUM_S * SUM_T) {
         if (site_e) acc[0] += site_e[i];
         if (vir)
             for (int k = 0; k < 9; ++k) acc[1 + k] += vir[9 * i + k];
     }
-    __shared__ double s[10][SUM_T];
-    for (int k = 0; k < 10; ++k) s[k][threadIdx.x] = acc[k];
+    __shared__ double sh[10][SUM_T];
+    for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] = acc[k];
     __syncthreads();
     for (int w = SUM_T / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
-            for (int k = 0; k < 10; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+            for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        if (energy) energy[c] = s[0][0];
-        if (stress)
-            for (int k = 0; k < 9; ++k) stress[9 * c + k] = s[1 + k][0];
+    if (threadIdx.x < 10) part[(int64_t)blockIdx.x * 10 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void cfg_final(int n_cfg, const double *part, double *energy, double *stress) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n_cfg * 10) return;
+    const int c = (int)(t / 10), k = (int)(t % 10);
+    double s = 0.0;
+    for (int q = 0; q < SUM_S; ++q) s += part[((int64_t)c * SUM_S + q) * 10 + k];
+    if (k == 0) {
+        if (energy) energy[c] = s;
+    } else if (stress) {
+        stress[9 * c + k - 1] = s;
     }
 }
 
@@ -128,7 +150,7 @@ void launch_zero(void *p, size_t bytes, hipStream_t st) {
 void launch_force_gather(const mtp_nbrs *nb, const void *gbuf, int precision, double *forces, hipStream_t st) {
     const int64_t n = nb->n_atoms;
     if (!n) return;
-    const dim3 grid((unsigned)((n + 255) / 256));
+    const dim3 grid((unsigned)((n * FG_LANES + 255) / 256));
     if (precision == MTP_FP64)
         hipLaunchKernelGGL(force_gather<double>, grid, dim3(256), 0, st, n, nb->n_types, nb->max_nbrs,
                            nb->tcnt.as<int32_t>(), nb->rev.as<int32_t>(), static_cast<const double *>(gbuf), forces);
@@ -138,9 +160,13 @@ void launch_force_gather(const mtp_nbrs *nb, const void *gbuf, int precision, do
 }
 
 void launch_cfg_sums(const mtp_system *s, const double *site_e, const double *virial, double *energy, double *stress,
-                     hipStream_t st) {
+                     hipStream_t st, DevBuf &work) {
     if (s->n_cfg <= 0) return;
-    hipLaunchKernelGGL(cfg_sums, dim3(s->n_cfg), dim3(SUM_T), 0, st, s->cfg_off, site_e, virial, energy, stress);
+    work.ensure(sizeof(double) * 10 * SUM_S * (size_t)s->n_cfg);
+    hipLaunchKernelGGL(cfg_partial, dim3((unsigned)(s->n_cfg * SUM_S)), dim3(SUM_T), 0, st, s->cfg_off, site_e, virial,
+                       work.as<double>());
+    hipLaunchKernelGGL(cfg_final, dim3((unsigned)((s->n_cfg * 10 + 255) / 256)), dim3(256), 0, st, s->n_cfg,
+                       work.as<double>(), energy, stress);
 }
 
 void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision, void *dst, hipStream_t st) {

@@ -258,21 +258,40 @@ def _c(rows, A):
     return om.grades(rows, A)[2]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_grade_level16_two_species_small(precision):
+def _fp32_row_emulation(rows, A):
+    """Oracle grade of the oracle's rows rounded to FP32 and solved in FP64:
+    the error that FP32 rows alone force, whatever the product does."""
+    g0 = om.grades(rows, A)[0]
+    g1 = om.grades(rows.astype(np.float32).astype(np.float64), A)[0]
+    return float((np.abs(g1 - g0) / np.maximum(1.0, g0)).max())
+
+
+@pytest.mark.parametrize("precision,mode", [("fp64", "full"), ("fp64", "linear"), ("mixed", "full"),
+                                            ("mixed", "linear")])
+def test_grade_level16_two_species_small(precision, mode):
     w = synth.workload2(reps=(4, 4, 4))
     cfg = w.configs[0]
-    pot, theta, keep, g = _grade_case(2, w, cfg, precision, "full")
+    pot, theta, keep, g = _grade_case(2, w, cfg, precision, mode)
     pairs = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, w.r_cut)
-    rows = om.b_rows(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs)[:, keep]
-    gam, _, _ = om.grades(rows, active_rows(2, "full")[:, keep])
+    if mode == "full":
+        rows = om.b_rows(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs)[:, keep]
+        A = active_rows(2, "full")[:, keep]
+    else:
+        rows = om.linear_rows(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs)
+        A = active_rows(2, "linear")
+    gam, _, _ = om.grades(rows, A)
     err = np.abs(g["gamma"] - gam) / np.maximum(1.0, gam)
-    print(f"{precision} gamma: max rel err {err.max():.3g}, gamma range {gam.min():.3g}..{gam.max():.3g}")
+    emul = _fp32_row_emulation(rows, A)
+    print(f"{precision}/{mode} gamma: max rel err {err.max():.3g} (FP32-row emulation {emul:.3g}), "
+          f"gamma range {gam.min():.3g}..{gam.max():.3g}")
     if precision == "fp64":
         assert rel_err(g["rows"], rows) <= FP64_TOL
         assert err.max() <= 1e-8
     else:
-        assert err.max() <= 1e-5
+        # FP32 rows cannot do better than their own rounding, amplified by the
+        # conditioning of A (the emulation); the GPU rows carry a few more
+        # roundings of the moment sums and products.
+        assert err.max() <= max(1e-5, 30 * emul)
 
 
 def test_gamma_is_one_on_active_rows():
