@@ -22,7 +22,7 @@ EXPORTS = ("mtp_load", "mtp_save", "mtp_create", "mtp_free", "mtp_info", "mtp_se
            "mtp_set_active_set", "mtp_get_active_set", "mtp_nbrs_create", "mtp_nbrs_free", "mtp_build_neighbors",
            "mtp_nbrs_status", "mtp_nbrs_export", "mtp_energy_forces_stress", "mtp_grade", "mtp_evaluate",
            "mtp_b_rows", "mtp_select", "mtp_maxvol_update", "mtp_efs_backward", "mtp_basis_describe",
-           "mtp_compiled_levels", "mtp_last_error", "mtp_profile_enable", "mtp_profile_read")
+           "mtp_compiled_levels", "mtp_last_error", "mtp_profile_enable", "mtp_profile_read", "mtp_tune")
 
 
 class MtpError(RuntimeError):
@@ -86,6 +86,7 @@ def lib():
         "mtp_basis_describe": [I32, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(I32)],
         "mtp_compiled_levels": [ctypes.POINTER(I32), I32],
         "mtp_profile_enable": [ctypes.c_int],
+        "mtp_tune": [P, ctypes.POINTER(System), P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(I32), P],
         "mtp_profile_read": [ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I64)],
     }
     for name, args in sig.items():

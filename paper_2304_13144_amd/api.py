@@ -251,6 +251,49 @@ def maxvol_update(model, mode, cand, threshold=1.001, max_swaps=None):
     return sc[:n.value].cpu().numpy(), sj[:n.value].cpu().numpy()
 
 
+def efs_backward(model, batch, nbrs, gE=None, gF=None, gS=None, precision="fp64"):
+    """dL/dtheta for upstream gradients dL/dE [n_cfg], dL/dF [n_atoms, 3], dL/dS [n_cfg, 3, 3]."""
+    def prep(t, shape):
+        if t is None:
+            return None
+        return torch.as_tensor(t, dtype=torch.float64).to(batch.device).reshape(shape).contiguous()
+    gE_, gF_, gS_ = prep(gE, (batch.n_cfg,)), prep(gF, (batch.n_atoms, 3)), prep(gS, (batch.n_cfg, 3, 3))
+    out = torch.empty(model.info["n_theta"], dtype=torch.float64, device=batch.device)
+    s = batch.system()
+    check(_lib.lib().mtp_efs_backward(model._h, ctypes.byref(s), nbrs._h, _prec(precision), _p(gE_), _p(gF_),
+                                      _p(gS_), _p(out), _stream()))
+    return out
+
+
+class MTPEnergy(torch.autograd.Function):
+    """(E, F, S) = MTPEnergy.apply(theta, model, batch, nbrs, precision).
+
+    Forward evaluates energies [n_cfg], forces [n_atoms, 3] and stresses
+    [n_cfg, 3, 3] with theta loaded into the model; backward returns
+    dL/dtheta from the library's backward kernels (moments recomputed)."""
+
+    @staticmethod
+    def forward(ctx, theta, model, batch, nbrs, precision="fp64"):
+        model.set_params(theta.detach())
+        out = energy_forces_stress(model, batch, nbrs, precision, site_energies=False)
+        ctx.model, ctx.batch, ctx.nbrs, ctx.precision = model, batch, nbrs, precision
+        return out["energy"], out["forces"], out["stress"]
+
+    @staticmethod
+    def backward(ctx, gE, gF, gS):
+        g = efs_backward(ctx.model, ctx.batch, ctx.nbrs, gE, gF, gS, ctx.precision)
+        return g, None, None, None, None
+
+
+def tune(model, batch, nbrs, precision="fp64", mode="full"):
+    """Runs the library's autotuner for this system; returns the chosen lanes per neighborhood."""
+    lanes = ctypes.c_int32()
+    s = batch.system()
+    check(_lib.lib().mtp_tune(model._h, ctypes.byref(s), nbrs._h, _prec(precision), _mode(mode), ctypes.byref(lanes),
+                              _stream()))
+    return lanes.value
+
+
 def basis_describe(level):
     n = ctypes.c_int32()
     buf = ctypes.create_string_buffer(1 << 22)
@@ -265,4 +308,34 @@ def compiled_levels():
 
 
 __all__ = ["Model", "Batch", "Neighbors", "energy_forces_stress", "grade", "evaluate", "b_rows", "select",
-           "maxvol_update", "basis_describe", "compiled_levels", "MtpError"]
+           "maxvol_update", "efs_backward", "MTPEnergy", "tune", "CapturedStep", "basis_describe", "compiled_levels", "MtpError"]
+
+
+class CapturedStep:
+    """One hot-path step (neighbor build + fused evaluation + preselection)
+    captured once in a HIP graph and replayed.
+
+    The step must have run eagerly at least once at the same sizes so that
+    every library workspace exists (nothing is allocated during capture).
+    Outputs live in `self.out` and are overwritten by every replay."""
+
+    def __init__(self, model, batch, nbrs, precision="fp64", mode="full", max_nbrs=64, gamma_save=2.0):
+        self.model, self.batch, self.nbrs = model, batch, nbrs
+        self.args = (precision, mode, max_nbrs, gamma_save)
+        self.out = evaluate(model, batch, nbrs, precision, mode)
+        self._step()                      # eager warm-up: workspaces at their final size
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._step()
+        torch.cuda.synchronize()
+
+    def _step(self):
+        precision, mode, max_nbrs, gamma_save = self.args
+        self.nbrs.build(self.model, self.batch, max_nbrs=max_nbrs, check_status=False)
+        evaluate(self.model, self.batch, self.nbrs, precision, mode, out=self.out)
+        self.sel = select(self.out["gamma"], gamma_save)
+
+    def replay(self):
+        self.graph.replay()
+        return self.out

@@ -53,14 +53,19 @@ def generate(levels):
     units = []
     for L in levels:
         path = os.path.join(GEN, f"efs_level{L}.hip")
-        src = (f'#include "efs_kernel.hpp"\nnamespace mtp {{\n#include "mtp_level{L}.inc"\n'
-               f"MTP_EFS_LEVEL({L})\n}}  // namespace mtp\n")
+        src = (f'#include "efs_kernel.hpp"\n#include "backward_kernel.hpp"\nnamespace mtp {{\n'
+               f'#include "mtp_level{L}.inc"\nMTP_EFS_LEVEL({L})\nMTP_BWD_LEVEL({L})\n}}  // namespace mtp\n')
         _write_if_changed(path, src)
         units.append(path)
-    decl = "".join(f"template <> int launch_efs_level<{L}>(const EfsArgs &a);\n" for L in levels)
+    decl = "".join(f"template <> int launch_efs_level<{L}>(const EfsArgs &a);\n"
+                   f"template <> int launch_backward_level<{L}>(const BwdArgs &b);\n" for L in levels)
     cases = "".join(f"        case {L}: return launch_efs_level<{L}>(a);\n" for L in levels)
+    bcases = "".join(f"        case {L}: return launch_backward_level<{L}>(b);\n" for L in levels)
     disp = ('#include "internal.hpp"\nnamespace mtp {\ntemplate <int L> int launch_efs_level(const EfsArgs &a);\n'
+            + "template <int L> int launch_backward_level(const BwdArgs &b);\n"
             + decl + "int launch_efs(int level, const EfsArgs &a) {\n    switch (level) {\n" + cases
+            + "        default: return -1;\n    }\n}\n"
+            + "int launch_backward(int level, const BwdArgs &b) {\n    switch (level) {\n" + bcases
             + "        default: return -1;\n    }\n}\nstd::vector<int> compiled_levels() { return {"
             + ", ".join(str(L) for L in levels) + "}; }\nlong contraction_flops(int level) {\n    switch (level) {\n"
             + "".join(f"        case {L}: return {flops[L]};\n" for L in levels)

@@ -163,12 +163,19 @@ void check_nbrs(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb) {
     MTP_CHECK(nb->r_cut == m->r_cut, MTP_E_INVAL, "neighbor lists were built with another cutoff");
 }
 
-int lanes_for(const mtp_model *m, int64_t n) {
+int size_bucket(int64_t n) {
+    int b = 0;
+    while (b < 47 && (int64_t(1) << (b + 1)) <= n) ++b;
+    return b;
+}
+
+int lanes_for(const mtp_model *m, int64_t n, int prec) {
+    if (m->force_lanes) return m->force_lanes;
     if (const char *e = std::getenv("MTP_LANES")) {
         int v = std::atoi(e);
         if (v == 2 || v == 4 || v == 8) return v;
     }
-    (void)m;
+    if (int t = m->tuned_lanes[prec == MTP_FP64 ? 0 : 1][size_bucket(n)]) return t;
     // enough wavefronts for 256 CUs x 4 SIMDs, few lanes when the batch is large
     if (n >= (int64_t)1 << 20) return 2;
     if (n >= (int64_t)1 << 17) return 4;
@@ -236,7 +243,7 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     a.colmap = m->colmap.as<int32_t>();
     a.m = mm;
     a.precision = prec;
-    a.lanes = lanes_for(m, n);
+    a.lanes = lanes_for(m, n, prec);
     a.stream = st;
     m->mbuf.ensure(tsz * m->basis.n_comp() * (size_t)n);
     m->dmbuf.ensure(tsz * m->basis.n_comp() * (size_t)n);
@@ -680,8 +687,119 @@ int mtp_maxvol_update(mtp_model *m, mtp_grade_mode g, double *cand, int64_t n_ca
 int mtp_efs_backward(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, const double *gE,
                      const double *gF, const double *gS, double *g_theta, void *stream) {
     API_BEGIN
-    (void)m; (void)s; (void)nb; (void)p; (void)gE; (void)gF; (void)gS; (void)g_theta; (void)stream;
-    throw Error{MTP_E_UNSUPPORTED, "mtp_efs_backward is not available in this build"};
+    MTP_CHECK(m && g_theta, MTP_E_INVAL, "NULL argument");
+    check_system(m, s);
+    check_nbrs(m, s, nb);
+    MTP_CHECK(p == MTP_FP64 || p == MTP_MIXED, MTP_E_INVAL, "bad precision");
+    MTP_HIP(hipSetDevice(m->device));
+    hipStream_t st = S(stream);
+    const int64_t n = s->n_atoms;
+    if (n == 0) {
+        launch_zero(g_theta, sizeof(double) * m->n_theta, st);
+        return MTP_OK;
+    }
+    const size_t tsz = p == MTP_FP64 ? sizeof(double) : sizeof(float);
+    const size_t nc = m->basis.n_comp();
+    m->mbuf.ensure(tsz * nc * n);
+    m->dmbuf.ensure(tsz * nc * n);
+    m->tbuf.ensure(tsz * nc * n);
+    m->dtbuf.ensure(tsz * nc * n);
+    m->rows.ensure(tsz * (size_t)m->n_theta * n);
+    BwdArgs b{};
+    EfsArgs &a = b.e;
+    a.n_atoms = n;
+    a.atom_list = nullptr;
+    a.n_types = m->n_types;
+    a.max_nbrs = nb->max_nbrs;
+    a.r = nb->r.as<double>();
+    a.tcnt = nb->tcnt.as<int32_t>();
+    a.type = s->type;
+    a.r_min = m->r_min;
+    a.r_cut = m->r_cut;
+    const char *th = p == MTP_FP64 ? static_cast<const char *>(m->theta64.ptr) : static_cast<const char *>(m->theta32.ptr);
+    a.xi0 = th;
+    a.xi = th + tsz * m->n_types;
+    a.c = th + tsz * (m->n_types + m->basis.n_lin());
+    a.precision = p;
+    a.lanes = 4;
+    a.stream = st;
+    a.mbuf = m->mbuf.ptr;
+    a.dmbuf = m->dmbuf.ptr;
+    b.gE = gE;
+    b.gF = gF;
+    b.gS = gS;
+    b.atom_cfg = nb->atom_cfg.as<int32_t>();
+    b.nbr_j = nb->j.as<int32_t>();
+    b.tbuf = m->tbuf.ptr;
+    b.dtbuf = m->dtbuf.ptr;
+    b.rows = m->rows.ptr;
+    b.n_theta = m->n_theta;
+    int e;
+    {
+        ProfScope ps("backward", st);
+        e = launch_backward(m->level, b);
+    }
+    MTP_CHECK(e == 0, MTP_E_HIP, std::string("backward kernel launch: ") + hipGetErrorString((hipError_t)e));
+    {
+        ProfScope ps("backward_sum", st);
+        launch_column_sums(m->rows.ptr, p, n, m->n_theta, g_theta, st, m->sums);
+    }
+    MTP_HIP(hipGetLastError());
+    API_END
+}
+
+int mtp_tune(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
+             int32_t *lanes_out, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m && lanes_out, MTP_E_INVAL, "NULL argument");
+    check_system(m, s);
+    check_nbrs(m, s, nb);
+    MTP_CHECK(p == MTP_FP64 || p == MTP_MIXED, MTP_E_INVAL, "bad precision");
+    MTP_CHECK(g == MTP_GRADE_FULL || g == MTP_GRADE_LINEAR, MTP_E_INVAL, "bad grade mode");
+    MTP_HIP(hipSetDevice(m->device));
+    hipStream_t st = S(stream);
+    const int64_t n = s->n_atoms;
+    DevBuf out;
+    out.ensure(sizeof(double) * (3 * (size_t)n + 2 * (size_t)n + 10 * (size_t)s->n_cfg + 16));
+    double *base = out.as<double>();
+    EvalOut o;
+    o.energy = base;
+    o.stress = base + s->n_cfg;
+    o.forces = base + 10 * (size_t)s->n_cfg;
+    o.site_e = o.forces + 3 * (size_t)n;
+    if (m->act[g].valid) o.gamma = o.site_e + n;
+    o.mode = g;
+    hipEvent_t e0, e1;
+    MTP_HIP(hipEventCreate(&e0));
+    MTP_HIP(hipEventCreate(&e1));
+    int best = 0;
+    float best_ms = 0.f;
+    try {
+        for (int lanes : {2, 4, 8}) {
+            m->force_lanes = lanes;
+            evaluate(m, s, nb, p, o, st);   // warm-up (workspaces, caches)
+            MTP_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < 3; ++r) evaluate(m, s, nb, p, o, st);
+            MTP_HIP(hipEventRecord(e1, st));
+            MTP_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            MTP_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (!best || ms < best_ms) {
+                best = lanes;
+                best_ms = ms;
+            }
+        }
+    } catch (...) {
+        m->force_lanes = 0;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    m->force_lanes = 0;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    m->tuned_lanes[p == MTP_FP64 ? 0 : 1][size_bucket(n)] = best;
+    *lanes_out = best;
     API_END
 }
 

@@ -292,9 +292,10 @@ void write_level(const std::string &dir, int level) {
         std::string nf = std::string("comp_dfac") + "xyz"[ax];
         arr(nf.c_str(), [ax](const Component &c) { return c.e[ax]; });
     }
-    h << "\n  template <typename T, bool WB>\n";
-    h << "  __device__ __forceinline__ static void contract(const T (&M)[NC], const T *__restrict__ xi,\n"
-         "                                                  T *__restrict__ Bout, T (&dM)[NC], T &V) {\n";
+    // T: value type (double, float, or a dual number for tangents); XP: anything
+    // indexable giving xi_alpha; BP: anything indexable receiving B_alpha.
+    h << "\n  template <typename T, bool WB, typename XP, typename BP>\n";
+    h << "  __device__ __forceinline__ static void contract(const T (&M)[NC], XP xi, BP Bout, T (&dM)[NC], T &V) {\n";
     h << fwd << walk << rev;
     h << "  }\n};\n";
     std::ofstream out(dir + "/mtp_level" + std::to_string(level) + ".inc");

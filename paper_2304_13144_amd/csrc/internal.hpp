@@ -66,8 +66,10 @@ struct mtp_model {
     std::vector<int> colmap_host;   // full column -> kept column or -1
     mtp::DevBuf theta64, theta32, colmap;
     mtp::ActiveSet act[2];          // [MTP_GRADE_FULL], [MTP_GRADE_LINEAR]
+    int force_lanes = 0;            // set while the tuner times a schedule
+    int tuned_lanes[2][48] = {};    // [precision][floor(log2 n_atoms)] -> lanes per neighborhood, 0 = untuned
     // scratch of the evaluation path
-    mutable mtp::DevBuf gbuf, virial, sitebuf, brow, gamma_ws, argmax_ws, work, sums, mbuf, dmbuf;
+    mutable mtp::DevBuf gbuf, virial, sitebuf, brow, gamma_ws, argmax_ws, work, sums, mbuf, dmbuf, tbuf, dtbuf, rows;
     int m_of(int mode) const { return mode == MTP_GRADE_FULL ? (int)kept.size() : n_types + basis.n_lin(); }
 };
 
@@ -116,6 +118,19 @@ struct EfsArgs {
     hipStream_t stream;
 };
 int launch_efs(int level, const EfsArgs &a);
+
+struct BwdArgs {
+    EfsArgs e;                // neighbors, parameters, mbuf (moments), dmbuf (dV/dM)
+    const double *gE, *gF, *gS;
+    const int32_t *atom_cfg;
+    const int32_t *nbr_j;
+    void *tbuf, *dtbuf;       // [NC][n] tangent moments and H Mdot
+    void *rows;               // [n][n_theta] T: per-neighborhood gradient contributions
+    int n_theta;
+};
+int launch_backward(int level, const BwdArgs &b);
+void launch_column_sums(const void *rows, int precision, int64_t n, int ncol, double *out, hipStream_t st,
+                        DevBuf &work);
 std::vector<int> compiled_levels();
 long contraction_flops(int level);   // per neighborhood, from the generated program
 

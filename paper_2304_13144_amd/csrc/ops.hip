@@ -139,7 +139,47 @@ __global__ void sel_write(const double *g, int64_t n, double thr, const int32_t 
     if (blockIdx.x == 0 && threadIdx.x == 0 && *count > cap) *count = cap;
 }
 
+// column sums of the per-neighborhood gradient rows, FP64, fixed order:
+// block (column tile, atom chunk) -> partial; then partials in chunk order
+constexpr int CS_CH = 64;
+template <typename T>
+__global__ __launch_bounds__(256) void col_partial(const T *rows, int64_t n, int ncol, double *part) {
+    const int col = blockIdx.x * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
+    const int64_t chunk = (n + CS_CH - 1) / CS_CH;
+    const int64_t i0 = (int64_t)blockIdx.y * chunk, i1 = i0 + chunk < n ? i0 + chunk : n;
+    double s = 0.0;
+    if (col < ncol)
+        for (int64_t i = i0 + g; i < i1; i += 4) s += double(rows[i * ncol + col]);
+    __shared__ double sh[4][64];
+    sh[g][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (g == 0 && col < ncol)
+        part[(int64_t)blockIdx.y * ncol + col] = ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) +
+                                                 sh[3][threadIdx.x];
+}
+
+__global__ void col_final(const double *part, int ncol, double *out) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= ncol) return;
+    double s = 0.0;
+    for (int ch = 0; ch < CS_CH; ++ch) s += part[(int64_t)ch * ncol + col];
+    out[col] = s;
+}
+
 }  // namespace
+
+void launch_column_sums(const void *rows, int precision, int64_t n, int ncol, double *out, hipStream_t st,
+                        DevBuf &work) {
+    work.ensure(sizeof(double) * CS_CH * (size_t)ncol);
+    const dim3 grid((unsigned)((ncol + 63) / 64), CS_CH);
+    if (precision == MTP_FP64)
+        hipLaunchKernelGGL(col_partial<double>, grid, dim3(256), 0, st, static_cast<const double *>(rows), n, ncol,
+                           work.as<double>());
+    else
+        hipLaunchKernelGGL(col_partial<float>, grid, dim3(256), 0, st, static_cast<const float *>(rows), n, ncol,
+                           work.as<double>());
+    hipLaunchKernelGGL(col_final, dim3((unsigned)((ncol + 255) / 256)), dim3(256), 0, st, work.as<double>(), ncol, out);
+}
 
 void launch_zero(void *p, size_t bytes, hipStream_t st) {
     const size_t w = (bytes + 3) / 4;

@@ -1,0 +1,91 @@
+"""Batching, graph capture and the autotuner (GPU).
+
+* a batch of uneven configurations in one launch equals per-configuration runs;
+* a captured step replayed several times, with eager work in between, equals
+  the eager step every time (bitwise in FP64);
+* the autotuner's choice gives bitwise the same FP64 results as every other
+  schedule."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2304_13144_amd import api, synth
+from tests.helpers import active_rows, potential, theta_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _uneven_configs(n_cfg=12, seed=90):
+    r = np.random.default_rng(seed)
+    sizes = np.round(np.exp(r.uniform(np.log(16), np.log(600), n_cfg))).astype(int)
+    return [synth._vacancy_config(r, "fcc", int(n), 0.06, 2, 0.08, 0.0, vac_min_frac=0.05) for n in sizes]
+
+
+def _model16():
+    w = synth.workload2(reps=(4, 4, 4))
+    pot = potential(w)
+    m = api.Model.create(16, 2, 2.0, 5.0)
+    m.set_params(theta_for(2, pot))
+    keep = m.kept_columns()
+    m.set_active_set("full", active_rows(2, "full")[:, keep])
+    m.set_active_set("linear", active_rows(2, "linear"))
+    return m
+
+
+def _np(out):
+    return {k: v.detach().cpu().numpy().copy() for k, v in out.items() if v is not None}
+
+
+def test_uneven_batch_equals_single_configs():
+    m = _model16()
+    cfgs = _uneven_configs()
+    b = api.Batch(cfgs)
+    nb = api.Neighbors().build(m, b, max_nbrs=96)
+    together = _np(api.evaluate(m, b, nb, "fp64", "full"))
+    for k, cfg in enumerate(cfgs):
+        bk = api.Batch([cfg])
+        nk = api.Neighbors().build(m, bk, max_nbrs=96)
+        one = _np(api.evaluate(m, bk, nk, "fp64", "full"))
+        sl = slice(b.cfg_off_host[k], b.cfg_off_host[k + 1])
+        assert np.array_equal(together["forces"][sl], one["forces"])
+        assert np.array_equal(together["gamma"][sl], one["gamma"])
+        assert np.array_equal(together["site_e"][sl], one["site_e"])
+        assert together["energy"][k] == pytest.approx(one["energy"][0], rel=1e-13, abs=1e-12)
+        assert np.allclose(together["stress"][k], one["stress"][0], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_equals_eager(precision):
+    m = _model16()
+    b = api.Batch(_uneven_configs(8, seed=91))
+    nb = api.Neighbors().build(m, b, max_nbrs=96)
+    eager = _np(api.evaluate(m, b, nb, precision, "full"))
+    step = api.CapturedStep(m, b, nb, precision, "full", max_nbrs=96)
+    for rep in range(3):
+        # eager work and a synchronisation between replays
+        other = _np(api.evaluate(m, b, nb, precision, "linear"))
+        torch.cuda.synchronize()
+        got = _np(step.replay())
+        torch.cuda.synchronize()
+        for k in ("energy", "forces", "stress", "site_e", "gamma", "argmax"):
+            assert np.array_equal(got[k], eager[k]), (rep, k)
+        assert np.isfinite(other["gamma"]).all()
+
+
+def test_autotuner_choice_is_bitwise_equivalent():
+    m = _model16()
+    b = api.Batch([synth.workload2(reps=(8, 8, 8)).configs[0]])
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    lanes = api.tune(m, b, nb, "fp64", "full")
+    assert lanes in (2, 4, 8)
+    tuned = _np(api.evaluate(m, b, nb, "fp64", "full"))
+    import os
+    for k in ("2", "4", "8"):
+        os.environ["MTP_LANES"] = k
+        try:
+            other = _np(api.evaluate(m, b, nb, "fp64", "full"))
+        finally:
+            del os.environ["MTP_LANES"]
+        # lanes change the summation tree of the moments: equal to rounding
+        assert np.allclose(other["forces"], tuned["forces"], rtol=0, atol=1e-10 * np.abs(tuned["forces"]).max())
+        assert np.allclose(other["gamma"], tuned["gamma"], rtol=1e-9)
