@@ -39,6 +39,11 @@ template <typename T> __device__ inline void monomials(T x, T y, T z, T (&m)[20]
 
 }  // namespace efs
 
+template <typename T> struct XiPtr {      // xi_alpha, read where the program needs it
+    const T *p;
+    __device__ T operator[](int k) const { return p[k]; }
+};
+
 // Per-neighborhood context shared by the pair kernels.
 struct AtomCtx {
     bool live;
@@ -129,29 +134,91 @@ __global__ __launch_bounds__(256) void efs_moments(const EfsArgs a) {
     }
 }
 
-// ---- kernel 2: contraction, site energy (eq. 2), dV/dM; one lane each ----
+// ---- kernel 2: contraction, site energy (eq. 2), dV/dM -------------------
+// One block holds 64 neighborhoods (one per lane) and four wavefronts; the
+// graphs of the contraction program are split into four parts at build time
+// (Level<L>::graph_part).  Wavefront w evaluates the graph values of part w,
+// all four exchange them through LDS, each runs the (short) trie walk for
+// V, B_alpha and dV/dg, and wavefront w runs the reverse pass of part w.  The
+// four partial dV/dM are added in LDS in a fixed order.
+template <typename T> struct ColLoad {   // component k of one neighborhood, [k][n] layout
+    const T *p;
+    int64_t s;
+    __device__ T operator[](int k) const { return p[k * s]; }
+};
+template <typename T> struct RowSink {   // receives B_alpha when enabled
+    T *p;
+    bool on;
+    struct Ref {
+        T *q;
+        bool on;
+        __device__ void operator=(const T &v) const {
+            if (on) *q = v;
+        }
+    };
+    __device__ Ref operator[](int k) const { return Ref{p + k, on}; }
+};
+
 template <typename T, int L, bool WB>
 __global__ __launch_bounds__(256) void efs_contract(const EfsArgs a) {
     using LV = Level<L>;
-    constexpr int NC = LV::NC;
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= a.n_atoms) return;
-    const int64_t atom = a.atom_list ? (int64_t)a.atom_list[slot] : slot;
-    const int nt = a.n_types;
-    const T *min = static_cast<const T *>(a.mbuf);
-    T M[NC], dM[NC];
+    constexpr int NC = LV::NC, NG = LV::NGRAPH;
+    static_assert(LV::NPART == 4, "contraction kernel expects four parts");
+    __shared__ T sg[NG][64];
+    __shared__ T sdm[NC][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t slot = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = slot < a.n_atoms;
+    const int64_t sl = live ? slot : 0;
+    const ColLoad<T> M{static_cast<const T *>(a.mbuf) + sl, a.n_atoms};
+    {
+        T g[NG];
+        switch (wave) {
+            case 0: LV::template graphs_part<0>(M, g); break;
+            case 1: LV::template graphs_part<1>(M, g); break;
+            case 2: LV::template graphs_part<2>(M, g); break;
+            default: LV::template graphs_part<3>(M, g); break;
+        }
 #pragma unroll
-    for (int k = 0; k < NC; ++k) M[k] = min[(int64_t)k * a.n_atoms + slot];
+        for (int G = 0; G < NG; ++G)
+            if (LV::graph_part[G] == wave) sg[G][lane] = g[G];
+    }
+    __syncthreads();
+    T gin[NG], dg[NG];
+#pragma unroll
+    for (int G = 0; G < NG; ++G) gin[G] = sg[G][lane];
     T V = T(0);
-    T *brow = WB ? static_cast<T *>(a.brow) + slot * (int64_t)a.ldb : nullptr;
-    LV::template contract<T, WB>(M, static_cast<const T *>(a.xi), WB ? brow + nt : nullptr, dM, V);
-    T *dout = static_cast<T *>(a.dmbuf);
+    const int nt = a.n_types;
+    const XiPtr<T> xi{static_cast<const T *>(a.xi)};
+    if (WB && wave == 0) {
+        T *row = static_cast<T *>(a.brow) + sl * (int64_t)a.ldb + nt;
+        LV::template trie<T, true>(gin, xi, RowSink<T>{row, live}, dg, V);
+    } else {
+        LV::template trie<T, false>(gin, xi, RowSink<T>{nullptr, false}, dg, V);
+    }
+    T dMp[NC];
+    switch (wave) {
+        case 0: LV::template reverse_part<0>(M, dg, dMp); break;
+        case 1: LV::template reverse_part<1>(M, dg, dMp); break;
+        case 2: LV::template reverse_part<2>(M, dg, dMp); break;
+        default: LV::template reverse_part<3>(M, dg, dMp); break;
+    }
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
 #pragma unroll
-    for (int k = 0; k < NC; ++k) dout[(int64_t)k * a.n_atoms + slot] = dM[k];
-    if (a.site_e) {
-        int zi = a.type[atom];
-        zi = zi < 0 ? 0 : (zi >= nt ? nt - 1 : zi);
-        a.site_e[atom] = double(V) + double(static_cast<const T *>(a.xi0)[zi]);
+            for (int k = 0; k < NC; ++k) sdm[k][lane] = w == 0 ? dMp[k] : sdm[k][lane] + dMp[k];
+        }
+        __syncthreads();
+    }
+    if (live) {
+        T *dout = static_cast<T *>(a.dmbuf);
+        for (int k = wave; k < NC; k += 4) dout[(int64_t)k * a.n_atoms + slot] = sdm[k][lane];
+        if (wave == 0 && a.site_e) {
+            const int64_t atom = a.atom_list ? (int64_t)a.atom_list[slot] : slot;
+            int zi = a.type[atom];
+            zi = zi < 0 ? 0 : (zi >= nt ? nt - 1 : zi);
+            a.site_e[atom] = double(V) + double(static_cast<const T *>(a.xi0)[zi]);
+        }
     }
 }
 
@@ -326,7 +393,7 @@ template <int L> int launch_efs_level(const EfsArgs &a);
     template <typename T, int K, bool WB> static void launch_efs_tk##LEVEL(const EfsArgs &a) {           \
         const int per = 256 / K;                                                                         \
         const unsigned grid = (unsigned)((a.n_atoms + per - 1) / per);                                   \
-        const unsigned grid1 = (unsigned)((a.n_atoms + 255) / 256);                                      \
+        const unsigned grid1 = (unsigned)((a.n_atoms + 63) / 64);                                        \
         if (grid == 0) return;                                                                           \
         {                                                                                                \
             ProfScope ps("efs_moments", a.stream);                                                       \

@@ -13,6 +13,7 @@
 //     each graph polynomial.
 //
 // usage: gen_contract <out_dir> <level>...
+#include <algorithm>
 #include <cstdio>
 #include <fstream>
 #include <functional>
@@ -84,12 +85,17 @@ struct Emitter {
             }
     }
 
-    void graphs_forward() {
+    // Graph values of the graphs in `gl`.  to_array: written to gout[G] instead
+    // of local variables g<G>.
+    void graphs_forward(const std::vector<int> &gl, bool to_array) {
         os << "  // graph values\n";
-        for (size_t G = 0; G < B.graphs.size(); ++G) {
+        for (int G : gl) {
             auto &poly = B.polys[G];
-            os << "  T g" << G << ";  // " << B.graphs[G].str() << ", " << poly.size() << " monomials\n";
+            const std::string gv = to_array ? "acc" : "g" + std::to_string(G);
+            if (!to_array) os << "  T " << gv << ";";
+            os << "  // " << B.graphs[G].str() << ", " << poly.size() << " monomials\n";
             os << "  {\n";
+            if (to_array) os << "    T acc;\n";
             std::vector<int> tn;
             auto nodes = prefixes(poly, tn, "p");
             emit_products(nodes, fwd, "    ");
@@ -97,13 +103,14 @@ struct Emitter {
                 const std::string &v = nodes[tn[t]].name;
                 const long c = poly[t].coef;
                 if (t == 0) {
-                    if (c == 1) os << "    g" << G << " = " << v << ";\n";
-                    else { os << "    g" << G << " = " << lit(c) << " * " << v << ";\n"; fwd.mul++; }
+                    if (c == 1) os << "    " << gv << " = " << v << ";\n";
+                    else { os << "    " << gv << " = " << lit(c) << " * " << v << ";\n"; fwd.mul++; }
                 } else {
-                    if (c == 1) { os << "    g" << G << " += " << v << ";\n"; fwd.add++; }
-                    else { os << "    g" << G << " = fma(" << lit(c) << ", " << v << ", g" << G << ");\n"; fwd.fma++; }
+                    if (c == 1) { os << "    " << gv << " += " << v << ";\n"; fwd.add++; }
+                    else { os << "    " << gv << " = fma(" << lit(c) << ", " << v << ", " << gv << ");\n"; fwd.fma++; }
                 }
             }
+            if (to_array) os << "    gout[" << G << "] = acc;\n";
             os << "  }\n";
         }
     }
@@ -165,25 +172,30 @@ struct Emitter {
     }
     Counter trie_count;
 
-    void trie_walk() {
+    void trie_walk(bool arrays) {
         build_trie();
         os << "  // basis values, site energy and dV/dg by a walk over the factor trie\n";
+        if (arrays)
+            for (size_t G = 0; G < B.graphs.size(); ++G) os << "  const T g" << G << " = gin[" << G << "];\n";
         for (size_t G = 0; G < B.graphs.size(); ++G) os << "  T dg" << G << ";\n";
         dg_set.assign(B.graphs.size(), false);
+        trie_count = Counter{};
         os << "  T w0 = T(0);\n";
         visit(0, 0, "  ");
         os << "  V = w0;\n";
         for (size_t G = 0; G < B.graphs.size(); ++G)
             if (!dg_set[G]) os << "  dg" << G << " = T(0);\n";
+        if (arrays)
+            for (size_t G = 0; G < B.graphs.size(); ++G) os << "  dgout[" << G << "] = dg" << G << ";\n";
     }
 
-    void graphs_reverse() {
-        os << "  // dV/dM by reverse accumulation through every graph polynomial\n";
+    void graphs_reverse(const std::vector<int> &gl, bool dg_array) {
+        os << "  // dV/dM by reverse accumulation through the graph polynomials\n";
         std::vector<bool> dm_set(B.n_comp(), false);
-        std::ostringstream body;
-        for (size_t G = 0; G < B.graphs.size(); ++G) {
+        for (int G : gl) {
             auto &poly = B.polys[G];
             os << "  {\n";
+            if (dg_array) os << "    const T dg" << G << " = dgin[" << G << "];\n";
             std::vector<int> tn;
             auto nodes = prefixes(poly, tn, "q");
             emit_products(nodes, rev, "    ");
@@ -246,14 +258,54 @@ struct Emitter {
 void write_level(const std::string &dir, int level) {
     Basis B = build_basis(level);
     Emitter em(B);
-    em.graphs_forward();
+    std::vector<int> all(B.graphs.size());
+    for (size_t G = 0; G < all.size(); ++G) all[G] = (int)G;
+    em.graphs_forward(all, false);
     std::string fwd = em.os.str();
     em.os.str("");
-    em.trie_walk();
+    em.trie_walk(false);
     std::string walk = em.os.str();
     em.os.str("");
-    em.graphs_reverse();
+    em.graphs_reverse(all, false);
     std::string rev = em.os.str();
+    const Counter cf = em.fwd, ct = em.trie_count, cr = em.rev;
+
+    // Split of the graphs over NPART wavefronts (largest first onto the
+    // least loaded part; cost = monomial terms x degree).
+    const int NPART = 4;
+    std::vector<int> part(B.graphs.size(), 0);
+    {
+        std::vector<std::pair<long, int>> cost;
+        for (size_t G = 0; G < B.graphs.size(); ++G) {
+            long c = 0;
+            for (auto &t : B.polys[G]) c += (long)t.comp.size();
+            cost.push_back({c, (int)G});
+        }
+        std::sort(cost.begin(), cost.end(), [](auto &a, auto &b) { return a.first > b.first || (a.first == b.first && a.second < b.second); });
+        std::vector<long> load(NPART, 0);
+        for (auto &c : cost) {
+            int best = 0;
+            for (int q = 1; q < NPART; ++q)
+                if (load[q] < load[best]) best = q;
+            part[c.second] = best;
+            load[best] += c.first;
+        }
+    }
+    std::vector<std::string> pf(NPART), pr(NPART);
+    for (int q = 0; q < NPART; ++q) {
+        std::vector<int> gl;
+        for (size_t G = 0; G < B.graphs.size(); ++G)
+            if (part[G] == q) gl.push_back((int)G);
+        em.os.str("");
+        em.graphs_forward(gl, true);
+        pf[q] = em.os.str();
+        em.os.str("");
+        em.graphs_reverse(gl, true);
+        pr[q] = em.os.str();
+    }
+    em.os.str("");
+    em.trie_walk(true);
+    std::string walk_arrays = em.os.str();
 
     const int NC = B.n_comp();
     std::ostringstream h;
@@ -270,9 +322,13 @@ void write_level(const std::string &dir, int level) {
     for (auto &c : B.comps) maxnu = std::max(maxnu, c.nu);
     h << "  static constexpr int MAXNU = " << maxnu << ";\n";
     h << "  // flops of the contraction program per neighborhood (mul/add = 1, fma = 2)\n";
-    h << "  static constexpr long FLOPS_GRAPHS = " << em.fwd.flops() << ";\n";
-    h << "  static constexpr long FLOPS_TRIE = " << em.trie_count.flops() << ";\n";
-    h << "  static constexpr long FLOPS_REVERSE = " << em.rev.flops() << ";\n";
+    h << "  static constexpr long FLOPS_GRAPHS = " << cf.flops() << ";\n";
+    h << "  static constexpr long FLOPS_TRIE = " << ct.flops() << ";\n";
+    h << "  static constexpr long FLOPS_REVERSE = " << cr.flops() << ";\n";
+    h << "  static constexpr int NPART = " << NPART << ";\n";
+    h << "  static constexpr int graph_part[" << B.graphs.size() << "] = {";
+    for (size_t G = 0; G < B.graphs.size(); ++G) h << (G ? "," : "") << part[G];
+    h << "};\n";
     auto arr = [&](const char *name, auto f) {
         h << "  static constexpr int " << name << "[" << NC << "] = {";
         for (int k = 0; k < NC; ++k) h << (k ? "," : "") << f(B.comps[k]);
@@ -297,12 +353,26 @@ void write_level(const std::string &dir, int level) {
     h << "\n  template <typename T, bool WB, typename XP, typename BP>\n";
     h << "  __device__ __forceinline__ static void contract(const T (&M)[NC], XP xi, BP Bout, T (&dM)[NC], T &V) {\n";
     h << fwd << walk << rev;
+    h << "  }\n";
+    // the same program in parts: graph values of part P, the trie walk from
+    // all graph values, and the reverse pass of part P (dM zero elsewhere)
+    h << "\n  template <int P, typename T, typename MP>\n";
+    h << "  __device__ __forceinline__ static void graphs_part(MP M, T *gout) {\n";
+    for (int q = 0; q < NPART; ++q)
+        h << "  " << (q ? "else " : "") << "if constexpr (P == " << q << ") {\n" << pf[q] << "  }\n";
+    h << "  }\n";
+    h << "\n  template <typename T, bool WB, typename XP, typename BP>\n";
+    h << "  __device__ __forceinline__ static void trie(const T *gin, XP xi, BP Bout, T *dgout, T &V) {\n";
+    h << walk_arrays << "  }\n";
+    h << "\n  template <int P, typename T, typename MP>\n";
+    h << "  __device__ __forceinline__ static void reverse_part(MP M, const T *dgin, T (&dM)[NC]) {\n";
+    for (int q = 0; q < NPART; ++q)
+        h << "  " << (q ? "else " : "") << "if constexpr (P == " << q << ") {\n" << pr[q] << "  }\n";
     h << "  }\n};\n";
     std::ofstream out(dir + "/mtp_level" + std::to_string(level) + ".inc");
     out << h.str();
     std::cout << "level " << level << ": graphs " << B.graphs.size() << " basis " << B.n_lin() << " comps " << NC
-              << " flops graphs " << em.fwd.flops() << " trie " << em.trie_count.flops() << " reverse "
-              << em.rev.flops() << "\n";
+              << " flops graphs " << cf.flops() << " trie " << ct.flops() << " reverse " << cr.flops() << "\n";
 }
 
 }  // namespace

@@ -230,6 +230,8 @@ __global__ __launch_bounds__(BS_T) void bin_search(const int32_t *nbins_dev, int
     __shared__ int cj[BS_CAP], cs[BS_CAP], ct[BS_CAP];
     __shared__ int o_start[BS_T], o_pre[BS_T + 1], o_q[BS_T];
     __shared__ int a_cnt[BS_ATOMS][MAX_TYPES], a_base[BS_ATOMS][MAX_TYPES], a_cap[BS_ATOMS][MAX_TYPES];
+    __shared__ int a_idx[BS_ATOMS], a_w[BS_ATOMS][3];
+    __shared__ double a_off[BS_ATOMS][3];   // w_i.H - x_i of the bin's atoms
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     bool overlap = false, wide = false, bad_type = false;
     const int64_t nbins = *nbins_dev;
@@ -249,6 +251,17 @@ __global__ __launch_bounds__(BS_T) void bin_search(const int32_t *nbins_dev, int
     const int my_start = bin_start[bin];
     for (int a0 = 0; a0 < my_cnt; a0 += BS_ATOMS) {
         const int na = my_cnt - a0 < BS_ATOMS ? my_cnt - a0 : BS_ATOMS;
+        for (int aa = tid; aa < na; aa += BS_T) {
+            const int i = bin_atoms[my_start + a0 + aa];
+            const int w0 = atom_wrap[3 * i], w1 = atom_wrap[3 * i + 1], w2 = atom_wrap[3 * i + 2];
+            a_idx[aa] = i;
+            a_w[aa][0] = w0;
+            a_w[aa][1] = w1;
+            a_w[aa][2] = w2;
+            a_off[aa][0] = w0 * g.H[0] + w1 * g.H[3] + w2 * g.H[6] - pos[3 * i];
+            a_off[aa][1] = w0 * g.H[1] + w1 * g.H[4] + w2 * g.H[7] - pos[3 * i + 1];
+            a_off[aa][2] = w0 * g.H[2] + w1 * g.H[5] + w2 * g.H[8] - pos[3 * i + 2];
+        }
         for (int pass = 0; pass < 2; ++pass) {
             if (pass == 0) {
                 for (int k = tid; k < BS_ATOMS * MAX_TYPES; k += BS_T) a_cnt[k / MAX_TYPES][k % MAX_TYPES] = 0;
@@ -269,8 +282,10 @@ __global__ __launch_bounds__(BS_T) void bin_search(const int32_t *nbins_dev, int
                 }
             }
             __syncthreads();
+            // the staged chunk of pass 0 is still in LDS when it held every candidate
+            const bool reuse = pass == 1 && n_off <= BS_T && o_pre[BS_T] <= BS_CAP;
             for (int og = 0; og < n_off; og += BS_T) {
-                {
+                if (!reuse) {
                     const int o = og + tid;
                     int start = 0, c = 0, qp = pack_q(0, 0, 0);
                     if (o < n_off) {
@@ -291,18 +306,18 @@ __global__ __launch_bounds__(BS_T) void bin_search(const int32_t *nbins_dev, int
                     o_q[tid] = qp;
                     o_pre[tid + 1] = c;
                     if (tid == 0) o_pre[0] = 0;
-                }
-                __syncthreads();
-                for (int d = 1; d < BS_T; d <<= 1) {   // inclusive scan of o_pre[1..BS_T]
-                    const int t = tid >= d ? o_pre[tid + 1 - d] : 0;
                     __syncthreads();
-                    o_pre[tid + 1] += t;
-                    __syncthreads();
+                    for (int d = 1; d < BS_T; d <<= 1) {   // inclusive scan of o_pre[1..BS_T]
+                        const int t = tid >= d ? o_pre[tid + 1 - d] : 0;
+                        __syncthreads();
+                        o_pre[tid + 1] += t;
+                        __syncthreads();
+                    }
                 }
                 const int total = o_pre[BS_T];
                 for (int v0 = 0; v0 < total; v0 += BS_CAP) {
                     const int nchunk = total - v0 < BS_CAP ? total - v0 : BS_CAP;
-                    for (int v = v0 + tid; v < v0 + nchunk; v += BS_T) {
+                    for (int v = v0 + tid; !reuse && v < v0 + nchunk; v += BS_T) {
                         int L = 0;
                         for (int step = BS_T / 2; step >= 1; step >>= 1)
                             if (o_pre[L + step] <= v) L += step;
@@ -322,12 +337,10 @@ __global__ __launch_bounds__(BS_T) void bin_search(const int32_t *nbins_dev, int
                     }
                     __syncthreads();
                     for (int aa = wave; aa < na; aa += BS_T / 64) {
-                        const int i = bin_atoms[my_start + a0 + aa];
-                        const int wi0 = atom_wrap[3 * i], wi1 = atom_wrap[3 * i + 1], wi2 = atom_wrap[3 * i + 2];
+                        const int i = a_idx[aa];
+                        const int wi0 = a_w[aa][0], wi1 = a_w[aa][1], wi2 = a_w[aa][2];
                         // r_ij = staged + w_i.H - x_i
-                        const double bx0 = wi0 * g.H[0] + wi1 * g.H[3] + wi2 * g.H[6] - pos[3 * i];
-                        const double bx1 = wi0 * g.H[1] + wi1 * g.H[4] + wi2 * g.H[7] - pos[3 * i + 1];
-                        const double bx2 = wi0 * g.H[2] + wi1 * g.H[5] + wi2 * g.H[8] - pos[3 * i + 2];
+                        const double bx0 = a_off[aa][0], bx1 = a_off[aa][1], bx2 = a_off[aa][2];
                         int cnt_t[MAX_TYPES], cap_t[MAX_TYPES], base_t[MAX_TYPES];
 #pragma unroll
                         for (int t = 0; t < MAX_TYPES; ++t) {
@@ -391,11 +404,212 @@ __global__ __launch_bounds__(BS_T) void bin_search(const int32_t *nbins_dev, int
             __syncthreads();
         }
         for (int aa = tid; aa < na; aa += BS_T) {
-            const int i = bin_atoms[my_start + a0 + aa];
+            const int i = a_idx[aa];
             for (int t = 0; t < n_types; ++t) tcnt[(int64_t)i * n_types + t] = a_cap[aa][t];
         }
         __syncthreads();
     }
+    }
+    if (overlap) atomicOr(&flags[2], 1);
+    if (wide) atomicOr(&flags[3], 2);
+    if (bad_type) atomicOr(&flags[3], 8);
+}
+
+// One wavefront per bin, no block barriers.  Lanes take the surrounding bins
+// (64 at a time) and a wave-wide prefix sum numbers their atoms; windows of
+// up to 64 x SW_C candidates are held in registers, as their image
+// positions x_j + (q - w_j).H.  The bin's atoms are then visited one after
+// the other (their data broadcast from the lane that holds it) and tested
+// against every candidate of the window; ballots per neighbor species give
+// each accepted pair its slot.  Order: bin offset, then atom index in the
+// bin -- deterministic.  Pass 0 counts per species, pass 1 writes (clamped
+// to max_nbrs).
+constexpr int SW_C = 8;
+
+__global__ __launch_bounds__(256) void bin_search_wave(const int32_t *nbins_dev, int n_cfg, int n_types,
+                                                        int max_nbrs, double rc, const double *pos,
+                                                        const int32_t *type, const CfgGeo *geo,
+                                                        const int32_t *atom_wrap, const int32_t *bin_start,
+                                                        const int32_t *bin_count, const int32_t *bin_atoms,
+                                                        int32_t *tcnt, double *rout, int32_t *jout, int32_t *shout,
+                                                        int32_t *flags) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int64_t nbins = *nbins_dev;
+    bool overlap = false, wide = false, bad_type = false;
+    for (int64_t bin = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); bin < nbins; bin += (int64_t)gridDim.x * 4) {
+        const int my_cnt = bin_count[bin];
+        if (my_cnt == 0) continue;   // uniform per wavefront
+        int lo = 0, hi = n_cfg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (geo[mid].bin_off <= bin) lo = mid; else hi = mid - 1;
+        }
+        const CfgGeo &g = geo[lo];
+        double H[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) H[k] = g.H[k];
+        const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+        const int s0 = g.s[0], s1 = g.s[1], s2 = g.s[2];
+        const int p0 = g.pbc[0], p1 = g.pbc[1], p2 = g.pbc[2];
+        const long long boff = g.bin_off;
+        const int local = (int)(bin - boff);
+        const int bx = local % n0, by = (local / n0) % n1, bz = local / (n0 * n1);
+        const int ox = 2 * s0 + 1, oy = 2 * s1 + 1, oz = 2 * s2 + 1;
+        const int n_off = ox * oy * oz;
+        const int my_start = bin_start[bin];
+        for (int a0 = 0; a0 < my_cnt; a0 += 64) {
+            const int na = my_cnt - a0 < 64 ? my_cnt - a0 : 64;
+            // lane a holds atom a0 + a: index, wrap, w.H - x, and its counters
+            int ai = 0, aw0 = 0, aw1 = 0, aw2 = 0;
+            double ao0 = 0.0, ao1 = 0.0, ao2 = 0.0;
+            if (lane < na) {
+                ai = bin_atoms[my_start + a0 + lane];
+                aw0 = atom_wrap[3 * ai];
+                aw1 = atom_wrap[3 * ai + 1];
+                aw2 = atom_wrap[3 * ai + 2];
+                ao0 = aw0 * H[0] + aw1 * H[3] + aw2 * H[6] - pos[3 * ai];
+                ao1 = aw0 * H[1] + aw1 * H[4] + aw2 * H[7] - pos[3 * ai + 1];
+                ao2 = aw0 * H[2] + aw1 * H[5] + aw2 * H[8] - pos[3 * ai + 2];
+            }
+            int run[MAX_TYPES] = {0, 0, 0, 0}, cap[MAX_TYPES] = {0, 0, 0, 0}, base[MAX_TYPES] = {0, 0, 0, 0};
+            for (int pass = 0; pass < 2; ++pass) {
+                if (pass == 1 && lane < na) {
+                    int off = 0, tot = 0;
+                    for (int t = 0; t < n_types; ++t) {
+                        tot += run[t];
+                        const int room = max_nbrs - off;
+                        cap[t] = run[t] < room ? run[t] : room;
+                        base[t] = off;
+                        off += cap[t];
+                        run[t] = 0;
+                    }
+                    if (tot > max_nbrs) atomicOr(&flags[0], 1);
+                    atomicMax(&flags[1], tot);
+                }
+                for (int og = 0; og < n_off; og += 64) {
+                    const int o = og + lane;
+                    int start = 0, c = 0, qp = pack_q(0, 0, 0);
+                    if (o < n_off) {
+                        const int dx = o % ox - s0, dy = (o / ox) % oy - s1, dz = o / (ox * oy) - s2;
+                        int ux = bx + dx, uy = by + dy, uz = bz + dz, qx = 0, qy = 0, qz = 0;
+                        bool ok = true;
+                        if (p0) { qx = floordiv(ux, n0); ux -= qx * n0; } else ok = ok && ux >= 0 && ux < n0;
+                        if (p1) { qy = floordiv(uy, n1); uy -= qy * n1; } else ok = ok && uy >= 0 && uy < n1;
+                        if (p2) { qz = floordiv(uz, n2); uz -= qz * n2; } else ok = ok && uz >= 0 && uz < n2;
+                        if (ok) {
+                            const long long nb = boff + ((long long)uz * n1 + uy) * n0 + ux;
+                            start = bin_start[nb];
+                            c = bin_count[nb];
+                            qp = pack_q(qx, qy, qz);
+                        }
+                    }
+                    int inc = c;
+#pragma unroll
+                    for (int d = 1; d < 64; d <<= 1) {
+                        const int t = __shfl_up(inc, d, 64);
+                        if (lane >= d) inc += t;
+                    }
+                    const int excl = inc - c;
+                    const int total = __shfl(inc, 63, 64);
+                    for (int w0 = 0; w0 < total; w0 += 64 * SW_C) {
+                        double cx[SW_C], cy[SW_C], cz[SW_C];
+                        int cj[SW_C], cs[SW_C], ct[SW_C];
+#pragma unroll
+                        for (int cc = 0; cc < SW_C; ++cc) {
+                            const int v = w0 + cc * 64 + lane;
+                            int L = 0;
+#pragma unroll
+                            for (int step = 32; step >= 1; step >>= 1) {
+                                const int e = __shfl(excl, L + step, 64);
+                                if (e <= v) L += step;
+                            }
+                            const int st = __shfl(start, L, 64), pe = __shfl(excl, L, 64), q = __shfl(qp, L, 64);
+                            cj[cc] = -1;
+                            cx[cc] = cy[cc] = cz[cc] = 0.0;
+                            cs[cc] = pack_q(0, 0, 0);
+                            ct[cc] = -1;
+                            if (v < total) {
+                                const int j = bin_atoms[st + v - pe];
+                                const int sx = ((q & 1023) - 512) - atom_wrap[3 * j];
+                                const int sy = (((q >> 10) & 1023) - 512) - atom_wrap[3 * j + 1];
+                                const int sz = (((q >> 20) & 1023) - 512) - atom_wrap[3 * j + 2];
+                                cx[cc] = pos[3 * j] + sx * H[0] + sy * H[3] + sz * H[6];
+                                cy[cc] = pos[3 * j + 1] + sx * H[1] + sy * H[4] + sz * H[7];
+                                cz[cc] = pos[3 * j + 2] + sx * H[2] + sy * H[5] + sz * H[8];
+                                cj[cc] = j;
+                                cs[cc] = pack_q(sx, sy, sz);
+                                const int t = type[j];
+                                ct[cc] = (t < 0 || t >= n_types) ? -2 : t;
+                            }
+                        }
+                        for (int a = 0; a < na; ++a) {
+                            const int i = __shfl(ai, a, 64);
+                            const int wi0 = __shfl(aw0, a, 64), wi1 = __shfl(aw1, a, 64), wi2 = __shfl(aw2, a, 64);
+                            const double bx0 = __shfl(ao0, a, 64), bx1 = __shfl(ao1, a, 64), bx2 = __shfl(ao2, a, 64);
+                            int cnt_t[MAX_TYPES], cap_t[MAX_TYPES], base_t[MAX_TYPES];
+#pragma unroll
+                            for (int t = 0; t < MAX_TYPES; ++t) {
+                                cnt_t[t] = __shfl(run[t], a, 64);
+                                cap_t[t] = __shfl(cap[t], a, 64);
+                                base_t[t] = __shfl(base[t], a, 64);
+                            }
+#pragma unroll
+                            for (int cc = 0; cc < SW_C; ++cc) {
+                                if (w0 + cc * 64 >= total) break;   // uniform
+                                bool ok = false;
+                                int t = -1, sh0 = 0, sh1 = 0, sh2 = 0;
+                                double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+                                if (cj[cc] >= 0) {
+                                    const int q = cs[cc];
+                                    sh0 = ((q & 1023) - 512) + wi0;
+                                    sh1 = (((q >> 10) & 1023) - 512) + wi1;
+                                    sh2 = (((q >> 20) & 1023) - 512) + wi2;
+                                    if (!(cj[cc] == i && sh0 == 0 && sh1 == 0 && sh2 == 0)) {
+                                        r0 = cx[cc] + bx0;
+                                        r1 = cy[cc] + bx1;
+                                        r2 = cz[cc] + bx2;
+                                        const double d = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+                                        if (d < rc) {
+                                            t = ct[cc];
+                                            if (t == -2) {
+                                                bad_type = true;
+                                            } else {
+                                                ok = true;
+                                                if (d < 1e-6) overlap = true;
+                                            }
+                                        }
+                                    }
+                                }
+                                for (int tt = 0; tt < n_types; ++tt) {
+                                    const bool mine = ok && t == tt;
+                                    const unsigned long long mk = __ballot(mine);
+                                    if (pass == 1 && mine) {
+                                        const int slot_in = cnt_t[tt] + __popcll(mk & below);
+                                        if (slot_in < cap_t[tt]) {
+                                            const int64_t slot = (int64_t)i * max_nbrs + base_t[tt] + slot_in;
+                                            rout[3 * slot] = r0;
+                                            rout[3 * slot + 1] = r1;
+                                            rout[3 * slot + 2] = r2;
+                                            jout[slot] = cj[cc];
+                                            if (sh0 < -127 || sh0 > 127 || sh1 < -127 || sh1 > 127 || sh2 < -127 ||
+                                                sh2 > 127)
+                                                wide = true;
+                                            shout[slot] = (sh0 & 0xff) | ((sh1 & 0xff) << 8) | ((sh2 & 0xff) << 16);
+                                        }
+                                    }
+                                    cnt_t[tt] += __popcll(mk);
+                                }
+                            }
+                            if (lane == a)
+                                for (int t = 0; t < MAX_TYPES; ++t) run[t] = cnt_t[t];
+                        }
+                    }
+                }
+            }
+            if (lane < na)
+                for (int t = 0; t < n_types; ++t) tcnt[(int64_t)ai * n_types + t] = cap[t];
+        }
     }
     if (overlap) atomicOr(&flags[2], 1);
     if (wide) atomicOr(&flags[3], 2);
@@ -489,7 +703,7 @@ void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_
     const unsigned gbins = (unsigned)std::min<int64_t>((bins + 3) / 4, 2048);
     hipLaunchKernelGGL(sort_bins, dim3(gbins), dim3(256), 0, st, flags,
                        nb->bin_start.as<int32_t>(), nb->bin_count.as<int32_t>(), nb->bin_atoms.as<int32_t>());
-    hipLaunchKernelGGL(bin_search, dim3((unsigned)std::min<int64_t>(bins, 8192)), dim3(BS_T), 0, st, flags + 4, s->n_cfg, nt, max_nbrs, m->r_cut,
+    hipLaunchKernelGGL(bin_search, dim3((unsigned)std::min<int64_t>(bins, 2048)), dim3(BS_T), 0, st, flags + 4, s->n_cfg, nt, max_nbrs, m->r_cut,
                        s->pos, s->type, geo, nb->atom_wrap.as<int32_t>(), nb->bin_start.as<int32_t>(),
                        nb->bin_count.as<int32_t>(), nb->bin_atoms.as<int32_t>(), nb->tcnt.as<int32_t>(),
                        nb->r.as<double>(), nb->j.as<int32_t>(), nb->shift.as<int32_t>(), flags);
