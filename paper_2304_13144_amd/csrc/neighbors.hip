@@ -176,16 +176,48 @@ __global__ void fill_bins(int64_t n, const int32_t *atom_bin, int32_t *cursor, i
     bin_atoms[slot] = (int32_t)i;
 }
 
+__device__ inline int pack_q(int x, int y, int z) { return (x + 512) | ((y + 512) << 10) | ((z + 512) << 20); }
+
+struct Stage {
+    const double *pos;
+    const int32_t *type, *atom_cfg, *atom_wrap;
+    const CfgGeo *geo;
+    int n_types;
+    double *sx;     // [3 n] x_j - w_j.H
+    int32_t *sw;    // [n] pack_q(-w_j)
+    int32_t *st;    // [n] species (0 where out of range: that is reported)
+};
+
+// slot u of the bin order holds atom j: wrapped position, packed -wrap, species
+__device__ inline void stage_atom(const Stage &S, int64_t u, int j, bool &wide, bool &bad) {
+    const CfgGeo &g = S.geo[S.atom_cfg[j]];
+    const int w0 = S.atom_wrap[3 * (int64_t)j], w1 = S.atom_wrap[3 * (int64_t)j + 1],
+              w2 = S.atom_wrap[3 * (int64_t)j + 2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        S.sx[3 * u + k] = S.pos[3 * (int64_t)j + k] - (w0 * g.H[k] + w1 * g.H[3 + k] + w2 * g.H[6 + k]);
+    if (w0 < -255 || w0 > 255 || w1 < -255 || w1 > 255 || w2 < -255 || w2 > 255) wide = true;
+    S.sw[u] = pack_q(-w0, -w1, -w2);
+    const int t = S.type[j];
+    if (t < 0 || t >= S.n_types) bad = true;   // reported as an error; 0 keeps later indexing in range
+    S.st[u] = (t < 0 || t >= S.n_types) ? 0 : t;
+}
+
 // One wavefront per bin: the bin's atoms (filled in arbitrary order by
 // atomics) are put in ascending index order, which makes every later step
-// deterministic.  Ranks come from all-pairs comparisons across the lanes.
-__device__ inline void sort_one_bin(int32_t *a, int c, int lane) {
-    if (c <= 1) return;
+// deterministic, and each is staged at its slot.  Ranks come from all-pairs
+// comparisons across the lanes; bins over 64 atoms are sorted by one lane.
+__device__ inline void sort_stage_bin(int32_t *a, int64_t start, int c, int lane, const Stage &S, bool &wide,
+                                      bool &bad) {
+    if (c <= 0) return;
     if (c <= 64) {
         const int v = lane < c ? a[lane] : 0x7fffffff;
         int rank = 0;
         for (int k = 0; k < c; ++k) rank += __shfl(v, k, 64) < v ? 1 : 0;
-        if (lane < c) a[rank] = v;
+        if (lane < c) {
+            a[rank] = v;
+            stage_atom(S, start + rank, v, wide, bad);
+        }
     } else if (lane == 0) {
         for (int x = 1; x < c; ++x) {
             const int32_t v = a[x];
@@ -196,250 +228,251 @@ __device__ inline void sort_one_bin(int32_t *a, int c, int lane) {
             }
             a[y + 1] = v;
         }
+        for (int x = 0; x < c; ++x) stage_atom(S, start + x, a[x], wide, bad);
     }
 }
 
-__global__ __launch_bounds__(256) void sort_bins(const int32_t *flags, const int32_t *start, const int32_t *count,
-                                                 int32_t *bin_atoms) {
+__global__ __launch_bounds__(256) void sort_bins(int32_t *flags, const int32_t *start, const int32_t *count,
+                                                 int32_t *bin_atoms, Stage S) {
     const int lane = threadIdx.x & 63;
     const int64_t nbins = flags[4];
+    bool wide = false, bad = false;
     for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nbins; b += (int64_t)gridDim.x * 4)
-        sort_one_bin(bin_atoms + start[b], count[b], lane);
+        sort_stage_bin(bin_atoms + start[b], start[b], count[b], lane, S, wide, bad);
+    const bool any_wide = __ballot(wide) != 0, any_bad = __ballot(bad) != 0;
+    if (lane == 0 && (any_wide || any_bad)) atomicOr(&flags[3], (any_wide ? 2 : 0) | (any_bad ? 8 : 0));
 }
 
 __device__ inline int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
-// One block per bin.  The atoms of the bins around it (all periodic images
-// that can hold a neighbor) are staged in LDS in chunks, each as its image
-// position x_j + (q - w_j).H, so that r_ij = staged + w_i.H - x_i.  Each
-// wavefront then tests one of the bin's atoms against the chunk, 64
-// candidates at a time; ballots per neighbor species give every accepted pair
-// its slot, so the order (bin offset, then atom index in the bin) is
-// deterministic.  Pass 0 counts per species, pass 1 writes the lists
-// (clamped to max_nbrs).
-constexpr int BS_T = 256, BS_CAP = 1024, BS_ATOMS = 64;
+// ---- pair search ------------------------------------------------------------
+//
+// One block of four wavefronts per bin.  The candidates of the bin (atoms of
+// the surrounding bins, every periodic image that can be in range) are
+// numbered by a wave-wide prefix sum over the bin offsets and staged in LDS,
+// a window of PS_WIN at a time, each as its image position y_j + q.H
+// (y_j = x_j - w_j.H: atom j wrapped into the cell, q: periodic wrap of the
+// bin offset).  For an atom i of the bin r_ij = image - y_i and the pair's
+// shift is q - w_j + w_i.  Wave w builds the neighborhoods of the bin's atoms
+// w, w + 4, ...: lanes test candidates 64 at a time, ballots per neighbor
+// species give every accepted pair its place in the list (grouped by
+// species, candidate order inside a group, clamped to max_nbrs), and the
+// pairs are then written with consecutive lanes on consecutive slots.  When
+// the candidates fit one window (the usual case) every distance is computed
+// once; otherwise each atom takes a counting sweep and a writing sweep over
+// the windows.
+constexpr int PS_WIN = 512;
+constexpr int PS_CC = PS_WIN / 64;
 
-__device__ inline int pack_q(int x, int y, int z) { return (x + 512) | ((y + 512) << 10) | ((z + 512) << 20); }
+__device__ inline int field(int p, int k) { return ((p >> (10 * k)) & 1023) - 512; }
 
-__global__ __launch_bounds__(BS_T) void bin_search(const int32_t *nbins_dev, int n_cfg, int n_types, int max_nbrs, double rc,
-                                                   const double *pos, const int32_t *type, const CfgGeo *geo,
-                                                   const int32_t *atom_wrap, const int32_t *bin_start,
-                                                   const int32_t *bin_count, const int32_t *bin_atoms, int32_t *tcnt,
-                                                   double *rout, int32_t *jout, int32_t *shout, int32_t *flags) {
-    __shared__ double cx[BS_CAP], cy[BS_CAP], cz[BS_CAP];
-    __shared__ int cj[BS_CAP], cs[BS_CAP], ct[BS_CAP];
-    __shared__ int o_start[BS_T], o_pre[BS_T + 1], o_q[BS_T];
-    __shared__ int a_cnt[BS_ATOMS][MAX_TYPES], a_base[BS_ATOMS][MAX_TYPES], a_cap[BS_ATOMS][MAX_TYPES];
-    __shared__ int a_idx[BS_ATOMS], a_w[BS_ATOMS][3];
-    __shared__ double a_off[BS_ATOMS][3];   // w_i.H - x_i of the bin's atoms
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    bool overlap = false, wide = false, bad_type = false;
-    const int64_t nbins = *nbins_dev;
-    for (int64_t bin = blockIdx.x; bin < nbins; bin += gridDim.x) {
-    const int my_cnt = bin_count[bin];
-    if (my_cnt == 0) continue;   // uniform per block
-    int lo = 0, hi = n_cfg - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) / 2;
-        if (geo[mid].bin_off <= bin) lo = mid; else hi = mid - 1;
-    }
-    const CfgGeo g = geo[lo];
-    const int local = (int)(bin - g.bin_off);
-    const int bx = local % g.n[0], by = (local / g.n[0]) % g.n[1], bz = local / (g.n[0] * g.n[1]);
-    const int ox = 2 * g.s[0] + 1, oy = 2 * g.s[1] + 1, oz = 2 * g.s[2] + 1;
-    const int n_off = ox * oy * oz;
-    const int my_start = bin_start[bin];
-    for (int a0 = 0; a0 < my_cnt; a0 += BS_ATOMS) {
-        const int na = my_cnt - a0 < BS_ATOMS ? my_cnt - a0 : BS_ATOMS;
-        for (int aa = tid; aa < na; aa += BS_T) {
-            const int i = bin_atoms[my_start + a0 + aa];
-            const int w0 = atom_wrap[3 * i], w1 = atom_wrap[3 * i + 1], w2 = atom_wrap[3 * i + 2];
-            a_idx[aa] = i;
-            a_w[aa][0] = w0;
-            a_w[aa][1] = w1;
-            a_w[aa][2] = w2;
-            a_off[aa][0] = w0 * g.H[0] + w1 * g.H[3] + w2 * g.H[6] - pos[3 * i];
-            a_off[aa][1] = w0 * g.H[1] + w1 * g.H[4] + w2 * g.H[7] - pos[3 * i + 1];
-            a_off[aa][2] = w0 * g.H[2] + w1 * g.H[5] + w2 * g.H[8] - pos[3 * i + 2];
+struct Around {   // the bins around one bin: this lane's bin offset
+    int start, count, qp, excl, total;
+};
+
+__device__ inline Around around_bin(const CfgGeo &g, int bx, int by, int bz, int o, int n_off, int lane,
+                                    const int32_t *bin_start, const int32_t *bin_count) {
+    Around A{0, 0, pack_q(0, 0, 0), 0, 0};
+    if (o < n_off) {
+        const int ox = 2 * g.s[0] + 1, oy = 2 * g.s[1] + 1;
+        const int dx = o % ox - g.s[0], dy = (o / ox) % oy - g.s[1], dz = o / (ox * oy) - g.s[2];
+        int ux = bx + dx, uy = by + dy, uz = bz + dz, qx = 0, qy = 0, qz = 0;
+        bool ok = true;
+        if (g.pbc[0]) { qx = floordiv(ux, g.n[0]); ux -= qx * g.n[0]; } else ok = ok && ux >= 0 && ux < g.n[0];
+        if (g.pbc[1]) { qy = floordiv(uy, g.n[1]); uy -= qy * g.n[1]; } else ok = ok && uy >= 0 && uy < g.n[1];
+        if (g.pbc[2]) { qz = floordiv(uz, g.n[2]); uz -= qz * g.n[2]; } else ok = ok && uz >= 0 && uz < g.n[2];
+        if (ok) {
+            const long long nb = g.bin_off + ((long long)uz * g.n[1] + uy) * g.n[0] + ux;
+            A.start = bin_start[nb];
+            A.count = bin_count[nb];
+            A.qp = pack_q(qx, qy, qz);
         }
-        for (int pass = 0; pass < 2; ++pass) {
-            if (pass == 0) {
-                for (int k = tid; k < BS_ATOMS * MAX_TYPES; k += BS_T) a_cnt[k / MAX_TYPES][k % MAX_TYPES] = 0;
-            } else {
-                for (int aa = tid; aa < na; aa += BS_T) {
-                    int off = 0, tot = 0;
-                    for (int t = 0; t < n_types; ++t) {
-                        const int c = a_cnt[aa][t];
-                        tot += c;
-                        const int room = max_nbrs - off;
-                        a_cap[aa][t] = c < room ? c : room;
-                        a_base[aa][t] = off;
-                        off += a_cap[aa][t];
-                        a_cnt[aa][t] = 0;
-                    }
-                    if (tot > max_nbrs) atomicOr(&flags[0], 1);
-                    atomicMax(&flags[1], tot);
-                }
-            }
-            __syncthreads();
-            // the staged chunk of pass 0 is still in LDS when it held every candidate
-            const bool reuse = pass == 1 && n_off <= BS_T && o_pre[BS_T] <= BS_CAP;
-            for (int og = 0; og < n_off; og += BS_T) {
-                if (!reuse) {
-                    const int o = og + tid;
-                    int start = 0, c = 0, qp = pack_q(0, 0, 0);
-                    if (o < n_off) {
-                        const int dx = o % ox - g.s[0], dy = (o / ox) % oy - g.s[1], dz = o / (ox * oy) - g.s[2];
-                        int ux = bx + dx, uy = by + dy, uz = bz + dz, qx = 0, qy = 0, qz = 0;
-                        bool ok = true;
-                        if (g.pbc[0]) { qx = floordiv(ux, g.n[0]); ux -= qx * g.n[0]; } else ok = ok && ux >= 0 && ux < g.n[0];
-                        if (g.pbc[1]) { qy = floordiv(uy, g.n[1]); uy -= qy * g.n[1]; } else ok = ok && uy >= 0 && uy < g.n[1];
-                        if (g.pbc[2]) { qz = floordiv(uz, g.n[2]); uz -= qz * g.n[2]; } else ok = ok && uz >= 0 && uz < g.n[2];
-                        if (ok) {
-                            const long long nb = g.bin_off + ((long long)uz * g.n[1] + uy) * g.n[0] + ux;
-                            start = bin_start[nb];
-                            c = bin_count[nb];
-                            qp = pack_q(qx, qy, qz);
-                        }
-                    }
-                    o_start[tid] = start;
-                    o_q[tid] = qp;
-                    o_pre[tid + 1] = c;
-                    if (tid == 0) o_pre[0] = 0;
-                    __syncthreads();
-                    for (int d = 1; d < BS_T; d <<= 1) {   // inclusive scan of o_pre[1..BS_T]
-                        const int t = tid >= d ? o_pre[tid + 1 - d] : 0;
-                        __syncthreads();
-                        o_pre[tid + 1] += t;
-                        __syncthreads();
-                    }
-                }
-                const int total = o_pre[BS_T];
-                for (int v0 = 0; v0 < total; v0 += BS_CAP) {
-                    const int nchunk = total - v0 < BS_CAP ? total - v0 : BS_CAP;
-                    for (int v = v0 + tid; !reuse && v < v0 + nchunk; v += BS_T) {
-                        int L = 0;
-                        for (int step = BS_T / 2; step >= 1; step >>= 1)
-                            if (o_pre[L + step] <= v) L += step;
-                        const int j = bin_atoms[o_start[L] + v - o_pre[L]];
-                        const int q = o_q[L];
-                        const int sx = ((q & 1023) - 512) - atom_wrap[3 * j];
-                        const int sy = (((q >> 10) & 1023) - 512) - atom_wrap[3 * j + 1];
-                        const int sz = (((q >> 20) & 1023) - 512) - atom_wrap[3 * j + 2];
-                        const int e = v - v0;
-                        cx[e] = pos[3 * j] + sx * g.H[0] + sy * g.H[3] + sz * g.H[6];
-                        cy[e] = pos[3 * j + 1] + sx * g.H[1] + sy * g.H[4] + sz * g.H[7];
-                        cz[e] = pos[3 * j + 2] + sx * g.H[2] + sy * g.H[5] + sz * g.H[8];
-                        cj[e] = j;
-                        cs[e] = pack_q(sx, sy, sz);
-                        const int t = type[j];
-                        ct[e] = (t < 0 || t >= n_types) ? -1 : t;
-                    }
-                    __syncthreads();
-                    for (int aa = wave; aa < na; aa += BS_T / 64) {
-                        const int i = a_idx[aa];
-                        const int wi0 = a_w[aa][0], wi1 = a_w[aa][1], wi2 = a_w[aa][2];
-                        // r_ij = staged + w_i.H - x_i
-                        const double bx0 = a_off[aa][0], bx1 = a_off[aa][1], bx2 = a_off[aa][2];
-                        int cnt_t[MAX_TYPES], cap_t[MAX_TYPES], base_t[MAX_TYPES];
+    }
+    int inc = A.count;
 #pragma unroll
-                        for (int t = 0; t < MAX_TYPES; ++t) {
-                            cnt_t[t] = a_cnt[aa][t];
-                            cap_t[t] = pass ? a_cap[aa][t] : 0;
-                            base_t[t] = pass ? a_base[aa][t] : 0;
-                        }
-                        for (int e0 = 0; e0 < nchunk; e0 += 64) {
-                            const int e = e0 + lane;
-                            bool ok = false;
-                            int t = -1, sh0 = 0, sh1 = 0, sh2 = 0, j = 0;
-                            double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-                            if (e < nchunk) {
-                                j = cj[e];
-                                const int q = cs[e];
-                                sh0 = ((q & 1023) - 512) + wi0;
-                                sh1 = (((q >> 10) & 1023) - 512) + wi1;
-                                sh2 = (((q >> 20) & 1023) - 512) + wi2;
-                                if (!(j == i && sh0 == 0 && sh1 == 0 && sh2 == 0)) {
-                                    r0 = cx[e] + bx0;
-                                    r1 = cy[e] + bx1;
-                                    r2 = cz[e] + bx2;
-                                    const double d = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
-                                    if (d < rc) {
-                                        t = ct[e];
-                                        if (t < 0) {
-                                            bad_type = true;
-                                        } else {
-                                            ok = true;
-                                            if (d < 1e-6) overlap = true;
-                                        }
-                                    }
-                                }
-                            }
-                            for (int tt = 0; tt < n_types; ++tt) {
-                                const bool mine = ok && t == tt;
-                                const unsigned long long mk = __ballot(mine);
-                                if (pass == 1 && mine) {
-                                    const int slot_in = cnt_t[tt] + __popcll(mk & ((1ull << lane) - 1ull));
-                                    if (slot_in < cap_t[tt]) {
-                                        const int64_t slot = (int64_t)i * max_nbrs + base_t[tt] + slot_in;
-                                        rout[3 * slot] = r0;
-                                        rout[3 * slot + 1] = r1;
-                                        rout[3 * slot + 2] = r2;
-                                        jout[slot] = j;
-                                        if (sh0 < -127 || sh0 > 127 || sh1 < -127 || sh1 > 127 || sh2 < -127 ||
-                                            sh2 > 127)
-                                            wide = true;
-                                        shout[slot] = (sh0 & 0xff) | ((sh1 & 0xff) << 8) | ((sh2 & 0xff) << 16);
-                                    }
-                                }
-                                cnt_t[tt] += __popcll(mk);
-                            }
-                        }
-                        if (lane == 0)
-                            for (int t = 0; t < MAX_TYPES; ++t) a_cnt[aa][t] = cnt_t[t];
-                    }
-                    __syncthreads();
-                }
-            }
-            __syncthreads();
-        }
-        for (int aa = tid; aa < na; aa += BS_T) {
-            const int i = a_idx[aa];
-            for (int t = 0; t < n_types; ++t) tcnt[(int64_t)i * n_types + t] = a_cap[aa][t];
-        }
-        __syncthreads();
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += t;
     }
-    }
-    if (overlap) atomicOr(&flags[2], 1);
-    if (wide) atomicOr(&flags[3], 2);
-    if (bad_type) atomicOr(&flags[3], 8);
+    A.excl = inc - A.count;
+    A.total = __shfl(inc, 63, 64);
+    return A;
 }
 
-// One wavefront per bin, no block barriers.  Lanes take the surrounding bins
-// (64 at a time) and a wave-wide prefix sum numbers their atoms; windows of
-// up to 64 x SW_C candidates are held in registers, as their image
-// positions x_j + (q - w_j).H.  The bin's atoms are then visited one after
-// the other (their data broadcast from the lane that holds it) and tested
-// against every candidate of the window; ballots per neighbor species give
-// each accepted pair its slot.  Order: bin offset, then atom index in the
-// bin -- deterministic.  Pass 0 counts per species, pass 1 writes (clamped
-// to max_nbrs).
-constexpr int SW_C = 8;
+struct Staged {
+    const double *sx;
+    const int32_t *sw, *st, *bin_atoms;
+};
 
-__global__ __launch_bounds__(256) void bin_search_wave(const int32_t *nbins_dev, int n_cfg, int n_types,
-                                                        int max_nbrs, double rc, const double *pos,
-                                                        const int32_t *type, const CfgGeo *geo,
-                                                        const int32_t *atom_wrap, const int32_t *bin_start,
-                                                        const int32_t *bin_count, const int32_t *bin_atoms,
-                                                        int32_t *tcnt, double *rout, int32_t *jout, int32_t *shout,
-                                                        int32_t *flags) {
-    const int lane = threadIdx.x & 63;
+struct Window {   // LDS: one window of candidates
+    double x[PS_WIN], y[PS_WIN], z[PS_WIN];
+    int jq[PS_WIN];   // j if the bin offset has no periodic wrap, else ~j (never equal to an atom index)
+    int qt[PS_WIN];   // pack_q(q - w_j) | species << 30
+};
+
+// Candidates w0 .. w0 + PS_WIN - 1 of an offset group into LDS; every wave
+// of the block holds the same offset group A, and each stages its quarter.
+__device__ inline void stage_window(Window &W, const Around &A, int w0, int wave, int lane, const double (&H)[9],
+                                    const Staged &S) {
+    for (int e = wave * 64 + lane, e0 = wave * 64; e0 < PS_WIN && w0 + e0 < A.total; e += 256, e0 += 256) {
+        const int v = w0 + e;
+        int L = 0;   // last lane whose bins start at or before candidate v
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const int ex = __shfl(A.excl, L + step, 64);
+            if (ex <= v) L += step;
+        }
+        const int st = __shfl(A.start, L, 64), pe = __shfl(A.excl, L, 64), q = __shfl(A.qp, L, 64);
+        if (v < A.total && e < PS_WIN) {
+            const int64_t u = st + v - pe;
+            const int qx = field(q, 0), qy = field(q, 1), qz = field(q, 2);
+            W.x[e] = S.sx[3 * u] + qx * H[0] + qy * H[3] + qz * H[6];
+            W.y[e] = S.sx[3 * u + 1] + qx * H[1] + qy * H[4] + qz * H[7];
+            W.z[e] = S.sx[3 * u + 2] + qx * H[2] + qy * H[5] + qz * H[8];
+            const int nw = S.sw[u];
+            const int j = S.bin_atoms[u];
+            W.jq[e] = (qx == 0 && qy == 0 && qz == 0) ? j : ~j;
+            W.qt[e] = pack_q(qx + field(nw, 0), qy + field(nw, 1), qz + field(nw, 2)) | (S.st[u] << 30);
+        }
+    }
+}
+
+struct Centre {   // the atom whose neighborhood is built (wave-uniform)
+    int i, w0, w1, w2;
+    double y0, y1, y2;   // y_i
+};
+
+struct Flags {
+    bool overlap = false, wide = false;
+};
+
+// Tests the window's candidates against atom i: bit cc of the returned mask
+// is candidate 64 cc + lane; *tb gets its species (2 bits each).  0 < |r| <
+// R_cut is decided as sqrt(r.r) < R_cut, the square root only evaluated next
+// to the sphere, where comparing squares could differ.
+__device__ inline unsigned test_window(const Window &W, int n, const Centre &c, int lane, double rc, double rc2lo,
+                                       double rc2hi, unsigned &tb, Flags &fl) {
+    unsigned in = 0;
+    tb = 0;
+    for (int cc = 0; cc * 64 < n; ++cc) {
+        const int e = cc * 64 + lane;
+        if (e >= n) break;
+        const double r0 = W.x[e] - c.y0, r1 = W.y[e] - c.y1, r2 = W.z[e] - c.y2;
+        const double d2 = r0 * r0 + r1 * r1 + r2 * r2;
+        bool ok = d2 < rc2lo;
+        if (d2 >= rc2lo && d2 < rc2hi) ok = sqrt(d2) < rc;
+        ok = ok && W.jq[e] != c.i;   // the atom itself (same image)
+        if (ok) {
+            in |= 1u << cc;
+            tb |= ((unsigned)W.qt[e] >> 30) << (2 * cc);
+            if (d2 < 1e-12) fl.overlap = true;
+        }
+    }
+    return in;
+}
+
+// per-species counts of the accepted candidates (wave-uniform)
+__device__ inline void count_window(unsigned in, unsigned tb, int n, int n_types, int (&cnt)[MAX_TYPES]) {
+    for (int cc = 0; cc * 64 < n; ++cc) {
+        const bool a = (in >> cc) & 1u;
+        const int t = (tb >> (2 * cc)) & 3;
+#pragma unroll
+        for (int s = 0; s < MAX_TYPES; ++s)
+            if (s < n_types) cnt[s] += __popcll(__ballot(a && t == s));
+    }
+}
+
+// Places the accepted candidates: list offset base[t] + run[t] + rank among
+// this window's pairs of species t; kept if the rank is below cap[t] - run[t].
+// perm_e / perm_k receive (candidate, list offset) for the kept ones; returns
+// how many.  run[] advances by the window's counts.
+__device__ inline int place_window(unsigned in, unsigned tb, int n, int n_types, int lane, int (&run)[MAX_TYPES],
+                                   const int (&cap)[MAX_TYPES], const int (&base)[MAX_TYPES], short *perm_e,
+                                   int *perm_k) {
     const unsigned long long below = (1ull << lane) - 1ull;
-    const int64_t nbins = *nbins_dev;
-    bool overlap = false, wide = false, bad_type = false;
-    for (int64_t bin = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); bin < nbins; bin += (int64_t)gridDim.x * 4) {
+    int kept = 0;
+    for (int cc = 0; cc * 64 < n; ++cc) {
+        const bool a = (in >> cc) & 1u;
+        const int t = (tb >> (2 * cc)) & 3;
+#pragma unroll
+        for (int s = 0; s < MAX_TYPES; ++s) {
+            if (s >= n_types) continue;
+            const unsigned long long mk = __ballot(a && t == s);
+            const int k = run[s] + __popcll(mk & below);
+            const bool keep = a && t == s && k < cap[s];
+            const unsigned long long km = __ballot(keep);
+            if (keep) {
+                const int slot = kept + __popcll(km & below);
+                perm_e[slot] = (short)(cc * 64 + lane);
+                perm_k[slot] = base[s] + k;
+            }
+            kept += __popcll(km);
+            run[s] += __popcll(mk);
+        }
+    }
+    return kept;
+}
+
+// consecutive lanes write consecutive kept pairs
+__device__ inline void write_kept(const Window &W, const short *perm_e, const int *perm_k, int kept,
+                                  const Centre &c, int lane, int max_nbrs, double *rout, int32_t *jout,
+                                  int32_t *shout, Flags &fl) {
+    for (int a = lane; a < kept; a += 64) {
+        const int e = perm_e[a];
+        const int64_t slot = (int64_t)c.i * max_nbrs + perm_k[a];
+        const int qt = W.qt[e], jq = W.jq[e];
+        const int sh0 = field(qt, 0) + c.w0, sh1 = field(qt, 1) + c.w1, sh2 = field(qt, 2) + c.w2;
+        rout[3 * slot] = W.x[e] - c.y0;
+        rout[3 * slot + 1] = W.y[e] - c.y1;
+        rout[3 * slot + 2] = W.z[e] - c.y2;
+        jout[slot] = jq >= 0 ? jq : ~jq;
+        if (sh0 < -127 || sh0 > 127 || sh1 < -127 || sh1 > 127 || sh2 < -127 || sh2 > 127) fl.wide = true;
+        shout[slot] = (sh0 & 0xff) | ((sh1 & 0xff) << 8) | ((sh2 & 0xff) << 16);
+    }
+}
+
+// Per-species slots of one neighborhood: counts -> capacities (clamped to
+// max_nbrs in species order) and list offsets.
+__device__ inline void list_layout(const int (&cnt)[MAX_TYPES], int n_types, int max_nbrs, int (&cap)[MAX_TYPES],
+                                   int (&base)[MAX_TYPES], int &tot) {
+    int off = 0;
+    tot = 0;
+#pragma unroll
+    for (int t = 0; t < MAX_TYPES; ++t) {
+        cap[t] = 0;
+        base[t] = off;
+        if (t < n_types) {
+            tot += cnt[t];
+            const int room = max_nbrs - off;
+            cap[t] = cnt[t] < room ? cnt[t] : room;
+            off += cap[t];
+        }
+    }
+}
+
+__device__ inline int from_lane(int v, int k) { return __shfl(v, k, 64); }
+
+// WIDE = false: every bin whose candidates fit one window; the others are
+// appended to wide_list (count in flags[5]) for the WIDE = true launch.
+template <bool WIDE>
+__global__ __launch_bounds__(256) void pair_search(const int32_t *nbins_dev, int n_cfg, int n_types, int max_nbrs,
+                                                   double rc, const CfgGeo *geo, Staged S, const int32_t *bin_start,
+                                                   const int32_t *bin_count, int32_t *tcnt, double *rout,
+                                                   int32_t *jout, int32_t *shout, int32_t *flags,
+                                                   int32_t *wide_list) {
+    __shared__ Window W;
+    __shared__ short perm_e[4][PS_WIN];
+    __shared__ int perm_k[4][PS_WIN];
+    __shared__ int s_max[4], s_bits[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t nbins = WIDE ? flags[5] : *nbins_dev;
+    const double rc2lo = rc * rc * (1.0 - 1e-12), rc2hi = rc * rc * (1.0 + 1e-12);
+    Flags fl;
+    int max_tot = 0;
+    for (int64_t it = blockIdx.x; it < nbins; it += gridDim.x) {   // block-uniform
+        const int64_t bin = WIDE ? wide_list[it] : it;
         const int my_cnt = bin_count[bin];
-        if (my_cnt == 0) continue;   // uniform per wavefront
+        if (my_cnt == 0) continue;
         int lo = 0, hi = n_cfg - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) / 2;
@@ -449,171 +482,150 @@ __global__ __launch_bounds__(256) void bin_search_wave(const int32_t *nbins_dev,
         double H[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) H[k] = g.H[k];
-        const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
-        const int s0 = g.s[0], s1 = g.s[1], s2 = g.s[2];
-        const int p0 = g.pbc[0], p1 = g.pbc[1], p2 = g.pbc[2];
-        const long long boff = g.bin_off;
-        const int local = (int)(bin - boff);
-        const int bx = local % n0, by = (local / n0) % n1, bz = local / (n0 * n1);
-        const int ox = 2 * s0 + 1, oy = 2 * s1 + 1, oz = 2 * s2 + 1;
-        const int n_off = ox * oy * oz;
+        const int local = (int)(bin - g.bin_off);
+        const int bx = local % g.n[0], by = (local / g.n[0]) % g.n[1], bz = local / (g.n[0] * g.n[1]);
+        const int n_off = (2 * g.s[0] + 1) * (2 * g.s[1] + 1) * (2 * g.s[2] + 1);
         const int my_start = bin_start[bin];
-        for (int a0 = 0; a0 < my_cnt; a0 += 64) {
-            const int na = my_cnt - a0 < 64 ? my_cnt - a0 : 64;
-            // lane a holds atom a0 + a: index, wrap, w.H - x, and its counters
-            int ai = 0, aw0 = 0, aw1 = 0, aw2 = 0;
-            double ao0 = 0.0, ao1 = 0.0, ao2 = 0.0;
-            if (lane < na) {
-                ai = bin_atoms[my_start + a0 + lane];
-                aw0 = atom_wrap[3 * ai];
-                aw1 = atom_wrap[3 * ai + 1];
-                aw2 = atom_wrap[3 * ai + 2];
-                ao0 = aw0 * H[0] + aw1 * H[3] + aw2 * H[6] - pos[3 * ai];
-                ao1 = aw0 * H[1] + aw1 * H[4] + aw2 * H[7] - pos[3 * ai + 1];
-                ao2 = aw0 * H[2] + aw1 * H[5] + aw2 * H[8] - pos[3 * ai + 2];
+        const Around A0 = around_bin(g, bx, by, bz, lane, n_off, lane, bin_start, bin_count);
+        const bool one_window = n_off <= 64 && A0.total <= PS_WIN;
+        if (!WIDE && !one_window) {
+            if (threadIdx.x == 0) wide_list[atomicAdd(&flags[5], 1)] = (int32_t)bin;
+            continue;
+        }
+        if (one_window) {
+            __syncthreads();   // the previous bin's window is no longer read
+            stage_window(W, A0, 0, wave, lane, H, S);
+            __syncthreads();
+        }
+        for (int a_base = 0; a_base < my_cnt; a_base += 256) {   // block-uniform
+            // lane k of wave w holds atom a_base + w + 4 k of the bin
+            const int ak = a_base + wave + 4 * lane;
+            int hold_i = 0, hold_w = pack_q(0, 0, 0);
+            double hold_x = 0.0, hold_y = 0.0, hold_z = 0.0;
+            if (ak < my_cnt) {
+                const int64_t u = (int64_t)my_start + ak;
+                hold_i = S.bin_atoms[u];
+                hold_w = S.sw[u];
+                hold_x = S.sx[3 * u];
+                hold_y = S.sx[3 * u + 1];
+                hold_z = S.sx[3 * u + 2];
             }
-            int run[MAX_TYPES] = {0, 0, 0, 0}, cap[MAX_TYPES] = {0, 0, 0, 0}, base[MAX_TYPES] = {0, 0, 0, 0};
-            for (int pass = 0; pass < 2; ++pass) {
-                if (pass == 1 && lane < na) {
-                    int off = 0, tot = 0;
-                    for (int t = 0; t < n_types; ++t) {
-                        tot += run[t];
-                        const int room = max_nbrs - off;
-                        cap[t] = run[t] < room ? run[t] : room;
-                        base[t] = off;
-                        off += cap[t];
-                        run[t] = 0;
+            const int left = (my_cnt - a_base - wave + 3) / 4;
+            const int na = left < 0 ? 0 : (left < 64 ? left : 64);
+            auto centre = [&](int k) {
+                Centre c;
+                c.i = from_lane(hold_i, k);
+                const int nw = from_lane(hold_w, k);
+                c.w0 = -field(nw, 0);
+                c.w1 = -field(nw, 1);
+                c.w2 = -field(nw, 2);
+                c.y0 = __shfl(hold_x, k, 64);
+                c.y1 = __shfl(hold_y, k, 64);
+                c.y2 = __shfl(hold_z, k, 64);
+                return c;
+            };
+            if (!WIDE) {
+                for (int k = 0; k < na; ++k) {
+                    const Centre c = centre(k);
+                    unsigned tb;
+                    const unsigned in = test_window(W, A0.total, c, lane, rc, rc2lo, rc2hi, tb, fl);
+                    int cnt[MAX_TYPES] = {0, 0, 0, 0}, cap[MAX_TYPES], base[MAX_TYPES], run[MAX_TYPES] = {0, 0, 0, 0};
+                    int tot;
+                    count_window(in, tb, A0.total, n_types, cnt);
+                    list_layout(cnt, n_types, max_nbrs, cap, base, tot);
+                    const int kept = place_window(in, tb, A0.total, n_types, lane, run, cap, base, perm_e[wave],
+                                                  perm_k[wave]);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    write_kept(W, perm_e[wave], perm_k[wave], kept, c, lane, max_nbrs, rout, jout, shout, fl);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    max_tot = tot > max_tot ? tot : max_tot;
+                    if (lane < n_types) {
+                        int v = 0;
+#pragma unroll
+                        for (int t = 0; t < MAX_TYPES; ++t)
+                            if (t == lane) v = cap[t];
+                        tcnt[(int64_t)c.i * n_types + lane] = v;
                     }
-                    if (tot > max_nbrs) atomicOr(&flags[0], 1);
-                    atomicMax(&flags[1], tot);
                 }
-                for (int og = 0; og < n_off; og += 64) {
-                    const int o = og + lane;
-                    int start = 0, c = 0, qp = pack_q(0, 0, 0);
-                    if (o < n_off) {
-                        const int dx = o % ox - s0, dy = (o / ox) % oy - s1, dz = o / (ox * oy) - s2;
-                        int ux = bx + dx, uy = by + dy, uz = bz + dz, qx = 0, qy = 0, qz = 0;
-                        bool ok = true;
-                        if (p0) { qx = floordiv(ux, n0); ux -= qx * n0; } else ok = ok && ux >= 0 && ux < n0;
-                        if (p1) { qy = floordiv(uy, n1); uy -= qy * n1; } else ok = ok && uy >= 0 && uy < n1;
-                        if (p2) { qz = floordiv(uz, n2); uz -= qz * n2; } else ok = ok && uz >= 0 && uz < n2;
-                        if (ok) {
-                            const long long nb = boff + ((long long)uz * n1 + uy) * n0 + ux;
-                            start = bin_start[nb];
-                            c = bin_count[nb];
-                            qp = pack_q(qx, qy, qz);
-                        }
+            } else {
+                // per held atom (lane k): counts, then capacities / offsets / placed so far
+                int hc[MAX_TYPES] = {0, 0, 0, 0}, hcap[MAX_TYPES] = {0, 0, 0, 0}, hbase[MAX_TYPES] = {0, 0, 0, 0},
+                    hrun[MAX_TYPES] = {0, 0, 0, 0};
+                for (int pass = 0; pass < 2; ++pass) {
+                    if (pass == 1) {
+                        int tot;
+                        list_layout(hc, n_types, max_nbrs, hcap, hbase, tot);
+                        if (lane < na) max_tot = tot > max_tot ? tot : max_tot;
                     }
-                    int inc = c;
-#pragma unroll
-                    for (int d = 1; d < 64; d <<= 1) {
-                        const int t = __shfl_up(inc, d, 64);
-                        if (lane >= d) inc += t;
-                    }
-                    const int excl = inc - c;
-                    const int total = __shfl(inc, 63, 64);
-                    for (int w0 = 0; w0 < total; w0 += 64 * SW_C) {
-                        double cx[SW_C], cy[SW_C], cz[SW_C];
-                        int cj[SW_C], cs[SW_C], ct[SW_C];
-#pragma unroll
-                        for (int cc = 0; cc < SW_C; ++cc) {
-                            const int v = w0 + cc * 64 + lane;
-                            int L = 0;
-#pragma unroll
-                            for (int step = 32; step >= 1; step >>= 1) {
-                                const int e = __shfl(excl, L + step, 64);
-                                if (e <= v) L += step;
-                            }
-                            const int st = __shfl(start, L, 64), pe = __shfl(excl, L, 64), q = __shfl(qp, L, 64);
-                            cj[cc] = -1;
-                            cx[cc] = cy[cc] = cz[cc] = 0.0;
-                            cs[cc] = pack_q(0, 0, 0);
-                            ct[cc] = -1;
-                            if (v < total) {
-                                const int j = bin_atoms[st + v - pe];
-                                const int sx = ((q & 1023) - 512) - atom_wrap[3 * j];
-                                const int sy = (((q >> 10) & 1023) - 512) - atom_wrap[3 * j + 1];
-                                const int sz = (((q >> 20) & 1023) - 512) - atom_wrap[3 * j + 2];
-                                cx[cc] = pos[3 * j] + sx * H[0] + sy * H[3] + sz * H[6];
-                                cy[cc] = pos[3 * j + 1] + sx * H[1] + sy * H[4] + sz * H[7];
-                                cz[cc] = pos[3 * j + 2] + sx * H[2] + sy * H[5] + sz * H[8];
-                                cj[cc] = j;
-                                cs[cc] = pack_q(sx, sy, sz);
-                                const int t = type[j];
-                                ct[cc] = (t < 0 || t >= n_types) ? -2 : t;
-                            }
-                        }
-                        for (int a = 0; a < na; ++a) {
-                            const int i = __shfl(ai, a, 64);
-                            const int wi0 = __shfl(aw0, a, 64), wi1 = __shfl(aw1, a, 64), wi2 = __shfl(aw2, a, 64);
-                            const double bx0 = __shfl(ao0, a, 64), bx1 = __shfl(ao1, a, 64), bx2 = __shfl(ao2, a, 64);
-                            int cnt_t[MAX_TYPES], cap_t[MAX_TYPES], base_t[MAX_TYPES];
-#pragma unroll
-                            for (int t = 0; t < MAX_TYPES; ++t) {
-                                cnt_t[t] = __shfl(run[t], a, 64);
-                                cap_t[t] = __shfl(cap[t], a, 64);
-                                base_t[t] = __shfl(base[t], a, 64);
-                            }
-#pragma unroll
-                            for (int cc = 0; cc < SW_C; ++cc) {
-                                if (w0 + cc * 64 >= total) break;   // uniform
-                                bool ok = false;
-                                int t = -1, sh0 = 0, sh1 = 0, sh2 = 0;
-                                double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-                                if (cj[cc] >= 0) {
-                                    const int q = cs[cc];
-                                    sh0 = ((q & 1023) - 512) + wi0;
-                                    sh1 = (((q >> 10) & 1023) - 512) + wi1;
-                                    sh2 = (((q >> 20) & 1023) - 512) + wi2;
-                                    if (!(cj[cc] == i && sh0 == 0 && sh1 == 0 && sh2 == 0)) {
-                                        r0 = cx[cc] + bx0;
-                                        r1 = cy[cc] + bx1;
-                                        r2 = cz[cc] + bx2;
-                                        const double d = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
-                                        if (d < rc) {
-                                            t = ct[cc];
-                                            if (t == -2) {
-                                                bad_type = true;
-                                            } else {
-                                                ok = true;
-                                                if (d < 1e-6) overlap = true;
-                                            }
-                                        }
-                                    }
+                    for (int og = 0; og < n_off; og += 64) {
+                        const Around A = around_bin(g, bx, by, bz, og + lane, n_off, lane, bin_start, bin_count);
+                        for (int w0 = 0; w0 < A.total; w0 += PS_WIN) {
+                            const int n = A.total - w0 < PS_WIN ? A.total - w0 : PS_WIN;
+                            __syncthreads();
+                            stage_window(W, A, w0, wave, lane, H, S);
+                            __syncthreads();
+                            for (int k = 0; k < na; ++k) {
+                                const Centre c = centre(k);
+                                unsigned tb;
+                                const unsigned in = test_window(W, n, c, lane, rc, rc2lo, rc2hi, tb, fl);
+                                int cnt[MAX_TYPES] = {0, 0, 0, 0};
+                                count_window(in, tb, n, n_types, cnt);
+                                if (pass == 0) {
+                                    if (lane == k)
+                                        for (int t = 0; t < MAX_TYPES; ++t) hc[t] += cnt[t];
+                                    continue;
                                 }
-                                for (int tt = 0; tt < n_types; ++tt) {
-                                    const bool mine = ok && t == tt;
-                                    const unsigned long long mk = __ballot(mine);
-                                    if (pass == 1 && mine) {
-                                        const int slot_in = cnt_t[tt] + __popcll(mk & below);
-                                        if (slot_in < cap_t[tt]) {
-                                            const int64_t slot = (int64_t)i * max_nbrs + base_t[tt] + slot_in;
-                                            rout[3 * slot] = r0;
-                                            rout[3 * slot + 1] = r1;
-                                            rout[3 * slot + 2] = r2;
-                                            jout[slot] = cj[cc];
-                                            if (sh0 < -127 || sh0 > 127 || sh1 < -127 || sh1 > 127 || sh2 < -127 ||
-                                                sh2 > 127)
-                                                wide = true;
-                                            shout[slot] = (sh0 & 0xff) | ((sh1 & 0xff) << 8) | ((sh2 & 0xff) << 16);
-                                        }
-                                    }
-                                    cnt_t[tt] += __popcll(mk);
+                                int run[MAX_TYPES], cap[MAX_TYPES], base[MAX_TYPES];
+#pragma unroll
+                                for (int t = 0; t < MAX_TYPES; ++t) {
+                                    run[t] = from_lane(hrun[t], k);
+                                    cap[t] = from_lane(hcap[t], k);
+                                    base[t] = from_lane(hbase[t], k);
                                 }
+                                const int kept = place_window(in, tb, n, n_types, lane, run, cap, base,
+                                                              perm_e[wave], perm_k[wave]);
+                                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                                __builtin_amdgcn_wave_barrier();
+                                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                                write_kept(W, perm_e[wave], perm_k[wave], kept, c, lane, max_nbrs, rout, jout, shout,
+                                           fl);
+                                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                                __builtin_amdgcn_wave_barrier();
+                                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                                if (lane == k)
+                                    for (int t = 0; t < MAX_TYPES; ++t) hrun[t] = run[t];
                             }
-                            if (lane == a)
-                                for (int t = 0; t < MAX_TYPES; ++t) run[t] = cnt_t[t];
                         }
                     }
                 }
+                if (lane < na)
+                    for (int t = 0; t < n_types; ++t) tcnt[(int64_t)hold_i * n_types + t] = hcap[t];
             }
-            if (lane < na)
-                for (int t = 0; t < n_types; ++t) tcnt[(int64_t)ai * n_types + t] = cap[t];
         }
     }
-    if (overlap) atomicOr(&flags[2], 1);
-    if (wide) atomicOr(&flags[3], 2);
-    if (bad_type) atomicOr(&flags[3], 8);
+    // Status words: one atomic per block (same-address atomics from every
+    // atom would serialise in L2), and only when the stored value changes.
+    const int bits = (__ballot(fl.overlap) ? 1 : 0) | (__ballot(fl.wide) ? 2 : 0);
+    int wmax = max_tot;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) wmax = max(wmax, __shfl_xor(wmax, d, 64));
+    if (lane == 0) {
+        s_max[wave] = wmax;
+        s_bits[wave] = bits;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int mt = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
+        const int b = s_bits[0] | s_bits[1] | s_bits[2] | s_bits[3];
+        if (mt > max_nbrs) atomicOr(&flags[0], 1);
+        if (mt > __hip_atomic_load(&flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&flags[1], mt);
+        if (b & 1) atomicOr(&flags[2], 1);
+        if (b & 2) atomicOr(&flags[3], 2);
+    }
 }
 
 __device__ inline int sx8(int v) { return (int)(signed char)(v & 0xff); }
@@ -679,6 +691,9 @@ void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_
     const int64_t nscan = (bins + SCAN_B - 1) / SCAN_B;
     nb->work_sums.ensure(sizeof(int32_t) * (nscan > 0 ? nscan : 1));
     nb->bin_atoms.ensure(sizeof(int32_t) * (n > 0 ? n : 1));
+    nb->stage_x.ensure(sizeof(double) * 3 * (n > 0 ? n : 1));
+    nb->stage_w.ensure(sizeof(int32_t) * (n > 0 ? n : 1));
+    nb->stage_t.ensure(sizeof(int32_t) * (n > 0 ? n : 1));
     nb->flags.ensure(sizeof(int32_t) * 8);
     nb->bins_cap = bins;
     launch_zero(nb->flags.ptr, sizeof(int32_t) * 8, st);
@@ -700,13 +715,22 @@ void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_
                        nb->work_sums.as<int32_t>(), flags + 4, nb->bin_cursor.as<int32_t>());
     hipLaunchKernelGGL(fill_bins, ga, dim3(TB), 0, st, n, nb->atom_bin.as<int32_t>(), nb->bin_cursor.as<int32_t>(),
                        nb->bin_atoms.as<int32_t>());
+    Stage sg{s->pos, s->type, nb->atom_cfg.as<int32_t>(), nb->atom_wrap.as<int32_t>(), geo, nt,
+             nb->stage_x.as<double>(), nb->stage_w.as<int32_t>(), nb->stage_t.as<int32_t>()};
     const unsigned gbins = (unsigned)std::min<int64_t>((bins + 3) / 4, 2048);
-    hipLaunchKernelGGL(sort_bins, dim3(gbins), dim3(256), 0, st, flags,
-                       nb->bin_start.as<int32_t>(), nb->bin_count.as<int32_t>(), nb->bin_atoms.as<int32_t>());
-    hipLaunchKernelGGL(bin_search, dim3((unsigned)std::min<int64_t>(bins, 2048)), dim3(BS_T), 0, st, flags + 4, s->n_cfg, nt, max_nbrs, m->r_cut,
-                       s->pos, s->type, geo, nb->atom_wrap.as<int32_t>(), nb->bin_start.as<int32_t>(),
-                       nb->bin_count.as<int32_t>(), nb->bin_atoms.as<int32_t>(), nb->tcnt.as<int32_t>(),
-                       nb->r.as<double>(), nb->j.as<int32_t>(), nb->shift.as<int32_t>(), flags);
+    hipLaunchKernelGGL(sort_bins, dim3(gbins), dim3(256), 0, st, flags, nb->bin_start.as<int32_t>(),
+                       nb->bin_count.as<int32_t>(), nb->bin_atoms.as<int32_t>(), sg);
+    // bin_cursor is free after fill_bins: it holds the list of bins for the WIDE launch
+    const Staged staged{nb->stage_x.as<double>(), nb->stage_w.as<int32_t>(), nb->stage_t.as<int32_t>(),
+                        nb->bin_atoms.as<int32_t>()};
+    hipLaunchKernelGGL(pair_search<false>, dim3((unsigned)std::min<int64_t>(bins, 8192)), dim3(256), 0, st,
+                       flags + 4, s->n_cfg, nt, max_nbrs, m->r_cut, geo, staged, nb->bin_start.as<int32_t>(),
+                       nb->bin_count.as<int32_t>(), nb->tcnt.as<int32_t>(), nb->r.as<double>(),
+                       nb->j.as<int32_t>(), nb->shift.as<int32_t>(), flags, nb->bin_cursor.as<int32_t>());
+    hipLaunchKernelGGL(pair_search<true>, dim3((unsigned)std::min<int64_t>(bins, 2048)), dim3(256), 0, st,
+                       flags + 4, s->n_cfg, nt, max_nbrs, m->r_cut, geo, staged, nb->bin_start.as<int32_t>(),
+                       nb->bin_count.as<int32_t>(), nb->tcnt.as<int32_t>(), nb->r.as<double>(),
+                       nb->j.as<int32_t>(), nb->shift.as<int32_t>(), flags, nb->bin_cursor.as<int32_t>());
     hipLaunchKernelGGL(reverse_pairs, dim3((unsigned)((P + TB - 1) / TB)), dim3(TB), 0, st, n, nt, max_nbrs, s->type,
                        nb->tcnt.as<int32_t>(), nb->j.as<int32_t>(), nb->shift.as<int32_t>(), nb->rev.as<int32_t>(),
                        flags);
