@@ -81,7 +81,8 @@ struct mtp_nbrs {
     double r_cut = 0;
     mtp::DevBuf r;        // [N*maxn*3] FP64 r_ij
     mtp::DevBuf j;        // [N*maxn] int32
-    mtp::DevBuf shift;    // [N*maxn] int32 packed (3 x int8, x in the low byte)
+    mtp::DevBuf shift;    // [N*maxn] int32 packed (3 x int8, x in the low byte; top byte: opposite bin offset)
+    mtp::DevBuf pre;      // [N*n_types*64] uint16 list position where each bin offset's run starts
     mtp::DevBuf rev;      // [N*maxn] int32 flat index of (j, i, -n)
     mtp::DevBuf tcnt;     // [N*n_types] int32 neighbors per species
     mtp::DevBuf atom_cfg; // [N] int32

@@ -250,10 +250,11 @@ __device__ inline int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b
 // One block of four wavefronts per bin.  The candidates of the bin (atoms of
 // the surrounding bins, every periodic image that can be in range) are
 // numbered by a wave-wide prefix sum over the bin offsets and staged in LDS,
-// a window of PS_WIN at a time, each as its image position y_j + q.H
-// (y_j = x_j - w_j.H: atom j wrapped into the cell, q: periodic wrap of the
-// bin offset).  For an atom i of the bin r_ij = image - y_i and the pair's
-// shift is q - w_j + w_i.  Wave w builds the neighborhoods of the bin's atoms
+// a window of PS_WIN at a time, each as y_j = x_j - w_j.H (atom j wrapped
+// into the cell) and its bin offset, whose periodic wrap q gives the lattice
+// vector q.H.  For an atom i of the bin r_ij = (y_j - y_i) + q.H, which is
+// bitwise -r_ji (the opposite pair has offset -d and wrap -q), so the lists
+// are exactly symmetric; the pair's shift is q - w_j + w_i.  Wave w builds the neighborhoods of the bin's atoms
 // w, w + 4, ...: lanes test candidates 64 at a time, ballots per neighbor
 // species give every accepted pair its place in the list (grouped by
 // species, candidate order inside a group, clamped to max_nbrs), and the
@@ -308,12 +309,19 @@ struct Window {   // LDS: one window of candidates
     double x[PS_WIN], y[PS_WIN], z[PS_WIN];
     int jq[PS_WIN];   // j if the bin offset has no periodic wrap, else ~j (never equal to an atom index)
     int qt[PS_WIN];   // pack_q(q - w_j) | species << 30
+    unsigned char lo[PS_WIN];   // bin offset (lane of the offset group)
+    double qh[64][3];           // q.H per bin offset of the group
 };
 
 // Candidates w0 .. w0 + PS_WIN - 1 of an offset group into LDS; every wave
 // of the block holds the same offset group A, and each stages its quarter.
 __device__ inline void stage_window(Window &W, const Around &A, int w0, int wave, int lane, const double (&H)[9],
                                     const Staged &S) {
+    if (wave == 0) {
+        const int qx = field(A.qp, 0), qy = field(A.qp, 1), qz = field(A.qp, 2);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) W.qh[lane][k] = qx * H[k] + qy * H[3 + k] + qz * H[6 + k];
+    }
     for (int e = wave * 64 + lane, e0 = wave * 64; e0 < PS_WIN && w0 + e0 < A.total; e += 256, e0 += 256) {
         const int v = w0 + e;
         int L = 0;   // last lane whose bins start at or before candidate v
@@ -326,13 +334,14 @@ __device__ inline void stage_window(Window &W, const Around &A, int w0, int wave
         if (v < A.total && e < PS_WIN) {
             const int64_t u = st + v - pe;
             const int qx = field(q, 0), qy = field(q, 1), qz = field(q, 2);
-            W.x[e] = S.sx[3 * u] + qx * H[0] + qy * H[3] + qz * H[6];
-            W.y[e] = S.sx[3 * u + 1] + qx * H[1] + qy * H[4] + qz * H[7];
-            W.z[e] = S.sx[3 * u + 2] + qx * H[2] + qy * H[5] + qz * H[8];
+            W.x[e] = S.sx[3 * u];
+            W.y[e] = S.sx[3 * u + 1];
+            W.z[e] = S.sx[3 * u + 2];
             const int nw = S.sw[u];
             const int j = S.bin_atoms[u];
             W.jq[e] = (qx == 0 && qy == 0 && qz == 0) ? j : ~j;
             W.qt[e] = pack_q(qx + field(nw, 0), qy + field(nw, 1), qz + field(nw, 2)) | (S.st[u] << 30);
+            W.lo[e] = (unsigned char)L;
         }
     }
 }
@@ -357,7 +366,9 @@ __device__ inline unsigned test_window(const Window &W, int n, const Centre &c, 
     for (int cc = 0; cc * 64 < n; ++cc) {
         const int e = cc * 64 + lane;
         if (e >= n) break;
-        const double r0 = W.x[e] - c.y0, r1 = W.y[e] - c.y1, r2 = W.z[e] - c.y2;
+        const int o = W.lo[e];
+        const double r0 = (W.x[e] - c.y0) + W.qh[o][0], r1 = (W.y[e] - c.y1) + W.qh[o][1],
+                     r2 = (W.z[e] - c.y2) + W.qh[o][2];
         const double d2 = r0 * r0 + r1 * r1 + r2 * r2;
         bool ok = d2 < rc2lo;
         if (d2 >= rc2lo && d2 < rc2hi) ok = sqrt(d2) < rc;
@@ -386,10 +397,15 @@ __device__ inline void count_window(unsigned in, unsigned tb, int n, int n_types
 // this window's pairs of species t; kept if the rank is below cap[t] - run[t].
 // perm_e / perm_k receive (candidate, list offset) for the kept ones; returns
 // how many.  run[] advances by the window's counts.
+template <bool PRE>
 __device__ inline int place_window(unsigned in, unsigned tb, int n, int n_types, int lane, int (&run)[MAX_TYPES],
                                    const int (&cap)[MAX_TYPES], const int (&base)[MAX_TYPES], short *perm_e,
-                                   int *perm_k) {
+                                   int *perm_k, int first_o, int (&pre)[MAX_TYPES]) {
+    // PRE: lane o also counts, per species, the accepted candidates before
+    // candidate first_o (the first one of bin offset o)
     const unsigned long long below = (1ull << lane) - 1ull;
+    const int cc_o = first_o >> 6;
+    const unsigned long long low_o = (1ull << (first_o & 63)) - 1ull;
     int kept = 0;
     for (int cc = 0; cc * 64 < n; ++cc) {
         const bool a = (in >> cc) & 1u;
@@ -408,26 +424,31 @@ __device__ inline int place_window(unsigned in, unsigned tb, int n, int n_types,
             }
             kept += __popcll(km);
             run[s] += __popcll(mk);
+            if (PRE) pre[s] += cc < cc_o ? __popcll(mk) : (cc == cc_o ? __popcll(mk & low_o) : 0);
         }
     }
     return kept;
 }
 
 // consecutive lanes write consecutive kept pairs
+// n_off_rec > 0: record the opposite bin offset n_off_rec - 1 - o in the
+// shift word's top byte (0xff: none)
 __device__ inline void write_kept(const Window &W, const short *perm_e, const int *perm_k, int kept,
-                                  const Centre &c, int lane, int max_nbrs, double *rout, int32_t *jout,
-                                  int32_t *shout, Flags &fl) {
+                                  const Centre &c, int lane, int max_nbrs, int n_off_rec, double *rout,
+                                  int32_t *jout, int32_t *shout, Flags &fl) {
     for (int a = lane; a < kept; a += 64) {
         const int e = perm_e[a];
         const int64_t slot = (int64_t)c.i * max_nbrs + perm_k[a];
         const int qt = W.qt[e], jq = W.jq[e];
         const int sh0 = field(qt, 0) + c.w0, sh1 = field(qt, 1) + c.w1, sh2 = field(qt, 2) + c.w2;
-        rout[3 * slot] = W.x[e] - c.y0;
-        rout[3 * slot + 1] = W.y[e] - c.y1;
-        rout[3 * slot + 2] = W.z[e] - c.y2;
+        const int o = W.lo[e];
+        rout[3 * slot] = (W.x[e] - c.y0) + W.qh[o][0];
+        rout[3 * slot + 1] = (W.y[e] - c.y1) + W.qh[o][1];
+        rout[3 * slot + 2] = (W.z[e] - c.y2) + W.qh[o][2];
+        const int orev = n_off_rec > 0 ? n_off_rec - 1 - o : 0xff;
         jout[slot] = jq >= 0 ? jq : ~jq;
         if (sh0 < -127 || sh0 > 127 || sh1 < -127 || sh1 > 127 || sh2 < -127 || sh2 > 127) fl.wide = true;
-        shout[slot] = (sh0 & 0xff) | ((sh1 & 0xff) << 8) | ((sh2 & 0xff) << 16);
+        shout[slot] = (sh0 & 0xff) | ((sh1 & 0xff) << 8) | ((sh2 & 0xff) << 16) | (orev << 24);
     }
 }
 
@@ -459,7 +480,7 @@ __global__ __launch_bounds__(256) void pair_search(const int32_t *nbins_dev, int
                                                    double rc, const CfgGeo *geo, Staged S, const int32_t *bin_start,
                                                    const int32_t *bin_count, int32_t *tcnt, double *rout,
                                                    int32_t *jout, int32_t *shout, int32_t *flags,
-                                                   int32_t *wide_list) {
+                                                   int32_t *wide_list, uint16_t *pre_out) {
     __shared__ Window W;
     __shared__ short perm_e[4][PS_WIN];
     __shared__ int perm_k[4][PS_WIN];
@@ -533,12 +554,15 @@ __global__ __launch_bounds__(256) void pair_search(const int32_t *nbins_dev, int
                     int tot;
                     count_window(in, tb, A0.total, n_types, cnt);
                     list_layout(cnt, n_types, max_nbrs, cap, base, tot);
-                    const int kept = place_window(in, tb, A0.total, n_types, lane, run, cap, base, perm_e[wave],
-                                                  perm_k[wave]);
+                    int pre[MAX_TYPES] = {0, 0, 0, 0};
+                    const int kept = place_window<true>(in, tb, A0.total, n_types, lane, run, cap, base,
+                                                        perm_e[wave], perm_k[wave], A0.excl, pre);
+                    for (int t = 0; t < n_types; ++t)
+                        pre_out[((int64_t)c.i * n_types + t) * 64 + lane] = (uint16_t)pre[t];
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    write_kept(W, perm_e[wave], perm_k[wave], kept, c, lane, max_nbrs, rout, jout, shout, fl);
+                    write_kept(W, perm_e[wave], perm_k[wave], kept, c, lane, max_nbrs, n_off, rout, jout, shout, fl);
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -586,13 +610,14 @@ __global__ __launch_bounds__(256) void pair_search(const int32_t *nbins_dev, int
                                     cap[t] = from_lane(hcap[t], k);
                                     base[t] = from_lane(hbase[t], k);
                                 }
-                                const int kept = place_window(in, tb, n, n_types, lane, run, cap, base,
-                                                              perm_e[wave], perm_k[wave]);
+                                int pre[MAX_TYPES];
+                                const int kept = place_window<false>(in, tb, n, n_types, lane, run, cap, base,
+                                                                     perm_e[wave], perm_k[wave], 0, pre);
                                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                                 __builtin_amdgcn_wave_barrier();
                                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                                write_kept(W, perm_e[wave], perm_k[wave], kept, c, lane, max_nbrs, rout, jout, shout,
-                                           fl);
+                                write_kept(W, perm_e[wave], perm_k[wave], kept, c, lane, max_nbrs, 0, rout, jout,
+                                           shout, fl);
                                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                                 __builtin_amdgcn_wave_barrier();
                                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -604,6 +629,9 @@ __global__ __launch_bounds__(256) void pair_search(const int32_t *nbins_dev, int
                 }
                 if (lane < na)
                     for (int t = 0; t < n_types; ++t) tcnt[(int64_t)hold_i * n_types + t] = hcap[t];
+                for (int k = 0; k < na; ++k)   // no offset table for these atoms
+                    for (int t = 0; t < n_types; ++t)
+                        pre_out[((int64_t)from_lane(hold_i, k) * n_types + t) * 64 + lane] = (uint16_t)0xffff;
             }
         }
     }
@@ -630,9 +658,14 @@ __global__ __launch_bounds__(256) void pair_search(const int32_t *nbins_dev, int
 
 __device__ inline int sx8(int v) { return (int)(signed char)(v & 0xff); }
 
-// one thread per list slot: find the slot of (j, i, -n) in j's list
+// One thread per list slot: find the slot of (j, i, -n) in j's list.  The
+// top byte of a slot's shift word is the index of the opposite bin offset
+// (from j's bin to i's); j's offset table gives where that offset's run
+// starts in j's species-z_i group, so only the run (ascending atom index) is
+// scanned.  Without a table entry the whole group is scanned.
 __global__ void reverse_pairs(int64_t n, int n_types, int max_nbrs, const int32_t *type, const int32_t *tcnt,
-                              const int32_t *jl, const int32_t *sh, int32_t *rev, int32_t *flags) {
+                              const int32_t *jl, const int32_t *sh, const uint16_t *pre, int32_t *rev,
+                              int32_t *flags) {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= n * max_nbrs) return;
     const int64_t i = slot / max_nbrs;
@@ -645,13 +678,26 @@ __global__ void reverse_pairs(int64_t n, int n_types, int max_nbrs, const int32_
     const int j = jl[slot];
     const int s = sh[slot];
     const int want = ((-sx8(s)) & 0xff) | ((-sx8(s >> 8)) & 0xff) << 8 | ((-sx8(s >> 16)) & 0xff) << 16;
+    const int orev = (s >> 24) & 0xff;
     int start = 0;
     for (int t = 0; t < zi; ++t) start += tcnt[(int64_t)j * n_types + t];
     const int cnt = tcnt[(int64_t)j * n_types + zi];
+    int lo = 0, hi = cnt;
+    if (orev != 0xff) {
+        const uint16_t *pj = pre + ((int64_t)j * n_types + zi) * 64;
+        const int a = pj[orev];
+        if (a != 0xffff) {
+            lo = a < cnt ? a : cnt;
+            if (orev + 1 < 64) {
+                const int b = pj[orev + 1];
+                hi = b < cnt ? b : cnt;
+            }
+        }
+    }
     int found = -1;
-    for (int q = start; q < start + cnt; ++q) {
+    for (int q = start + lo; q < start + hi; ++q) {
         const int64_t s2 = (int64_t)j * max_nbrs + q;
-        if (jl[s2] == (int)i && sh[s2] == want) {
+        if (jl[s2] == (int)i && (sh[s2] & 0xffffff) == want) {
             found = (int)s2;
             break;
         }
@@ -694,6 +740,7 @@ void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_
     nb->stage_x.ensure(sizeof(double) * 3 * (n > 0 ? n : 1));
     nb->stage_w.ensure(sizeof(int32_t) * (n > 0 ? n : 1));
     nb->stage_t.ensure(sizeof(int32_t) * (n > 0 ? n : 1));
+    nb->pre.ensure(sizeof(uint16_t) * 64 * (n * nt > 0 ? n * nt : 1));
     nb->flags.ensure(sizeof(int32_t) * 8);
     nb->bins_cap = bins;
     launch_zero(nb->flags.ptr, sizeof(int32_t) * 8, st);
@@ -726,14 +773,16 @@ void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_
     hipLaunchKernelGGL(pair_search<false>, dim3((unsigned)std::min<int64_t>(bins, 8192)), dim3(256), 0, st,
                        flags + 4, s->n_cfg, nt, max_nbrs, m->r_cut, geo, staged, nb->bin_start.as<int32_t>(),
                        nb->bin_count.as<int32_t>(), nb->tcnt.as<int32_t>(), nb->r.as<double>(),
-                       nb->j.as<int32_t>(), nb->shift.as<int32_t>(), flags, nb->bin_cursor.as<int32_t>());
+                       nb->j.as<int32_t>(), nb->shift.as<int32_t>(), flags, nb->bin_cursor.as<int32_t>(),
+                       nb->pre.as<uint16_t>());
     hipLaunchKernelGGL(pair_search<true>, dim3((unsigned)std::min<int64_t>(bins, 2048)), dim3(256), 0, st,
                        flags + 4, s->n_cfg, nt, max_nbrs, m->r_cut, geo, staged, nb->bin_start.as<int32_t>(),
                        nb->bin_count.as<int32_t>(), nb->tcnt.as<int32_t>(), nb->r.as<double>(),
-                       nb->j.as<int32_t>(), nb->shift.as<int32_t>(), flags, nb->bin_cursor.as<int32_t>());
+                       nb->j.as<int32_t>(), nb->shift.as<int32_t>(), flags, nb->bin_cursor.as<int32_t>(),
+                       nb->pre.as<uint16_t>());
     hipLaunchKernelGGL(reverse_pairs, dim3((unsigned)((P + TB - 1) / TB)), dim3(TB), 0, st, n, nt, max_nbrs, s->type,
-                       nb->tcnt.as<int32_t>(), nb->j.as<int32_t>(), nb->shift.as<int32_t>(), nb->rev.as<int32_t>(),
-                       flags);
+                       nb->tcnt.as<int32_t>(), nb->j.as<int32_t>(), nb->shift.as<int32_t>(), nb->pre.as<uint16_t>(),
+                       nb->rev.as<int32_t>(), flags);
     MTP_HIP(hipGetLastError());
 }
 
