@@ -7,9 +7,9 @@
 // the BF16 rounding of what is left), and C = sum_{s+t < NS} b_s A_t on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation.
 //
-// A block of 256 threads owns 64 rows of C; each wavefront 16 rows.  The
-// block walks the columns in tiles of 64 and keeps a running max / argmax
-// per row, so C is never written.  A^-1 (<= m^2 x 8 B) stays L2-resident.
+// A block of 512 threads owns 64 rows of C; each wavefront 16 rows and half
+// of each pass of 224 columns.  The block keeps a running max / argmax per
+// row, so C is never written.  A^-1 (<= m^2 x 8 B) stays L2-resident.
 //
 // Also here: A^-1 by Gauss-Jordan elimination (FP64, partial pivoting) and
 // the MaxVol swap loop with Sherman-Morrison updates (FP64 only).
@@ -34,10 +34,95 @@ __device__ inline void better(double v, int c, double &bv, int &bc) {
 // Result layouts of the two MFMAs (16x16 tile, lane l, register r):
 //   f64 16x16x4:       row (l/16) + 4 r, column l % 16
 //   f32 16x16x32 bf16: row 4 (l/16) + r, column l % 16
-template <bool F64LAYOUT>
-__device__ inline void finish_rows(double (&best)[4], int (&bidx)[4], int64_t row0, int lane, int64_t n,
-                                   double *gamma, int32_t *argmax) {
-    // the row of (lane, r) is shared by the 16 lanes with equal lane/16
+
+// FP64: a block of eight wavefronts owns 64 rows; wave w takes rows
+// 16 (w % 4) .. + 16 and one half (w / 4) of each pass of 224 columns (7
+// MFMA column blocks, accumulators in registers).  k runs in chunks of 16,
+// staged through two LDS buffers: while the MFMAs consume one chunk, the
+// next one is in flight from global memory into registers, then stored to
+// the other buffer -- one barrier per chunk.  Two wavefronts per SIMD keep
+// the matrix pipe busy across the barrier.  The two column halves of a row
+// meet in LDS at the end.
+constexpr int GF_ROWS = 64, GF_KC = 16, GF_HALF = 7, GF_CT = 2 * GF_HALF * 16;
+__global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow, int ldb, int64_t n,
+                                                 const double *__restrict__ Ainv, int m, double *gamma,
+                                                 int32_t *argmax) {
+    __shared__ double sA[2][GF_ROWS][GF_KC + 1];
+    __shared__ double sB[2][GF_KC][GF_CT];
+    __shared__ double s_best[2][GF_ROWS];
+    __shared__ int s_idx[2][GF_ROWS];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int rg = wave & 3, half = wave >> 2;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int64_t row0 = (int64_t)blockIdx.x * GF_ROWS;
+    const int nchunk = (m + GF_KC - 1) / GF_KC;
+    double best[4] = {-1.0, -1.0, -1.0, -1.0};
+    int bidx[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
+    constexpr int RA = GF_ROWS * GF_KC / 512, RB = GF_KC * GF_CT / 512;
+    for (int ct0 = 0; ct0 < m; ct0 += GF_CT) {
+        const int ncb = min(GF_CT, m - ct0 + 15) / 16;   // column blocks holding real columns
+        const int cb0 = half * GF_HALF;
+        const int my_cb = max(0, min(GF_HALF, ncb - cb0));   // wave-uniform
+        doublex4 acc[GF_HALF];
+#pragma unroll
+        for (int c = 0; c < GF_HALF; ++c) acc[c] = doublex4{0.0, 0.0, 0.0, 0.0};
+        double ra[RA], rb[RB];
+        auto fetch = [&](int k0) {
+#pragma unroll
+            for (int q = 0; q < RA; ++q) {
+                const int e = tid + 512 * q;
+                const int r = e / GF_KC, k = e % GF_KC;
+                const int64_t row = row0 + r;
+                ra[q] = (row < n && k0 + k < m) ? brow[row * ldb + k0 + k] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                const int e = tid + 512 * q;
+                const int k = e / GF_CT, c = e % GF_CT;
+                rb[q] = (k0 + k < m && ct0 + c < m) ? Ainv[(int64_t)(k0 + k) * m + ct0 + c] : 0.0;
+            }
+        };
+        auto store = [&](int buf) {
+#pragma unroll
+            for (int q = 0; q < RA; ++q) {
+                const int e = tid + 512 * q;
+                sA[buf][e / GF_KC][e % GF_KC] = ra[q];
+            }
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                const int e = tid + 512 * q;
+                sB[buf][e / GF_CT][e % GF_CT] = rb[q];
+            }
+        };
+        __syncthreads();   // the previous pass no longer reads the buffers
+        fetch(0);
+        store(0);
+        __syncthreads();
+        for (int ch = 0; ch < nchunk; ++ch) {
+            const int buf = ch & 1;
+            if (ch + 1 < nchunk) fetch((ch + 1) * GF_KC);
+#pragma unroll
+            for (int kk = 0; kk < GF_KC; kk += 4) {
+                const double av = sA[buf][rg * 16 + lr][kk + lk];
+#pragma unroll
+                for (int c = 0; c < GF_HALF; ++c)
+                    if (c < my_cb)
+                        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sB[buf][kk + lk][(cb0 + c) * 16 + lr],
+                                                                      acc[c], 0, 0, 0);
+            }
+            if (ch + 1 < nchunk) store(buf ^ 1);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int c = 0; c < GF_HALF; ++c) {
+            const int col = ct0 + (cb0 + c) * 16 + lr;
+            if (c < my_cb && col < m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) better(fabs(acc[c][r]), col, best[r], bidx[r]);
+        }
+    }
+    // the 16 lanes of a row, then the two column halves
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1)
 #pragma unroll
@@ -46,90 +131,20 @@ __device__ inline void finish_rows(double (&best)[4], int (&bidx)[4], int64_t ro
             const int oc = __shfl_xor(bidx[r], o, 64);
             better(ov, oc, best[r], bidx[r]);
         }
-    if ((lane & 15) == 0) {
+    if (lr == 0)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int64_t row = row0 + (F64LAYOUT ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
-            if (row < n) {
-                gamma[row] = best[r];
-                if (argmax) argmax[row] = bidx[r];
-            }
+            s_best[half][rg * 16 + lk + 4 * r] = best[r];
+            s_idx[half][rg * 16 + lk + 4 * r] = bidx[r];
         }
+    __syncthreads();
+    if (tid < GF_ROWS && row0 + tid < n) {
+        double bv = s_best[0][tid];
+        int bc = s_idx[0][tid];
+        better(s_best[1][tid], s_idx[1][tid], bv, bc);
+        gamma[row0 + tid] = bv;
+        if (argmax) argmax[row0 + tid] = bc;
     }
-}
-
-// FP64: a block owns 64 rows; the columns are taken in super-tiles of 256
-// (16 MFMA column blocks per wavefront, accumulators in registers) and the
-// k dimension in chunks of 16 staged through LDS: the 64 x 16 slab of b and
-// the 16 x 256 slab of A^-1 are loaded once per chunk by the whole block.
-constexpr int GF_ROWS = 64, GF_KC = 16, GF_CT = 256;
-__global__ __launch_bounds__(256) void grade_f64(const double *__restrict__ brow, int ldb, int64_t n,
-                                                 const double *__restrict__ Ainv, int m, double *gamma,
-                                                 int32_t *argmax) {
-    __shared__ double sA[GF_ROWS][GF_KC + 1];
-    __shared__ double sB[GF_KC][GF_CT];
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int64_t row0 = (int64_t)blockIdx.x * GF_ROWS;
-    double best[4] = {-1.0, -1.0, -1.0, -1.0};
-    int bidx[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
-    for (int ct0 = 0; ct0 < m; ct0 += GF_CT) {
-        const int ncb = min(GF_CT, m - ct0 + 15) / 16;   // column blocks holding real columns
-        doublex4 acc[GF_CT / 16];
-#pragma unroll
-        for (int cb = 0; cb < GF_CT / 16; ++cb) acc[cb] = doublex4{0.0, 0.0, 0.0, 0.0};
-        // register-staged double buffering: the next chunk's global loads are
-        // in flight while the MFMAs consume the current chunk from LDS
-        constexpr int RA = GF_ROWS * GF_KC / 256, RB = GF_KC * GF_CT / 256;
-        double ra[RA], rb[RB];
-        auto fetch = [&](int k0) {
-#pragma unroll
-            for (int q = 0; q < RA; ++q) {
-                const int e = tid + 256 * q;
-                const int r = e / GF_KC, k = e % GF_KC;
-                const int64_t row = row0 + r;
-                ra[q] = (row < n && k0 + k < m) ? brow[row * ldb + k0 + k] : 0.0;
-            }
-#pragma unroll
-            for (int q = 0; q < RB; ++q) {
-                const int e = tid + 256 * q;
-                const int k = e / GF_CT, c = e % GF_CT;
-                rb[q] = (k0 + k < m && ct0 + c < m) ? Ainv[(int64_t)(k0 + k) * m + ct0 + c] : 0.0;
-            }
-        };
-        fetch(0);
-        for (int k0 = 0; k0 < m; k0 += GF_KC) {
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < RA; ++q) {
-                const int e = tid + 256 * q;
-                sA[e / GF_KC][e % GF_KC] = ra[q];
-            }
-#pragma unroll
-            for (int q = 0; q < RB; ++q) {
-                const int e = tid + 256 * q;
-                sB[e / GF_CT][e % GF_CT] = rb[q];
-            }
-            __syncthreads();
-            if (k0 + GF_KC < m) fetch(k0 + GF_KC);
-#pragma unroll
-            for (int kk = 0; kk < GF_KC; kk += 4) {
-                const double av = sA[wave * 16 + lr][kk + lk];
-#pragma unroll
-                for (int cb = 0; cb < GF_CT / 16; ++cb)
-                    if (cb < ncb) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sB[kk + lk][cb * 16 + lr], acc[cb], 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int cb = 0; cb < GF_CT / 16; ++cb) {
-            const int col = ct0 + cb * 16 + lr;
-            if (cb < ncb && col < m)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) better(fabs(acc[cb][r]), col, best[r], bidx[r]);
-        }
-    }
-    finish_rows<true>(best, bidx, row0 + wave * 16, lane, n, gamma, argmax);
 }
 
 // split of x into NS BF16 terms (round to nearest even at every step)
@@ -142,66 +157,131 @@ template <int NS> __device__ inline void split_f32(float x, __bf16 (&t)[NS]) {
 }
 
 // Ainv split layout: S[term][col][kp] (kp = k padded to KP, col padded to CP),
-// so that the 8 consecutive k of one column are one 16-byte load.
+// so that 8 consecutive k of one column are one 16-byte load.
+//
+// Block of eight wavefronts, 64 rows; wave w takes rows 16 (w % 4) .. + 16
+// and half w / 4 of each pass of 224 columns.  k runs in chunks of 32 (one
+// MFMA k step) through two LDS buffers: the rows' FP32 chunk is split into
+// its BF16 terms as it is stored, the split A^-1 chunk is copied as is.
+constexpr int GB_KC = 32, GB_KPAD = GB_KC + 8;   // +8 bf16: 80-byte rows spread the LDS banks
 template <int NS>
-__global__ __launch_bounds__(256) void grade_bf16(const float *__restrict__ brow, int ldb, int64_t n,
+__global__ __launch_bounds__(512) void grade_bf16(const float *__restrict__ brow, int ldb, int64_t n,
                                                   const __bf16 *__restrict__ S, int m, int KP, int CP, double *gamma,
                                                   int32_t *argmax) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ __attribute__((aligned(16))) __bf16 sA[2][NS][GF_ROWS][GB_KPAD];
+    __shared__ __attribute__((aligned(16))) __bf16 sB[2][NS][GF_CT][GB_KPAD];
+    __shared__ double s_best[2][GF_ROWS];
+    __shared__ int s_idx[2][GF_ROWS];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int rg = wave & 3, half = wave >> 2;
     const int lr = lane & 15, lk = lane >> 4;
-    const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
-    const int64_t arow = row0 + lr;
-    const bool arow_ok = arow < n;
-    const float *ap = brow + (arow_ok ? arow : 0) * (int64_t)ldb;
+    const int64_t row0 = (int64_t)blockIdx.x * GF_ROWS;
     const int64_t term = (int64_t)CP * KP;
+    const int nchunk = KP / GB_KC;
+    // global -> register staging: A, one float4 per thread (row tid / 8, k 4 (tid % 8));
+    // B, 16-byte pieces e = tid + 512 q of (term, column, k group of 8)
+    constexpr int NBP = NS * GF_CT * (GB_KC / 8);
+    constexpr int RB = (NBP + 511) / 512;
     double best[4] = {-1.0, -1.0, -1.0, -1.0};
     int bidx[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
-    for (int col0 = 0; col0 < m; col0 += 64) {
-        floatx4 acc[4];
+    for (int ct0 = 0; ct0 < m; ct0 += GF_CT) {
+        const int ncb = min(GF_CT, m - ct0 + 15) / 16;
+        const int cb0 = half * GF_HALF;
+        const int my_cb = max(0, min(GF_HALF, ncb - cb0));
+        floatx4 acc[GF_HALF];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < KP; k0 += 32) {
-            const int kb = k0 + 8 * lk;   // this lane's 8 consecutive k
-            float av[8];
-            if (arow_ok) {
-                const float4 v0 = *reinterpret_cast<const float4 *>(ap + kb);
-                const float4 v1 = *reinterpret_cast<const float4 *>(ap + kb + 4);
-                av[0] = v0.x; av[1] = v0.y; av[2] = v0.z; av[3] = v0.w;
-                av[4] = v1.x; av[5] = v1.y; av[6] = v1.z; av[7] = v1.w;
-            } else {
+        for (int c = 0; c < GF_HALF; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+        float4 ra;
+        uint4 rb[RB];
+        auto fetch = [&](int k0) {
+            const int r = tid >> 3, k = k0 + 4 * (tid & 7);
+            const int64_t row = row0 + r;
+            ra = row < n ? *reinterpret_cast<const float4 *>(brow + row * ldb + k) : float4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int e = 0; e < 8; ++e) av[e] = 0.f;
+            for (int q = 0; q < RB; ++q) {
+                const int e = tid + 512 * q;
+                const int t = e / (GF_CT * 4), rem = e % (GF_CT * 4), c = rem >> 2, kg = rem & 3;
+                const int col = ct0 + c;
+                rb[q] = (e < NBP && col < CP)
+                            ? *reinterpret_cast<const uint4 *>(S + t * term + (int64_t)col * KP + k0 + 8 * kg)
+                            : uint4{0u, 0u, 0u, 0u};
             }
-            bf16x8 A[NS];
+        };
+        auto store = [&](int buf) {
+            const int r = tid >> 3, k = 4 * (tid & 7);
+            const float v[4] = {ra.x, ra.y, ra.z, ra.w};
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
+            for (int e = 0; e < 4; ++e) {
                 __bf16 t[NS];
-                split_f32<NS>(av[e], t);
+                split_f32<NS>(v[e], t);
 #pragma unroll
-                for (int s = 0; s < NS; ++s) A[s][e] = t[s];
+                for (int s2 = 0; s2 < NS; ++s2) sA[buf][s2][r][k + e] = t[s2];
             }
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
-                const int col = col0 + cb * 16 + lr;
-                const int colc = col < CP ? col : CP - 1;
-#pragma unroll
-                for (int t = 0; t < NS; ++t) {
-                    const bf16x8 B = *reinterpret_cast<const bf16x8 *>(S + t * term + (int64_t)colc * KP + kb);
-#pragma unroll
-                    for (int s = 0; s + t < NS; ++s)
-                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s], B, acc[cb], 0, 0, 0);
+            for (int q = 0; q < RB; ++q) {
+                const int e = tid + 512 * q;
+                if (e < NBP) {
+                    const int t = e / (GF_CT * 4), rem = e % (GF_CT * 4), c = rem >> 2, kg = rem & 3;
+                    *reinterpret_cast<uint4 *>(&sB[buf][t][c][8 * kg]) = rb[q];
                 }
             }
+        };
+        __syncthreads();
+        fetch(0);
+        store(0);
+        __syncthreads();
+        for (int ch = 0; ch < nchunk; ++ch) {
+            const int buf = ch & 1;
+            if (ch + 1 < nchunk) fetch((ch + 1) * GB_KC);
+            bf16x8 A[NS];
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2) A[s2] = *reinterpret_cast<const bf16x8 *>(&sA[buf][s2][rg * 16 + lr][8 * lk]);
+#pragma unroll
+            for (int c = 0; c < GF_HALF; ++c) {
+                if (c < my_cb) {
+#pragma unroll
+                    for (int t = 0; t < NS; ++t) {
+                        const bf16x8 B = *reinterpret_cast<const bf16x8 *>(&sB[buf][t][(cb0 + c) * 16 + lr][8 * lk]);
+#pragma unroll
+                        for (int s2 = 0; s2 + t < NS; ++s2)
+                            acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s2], B, acc[c], 0, 0, 0);
+                    }
+                }
+            }
+            if (ch + 1 < nchunk) store(buf ^ 1);
+            __syncthreads();
         }
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            const int col = col0 + cb * 16 + lr;
-            if (col < m)
+        for (int c = 0; c < GF_HALF; ++c) {
+            const int col = ct0 + (cb0 + c) * 16 + lr;
+            if (c < my_cb && col < m)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) better((double)fabsf(acc[cb][r]), col, best[r], bidx[r]);
+                for (int r = 0; r < 4; ++r) better((double)fabsf(acc[c][r]), col, best[r], bidx[r]);
         }
     }
-    finish_rows<false>(best, bidx, row0, lane, n, gamma, argmax);
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double ov = __shfl_xor(best[r], o, 64);
+            const int oc = __shfl_xor(bidx[r], o, 64);
+            better(ov, oc, best[r], bidx[r]);
+        }
+    if (lr == 0)   // bf16 layout: row 4 (lane / 16) + r
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            s_best[half][rg * 16 + 4 * lk + r] = best[r];
+            s_idx[half][rg * 16 + 4 * lk + r] = bidx[r];
+        }
+    __syncthreads();
+    if (tid < GF_ROWS && row0 + tid < n) {
+        double bv = s_best[0][tid];
+        int bc = s_idx[0][tid];
+        better(s_best[1][tid], s_idx[1][tid], bv, bc);
+        gamma[row0 + tid] = bv;
+        if (argmax) argmax[row0 + tid] = bc;
+    }
 }
 
 __global__ void split_ainv(const double *Ainv, int m, int KP, int CP, int NS, __bf16 *S) {
@@ -444,11 +524,11 @@ void launch_grade(const ActiveSet &as, int precision, const void *brow, int ldb,
     if (n == 0) return;
     const dim3 grid((unsigned)((n + 63) / 64));
     if (precision == MTP_FP64) {
-        hipLaunchKernelGGL(grade_f64, grid, dim3(256), 0, st, static_cast<const double *>(brow), ldb, n,
+        hipLaunchKernelGGL(grade_f64, grid, dim3(512), 0, st, static_cast<const double *>(brow), ldb, n,
                            as.Ainv.as<double>(), as.m, gamma, argmax);
     } else {
         const int KP = (as.m + 31) / 32 * 32, CP = (as.m + 15) / 16 * 16;
-        hipLaunchKernelGGL(grade_bf16<3>, grid, dim3(256), 0, st, static_cast<const float *>(brow), ldb, n,
+        hipLaunchKernelGGL(grade_bf16<3>, grid, dim3(512), 0, st, static_cast<const float *>(brow), ldb, n,
                            as.Ainv32.as<__bf16>(), as.m, KP, CP, gamma, argmax);
     }
 }

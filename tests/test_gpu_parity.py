@@ -100,6 +100,27 @@ def test_neighbors_full_size_workload2_sampled():
     assert _nbr_sets(count, j, sh, atoms) == _oracle_sets(pairs, atoms)
 
 
+def test_neighbors_dense_cluster_mixed_bins():
+    """A dense cluster in a sparse periodic box: bins next to the cluster have
+    more candidates than one register window holds (the two-sweep path),
+    the others take the one-window path; lists must match the oracle and be
+    symmetric: (i, j, n) present iff (j, i, -n) is."""
+    r = np.random.default_rng(11)
+    dense = r.random((600, 3)) * 10.0
+    sparse = r.random((100, 3)) * 20.0
+    pos = np.vstack([dense, sparse])
+    cfg = synth.Config(pos, r.integers(0, 2, len(pos)).astype(np.int32), np.diag([20.0, 20.0, 20.0]))
+    m = api.Model.create(8, 2, 2.0, 5.0)
+    b = api.Batch([cfg])
+    nb = api.Neighbors().build(m, b, max_nbrs=512)
+    count, j, sh = (t.cpu().numpy() for t in nb.export(b))
+    atoms = list(range(cfg.n))
+    got = _nbr_sets(count, j, sh, atoms)
+    assert got == _oracle_sets(onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, 5.0), atoms)
+    directed = {(a,) + e for a, v in got.items() for e in v}
+    assert all((e[1], e[0], -e[2], -e[3], -e[4]) in directed for e in directed)
+
+
 def test_neighbor_capacity_and_overlap_are_reported():
     w = synth.workload1()
     m = api.Model.create(8, 1, 2.0, 5.0)
