@@ -227,7 +227,7 @@ __global__ __launch_bounds__(256) void bwd_pairs(const BwdArgs b) {
         for (int mu = 0; mu < NR; ++mu)
 #pragma unroll
             for (int q = 0; q < NPOLY; ++q) acc[mu][q] = T(0);
-        for (int qq = sub; qq < c.tc[t]; qq += K) {
+        for (int qq = sub; qq < tcount(a, c, t); qq += K) {
             const int p = gstart + qq;
             const T x = T(c.rp[3 * p]), y = T(c.rp[3 * p + 1]), z = T(c.rp[3 * p + 2]);
             const T r = sqrt(x * x + y * y + z * z);
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(256) void bwd_pairs(const BwdArgs b) {
                 for (int q = 0; q < NPOLY; ++q)
                     if ((mu * NPOLY + q) % K == sub) row[((mu * nt + c.zi) * nt + t) * NPOLY + q] = acc[mu][q];
         }
-        gstart += c.tc[t];
+        gstart += tcount(a, c, t);
     }
     if (row) {   // c blocks of the other central species are zero
         const int nblk = NR * nt * nt * NPOLY;

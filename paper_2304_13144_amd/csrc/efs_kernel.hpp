@@ -29,6 +29,28 @@ namespace efs {
 
 template <typename T> __device__ inline T xor_shuffle(T v, int mask) { return __shfl_xor(v, mask, 64); }
 
+// Reduce-scatter over the K lanes of a group (sub = lane % K): afterwards
+// v[0 .. M/K) of lane sub holds the group totals of v[sub M/K .. (sub+1) M/K).
+// Each round halves the live values (the lane whose bit O is set keeps the
+// upper half), so it takes M (1 - 1/K) shuffles instead of the M log2 K of a
+// butterfly all-reduce.
+template <typename T, int M, int N, int O> __device__ inline void rs_step(T (&v)[M], int sub) {
+    if constexpr (O >= 1) {
+        const bool up = (sub & O) != 0;
+#pragma unroll
+        for (int i = 0; i < N / 2; ++i) {
+            const T send = up ? v[i] : v[i + N / 2];
+            const T keep = up ? v[i + N / 2] : v[i];
+            v[i] = keep + xor_shuffle(send, O);
+        }
+        rs_step<T, M, N / 2, O / 2>(v, sub);
+    }
+}
+template <typename T, int M, int K> __device__ inline void reduce_scatter(T (&v)[M], int sub) {
+    static_assert(M % K == 0, "reduce_scatter: M must be a multiple of K");
+    rs_step<T, M, M, K / 2>(v, sub);
+}
+
 // monomials x^a y^b z^c, a+b+c <= 3, in the order of monomial_index()
 template <typename T> __device__ inline void monomials(T x, T y, T z, T (&m)[20]) {
     m[0] = T(1); m[1] = x; m[2] = y; m[3] = z;
@@ -71,6 +93,12 @@ template <int K> __device__ inline AtomCtx atom_ctx(const EfsArgs &a) {
     return c;
 }
 
+// neighbors of species t, re-read from the (cached) counts: a runtime index
+// into c.tc would put the whole context in scratch memory
+template <typename A> __device__ inline int tcount(const A &a, const AtomCtx &c, int t) {
+    return c.live ? a.tcnt[c.atom * a.n_types + t] : 0;
+}
+
 template <typename T, int NR> __device__ inline void load_coefs(const EfsArgs &a, T *c_s) {
     const T *cg = static_cast<const T *>(a.c);
     const int ncoef = NR * a.n_types * a.n_types * NPOLY;
@@ -91,9 +119,10 @@ __global__ __launch_bounds__(256) void efs_moments(const EfsArgs a) {
     const T rc = T(a.r_cut);
     const T xs = T(2.0 / (a.r_cut - a.r_min));
     const T x0 = T(-(a.r_min + a.r_cut) / (a.r_cut - a.r_min));
-    T M[NC];
+    constexpr int NCP = (NC + K - 1) / K * K;   // padded for the reduce-scatter
+    T M[NCP];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) M[k] = T(0);
+    for (int k = 0; k < NCP; ++k) M[k] = T(0);
     int zj = 0, tend = c.tc[0];
     for (int p = sub; p < c.ntot; p += K) {
         while (p >= tend && zj < nt - 1) tend += c.tc[++zj];
@@ -122,15 +151,14 @@ __global__ __launch_bounds__(256) void efs_moments(const EfsArgs a) {
 #pragma unroll
         for (int k = 0; k < NC; ++k) M[k] = fma(fm[LV::comp_mu[k]], mono[LV::comp_mono[k]], M[k]);
     }
-#pragma unroll
-    for (int o = K / 2; o > 0; o >>= 1)
-#pragma unroll
-        for (int k = 0; k < NC; ++k) M[k] += efs::xor_shuffle(M[k], o);
+    efs::reduce_scatter<T, NCP, K>(M, sub);
     if (c.live) {
         T *out = static_cast<T *>(a.mbuf);
 #pragma unroll
-        for (int k = 0; k < NC; ++k)
-            if (k % K == sub) out[(int64_t)k * a.n_atoms + c.slot] = M[k];
+        for (int i = 0; i < NCP / K; ++i) {
+            const int k = sub * (NCP / K) + i;
+            if (k < NC) out[(int64_t)k * a.n_atoms + c.slot] = M[i];
+        }
     }
 }
 
@@ -222,62 +250,72 @@ __global__ __launch_bounds__(256) void efs_contract(const EfsArgs a) {
     }
 }
 
-// ---- kernel 3: pair gradients, virial, b-row c part; LANES per atom -------
-template <typename T, int L, int K, bool WB>
+// Chebyshev values (and derivatives) at u for the radial basis (eq. 4)
+template <typename T, bool DERIV>
+__device__ inline void chebyshev(T u, T (&Tb)[NPOLY], T (&dT)[NPOLY]) {
+    Tb[0] = T(1);
+    Tb[1] = u;
+    if (DERIV) {
+        dT[0] = T(0);
+        dT[1] = T(1);
+    }
+#pragma unroll
+    for (int b = 2; b < NPOLY; ++b) {
+        Tb[b] = fma(T(2) * u, Tb[b - 1], -Tb[b - 2]);
+        if (DERIV) dT[b] = fma(T(2) * u, dT[b - 1], fma(T(2), Tb[b - 1], -dT[b - 2]));
+    }
+}
+
+// dE/dM of the block's neighborhoods in LDS, [k][neighborhood in block]: the
+// K lanes of a neighborhood read the same word (broadcast); in registers
+// they would cost 2 NC VGPRs per lane.
+template <typename T, int NC, int K>
+__device__ inline void load_dm(const EfsArgs &a, const AtomCtx &c, int sub, T (&s_dm)[NC][256 / K]) {
+    const T *din = static_cast<const T *>(a.dmbuf);
+    const int la = threadIdx.x / K;
+    for (int k = sub; k < NC; k += K) s_dm[k][la] = c.live ? din[(int64_t)k * a.n_atoms + c.slot] : T(0);
+    __syncthreads();
+}
+
+// ---- kernel 3: pair gradients and virial; LANES per atom ------------------
+// g_ij = dE_i/dr_ij = sum_mu [f_mu'(r) P_mu r_ij / r + f_mu(r) grad P_mu] with
+// P_mu = sum_nu dE/dM_{mu,nu} (r_ij)^{(x)nu} (the moment tensors contracted
+// with dE/dM), written per pair; virial S_ab = -sum_j g_a r_b per atom.
+template <typename T, int L, int K>
 __global__ __launch_bounds__(256) void efs_forces(const EfsArgs a) {
     using LV = Level<L>;
-    constexpr int NC = LV::NC, NR = LV::NRAD, NL = LV::NLIN;
+    constexpr int NC = LV::NC, NR = LV::NRAD;
     __shared__ T c_s[NR * MAX_TYPES * MAX_TYPES * NPOLY];
+    __shared__ T s_dm[NC][256 / K];
     load_coefs<T, NR>(a, c_s);
     const int nt = a.n_types;
     const int sub = threadIdx.x % K;
     const AtomCtx c = atom_ctx<K>(a);
+    load_dm<T, NC, K>(a, c, sub, s_dm);
+    const int la = threadIdx.x / K;
     const T rc = T(a.r_cut);
     const T xs = T(2.0 / (a.r_cut - a.r_min));
     const T x0 = T(-(a.r_min + a.r_cut) / (a.r_cut - a.r_min));
-    T dM[NC];
-    {
-        const T *din = static_cast<const T *>(a.dmbuf);
-#pragma unroll
-        for (int k = 0; k < NC; ++k) dM[k] = c.live ? din[(int64_t)k * a.n_atoms + c.slot] : T(0);
-    }
-    T *brow = (WB && c.live) ? static_cast<T *>(a.brow) + c.slot * (int64_t)a.ldb : nullptr;
     T vir[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) vir[k] = T(0);
     T *gout = static_cast<T *>(a.gbuf);
-    const bool full_rows = WB && a.grade_mode == MTP_GRADE_FULL;
     int gstart = 0;
     for (int t = 0; t < nt; ++t) {
-        T dc[NR][NPOLY];
-#pragma unroll
-        for (int mu = 0; mu < NR; ++mu)
-#pragma unroll
-            for (int b = 0; b < NPOLY; ++b) dc[mu][b] = T(0);
-        for (int q = sub; q < c.tc[t]; q += K) {
+        for (int q = sub; q < tcount(a, c, t); q += K) {
             const int p = gstart + q;
             const T x = T(c.rp[3 * p]), y = T(c.rp[3 * p + 1]), z = T(c.rp[3 * p + 2]);
             const T r = sqrt(x * x + y * y + z * z);
             T g0 = T(0), g1 = T(0), g2 = T(0);
             if (r < rc) {
-                T f[NR], fp[NR], Q[NPOLY];
+                T f[NR], fp[NR];
                 {
                     const T u = fma(r, xs, x0);
                     const T d = rc - r;
                     const T cut = d * d;
                     const T dcut = T(-2) * d;
                     T Tb[NPOLY], dT[NPOLY];
-                    Tb[0] = T(1);
-                    Tb[1] = u;
-                    dT[0] = T(0);
-                    dT[1] = T(1);
-#pragma unroll
-                    for (int b = 2; b < NPOLY; ++b) {
-                        Tb[b] = fma(T(2) * u, Tb[b - 1], -Tb[b - 2]);
-                        dT[b] = fma(T(2) * u, dT[b - 1], fma(T(2), Tb[b - 1], -dT[b - 2]));
-                    }
-#pragma unroll
-                    for (int b = 0; b < NPOLY; ++b) Q[b] = Tb[b] * cut;
+                    chebyshev<T, true>(u, Tb, dT);
 #pragma unroll
                     for (int mu = 0; mu < NR; ++mu) {
                         const T *cm = c_s + ((mu * nt + c.zi) * nt + t) * NPOLY;
@@ -299,7 +337,7 @@ __global__ __launch_bounds__(256) void efs_forces(const EfsArgs a) {
 #pragma unroll
                 for (int k = 0; k < NC; ++k) {
                     const int mu = LV::comp_mu[k];
-                    const T dmk = dM[k];
+                    const T dmk = s_dm[k][la];
                     P[mu] = fma(dmk, mono[LV::comp_mono[k]], P[mu]);
                     if (LV::comp_dmonox[k] >= 0)
                         Gx[mu] = fma(dmk * T(LV::comp_dfacx[k]), mono[LV::comp_dmonox[k] < 0 ? 0 : LV::comp_dmonox[k]], Gx[mu]);
@@ -321,12 +359,6 @@ __global__ __launch_bounds__(256) void efs_forces(const EfsArgs a) {
                 g0 = fma(radial_part, x, g0);
                 g1 = fma(radial_part, y, g1);
                 g2 = fma(radial_part, z, g2);
-                if (full_rows) {
-#pragma unroll
-                    for (int mu = 0; mu < NR; ++mu)
-#pragma unroll
-                        for (int b = 0; b < NPOLY; ++b) dc[mu][b] = fma(Q[b], P[mu], dc[mu][b]);
-                }
                 // S_ab = -sum g_a r_b
                 vir[0] -= g0 * x; vir[1] -= g0 * y; vir[2] -= g0 * z;
                 vir[3] -= g1 * x; vir[4] -= g1 * y; vir[5] -= g1 * z;
@@ -339,35 +371,86 @@ __global__ __launch_bounds__(256) void efs_forces(const EfsArgs a) {
                 gout[s3 + 2] = g2;
             }
         }
-        if (full_rows) {
+        gstart += tcount(a, c, t);
+    }
+    constexpr int NV = (9 + K - 1) / K * K;
+    T vp[NV];
 #pragma unroll
-            for (int o = K / 2; o > 0; o >>= 1)
+    for (int k = 0; k < NV; ++k) vp[k] = k < 9 ? vir[k] : T(0);
+    efs::reduce_scatter<T, NV, K>(vp, sub);
+    if (c.live && a.virial) {
 #pragma unroll
-                for (int mu = 0; mu < NR; ++mu)
+        for (int i = 0; i < NV / K; ++i) {
+            const int k = sub * (NV / K) + i;
+            if (k < 9) a.virial[c.atom * 9 + k] = double(vp[i]);
+        }
+    }
+}
+
+// ---- kernel 4: the rest of b_i (Sec. II.C); LANES per atom ----------------
+// FULL grade mode: the radial-coefficient part
+//   dV_i/dc_{mu, z_i, z_j, beta} = sum_{j of species z_j} T_beta(r_ij) (R_cut - r_ij)^2 P_mu(r_ij)
+// (P_mu as in kernel 3), zero for the blocks of the other central species;
+// both modes: the species one-hot (dV_i/dxi0) and zero padding.  The
+// xi part (B_alpha) comes from kernel 2.
+template <typename T, int L, int K>
+__global__ __launch_bounds__(256) void efs_rows(const EfsArgs a) {
+    using LV = Level<L>;
+    constexpr int NC = LV::NC, NR = LV::NRAD, NL = LV::NLIN;
+    __shared__ T s_dm[NC][256 / K];
+    const int nt = a.n_types;
+    const int sub = threadIdx.x % K;
+    const AtomCtx c = atom_ctx<K>(a);
+    const bool full_rows = a.grade_mode == MTP_GRADE_FULL;
+    if (full_rows) load_dm<T, NC, K>(a, c, sub, s_dm);
+    const int la = threadIdx.x / K;
+    T *brow = c.live ? static_cast<T *>(a.brow) + c.slot * (int64_t)a.ldb : nullptr;
+    const T rc = T(a.r_cut);
+    const T xs = T(2.0 / (a.r_cut - a.r_min));
+    const T x0 = T(-(a.r_min + a.r_cut) / (a.r_cut - a.r_min));
+    if (full_rows) {
+        int gstart = 0;
+        for (int t = 0; t < nt; ++t) {
+            constexpr int ND = NR * NPOLY;   // a multiple of K (NPOLY = 8)
+            T dc[ND];
 #pragma unroll
-                    for (int b = 0; b < NPOLY; ++b) dc[mu][b] += efs::xor_shuffle(dc[mu][b], o);
+            for (int k = 0; k < ND; ++k) dc[k] = T(0);
+            for (int q = sub; q < tcount(a, c, t); q += K) {
+                const int p = gstart + q;
+                const T x = T(c.rp[3 * p]), y = T(c.rp[3 * p + 1]), z = T(c.rp[3 * p + 2]);
+                const T r = sqrt(x * x + y * y + z * z);
+                if (!(r < rc)) continue;
+                const T u = fma(r, xs, x0);
+                const T d = rc - r;
+                const T cut = d * d;
+                T Tb[NPOLY], dT[NPOLY];
+                chebyshev<T, false>(u, Tb, dT);
+                T mono[20];
+                efs::monomials(x, y, z, mono);
+                T P[NR];
+#pragma unroll
+                for (int mu = 0; mu < NR; ++mu) P[mu] = T(0);
+#pragma unroll
+                for (int k = 0; k < NC; ++k) P[LV::comp_mu[k]] = fma(s_dm[k][la], mono[LV::comp_mono[k]], P[LV::comp_mu[k]]);
+#pragma unroll
+                for (int b = 0; b < NPOLY; ++b) {
+                    const T qb = Tb[b] * cut;
+#pragma unroll
+                    for (int mu = 0; mu < NR; ++mu) dc[mu * NPOLY + b] = fma(qb, P[mu], dc[mu * NPOLY + b]);
+                }
+            }
+            efs::reduce_scatter<T, ND, K>(dc, sub);
             if (brow) {
                 const int base = nt + NL;
 #pragma unroll
-                for (int mu = 0; mu < NR; ++mu)
-#pragma unroll
-                    for (int b = 0; b < NPOLY; ++b) {
-                        if ((mu * NPOLY + b) % K != sub) continue;
-                        const int col = a.colmap[base + ((mu * nt + c.zi) * nt + t) * NPOLY + b];
-                        if (col >= 0) brow[col] = dc[mu][b];
-                    }
+                for (int i = 0; i < ND / K; ++i) {
+                    const int k = sub * (ND / K) + i, mu = k / NPOLY, b = k % NPOLY;
+                    const int col = a.colmap[base + ((mu * nt + c.zi) * nt + t) * NPOLY + b];
+                    if (col >= 0) brow[col] = dc[i];
+                }
             }
+            gstart += tcount(a, c, t);
         }
-        gstart += c.tc[t];
-    }
-#pragma unroll
-    for (int o = K / 2; o > 0; o >>= 1)
-#pragma unroll
-        for (int k = 0; k < 9; ++k) vir[k] += efs::xor_shuffle(vir[k], o);
-    if (c.live && a.virial) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k)
-            if (k % K == sub) a.virial[c.atom * 9 + k] = double(vir[k]);
     }
     if (brow) {
         // species one-hot, zero c blocks of the other central species, zero padding
@@ -405,7 +488,11 @@ template <int L> int launch_efs_level(const EfsArgs &a);
         }                                                                                                \
         {                                                                                                \
             ProfScope ps("efs_forces", a.stream);                                                        \
-            hipLaunchKernelGGL((efs_forces<T, LEVEL, K, WB>), dim3(grid), dim3(256), 0, a.stream, a);    \
+            hipLaunchKernelGGL((efs_forces<T, LEVEL, K>), dim3(grid), dim3(256), 0, a.stream, a);        \
+        }                                                                                                \
+        if (WB) {                                                                                        \
+            ProfScope ps("efs_rows", a.stream);                                                          \
+            hipLaunchKernelGGL((efs_rows<T, LEVEL, K>), dim3(grid), dim3(256), 0, a.stream, a);          \
         }                                                                                                \
     }                                                                                                    \
     template <typename T, bool WB> static void launch_efs_t##LEVEL(const EfsArgs &a) {                   \
