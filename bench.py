@@ -29,8 +29,8 @@ PEAK_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz,
 PEAK_MFMA_F64_TFLOPS = 78.6
 PEAK_MFMA_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
-KERNELS = ("neighbors", "efs", "efs_moments", "efs_contract", "efs_forces", "efs_rows", "force_gather", "cfg_sums",
-           "grade", "select")
+KERNELS = ("neighbors", "efs", "efs_moments", "efs_contract", "efs_forces", "force_gather", "cfg_sums", "grade",
+           "select")
 
 
 def log(msg):
@@ -42,18 +42,16 @@ def efs_flops_per_atom(n_pairs_per_atom, nc, nr, contraction_flops, with_rows):
 
     efs_moments, per pair:  r (6) + T_0..T_7 (12) + f_mu (16 nr + 2) + monomials (16) + moments (2 nc)
     efs_contract:           the generated contraction program (graph values, trie walk, reverse)
-    efs_forces, per pair:   r (6) + T, T' (30) + f, f' (32 nr + 4 nr + 3) + monomials (16)
+    efs_forces (one launch, two block ranges), per pair:
+      pair gradients:       r (6) + T, T' (30) + f, f' (32 nr + 4 nr + 3) + monomials (16)
                             + P and grad P (8 nc) + g assembly (8 nr + 7) + virial (18)
-    efs_rows, per pair:     r (6) + T (12) + cutoff (3) + monomials (16) + P (2 nc) + c part (2 nr NPOLY + NPOLY)
+      b-row c part:         r (6) + T (12) + cutoff (3) + monomials (16) + P (2 nc) + 2 nr NPOLY + NPOLY
     """
     p1 = 6 + 12 + 16 * nr + 2 + 16 + 2 * nc
     p3 = 6 + 30 + 36 * nr + 3 + 16 + 8 * nc + 8 * nr + 7 + 18
     p4 = 6 + 12 + 3 + 16 + 2 * nc + 2 * nr * 8 + 8
-    out = {"efs_moments": n_pairs_per_atom * p1, "efs_contract": float(contraction_flops),
-           "efs_forces": n_pairs_per_atom * p3}
-    if with_rows:
-        out["efs_rows"] = n_pairs_per_atom * p4
-    return out
+    return {"efs_moments": n_pairs_per_atom * p1, "efs_contract": float(contraction_flops),
+            "efs_forces": n_pairs_per_atom * (p3 + (p4 if with_rows else 0))}
 
 
 def main():

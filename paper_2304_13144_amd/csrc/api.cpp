@@ -262,7 +262,7 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     if (o.energy || want_v) {
         ProfScope ps("cfg_sums", st);
         launch_cfg_sums(s, o.energy ? site : nullptr, want_v ? m->virial.as<double>() : nullptr, o.energy, o.stress,
-                        st, m->sums);
+                        st, m->sums, ticket_buf(m->tickets, st));
     }
     if (want_grade) {
         m->gamma_ws.ensure(sizeof(double) * n);
@@ -657,9 +657,9 @@ int mtp_select(const double *gamma, int64_t n, double threshold, int32_t *idx, i
     API_BEGIN
     MTP_CHECK(gamma && idx && count, MTP_E_INVAL, "NULL argument");
     MTP_CHECK(n >= 0 && capacity >= 0, MTP_E_INVAL, "negative size");
-    static thread_local DevBuf work;
+    static thread_local DevBuf work, tickets;
     ProfScope ps("select", S(stream));
-    launch_select(gamma, n, threshold, idx, capacity, count, S(stream), work);
+    launch_select(gamma, n, threshold, idx, capacity, count, S(stream), work, ticket_buf(tickets, S(stream)));
     API_END
 }
 

@@ -75,10 +75,10 @@ struct AtomCtx {
     const double *rp;
 };
 
-template <int K> __device__ inline AtomCtx atom_ctx(const EfsArgs &a) {
+template <int K> __device__ inline AtomCtx atom_ctx(const EfsArgs &a, int64_t blk = -1) {
     AtomCtx c;
     const int nt = a.n_types;
-    c.slot = (int64_t)blockIdx.x * (blockDim.x / K) + threadIdx.x / K;
+    c.slot = (blk < 0 ? (int64_t)blockIdx.x : blk) * (blockDim.x / K) + threadIdx.x / K;
     c.live = c.slot < a.n_atoms;
     c.atom = c.live ? (a.atom_list ? (int64_t)a.atom_list[c.slot] : c.slot) : 0;
     int zi = c.live ? a.type[c.atom] : 0;
@@ -282,15 +282,13 @@ __device__ inline void load_dm(const EfsArgs &a, const AtomCtx &c, int sub, T (&
 // P_mu = sum_nu dE/dM_{mu,nu} (r_ij)^{(x)nu} (the moment tensors contracted
 // with dE/dM), written per pair; virial S_ab = -sum_j g_a r_b per atom.
 template <typename T, int L, int K>
-__global__ __launch_bounds__(256) void efs_forces(const EfsArgs a) {
+__device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T (&s_dm)[Level<L>::NC][256 / K]) {
     using LV = Level<L>;
     constexpr int NC = LV::NC, NR = LV::NRAD;
-    __shared__ T c_s[NR * MAX_TYPES * MAX_TYPES * NPOLY];
-    __shared__ T s_dm[NC][256 / K];
     load_coefs<T, NR>(a, c_s);
     const int nt = a.n_types;
     const int sub = threadIdx.x % K;
-    const AtomCtx c = atom_ctx<K>(a);
+    const AtomCtx c = atom_ctx<K>(a, blk);
     load_dm<T, NC, K>(a, c, sub, s_dm);
     const int la = threadIdx.x / K;
     const T rc = T(a.r_cut);
@@ -394,13 +392,12 @@ __global__ __launch_bounds__(256) void efs_forces(const EfsArgs a) {
 // both modes: the species one-hot (dV_i/dxi0) and zero padding.  The
 // xi part (B_alpha) comes from kernel 2.
 template <typename T, int L, int K>
-__global__ __launch_bounds__(256) void efs_rows(const EfsArgs a) {
+__device__ inline void efs_rows_body(const EfsArgs &a, int64_t blk, T (&s_dm)[Level<L>::NC][256 / K]) {
     using LV = Level<L>;
     constexpr int NC = LV::NC, NR = LV::NRAD, NL = LV::NLIN;
-    __shared__ T s_dm[NC][256 / K];
     const int nt = a.n_types;
     const int sub = threadIdx.x % K;
-    const AtomCtx c = atom_ctx<K>(a);
+    const AtomCtx c = atom_ctx<K>(a, blk);
     const bool full_rows = a.grade_mode == MTP_GRADE_FULL;
     if (full_rows) load_dm<T, NC, K>(a, c, sub, s_dm);
     const int la = threadIdx.x / K;
@@ -469,6 +466,18 @@ __global__ __launch_bounds__(256) void efs_rows(const EfsArgs a) {
     }
 }
 
+// Kernels 3 and 4 in one launch: blocks [0, nblk) take kernel 3, blocks
+// [nblk, 2 nblk) kernel 4 (when rows are wanted); both only read dE/dM.
+template <typename T, int L, int K>
+__global__ __launch_bounds__(256) void efs_forces_rows(const EfsArgs a, int64_t nblk) {
+    __shared__ T c_s[Level<L>::NRAD * MAX_TYPES * MAX_TYPES * NPOLY];
+    __shared__ T s_dm[Level<L>::NC][256 / K];
+    if ((int64_t)blockIdx.x < nblk)
+        efs_forces_body<T, L, K>(a, blockIdx.x, c_s, s_dm);
+    else
+        efs_rows_body<T, L, K>(a, (int64_t)blockIdx.x - nblk, s_dm);
+}
+
 template <int L> int launch_efs_level(const EfsArgs &a);
 
 // instantiates the launchers of one level (used by the generated units)
@@ -488,11 +497,8 @@ template <int L> int launch_efs_level(const EfsArgs &a);
         }                                                                                                \
         {                                                                                                \
             ProfScope ps("efs_forces", a.stream);                                                        \
-            hipLaunchKernelGGL((efs_forces<T, LEVEL, K>), dim3(grid), dim3(256), 0, a.stream, a);        \
-        }                                                                                                \
-        if (WB) {                                                                                        \
-            ProfScope ps("efs_rows", a.stream);                                                          \
-            hipLaunchKernelGGL((efs_rows<T, LEVEL, K>), dim3(grid), dim3(256), 0, a.stream, a);          \
+            hipLaunchKernelGGL((efs_forces_rows<T, LEVEL, K>), dim3(WB ? 2 * grid : grid), dim3(256), 0,  \
+                               a.stream, a, (int64_t)grid);                                              \
         }                                                                                                \
     }                                                                                                    \
     template <typename T, bool WB> static void launch_efs_t##LEVEL(const EfsArgs &a) {                   \

@@ -42,6 +42,19 @@ struct DevBuf {
     DevBuf &operator=(const DevBuf &) = delete;
 };
 
+void launch_zero(void *p, size_t bytes, hipStream_t st);
+
+// Counters for last-block completion (device_util.hpp), zeroed once when
+// first allocated; each use resets its own counter, so no memset is needed
+// per call (nor inside a captured graph).
+inline unsigned *ticket_buf(DevBuf &b, hipStream_t st) {
+    if (!b.ptr) {
+        b.ensure(64 * sizeof(unsigned));
+        launch_zero(b.ptr, 64 * sizeof(unsigned), st);
+    }
+    return b.as<unsigned>();
+}
+
 constexpr int NPOLY = 8;     // Chebyshev polynomials per radial function
 constexpr int MAX_TYPES = 4;
 
@@ -70,6 +83,7 @@ struct mtp_model {
     int tuned_lanes[2][48] = {};    // [precision][floor(log2 n_atoms)] -> lanes per neighborhood, 0 = untuned
     // scratch of the evaluation path
     mutable mtp::DevBuf gbuf, virial, sitebuf, brow, gamma_ws, argmax_ws, work, sums, mbuf, dmbuf, tbuf, dtbuf, rows;
+    mutable mtp::DevBuf tickets;    // last-block counters: [0] configuration sums, [1] preselection
     int m_of(int mode) const { return mode == MTP_GRADE_FULL ? (int)kept.size() : n_types + basis.n_lin(); }
 };
 
@@ -90,6 +104,7 @@ struct mtp_nbrs {
     mtp::DevBuf bin_count, bin_start, bin_cursor, bin_atoms, atom_bin, atom_wrap, work_sums;
     // atoms in bin order: position wrapped into the cell, packed -wrap, species
     mtp::DevBuf stage_x, stage_w, stage_t;
+    mtp::DevBuf tickets;  // last-block counters
     mtp::DevBuf flags;    // [4] int32: overflow, max count, overlap, spare
     int64_t bins_cap = 0;
 };
@@ -150,7 +165,7 @@ void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_
 
 void launch_force_gather(const mtp_nbrs *nb, const void *gbuf, int precision, double *forces, hipStream_t st);
 void launch_cfg_sums(const mtp_system *s, const double *site_e, const double *virial, double *energy,
-                     double *stress, hipStream_t st, DevBuf &work);
+                     double *stress, hipStream_t st, DevBuf &work, unsigned *ticket);
 
 // grade: C = brow * Ainv (ld ldb), gamma/argmax per row
 void launch_grade(const ActiveSet &as, int precision, const void *brow, int ldb, int64_t n, double *gamma,
@@ -159,7 +174,7 @@ void prepare_split(ActiveSet &as, hipStream_t st);
 int split_terms();
 void launch_invert(ActiveSet &as, const double *A, hipStream_t st, DevBuf &work, int *singular_host);
 void launch_select(const double *gamma, int64_t n, double thr, int32_t *idx, int32_t cap, int32_t *count,
-                   hipStream_t st, DevBuf &work);
+                   hipStream_t st, DevBuf &work, unsigned *ticket);
 void run_maxvol(ActiveSet &as, double *cand, int64_t n_cand, double thr, int max_swaps, int32_t *swap_cand,
                 int32_t *swap_col, int32_t *n_swaps, hipStream_t st, DevBuf &work);
 void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision, void *dst, hipStream_t st);

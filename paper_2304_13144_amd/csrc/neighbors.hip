@@ -16,7 +16,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <type_traits>
 
+#include "device_util.hpp"
 #include "internal.hpp"
 
 namespace mtp {
@@ -35,10 +38,17 @@ __device__ inline double height(const double *H, int k) {
     return vol / sqrt(cx * cx + cy * cy + cz * cz);
 }
 
-// one thread walks all configurations (bin offsets are a running sum)
-__global__ void geo_kernel(int n_cfg, const int64_t *cfg_off, const double *cell, const uint8_t *pbc, double rc,
-                           CfgGeo *geo, int *flags) {
+// Clears the bin counters and fill cursors (all threads) and the status
+// words; thread 0 then walks all configurations (bin offsets are a running
+// sum) and writes their geometry.
+__global__ void nbr_prepare(int n_cfg, const int64_t *cfg_off, const double *cell, const uint8_t *pbc, double rc,
+                            CfgGeo *geo, int *flags, int32_t *bin_count, int32_t *cursor, int64_t bins) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < bins; i += (int64_t)gridDim.x * blockDim.x) {
+        bin_count[i] = 0;
+        cursor[i] = 0;
+    }
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int k = 0; k < 8; ++k) flags[k] = 0;
     long long off = 0;
     for (int c = 0; c < n_cfg; ++c) {
         CfgGeo g;
@@ -115,65 +125,44 @@ __global__ void bin_kernel(int64_t n, int n_cfg, const int64_t *cfg_off, const d
     atomicAdd(&bin_count[bin], 1);
 }
 
-// exclusive scan, three kernels (block scan, scan of block sums, add)
+// Exclusive scan of the bin counts in one launch: each block scans 1024
+// bins, and the last block to finish scans the block totals.  A bin's
+// start is then loc[b] + off[b / 1024] (BinStart).
 constexpr int SCAN_B = 1024;
 
-__global__ void scan_block(const int32_t *in, int32_t *out, int32_t *sums, const int32_t *n_dev) {
+struct BinStart {
+    const int32_t *loc, *off;
+    __device__ int32_t operator[](int64_t b) const { return loc[b] + off[b / SCAN_B]; }
+};
+
+__global__ __launch_bounds__(SCAN_B) void scan_bins(const int32_t *in, int32_t *loc, int32_t *off,
+                                                    const int32_t *n_dev, unsigned *ticket) {
     __shared__ int32_t s[SCAN_B];
     const int64_t n = *n_dev;
     const int64_t i = (int64_t)blockIdx.x * SCAN_B + threadIdx.x;
-    int32_t v = i < n ? in[i] : 0;
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int d = 1; d < SCAN_B; d <<= 1) {
-        int32_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
-        __syncthreads();
-        s[threadIdx.x] += t;
-        __syncthreads();
-    }
-    if (i < n) out[i] = s[threadIdx.x] - v;
-    if (threadIdx.x == SCAN_B - 1) sums[blockIdx.x] = s[threadIdx.x];
-}
-
-__global__ void scan_sums(int32_t *sums, int64_t nb) {
-    // single block; sequential carry over chunks of SCAN_B
-    __shared__ int32_t s[SCAN_B];
-    __shared__ int32_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
+    const int32_t v = i < n ? in[i] : 0;
+    const int32_t inc = block_scan<SCAN_B>(v, s);
+    if (i < n) loc[i] = inc - v;
+    if (threadIdx.x == SCAN_B - 1) off[blockIdx.x] = inc;
+    if (!last_block(ticket)) return;
+    const int64_t nb = gridDim.x;
+    int32_t carry = 0;
     for (int64_t base = 0; base < nb; base += SCAN_B) {
-        const int64_t i = base + threadIdx.x;
-        int32_t v = i < nb ? sums[i] : 0;
-        s[threadIdx.x] = v;
         __syncthreads();
-        for (int d = 1; d < SCAN_B; d <<= 1) {
-            int32_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
-            __syncthreads();
-            s[threadIdx.x] += t;
-            __syncthreads();
-        }
-        if (i < nb) sums[i] = carry + s[threadIdx.x] - v;
-        __syncthreads();
-        if (threadIdx.x == SCAN_B - 1) carry += s[threadIdx.x];
-        __syncthreads();
+        const int64_t k = base + threadIdx.x;
+        const int32_t x = k < nb ? off[k] : 0;
+        const int32_t kinc = block_scan<SCAN_B>(x, s);
+        if (k < nb) off[k] = carry + kinc - x;
+        carry += s[SCAN_B - 1];
     }
+    reset_ticket(ticket);
 }
 
-__global__ void scan_add(int32_t *out, const int32_t *sums, const int32_t *n_dev, int32_t *copy) {
-    const int64_t n = *n_dev;
-    const int64_t i = (int64_t)blockIdx.x * SCAN_B + threadIdx.x;
-    if (i < n) {
-        const int32_t v = out[i] + sums[blockIdx.x];
-        out[i] = v;
-        copy[i] = v;
-    }
-}
-
-__global__ void fill_bins(int64_t n, const int32_t *atom_bin, int32_t *cursor, int32_t *bin_atoms) {
+__global__ void fill_bins(int64_t n, const int32_t *atom_bin, BinStart start, int32_t *cursor, int32_t *bin_atoms) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int slot = atomicAdd(&cursor[atom_bin[i]], 1);
-    bin_atoms[slot] = (int32_t)i;
+    const int32_t b = atom_bin[i];
+    bin_atoms[start[b] + atomicAdd(&cursor[b], 1)] = (int32_t)i;
 }
 
 __device__ inline int pack_q(int x, int y, int z) { return (x + 512) | ((y + 512) << 10) | ((z + 512) << 20); }
@@ -232,13 +221,15 @@ __device__ inline void sort_stage_bin(int32_t *a, int64_t start, int c, int lane
     }
 }
 
-__global__ __launch_bounds__(256) void sort_bins(int32_t *flags, const int32_t *start, const int32_t *count,
+__global__ __launch_bounds__(256) void sort_bins(int32_t *flags, BinStart start, const int32_t *count,
                                                  int32_t *bin_atoms, Stage S) {
     const int lane = threadIdx.x & 63;
     const int64_t nbins = flags[4];
     bool wide = false, bad = false;
-    for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nbins; b += (int64_t)gridDim.x * 4)
-        sort_stage_bin(bin_atoms + start[b], start[b], count[b], lane, S, wide, bad);
+    for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nbins; b += (int64_t)gridDim.x * 4) {
+        const int32_t sb = start[b];
+        sort_stage_bin(bin_atoms + sb, sb, count[b], lane, S, wide, bad);
+    }
     const bool any_wide = __ballot(wide) != 0, any_bad = __ballot(bad) != 0;
     if (lane == 0 && (any_wide || any_bad)) atomicOr(&flags[3], (any_wide ? 2 : 0) | (any_bad ? 8 : 0));
 }
@@ -272,7 +263,7 @@ struct Around {   // the bins around one bin: this lane's bin offset
 };
 
 __device__ inline Around around_bin(const CfgGeo &g, int bx, int by, int bz, int o, int n_off, int lane,
-                                    const int32_t *bin_start, const int32_t *bin_count) {
+                                    const BinStart &bin_start, const int32_t *bin_count) {
     Around A{0, 0, pack_q(0, 0, 0), 0, 0};
     if (o < n_off) {
         const int ox = 2 * g.s[0] + 1, oy = 2 * g.s[1] + 1;
@@ -356,11 +347,12 @@ struct Flags {
 };
 
 // Tests the window's candidates against atom i: bit cc of the returned mask
-// is candidate 64 cc + lane; *tb gets its species (2 bits each).  0 < |r| <
-// R_cut is decided as sqrt(r.r) < R_cut, the square root only evaluated next
-// to the sphere, where comparing squares could differ.
-__device__ inline unsigned test_window(const Window &W, int n, const Centre &c, int lane, double rc, double rc2lo,
-                                       double rc2hi, unsigned &tb, Flags &fl) {
+// is candidate 64 cc + lane; *tb gets its species (2 bits each).  The test
+// 0 < |r| < R_cut is made as r.r <= d2max, d2max being the largest double
+// whose (correctly rounded) square root is below R_cut: the same decision as
+// sqrt(r.r) < R_cut, without the square root.
+__device__ inline unsigned test_window(const Window &W, int n, const Centre &c, int lane, double d2max, unsigned &tb,
+                                       Flags &fl) {
     unsigned in = 0;
     tb = 0;
     for (int cc = 0; cc * 64 < n; ++cc) {
@@ -370,8 +362,7 @@ __device__ inline unsigned test_window(const Window &W, int n, const Centre &c, 
         const double r0 = (W.x[e] - c.y0) + W.qh[o][0], r1 = (W.y[e] - c.y1) + W.qh[o][1],
                      r2 = (W.z[e] - c.y2) + W.qh[o][2];
         const double d2 = r0 * r0 + r1 * r1 + r2 * r2;
-        bool ok = d2 < rc2lo;
-        if (d2 >= rc2lo && d2 < rc2hi) ok = sqrt(d2) < rc;
+        bool ok = d2 <= d2max;
         ok = ok && W.jq[e] != c.i;   // the atom itself (same image)
         if (ok) {
             in |= 1u << cc;
@@ -397,15 +388,10 @@ __device__ inline void count_window(unsigned in, unsigned tb, int n, int n_types
 // this window's pairs of species t; kept if the rank is below cap[t] - run[t].
 // perm_e / perm_k receive (candidate, list offset) for the kept ones; returns
 // how many.  run[] advances by the window's counts.
-template <bool PRE>
 __device__ inline int place_window(unsigned in, unsigned tb, int n, int n_types, int lane, int (&run)[MAX_TYPES],
                                    const int (&cap)[MAX_TYPES], const int (&base)[MAX_TYPES], short *perm_e,
-                                   int *perm_k, int first_o, int (&pre)[MAX_TYPES]) {
-    // PRE: lane o also counts, per species, the accepted candidates before
-    // candidate first_o (the first one of bin offset o)
+                                   int *perm_k) {
     const unsigned long long below = (1ull << lane) - 1ull;
-    const int cc_o = first_o >> 6;
-    const unsigned long long low_o = (1ull << (first_o & 63)) - 1ull;
     int kept = 0;
     for (int cc = 0; cc * 64 < n; ++cc) {
         const bool a = (in >> cc) & 1u;
@@ -424,18 +410,16 @@ __device__ inline int place_window(unsigned in, unsigned tb, int n, int n_types,
             }
             kept += __popcll(km);
             run[s] += __popcll(mk);
-            if (PRE) pre[s] += cc < cc_o ? __popcll(mk) : (cc == cc_o ? __popcll(mk & low_o) : 0);
         }
     }
     return kept;
 }
 
-// consecutive lanes write consecutive kept pairs
-// n_off_rec > 0: record the opposite bin offset n_off_rec - 1 - o in the
-// shift word's top byte (0xff: none)
+// consecutive lanes write consecutive kept pairs (multi-window path: the
+// opposite bin offset is not recorded, 0xff)
 __device__ inline void write_kept(const Window &W, const short *perm_e, const int *perm_k, int kept,
-                                  const Centre &c, int lane, int max_nbrs, int n_off_rec, double *rout,
-                                  int32_t *jout, int32_t *shout, Flags &fl) {
+                                  const Centre &c, int lane, int max_nbrs, double *rout, int32_t *jout,
+                                  int32_t *shout, Flags &fl) {
     for (int a = lane; a < kept; a += 64) {
         const int e = perm_e[a];
         const int64_t slot = (int64_t)c.i * max_nbrs + perm_k[a];
@@ -445,10 +429,69 @@ __device__ inline void write_kept(const Window &W, const short *perm_e, const in
         rout[3 * slot] = (W.x[e] - c.y0) + W.qh[o][0];
         rout[3 * slot + 1] = (W.y[e] - c.y1) + W.qh[o][1];
         rout[3 * slot + 2] = (W.z[e] - c.y2) + W.qh[o][2];
-        const int orev = n_off_rec > 0 ? n_off_rec - 1 - o : 0xff;
         jout[slot] = jq >= 0 ? jq : ~jq;
         if (sh0 < -127 || sh0 > 127 || sh1 < -127 || sh1 > 127 || sh2 < -127 || sh2 > 127) fl.wide = true;
-        shout[slot] = (sh0 & 0xff) | ((sh1 & 0xff) << 8) | ((sh2 & 0xff) << 16) | (orev << 24);
+        shout[slot] = (sh0 & 0xff) | ((sh1 & 0xff) << 8) | ((sh2 & 0xff) << 16) | (0xff << 24);
+    }
+}
+
+// One-window neighborhoods: the list offset base[t] + rank of an accepted
+// candidate is below PS_WIN, so perm is indexed by it directly (no
+// compaction): every offset below the capped total gets exactly one
+// candidate, in candidate order within each species group.
+__device__ inline void place_direct(unsigned in, unsigned tb, int n, int n_types, int lane,
+                                    const int (&cap)[MAX_TYPES], const int (&base)[MAX_TYPES], short *perm) {
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int run[MAX_TYPES] = {0, 0, 0, 0};
+    for (int cc = 0; cc * 64 < n; ++cc) {
+        const bool a = (in >> cc) & 1u;
+        const int t = (tb >> (2 * cc)) & 3;
+        unsigned long long mine = 0ull;
+        int my_run = 0, my_cap = 0, my_base = 0;
+#pragma unroll
+        for (int s = 0; s < MAX_TYPES; ++s) {
+            if (s >= n_types) break;
+            const unsigned long long mk = __ballot(a && t == s);
+            if (t == s) {
+                mine = mk;
+                my_run = run[s];
+                my_cap = cap[s];
+                my_base = base[s];
+            }
+            run[s] += __popcll(mk);
+        }
+        const int k = my_run + __popcll(mine & below);
+        if (a && k < my_cap) perm[my_base + k] = (short)(cc * 64 + lane);
+    }
+}
+
+// entries of perm[0 .. n) (ascending) below key
+__device__ inline int count_below(const short *p, int n, int key) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (p[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// consecutive lanes write list slots 0 .. tot - 1 from perm
+__device__ inline void write_direct(const Window &W, const short *perm, int tot, const Centre &c, int lane,
+                                    int max_nbrs, int n_off, double *rout, int32_t *jout, int32_t *shout,
+                                    Flags &fl) {
+    for (int a = lane; a < tot; a += 64) {
+        const int e = perm[a];
+        const int64_t slot = (int64_t)c.i * max_nbrs + a;
+        const int qt = W.qt[e], jq = W.jq[e];
+        const int sh0 = field(qt, 0) + c.w0, sh1 = field(qt, 1) + c.w1, sh2 = field(qt, 2) + c.w2;
+        const int o = W.lo[e];
+        rout[3 * slot] = (W.x[e] - c.y0) + W.qh[o][0];
+        rout[3 * slot + 1] = (W.y[e] - c.y1) + W.qh[o][1];
+        rout[3 * slot + 2] = (W.z[e] - c.y2) + W.qh[o][2];
+        jout[slot] = jq >= 0 ? jq : ~jq;
+        if (sh0 < -127 || sh0 > 127 || sh1 < -127 || sh1 > 127 || sh2 < -127 || sh2 > 127) fl.wide = true;
+        // top byte: the opposite bin offset (from j's bin to i's), for the reverse-pair search
+        shout[slot] = (sh0 & 0xff) | ((sh1 & 0xff) << 8) | ((sh2 & 0xff) << 16) | ((n_off - 1 - o) << 24);
     }
 }
 
@@ -475,9 +518,9 @@ __device__ inline int from_lane(int v, int k) { return __shfl(v, k, 64); }
 
 // WIDE = false: every bin whose candidates fit one window; the others are
 // appended to wide_list (count in flags[5]) for the WIDE = true launch.
-template <bool WIDE>
-__global__ __launch_bounds__(256) void pair_search(const int32_t *nbins_dev, int n_cfg, int n_types, int max_nbrs,
-                                                   double rc, const CfgGeo *geo, Staged S, const int32_t *bin_start,
+template <bool WIDE, int NT>
+__global__ __launch_bounds__(256) void pair_search(const int32_t *nbins_dev, int n_cfg, int n_types_arg, int max_nbrs,
+                                                   double d2max, const CfgGeo *geo, Staged S, BinStart bin_start,
                                                    const int32_t *bin_count, int32_t *tcnt, double *rout,
                                                    int32_t *jout, int32_t *shout, int32_t *flags,
                                                    int32_t *wide_list, uint16_t *pre_out) {
@@ -486,8 +529,9 @@ __global__ __launch_bounds__(256) void pair_search(const int32_t *nbins_dev, int
     __shared__ int perm_k[4][PS_WIN];
     __shared__ int s_max[4], s_bits[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int n_types = NT;   // species loops unroll to the actual count
+    (void)n_types_arg;
     const int64_t nbins = WIDE ? flags[5] : *nbins_dev;
-    const double rc2lo = rc * rc * (1.0 - 1e-12), rc2hi = rc * rc * (1.0 + 1e-12);
     Flags fl;
     int max_tot = 0;
     for (int64_t it = blockIdx.x; it < nbins; it += gridDim.x) {   // block-uniform
@@ -549,20 +593,22 @@ __global__ __launch_bounds__(256) void pair_search(const int32_t *nbins_dev, int
                 for (int k = 0; k < na; ++k) {
                     const Centre c = centre(k);
                     unsigned tb;
-                    const unsigned in = test_window(W, A0.total, c, lane, rc, rc2lo, rc2hi, tb, fl);
-                    int cnt[MAX_TYPES] = {0, 0, 0, 0}, cap[MAX_TYPES], base[MAX_TYPES], run[MAX_TYPES] = {0, 0, 0, 0};
+                    const unsigned in = test_window(W, A0.total, c, lane, d2max, tb, fl);
+                    int cnt[MAX_TYPES] = {0, 0, 0, 0}, cap[MAX_TYPES], base[MAX_TYPES];
                     int tot;
                     count_window(in, tb, A0.total, n_types, cnt);
                     list_layout(cnt, n_types, max_nbrs, cap, base, tot);
-                    int pre[MAX_TYPES] = {0, 0, 0, 0};
-                    const int kept = place_window<true>(in, tb, A0.total, n_types, lane, run, cap, base,
-                                                        perm_e[wave], perm_k[wave], A0.excl, pre);
-                    for (int t = 0; t < n_types; ++t)
-                        pre_out[((int64_t)c.i * n_types + t) * 64 + lane] = (uint16_t)pre[t];
+                    place_direct(in, tb, A0.total, n_types, lane, cap, base, perm_e[wave]);
+                    const int kept = tot < max_nbrs ? tot : max_nbrs;
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    write_kept(W, perm_e[wave], perm_k[wave], kept, c, lane, max_nbrs, n_off, rout, jout, shout, fl);
+                    // lane o: where the run of bin offset o starts in each species group
+#pragma unroll
+                    for (int t = 0; t < n_types; ++t)
+                        pre_out[((int64_t)c.i * n_types + t) * 64 + lane] =
+                            (uint16_t)count_below(perm_e[wave] + base[t], cap[t], A0.excl);
+                    write_direct(W, perm_e[wave], kept, c, lane, max_nbrs, n_off, rout, jout, shout, fl);
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -595,7 +641,7 @@ __global__ __launch_bounds__(256) void pair_search(const int32_t *nbins_dev, int
                             for (int k = 0; k < na; ++k) {
                                 const Centre c = centre(k);
                                 unsigned tb;
-                                const unsigned in = test_window(W, n, c, lane, rc, rc2lo, rc2hi, tb, fl);
+                                const unsigned in = test_window(W, n, c, lane, d2max, tb, fl);
                                 int cnt[MAX_TYPES] = {0, 0, 0, 0};
                                 count_window(in, tb, n, n_types, cnt);
                                 if (pass == 0) {
@@ -610,14 +656,13 @@ __global__ __launch_bounds__(256) void pair_search(const int32_t *nbins_dev, int
                                     cap[t] = from_lane(hcap[t], k);
                                     base[t] = from_lane(hbase[t], k);
                                 }
-                                int pre[MAX_TYPES];
-                                const int kept = place_window<false>(in, tb, n, n_types, lane, run, cap, base,
-                                                                     perm_e[wave], perm_k[wave], 0, pre);
+                                const int kept = place_window(in, tb, n, n_types, lane, run, cap, base, perm_e[wave],
+                                                              perm_k[wave]);
                                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                                 __builtin_amdgcn_wave_barrier();
                                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                                write_kept(W, perm_e[wave], perm_k[wave], kept, c, lane, max_nbrs, 0, rout, jout,
-                                           shout, fl);
+                                write_kept(W, perm_e[wave], perm_k[wave], kept, c, lane, max_nbrs, rout, jout, shout,
+                                           fl);
                                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                                 __builtin_amdgcn_wave_barrier();
                                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -743,43 +788,54 @@ void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_
     nb->pre.ensure(sizeof(uint16_t) * 64 * (n * nt > 0 ? n * nt : 1));
     nb->flags.ensure(sizeof(int32_t) * 8);
     nb->bins_cap = bins;
-    launch_zero(nb->flags.ptr, sizeof(int32_t) * 8, st);
-    launch_zero(nb->bin_count.ptr, sizeof(int32_t) * bins, st);
-    if (n == 0) return;
+    unsigned *ticket = ticket_buf(nb->tickets, st);
     auto *geo = nb->cfg_geo.as<CfgGeo>();
     int32_t *flags = nb->flags.as<int32_t>();
-    hipLaunchKernelGGL(geo_kernel, dim3(1), dim3(64), 0, st, s->n_cfg, s->cfg_off, s->cell, s->pbc, m->r_cut, geo,
-                       flags);
     const int TB = 256;
+    hipLaunchKernelGGL(nbr_prepare, dim3((unsigned)std::min<int64_t>((bins + TB - 1) / TB, 1024)), dim3(TB), 0, st,
+                       s->n_cfg, s->cfg_off, s->cell, s->pbc, m->r_cut, geo, flags, nb->bin_count.as<int32_t>(),
+                       nb->bin_cursor.as<int32_t>(), bins);
+    if (n == 0) return;
     const dim3 ga((unsigned)((n + TB - 1) / TB));
     hipLaunchKernelGGL(bin_kernel, ga, dim3(TB), 0, st, n, s->n_cfg, s->cfg_off, s->pos, geo,
                        nb->atom_cfg.as<int32_t>(), nb->atom_bin.as<int32_t>(), nb->atom_wrap.as<int32_t>(),
                        nb->bin_count.as<int32_t>());
-    hipLaunchKernelGGL(scan_block, dim3((unsigned)nscan), dim3(SCAN_B), 0, st, nb->bin_count.as<int32_t>(),
-                       nb->bin_start.as<int32_t>(), nb->work_sums.as<int32_t>(), flags + 4);
-    hipLaunchKernelGGL(scan_sums, dim3(1), dim3(SCAN_B), 0, st, nb->work_sums.as<int32_t>(), nscan);
-    hipLaunchKernelGGL(scan_add, dim3((unsigned)nscan), dim3(SCAN_B), 0, st, nb->bin_start.as<int32_t>(),
-                       nb->work_sums.as<int32_t>(), flags + 4, nb->bin_cursor.as<int32_t>());
-    hipLaunchKernelGGL(fill_bins, ga, dim3(TB), 0, st, n, nb->atom_bin.as<int32_t>(), nb->bin_cursor.as<int32_t>(),
-                       nb->bin_atoms.as<int32_t>());
+    hipLaunchKernelGGL(scan_bins, dim3((unsigned)nscan), dim3(SCAN_B), 0, st, nb->bin_count.as<int32_t>(),
+                       nb->bin_start.as<int32_t>(), nb->work_sums.as<int32_t>(), flags + 4, ticket);
+    const BinStart bstart{nb->bin_start.as<int32_t>(), nb->work_sums.as<int32_t>()};
+    hipLaunchKernelGGL(fill_bins, ga, dim3(TB), 0, st, n, nb->atom_bin.as<int32_t>(), bstart,
+                       nb->bin_cursor.as<int32_t>(), nb->bin_atoms.as<int32_t>());
     Stage sg{s->pos, s->type, nb->atom_cfg.as<int32_t>(), nb->atom_wrap.as<int32_t>(), geo, nt,
              nb->stage_x.as<double>(), nb->stage_w.as<int32_t>(), nb->stage_t.as<int32_t>()};
     const unsigned gbins = (unsigned)std::min<int64_t>((bins + 3) / 4, 2048);
-    hipLaunchKernelGGL(sort_bins, dim3(gbins), dim3(256), 0, st, flags, nb->bin_start.as<int32_t>(),
+    hipLaunchKernelGGL(sort_bins, dim3(gbins), dim3(256), 0, st, flags, bstart,
                        nb->bin_count.as<int32_t>(), nb->bin_atoms.as<int32_t>(), sg);
+    // largest d2 with sqrt(d2) < R_cut (IEEE square roots are correctly rounded, host and device alike)
+    double d2max = m->r_cut * m->r_cut;
+    while (d2max > 0 && std::sqrt(d2max) >= m->r_cut) d2max = std::nextafter(d2max, 0.0);
+    while (std::sqrt(std::nextafter(d2max, INFINITY)) < m->r_cut) d2max = std::nextafter(d2max, INFINITY);
     // bin_cursor is free after fill_bins: it holds the list of bins for the WIDE launch
     const Staged staged{nb->stage_x.as<double>(), nb->stage_w.as<int32_t>(), nb->stage_t.as<int32_t>(),
                         nb->bin_atoms.as<int32_t>()};
-    hipLaunchKernelGGL(pair_search<false>, dim3((unsigned)std::min<int64_t>(bins, 8192)), dim3(256), 0, st,
-                       flags + 4, s->n_cfg, nt, max_nbrs, m->r_cut, geo, staged, nb->bin_start.as<int32_t>(),
-                       nb->bin_count.as<int32_t>(), nb->tcnt.as<int32_t>(), nb->r.as<double>(),
-                       nb->j.as<int32_t>(), nb->shift.as<int32_t>(), flags, nb->bin_cursor.as<int32_t>(),
-                       nb->pre.as<uint16_t>());
-    hipLaunchKernelGGL(pair_search<true>, dim3((unsigned)std::min<int64_t>(bins, 2048)), dim3(256), 0, st,
-                       flags + 4, s->n_cfg, nt, max_nbrs, m->r_cut, geo, staged, nb->bin_start.as<int32_t>(),
-                       nb->bin_count.as<int32_t>(), nb->tcnt.as<int32_t>(), nb->r.as<double>(),
-                       nb->j.as<int32_t>(), nb->shift.as<int32_t>(), flags, nb->bin_cursor.as<int32_t>(),
-                       nb->pre.as<uint16_t>());
+    auto search = [&](auto wide, auto ntc) {
+        constexpr bool W = decltype(wide)::value;
+        constexpr int NTC = decltype(ntc)::value;
+        hipLaunchKernelGGL((pair_search<W, NTC>), dim3((unsigned)std::min<int64_t>(bins, 2048)), dim3(256), 0, st,
+                           flags + 4, s->n_cfg, nt, max_nbrs, d2max, geo, staged, bstart,
+                           nb->bin_count.as<int32_t>(), nb->tcnt.as<int32_t>(), nb->r.as<double>(),
+                           nb->j.as<int32_t>(), nb->shift.as<int32_t>(), flags, nb->bin_cursor.as<int32_t>(),
+                           nb->pre.as<uint16_t>());
+    };
+    auto both = [&](auto ntc) {
+        search(std::false_type{}, ntc);
+        search(std::true_type{}, ntc);
+    };
+    switch (nt) {
+        case 1: both(std::integral_constant<int, 1>{}); break;
+        case 2: both(std::integral_constant<int, 2>{}); break;
+        case 3: both(std::integral_constant<int, 3>{}); break;
+        default: both(std::integral_constant<int, 4>{}); break;
+    }
     hipLaunchKernelGGL(reverse_pairs, dim3((unsigned)((P + TB - 1) / TB)), dim3(TB), 0, st, n, nt, max_nbrs, s->type,
                        nb->tcnt.as<int32_t>(), nb->j.as<int32_t>(), nb->shift.as<int32_t>(), nb->pre.as<uint16_t>(),
                        nb->rev.as<int32_t>(), flags);

@@ -2,6 +2,7 @@
 // configuration energy / stress sums, row copies, preselection compaction.
 #include <hip/hip_runtime.h>
 
+#include "device_util.hpp"
 #include "internal.hpp"
 
 namespace mtp {
@@ -49,10 +50,12 @@ __global__ __launch_bounds__(256) void force_gather(int64_t n, int nt, int maxn,
 
 // E_c = sum_i V_i and S_c = sum_i W_i over the atoms of configuration c
 // (eq. 1) in FP64.  Block (c, s) sums every SUM_S-th chunk of 256 atoms of
-// configuration c; a second kernel adds the SUM_S partials in order.
+// configuration c; the last block to finish adds the SUM_S partials of every
+// configuration in order (deterministic).
 constexpr int SUM_T = 256, SUM_S = 32;
-__global__ __launch_bounds__(SUM_T) void cfg_partial(const int64_t *cfg_off, const double *site_e, const double *vir,
-                                                     double *part) {
+__global__ __launch_bounds__(SUM_T) void cfg_sums(const int64_t *cfg_off, const double *site_e, const double *vir,
+                                                  double *part, int n_cfg, double *energy, double *stress,
+                                                  unsigned *ticket) {
     const int c = blockIdx.x / SUM_S, s = blockIdx.x % SUM_S;
     const int64_t b = cfg_off[c], e = cfg_off[c + 1];
     double acc[10];
@@ -71,19 +74,18 @@ __global__ __launch_bounds__(SUM_T) void cfg_partial(const int64_t *cfg_off, con
         __syncthreads();
     }
     if (threadIdx.x < 10) part[(int64_t)blockIdx.x * 10 + threadIdx.x] = sh[threadIdx.x][0];
-}
-
-__global__ void cfg_final(int n_cfg, const double *part, double *energy, double *stress) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)n_cfg * 10) return;
-    const int c = (int)(t / 10), k = (int)(t % 10);
-    double s = 0.0;
-    for (int q = 0; q < SUM_S; ++q) s += part[((int64_t)c * SUM_S + q) * 10 + k];
-    if (k == 0) {
-        if (energy) energy[c] = s;
-    } else if (stress) {
-        stress[9 * c + k - 1] = s;
+    if (!last_block(ticket)) return;
+    for (int64_t t = threadIdx.x; t < (int64_t)n_cfg * 10; t += SUM_T) {
+        const int cc = (int)(t / 10), k = (int)(t % 10);
+        double v = 0.0;
+        for (int q = 0; q < SUM_S; ++q) v += part[((int64_t)cc * SUM_S + q) * 10 + k];
+        if (k == 0) {
+            if (energy) energy[cc] = v;
+        } else if (stress) {
+            stress[9 * cc + k - 1] = v;
+        }
     }
+    reset_ticket(ticket);
 }
 
 template <typename T>
@@ -94,49 +96,44 @@ __global__ void copy_rows(const T *src, int ldb, int m, int64_t n, T *dst) {
     dst[i] = src[r * ldb + c];
 }
 
-// preselection: indices with gamma > thr in ascending order
+// Preselection: indices with gamma > thr in ascending order, one launch.
+// Each block compacts its SEL_T rows into its own stretch of `stage` and
+// records the count; the last block to finish scans the counts and copies
+// the selected indices out in order (output position -> block by binary
+// search over the prefix).
 constexpr int SEL_T = 256;
-__global__ void sel_count(const double *g, int64_t n, double thr, int32_t *blk) {
+__global__ __launch_bounds__(SEL_T) void select_rows(const double *g, int64_t n, double thr, int32_t *blk,
+                                                     int32_t *stage, int32_t *idx, int32_t cap, int32_t *count,
+                                                     unsigned *ticket) {
     __shared__ int32_t s[SEL_T];
     const int64_t i = (int64_t)blockIdx.x * SEL_T + threadIdx.x;
-    s[threadIdx.x] = (i < n && g[i] > thr) ? 1 : 0;
-    __syncthreads();
-    for (int w = SEL_T / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    const int32_t flag = (i < n && g[i] > thr) ? 1 : 0;
+    const int32_t inc = block_scan<SEL_T>(flag, s);
+    if (flag) stage[(int64_t)blockIdx.x * SEL_T + inc - 1] = (int32_t)i;
+    if (threadIdx.x == SEL_T - 1) blk[blockIdx.x] = inc;
+    if (!last_block(ticket)) return;
+    const int64_t nb = gridDim.x;
+    int32_t carry = 0;
+    for (int64_t base = 0; base < nb; base += SEL_T) {
         __syncthreads();
+        const int64_t k = base + threadIdx.x;
+        const int32_t x = k < nb ? blk[k] : 0;
+        const int32_t kinc = block_scan<SEL_T>(x, s);
+        if (k < nb) blk[k] = carry + kinc - x;
+        carry += s[SEL_T - 1];
     }
-    if (threadIdx.x == 0) blk[blockIdx.x] = s[0];
-}
-
-__global__ void sel_scan(int32_t *blk, int64_t nb, int32_t *count) {
-    if (threadIdx.x != 0) return;
-    int32_t run = 0;
-    for (int64_t b = 0; b < nb; ++b) {
-        const int32_t v = blk[b];
-        blk[b] = run;
-        run += v;
+    __syncthreads();   // blk holds exclusive prefixes for every thread below
+    const int32_t out = carry < cap ? carry : cap;
+    if (threadIdx.x == 0) *count = out;
+    for (int32_t p = threadIdx.x; p < out; p += SEL_T) {
+        int64_t lo = 0, hi = nb - 1;   // last block whose prefix is <= p
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (blk[mid] <= p) lo = mid; else hi = mid - 1;
+        }
+        idx[p] = stage[lo * SEL_T + (p - blk[lo])];
     }
-    *count = run;
-}
-
-__global__ void sel_write(const double *g, int64_t n, double thr, const int32_t *blk, int32_t *idx, int32_t cap,
-                          int32_t *count) {
-    __shared__ int32_t s[SEL_T];
-    const int64_t i = (int64_t)blockIdx.x * SEL_T + threadIdx.x;
-    const int flag = (i < n && g[i] > thr) ? 1 : 0;
-    s[threadIdx.x] = flag;
-    __syncthreads();
-    for (int d = 1; d < SEL_T; d <<= 1) {
-        const int32_t t = (int)threadIdx.x >= d ? s[threadIdx.x - d] : 0;
-        __syncthreads();
-        s[threadIdx.x] += t;
-        __syncthreads();
-    }
-    if (flag) {
-        const int32_t pos = blk[blockIdx.x] + s[threadIdx.x] - 1;
-        if (pos < cap) idx[pos] = (int32_t)i;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && *count > cap) *count = cap;
+    reset_ticket(ticket);
 }
 
 // column sums of the per-neighborhood gradient rows, FP64, fixed order:
@@ -200,13 +197,11 @@ void launch_force_gather(const mtp_nbrs *nb, const void *gbuf, int precision, do
 }
 
 void launch_cfg_sums(const mtp_system *s, const double *site_e, const double *virial, double *energy, double *stress,
-                     hipStream_t st, DevBuf &work) {
+                     hipStream_t st, DevBuf &work, unsigned *ticket) {
     if (s->n_cfg <= 0) return;
     work.ensure(sizeof(double) * 10 * SUM_S * (size_t)s->n_cfg);
-    hipLaunchKernelGGL(cfg_partial, dim3((unsigned)(s->n_cfg * SUM_S)), dim3(SUM_T), 0, st, s->cfg_off, site_e, virial,
-                       work.as<double>());
-    hipLaunchKernelGGL(cfg_final, dim3((unsigned)((s->n_cfg * 10 + 255) / 256)), dim3(256), 0, st, s->n_cfg,
-                       work.as<double>(), energy, stress);
+    hipLaunchKernelGGL(cfg_sums, dim3((unsigned)(s->n_cfg * SUM_S)), dim3(SUM_T), 0, st, s->cfg_off, site_e, virial,
+                       work.as<double>(), s->n_cfg, energy, stress, ticket);
 }
 
 void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision, void *dst, hipStream_t st) {
@@ -222,17 +217,16 @@ void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision,
 }
 
 void launch_select(const double *gamma, int64_t n, double thr, int32_t *idx, int32_t cap, int32_t *count,
-                   hipStream_t st, DevBuf &work) {
+                   hipStream_t st, DevBuf &work, unsigned *ticket) {
     const int64_t nb = (n + SEL_T - 1) / SEL_T;
-    work.ensure(sizeof(int32_t) * (nb > 0 ? nb : 1));
+    work.ensure(sizeof(int32_t) * (nb > 0 ? nb : 1) * (1 + SEL_T));
     if (n == 0) {
         launch_zero(count, sizeof(int32_t), st);
         return;
     }
-    hipLaunchKernelGGL(sel_count, dim3((unsigned)nb), dim3(SEL_T), 0, st, gamma, n, thr, work.as<int32_t>());
-    hipLaunchKernelGGL(sel_scan, dim3(1), dim3(64), 0, st, work.as<int32_t>(), nb, count);
-    hipLaunchKernelGGL(sel_write, dim3((unsigned)nb), dim3(SEL_T), 0, st, gamma, n, thr, work.as<int32_t>(), idx, cap,
-                       count);
+    int32_t *blk = work.as<int32_t>();
+    hipLaunchKernelGGL(select_rows, dim3((unsigned)nb), dim3(SEL_T), 0, st, gamma, n, thr, blk, blk + nb, idx, cap,
+                       count, ticket);
 }
 
 }  // namespace mtp
