@@ -101,10 +101,9 @@ struct mtp_nbrs {
     mtp::DevBuf tcnt;     // [N*n_types] int32 neighbors per species
     mtp::DevBuf atom_cfg; // [N] int32
     mtp::DevBuf cfg_geo;  // per cfg geometry (see neighbors.hip)
-    mtp::DevBuf bin_count, bin_start, bin_cursor, bin_atoms, atom_bin, atom_wrap, work_sums;
+    mtp::DevBuf bin_count, bin_start, bin_cursor, bin_atoms, atom_bin, atom_wrap;
     // atoms in bin order: position wrapped into the cell, packed -wrap, species
     mtp::DevBuf stage_x, stage_w, stage_t;
-    mtp::DevBuf tickets;  // last-block counters
     mtp::DevBuf flags;    // [4] int32: overflow, max count, overlap, spare
     int64_t bins_cap = 0;
 };

@@ -19,7 +19,6 @@
 #include <cmath>
 #include <type_traits>
 
-#include "device_util.hpp"
 #include "internal.hpp"
 
 namespace mtp {
@@ -125,37 +124,58 @@ __global__ void bin_kernel(int64_t n, int n_cfg, const int64_t *cfg_off, const d
     atomicAdd(&bin_count[bin], 1);
 }
 
-// Exclusive scan of the bin counts in one launch: each block scans 1024
-// bins, and the last block to finish scans the block totals.  A bin's
-// start is then loc[b] + off[b / 1024] (BinStart).
-constexpr int SCAN_B = 1024;
+// Exclusive scan of the bin counts (only the bins in use, a few per 10
+// atoms) by one block: chunks of 4096, four per thread, wave scans by
+// shuffles and one LDS step across the 16 wavefronts.
+constexpr int SCAN_T = 1024;
 
 struct BinStart {
-    const int32_t *loc, *off;
-    __device__ int32_t operator[](int64_t b) const { return loc[b] + off[b / SCAN_B]; }
+    const int32_t *loc;
+    __device__ int32_t operator[](int64_t b) const { return loc[b]; }
 };
 
-__global__ __launch_bounds__(SCAN_B) void scan_bins(const int32_t *in, int32_t *loc, int32_t *off,
-                                                    const int32_t *n_dev, unsigned *ticket) {
-    __shared__ int32_t s[SCAN_B];
+__global__ __launch_bounds__(SCAN_T) void scan_bins(const int32_t *in, int32_t *out, const int32_t *n_dev) {
+    __shared__ int32_t wsum[SCAN_T / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t n = *n_dev;
-    const int64_t i = (int64_t)blockIdx.x * SCAN_B + threadIdx.x;
-    const int32_t v = i < n ? in[i] : 0;
-    const int32_t inc = block_scan<SCAN_B>(v, s);
-    if (i < n) loc[i] = inc - v;
-    if (threadIdx.x == SCAN_B - 1) off[blockIdx.x] = inc;
-    if (!last_block(ticket)) return;
-    const int64_t nb = gridDim.x;
     int32_t carry = 0;
-    for (int64_t base = 0; base < nb; base += SCAN_B) {
+    for (int64_t base = 0; base < n; base += 4 * SCAN_T) {
+        const int64_t i0 = base + 4 * (int64_t)threadIdx.x;
+        int32_t v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = i0 + e < n ? in[i0 + e] : 0;
+        const int32_t tot = v[0] + v[1] + v[2] + v[3];
+        int32_t inc = tot;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t t = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += t;
+        }
+        if (lane == 63) wsum[wave] = inc;
         __syncthreads();
-        const int64_t k = base + threadIdx.x;
-        const int32_t x = k < nb ? off[k] : 0;
-        const int32_t kinc = block_scan<SCAN_B>(x, s);
-        if (k < nb) off[k] = carry + kinc - x;
-        carry += s[SCAN_B - 1];
+        if (wave == 0) {
+            int32_t w = lane < SCAN_T / 64 ? wsum[lane] : 0, wi = w;
+#pragma unroll
+            for (int d = 1; d < SCAN_T / 64; d <<= 1) {
+                const int32_t t = __shfl_up(wi, d, 64);
+                if (lane >= d) wi += t;
+            }
+            if (lane < SCAN_T / 64) wsum[lane] = wi - w;   // exclusive over the wavefronts
+        }
+        __syncthreads();
+        int32_t run = carry + wsum[wave] + inc - tot;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (i0 + e < n) out[i0 + e] = run;
+            run += v[e];
+        }
+        // the running total after this chunk: the last thread's value
+        __syncthreads();
+        if (threadIdx.x == SCAN_T - 1) wsum[0] = run;
+        __syncthreads();
+        carry = wsum[0];
+        __syncthreads();
     }
-    reset_ticket(ticket);
 }
 
 __global__ void fill_bins(int64_t n, const int32_t *atom_bin, BinStart start, int32_t *cursor, int32_t *bin_atoms) {
@@ -779,8 +799,6 @@ void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_
     nb->bin_count.ensure(sizeof(int32_t) * bins);
     nb->bin_start.ensure(sizeof(int32_t) * bins);
     nb->bin_cursor.ensure(sizeof(int32_t) * bins);
-    const int64_t nscan = (bins + SCAN_B - 1) / SCAN_B;
-    nb->work_sums.ensure(sizeof(int32_t) * (nscan > 0 ? nscan : 1));
     nb->bin_atoms.ensure(sizeof(int32_t) * (n > 0 ? n : 1));
     nb->stage_x.ensure(sizeof(double) * 3 * (n > 0 ? n : 1));
     nb->stage_w.ensure(sizeof(int32_t) * (n > 0 ? n : 1));
@@ -788,7 +806,6 @@ void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_
     nb->pre.ensure(sizeof(uint16_t) * 64 * (n * nt > 0 ? n * nt : 1));
     nb->flags.ensure(sizeof(int32_t) * 8);
     nb->bins_cap = bins;
-    unsigned *ticket = ticket_buf(nb->tickets, st);
     auto *geo = nb->cfg_geo.as<CfgGeo>();
     int32_t *flags = nb->flags.as<int32_t>();
     const int TB = 256;
@@ -800,9 +817,9 @@ void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_
     hipLaunchKernelGGL(bin_kernel, ga, dim3(TB), 0, st, n, s->n_cfg, s->cfg_off, s->pos, geo,
                        nb->atom_cfg.as<int32_t>(), nb->atom_bin.as<int32_t>(), nb->atom_wrap.as<int32_t>(),
                        nb->bin_count.as<int32_t>());
-    hipLaunchKernelGGL(scan_bins, dim3((unsigned)nscan), dim3(SCAN_B), 0, st, nb->bin_count.as<int32_t>(),
-                       nb->bin_start.as<int32_t>(), nb->work_sums.as<int32_t>(), flags + 4, ticket);
-    const BinStart bstart{nb->bin_start.as<int32_t>(), nb->work_sums.as<int32_t>()};
+    hipLaunchKernelGGL(scan_bins, dim3(1), dim3(SCAN_T), 0, st, nb->bin_count.as<int32_t>(),
+                       nb->bin_start.as<int32_t>(), flags + 4);
+    const BinStart bstart{nb->bin_start.as<int32_t>()};
     hipLaunchKernelGGL(fill_bins, ga, dim3(TB), 0, st, n, nb->atom_bin.as<int32_t>(), bstart,
                        nb->bin_cursor.as<int32_t>(), nb->bin_atoms.as<int32_t>());
     Stage sg{s->pos, s->type, nb->atom_cfg.as<int32_t>(), nb->atom_wrap.as<int32_t>(), geo, nt,
