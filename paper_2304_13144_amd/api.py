@@ -312,16 +312,18 @@ __all__ = ["Model", "Batch", "Neighbors", "energy_forces_stress", "grade", "eval
 
 
 class CapturedStep:
-    """One hot-path step (neighbor build + fused evaluation + preselection)
-    captured once in a HIP graph and replayed.
+    """One hot-path step (neighbor build if `rebuild`, fused evaluation,
+    preselection) captured once in a HIP graph and replayed.
 
     The step must have run eagerly at least once at the same sizes so that
     every library workspace exists (nothing is allocated during capture).
     Outputs live in `self.out` and are overwritten by every replay."""
 
-    def __init__(self, model, batch, nbrs, precision="fp64", mode="full", max_nbrs=64, gamma_save=2.0):
+    def __init__(self, model, batch, nbrs, precision="fp64", mode="full", max_nbrs=64, gamma_save=2.0,
+                 rebuild=True):
         self.model, self.batch, self.nbrs = model, batch, nbrs
         self.args = (precision, mode, max_nbrs, gamma_save)
+        self.rebuild = rebuild
         self.out = evaluate(model, batch, nbrs, precision, mode)
         self._step()                      # eager warm-up: workspaces at their final size
         torch.cuda.synchronize()
@@ -332,7 +334,8 @@ class CapturedStep:
 
     def _step(self):
         precision, mode, max_nbrs, gamma_save = self.args
-        self.nbrs.build(self.model, self.batch, max_nbrs=max_nbrs, check_status=False)
+        if self.rebuild:
+            self.nbrs.build(self.model, self.batch, max_nbrs=max_nbrs, check_status=False)
         evaluate(self.model, self.batch, self.nbrs, precision, mode, out=self.out)
         self.sel = select(self.out["gamma"], gamma_save)
 

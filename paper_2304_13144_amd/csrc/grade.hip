@@ -37,18 +37,19 @@ __device__ inline void better(double v, int c, double &bv, int &bc) {
 
 // FP64: a block of eight wavefronts owns 64 rows; wave w takes rows
 // 16 (w % 4) .. + 16 and one half (w / 4) of each pass of 224 columns (7
-// MFMA column blocks, accumulators in registers).  k runs in chunks of 16,
-// staged through two LDS buffers: while the MFMAs consume one chunk, the
-// next one is in flight from global memory into registers, then stored to
-// the other buffer -- one barrier per chunk.  Two wavefronts per SIMD keep
-// the matrix pipe busy across the barrier.  The two column halves of a row
-// meet in LDS at the end.
-constexpr int GF_ROWS = 64, GF_KC = 16, GF_HALF = 7, GF_CT = 2 * GF_HALF * 16;
+// MFMA column blocks, accumulators in registers).  k runs in chunks of 16
+// through three LDS buffers, fetched two chunks ahead: chunk c + 2 is in
+// flight from global memory into registers while the MFMAs consume chunk c,
+// and chunk c + 1 (fetched one iteration earlier) is stored to its buffer --
+// one barrier per chunk, a full chunk of MFMA work to cover each load.  Two
+// wavefronts per SIMD keep the matrix pipe busy across the barrier.  The two
+// column halves of a row meet in LDS at the end.
+constexpr int GF_ROWS = 64, GF_KC = 16, GF_HALF = 7, GF_CT = 2 * GF_HALF * 16, GF_NBUF = 3;
 __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow, int ldb, int64_t n,
                                                  const double *__restrict__ Ainv, int m, double *gamma,
                                                  int32_t *argmax) {
-    __shared__ double sA[2][GF_ROWS][GF_KC + 1];
-    __shared__ double sB[2][GF_KC][GF_CT];
+    __shared__ double sA[GF_NBUF][GF_ROWS][GF_KC + 1];
+    __shared__ double sB[GF_NBUF][GF_KC][GF_CT];
     __shared__ double s_best[2][GF_ROWS];
     __shared__ int s_idx[2][GF_ROWS];
     const int tid = threadIdx.x;
@@ -60,6 +61,9 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
     double best[4] = {-1.0, -1.0, -1.0, -1.0};
     int bidx[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
     constexpr int RA = GF_ROWS * GF_KC / 512, RB = GF_KC * GF_CT / 512;
+    struct Regs {
+        double a[RA], b[RB];
+    };
     for (int ct0 = 0; ct0 < m; ct0 += GF_CT) {
         const int ncb = min(GF_CT, m - ct0 + 15) / 16;   // column blocks holding real columns
         const int cb0 = half * GF_HALF;
@@ -67,41 +71,35 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
         doublex4 acc[GF_HALF];
 #pragma unroll
         for (int c = 0; c < GF_HALF; ++c) acc[c] = doublex4{0.0, 0.0, 0.0, 0.0};
-        double ra[RA], rb[RB];
-        auto fetch = [&](int k0) {
+        auto fetch = [&](Regs &R, int ch) {
+            const int k0 = ch * GF_KC;
 #pragma unroll
             for (int q = 0; q < RA; ++q) {
                 const int e = tid + 512 * q;
                 const int r = e / GF_KC, k = e % GF_KC;
                 const int64_t row = row0 + r;
-                ra[q] = (row < n && k0 + k < m) ? brow[row * ldb + k0 + k] : 0.0;
+                R.a[q] = (row < n && k0 + k < m) ? brow[row * ldb + k0 + k] : 0.0;
             }
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
                 const int e = tid + 512 * q;
                 const int k = e / GF_CT, c = e % GF_CT;
-                rb[q] = (k0 + k < m && ct0 + c < m) ? Ainv[(int64_t)(k0 + k) * m + ct0 + c] : 0.0;
+                R.b[q] = (k0 + k < m && ct0 + c < m) ? Ainv[(int64_t)(k0 + k) * m + ct0 + c] : 0.0;
             }
         };
-        auto store = [&](int buf) {
+        auto store = [&](const Regs &R, int buf) {
 #pragma unroll
             for (int q = 0; q < RA; ++q) {
                 const int e = tid + 512 * q;
-                sA[buf][e / GF_KC][e % GF_KC] = ra[q];
+                sA[buf][e / GF_KC][e % GF_KC] = R.a[q];
             }
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
                 const int e = tid + 512 * q;
-                sB[buf][e / GF_CT][e % GF_CT] = rb[q];
+                sB[buf][e / GF_CT][e % GF_CT] = R.b[q];
             }
         };
-        __syncthreads();   // the previous pass no longer reads the buffers
-        fetch(0);
-        store(0);
-        __syncthreads();
-        for (int ch = 0; ch < nchunk; ++ch) {
-            const int buf = ch & 1;
-            if (ch + 1 < nchunk) fetch((ch + 1) * GF_KC);
+        auto compute = [&](int buf) {
 #pragma unroll
             for (int kk = 0; kk < GF_KC; kk += 4) {
                 const double av = sA[buf][rg * 16 + lr][kk + lk];
@@ -111,8 +109,23 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
                         acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sB[buf][kk + lk][(cb0 + c) * 16 + lr],
                                                                       acc[c], 0, 0, 0);
             }
-            if (ch + 1 < nchunk) store(buf ^ 1);
+        };
+        // one iteration: fetch chunk ch + 2 into F, compute chunk ch, store chunk ch + 1 (held in S)
+        auto step = [&](int ch, Regs &F, const Regs &S) {
+            if (ch + 2 < nchunk) fetch(F, ch + 2);
+            compute(ch % GF_NBUF);
+            if (ch + 1 < nchunk) store(S, (ch + 1) % GF_NBUF);
             __syncthreads();
+        };
+        Regs R0, R1;
+        __syncthreads();   // the previous pass no longer reads the buffers
+        fetch(R0, 0);
+        if (nchunk > 1) fetch(R1, 1);
+        store(R0, 0);
+        __syncthreads();
+        for (int ch = 0; ch < nchunk; ch += 2) {
+            step(ch, R0, R1);   // R0 (chunk ch, stored) is free: chunk ch + 2 goes there
+            if (ch + 1 < nchunk) step(ch + 1, R1, R0);
         }
 #pragma unroll
         for (int c = 0; c < GF_HALF; ++c) {
