@@ -2,7 +2,8 @@
 
 Steps: compile the basis generator (g++) -> write one contraction header per
 level -> one HIP translation unit per level with the fused kernel
-instantiated for it -> compile every unit with hipcc in parallel -> link.
+instantiated for it (forward and backward, FP64 and FP32: four units per
+level) -> compile every unit with hipcc in parallel -> link.
 
     python -m paper_2304_13144_amd.build [--levels 8,16] [-j 8]
 """
@@ -51,21 +52,30 @@ def generate(levels):
         txt = open(os.path.join(GEN, f"mtp_level{L}.inc")).read()
         flops[L] = sum(int(txt.split(f"FLOPS_{k} = ")[1].split(";")[0]) for k in ("GRAPHS", "TRIE", "REVERSE"))
     units = []
-    for L in levels:
-        path = os.path.join(GEN, f"efs_level{L}.hip")
-        src = (f'#include "efs_kernel.hpp"\n#include "backward_kernel.hpp"\nnamespace mtp {{\n'
-               f'#include "mtp_level{L}.inc"\nMTP_EFS_LEVEL({L})\nMTP_BWD_LEVEL({L})\n}}  // namespace mtp\n')
-        _write_if_changed(path, src)
-        units.append(path)
-    decl = "".join(f"template <> int launch_efs_level<{L}>(const EfsArgs &a);\n"
-                   f"template <> int launch_backward_level<{L}>(const BwdArgs &b);\n" for L in levels)
-    cases = "".join(f"        case {L}: return launch_efs_level<{L}>(a);\n" for L in levels)
-    bcases = "".join(f"        case {L}: return launch_backward_level<{L}>(b);\n" for L in levels)
-    disp = ('#include "internal.hpp"\nnamespace mtp {\ntemplate <int L> int launch_efs_level(const EfsArgs &a);\n'
-            + "template <int L> int launch_backward_level(const BwdArgs &b);\n"
-            + decl + "int launch_efs(int level, const EfsArgs &a) {\n    switch (level) {\n" + cases
+    for L in levels:   # one unit per (level, arithmetic type, forward / backward): they compile in parallel
+        for T, tag in (("double", "f64"), ("float", "f32")):
+            for kind, macro, hdr in (("efs", "MTP_EFS_LEVEL_T", "efs_kernel.hpp"),
+                                     ("bwd", "MTP_BWD_LEVEL_T", "backward_kernel.hpp")):
+                path = os.path.join(GEN, f"{kind}_level{L}_{tag}.hip")
+                src = (f'#include "efs_kernel.hpp"\n#include "backward_kernel.hpp"\nnamespace mtp {{\n'
+                       f'#include "mtp_level{L}.inc"\n{macro}({L}, {T})\n}}  // namespace mtp\n')
+                _write_if_changed(path, src)
+                units.append(path)
+    decl = "".join(f"template <> int launch_efs_level_t<{L}, {T}>(const EfsArgs &a);\n"
+                   f"template <> int launch_backward_level_t<{L}, {T}>(const BwdArgs &b);\n"
+                   for L in levels for T in ("double", "float"))
+    cases = "".join(f"        case {L}: return f64 ? launch_efs_level_t<{L}, double>(a) : launch_efs_level_t<{L}, float>(a);\n"
+                    for L in levels)
+    bcases = "".join(f"        case {L}: return f64 ? launch_backward_level_t<{L}, double>(b) : "
+                     f"launch_backward_level_t<{L}, float>(b);\n" for L in levels)
+    disp = ('#include "internal.hpp"\nnamespace mtp {\n'
+            + "template <int L, typename T> int launch_efs_level_t(const EfsArgs &a);\n"
+            + "template <int L, typename T> int launch_backward_level_t(const BwdArgs &b);\n"
+            + decl + "int launch_efs(int level, const EfsArgs &a) {\n    const bool f64 = a.precision == MTP_FP64;\n"
+            + "    switch (level) {\n" + cases
             + "        default: return -1;\n    }\n}\n"
-            + "int launch_backward(int level, const BwdArgs &b) {\n    switch (level) {\n" + bcases
+            + "int launch_backward(int level, const BwdArgs &b) {\n    const bool f64 = b.e.precision == MTP_FP64;\n"
+            + "    switch (level) {\n" + bcases
             + "        default: return -1;\n    }\n}\nstd::vector<int> compiled_levels() { return {"
             + ", ".join(str(L) for L in levels) + "}; }\nlong contraction_flops(int level) {\n    switch (level) {\n"
             + "".join(f"        case {L}: return {flops[L]};\n" for L in levels)

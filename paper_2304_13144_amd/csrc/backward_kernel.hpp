@@ -304,9 +304,9 @@ __global__ __launch_bounds__(256) void bwd_pairs(const BwdArgs b) {
     }
 }
 
-template <int L> int launch_backward_level(const BwdArgs &b);
+template <int L, typename T> int launch_backward_level_t(const BwdArgs &b);
 
-#define MTP_BWD_LEVEL(LEVEL)                                                                              \
+#define MTP_BWD_LEVEL_T(LEVEL, TT)                                                                        \
     template <typename T, int K> static void launch_bwd_tk##LEVEL(const BwdArgs &b) {                     \
         const int per = 256 / K;                                                                          \
         const unsigned grid = (unsigned)((b.e.n_atoms + per - 1) / per);                                  \
@@ -317,9 +317,8 @@ template <int L> int launch_backward_level(const BwdArgs &b);
         hipLaunchKernelGGL((bwd_contract<T, LEVEL>), dim3(grid1), dim3(256), 0, b.e.stream, b);           \
         hipLaunchKernelGGL((bwd_pairs<T, LEVEL, K>), dim3(grid), dim3(256), 0, b.e.stream, b);            \
     }                                                                                                     \
-    template <> int launch_backward_level<LEVEL>(const BwdArgs &b) {                                      \
-        if (b.e.precision == MTP_FP64) launch_bwd_tk##LEVEL<double, 4>(b);                                \
-        else launch_bwd_tk##LEVEL<float, 4>(b);                                                           \
+    template <> int launch_backward_level_t<LEVEL, TT>(const BwdArgs &b) {                                \
+        launch_bwd_tk##LEVEL<TT, 4>(b);                                                                   \
         return (int)hipGetLastError();                                                                    \
     }
 

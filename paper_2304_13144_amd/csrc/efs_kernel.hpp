@@ -478,10 +478,11 @@ __global__ __launch_bounds__(256) void efs_forces_rows(const EfsArgs a, int64_t 
         efs_rows_body<T, L, K>(a, (int64_t)blockIdx.x - nblk, s_dm);
 }
 
-template <int L> int launch_efs_level(const EfsArgs &a);
+template <int L, typename T> int launch_efs_level_t(const EfsArgs &a);
 
-// instantiates the launchers of one level (used by the generated units)
-#define MTP_EFS_LEVEL(LEVEL)                                                                             \
+// instantiates the launchers of one level and one arithmetic type (each
+// (level, type) pair is a translation unit of its own, generated at build time)
+#define MTP_EFS_LEVEL_T(LEVEL, TT)                                                                       \
     template <typename T, int K, bool WB> static void launch_efs_tk##LEVEL(const EfsArgs &a) {           \
         const int per = 256 / K;                                                                         \
         const unsigned grid = (unsigned)((a.n_atoms + per - 1) / per);                                   \
@@ -508,13 +509,8 @@ template <int L> int launch_efs_level(const EfsArgs &a);
             default: launch_efs_tk##LEVEL<T, 8, WB>(a); break;                                           \
         }                                                                                                \
     }                                                                                                    \
-    template <> int launch_efs_level<LEVEL>(const EfsArgs &a) {                                          \
-        const bool wb = a.brow != nullptr;                                                               \
-        if (a.precision == MTP_FP64) {                                                                   \
-            if (wb) launch_efs_t##LEVEL<double, true>(a); else launch_efs_t##LEVEL<double, false>(a);    \
-        } else {                                                                                         \
-            if (wb) launch_efs_t##LEVEL<float, true>(a); else launch_efs_t##LEVEL<float, false>(a);      \
-        }                                                                                                \
+    template <> int launch_efs_level_t<LEVEL, TT>(const EfsArgs &a) {                                    \
+        if (a.brow != nullptr) launch_efs_t##LEVEL<TT, true>(a); else launch_efs_t##LEVEL<TT, false>(a); \
         return (int)hipGetLastError();                                                                   \
     }
 
