@@ -22,7 +22,7 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 GEN = os.path.join(BUILD, "gen")
 LIB = os.path.join(HERE, "libmtp.so")
 
-DEFAULT_LEVELS = (2, 4, 6, 8, 12, 16)
+DEFAULT_LEVELS = (2, 4, 6, 8, 12, 16, 20)
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wno-unused-result",
@@ -46,7 +46,11 @@ def generate(levels):
     gen_exe = os.path.join(BUILD, "gen_contract")
     _run(["g++", "-O2", "-std=c++17", "-o", gen_exe, os.path.join(CSRC, "gen_contract.cpp"),
           os.path.join(CSRC, "basis.cpp")])
-    _run([gen_exe, GEN] + [str(L) for L in levels])
+    tmp = os.path.join(BUILD, "gen_tmp")
+    os.makedirs(tmp, exist_ok=True)
+    _run([gen_exe, tmp] + [str(L) for L in levels])
+    for f in os.listdir(tmp):   # keep the mtime of unchanged programs (incremental builds)
+        _write_if_changed(os.path.join(GEN, f), open(os.path.join(tmp, f)).read())
     flops = {}
     for L in levels:
         txt = open(os.path.join(GEN, f"mtp_level{L}.inc")).read()
@@ -92,25 +96,39 @@ def _write_if_changed(path, text):
         fh.write(text)
 
 
-def build(levels=DEFAULT_LEVELS, jobs=None, verbose=True):
+def _stale(src, obj, deps_mtime):
+    return not os.path.exists(obj) or os.path.getmtime(obj) < max(os.path.getmtime(src), deps_mtime)
+
+
+def build(levels=DEFAULT_LEVELS, jobs=None, verbose=True, force=True):
+    """force=False recompiles only units older than their source or any
+    header / generated program (development loop); the default rebuilds all."""
     t0 = time.time()
     units, dispatch = generate(levels)
+    deps = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    deps += [os.path.join(GEN, f) for f in os.listdir(GEN) if f.endswith(".inc")]
+    deps += [os.path.join(os.path.dirname(HERE), "include", "mtp.h"), os.path.abspath(__file__)]
+    deps_mtime = max(os.path.getmtime(d) for d in deps)
     objs = []
     jobs_list = []
     for src in [os.path.join(CSRC, s) for s in HOST_SOURCES + HIP_SOURCES] + [dispatch] + units:
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
         objs.append(obj)
-        jobs_list.append([HIPCC] + HIP_FLAGS + ["-c", src, "-o", obj])
+        if force or _stale(src, obj, deps_mtime):
+            jobs_list.append([HIPCC] + HIP_FLAGS + ["-c", src, "-o", obj])
     n = jobs or min(8, os.cpu_count() or 4)
+    # longest units first (the backward units of the highest levels)
+    jobs_list.sort(key=lambda c: ("bwd_level" not in c[-3], -int(''.join(ch for ch in os.path.basename(c[-3]) if ch.isdigit()) or 0)))
     with cf.ThreadPoolExecutor(n) as ex:
-        times = list(ex.map(_run, jobs_list))
+        times = list(ex.map(_run, jobs_list)) or [0.0]
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs)
     os.replace(tmp, LIB)
     if verbose:
-        slow = sorted(zip(times, jobs_list), key=lambda t: -t[0])[:3]
+        slow = sorted(zip(times, jobs_list), key=lambda t: -t[0])[:1]
+        what = f"slowest unit {slow[0][0]:.1f}s: {os.path.basename(slow[0][1][-3])}" if slow else "nothing to compile"
         print(f"[build] libmtp.so with levels {list(levels)} in {time.time() - t0:.1f}s "
-              f"(slowest unit {slow[0][0]:.1f}s: {os.path.basename(slow[0][1][-3])})", flush=True)
+              f"({len(jobs_list)} units compiled, {what})", flush=True)
     return LIB
 
 
@@ -118,8 +136,9 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--levels", default=",".join(str(L) for L in DEFAULT_LEVELS))
     ap.add_argument("-j", type=int, default=None)
+    ap.add_argument("--incremental", action="store_true", help="compile only out-of-date units")
     a = ap.parse_args(argv)
-    build(tuple(int(x) for x in a.levels.split(",")), a.j)
+    build(tuple(int(x) for x in a.levels.split(",")), a.j, force=not a.incremental)
 
 
 if __name__ == "__main__":

@@ -124,9 +124,21 @@ __global__ __launch_bounds__(256) void efs_moments(const EfsArgs a) {
 #pragma unroll
     for (int k = 0; k < NCP; ++k) M[k] = T(0);
     int zj = 0, tend = c.tc[0];
+    // the next pair vector is loaded while the current one is used
+    double nx = 0.0, ny = 0.0, nz = 0.0;
+    if (sub < c.ntot) {
+        nx = c.rp[3 * sub];
+        ny = c.rp[3 * sub + 1];
+        nz = c.rp[3 * sub + 2];
+    }
     for (int p = sub; p < c.ntot; p += K) {
         while (p >= tend && zj < nt - 1) tend += c.tc[++zj];
-        const T x = T(c.rp[3 * p]), y = T(c.rp[3 * p + 1]), z = T(c.rp[3 * p + 2]);
+        const T x = T(nx), y = T(ny), z = T(nz);
+        if (p + K < c.ntot) {
+            nx = c.rp[3 * (p + K)];
+            ny = c.rp[3 * (p + K) + 1];
+            nz = c.rp[3 * (p + K) + 2];
+        }
         const T r = sqrt(x * x + y * y + z * z);
         if (!(r < rc)) continue;
         T fm[NR];
@@ -300,9 +312,22 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
     T *gout = static_cast<T *>(a.gbuf);
     int gstart = 0;
     for (int t = 0; t < nt; ++t) {
-        for (int q = sub; q < tcount(a, c, t); q += K) {
+        const int tc = tcount(a, c, t);
+        // the next pair vector is loaded while the current one is used
+        double nx = 0.0, ny = 0.0, nz = 0.0;
+        if (sub < tc) {
+            nx = c.rp[3 * (gstart + sub)];
+            ny = c.rp[3 * (gstart + sub) + 1];
+            nz = c.rp[3 * (gstart + sub) + 2];
+        }
+        for (int q = sub; q < tc; q += K) {
             const int p = gstart + q;
-            const T x = T(c.rp[3 * p]), y = T(c.rp[3 * p + 1]), z = T(c.rp[3 * p + 2]);
+            const T x = T(nx), y = T(ny), z = T(nz);
+            if (q + K < tc) {
+                nx = c.rp[3 * (p + K)];
+                ny = c.rp[3 * (p + K) + 1];
+                nz = c.rp[3 * (p + K) + 2];
+            }
             const T r = sqrt(x * x + y * y + z * z);
             T g0 = T(0), g1 = T(0), g2 = T(0);
             if (r < rc) {
@@ -369,7 +394,7 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
                 gout[s3 + 2] = g2;
             }
         }
-        gstart += tcount(a, c, t);
+        gstart += tc;
     }
     constexpr int NV = (9 + K - 1) / K * K;
     T vp[NV];
@@ -412,9 +437,21 @@ __device__ inline void efs_rows_body(const EfsArgs &a, int64_t blk, T (&s_dm)[Le
             T dc[ND];
 #pragma unroll
             for (int k = 0; k < ND; ++k) dc[k] = T(0);
-            for (int q = sub; q < tcount(a, c, t); q += K) {
+            const int tc = tcount(a, c, t);
+            double nx = 0.0, ny = 0.0, nz = 0.0;   // next pair vector, in flight
+            if (sub < tc) {
+                nx = c.rp[3 * (gstart + sub)];
+                ny = c.rp[3 * (gstart + sub) + 1];
+                nz = c.rp[3 * (gstart + sub) + 2];
+            }
+            for (int q = sub; q < tc; q += K) {
                 const int p = gstart + q;
-                const T x = T(c.rp[3 * p]), y = T(c.rp[3 * p + 1]), z = T(c.rp[3 * p + 2]);
+                const T x = T(nx), y = T(ny), z = T(nz);
+                if (q + K < tc) {
+                    nx = c.rp[3 * (p + K)];
+                    ny = c.rp[3 * (p + K) + 1];
+                    nz = c.rp[3 * (p + K) + 2];
+                }
                 const T r = sqrt(x * x + y * y + z * z);
                 if (!(r < rc)) continue;
                 const T u = fma(r, xs, x0);
@@ -446,7 +483,7 @@ __device__ inline void efs_rows_body(const EfsArgs &a, int64_t blk, T (&s_dm)[Le
                     if (col >= 0) brow[col] = dc[i];
                 }
             }
-            gstart += tcount(a, c, t);
+            gstart += tc;
         }
     }
     if (brow) {

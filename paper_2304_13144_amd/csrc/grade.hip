@@ -45,11 +45,14 @@ __device__ inline void better(double v, int c, double &bv, int &bc) {
 // wavefronts per SIMD keep the matrix pipe busy across the barrier.  The two
 // column halves of a row meet in LDS at the end.
 constexpr int GF_ROWS = 64, GF_KC = 16, GF_HALF = 7, GF_CT = 2 * GF_HALF * 16, GF_NBUF = 3;
+// B rows padded by 16 doubles: the four k rows one MFMA operand read touches
+// then start 32 banks apart instead of on the same bank
+constexpr int GF_CTP = GF_CT + 16;
 __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow, int ldb, int64_t n,
                                                  const double *__restrict__ Ainv, int m, double *gamma,
                                                  int32_t *argmax) {
     __shared__ double sA[GF_NBUF][GF_ROWS][GF_KC + 1];
-    __shared__ double sB[GF_NBUF][GF_KC][GF_CT];
+    __shared__ double sB[GF_NBUF][GF_KC][GF_CTP];
     __shared__ double s_best[2][GF_ROWS];
     __shared__ int s_idx[2][GF_ROWS];
     const int tid = threadIdx.x;

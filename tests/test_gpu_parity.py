@@ -214,6 +214,33 @@ def test_efs_full_size_workload2_sampled():
         assert np.abs(g["stress"][0] - g["stress"][0].T).max() <= 1e-8 * np.abs(g["stress"][0]).max()
 
 
+@pytest.mark.skipif(20 not in api.compiled_levels(), reason="level 20 not compiled into libmtp.so")
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_efs_level20_three_species_uneven_batch(precision):
+    """Six configurations of the level-20, three-species training workload
+    (uneven sizes, BCC/FCC/HCP, strained, vacancies) in one batch."""
+    w = synth.workload3(n_cfg=6)
+    pot = potential(w)
+    theta = theta_for(3, pot)
+    m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
+    m.set_params(theta)
+    b = api.Batch(w.configs)
+    nb = api.Neighbors().build(m, b, max_nbrs=128)
+    g = {k: v.cpu().numpy() for k, v in api.energy_forces_stress(m, b, nb, precision).items()}
+    off = b.cfg_off_host
+    for k, cfg in enumerate(w.configs):
+        pairs = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, w.r_cut)
+        E, F, S, V = om.energy_forces_stress(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs)
+        Fg = g["forces"][off[k]:off[k + 1]]
+        if precision == "fp64":
+            assert rel_err(g["energy"][k], E) <= FP64_TOL
+            assert rel_err(g["site_e"][off[k]:off[k + 1]], V) <= FP64_TOL
+            assert rel_err(Fg, F) <= FP64_TOL
+            assert rel_err(g["stress"][k], S) <= FP64_TOL
+        else:
+            assert np.abs(Fg - F).max() <= 1e-4
+
+
 def test_efs_fp64_bitwise_deterministic():
     w = synth.workload2(reps=(6, 6, 6))
     pot = potential(w)
