@@ -93,7 +93,7 @@ def recorded_traffic(kernel_substr):
         f = line.strip().strip("`").split()
         if len(f) >= 5 and f[0] == "traffic":
             kv = dict(x.split("=", 1) for x in f[2:] if "=" in x)
-            if f[1] == kernel_substr and kv.get("source") == digest:
+            if f[1] == kernel_substr.replace(" ", "") and kv.get("source") == digest:
                 return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
     return None
 
@@ -120,13 +120,13 @@ def profile_summary(trace_dir, fetch_dir, write_dir, kernels):
         for r in csv.DictReader(open(one(os.path.join(d, "**", "*counter_collection.csv")))):
             if r["Counter_Name"] == name:
                 agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-        return {k: sum(v) / len(v) for k, v in agg.items()}
+        return {k: sum(v) / len(v) for k, v in agg.items()}, {k: max(v) for k, v in agg.items()}
 
-    fetch, write = counter(fetch_dir, "FETCH_SIZE"), counter(write_dir, "WRITE_SIZE")
+    (fetch, fmax), (write, wmax) = counter(fetch_dir, "FETCH_SIZE"), counter(write_dir, "WRITE_SIZE")
     copy = [k for k in fetch if "copyBuffer" in k]
-    big = 256 * 1024.0   # KiB moved each way by the calibration copy
-    cf = big / max(fetch[k] for k in copy) if copy else 1.0
-    cw = big / max(write.get(k, 0.0) for k in copy) if copy else 1.0
+    big = 256 * 1024.0   # KiB moved each way by the calibration copy (its largest dispatch)
+    cf = big / max(fmax[k] for k in copy) if copy else 1.0
+    cw = big / max(wmax.get(k, 0.0) for k in copy) if copy else 1.0
     dur = {r["Name"]: float(r["AverageNs"]) for r in stats}
     out = ["| kernel | calls | avg us | FETCH KiB | WRITE KiB | HBM GB/s (calibrated) |", "|---|---|---|---|---|---|"]
     for r in stats[:24]:
@@ -145,7 +145,7 @@ def profile_summary(trace_dir, fetch_dir, write_dir, kernels):
         if not names:
             continue
         k = names[0]
-        out.append(f"`traffic {sub} fetch_bytes={fetch[k] * cf * 1024:.0f} write_bytes={write.get(k, 0.0) * cw * 1024:.0f} "
+        out.append(f"`traffic {sub.replace(' ', '')} fetch_bytes={fetch[k] * cf * 1024:.0f} write_bytes={write.get(k, 0.0) * cw * 1024:.0f} "
                    f"source={digest} avg_ns={dur.get(k, float('nan')):.0f}`")
     return "\n".join(out)
 
