@@ -255,28 +255,14 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
         e = launch_efs(m->level, a);
     }
     MTP_CHECK(e == 0, MTP_E_HIP, std::string("efs kernel launch: ") + hipGetErrorString((hipError_t)e));
-    // The force gather and the per-configuration sums do not depend on the grade
-    // GEMM: with a grade they run on the model's second stream, concurrently.
-    const bool fork = want_grade && (want_f || o.energy || want_v);
-    hipStream_t sst = st;
-    if (fork) {
-        if (!m->side) {
-            MTP_HIP(hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking));
-            MTP_HIP(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
-            MTP_HIP(hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming));
-        }
-        sst = m->side;
-        MTP_HIP(hipEventRecord(m->ev_fork, st));
-        MTP_HIP(hipStreamWaitEvent(sst, m->ev_fork, 0));
-    }
     if (want_f) {
-        ProfScope ps("force_gather", sst);
-        launch_force_gather(nb, m->gbuf.ptr, prec, o.forces, sst);
+        ProfScope ps("force_gather", st);
+        launch_force_gather(nb, m->gbuf.ptr, prec, o.forces, st);
     }
     if (o.energy || want_v) {
-        ProfScope ps("cfg_sums", sst);
+        ProfScope ps("cfg_sums", st);
         launch_cfg_sums(s, o.energy ? site : nullptr, want_v ? m->virial.as<double>() : nullptr, o.energy, o.stress,
-                        sst, m->sums, ticket_buf(m->tickets, sst));
+                        st, m->sums, ticket_buf(m->tickets, st));
     }
     if (want_grade) {
         m->gamma_ws.ensure(sizeof(double) * n);
@@ -285,10 +271,6 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
                      o.argmax, st);
     }
     if (o.b_rows) launch_copy_rows(m->brow.ptr, ldb, mm, n, prec, o.b_rows, st);
-    if (fork) {
-        MTP_HIP(hipEventRecord(m->ev_join, sst));
-        MTP_HIP(hipStreamWaitEvent(st, m->ev_join, 0));
-    }
     MTP_HIP(hipGetLastError());
 }
 

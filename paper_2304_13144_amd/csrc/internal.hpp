@@ -84,19 +84,7 @@ struct mtp_model {
     // scratch of the evaluation path
     mutable mtp::DevBuf gbuf, virial, sitebuf, brow, gamma_ws, argmax_ws, work, sums, mbuf, dmbuf, tbuf, dtbuf, rows;
     mutable mtp::DevBuf tickets;    // last-block counters: [0] configuration sums, [1] preselection
-    // second stream (default priority) for work independent of the grade GEMM,
-    // forked from and joined back into the caller's stream with events
-    mutable hipStream_t side = nullptr;
-    mutable hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int m_of(int mode) const { return mode == MTP_GRADE_FULL ? (int)kept.size() : n_types + basis.n_lin(); }
-    mtp_model() = default;
-    mtp_model(const mtp_model &) = delete;
-    mtp_model &operator=(const mtp_model &) = delete;
-    ~mtp_model() {
-        if (side) (void)hipStreamDestroy(side);
-        if (ev_fork) (void)hipEventDestroy(ev_fork);
-        if (ev_join) (void)hipEventDestroy(ev_join);
-    }
 };
 
 struct mtp_nbrs {
