@@ -355,6 +355,11 @@ def cpu_baseline(cfg, w, theta, keep, A_full, f64, mix, n_centers):
         errs[name] = {"site_e_max_abs": float(np.abs(g["site_e"][atoms] - V[atoms]).max()),
                       "gamma_max_rel": float((np.abs(g["gamma"][atoms] - gam) / np.maximum(1, gam)).max()),
                       "forces_max_abs_eVA": float(np.abs(g["forces"][centers] - F[centers]).max())}
+    # what the FP32 rows alone force on the mixed grade: the oracle's rows rounded
+    # to FP32, graded in FP64; and the conditioning of A that amplifies it
+    g32 = om.grades(rows.astype(np.float32).astype(np.float64), A_full)[0]
+    errs["mixed_gamma_predicted_from_fp32_rows"] = float((np.abs(g32 - gam) / np.maximum(1, gam)).max())
+    errs["kappa_A_column_equilibrated"] = float(np.linalg.cond(A_full / np.abs(A_full).max(axis=0)))
     base = {"value": len(atoms) / dt, "unit": "atom-steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
             "sample": f"{len(atoms)} neighborhoods ({len(centers)} atoms and all their neighbors) of the same "
                       f"16,384-atom configuration: site energies, pair gradients, rows b_i and grades "
