@@ -164,6 +164,9 @@ def main():
                     help="also run a plain 256 MiB device copy (for scaling HBM counters)")
     ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="print a markdown summary of rocprofv3 output and exit")
+    ap.add_argument("--extra-workloads", action="store_true",
+                    help="also time the level-20 training step (512 configurations, forward + backward) and the "
+                         "grades of the 1,048,576-atom active-learning snapshots (adds `extra_workloads`)")
     a = ap.parse_args()
     if a.profile_summary:
         print(profile_summary(*a.profile_summary, kernels=TRAFFIC_KERNELS))
@@ -322,11 +325,65 @@ def main():
         "mixed_speedup_vs_fp64": results["mixed"]["atom_steps_per_s"] / results["fp64"]["atom_steps_per_s"],
         "mixed_vs_fp64": mixed_vs_fp64,
     }
+    if a.extra_workloads:
+        out["extra_workloads"] = extra_workloads(timed)
     if not a.no_cpu_baseline:
         out["cpu_baseline"], out["errors_vs_oracle"] = cpu_baseline(cfg, w, theta, keep, A_full, f64, mix,
                                                                    a.cpu_centers)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def extra_workloads(timed):
+    """The training workload (level 20, 3 species, 512 uneven configurations:
+    loss forward + backward through MTPEnergy) and the active-learning
+    snapshots (level 16, 1,048,576 atoms: grades + preselection gamma > 2, FULL
+    and LINEAR) at their full sizes."""
+    import torch
+
+    from paper_2304_13144_amd import api, synth
+
+    res = {}
+    w = synth.workload3()
+    n_lin = {20: 293}[w.level]
+    n_rad = {20: 5}[w.level]
+    theta = synth.theta_teacher(3, w.n_types, n_lin, n_rad)
+    m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
+    m.set_params(theta)
+    b = api.Batch(w.configs)
+    nb = api.Neighbors().build(m, b, max_nbrs=96)
+    for prec in ("fp64", "mixed"):
+        th = torch.tensor(theta, dtype=torch.float64, device="cuda", requires_grad=True)
+
+        def step():
+            E, F, S = api.MTPEnergy.apply(th, m, b, nb, prec)
+            ((E ** 2).sum() + 0.01 * (F ** 2).sum() + 0.001 * (S ** 2).sum()).backward()
+
+        ms = timed(step)
+        res[f"training_level20_{prec}"] = {"configs": len(w.configs), "atoms": b.n_atoms, "ms_per_step": ms,
+                                           "atom_steps_per_s": b.n_atoms / (ms * 1e-3),
+                                           "step": "E, F, S forward + loss backward to theta"}
+    w5 = synth.workload5()
+    m5 = api.Model.create(w5.level, w5.n_types, w5.r_min, w5.r_cut)
+    m5.set_params(synth.theta_teacher(5, w5.n_types, 92, 4))
+    keep = m5.kept_columns()
+    m5.set_active_set("full", np.load(os.path.join(ROOT, "tests", "golden", "active_w5_full.npy"))[:, keep])
+    m5.set_active_set("linear", np.load(os.path.join(ROOT, "tests", "golden", "active_w5_linear.npy")))
+    for k in (0, 19):
+        cfg = synth.workload5_snapshot(k)
+        b5 = api.Batch([cfg])
+        nb5 = api.Neighbors().build(m5, b5, max_nbrs=64)
+        nbuild = timed(lambda: nb5.build(m5, b5, max_nbrs=64, check_status=False))
+        for mode in ("full", "linear"):
+            def g():
+                o = api.grade(m5, b5, nb5, "fp64", mode)
+                return api.select(o["gamma"], 2.0)
+            ms = timed(g)
+            _, cnt = g()
+            res[f"active_learning_snapshot{k}_{mode}_fp64"] = {
+                "atoms": cfg.n, "ms_per_step": ms, "grades_per_s": cfg.n / (ms * 1e-3),
+                "selected_gamma_gt_2": int(cnt.item()), "neighbor_build_ms": nbuild}
+    return res
 
 
 def cpu_baseline(cfg, w, theta, keep, A_full, f64, mix, n_centers):

@@ -96,20 +96,18 @@ __global__ void copy_rows(const T *src, int ldb, int m, int64_t n, T *dst) {
     dst[i] = src[r * ldb + c];
 }
 
-// Preselection: indices with gamma > thr in ascending order, one launch.
-// Each block compacts its SEL_T rows into its own stretch of `stage` and
-// records the count; the last block to finish scans the counts and copies
-// the selected indices out in order (output position -> block by binary
-// search over the prefix).
+// Preselection: indices with gamma > thr in ascending order, two launches.
+// select_count: each block counts its SEL_T rows; the last block to finish
+// turns the counts into exclusive block offsets and writes the total.
+// select_write: each block ranks its selected rows and writes them from its
+// offset (every block in parallel, however many rows are selected).
 constexpr int SEL_T = 256;
-__global__ __launch_bounds__(SEL_T) void select_rows(const double *g, int64_t n, double thr, int32_t *blk,
-                                                     int32_t *stage, int32_t *idx, int32_t cap, int32_t *count,
-                                                     unsigned *ticket) {
+__global__ __launch_bounds__(SEL_T) void select_count(const double *g, int64_t n, double thr, int32_t *blk,
+                                                      int32_t cap, int32_t *count, unsigned *ticket) {
     __shared__ int32_t s[SEL_T];
     const int64_t i = (int64_t)blockIdx.x * SEL_T + threadIdx.x;
     const int32_t flag = (i < n && g[i] > thr) ? 1 : 0;
     const int32_t inc = block_scan<SEL_T>(flag, s);
-    if (flag) stage[(int64_t)blockIdx.x * SEL_T + inc - 1] = (int32_t)i;
     if (threadIdx.x == SEL_T - 1) blk[blockIdx.x] = inc;
     if (!last_block(ticket)) return;
     const int64_t nb = gridDim.x;
@@ -122,18 +120,20 @@ __global__ __launch_bounds__(SEL_T) void select_rows(const double *g, int64_t n,
         if (k < nb) blk[k] = carry + kinc - x;
         carry += s[SEL_T - 1];
     }
-    __syncthreads();   // blk holds exclusive prefixes for every thread below
-    const int32_t out = carry < cap ? carry : cap;
-    if (threadIdx.x == 0) *count = out;
-    for (int32_t p = threadIdx.x; p < out; p += SEL_T) {
-        int64_t lo = 0, hi = nb - 1;   // last block whose prefix is <= p
-        while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) / 2;
-            if (blk[mid] <= p) lo = mid; else hi = mid - 1;
-        }
-        idx[p] = stage[lo * SEL_T + (p - blk[lo])];
-    }
+    if (threadIdx.x == 0) *count = carry < cap ? carry : cap;
     reset_ticket(ticket);
+}
+
+__global__ __launch_bounds__(SEL_T) void select_write(const double *g, int64_t n, double thr, const int32_t *blk,
+                                                      int32_t *idx, int32_t cap) {
+    __shared__ int32_t s[SEL_T];
+    const int64_t i = (int64_t)blockIdx.x * SEL_T + threadIdx.x;
+    const int32_t flag = (i < n && g[i] > thr) ? 1 : 0;
+    const int32_t inc = block_scan<SEL_T>(flag, s);
+    if (flag) {
+        const int64_t pos = (int64_t)blk[blockIdx.x] + inc - 1;
+        if (pos < cap) idx[pos] = (int32_t)i;
+    }
 }
 
 // column sums of the per-neighborhood gradient rows, FP64, fixed order:
@@ -219,14 +219,14 @@ void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision,
 void launch_select(const double *gamma, int64_t n, double thr, int32_t *idx, int32_t cap, int32_t *count,
                    hipStream_t st, DevBuf &work, unsigned *ticket) {
     const int64_t nb = (n + SEL_T - 1) / SEL_T;
-    work.ensure(sizeof(int32_t) * (nb > 0 ? nb : 1) * (1 + SEL_T));
+    work.ensure(sizeof(int32_t) * (nb > 0 ? nb : 1));
     if (n == 0) {
         launch_zero(count, sizeof(int32_t), st);
         return;
     }
     int32_t *blk = work.as<int32_t>();
-    hipLaunchKernelGGL(select_rows, dim3((unsigned)nb), dim3(SEL_T), 0, st, gamma, n, thr, blk, blk + nb, idx, cap,
-                       count, ticket);
+    hipLaunchKernelGGL(select_count, dim3((unsigned)nb), dim3(SEL_T), 0, st, gamma, n, thr, blk, cap, count, ticket);
+    hipLaunchKernelGGL(select_write, dim3((unsigned)nb), dim3(SEL_T), 0, st, gamma, n, thr, blk, idx, cap);
 }
 
 }  // namespace mtp

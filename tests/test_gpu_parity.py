@@ -376,12 +376,17 @@ def test_maxvol_matches_oracle_swap_sequence():
     assert rel_err(Ainv.cpu().numpy() @ A_or, np.eye(A_or.shape[0])) <= 1e-6
 
 
-def test_select_matches_numpy():
-    g = torch.as_tensor(np.random.default_rng(9).exponential(1.0, 100000)).cuda()
-    idx, cnt = api.select(g, 2.0)
+@pytest.mark.parametrize("n,shift,cap", [(100000, 0.0, None), (1048577, 5.0, None), (300000, 5.0, 1000),
+                                         (7, 0.0, None)])
+def test_select_matches_numpy(n, shift, cap):
+    """Indices with gamma > 2 in ascending order: few, all (past the block
+    size, one more than 2^20), a capacity below the count, a tiny input."""
+    g = torch.as_tensor(np.random.default_rng(9).exponential(1.0, n) + shift).cuda()
+    idx, cnt = api.select(g, 2.0, capacity=cap)
     want = np.nonzero(g.cpu().numpy() > 2.0)[0]
-    assert int(cnt.item()) == len(want)
-    assert np.array_equal(idx[:len(want)].cpu().numpy(), want)
+    k = len(want) if cap is None else min(cap, len(want))
+    assert int(cnt.item()) == k
+    assert np.array_equal(idx[:k].cpu().numpy(), want[:k])
 
 
 def test_singular_active_set_is_reported():
