@@ -158,7 +158,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="form reported as `value`; the other form is timed too")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-centers", type=int, default=1536,
+    ap.add_argument("--cpu-centers", type=int, default=2048,
                     help="oracle sample: this many atoms and all their neighbors (about 10-30 s of host time)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for scaling HBM counters)")
