@@ -194,7 +194,7 @@ def main():
     nbrs = api.Neighbors().build(model, batch, max_nbrs=64)
     count, _, _ = nbrs.export(batch)
     pairs_per_atom = float(count.double().mean().item())
-    outs = {p: api.evaluate(model, batch, nbrs, p, "full") for p in ("fp64", "mixed")}
+    outs = {p: api.evaluate(model, batch, nbrs, p, "full", gamma_save=2.0) for p in ("fp64", "mixed")}
     tuned = {p: api.tune(model, batch, nbrs, p, "full") for p in ("fp64", "mixed")}
     torch.cuda.synchronize()
     log(f"[bench] autotuned lanes per neighborhood: {tuned}")
@@ -206,8 +206,7 @@ def main():
         del src, dst
 
     def eval_step(prec):
-        o = api.evaluate(model, batch, nbrs, prec, "full", out=outs[prec])
-        api.select(o["gamma"], 2.0)
+        api.evaluate(model, batch, nbrs, prec, "full", out=outs[prec], gamma_save=2.0)
 
     def full_step(prec):
         nbrs.build(model, batch, max_nbrs=64, check_status=False)
@@ -309,7 +308,7 @@ def main():
         "config": {"workload": "fcc-alloy-16x16x16-level16-2species", "atoms": cfg.n, "level": level,
                    "n_types": n_types, "r_cut": w.r_cut, "grade_mode": "full", "m": m,
                    "pairs_per_atom": pairs_per_atom,
-                   "step": "evaluate(E, F, S, site energies, b rows, gamma, argmax) + select(gamma > 2) "
+                   "step": "evaluate(E, F, S, site energies, b rows, gamma, argmax) + preselection gamma > 2 (fused) "
                            "on a built neighbor list",
                    "lanes_per_neighborhood": tuned[prec]},
         "with_rebuild": {"atom_steps_per_s": r["with_rebuild_atom_steps_per_s"],
@@ -375,11 +374,12 @@ def extra_workloads(timed):
         nb5 = api.Neighbors().build(m5, b5, max_nbrs=64)
         nbuild = timed(lambda: nb5.build(m5, b5, max_nbrs=64, check_status=False))
         for mode in ("full", "linear"):
+            o5 = {"gamma": torch.empty(cfg.n, dtype=torch.float64, device=b5.device)}
+
             def g():
-                o = api.grade(m5, b5, nb5, "fp64", mode)
-                return api.select(o["gamma"], 2.0)
+                return api.evaluate(m5, b5, nb5, "fp64", mode, out=o5, gamma_save=2.0)
             ms = timed(g)
-            _, cnt = g()
+            cnt = g()["sel_count"]
             res[f"active_learning_snapshot{k}_{mode}_fp64"] = {
                 "atoms": cfg.n, "ms_per_step": ms, "grades_per_s": cfg.n / (ms * 1e-3),
                 "selected_gamma_gt_2": int(cnt.item()), "neighbor_build_ms": nbuild}

@@ -182,6 +182,18 @@ int mtp_evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mt
                  double *energy, double *forces, double *stress, double *site_e, double *gamma, int32_t *argmax,
                  void *stream);
 
+/* mtp_evaluate followed by the preselection of mtp_select (Sec. II.E) on the
+ * grades just computed: idx [capacity] receives the i with gamma_i >
+ * threshold in ascending order and *count (device int32) their number, at
+ * most `capacity`.  The grade kernel counts the selected rows of each block
+ * of rows as it writes gamma, so only the placement remains (one launch
+ * instead of mtp_select's two).  gamma may be NULL (grades kept internally);
+ * needs the active set of `g`.  idx and count must not be NULL. */
+int mtp_evaluate_select(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p,
+                        mtp_grade_mode g, double *energy, double *forces, double *stress, double *site_e,
+                        double *gamma, int32_t *argmax, double threshold, int32_t *idx, int32_t capacity,
+                        int32_t *count, void *stream);
+
 /* FP64 rows b_i of the listed atoms only ([n_idx*m] row-major), e.g. the
  * candidates preselected by mtp_select for MaxVol. */
 int mtp_b_rows(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_grade_mode g, const int32_t *idx,

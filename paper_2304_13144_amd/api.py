@@ -203,8 +203,11 @@ def grade(model, batch, nbrs, precision="fp64", mode="full", rows=False):
     return {"gamma": g, "argmax": am, "rows": b}
 
 
-def evaluate(model, batch, nbrs, precision="fp64", mode="full", out=None):
-    """Fused energy, forces, stress, site energies and grades; `out` reuses tensors."""
+def evaluate(model, batch, nbrs, precision="fp64", mode="full", out=None, gamma_save=None, capacity=None):
+    """Fused energy, forces, stress, site energies and grades; `out` reuses tensors.
+
+    With `gamma_save`, the preselection (gamma > gamma_save) runs in the same
+    call: out["sel_idx"] (capacity, default n_atoms) and out["sel_count"]."""
     d = batch.device
     if out is None:
         out = {"energy": _out(batch.n_cfg, torch.float64, d),
@@ -214,9 +217,18 @@ def evaluate(model, batch, nbrs, precision="fp64", mode="full", out=None):
                "gamma": _out(batch.n_atoms, torch.float64, d),
                "argmax": _out(batch.n_atoms, torch.int32, d)}
     s = batch.system()
-    check(_lib.lib().mtp_evaluate(model._h, ctypes.byref(s), nbrs._h, _prec(precision), _mode(mode),
-                                  _p(out.get("energy")), _p(out.get("forces")), _p(out.get("stress")),
-                                  _p(out.get("site_e")), _p(out.get("gamma")), _p(out.get("argmax")), _stream()))
+    common = (model._h, ctypes.byref(s), nbrs._h, _prec(precision), _mode(mode), _p(out.get("energy")),
+              _p(out.get("forces")), _p(out.get("stress")), _p(out.get("site_e")), _p(out.get("gamma")),
+              _p(out.get("argmax")))
+    if gamma_save is None:
+        check(_lib.lib().mtp_evaluate(*common, _stream()))
+        return out
+    cap = batch.n_atoms if capacity is None else capacity
+    if "sel_idx" not in out or out["sel_idx"].numel() < max(cap, 1):
+        out["sel_idx"] = _out(max(cap, 1), torch.int32, d)
+        out["sel_count"] = _out(1, torch.int32, d)
+    check(_lib.lib().mtp_evaluate_select(*common, float(gamma_save), _p(out["sel_idx"]), cap,
+                                         _p(out["sel_count"]), _stream()))
     return out
 
 
@@ -324,7 +336,7 @@ class CapturedStep:
         self.model, self.batch, self.nbrs = model, batch, nbrs
         self.args = (precision, mode, max_nbrs, gamma_save)
         self.rebuild = rebuild
-        self.out = evaluate(model, batch, nbrs, precision, mode)
+        self.out = evaluate(model, batch, nbrs, precision, mode, gamma_save=gamma_save)
         self._step()                      # eager warm-up: workspaces at their final size
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
@@ -336,8 +348,8 @@ class CapturedStep:
         precision, mode, max_nbrs, gamma_save = self.args
         if self.rebuild:
             self.nbrs.build(self.model, self.batch, max_nbrs=max_nbrs, check_status=False)
-        evaluate(self.model, self.batch, self.nbrs, precision, mode, out=self.out)
-        self.sel = select(self.out["gamma"], gamma_save)
+        evaluate(self.model, self.batch, self.nbrs, precision, mode, out=self.out, gamma_save=gamma_save)
+        self.sel = (self.out["sel_idx"], self.out["sel_count"])
 
     def replay(self):
         self.graph.replay()

@@ -188,6 +188,10 @@ struct EvalOut {
     int32_t *argmax = nullptr;
     void *b_rows = nullptr;
     int mode = MTP_GRADE_FULL;
+    // preselection fused into the grade (gamma > sel_thr), or sel_idx NULL
+    double sel_thr = 0.0;
+    int32_t *sel_idx = nullptr, *sel_count = nullptr;
+    int32_t sel_cap = 0;
 };
 
 void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int prec, const EvalOut &o,
@@ -196,7 +200,8 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     check_nbrs(m, s, nb);
     MTP_CHECK(prec == MTP_FP64 || prec == MTP_MIXED, MTP_E_INVAL, "bad precision");
     MTP_CHECK(o.mode == MTP_GRADE_FULL || o.mode == MTP_GRADE_LINEAR, MTP_E_INVAL, "bad grade mode");
-    const bool want_grade = o.gamma || o.argmax;
+    const bool want_sel = o.sel_idx != nullptr;
+    const bool want_grade = o.gamma || o.argmax || want_sel;
     const bool want_rows = want_grade || o.b_rows;
     if (want_grade) MTP_CHECK(m->act[o.mode].valid, MTP_E_INVAL, "no active set for this grade mode");
     MTP_HIP(hipSetDevice(m->device));
@@ -218,6 +223,7 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     if (n == 0) {
         if (o.energy) launch_zero(o.energy, sizeof(double) * s->n_cfg, st);
         if (o.stress) launch_zero(o.stress, sizeof(double) * 9 * s->n_cfg, st);
+        if (want_sel) launch_zero(o.sel_count, sizeof(int32_t), st);
         return;
     }
     EfsArgs a{};
@@ -266,9 +272,20 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     }
     if (want_grade) {
         m->gamma_ws.ensure(sizeof(double) * n);
-        ProfScope ps("grade", st);
-        launch_grade(m->act[o.mode], prec, m->brow.ptr, ldb, n, o.gamma ? o.gamma : m->gamma_ws.as<double>(),
-                     o.argmax, st);
+        double *gam = o.gamma ? o.gamma : m->gamma_ws.as<double>();
+        int32_t *blk = nullptr;
+        if (want_sel) {
+            m->selblk.ensure(sizeof(int32_t) * (size_t)((n + GRADE_ROWS - 1) / GRADE_ROWS + 1));
+            blk = m->selblk.as<int32_t>();
+        }
+        {
+            ProfScope ps("grade", st);
+            launch_grade(m->act[o.mode], prec, m->brow.ptr, ldb, n, gam, o.argmax, st, o.sel_thr, blk);
+        }
+        if (want_sel) {
+            ProfScope ps("select", st);
+            launch_select_write(gam, n, o.sel_thr, blk, o.sel_idx, o.sel_cap, o.sel_count, st);
+        }
     }
     if (o.b_rows) launch_copy_rows(m->brow.ptr, ldb, mm, n, prec, o.b_rows, st);
     MTP_HIP(hipGetLastError());
@@ -607,6 +624,29 @@ int mtp_evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mt
     API_END
 }
 
+int mtp_evaluate_select(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p,
+                        mtp_grade_mode g, double *energy, double *forces, double *stress, double *site_e,
+                        double *gamma, int32_t *argmax, double threshold, int32_t *idx, int32_t capacity,
+                        int32_t *count, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m && idx && count, MTP_E_INVAL, "NULL argument");
+    MTP_CHECK(capacity >= 0, MTP_E_INVAL, "negative capacity");
+    EvalOut o;
+    o.energy = energy;
+    o.forces = forces;
+    o.stress = stress;
+    o.site_e = site_e;
+    o.gamma = gamma;
+    o.argmax = argmax;
+    o.mode = g;
+    o.sel_thr = threshold;
+    o.sel_idx = idx;
+    o.sel_cap = capacity;
+    o.sel_count = count;
+    evaluate(m, s, nb, p, o, S(stream));
+    API_END
+}
+
 int mtp_b_rows(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_grade_mode g, const int32_t *idx,
                int32_t n_idx, double *rows, void *stream) {
     API_BEGIN
@@ -657,9 +697,9 @@ int mtp_select(const double *gamma, int64_t n, double threshold, int32_t *idx, i
     API_BEGIN
     MTP_CHECK(gamma && idx && count, MTP_E_INVAL, "NULL argument");
     MTP_CHECK(n >= 0 && capacity >= 0, MTP_E_INVAL, "negative size");
-    static thread_local DevBuf work, tickets;
+    static thread_local DevBuf work;
     ProfScope ps("select", S(stream));
-    launch_select(gamma, n, threshold, idx, capacity, count, S(stream), work, ticket_buf(tickets, S(stream)));
+    launch_select(gamma, n, threshold, idx, capacity, count, S(stream), work);
     API_END
 }
 

@@ -50,7 +50,7 @@ constexpr int GF_ROWS = 64, GF_KC = 16, GF_HALF = 7, GF_CT = 2 * GF_HALF * 16, G
 constexpr int GF_CTP = GF_CT + 16;
 __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow, int ldb, int64_t n,
                                                  const double *__restrict__ Ainv, int m, double *gamma,
-                                                 int32_t *argmax) {
+                                                 int32_t *argmax, double thr, int32_t *sel_blk) {
     __shared__ double sA[GF_NBUF][GF_ROWS][GF_KC + 1];
     __shared__ double sB[GF_NBUF][GF_KC][GF_CTP];
     __shared__ double s_best[2][GF_ROWS];
@@ -154,12 +154,18 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
             s_idx[half][rg * 16 + lk + 4 * r] = bidx[r];
         }
     __syncthreads();
-    if (tid < GF_ROWS && row0 + tid < n) {
+    if (tid < GF_ROWS) {   // wavefront 0: one row per lane
         double bv = s_best[0][tid];
         int bc = s_idx[0][tid];
         better(s_best[1][tid], s_idx[1][tid], bv, bc);
-        gamma[row0 + tid] = bv;
-        if (argmax) argmax[row0 + tid] = bc;
+        const bool live = row0 + tid < n;
+        if (live) {
+            gamma[row0 + tid] = bv;
+            if (argmax) argmax[row0 + tid] = bc;
+        }
+        // preselection counts (gamma > thr) of this block, for select_write
+        const unsigned long long sel = __ballot(live && bv > thr);
+        if (sel_blk && tid == 0) sel_blk[blockIdx.x] = __popcll(sel);
     }
 }
 
@@ -183,7 +189,7 @@ constexpr int GB_KC = 32, GB_KPAD = GB_KC + 8;   // +8 bf16: 80-byte rows spread
 template <int NS>
 __global__ __launch_bounds__(512) void grade_bf16(const float *__restrict__ brow, int ldb, int64_t n,
                                                   const __bf16 *__restrict__ S, int m, int KP, int CP, double *gamma,
-                                                  int32_t *argmax) {
+                                                  int32_t *argmax, double thr, int32_t *sel_blk) {
     __shared__ __attribute__((aligned(16))) __bf16 sA[2][NS][GF_ROWS][GB_KPAD];
     __shared__ __attribute__((aligned(16))) __bf16 sB[2][NS][GF_CT][GB_KPAD];
     __shared__ double s_best[2][GF_ROWS];
@@ -291,12 +297,18 @@ __global__ __launch_bounds__(512) void grade_bf16(const float *__restrict__ brow
             s_idx[half][rg * 16 + 4 * lk + r] = bidx[r];
         }
     __syncthreads();
-    if (tid < GF_ROWS && row0 + tid < n) {
+    if (tid < GF_ROWS) {   // wavefront 0: one row per lane
         double bv = s_best[0][tid];
         int bc = s_idx[0][tid];
         better(s_best[1][tid], s_idx[1][tid], bv, bc);
-        gamma[row0 + tid] = bv;
-        if (argmax) argmax[row0 + tid] = bc;
+        const bool live = row0 + tid < n;
+        if (live) {
+            gamma[row0 + tid] = bv;
+            if (argmax) argmax[row0 + tid] = bc;
+        }
+        // preselection counts (gamma > thr) of this block, for select_write
+        const unsigned long long sel = __ballot(live && bv > thr);
+        if (sel_blk && tid == 0) sel_blk[blockIdx.x] = __popcll(sel);
     }
 }
 
@@ -536,16 +548,16 @@ void prepare_split(ActiveSet &as, hipStream_t st) {
 }
 
 void launch_grade(const ActiveSet &as, int precision, const void *brow, int ldb, int64_t n, double *gamma,
-                  int32_t *argmax, hipStream_t st) {
+                  int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
     if (n == 0) return;
     const dim3 grid((unsigned)((n + 63) / 64));
     if (precision == MTP_FP64) {
         hipLaunchKernelGGL(grade_f64, grid, dim3(512), 0, st, static_cast<const double *>(brow), ldb, n,
-                           as.Ainv.as<double>(), as.m, gamma, argmax);
+                           as.Ainv.as<double>(), as.m, gamma, argmax, thr, sel_blk);
     } else {
         const int KP = (as.m + 31) / 32 * 32, CP = (as.m + 15) / 16 * 16;
         hipLaunchKernelGGL(grade_bf16<3>, grid, dim3(512), 0, st, static_cast<const float *>(brow), ldb, n,
-                           as.Ainv32.as<__bf16>(), as.m, KP, CP, gamma, argmax);
+                           as.Ainv32.as<__bf16>(), as.m, KP, CP, gamma, argmax, thr, sel_blk);
     }
 }
 

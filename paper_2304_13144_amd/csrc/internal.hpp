@@ -83,7 +83,8 @@ struct mtp_model {
     int tuned_lanes[2][48] = {};    // [precision][floor(log2 n_atoms)] -> lanes per neighborhood, 0 = untuned
     // scratch of the evaluation path
     mutable mtp::DevBuf gbuf, virial, sitebuf, brow, gamma_ws, argmax_ws, work, sums, mbuf, dmbuf, tbuf, dtbuf, rows;
-    mutable mtp::DevBuf tickets;    // last-block counters: [0] configuration sums, [1] preselection
+    mutable mtp::DevBuf tickets;    // last-block counters: [0] configuration sums
+    mutable mtp::DevBuf selblk;     // per-block preselection counts written by the grade kernels
     int m_of(int mode) const { return mode == MTP_GRADE_FULL ? (int)kept.size() : n_types + basis.n_lin(); }
 };
 
@@ -167,13 +168,20 @@ void launch_cfg_sums(const mtp_system *s, const double *site_e, const double *vi
                      double *stress, hipStream_t st, DevBuf &work, unsigned *ticket);
 
 // grade: C = brow * Ainv (ld ldb), gamma/argmax per row
+// thr / sel_blk (nullable): the grade also writes, per block of GRADE_ROWS
+// rows, how many have gamma > thr (input of launch_select_write)
+constexpr int GRADE_ROWS = 64;
 void launch_grade(const ActiveSet &as, int precision, const void *brow, int ldb, int64_t n, double *gamma,
-                  int32_t *argmax, hipStream_t st);
+                  int32_t *argmax, hipStream_t st, double thr = 0.0, int32_t *sel_blk = nullptr);
 void prepare_split(ActiveSet &as, hipStream_t st);
 int split_terms();
 void launch_invert(ActiveSet &as, const double *A, hipStream_t st, DevBuf &work, int *singular_host);
 void launch_select(const double *gamma, int64_t n, double thr, int32_t *idx, int32_t cap, int32_t *count,
-                   hipStream_t st, DevBuf &work, unsigned *ticket);
+                   hipStream_t st, DevBuf &work);
+// the write half of the preselection, given per-GRADE_ROWS-block counts in
+// blk [nb + 1] (overwritten with offsets when nb is large)
+void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *blk, int32_t *idx, int32_t cap,
+                         int32_t *count, hipStream_t st);
 void run_maxvol(ActiveSet &as, double *cand, int64_t n_cand, double thr, int max_swaps, int32_t *swap_cand,
                 int32_t *swap_col, int32_t *n_swaps, hipStream_t st, DevBuf &work);
 void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision, void *dst, hipStream_t st);

@@ -96,43 +96,59 @@ __global__ void copy_rows(const T *src, int ldb, int m, int64_t n, T *dst) {
     dst[i] = src[r * ldb + c];
 }
 
-// Preselection: indices with gamma > thr in ascending order, two launches.
-// select_count: each block counts its SEL_T rows; the last block to finish
-// turns the counts into exclusive block offsets and writes the total.
-// select_write: each block ranks its selected rows and writes them from its
-// offset (every block in parallel, however many rows are selected).
-constexpr int SEL_T = 256;
-__global__ __launch_bounds__(SEL_T) void select_count(const double *g, int64_t n, double thr, int32_t *blk,
-                                                      int32_t cap, int32_t *count, unsigned *ticket) {
-    __shared__ int32_t s[SEL_T];
-    const int64_t i = (int64_t)blockIdx.x * SEL_T + threadIdx.x;
-    const int32_t flag = (i < n && g[i] > thr) ? 1 : 0;
-    const int32_t inc = block_scan<SEL_T>(flag, s);
-    if (threadIdx.x == SEL_T - 1) blk[blockIdx.x] = inc;
-    if (!last_block(ticket)) return;
-    const int64_t nb = gridDim.x;
-    int32_t carry = 0;
-    for (int64_t base = 0; base < nb; base += SEL_T) {
-        __syncthreads();
-        const int64_t k = base + threadIdx.x;
-        const int32_t x = k < nb ? blk[k] : 0;
-        const int32_t kinc = block_scan<SEL_T>(x, s);
-        if (k < nb) blk[k] = carry + kinc - x;
-        carry += s[SEL_T - 1];
-    }
-    if (threadIdx.x == 0) *count = carry < cap ? carry : cap;
-    reset_ticket(ticket);
+// Preselection: indices with gamma > thr in ascending order.  Blocks of
+// GRADE_ROWS rows (one wavefront): select_count writes each block's count
+// (the grade kernels can write the same counts themselves); select_write
+// gives block b the offset sum_{b' < b} count[b'] by summing the counts
+// before it (no cross-block synchronisation), ranks its rows by a ballot and
+// writes them; the block holding the last row writes the total (clamped to
+// the capacity).
+__global__ __launch_bounds__(GRADE_ROWS) void select_count(const double *g, int64_t n, double thr, int32_t *blk) {
+    const int64_t i = (int64_t)blockIdx.x * GRADE_ROWS + threadIdx.x;
+    const unsigned long long sel = __ballot(i < n && g[i] > thr);
+    if (threadIdx.x == 0) blk[blockIdx.x] = __popcll(sel);
 }
 
-__global__ __launch_bounds__(SEL_T) void select_write(const double *g, int64_t n, double thr, const int32_t *blk,
-                                                      int32_t *idx, int32_t cap) {
-    __shared__ int32_t s[SEL_T];
-    const int64_t i = (int64_t)blockIdx.x * SEL_T + threadIdx.x;
-    const int32_t flag = (i < n && g[i] > thr) ? 1 : 0;
-    const int32_t inc = block_scan<SEL_T>(flag, s);
-    if (flag) {
-        const int64_t pos = (int64_t)blk[blockIdx.x] + inc - 1;
-        if (pos < cap) idx[pos] = (int32_t)i;
+// Above SEL_DIRECT_BLOCKS blocks the summing would grow quadratically:
+// select_scan (one block) first turns the counts into exclusive offsets, in
+// place, with the total in blk[nb], and select_write reads its offset.
+constexpr int64_t SEL_DIRECT_BLOCKS = 1024;
+constexpr int SCAN_T = 1024;
+__global__ __launch_bounds__(SCAN_T) void select_scan(int32_t *blk, int64_t nb) {
+    __shared__ int32_t s[SCAN_T];
+    int32_t carry = 0;
+    for (int64_t base = 0; base < nb; base += SCAN_T) {
+        const int64_t k = base + threadIdx.x;
+        const int32_t x = k < nb ? blk[k] : 0;
+        const int32_t inc = block_scan<SCAN_T>(x, s);
+        if (k < nb) blk[k] = carry + inc - x;
+        carry += s[SCAN_T - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) blk[nb] = carry;
+}
+
+template <bool SCANNED>
+__global__ __launch_bounds__(GRADE_ROWS) void select_write(const double *g, int64_t n, double thr,
+                                                           const int32_t *blk, int32_t *idx, int32_t cap,
+                                                           int32_t *count) {
+    const int lane = threadIdx.x;
+    int64_t off = 0;
+    if (SCANNED) {
+        off = blk[blockIdx.x];
+    } else {
+        for (int64_t b = lane; b < blockIdx.x; b += GRADE_ROWS) off += blk[b];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) off += __shfl_xor(off, d, 64);
+    }
+    const int64_t i = (int64_t)blockIdx.x * GRADE_ROWS + lane;
+    const bool flag = i < n && g[i] > thr;
+    const unsigned long long sel = __ballot(flag);
+    const int64_t pos = off + __popcll(sel & ((1ull << lane) - 1ull));
+    if (flag && pos < cap) idx[pos] = (int32_t)i;
+    if (blockIdx.x == gridDim.x - 1 && lane == 0) {
+        const int64_t tot = off + __popcll(sel);
+        *count = (int32_t)(tot < cap ? tot : cap);
     }
 }
 
@@ -216,17 +232,31 @@ void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision,
                            static_cast<float *>(dst));
 }
 
-void launch_select(const double *gamma, int64_t n, double thr, int32_t *idx, int32_t cap, int32_t *count,
-                   hipStream_t st, DevBuf &work, unsigned *ticket) {
-    const int64_t nb = (n + SEL_T - 1) / SEL_T;
-    work.ensure(sizeof(int32_t) * (nb > 0 ? nb : 1));
+void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *blk, int32_t *idx, int32_t cap,
+                         int32_t *count, hipStream_t st) {
     if (n == 0) {
         launch_zero(count, sizeof(int32_t), st);
         return;
     }
-    int32_t *blk = work.as<int32_t>();
-    hipLaunchKernelGGL(select_count, dim3((unsigned)nb), dim3(SEL_T), 0, st, gamma, n, thr, blk, cap, count, ticket);
-    hipLaunchKernelGGL(select_write, dim3((unsigned)nb), dim3(SEL_T), 0, st, gamma, n, thr, blk, idx, cap);
+    const int64_t nb = (n + GRADE_ROWS - 1) / GRADE_ROWS;
+    if (nb <= SEL_DIRECT_BLOCKS) {
+        hipLaunchKernelGGL(select_write<false>, dim3((unsigned)nb), dim3(GRADE_ROWS), 0, st, gamma, n, thr, blk, idx,
+                           cap, count);
+    } else {
+        hipLaunchKernelGGL(select_scan, dim3(1), dim3(SCAN_T), 0, st, blk, nb);
+        hipLaunchKernelGGL(select_write<true>, dim3((unsigned)nb), dim3(GRADE_ROWS), 0, st, gamma, n, thr, blk, idx,
+                           cap, count);
+    }
+}
+
+void launch_select(const double *gamma, int64_t n, double thr, int32_t *idx, int32_t cap, int32_t *count,
+                   hipStream_t st, DevBuf &work) {
+    const int64_t nb = (n + GRADE_ROWS - 1) / GRADE_ROWS;
+    work.ensure(sizeof(int32_t) * (size_t)(nb + 1));
+    if (n > 0)
+        hipLaunchKernelGGL(select_count, dim3((unsigned)nb), dim3(GRADE_ROWS), 0, st, gamma, n, thr,
+                           work.as<int32_t>());
+    launch_select_write(gamma, n, thr, work.as<int32_t>(), idx, cap, count, st);
 }
 
 }  // namespace mtp

@@ -146,4 +146,15 @@ def test_full_size_snapshot_grades_sampled():
         print(f"{mode}: kappa {kappa:.3e}, max gamma {np.abs(g_or).max():.3e}, rel err {err:.3e}, tol {tol:.3e}")
         assert err <= tol
         idx, cnt = api.select(torch.as_tensor(g).cuda(), GAMMA_SAVE)
-        assert int(cnt.item()) == int((g > GAMMA_SAVE).sum())
+        want = np.nonzero(g > GAMMA_SAVE)[0]
+        assert int(cnt.item()) == len(want)
+        assert np.array_equal(idx[:len(want)].cpu().numpy(), want)
+        # the preselection fused into the grade (past 1024 blocks of rows: the
+        # block counts are scanned first), with and without a capacity
+        for cap in (None, 1000):
+            out = api.evaluate(m, b, nb, "fp64", mode, gamma_save=GAMMA_SAVE, capacity=cap,
+                               out={"gamma": torch.empty(cfg.n, dtype=torch.float64, device=b.device)})
+            assert np.array_equal(out["gamma"].cpu().numpy(), g)
+            k = len(want) if cap is None else min(cap, len(want))
+            assert int(out["sel_count"].item()) == k
+            assert np.array_equal(out["sel_idx"][:k].cpu().numpy(), want[:k])

@@ -389,6 +389,32 @@ def test_select_matches_numpy(n, shift, cap):
     assert np.array_equal(idx[:k].cpu().numpy(), want[:k])
 
 
+@pytest.mark.parametrize("precision,reps,q,cap", [("fp64", (16, 16, 16), 0.5, None), ("mixed", (16, 16, 16), 0.9, 100),
+                                                  ("fp64", (5, 4, 3), 0.3, None), ("fp64", (5, 4, 3), 1.0, None)])
+def test_evaluate_select_fused(precision, reps, q, cap):
+    """Preselection fused into the evaluation (per-block counts written by the
+    grade kernel): the grades equal mtp_grade's bit for bit and the indices
+    are those with gamma above the threshold, ascending (a quantile of the
+    grades as threshold; a capacity below the count; a ragged 240-atom cell;
+    nothing selected)."""
+    w = synth.workload2(reps=reps)
+    cfg = w.configs[0]
+    pot = potential(w)
+    theta = theta_for(2, pot)
+    m, _ = _model(w, theta, modes=("full",))
+    b = api.Batch([cfg])
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    g_ref = api.grade(m, b, nb, precision, "full")["gamma"].cpu().numpy()
+    thr = float(np.quantile(g_ref, q))
+    out = api.evaluate(m, b, nb, precision, "full", gamma_save=thr, capacity=cap)
+    g = out["gamma"].cpu().numpy()
+    assert np.array_equal(g, g_ref)
+    want = np.nonzero(g > thr)[0]
+    k = len(want) if cap is None else min(cap, len(want))
+    assert int(out["sel_count"].item()) == k
+    assert np.array_equal(out["sel_idx"][:k].cpu().numpy(), want[:k])
+
+
 def test_singular_active_set_is_reported():
     w = synth.workload1()
     m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
