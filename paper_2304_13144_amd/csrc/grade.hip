@@ -23,6 +23,7 @@ namespace {
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));   // a 16-byte piece, kept in registers
 
 __device__ inline void better(double v, int c, double &bv, int &bc) {
     if (v > bv || (v == bv && c < bc)) {
@@ -36,23 +37,32 @@ __device__ inline void better(double v, int c, double &bv, int &bc) {
 //   f32 16x16x32 bf16: row 4 (l/16) + r, column l % 16
 
 // FP64: a block of eight wavefronts owns 64 rows; wave w takes rows
-// 16 (w % 4) .. + 16 and one half (w / 4) of each pass of 224 columns (7
-// MFMA column blocks, accumulators in registers).  k runs in chunks of 16
-// through three LDS buffers, fetched two chunks ahead: chunk c + 2 is in
-// flight from global memory into registers while the MFMAs consume chunk c,
-// and chunk c + 1 (fetched one iteration earlier) is stored to its buffer --
-// one barrier per chunk, a full chunk of MFMA work to cover each load.  Two
-// wavefronts per SIMD keep the matrix pipe busy across the barrier.  The two
-// column halves of a row meet in LDS at the end.
-constexpr int GF_ROWS = 64, GF_KC = 16, GF_HALF = 7, GF_CT = 2 * GF_HALF * 16, GF_NBUF = 3;
-// B rows padded by 16 doubles: the four k rows one MFMA operand read touches
-// then start 32 banks apart instead of on the same bank
-constexpr int GF_CTP = GF_CT + 16;
+// 16 (w % 4) .. + 16 and one half (w / 4) of each pass of CT = 32 HALF
+// columns (HALF MFMA column blocks, accumulators in registers).  k runs in
+// chunks of 16 through three LDS buffers, fetched two chunks ahead: chunk
+// c + 2 is in flight from global memory into registers while the MFMAs
+// consume chunk c, and chunk c + 1 (fetched one iteration earlier) is stored
+// to its buffer -- one barrier per chunk, a full chunk of MFMA work to cover
+// each load.  Two wavefronts per SIMD keep the matrix pipe busy across the
+// barrier.  The two column halves of a row meet in LDS at the end.
+//
+// The inner loop has no branches: loads read clamped addresses (row n - 1
+// for rows past n, whose results are never written; k rows of A^-1 past m
+// meet the zero padding of the b rows, columns past m are never compared)
+// and every wave runs all HALF column blocks, so the compiler can interleave
+// the LDS reads of the next MFMAs with the current ones.  HALF is chosen per
+// m on the host (the smallest padding of m to passes of 32 HALF columns).
+constexpr int GF_ROWS = 64, GF_KC = 16, GF_NBUF = 3;
+template <int HALF>
 __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow, int ldb, int64_t n,
                                                  const double *__restrict__ Ainv, int m, double *gamma,
                                                  int32_t *argmax, double thr, int32_t *sel_blk) {
+    constexpr int CT = 32 * HALF;
+    // B rows padded by 16 doubles: the four k rows one MFMA operand read
+    // touches then start 32 banks apart instead of on the same bank
+    constexpr int CTP = CT + 16;
     __shared__ double sA[GF_NBUF][GF_ROWS][GF_KC + 1];
-    __shared__ double sB[GF_NBUF][GF_KC][GF_CTP];
+    __shared__ double sB[GF_NBUF][GF_KC][CTP];
     __shared__ double s_best[2][GF_ROWS];
     __shared__ int s_idx[2][GF_ROWS];
     const int tid = threadIdx.x;
@@ -63,31 +73,29 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
     const int nchunk = (m + GF_KC - 1) / GF_KC;
     double best[4] = {-1.0, -1.0, -1.0, -1.0};
     int bidx[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
-    constexpr int RA = GF_ROWS * GF_KC / 512, RB = GF_KC * GF_CT / 512;
+    constexpr int RA = GF_ROWS * GF_KC / 512, RB = GF_KC * CT / 512;
+    static_assert(RA * 512 == GF_ROWS * GF_KC && RB * 512 == GF_KC * CT, "staging must tile the block");
     struct Regs {
         double a[RA], b[RB];
     };
-    for (int ct0 = 0; ct0 < m; ct0 += GF_CT) {
-        const int ncb = min(GF_CT, m - ct0 + 15) / 16;   // column blocks holding real columns
-        const int cb0 = half * GF_HALF;
-        const int my_cb = max(0, min(GF_HALF, ncb - cb0));   // wave-uniform
-        doublex4 acc[GF_HALF];
+    for (int ct0 = 0; ct0 < m; ct0 += CT) {
+        const int cb0 = half * HALF;
+        doublex4 acc[HALF];
 #pragma unroll
-        for (int c = 0; c < GF_HALF; ++c) acc[c] = doublex4{0.0, 0.0, 0.0, 0.0};
+        for (int c = 0; c < HALF; ++c) acc[c] = doublex4{0.0, 0.0, 0.0, 0.0};
         auto fetch = [&](Regs &R, int ch) {
             const int k0 = ch * GF_KC;
 #pragma unroll
             for (int q = 0; q < RA; ++q) {
                 const int e = tid + 512 * q;
-                const int r = e / GF_KC, k = e % GF_KC;
-                const int64_t row = row0 + r;
-                R.a[q] = (row < n && k0 + k < m) ? brow[row * ldb + k0 + k] : 0.0;
+                const int r = e / GF_KC, k = k0 + e % GF_KC;   // k < ldb: the rows are padded with zeros
+                R.a[q] = brow[min(row0 + r, n - 1) * ldb + k];
             }
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
                 const int e = tid + 512 * q;
-                const int k = e / GF_CT, c = e % GF_CT;
-                R.b[q] = (k0 + k < m && ct0 + c < m) ? Ainv[(int64_t)(k0 + k) * m + ct0 + c] : 0.0;
+                const int k = k0 + e / CT, c = ct0 + e % CT;
+                R.b[q] = Ainv[(int64_t)min(k, m - 1) * m + min(c, m - 1)];
             }
         };
         auto store = [&](const Regs &R, int buf) {
@@ -99,7 +107,7 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
                 const int e = tid + 512 * q;
-                sB[buf][e / GF_CT][e % GF_CT] = R.b[q];
+                sB[buf][e / CT][e % CT] = R.b[q];
             }
         };
         auto compute = [&](int buf) {
@@ -107,10 +115,9 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
             for (int kk = 0; kk < GF_KC; kk += 4) {
                 const double av = sA[buf][rg * 16 + lr][kk + lk];
 #pragma unroll
-                for (int c = 0; c < GF_HALF; ++c)
-                    if (c < my_cb)
-                        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sB[buf][kk + lk][(cb0 + c) * 16 + lr],
-                                                                      acc[c], 0, 0, 0);
+                for (int c = 0; c < HALF; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sB[buf][kk + lk][(cb0 + c) * 16 + lr],
+                                                                  acc[c], 0, 0, 0);
             }
         };
         // one iteration: fetch chunk ch + 2 into F, compute chunk ch, store chunk ch + 1 (held in S)
@@ -131,9 +138,9 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
             if (ch + 1 < nchunk) step(ch + 1, R1, R0);
         }
 #pragma unroll
-        for (int c = 0; c < GF_HALF; ++c) {
+        for (int c = 0; c < HALF; ++c) {
             const int col = ct0 + (cb0 + c) * 16 + lr;
-            if (c < my_cb && col < m)
+            if (col < m)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) better(fabs(acc[c][r]), col, best[r], bidx[r]);
         }
@@ -182,16 +189,19 @@ template <int NS> __device__ inline void split_f32(float x, __bf16 (&t)[NS]) {
 // so that 8 consecutive k of one column are one 16-byte load.
 //
 // Block of eight wavefronts, 64 rows; wave w takes rows 16 (w % 4) .. + 16
-// and half w / 4 of each pass of 224 columns.  k runs in chunks of 32 (one
-// MFMA k step) through two LDS buffers: the rows' FP32 chunk is split into
-// its BF16 terms as it is stored, the split A^-1 chunk is copied as is.
+// and half w / 4 of each pass of 32 HALF columns.  k runs in chunks of 32
+// (one MFMA k step) through two LDS buffers: the rows' FP32 chunk is split
+// into its BF16 terms as it is stored, the split A^-1 chunk is copied as is.
+// Branch-free inner loop as in grade_f64 (clamped loads; the split A^-1 is
+// zero past m in k, columns past m are never compared).
 constexpr int GB_KC = 32, GB_KPAD = GB_KC + 8;   // +8 bf16: 80-byte rows spread the LDS banks
-template <int NS>
+template <int NS, int HALF>
 __global__ __launch_bounds__(512) void grade_bf16(const float *__restrict__ brow, int ldb, int64_t n,
                                                   const __bf16 *__restrict__ S, int m, int KP, int CP, double *gamma,
                                                   int32_t *argmax, double thr, int32_t *sel_blk) {
+    constexpr int CT = 32 * HALF;
     __shared__ __attribute__((aligned(16))) __bf16 sA[2][NS][GF_ROWS][GB_KPAD];
-    __shared__ __attribute__((aligned(16))) __bf16 sB[2][NS][GF_CT][GB_KPAD];
+    __shared__ __attribute__((aligned(16))) __bf16 sB[2][NS][CT][GB_KPAD];
     __shared__ double s_best[2][GF_ROWS];
     __shared__ int s_idx[2][GF_ROWS];
     const int tid = threadIdx.x;
@@ -203,31 +213,28 @@ __global__ __launch_bounds__(512) void grade_bf16(const float *__restrict__ brow
     const int nchunk = KP / GB_KC;
     // global -> register staging: A, one float4 per thread (row tid / 8, k 4 (tid % 8));
     // B, 16-byte pieces e = tid + 512 q of (term, column, k group of 8)
-    constexpr int NBP = NS * GF_CT * (GB_KC / 8);
+    constexpr int NBP = NS * CT * (GB_KC / 8);
     constexpr int RB = (NBP + 511) / 512;
     double best[4] = {-1.0, -1.0, -1.0, -1.0};
     int bidx[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
-    for (int ct0 = 0; ct0 < m; ct0 += GF_CT) {
-        const int ncb = min(GF_CT, m - ct0 + 15) / 16;
-        const int cb0 = half * GF_HALF;
-        const int my_cb = max(0, min(GF_HALF, ncb - cb0));
-        floatx4 acc[GF_HALF];
+    for (int ct0 = 0; ct0 < m; ct0 += CT) {
+        const int cb0 = half * HALF;
+        floatx4 acc[HALF];
 #pragma unroll
-        for (int c = 0; c < GF_HALF; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < HALF; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
         float4 ra;
-        uint4 rb[RB];
-        auto fetch = [&](int k0) {
+        u32x4 rb[RB];
+        auto fetch = [&](int ch) {
+            const int k0 = ch * GB_KC;
             const int r = tid >> 3, k = k0 + 4 * (tid & 7);
-            const int64_t row = row0 + r;
-            ra = row < n ? *reinterpret_cast<const float4 *>(brow + row * ldb + k) : float4{0.f, 0.f, 0.f, 0.f};
+            ra = *reinterpret_cast<const float4 *>(brow + min(row0 + r, n - 1) * ldb + k);
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
                 const int e = tid + 512 * q;
-                const int t = e / (GF_CT * 4), rem = e % (GF_CT * 4), c = rem >> 2, kg = rem & 3;
-                const int col = ct0 + c;
-                rb[q] = (e < NBP && col < CP)
-                            ? *reinterpret_cast<const uint4 *>(S + t * term + (int64_t)col * KP + k0 + 8 * kg)
-                            : uint4{0u, 0u, 0u, 0u};
+                const int t = e / (CT * 4), rem = e % (CT * 4), c = rem >> 2, kg = rem & 3;
+                const int col = min(ct0 + c, CP - 1);
+                if (q < RB - 1 || e < NBP)
+                    rb[q] = *reinterpret_cast<const u32x4 *>(S + t * term + (int64_t)col * KP + k0 + 8 * kg);
             }
         };
         auto store = [&](int buf) {
@@ -243,9 +250,9 @@ __global__ __launch_bounds__(512) void grade_bf16(const float *__restrict__ brow
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
                 const int e = tid + 512 * q;
-                if (e < NBP) {
-                    const int t = e / (GF_CT * 4), rem = e % (GF_CT * 4), c = rem >> 2, kg = rem & 3;
-                    *reinterpret_cast<uint4 *>(&sB[buf][t][c][8 * kg]) = rb[q];
+                if (q < RB - 1 || e < NBP) {
+                    const int t = e / (CT * 4), rem = e % (CT * 4), c = rem >> 2, kg = rem & 3;
+                    *reinterpret_cast<u32x4 *>(&sB[buf][t][c][8 * kg]) = rb[q];
                 }
             }
         };
@@ -255,29 +262,27 @@ __global__ __launch_bounds__(512) void grade_bf16(const float *__restrict__ brow
         __syncthreads();
         for (int ch = 0; ch < nchunk; ++ch) {
             const int buf = ch & 1;
-            if (ch + 1 < nchunk) fetch((ch + 1) * GB_KC);
+            if (ch + 1 < nchunk) fetch(ch + 1);
             bf16x8 A[NS];
 #pragma unroll
             for (int s2 = 0; s2 < NS; ++s2) A[s2] = *reinterpret_cast<const bf16x8 *>(&sA[buf][s2][rg * 16 + lr][8 * lk]);
 #pragma unroll
-            for (int c = 0; c < GF_HALF; ++c) {
-                if (c < my_cb) {
+            for (int c = 0; c < HALF; ++c) {
 #pragma unroll
-                    for (int t = 0; t < NS; ++t) {
-                        const bf16x8 B = *reinterpret_cast<const bf16x8 *>(&sB[buf][t][(cb0 + c) * 16 + lr][8 * lk]);
+                for (int t = 0; t < NS; ++t) {
+                    const bf16x8 B = *reinterpret_cast<const bf16x8 *>(&sB[buf][t][(cb0 + c) * 16 + lr][8 * lk]);
 #pragma unroll
-                        for (int s2 = 0; s2 + t < NS; ++s2)
-                            acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s2], B, acc[c], 0, 0, 0);
-                    }
+                    for (int s2 = 0; s2 + t < NS; ++s2)
+                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s2], B, acc[c], 0, 0, 0);
                 }
             }
             if (ch + 1 < nchunk) store(buf ^ 1);
             __syncthreads();
         }
 #pragma unroll
-        for (int c = 0; c < GF_HALF; ++c) {
+        for (int c = 0; c < HALF; ++c) {
             const int col = ct0 + (cb0 + c) * 16 + lr;
-            if (c < my_cb && col < m)
+            if (col < m)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) better((double)fabsf(acc[c][r]), col, best[r], bidx[r]);
         }
@@ -547,17 +552,47 @@ void prepare_split(ActiveSet &as, hipStream_t st) {
                        CP, NS, as.Ainv32.as<__bf16>());
 }
 
-void launch_grade(const ActiveSet &as, int precision, const void *brow, int ldb, int64_t n, double *gamma,
-                  int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
-    if (n == 0) return;
-    const dim3 grid((unsigned)((n + 63) / 64));
+// column blocks per wave (HALF): the pass width 32 HALF that pads m the
+// least, the widest on ties
+static int grade_half(int m) {
+    int best = 7, pad = 1 << 30;
+    for (int h = 7; h >= 1; --h) {
+        const int w = 32 * h, p = (m + w - 1) / w * w;
+        if (p < pad) {
+            pad = p;
+            best = h;
+        }
+    }
+    return best;
+}
+
+template <int HALF>
+static void launch_grade_h(const ActiveSet &as, int precision, const void *brow, int ldb, int64_t n, double *gamma,
+                           int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
+    const dim3 grid((unsigned)((n + GF_ROWS - 1) / GF_ROWS));
     if (precision == MTP_FP64) {
-        hipLaunchKernelGGL(grade_f64, grid, dim3(512), 0, st, static_cast<const double *>(brow), ldb, n,
+        hipLaunchKernelGGL(grade_f64<HALF>, grid, dim3(512), 0, st, static_cast<const double *>(brow), ldb, n,
                            as.Ainv.as<double>(), as.m, gamma, argmax, thr, sel_blk);
     } else {
         const int KP = (as.m + 31) / 32 * 32, CP = (as.m + 15) / 16 * 16;
-        hipLaunchKernelGGL(grade_bf16<3>, grid, dim3(512), 0, st, static_cast<const float *>(brow), ldb, n,
+        hipLaunchKernelGGL((grade_bf16<3, HALF>), grid, dim3(512), 0, st, static_cast<const float *>(brow), ldb, n,
                            as.Ainv32.as<__bf16>(), as.m, KP, CP, gamma, argmax, thr, sel_blk);
+    }
+}
+
+void launch_grade(const ActiveSet &as, int precision, const void *brow, int ldb, int64_t n, double *gamma,
+                  int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
+    static_assert(GRADE_ROWS == GF_ROWS, "preselection blocks are grade blocks");
+    if (n == 0) return;
+    MTP_CHECK(ldb >= (as.m + 31) / 32 * 32, MTP_E_INVAL, "grade: row stride below the padded row length");
+    switch (grade_half(as.m)) {
+        case 1: launch_grade_h<1>(as, precision, brow, ldb, n, gamma, argmax, st, thr, sel_blk); break;
+        case 2: launch_grade_h<2>(as, precision, brow, ldb, n, gamma, argmax, st, thr, sel_blk); break;
+        case 3: launch_grade_h<3>(as, precision, brow, ldb, n, gamma, argmax, st, thr, sel_blk); break;
+        case 4: launch_grade_h<4>(as, precision, brow, ldb, n, gamma, argmax, st, thr, sel_blk); break;
+        case 5: launch_grade_h<5>(as, precision, brow, ldb, n, gamma, argmax, st, thr, sel_blk); break;
+        case 6: launch_grade_h<6>(as, precision, brow, ldb, n, gamma, argmax, st, thr, sel_blk); break;
+        default: launch_grade_h<7>(as, precision, brow, ldb, n, gamma, argmax, st, thr, sel_blk); break;
     }
 }
 
