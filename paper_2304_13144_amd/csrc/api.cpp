@@ -261,14 +261,22 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
         e = launch_efs(m->level, a);
     }
     MTP_CHECK(e == 0, MTP_E_HIP, std::string("efs kernel launch: ") + hipGetErrorString((hipError_t)e));
+    // per-configuration sums: chunk partials (in the force gather when forces
+    // are wanted), then one block per configuration
+    const bool want_sums = o.energy || want_v;
+    const double *sum_e = o.energy ? site : nullptr;
+    const double *sum_v = want_v ? m->virial.as<double>() : nullptr;
+    if (want_sums) m->sums.ensure(cfg_partials_bytes(n));
     if (want_f) {
         ProfScope ps("force_gather", st);
-        launch_force_gather(nb, m->gbuf.ptr, prec, o.forces, st);
+        launch_force_gather(nb, m->gbuf.ptr, prec, o.forces, st, sum_e, sum_v,
+                            want_sums ? m->sums.as<double>() : nullptr);
+    } else if (want_sums) {
+        launch_cfg_partials(n, sum_e, sum_v, m->sums.as<double>(), st);
     }
-    if (o.energy || want_v) {
+    if (want_sums) {
         ProfScope ps("cfg_sums", st);
-        launch_cfg_sums(s, o.energy ? site : nullptr, want_v ? m->virial.as<double>() : nullptr, o.energy, o.stress,
-                        st, m->sums, ticket_buf(m->tickets, st));
+        launch_cfg_final(s, sum_e, sum_v, m->sums.as<double>(), o.energy, o.stress, st);
     }
     if (want_grade) {
         m->gamma_ws.ensure(sizeof(double) * n);

@@ -44,17 +44,6 @@ struct DevBuf {
 
 void launch_zero(void *p, size_t bytes, hipStream_t st);
 
-// Counters for last-block completion (device_util.hpp), zeroed once when
-// first allocated; each use resets its own counter, so no memset is needed
-// per call (nor inside a captured graph).
-inline unsigned *ticket_buf(DevBuf &b, hipStream_t st) {
-    if (!b.ptr) {
-        b.ensure(64 * sizeof(unsigned));
-        launch_zero(b.ptr, 64 * sizeof(unsigned), st);
-    }
-    return b.as<unsigned>();
-}
-
 constexpr int NPOLY = 8;     // Chebyshev polynomials per radial function
 constexpr int MAX_TYPES = 4;
 
@@ -83,7 +72,6 @@ struct mtp_model {
     int tuned_lanes[2][48] = {};    // [precision][floor(log2 n_atoms)] -> lanes per neighborhood, 0 = untuned
     // scratch of the evaluation path
     mutable mtp::DevBuf gbuf, virial, sitebuf, brow, gamma_ws, argmax_ws, work, sums, mbuf, dmbuf, tbuf, dtbuf, rows;
-    mutable mtp::DevBuf tickets;    // last-block counters: [0] configuration sums
     mutable mtp::DevBuf selblk;     // per-block preselection counts written by the grade kernels
     int m_of(int mode) const { return mode == MTP_GRADE_FULL ? (int)kept.size() : n_types + basis.n_lin(); }
 };
@@ -163,9 +151,15 @@ struct ProfScope {
 
 void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_nbrs *nb, hipStream_t st);
 
-void launch_force_gather(const mtp_nbrs *nb, const void *gbuf, int precision, double *forces, hipStream_t st);
-void launch_cfg_sums(const mtp_system *s, const double *site_e, const double *virial, double *energy,
-                     double *stress, hipStream_t st, DevBuf &work, unsigned *ticket);
+// Energy / stress per configuration (eq. 1) in two steps: partial sums over
+// chunks of 32 atoms (written by the force gather when `part` is given, else
+// by launch_cfg_partials), then one block per configuration.
+void launch_force_gather(const mtp_nbrs *nb, const void *gbuf, int precision, double *forces, hipStream_t st,
+                         const double *site_e = nullptr, const double *virial = nullptr, double *part = nullptr);
+size_t cfg_partials_bytes(int64_t n_atoms);
+void launch_cfg_partials(int64_t n, const double *site_e, const double *virial, double *part, hipStream_t st);
+void launch_cfg_final(const mtp_system *s, const double *site_e, const double *virial, const double *part,
+                      double *energy, double *stress, hipStream_t st);
 
 // grade: C = brow * Ainv (ld ldb), gamma/argmax per row
 // thr / sel_blk (nullable): the grade also writes, per block of GRADE_ROWS

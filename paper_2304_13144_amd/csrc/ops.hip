@@ -2,6 +2,8 @@
 // configuration energy / stress sums, row copies, preselection compaction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_util.hpp"
 #include "internal.hpp"
 
@@ -13,14 +15,49 @@ __global__ void zero_kernel(uint32_t *p, size_t n_words) {
     if (i < n_words) p[i] = 0u;
 }
 
+// Partial sums of eq. 1 over chunks of SUM_CHUNK consecutive atoms:
+// part[chunk][0] = sum V_i, part[chunk][1 + k] = sum W_i,k (virial component
+// k), zero where the input is NULL.  Called by a whole block of 256 threads
+// for one chunk: wavefront w takes atoms 8 w .. 8 w + 7 of the chunk, lane l
+// atom l / 8 and the values l % 8 and 8 + l % 8; shuffles add the eight
+// atoms of a wavefront, then the four wavefronts are added in order.
+constexpr int SUM_CHUNK = 32;
+__device__ inline void chunk_partials(int64_t chunk, int64_t n, const double *site_e, const double *vir,
+                                      double *part) {
+    __shared__ double sp[4][10];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, s = lane & 7;
+    const int64_t i = chunk * SUM_CHUNK + 8 * w + (lane >> 3);
+    double v0 = 0.0, v1 = 0.0;   // value s and value 8 + s (0: V_i, 1 + k: W_i,k)
+    if (i < n) {
+        if (s == 0) v0 = site_e ? site_e[i] : 0.0;
+        else v0 = vir ? vir[9 * i + s - 1] : 0.0;
+        if (s < 2) v1 = vir ? vir[9 * i + 7 + s] : 0.0;
+    }
+#pragma unroll
+    for (int o = 8; o < 64; o <<= 1) {
+        v0 += __shfl_xor(v0, o, 64);
+        v1 += __shfl_xor(v1, o, 64);
+    }
+    if (lane < 8) sp[w][lane] = v0;
+    if (lane < 2) sp[w][8 + lane] = v1;
+    __syncthreads();
+    if (threadIdx.x < 10) {
+        const int t = threadIdx.x;
+        part[chunk * 10 + t] = ((sp[0][t] + sp[1][t]) + sp[2][t]) + sp[3][t];
+    }
+}
+
 // F_l = sum_{p in list(l)} (g_p - g_rev(p)): the first sum is -dV_l/dx_l, the
 // second collects dV_i/dx_l over every neighborhood i that holds l (or an
 // image of l).  FG_LANES lanes per atom, a fixed shuffle tree at the end, no
-// atomics: results are bitwise reproducible.
+// atomics: results are bitwise reproducible.  A block holds SUM_CHUNK atoms;
+// with `part` it also writes that chunk's partial energy / virial sums.
 constexpr int FG_LANES = 8;
+static_assert(256 / FG_LANES == SUM_CHUNK, "one force_gather block per sum chunk");
 template <typename T>
 __global__ __launch_bounds__(256) void force_gather(int64_t n, int nt, int maxn, const int32_t *tcnt,
-                                                    const int32_t *rev, const T *g, double *F) {
+                                                    const int32_t *rev, const T *g, double *F, const double *site_e,
+                                                    const double *vir, double *part) {
     const int sub = threadIdx.x % FG_LANES;
     const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / FG_LANES;
     const bool live = i < n;
@@ -46,46 +83,62 @@ __global__ __launch_bounds__(256) void force_gather(int64_t n, int nt, int maxn,
         F[3 * i + 1] = fy;
         F[3 * i + 2] = fz;
     }
+    if (part) chunk_partials(blockIdx.x, n, site_e, vir, part);   // uniform branch
 }
 
-// E_c = sum_i V_i and S_c = sum_i W_i over the atoms of configuration c
-// (eq. 1) in FP64.  Block (c, s) sums every SUM_S-th chunk of 256 atoms of
-// configuration c; the last block to finish adds the SUM_S partials of every
-// configuration in order (deterministic).
-constexpr int SUM_T = 256, SUM_S = 32;
-__global__ __launch_bounds__(SUM_T) void cfg_sums(const int64_t *cfg_off, const double *site_e, const double *vir,
-                                                  double *part, int n_cfg, double *energy, double *stress,
-                                                  unsigned *ticket) {
-    const int c = blockIdx.x / SUM_S, s = blockIdx.x % SUM_S;
+// the chunk partials alone (energy or stress without forces)
+__global__ __launch_bounds__(256) void cfg_partials(int64_t n, const double *site_e, const double *vir,
+                                                    double *part) {
+    chunk_partials(blockIdx.x, n, site_e, vir, part);
+}
+
+// E_c = sum_i V_i and S_c = sum_i W_i over the atoms [b, e) of configuration
+// c (eq. 1), one block per configuration: the partials of the chunks that
+// lie inside [b, e), plus the atoms of the chunks it shares with its
+// neighbors.  Fixed assignment of terms to threads and a fixed reduction
+// tree: deterministic.
+__global__ __launch_bounds__(256) void cfg_final(const int64_t *cfg_off, const double *site_e, const double *vir,
+                                                 const double *part, double *energy, double *stress) {
+    __shared__ double sp[4][10];
+    const int c = blockIdx.x;
     const int64_t b = cfg_off[c], e = cfg_off[c + 1];
+    const int64_t cb = (b + SUM_CHUNK - 1) / SUM_CHUNK, ce = e / SUM_CHUNK;   // whole chunks [cb, ce)
     double acc[10];
+#pragma unroll
     for (int k = 0; k < 10; ++k) acc[k] = 0.0;
-    for (int64_t i = b + (int64_t)s * SUM_T + threadIdx.x; i < e; i += (int64_t)SUM_S * SUM_T) {
+    auto atom = [&](int64_t i) {
         if (site_e) acc[0] += site_e[i];
         if (vir)
+#pragma unroll
             for (int k = 0; k < 9; ++k) acc[1 + k] += vir[9 * i + k];
+    };
+    if (cb < ce) {
+        for (int64_t k = cb + threadIdx.x; k < ce; k += 256)
+#pragma unroll
+            for (int q = 0; q < 10; ++q) acc[q] += part[k * 10 + q];
+        for (int64_t i = b + threadIdx.x; i < cb * SUM_CHUNK; i += 256) atom(i);
+        for (int64_t i = ce * SUM_CHUNK + threadIdx.x; i < e; i += 256) atom(i);
+    } else {
+        for (int64_t i = b + threadIdx.x; i < e; i += 256) atom(i);
     }
-    __shared__ double sh[10][SUM_T];
-    for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] = acc[k];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 10; ++q) sp[w][q] = acc[q];
     __syncthreads();
-    for (int w = SUM_T / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 10) part[(int64_t)blockIdx.x * 10 + threadIdx.x] = sh[threadIdx.x][0];
-    if (!last_block(ticket)) return;
-    for (int64_t t = threadIdx.x; t < (int64_t)n_cfg * 10; t += SUM_T) {
-        const int cc = (int)(t / 10), k = (int)(t % 10);
-        double v = 0.0;
-        for (int q = 0; q < SUM_S; ++q) v += part[((int64_t)cc * SUM_S + q) * 10 + k];
-        if (k == 0) {
-            if (energy) energy[cc] = v;
+    if (threadIdx.x < 10) {
+        const int t = threadIdx.x;
+        const double v = ((sp[0][t] + sp[1][t]) + sp[2][t]) + sp[3][t];
+        if (t == 0) {
+            if (energy) energy[c] = v;
         } else if (stress) {
-            stress[9 * cc + k - 1] = v;
+            stress[9 * c + t - 1] = v;
         }
     }
-    reset_ticket(ticket);
 }
 
 template <typename T>
@@ -200,24 +253,36 @@ void launch_zero(void *p, size_t bytes, hipStream_t st) {
     hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((w + 255) / 256)), dim3(256), 0, st, static_cast<uint32_t *>(p), w);
 }
 
-void launch_force_gather(const mtp_nbrs *nb, const void *gbuf, int precision, double *forces, hipStream_t st) {
+void launch_force_gather(const mtp_nbrs *nb, const void *gbuf, int precision, double *forces, hipStream_t st,
+                         const double *site_e, const double *virial, double *part) {
     const int64_t n = nb->n_atoms;
     if (!n) return;
     const dim3 grid((unsigned)((n * FG_LANES + 255) / 256));
     if (precision == MTP_FP64)
         hipLaunchKernelGGL(force_gather<double>, grid, dim3(256), 0, st, n, nb->n_types, nb->max_nbrs,
-                           nb->tcnt.as<int32_t>(), nb->rev.as<int32_t>(), static_cast<const double *>(gbuf), forces);
+                           nb->tcnt.as<int32_t>(), nb->rev.as<int32_t>(), static_cast<const double *>(gbuf), forces,
+                           site_e, virial, part);
     else
         hipLaunchKernelGGL(force_gather<float>, grid, dim3(256), 0, st, n, nb->n_types, nb->max_nbrs,
-                           nb->tcnt.as<int32_t>(), nb->rev.as<int32_t>(), static_cast<const float *>(gbuf), forces);
+                           nb->tcnt.as<int32_t>(), nb->rev.as<int32_t>(), static_cast<const float *>(gbuf), forces,
+                           site_e, virial, part);
 }
 
-void launch_cfg_sums(const mtp_system *s, const double *site_e, const double *virial, double *energy, double *stress,
-                     hipStream_t st, DevBuf &work, unsigned *ticket) {
+size_t cfg_partials_bytes(int64_t n) {
+    return sizeof(double) * 10 * (size_t)std::max<int64_t>(1, (n + SUM_CHUNK - 1) / SUM_CHUNK);
+}
+
+void launch_cfg_partials(int64_t n, const double *site_e, const double *virial, double *part, hipStream_t st) {
+    if (n > 0)
+        hipLaunchKernelGGL(cfg_partials, dim3((unsigned)((n + SUM_CHUNK - 1) / SUM_CHUNK)), dim3(256), 0, st, n,
+                           site_e, virial, part);
+}
+
+void launch_cfg_final(const mtp_system *s, const double *site_e, const double *virial, const double *part,
+                      double *energy, double *stress, hipStream_t st) {
     if (s->n_cfg <= 0) return;
-    work.ensure(sizeof(double) * 10 * SUM_S * (size_t)s->n_cfg);
-    hipLaunchKernelGGL(cfg_sums, dim3((unsigned)(s->n_cfg * SUM_S)), dim3(SUM_T), 0, st, s->cfg_off, site_e, virial,
-                       work.as<double>(), s->n_cfg, energy, stress, ticket);
+    hipLaunchKernelGGL(cfg_final, dim3((unsigned)s->n_cfg), dim3(256), 0, st, s->cfg_off, site_e, virial, part,
+                       energy, stress);
 }
 
 void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision, void *dst, hipStream_t st) {
