@@ -37,7 +37,8 @@ PEAK_HBM_GBS = 8000.0
 KERNELS = ("neighbors", "efs", "efs_moments", "efs_contract", "efs_forces", "force_gather", "cfg_sums", "grade",
            "select")
 # kernels whose HBM traffic the profile summary records (rocprof name substrings)
-TRAFFIC_KERNELS = ("efs_moments<double, 16, 4>", "efs_moments<double, 16, 8>", "efs_moments<float, 16, 8>",
+TRAFFIC_KERNELS = ("efs_moments_contract<double, 16, true>", "efs_moments_contract<float, 16, true>",
+                   "efs_moments<double, 16, 8>", "efs_moments<float, 16, 8>",
                    "efs_contract<double, 16, true>", "efs_contract<float, 16, true>",
                    "efs_forces_rows<double, 16, 4>", "efs_forces_rows<double, 16, 8>",
                    "efs_forces_rows<float, 16, 4>", "efs_forces_rows<float, 16, 8>",
@@ -274,9 +275,11 @@ def main():
     r = results[prec]
     m = info["m_full"]
     fl = efs_flops_per_atom(pairs_per_atom, info["n_comp"], info["n_rad"], info["contraction_flops"], True)
+    if r["kernels"]["efs_contract"]["launches"] == 0:   # four lanes: moments and contraction in one launch
+        fl = {"efs_moments_contract": fl["efs_moments"] + fl["efs_contract"], "efs_forces": fl["efs_forces"]}
     per_kernel = {}
     for k, f in fl.items():
-        us = r["kernels"][k]["avg_us"]
+        us = r["kernels"]["efs_moments" if k == "efs_moments_contract" else k]["avg_us"]
         per_kernel[k] = {"avg_us": us, "flops_per_atom": f, "bound": "alu", "peak_tflops": PEAK_VALU_TFLOPS,
                          "tflops": f * cfg.n / max(us * 1e-6, 1e-12) / 1e12}
     gf = 2.0 * m * m * (1 if prec == "fp64" else 6)
@@ -287,6 +290,8 @@ def main():
     dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"])
     d = per_kernel[dom]
     rocprof_name = {"efs_moments": f"efs_moments<{'double' if prec == 'fp64' else 'float'}, {level}, {tuned[prec]}>",
+                    "efs_moments_contract": f"efs_moments_contract<{'double' if prec == 'fp64' else 'float'}, {level}, "
+                                            "true>",
                     "efs_contract": f"efs_contract<{'double' if prec == 'fp64' else 'float'}, {level}, true>",
                     "efs_forces": f"efs_forces_rows<{'double' if prec == 'fp64' else 'float'}, {level}, {tuned[prec]}>",
                     "grade": "grade_f64" if prec == "fp64" else "grade_bf16<3>"}[dom]

@@ -107,20 +107,20 @@ template <typename T, int NR> __device__ inline void load_coefs(const EfsArgs &a
 }
 
 // ---- kernel 1: moments (eq. 3), LANES lanes per neighborhood -------------
+// Moments of the neighborhood of c, reduce-scattered over its K lanes: on
+// return M[i] of lane sub holds component sub NCP/K + i (NCP = NC padded to
+// a multiple of K).  c_s: the radial coefficients, already in LDS.
 template <typename T, int L, int K>
-__global__ __launch_bounds__(256) void efs_moments(const EfsArgs a) {
+__device__ inline void moments_scattered(const EfsArgs &a, const AtomCtx &c, const T *c_s,
+                                         T (&M)[(Level<L>::NC + K - 1) / K * K]) {
     using LV = Level<L>;
     constexpr int NC = LV::NC, NR = LV::NRAD;
-    __shared__ T c_s[NR * MAX_TYPES * MAX_TYPES * NPOLY];
-    load_coefs<T, NR>(a, c_s);
     const int nt = a.n_types;
     const int sub = threadIdx.x % K;
-    const AtomCtx c = atom_ctx<K>(a);
     const T rc = T(a.r_cut);
     const T xs = T(2.0 / (a.r_cut - a.r_min));
     const T x0 = T(-(a.r_min + a.r_cut) / (a.r_cut - a.r_min));
     constexpr int NCP = (NC + K - 1) / K * K;   // padded for the reduce-scatter
-    T M[NCP];
 #pragma unroll
     for (int k = 0; k < NCP; ++k) M[k] = T(0);
     int zj = 0, tend = c.tc[0];
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void efs_moments(const EfsArgs a) {
         nz = c.rp[3 * sub + 2];
     }
     for (int p = sub; p < c.ntot; p += K) {
-        while (p >= tend && zj < nt - 1) tend += c.tc[++zj];
+        while (p >= tend && zj < nt - 1) tend += tcount(a, c, ++zj);
         const T x = T(nx), y = T(ny), z = T(nz);
         if (p + K < c.ntot) {
             nx = c.rp[3 * (p + K)];
@@ -164,6 +164,19 @@ __global__ __launch_bounds__(256) void efs_moments(const EfsArgs a) {
         for (int k = 0; k < NC; ++k) M[k] = fma(fm[LV::comp_mu[k]], mono[LV::comp_mono[k]], M[k]);
     }
     efs::reduce_scatter<T, NCP, K>(M, sub);
+}
+
+template <typename T, int L, int K>
+__global__ __launch_bounds__(256) void efs_moments(const EfsArgs a) {
+    using LV = Level<L>;
+    constexpr int NC = LV::NC, NR = LV::NRAD;
+    constexpr int NCP = (NC + K - 1) / K * K;
+    __shared__ T c_s[NR * MAX_TYPES * MAX_TYPES * NPOLY];
+    load_coefs<T, NR>(a, c_s);
+    const int sub = threadIdx.x % K;
+    const AtomCtx c = atom_ctx<K>(a);
+    T M[NCP];
+    moments_scattered<T, L, K>(a, c, c_s, M);
     if (c.live) {
         T *out = static_cast<T *>(a.mbuf);
 #pragma unroll
@@ -199,18 +212,23 @@ template <typename T> struct RowSink {   // receives B_alpha when enabled
     __device__ Ref operator[](int k) const { return Ref{p + k, on}; }
 };
 
-template <typename T, int L, bool WB>
-__global__ __launch_bounds__(256) void efs_contract(const EfsArgs a) {
+template <typename T> struct LdsCol {   // component k of one neighborhood, [k][64] in LDS
+    const T *p;
+    __device__ T operator[](int k) const { return p[k * 64]; }
+};
+
+// The contraction of the 64 neighborhoods of block blk (a block of four
+// wavefronts), the moments read through M; sg, sdm: LDS scratch.
+template <typename T, int L, bool WB, typename MA>
+__device__ inline void contract_body(const EfsArgs &a, int64_t blk, const MA &M,
+                                     T (&sg)[Level<L>::NGRAPH][64], T (&sdm)[Level<L>::NC][64]) {
     using LV = Level<L>;
     constexpr int NC = LV::NC, NG = LV::NGRAPH;
     static_assert(LV::NPART == 4, "contraction kernel expects four parts");
-    __shared__ T sg[NG][64];
-    __shared__ T sdm[NC][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t slot = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t slot = blk * 64 + lane;
     const bool live = slot < a.n_atoms;
     const int64_t sl = live ? slot : 0;
-    const ColLoad<T> M{static_cast<const T *>(a.mbuf) + sl, a.n_atoms};
     {
         T g[NG];
         switch (wave) {
@@ -260,6 +278,43 @@ __global__ __launch_bounds__(256) void efs_contract(const EfsArgs a) {
             a.site_e[atom] = double(V) + double(static_cast<const T *>(a.xi0)[zi]);
         }
     }
+}
+
+template <typename T, int L, bool WB>
+__global__ __launch_bounds__(256) void efs_contract(const EfsArgs a) {
+    using LV = Level<L>;
+    __shared__ T sg[LV::NGRAPH][64];
+    __shared__ T sdm[LV::NC][64];
+    const int64_t slot = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    const int64_t sl = slot < a.n_atoms ? slot : 0;
+    contract_body<T, L, WB>(a, blockIdx.x, ColLoad<T>{static_cast<const T *>(a.mbuf) + sl, a.n_atoms}, sg, sdm);
+}
+
+// Kernels 1 and 2 in one launch (four lanes per neighborhood: the 256
+// threads of a block hold the same 64 neighborhoods in both phases): the
+// reduce-scattered moments go to LDS instead of memory, and after one
+// barrier the contraction reads them there.
+template <typename T, int L, bool WB>
+__global__ __launch_bounds__(256) void efs_moments_contract(const EfsArgs a) {
+    using LV = Level<L>;
+    constexpr int K = 4, NC = LV::NC, NR = LV::NRAD;
+    constexpr int NCP = (NC + K - 1) / K * K;
+    __shared__ T c_s[NR * MAX_TYPES * MAX_TYPES * NPOLY];
+    __shared__ T sM[NCP][64];
+    __shared__ T sg[LV::NGRAPH][64];
+    __shared__ T sdm[NC][64];
+    load_coefs<T, NR>(a, c_s);
+    const int sub = threadIdx.x % K;
+    const AtomCtx c = atom_ctx<K>(a);
+    {
+        T M[NCP];
+        moments_scattered<T, L, K>(a, c, c_s, M);
+        const int la = threadIdx.x / K;
+#pragma unroll
+        for (int i = 0; i < NCP / K; ++i) sM[sub * (NCP / K) + i][la] = M[i];
+    }
+    __syncthreads();
+    contract_body<T, L, WB>(a, blockIdx.x, LdsCol<T>{&sM[0][threadIdx.x & 63]}, sg, sdm);
 }
 
 // Chebyshev values (and derivatives) at u for the radial basis (eq. 4)
@@ -525,11 +580,15 @@ template <int L, typename T> int launch_efs_level_t(const EfsArgs &a);
         const unsigned grid = (unsigned)((a.n_atoms + per - 1) / per);                                   \
         const unsigned grid1 = (unsigned)((a.n_atoms + 63) / 64);                                        \
         if (grid == 0) return;                                                                           \
-        {                                                                                                \
+        if (K == 4) {                                                                                    \
             ProfScope ps("efs_moments", a.stream);                                                       \
-            hipLaunchKernelGGL((efs_moments<T, LEVEL, K>), dim3(grid), dim3(256), 0, a.stream, a);       \
-        }                                                                                                \
-        {                                                                                                \
+            hipLaunchKernelGGL((efs_moments_contract<T, LEVEL, WB>), dim3(grid1), dim3(256), 0, a.stream, \
+                               a);                                                                       \
+        } else {                                                                                         \
+            {                                                                                            \
+                ProfScope ps("efs_moments", a.stream);                                                   \
+                hipLaunchKernelGGL((efs_moments<T, LEVEL, K>), dim3(grid), dim3(256), 0, a.stream, a);   \
+            }                                                                                            \
             ProfScope ps("efs_contract", a.stream);                                                      \
             hipLaunchKernelGGL((efs_contract<T, LEVEL, WB>), dim3(grid1), dim3(256), 0, a.stream, a);    \
         }                                                                                                \
