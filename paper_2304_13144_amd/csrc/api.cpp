@@ -274,7 +274,9 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     } else if (want_sums) {
         launch_cfg_partials(n, sum_e, sum_v, m->sums.as<double>(), st);
     }
-    if (want_sums) {
+    // with a preselection the sums are finished by the preselection's launch
+    const CfgSums sums{s, sum_e, sum_v, m->sums.as<double>(), o.energy, o.stress};
+    if (want_sums && !want_sel) {
         ProfScope ps("cfg_sums", st);
         launch_cfg_final(s, sum_e, sum_v, m->sums.as<double>(), o.energy, o.stress, st);
     }
@@ -292,7 +294,8 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
         }
         if (want_sel) {
             ProfScope ps("select", st);
-            launch_select_write(gam, n, o.sel_thr, blk, o.sel_idx, o.sel_cap, o.sel_count, st);
+            launch_select_write(gam, n, o.sel_thr, blk, o.sel_idx, o.sel_cap, o.sel_count, st,
+                                want_sums ? &sums : nullptr);
         }
     }
     if (o.b_rows) launch_copy_rows(m->brow.ptr, ldb, mm, n, prec, o.b_rows, st);

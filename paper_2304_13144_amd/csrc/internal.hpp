@@ -173,9 +173,15 @@ void launch_invert(ActiveSet &as, const double *A, hipStream_t st, DevBuf &work,
 void launch_select(const double *gamma, int64_t n, double thr, int32_t *idx, int32_t cap, int32_t *count,
                    hipStream_t st, DevBuf &work);
 // the write half of the preselection, given per-GRADE_ROWS-block counts in
-// blk [nb + 1] (overwritten with offsets when nb is large)
+// blk [nb + 1] (overwritten with offsets when nb is large); with `sums` the
+// same launch also finishes the configuration sums (launch_cfg_final)
+struct CfgSums {
+    const mtp_system *s;
+    const double *site_e, *virial, *part;
+    double *energy, *stress;
+};
 void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *blk, int32_t *idx, int32_t cap,
-                         int32_t *count, hipStream_t st);
+                         int32_t *count, hipStream_t st, const CfgSums *sums = nullptr);
 void run_maxvol(ActiveSet &as, double *cand, int64_t n_cand, double thr, int max_swaps, int32_t *swap_cand,
                 int32_t *swap_col, int32_t *n_swaps, hipStream_t st, DevBuf &work);
 void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision, void *dst, hipStream_t st);

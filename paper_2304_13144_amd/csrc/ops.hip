@@ -65,12 +65,25 @@ __global__ __launch_bounds__(256) void force_gather(int64_t n, int nt, int maxn,
     if (live)
         for (int t = 0; t < nt; ++t) tot += tcnt[i * nt + t];
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int p = sub; p < tot; p += FG_LANES) {
-        const int64_t s = i * maxn + p;
-        const int64_t q = rev[s];
-        fx += double(g[3 * s]) - double(g[3 * q]);
-        fy += double(g[3 * s + 1]) - double(g[3 * q + 1]);
-        fz += double(g[3 * s + 2]) - double(g[3 * q + 2]);
+    // FG_DEPTH pairs per lane at a time: their reverse indices, then their
+    // gradients, are all in flight together (the loads form a dependent chain)
+    constexpr int FG_DEPTH = 4;
+    for (int p0 = sub; p0 < tot; p0 += FG_DEPTH * FG_LANES) {
+        int64_t q[FG_DEPTH];
+#pragma unroll
+        for (int d = 0; d < FG_DEPTH; ++d) {
+            const int p = p0 + d * FG_LANES;
+            q[d] = p < tot ? (int64_t)rev[i * maxn + p] : -1;
+        }
+#pragma unroll
+        for (int d = 0; d < FG_DEPTH; ++d) {
+            if (q[d] >= 0) {
+                const int64_t s = i * maxn + p0 + d * FG_LANES;
+                fx += double(g[3 * s]) - double(g[3 * q[d]]);
+                fy += double(g[3 * s + 1]) - double(g[3 * q[d] + 1]);
+                fz += double(g[3 * s + 2]) - double(g[3 * q[d] + 2]);
+            }
+        }
     }
 #pragma unroll
     for (int o = FG_LANES / 2; o > 0; o >>= 1) {
@@ -97,10 +110,9 @@ __global__ __launch_bounds__(256) void cfg_partials(int64_t n, const double *sit
 // lie inside [b, e), plus the atoms of the chunks it shares with its
 // neighbors.  Fixed assignment of terms to threads and a fixed reduction
 // tree: deterministic.
-__global__ __launch_bounds__(256) void cfg_final(const int64_t *cfg_off, const double *site_e, const double *vir,
-                                                 const double *part, double *energy, double *stress) {
+__device__ inline void cfg_final_block(int c, const int64_t *cfg_off, const double *site_e, const double *vir,
+                                       const double *part, double *energy, double *stress) {
     __shared__ double sp[4][10];
-    const int c = blockIdx.x;
     const int64_t b = cfg_off[c], e = cfg_off[c + 1];
     const int64_t cb = (b + SUM_CHUNK - 1) / SUM_CHUNK, ce = e / SUM_CHUNK;   // whole chunks [cb, ce)
     double acc[10];
@@ -139,6 +151,11 @@ __global__ __launch_bounds__(256) void cfg_final(const int64_t *cfg_off, const d
             stress[9 * c + t - 1] = v;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void cfg_final(const int64_t *cfg_off, const double *site_e, const double *vir,
+                                                 const double *part, double *energy, double *stress) {
+    cfg_final_block(blockIdx.x, cfg_off, site_e, vir, part, energy, stress);
 }
 
 template <typename T>
@@ -181,28 +198,45 @@ __global__ __launch_bounds__(SCAN_T) void select_scan(int32_t *blk, int64_t nb) 
     if (threadIdx.x == 0) blk[nb] = carry;
 }
 
+// one wavefront places the selected rows of preselection block gb (of nb)
 template <bool SCANNED>
-__global__ __launch_bounds__(GRADE_ROWS) void select_write(const double *g, int64_t n, double thr,
-                                                           const int32_t *blk, int32_t *idx, int32_t cap,
-                                                           int32_t *count) {
-    const int lane = threadIdx.x;
+__device__ inline void select_write_wave(int64_t gb, int64_t nb, const double *g, int64_t n, double thr,
+                                         const int32_t *blk, int32_t *idx, int32_t cap, int32_t *count) {
+    const int lane = threadIdx.x & 63;
     int64_t off = 0;
     if (SCANNED) {
-        off = blk[blockIdx.x];
+        off = blk[gb];
     } else {
-        for (int64_t b = lane; b < blockIdx.x; b += GRADE_ROWS) off += blk[b];
+        for (int64_t b = lane; b < gb; b += GRADE_ROWS) off += blk[b];
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) off += __shfl_xor(off, d, 64);
     }
-    const int64_t i = (int64_t)blockIdx.x * GRADE_ROWS + lane;
+    const int64_t i = gb * GRADE_ROWS + lane;
     const bool flag = i < n && g[i] > thr;
     const unsigned long long sel = __ballot(flag);
     const int64_t pos = off + __popcll(sel & ((1ull << lane) - 1ull));
     if (flag && pos < cap) idx[pos] = (int32_t)i;
-    if (blockIdx.x == gridDim.x - 1 && lane == 0) {
+    if (gb == nb - 1 && lane == 0) {
         const int64_t tot = off + __popcll(sel);
         *count = (int32_t)(tot < cap ? tot : cap);
     }
+}
+
+// four preselection blocks per block of 256 threads; with n_cfg > 0 the
+// first n_cfg blocks add the configuration sums instead (one launch for both
+// at the end of the evaluation)
+template <bool SCANNED>
+__global__ __launch_bounds__(256) void select_write(const double *g, int64_t n, double thr, const int32_t *blk,
+                                                    int32_t *idx, int32_t cap, int32_t *count, int n_cfg,
+                                                    const int64_t *cfg_off, const double *site_e, const double *vir,
+                                                    const double *part, double *energy, double *stress) {
+    if ((int)blockIdx.x < n_cfg) {
+        cfg_final_block(blockIdx.x, cfg_off, site_e, vir, part, energy, stress);
+        return;
+    }
+    const int64_t nb = (n + GRADE_ROWS - 1) / GRADE_ROWS;
+    const int64_t gb = ((int64_t)blockIdx.x - n_cfg) * 4 + (threadIdx.x >> 6);
+    if (gb < nb) select_write_wave<SCANNED>(gb, nb, g, n, thr, blk, idx, cap, count);
 }
 
 // column sums of the per-neighborhood gradient rows, FP64, fixed order:
@@ -298,19 +332,26 @@ void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision,
 }
 
 void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *blk, int32_t *idx, int32_t cap,
-                         int32_t *count, hipStream_t st) {
+                         int32_t *count, hipStream_t st, const CfgSums *sums) {
+    const int n_cfg = sums ? sums->s->n_cfg : 0;
+    const int64_t *off = sums ? sums->s->cfg_off : nullptr;
+    const double *se = sums ? sums->site_e : nullptr, *vir = sums ? sums->virial : nullptr;
+    const double *part = sums ? sums->part : nullptr;
+    double *energy = sums ? sums->energy : nullptr, *stress = sums ? sums->stress : nullptr;
     if (n == 0) {
         launch_zero(count, sizeof(int32_t), st);
+        if (sums) launch_cfg_final(sums->s, se, vir, part, energy, stress, st);
         return;
     }
     const int64_t nb = (n + GRADE_ROWS - 1) / GRADE_ROWS;
+    const dim3 grid((unsigned)(n_cfg + (nb + 3) / 4));
     if (nb <= SEL_DIRECT_BLOCKS) {
-        hipLaunchKernelGGL(select_write<false>, dim3((unsigned)nb), dim3(GRADE_ROWS), 0, st, gamma, n, thr, blk, idx,
-                           cap, count);
+        hipLaunchKernelGGL(select_write<false>, grid, dim3(256), 0, st, gamma, n, thr, blk, idx, cap, count, n_cfg, off,
+                           se, vir, part, energy, stress);
     } else {
         hipLaunchKernelGGL(select_scan, dim3(1), dim3(SCAN_T), 0, st, blk, nb);
-        hipLaunchKernelGGL(select_write<true>, dim3((unsigned)nb), dim3(GRADE_ROWS), 0, st, gamma, n, thr, blk, idx,
-                           cap, count);
+        hipLaunchKernelGGL(select_write<true>, grid, dim3(256), 0, st, gamma, n, thr, blk, idx, cap, count, n_cfg, off,
+                           se, vir, part, energy, stress);
     }
 }
 
