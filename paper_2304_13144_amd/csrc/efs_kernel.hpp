@@ -216,12 +216,24 @@ template <typename T> struct LdsCol {   // component k of one neighborhood, [k][
     const T *p;
     __device__ T operator[](int k) const { return p[k * 64]; }
 };
+template <typename T> struct LdsSink {   // receives B_alpha into [alpha][64] in LDS
+    T *p;
+    __device__ T &operator[](int k) const { return p[k * 64]; }
+};
+
+// B_alpha of a block's 64 neighborhoods are staged in LDS ([NLIN][64]) and
+// written as whole rows when that fits in STAGE_BYTES; otherwise each lane
+// writes its own row entries (strided by the row length)
+constexpr int STAGE_BYTES = 64 * 1024;
+template <typename T, int L> constexpr bool stage_rows() { return Level<L>::NLIN * 64 * sizeof(T) <= STAGE_BYTES; }
+template <typename T, int L> constexpr int stage_len() { return stage_rows<T, L>() ? Level<L>::NLIN : 1; }
 
 // The contraction of the 64 neighborhoods of block blk (a block of four
 // wavefronts), the moments read through M; sg, sdm: LDS scratch.
 template <typename T, int L, bool WB, typename MA>
 __device__ inline void contract_body(const EfsArgs &a, int64_t blk, const MA &M,
-                                     T (&sg)[Level<L>::NGRAPH][64], T (&sdm)[Level<L>::NC][64]) {
+                                     T (&sg)[Level<L>::NGRAPH][64], T (&sdm)[Level<L>::NC][64],
+                                     T (&sB)[stage_len<T, L>()][64]) {
     using LV = Level<L>;
     constexpr int NC = LV::NC, NG = LV::NGRAPH;
     static_assert(LV::NPART == 4, "contraction kernel expects four parts");
@@ -249,8 +261,12 @@ __device__ inline void contract_body(const EfsArgs &a, int64_t blk, const MA &M,
     const int nt = a.n_types;
     const XiPtr<T> xi{static_cast<const T *>(a.xi)};
     if (WB && wave == 0) {
-        T *row = static_cast<T *>(a.brow) + sl * (int64_t)a.ldb + nt;
-        LV::template trie<T, true>(gin, xi, RowSink<T>{row, live}, dg, V);
+        if constexpr (stage_rows<T, L>()) {
+            LV::template trie<T, true>(gin, xi, LdsSink<T>{&sB[0][lane]}, dg, V);
+        } else {
+            T *row = static_cast<T *>(a.brow) + sl * (int64_t)a.ldb + nt;
+            LV::template trie<T, true>(gin, xi, RowSink<T>{row, live}, dg, V);
+        }
     } else {
         LV::template trie<T, false>(gin, xi, RowSink<T>{nullptr, false}, dg, V);
     }
@@ -267,6 +283,15 @@ __device__ inline void contract_body(const EfsArgs &a, int64_t blk, const MA &M,
             for (int k = 0; k < NC; ++k) sdm[k][lane] = w == 0 ? dMp[k] : sdm[k][lane] + dMp[k];
         }
         __syncthreads();
+    }
+    if (WB && stage_rows<T, L>()) {   // B_alpha rows: consecutive threads, consecutive columns
+        constexpr int NL = LV::NLIN;
+        const int64_t nlive = a.n_atoms - blk * 64;
+        T *rows = static_cast<T *>(a.brow) + blk * 64 * (int64_t)a.ldb + nt;
+        for (int e = threadIdx.x; e < 64 * NL; e += 256) {
+            const int r = e / NL, k = e % NL;
+            if (r < nlive) rows[r * (int64_t)a.ldb + k] = sB[k][r];
+        }
     }
     if (live) {
         T *dout = static_cast<T *>(a.dmbuf);
@@ -285,9 +310,11 @@ __global__ __launch_bounds__(256) void efs_contract(const EfsArgs a) {
     using LV = Level<L>;
     __shared__ T sg[LV::NGRAPH][64];
     __shared__ T sdm[LV::NC][64];
+    __shared__ T sB[WB ? stage_len<T, L>() : 1][64];
     const int64_t slot = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
     const int64_t sl = slot < a.n_atoms ? slot : 0;
-    contract_body<T, L, WB>(a, blockIdx.x, ColLoad<T>{static_cast<const T *>(a.mbuf) + sl, a.n_atoms}, sg, sdm);
+    contract_body<T, L, WB>(a, blockIdx.x, ColLoad<T>{static_cast<const T *>(a.mbuf) + sl, a.n_atoms}, sg, sdm,
+                            reinterpret_cast<T (&)[stage_len<T, L>()][64]>(sB));
 }
 
 // Kernels 1 and 2 in one launch (four lanes per neighborhood: the 256
@@ -303,6 +330,7 @@ __global__ __launch_bounds__(256) void efs_moments_contract(const EfsArgs a) {
     __shared__ T sM[NCP][64];
     __shared__ T sg[LV::NGRAPH][64];
     __shared__ T sdm[NC][64];
+    __shared__ T sB[WB ? stage_len<T, L>() : 1][64];
     load_coefs<T, NR>(a, c_s);
     const int sub = threadIdx.x % K;
     const AtomCtx c = atom_ctx<K>(a);
@@ -314,7 +342,8 @@ __global__ __launch_bounds__(256) void efs_moments_contract(const EfsArgs a) {
         for (int i = 0; i < NCP / K; ++i) sM[sub * (NCP / K) + i][la] = M[i];
     }
     __syncthreads();
-    contract_body<T, L, WB>(a, blockIdx.x, LdsCol<T>{&sM[0][threadIdx.x & 63]}, sg, sdm);
+    contract_body<T, L, WB>(a, blockIdx.x, LdsCol<T>{&sM[0][threadIdx.x & 63]}, sg, sdm,
+                            reinterpret_cast<T (&)[stage_len<T, L>()][64]>(sB));
 }
 
 // Chebyshev values (and derivatives) at u for the radial basis (eq. 4)
