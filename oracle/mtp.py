@@ -283,6 +283,22 @@ def kept_columns(pot: Potential, theta):
     return [k for k in range(pot.n_theta) if k not in drop]
 
 
+def cfg_rows(rows, sizes):
+    """Configuration-mode rows (Sec. II.C): b(cfg) = dE(cfg)/dtheta at the
+    current theta.  With E = sum_i V_i (eq. 1) this is the sum of the
+    neighborhood rows b_i over the configuration's atoms.  rows: [N, m] in
+    configuration order; sizes: atoms per configuration.  Returns
+    [n_cfg, m]."""
+    rows = np.asarray(rows, dtype=np.float64)
+    out = np.zeros((len(sizes), rows.shape[1]))
+    o = 0
+    for k, n in enumerate(sizes):
+        out[k] = rows[o:o + int(n)].sum(axis=0)
+        o += int(n)
+    assert o == len(rows), "sizes do not add up to the number of rows"
+    return out
+
+
 def grades(rows, A):
     """gamma_i = max_p |c_ip| with c_i A = b_i solved by LU (Sec. II.D).
 

@@ -439,6 +439,55 @@ def test_linear_mode_reproduces_site_energies():
     assert np.allclose(C @ V[act], V, rtol=1e-9, atol=1e-9 * np.abs(V).max())
 
 
+# ------------------------------------------------- configuration mode -----
+def _small_cfgs(n_cfg, seed, n_types=1, level=8):
+    """Small BCC cells (2x2x2 or 3x2x2) with random vacancies and species."""
+    r = np.random.default_rng(seed)
+    out = []
+    for k in range(n_cfg):
+        reps = (2, 2, 2) if k % 2 == 0 else (3, 2, 2)
+        pos, cell = _bcc(reps, sigma=0.12, seed=seed * 1000 + k)
+        keep = np.sort(r.choice(len(pos), len(pos) - int(r.integers(0, 4)), replace=False))
+        types = r.integers(0, n_types, len(keep)).astype(np.int32)
+        out.append((pos[keep], types, cell))
+    return out
+
+
+def test_cfg_rows_are_total_energy_gradients():
+    # b(cfg) = dE(cfg)/dtheta (Sec. II.C): central differences of the total energy
+    pot, theta, _, _, _ = _setup(level=8, n_types=2)
+    (pos, types, cell), = _small_cfgs(1, 41, n_types=2)
+    pairs = _nbrs(pos, cell)
+    b = om.cfg_rows(om.b_rows(pot, theta, pos, types, cell, pairs), [len(pos)])[0]
+    h = 1e-6
+    for p in [0, 1, 2, 7, pot.n_types + pot.n_lin, pot.n_types + pot.n_lin + 9, pot.n_theta - 1]:
+        tp, tm = theta.copy(), theta.copy()
+        tp[p] += h
+        tm[p] -= h
+        Ep = om.energy_forces_stress(pot, tp, pos, types, cell, pairs)[0]
+        Em = om.energy_forces_stress(pot, tm, pos, types, cell, pairs)[0]
+        assert abs((Ep - Em) / (2 * h) - b[p]) <= 1e-6 * max(1.0, abs(b[p]))
+    # the species columns count the atoms of each species
+    assert np.array_equal(b[:pot.n_types], np.bincount(types, minlength=pot.n_types).astype(float))
+
+
+def test_cfg_mode_linear_energies_are_combinations_of_active_energies():
+    # with the active configurations as training set, E(cfg) = sum_j c_j E(cfg_j)
+    # and c = b(cfg) A^-1 (Sec. II.C), exactly in the LINEAR mode
+    pot, theta, _, _, _ = _setup(level=8, n_types=1)
+    cfgs = _small_cfgs(24, 43)
+    rows, E = [], []
+    for pos, types, cell in cfgs:
+        pairs = _nbrs(pos, cell)
+        rows.append(om.cfg_rows(om.linear_rows(pot, theta, pos, types, cell, pairs), [len(pos)])[0])
+        E.append(om.energy_forces_stress(pot, theta, pos, types, cell, pairs)[0])
+    rows, E = np.array(rows), np.array(E)
+    act = om.initial_active_set(rows)
+    g, _, C = om.grades(rows, rows[act])
+    assert np.allclose(g[act], 1.0, rtol=0, atol=1e-9)
+    assert np.allclose(C @ E[act], E, rtol=1e-9, atol=1e-9 * np.abs(E).max())
+
+
 # -------------------------------------------------------------- maxvol -----
 def test_maxvol_det_ratios_and_local_optimality_exhaustive():
     rng = np.random.default_rng(27)
