@@ -68,11 +68,21 @@ typedef enum { MTP_FP64 = 0, MTP_MIXED = 1 } mtp_precision;
  *   rows in FP32; grade product on MFMA with BF16 split operands and FP32
  *   accumulation; energy, force and stress sums, A^-1 and MaxVol in FP64. */
 
-typedef enum { MTP_GRADE_FULL = 0, MTP_GRADE_LINEAR = 1 } mtp_grade_mode;
+typedef enum {
+    MTP_GRADE_FULL = 0,
+    MTP_GRADE_LINEAR = 1,
+    MTP_GRADE_FULL_CFG = 2,
+    MTP_GRADE_LINEAR_CFG = 3
+} mtp_grade_mode;
 /* FULL: b_i over all of theta minus N_rad(N_rad+1)/2 gauge columns of the c
  *   block (the rows are exactly rank deficient by that many directions), so
  *   m = n_theta - N_rad(N_rad+1)/2.  LINEAR: b_i = (onehot(z_i), B_alpha),
- *   m = n_types + N_lin. */
+ *   m = n_types + N_lin.
+ * FULL_CFG / LINEAR_CFG: the query strategy on whole configurations (Sec.
+ *   II.C): the row of a configuration is b(cfg) = dE/dtheta = sum_i b_i over
+ *   its atoms (FULL or LINEAR columns), and the active set holds m such
+ *   configuration rows.  Each of the four modes has an active set of its own
+ *   (mtp_set_active_set, mtp_maxvol_update). */
 
 typedef struct mtp_model mtp_model; /* theta, basis, A^-1 per mode (device) */
 typedef struct mtp_nbrs mtp_nbrs;   /* neighbor lists of one system (device) */
@@ -175,6 +185,16 @@ int mtp_energy_forces_stress(const mtp_model *m, const mtp_system *s, const mtp_
  * active set. */
 int mtp_grade(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
               double *gamma, int32_t *argmax, void *b_rows, void *stream);
+
+/* Configuration grades (Sec. II.C): gamma(cfg) = max_p |(b(cfg) A^-1)_p|
+ * with b(cfg) = sum of the rows b_i of the configuration's atoms (summed in
+ * FP64; the b_i in FP64 for MTP_FP64, FP32 for MTP_MIXED) and A the active
+ * set of mode g (MTP_GRADE_FULL_CFG or MTP_GRADE_LINEAR_CFG; the product in
+ * FP64 in both precisions).  gamma [n_cfg] FP64 and argmax [n_cfg] int32
+ * (lowest p on ties) may be NULL when b_cfg is given; b_cfg [n_cfg*m] FP64
+ * row-major or NULL.  gamma needs the mode's active set. */
+int mtp_grade_cfg(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
+                  double *gamma, int32_t *argmax, double *b_cfg, void *stream);
 
 /* One fused pass: energy, forces, stress, site energies and grades (any
  * output pointer may be NULL; gamma needs the active set of `g`). */

@@ -11,10 +11,12 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import MTP_FP64, MTP_GRADE_FULL, MTP_GRADE_LINEAR, MTP_MIXED, MtpError, check
+from ._lib import (MTP_FP64, MTP_GRADE_FULL, MTP_GRADE_FULL_CFG, MTP_GRADE_LINEAR, MTP_GRADE_LINEAR_CFG, MTP_MIXED,
+                   MtpError, check)
 
 PRECISION = {"fp64": MTP_FP64, "mixed": MTP_MIXED}
-MODE = {"full": MTP_GRADE_FULL, "linear": MTP_GRADE_LINEAR}
+MODE = {"full": MTP_GRADE_FULL, "linear": MTP_GRADE_LINEAR, "full_cfg": MTP_GRADE_FULL_CFG,
+        "linear_cfg": MTP_GRADE_LINEAR_CFG}
 
 
 def _p(t):
@@ -78,7 +80,7 @@ class Model:
 
     def m(self, mode):
         i = self.info
-        return i["m_full"] if _mode(mode) == MTP_GRADE_FULL else i["m_linear"]
+        return i["m_full"] if _mode(mode) in (MTP_GRADE_FULL, MTP_GRADE_FULL_CFG) else i["m_linear"]
 
     def set_params(self, theta):
         t = torch.as_tensor(theta, dtype=torch.float64).to(self.device).contiguous()
@@ -203,6 +205,28 @@ def grade(model, batch, nbrs, precision="fp64", mode="full", rows=False):
     return {"gamma": g, "argmax": am, "rows": b}
 
 
+def grade_cfg(model, batch, nbrs, precision="fp64", mode="full_cfg", rows=False):
+    """Configuration grades (mode "full_cfg" / "linear_cfg"): gamma [n_cfg],
+    argmax [n_cfg] and, with rows=True, b(cfg) [n_cfg, m] FP64."""
+    d = batch.device
+    g = _out(batch.n_cfg, torch.float64, d)
+    am = _out(batch.n_cfg, torch.int32, d)
+    b = _out(None, torch.float64, d, (batch.n_cfg, model.m(mode))) if rows else None
+    s = batch.system()
+    check(_lib.lib().mtp_grade_cfg(model._h, ctypes.byref(s), nbrs._h, _prec(precision), _mode(mode), _p(g), _p(am),
+                                   _p(b), _stream()))
+    return {"gamma": g, "argmax": am, "rows": b}
+
+
+def cfg_rows(model, batch, nbrs, precision="fp64", mode="full_cfg"):
+    """b(cfg) = sum of the configuration's neighborhood rows, [n_cfg, m] FP64 (no active set needed)."""
+    b = _out(None, torch.float64, batch.device, (batch.n_cfg, model.m(mode)))
+    s = batch.system()
+    check(_lib.lib().mtp_grade_cfg(model._h, ctypes.byref(s), nbrs._h, _prec(precision), _mode(mode), None, None,
+                                   _p(b), _stream()))
+    return b
+
+
 def evaluate(model, batch, nbrs, precision="fp64", mode="full", out=None, gamma_save=None, capacity=None):
     """Fused energy, forces, stress, site energies and grades; `out` reuses tensors.
 
@@ -319,7 +343,8 @@ def compiled_levels():
     return list(arr[:n])
 
 
-__all__ = ["Model", "Batch", "Neighbors", "energy_forces_stress", "grade", "evaluate", "b_rows", "select",
+__all__ = ["Model", "Batch", "Neighbors", "energy_forces_stress", "grade", "grade_cfg", "cfg_rows", "evaluate",
+           "b_rows", "select",
            "maxvol_update", "efs_backward", "MTPEnergy", "tune", "CapturedStep", "basis_describe", "compiled_levels", "MtpError"]
 
 

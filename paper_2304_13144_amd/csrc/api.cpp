@@ -192,6 +192,7 @@ struct EvalOut {
     double sel_thr = 0.0;
     int32_t *sel_idx = nullptr, *sel_count = nullptr;
     int32_t sel_cap = 0;
+    bool keep_rows = false;   // leave the rows in m->brow (configuration mode)
 };
 
 void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int prec, const EvalOut &o,
@@ -202,7 +203,7 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     MTP_CHECK(o.mode == MTP_GRADE_FULL || o.mode == MTP_GRADE_LINEAR, MTP_E_INVAL, "bad grade mode");
     const bool want_sel = o.sel_idx != nullptr;
     const bool want_grade = o.gamma || o.argmax || want_sel;
-    const bool want_rows = want_grade || o.b_rows;
+    const bool want_rows = want_grade || o.b_rows || o.keep_rows;
     if (want_grade) MTP_CHECK(m->act[o.mode].valid, MTP_E_INVAL, "no active set for this grade mode");
     MTP_HIP(hipSetDevice(m->device));
     const int64_t n = s->n_atoms;
@@ -377,11 +378,15 @@ int mtp_load(const char *path, int hip_device, mtp_model **out) {
             std::string mode;
             long mm = -1;
             in >> mode >> mm;
-            MTP_CHECK(mode == "full" || mode == "linear", MTP_E_PARSE, "active mode must be full or linear");
+            const char *names[4] = {"full", "linear", "full_cfg", "linear_cfg"};
+            int mi = -1;
+            for (int k = 0; k < 4; ++k)
+                if (mode == names[k]) mi = k;
+            MTP_CHECK(mi >= 0, MTP_E_PARSE, "active mode must be full, linear, full_cfg or linear_cfg");
             MTP_CHECK(mm > 0 && mm < 100000, MTP_E_PARSE, "bad active-set size");
             std::vector<double> A(mm * mm);
             for (long k = 0; k < mm * mm; ++k) MTP_CHECK(bool(in >> A[k]), MTP_E_PARSE, "active set truncated");
-            acts.push_back({mode == "full" ? MTP_GRADE_FULL : MTP_GRADE_LINEAR, A});
+            acts.push_back({mi, A});
         } else {
             throw Error{MTP_E_PARSE, "unknown key '" + key + "'"};
         }
@@ -427,13 +432,14 @@ int mtp_save(const mtp_model *m, const char *path) {
       << "\nr_min " << m->r_min << "\nr_cut " << m->r_cut << "\nn_polyn " << NPOLY << "\ntheta " << m->n_theta << "\n";
     for (int k = 0; k < m->n_theta; ++k) f << m->theta_host[k] << (k % 8 == 7 ? "\n" : " ");
     f << "\n";
-    for (int mode = 0; mode < 2; ++mode) {
+    const char *names[4] = {"full", "linear", "full_cfg", "linear_cfg"};
+    for (int mode = 0; mode < 4; ++mode) {
         const ActiveSet &as = m->act[mode];
         if (!as.valid) continue;
         std::vector<double> A((size_t)as.m * as.m);
         MTP_HIP(hipSetDevice(m->device));
         MTP_HIP(hipMemcpy(A.data(), as.A.ptr, sizeof(double) * A.size(), hipMemcpyDeviceToHost));
-        f << "active " << (mode == MTP_GRADE_FULL ? "full " : "linear ") << as.m << "\n";
+        f << "active " << names[mode] << " " << as.m << "\n";
         for (size_t k = 0; k < A.size(); ++k) f << A[k] << ((k + 1) % as.m == 0 ? "\n" : " ");
     }
     MTP_CHECK(f.good(), MTP_E_IO, "write failed");
@@ -481,6 +487,7 @@ int mtp_set_params(mtp_model *m, const double *theta, void *stream) {
     choose_gauge(m);
     upload_params(m);
     m->act[MTP_GRADE_FULL].valid = false;   // FULL rows depend on theta
+    m->act[MTP_GRADE_FULL_CFG].valid = false;
     API_END
 }
 
@@ -494,7 +501,7 @@ int mtp_kept_columns(const mtp_model *m, int32_t *cols) {
 int mtp_set_active_set(mtp_model *m, mtp_grade_mode mode, const double *A, void *stream) {
     API_BEGIN
     MTP_CHECK(m && A, MTP_E_INVAL, "NULL argument");
-    MTP_CHECK(mode == MTP_GRADE_FULL || mode == MTP_GRADE_LINEAR, MTP_E_INVAL, "bad grade mode");
+    MTP_CHECK(mode >= MTP_GRADE_FULL && mode <= MTP_GRADE_LINEAR_CFG, MTP_E_INVAL, "bad grade mode");
     MTP_HIP(hipSetDevice(m->device));
     set_active(m, mode, A, S(stream));
     API_END
@@ -503,7 +510,7 @@ int mtp_set_active_set(mtp_model *m, mtp_grade_mode mode, const double *A, void 
 int mtp_get_active_set(const mtp_model *m, mtp_grade_mode mode, double *A_out, double *Ainv_out, void *stream) {
     API_BEGIN
     MTP_CHECK(m, MTP_E_INVAL, "NULL model");
-    MTP_CHECK(mode == MTP_GRADE_FULL || mode == MTP_GRADE_LINEAR, MTP_E_INVAL, "bad grade mode");
+    MTP_CHECK(mode >= MTP_GRADE_FULL && mode <= MTP_GRADE_LINEAR_CFG, MTP_E_INVAL, "bad grade mode");
     const ActiveSet &as = m->act[mode];
     MTP_CHECK(as.valid, MTP_E_INVAL, "no active set for this mode");
     MTP_HIP(hipSetDevice(m->device));
@@ -618,6 +625,42 @@ int mtp_grade(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_p
     API_END
 }
 
+int mtp_grade_cfg(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
+                  double *gamma, int32_t *argmax, double *b_cfg, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m && (gamma || b_cfg), MTP_E_INVAL, "NULL argument");
+    MTP_CHECK(g == MTP_GRADE_FULL_CFG || g == MTP_GRADE_LINEAR_CFG, MTP_E_INVAL,
+              "configuration grades take MTP_GRADE_FULL_CFG or MTP_GRADE_LINEAR_CFG");
+    check_system(m, s);
+    const bool want_grade = gamma || argmax;
+    if (want_grade) MTP_CHECK(m->act[g].valid, MTP_E_INVAL, "no active set for this grade mode");
+    hipStream_t st = S(stream);
+    // the neighborhood rows of every atom (FP64 or FP32), left in m->brow
+    EvalOut o;
+    o.mode = g & 1;
+    o.keep_rows = true;
+    evaluate(m, s, nb, p, o, st);
+    const int mm = m->m_of(g), ldb = ld_of(mm);
+    const int64_t n = s->n_atoms;
+    m->cfgrows.ensure(sizeof(double) * (size_t)ldb * s->n_cfg);
+    m->cfgpart.ensure(cfg_row_partials_bytes(n, ldb));
+    if (n == 0) {
+        launch_zero(m->cfgrows.ptr, sizeof(double) * (size_t)ldb * s->n_cfg, st);
+    } else {
+        ProfScope ps("cfg_rows", st);
+        launch_cfg_rows(m->brow.ptr, p, ldb, n, s, m->cfgpart.as<double>(), m->cfgrows.as<double>(), st);
+    }
+    if (want_grade) {
+        m->gamma_ws.ensure(sizeof(double) * s->n_cfg);
+        ProfScope ps("grade", st);
+        launch_grade(m->act[g], MTP_FP64, m->cfgrows.ptr, ldb, s->n_cfg, gamma ? gamma : m->gamma_ws.as<double>(),
+                     argmax, st);
+    }
+    if (b_cfg) launch_copy_rows(m->cfgrows.ptr, ldb, mm, s->n_cfg, MTP_FP64, b_cfg, st);
+    MTP_HIP(hipGetLastError());
+    API_END
+}
+
 int mtp_evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
                  double *energy, double *forces, double *stress, double *site_e, double *gamma, int32_t *argmax,
                  void *stream) {
@@ -718,7 +761,7 @@ int mtp_maxvol_update(mtp_model *m, mtp_grade_mode g, double *cand, int64_t n_ca
                       int32_t max_swaps, int32_t *swap_cand, int32_t *swap_col, int32_t *n_swaps, void *stream) {
     API_BEGIN
     MTP_CHECK(m && n_swaps, MTP_E_INVAL, "NULL argument");
-    MTP_CHECK(g == MTP_GRADE_FULL || g == MTP_GRADE_LINEAR, MTP_E_INVAL, "bad grade mode");
+    MTP_CHECK(g >= MTP_GRADE_FULL && g <= MTP_GRADE_LINEAR_CFG, MTP_E_INVAL, "bad grade mode");
     MTP_CHECK(threshold > 1.0, MTP_E_INVAL, "threshold must exceed 1");
     MTP_CHECK(n_cand >= 0 && max_swaps >= 0, MTP_E_INVAL, "negative size");
     MTP_CHECK(n_cand == 0 || cand, MTP_E_INVAL, "cand is NULL");

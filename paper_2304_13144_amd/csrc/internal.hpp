@@ -67,13 +67,15 @@ struct mtp_model {
     std::vector<int> kept;          // FULL-mode kept columns
     std::vector<int> colmap_host;   // full column -> kept column or -1
     mtp::DevBuf theta64, theta32, colmap;
-    mtp::ActiveSet act[2];          // [MTP_GRADE_FULL], [MTP_GRADE_LINEAR]
+    mtp::ActiveSet act[4];          // indexed by mtp_grade_mode: neighborhood and configuration modes
     int force_lanes = 0;            // set while the tuner times a schedule
     int tuned_lanes[2][48] = {};    // [precision][floor(log2 n_atoms)] -> lanes per neighborhood, 0 = untuned
     // scratch of the evaluation path
     mutable mtp::DevBuf gbuf, virial, sitebuf, brow, gamma_ws, argmax_ws, work, sums, mbuf, dmbuf, tbuf, dtbuf, rows;
     mutable mtp::DevBuf selblk;     // per-block preselection counts written by the grade kernels
-    int m_of(int mode) const { return mode == MTP_GRADE_FULL ? (int)kept.size() : n_types + basis.n_lin(); }
+    mutable mtp::DevBuf cfgrows, cfgpart;   // configuration-mode rows and their chunk partials
+    // the configuration modes use the rows of their neighborhood mode (mode & 1)
+    int m_of(int mode) const { return (mode & 1) == MTP_GRADE_FULL ? (int)kept.size() : n_types + basis.n_lin(); }
 };
 
 struct mtp_nbrs {
@@ -185,6 +187,11 @@ void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *bl
 void run_maxvol(ActiveSet &as, double *cand, int64_t n_cand, double thr, int max_swaps, int32_t *swap_cand,
                 int32_t *swap_col, int32_t *n_swaps, hipStream_t st, DevBuf &work);
 void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision, void *dst, hipStream_t st);
+// configuration-mode rows: out [n_cfg][ldb] FP64 = per-configuration sums of
+// the rows [n][ldb] (precision-typed); part: cfg_row_partials_bytes(n, ldb)
+size_t cfg_row_partials_bytes(int64_t n, int ldb);
+void launch_cfg_rows(const void *rows, int precision, int ldb, int64_t n, const mtp_system *s, double *part,
+                     double *out, hipStream_t st);
 void launch_zero(void *p, size_t bytes, hipStream_t st);
 
 }  // namespace mtp

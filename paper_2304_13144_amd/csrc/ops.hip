@@ -158,6 +158,43 @@ __global__ __launch_bounds__(256) void cfg_final(const int64_t *cfg_off, const d
     cfg_final_block(blockIdx.x, cfg_off, site_e, vir, part, energy, stress);
 }
 
+// Configuration-mode rows b(cfg) = sum_i b_i over the atoms of each
+// configuration, in FP64 whatever the rows' type, in two steps like the
+// energy sums: partial sums over chunks of ROW_CHUNK atoms (thread t of a
+// block adds column t, t + 256, ... of its chunk's rows in atom order), then
+// one block per configuration adds the partials of its whole chunks and the
+// rows of the chunks it shares with its neighbors.  Fixed order throughout.
+constexpr int ROW_CHUNK = 64;
+template <typename T>
+__global__ __launch_bounds__(256) void row_partials(const T *rows, int ldb, int64_t n, double *part) {
+    const int64_t a0 = (int64_t)blockIdx.x * ROW_CHUNK;
+    const int64_t a1 = a0 + ROW_CHUNK < n ? a0 + ROW_CHUNK : n;
+    for (int k = threadIdx.x; k < ldb; k += 256) {
+        double acc = 0.0;
+        for (int64_t i = a0; i < a1; ++i) acc += double(rows[i * ldb + k]);
+        part[(int64_t)blockIdx.x * ldb + k] = acc;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void row_final(const T *rows, int ldb, const double *part, const int64_t *cfg_off,
+                                                 double *out) {
+    const int c = blockIdx.x;
+    const int64_t b = cfg_off[c], e = cfg_off[c + 1];
+    const int64_t cb = (b + ROW_CHUNK - 1) / ROW_CHUNK, ce = e / ROW_CHUNK;   // whole chunks [cb, ce)
+    for (int k = threadIdx.x; k < ldb; k += 256) {
+        double acc = 0.0;
+        if (cb < ce) {
+            for (int64_t i = b; i < cb * ROW_CHUNK; ++i) acc += double(rows[i * ldb + k]);
+            for (int64_t q = cb; q < ce; ++q) acc += part[q * ldb + k];
+            for (int64_t i = ce * ROW_CHUNK; i < e; ++i) acc += double(rows[i * ldb + k]);
+        } else {
+            for (int64_t i = b; i < e; ++i) acc += double(rows[i * ldb + k]);
+        }
+        out[(int64_t)c * ldb + k] = acc;
+    }
+}
+
 template <typename T>
 __global__ void copy_rows(const T *src, int ldb, int m, int64_t n, T *dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -329,6 +366,27 @@ void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision,
     else
         hipLaunchKernelGGL(copy_rows<float>, grid, dim3(256), 0, st, static_cast<const float *>(src), ldb, m, n,
                            static_cast<float *>(dst));
+}
+
+size_t cfg_row_partials_bytes(int64_t n, int ldb) {
+    return sizeof(double) * (size_t)ldb * (size_t)std::max<int64_t>(1, (n + ROW_CHUNK - 1) / ROW_CHUNK);
+}
+
+void launch_cfg_rows(const void *rows, int precision, int ldb, int64_t n, const mtp_system *s, double *part,
+                     double *out, hipStream_t st) {
+    if (s->n_cfg <= 0) return;
+    const unsigned nch = (unsigned)((n + ROW_CHUNK - 1) / ROW_CHUNK);
+    if (precision == MTP_FP64) {
+        const double *r = static_cast<const double *>(rows);
+        if (nch) hipLaunchKernelGGL(row_partials<double>, dim3(nch), dim3(256), 0, st, r, ldb, n, part);
+        hipLaunchKernelGGL(row_final<double>, dim3((unsigned)s->n_cfg), dim3(256), 0, st, r, ldb, part, s->cfg_off,
+                           out);
+    } else {
+        const float *r = static_cast<const float *>(rows);
+        if (nch) hipLaunchKernelGGL(row_partials<float>, dim3(nch), dim3(256), 0, st, r, ldb, n, part);
+        hipLaunchKernelGGL(row_final<float>, dim3((unsigned)s->n_cfg), dim3(256), 0, st, r, ldb, part, s->cfg_off,
+                           out);
+    }
 }
 
 void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *blk, int32_t *idx, int32_t cap,

@@ -34,6 +34,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 # purposes of the random streams
 P_LATTICE, P_DISPLACE, P_THETA, P_TRAIN, P_STRAIN, P_SIZES, P_VACANCY = 0, 1, 2, 3, 4, 5, 6
+P_CFGMODE = 7
 P_SNAPSHOT = 10
 
 
@@ -173,6 +174,24 @@ def _vacancy_config(r, kind, n_atoms, density, n_types, sigma, strain_amp, vac_m
     pos = pos + r.normal(0.0, sigma, pos.shape)
     types = r.integers(0, n_types, n_atoms).astype(np.int32)
     return Config(pos, types, cell)
+
+
+def cfg_pool(wid, n_cfg, stream=0, n_min=8, n_max=54):
+    """Small periodic configurations for the configuration query mode with the
+    potential of workload 1 (one species, BCC a = 3.30, sigma = 0.10) or 2
+    (two species, FCC a = 4.05, sigma = 0.08): n_min..n_max atoms each on the
+    smallest near-cubic cell, random vacancies, strain U(-0.03, 0.03).
+    `stream` selects an independent pool."""
+    r = np.random.default_rng([SEED, wid, P_CFGMODE, stream])
+    if wid == 1:
+        kind, a, n_types, sigma = "bcc", 3.30, 1, 0.10
+    elif wid == 2:
+        kind, a, n_types, sigma = "fcc", 4.05, 2, 0.08
+    else:
+        raise ValueError("configuration pools exist for workloads 1 and 2")
+    density = len(_BASIS[kind]) / a ** 3
+    sizes = r.integers(n_min, n_max + 1, n_cfg)
+    return [_vacancy_config(r, kind, int(n), density, n_types, sigma, 0.03) for n in sizes]
 
 
 def workload3(n_cfg=512):

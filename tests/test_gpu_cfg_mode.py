@@ -1,0 +1,119 @@
+"""GPU parity of the configuration query mode (Sec. II.C) through the C ABI.
+
+A configuration's row is b(cfg) = dE(cfg)/dtheta = sum_i b_i; its grade is
+max_p |(b(cfg) A^-1)_p| with A the rows of m active configurations.  The
+oracle side sums its own FP64 neighborhood rows (oracle.mtp.cfg_rows) and
+solves by LU.  Bars: rows within 1e-10 relative (norm-wise), FP64 grades
+within max(1e-10, kappa(A) 1e-15) of max(1, gamma), mixed grades within
+max(1e-5, 30 x what FP32 neighborhood rows alone force), MaxVol swap logs
+identical.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mtp as om
+from oracle import neighbors as onb
+from paper_2304_13144_amd import api, synth
+from tests.helpers import potential, rel_err, theta_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_rows(pot, theta, cfgs, mode, keep):
+    """Neighborhood rows of every atom, configuration after configuration."""
+    out = []
+    for c in cfgs:
+        pairs = onb.neighbors(c.pos, c.cell, c.pbc, pot.r_cut)
+        if mode == "full":
+            out.append(om.b_rows(pot, theta, c.pos, c.types, c.cell, pairs)[:, keep])
+        else:
+            out.append(om.linear_rows(pot, theta, c.pos, c.types, c.cell, pairs))
+    return np.concatenate(out, axis=0)
+
+
+def _setup(wid, mode, n_pool, n_test):
+    w = synth.workload1() if wid == 1 else synth.workload2(reps=(2, 2, 2))
+    pot = potential(w)
+    theta = theta_for(wid, pot)
+    m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
+    m.set_params(theta)
+    keep = m.kept_columns()
+    pool = synth.cfg_pool(wid, n_pool, stream=0)
+    test = synth.cfg_pool(wid, n_test, stream=1)
+    rows_pool = om.cfg_rows(_oracle_rows(pot, theta, pool, mode, keep), [c.n for c in pool])
+    A = rows_pool[om.initial_active_set(rows_pool)]
+    nrows_test = _oracle_rows(pot, theta, test, mode, keep)
+    return w, pot, theta, m, keep, test, A, nrows_test
+
+
+@pytest.mark.parametrize("mode", ["full", "linear"])
+def test_cfg_grades_level8(mode):
+    """48 pool configurations give the active set (QR pivoting on the oracle's
+    rows); 40 other configurations of 8..54 atoms in one batch are graded."""
+    w, pot, theta, m, keep, test, A, nrows = _setup(1, mode, 48, 40)
+    sizes = [c.n for c in test]
+    rows_or = om.cfg_rows(nrows, sizes)
+    gam, am, C = om.grades(rows_or, A)
+    m.set_active_set(mode + "_cfg", A)
+    b = api.Batch(test)
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    g = api.grade_cfg(m, b, nb, "fp64", mode + "_cfg", rows=True)
+    rows = g["rows"].cpu().numpy()
+    assert rows.shape == rows_or.shape
+    assert rel_err(rows, rows_or) <= 1e-10
+    kappa = np.linalg.cond(A / np.abs(A).max(axis=0))
+    tol = max(1e-10, kappa * 1e-15)
+    err = float(np.abs(g["gamma"].cpu().numpy() - gam).max() / max(1.0, gam.max()))
+    print(f"{mode}: m {A.shape[0]}, kappa {kappa:.3g}, gamma {gam.min():.3g}..{gam.max():.3g}, rel err {err:.3g}")
+    assert err <= tol
+    srt = np.sort(np.abs(C), axis=1)
+    clear = srt[:, -1] - srt[:, -2] > 1e-8 * srt[:, -1]
+    assert np.array_equal(g["argmax"].cpu().numpy()[clear], am[clear])
+    # the mixed form: FP32 neighborhood rows, FP64 sums and product
+    emul_rows = om.cfg_rows(nrows.astype(np.float32).astype(np.float64), sizes)
+    g_emul = om.grades(emul_rows, A)[0]
+    emul = float((np.abs(g_emul - gam) / np.maximum(1.0, gam)).max())
+    gm = api.grade_cfg(m, b, nb, "mixed", mode + "_cfg")["gamma"].cpu().numpy()
+    err_m = float((np.abs(gm - gam) / np.maximum(1.0, gam)).max())
+    print(f"{mode} mixed: rel err {err_m:.3g} (FP32-row emulation {emul:.3g})")
+    assert err_m <= max(1e-5, 30 * emul)
+
+
+def test_cfg_rows_level16_two_species():
+    """Rows of six alloy configurations (FULL, m = 212) with the level-16
+    potential of workload 2; no active set needed."""
+    w = synth.workload2(reps=(2, 2, 2))
+    pot = potential(w)
+    theta = theta_for(2, pot)
+    m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
+    m.set_params(theta)
+    keep = m.kept_columns()
+    cfgs = synth.cfg_pool(2, 6, stream=2, n_min=8, n_max=40)
+    rows_or = om.cfg_rows(_oracle_rows(pot, theta, cfgs, "full", keep), [c.n for c in cfgs])
+    b = api.Batch(cfgs)
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    rows = api.cfg_rows(m, b, nb, "fp64", "full_cfg").cpu().numpy()
+    assert rel_err(rows, rows_or) <= 1e-10
+    # the species columns count the atoms of each species, exactly
+    counts = np.array([np.bincount(c.types, minlength=2) for c in cfgs], dtype=np.float64)
+    assert np.array_equal(rows[:, :2], counts)
+
+
+def test_cfg_mode_maxvol_matches_oracle():
+    """MaxVol over configurations: the test configurations' oracle rows as
+    candidates against the configuration active set; identical swap logs."""
+    w, pot, theta, m, keep, test, A, nrows = _setup(1, "full", 48, 40)
+    rows = om.cfg_rows(nrows, [c.n for c in test])
+    A_or, cand_or, swaps = om.maxvol(A, rows, threshold=1.001)
+    m.set_active_set("full_cfg", A)
+    cand = torch.as_tensor(rows).cuda().contiguous()
+    sc, sj = api.maxvol_update(m, "full_cfg", cand, threshold=1.001)
+    print(f"{len(swaps)} swaps")
+    assert [(int(a), int(b)) for a, b in zip(sc, sj)] == [(i, j) for i, j, _ in swaps]
+    A_gpu, Ainv = m.get_active_set("full_cfg")
+    assert np.array_equal(A_gpu.cpu().numpy(), A_or)
+    assert np.array_equal(cand.cpu().numpy(), cand_or)
+    # the neighborhood-mode active set is a separate one
+    with pytest.raises(api.MtpError):
+        m.get_active_set("full")
