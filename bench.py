@@ -342,7 +342,8 @@ def extra_workloads(timed):
     """The training workload (level 20, 3 species, 512 uneven configurations:
     loss forward + backward through MTPEnergy) and the active-learning
     snapshots (level 16, 1,048,576 atoms: grades + preselection gamma > 2, FULL
-    and LINEAR) at their full sizes."""
+    and LINEAR) at their full sizes, and configuration-mode grades of 1,024
+    small alloy cells."""
     import torch
 
     from paper_2304_13144_amd import api, synth
@@ -388,6 +389,27 @@ def extra_workloads(timed):
             res[f"active_learning_snapshot{k}_{mode}_fp64"] = {
                 "atoms": cfg.n, "ms_per_step": ms, "grades_per_s": cfg.n / (ms * 1e-3),
                 "selected_gamma_gt_2": int(cnt.item()), "neighbor_build_ms": nbuild}
+    # configuration query mode (Sec. II.C) with workload 2's level-16 potential:
+    # 1,024 small alloy cells graded against 212 configuration rows (the
+    # library's own rows of another pool: a timing input, not a parity one)
+    w2 = synth.workload2(reps=(2, 2, 2))
+    m2 = api.Model.create(w2.level, w2.n_types, w2.r_min, w2.r_cut)
+    m2.set_params(synth.theta_teacher(2, w2.n_types, 92, 4))
+    pool = synth.cfg_pool(2, 212, stream=3)
+    bp = api.Batch(pool)
+    nbp = api.Neighbors().build(m2, bp, max_nbrs=64)
+    m2.set_active_set("full_cfg", api.cfg_rows(m2, bp, nbp, "fp64", "full_cfg"))
+    cfgs = synth.cfg_pool(2, 1024, stream=4)
+    bc = api.Batch(cfgs)
+    nbc = api.Neighbors().build(m2, bc, max_nbrs=64)
+    for prec in ("fp64", "mixed"):
+        ms = timed(lambda: api.grade_cfg(m2, bc, nbc, prec, "full_cfg"))
+        g = api.grade_cfg(m2, bc, nbc, prec, "full_cfg")["gamma"]
+        res[f"cfg_mode_level16_{prec}"] = {
+            "configs": len(cfgs), "atoms": bc.n_atoms, "m": m2.m("full_cfg"), "ms_per_step": ms,
+            "configs_per_s": len(cfgs) / (ms * 1e-3), "atom_steps_per_s": bc.n_atoms / (ms * 1e-3),
+            "gamma_max": float(g.max().item()),
+            "step": "neighborhood rows, per-configuration sums, FP64 grade GEMM (neighbor lists built)"}
     return res
 
 
