@@ -488,6 +488,63 @@ def test_cfg_mode_linear_energies_are_combinations_of_active_energies():
     assert np.allclose(C @ E[act], E, rtol=1e-9, atol=1e-9 * np.abs(E).max())
 
 
+# ------------------------------------- extrapolation-controlled runs -----
+def test_neighborhood_cut_on_simple_cubic_shells():
+    # shells of a simple cubic lattice: 1 + 6 (a), + 12 (sqrt 2 a), + 8 (sqrt 3 a)
+    from oracle import al
+    a = 2.5
+    g = np.array([[i, j, k] for i in range(4) for j in range(4) for k in range(4)], float) * a
+    cell = np.eye(3) * 4 * a
+    grades = np.zeros(len(g))
+    grades[21] = 3.0
+    for cut, n in [(1.01 * a, 7), (1.42 * a, 19), (1.74 * a, 27)]:
+        c, src, shift, p, _ = al.extrapolative_neighborhood(g, np.zeros(len(g), int), cell, (1, 1, 1), grades, cut)
+        assert c == 21 and len(src) == n
+        d = np.linalg.norm(p - g[21], axis=1)
+        assert d.max() < cut and np.isclose(np.sort(d)[1], a)
+    # ties: the lowest index
+    assert al.extrapolative_neighborhood(g, np.zeros(len(g), int), cell, (1, 1, 1), np.ones(len(g)), 1.01 * a)[0] == 0
+
+
+def _md_case():
+    pot, theta, pos, types, cell = _setup(level=8, n_types=2, sigma=0.05)
+    theta = theta.copy()
+    theta[:pot.n_types + pot.n_lin] *= 1e-4   # E is linear in xi: forces of ~1 eV/A instead of ~1e4
+    vel = np.random.default_rng(50).normal(0, 0.01, pos.shape)   # A/fs
+    return pot, theta, pos, types, cell, vel, np.array([60.0, 30.0])
+
+
+def test_md_verlet_is_time_reversible():
+    from oracle import al
+    pot, theta, pos, types, cell, vel, masses = _md_case()
+    fw = al.md_verlet(pot, theta, pos, vel, types, cell, (1, 1, 1), masses, 1.0, 12, None, "full", None, 0, 1e300)
+    bw = al.md_verlet(pot, theta, fw["pos"], -fw["vel"], types, cell, (1, 1, 1), masses, 1.0, 12, None, "full",
+                      None, 0, 1e300)
+    assert np.abs(fw["pos"] - pos).max() > 1e-3
+    assert np.abs(bw["pos"] - pos).max() < 1e-10 and np.abs(bw["vel"] + vel).max() < 1e-12
+
+
+def test_md_verlet_energy_error_is_second_order():
+    from oracle import al
+    pot, theta, pos, types, cell, vel, masses = _md_case()
+    m_at = masses[types]
+
+    def drift(dt, steps):
+        x, v, worst = pos, vel, 0.0
+        E0 = None
+        for _ in range(steps):
+            r = al.md_verlet(pot, theta, x, v, types, cell, (1, 1, 1), masses, dt, 1, None, "full", None, 0, 1e300)
+            x, v = r["pos"], r["vel"]
+            Ep = om.energy_forces_stress(pot, theta, x, types, cell, _nbrs(x, cell))[0]
+            Ek = 0.5 * float((m_at[:, None] * v * v).sum()) / al.EV_PER_A_AMU_IN_A_PER_FS2
+            E0 = (Ep + Ek) if E0 is None else E0
+            worst = max(worst, abs(Ep + Ek - E0))
+        return worst
+
+    e1, e2 = drift(2.0, 8), drift(1.0, 16)
+    assert 2.5 < e1 / e2 < 6.0
+
+
 # -------------------------------------------------------------- maxvol -----
 def test_maxvol_det_ratios_and_local_optimality_exhaustive():
     rng = np.random.default_rng(27)
