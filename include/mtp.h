@@ -234,6 +234,42 @@ int mtp_select(const double *gamma, int64_t n, double threshold, int32_t *idx, i
 int mtp_maxvol_update(mtp_model *m, mtp_grade_mode g, double *cand, int64_t n_cand, double threshold,
                       int32_t max_swaps, int32_t *swap_cand, int32_t *swap_col, int32_t *n_swaps, void *stream);
 
+/* --- extrapolation-controlled runs (Sec. II.F, Sec. III.A) ------------------ */
+
+/* The spherical fragment around the atom of largest grade, for learning on
+ * neighborhoods: that atom (the lowest index among equal maxima) and every
+ * atom or periodic image strictly closer than `cutoff` (e.g. 8 A), as a
+ * non-periodic cluster.  s: one configuration; grades: device [n_atoms]
+ * (e.g. from mtp_grade).  Outputs (device, any may be NULL), ordered by
+ * (source atom, image shift), at most `capacity` entries: pos_out [k*3]
+ * (A, x_j + n.H in the frame of the cell), type_out [k], src_out [k] (source
+ * atom), shift_out [k*3] (n).  *count (host) = entries written (the total
+ * when it fits, else capacity); *center (host, may be NULL) = the central
+ * atom.  Synchronises `stream`. */
+int mtp_cut_neighborhood(const mtp_system *s, const double *grades, double cutoff, int32_t capacity, double *pos_out,
+                         int32_t *type_out, int32_t *src_out, int32_t *shift_out, int32_t *count /* host */,
+                         int32_t *center /* host */, void *stream);
+
+/* Velocity-Verlet molecular dynamics (NVE; A, fs, amu, eV) with
+ * extrapolation control: every configuration, the initial one included, is
+ * graded before its forces are used, gamma(cfg) = max_i gamma_i in the
+ * neighborhood mode g (FULL or LINEAR, needs its active set).  gamma(cfg) <=
+ * gamma_save: go on; gamma_save < gamma(cfg) <= gamma_break: record the
+ * step in saved[] and go on (no step when gamma_save >= gamma_break);
+ * gamma(cfg) > gamma_break: stop (positions are
+ * those of the graded step, velocities half-kicked).  One configuration;
+ * pos must be s->pos (device [n_atoms*3], updated in place), vel device
+ * [n_atoms*3] A/fs (updated); masses host [n_types] amu.  Neighbor lists
+ * are rebuilt every step into nb with max_nbrs.  gamma_hist (host
+ * [n_steps+1] or NULL) receives gamma(cfg) of steps 0..; saved (host
+ * [n_steps+1] or NULL) the recorded steps, *n_saved their number;
+ * *steps_done the completed steps (n_steps unless stopped).  Synchronises
+ * `stream` every step (the grade decides whether to go on). */
+int mtp_md_run(const mtp_model *m, const mtp_system *s, mtp_nbrs *nb, int32_t max_nbrs, double *pos, double *vel,
+               const double *masses /* host */, double dt, int32_t n_steps, mtp_precision p, mtp_grade_mode g,
+               double gamma_save, double gamma_break, double *gamma_hist /* host */, int32_t *saved /* host */,
+               int32_t *n_saved /* host */, int32_t *steps_done /* host */, void *stream);
+
 /* Gradient of the fitting objective (eq. 7) with respect to theta, given
  * the upstream gradients dL/dE [n_cfg], dL/dF [n_atoms*3], dL/dS [n_cfg*9]
  * (any may be NULL = 0): g_theta [n_theta] FP64.  Moments are recomputed;

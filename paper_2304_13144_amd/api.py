@@ -274,6 +274,54 @@ def select(gamma, threshold, capacity=None):
     return idx, cnt
 
 
+def cut_neighborhood(batch, grades, cutoff=8.0, capacity=None):
+    """The spherical fragment (cutoff, A) around the atom of largest grade of a
+    one-configuration batch: dict of pos [k, 3], types, src, shift [k, 3],
+    center."""
+    d = batch.device
+    g = torch.as_tensor(grades, dtype=torch.float64).to(d).contiguous()
+    if capacity is None:   # three times the atoms of the sphere at the cell's mean density, doubled while full
+        vol = abs(float(np.linalg.det(batch.cells[0].cpu().numpy())))
+        cap, grow = int(3 * 4.18879 * cutoff ** 3 * batch.n_atoms / vol) + 64, True
+    else:
+        cap, grow = capacity, False
+    while True:
+        pos = torch.empty((cap, 3), dtype=torch.float64, device=d)
+        typ = torch.empty(cap, dtype=torch.int32, device=d)
+        src = torch.empty(cap, dtype=torch.int32, device=d)
+        sh = torch.empty((cap, 3), dtype=torch.int32, device=d)
+        cnt, ctr = ctypes.c_int32(), ctypes.c_int32()
+        s = batch.system()
+        check(_lib.lib().mtp_cut_neighborhood(ctypes.byref(s), _p(g), float(cutoff), cap, _p(pos), _p(typ), _p(src),
+                                              _p(sh), ctypes.byref(cnt), ctypes.byref(ctr), _stream()))
+        if not grow or cnt.value < cap:
+            break
+        cap *= 2
+    k = cnt.value
+    return {"pos": pos[:k], "types": typ[:k], "src": src[:k], "shift": sh[:k], "center": ctr.value}
+
+
+def md_run(model, batch, nbrs, vel, masses, dt, n_steps, precision="fp64", mode="full", gamma_save=2.0,
+           gamma_break=10.0, max_nbrs=64):
+    """Velocity-Verlet MD with extrapolation control on a one-configuration
+    batch; batch.pos and vel (device [n, 3], A/fs) are updated in place.
+    Returns gamma(cfg) per graded step, the saved steps and the steps done."""
+    assert vel.dtype == torch.float64 and vel.is_contiguous() and vel.device == batch.pos.device
+    m = np.ascontiguousarray(masses, dtype=np.float64)
+    hist = np.full(n_steps + 1, np.nan)   # entries past the last graded step stay NaN
+    saved = np.zeros(n_steps + 1, dtype=np.int32)
+    ns, done = ctypes.c_int32(), ctypes.c_int32()
+    s = batch.system()
+    check(_lib.lib().mtp_md_run(model._h, ctypes.byref(s), nbrs._h, max_nbrs, _p(batch.pos), _p(vel),
+                                m.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(dt), n_steps,
+                                _prec(precision), _mode(mode), float(gamma_save), float(gamma_break),
+                                hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                saved.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(ns),
+                                ctypes.byref(done), _stream()))
+    graded = int(np.count_nonzero(~np.isnan(hist)))
+    return {"gamma": hist[:graded], "saved": saved[:ns.value].tolist(), "steps": done.value}
+
+
 def maxvol_update(model, mode, cand, threshold=1.001, max_swaps=None):
     """Swaps candidate rows (FP64 device [n, m], modified in place) into the active set."""
     m = model.m(mode)
@@ -344,7 +392,7 @@ def compiled_levels():
 
 
 __all__ = ["Model", "Batch", "Neighbors", "energy_forces_stress", "grade", "grade_cfg", "cfg_rows", "evaluate",
-           "b_rows", "select",
+           "b_rows", "select", "cut_neighborhood", "md_run",
            "maxvol_update", "efs_backward", "MTPEnergy", "tune", "CapturedStep", "basis_describe", "compiled_levels", "MtpError"]
 
 

@@ -757,6 +757,118 @@ int mtp_select(const double *gamma, int64_t n, double threshold, int32_t *idx, i
     API_END
 }
 
+int mtp_cut_neighborhood(const mtp_system *s, const double *grades, double cutoff, int32_t capacity, double *pos_out,
+                         int32_t *type_out, int32_t *src_out, int32_t *shift_out, int32_t *count, int32_t *center,
+                         void *stream) {
+    API_BEGIN
+    MTP_CHECK(s && grades && count, MTP_E_INVAL, "NULL argument");
+    MTP_CHECK(s->n_cfg == 1 && s->n_atoms >= 1, MTP_E_INVAL, "one configuration with at least one atom");
+    MTP_CHECK(s->pos && s->type && s->cell, MTP_E_INVAL, "system arrays must not be NULL");
+    MTP_CHECK(cutoff > 0 && std::isfinite(cutoff), MTP_E_INVAL, "cutoff must be positive");
+    MTP_CHECK(capacity >= 0, MTP_E_INVAL, "negative capacity");
+    hipStream_t st = S(stream);
+    double H[9];
+    uint8_t pb[3] = {1, 1, 1};
+    MTP_HIP(hipMemcpyAsync(H, s->cell, sizeof(H), hipMemcpyDeviceToHost, st));
+    if (s->pbc) MTP_HIP(hipMemcpyAsync(pb, s->pbc, sizeof(pb), hipMemcpyDeviceToHost, st));
+    MTP_HIP(hipStreamSynchronize(st));
+    const int per[3] = {pb[0] != 0, pb[1] != 0, pb[2] != 0};
+    static thread_local DevBuf keys, idx, work, scal;
+    scal.ensure(2 * sizeof(int32_t));
+    int32_t *dev = scal.as<int32_t>();   // [0] count, [1] center
+    ProfScope ps("cut", st);
+    cut_fragment(s->pos, s->type, s->n_atoms, H, per, grades, cutoff, capacity, pos_out, type_out, src_out,
+                 shift_out, dev, dev + 1, st, keys, idx, work);
+    int32_t h[2] = {0, 0};
+    MTP_HIP(hipMemcpyAsync(h, dev, sizeof(h), hipMemcpyDeviceToHost, st));
+    MTP_HIP(hipStreamSynchronize(st));
+    *count = h[0];
+    if (center) *center = h[1];
+    API_END
+}
+
+namespace mtp {
+namespace {
+// acceleration of 1 eV/A on 1 amu in A/fs^2: CODATA 2018 elementary charge
+// (exact) over the atomic mass constant, m/s^2 -> A/fs^2
+constexpr double EV_A_AMU = 1.602176634e-19 / 1e-10 / 1.66053906660e-27 * 1e-20;
+
+void throw_nbr_flags(const int32_t *f, int max_nbrs) {
+    MTP_CHECK(!(f[3] & 1), MTP_E_INVAL, "a cell matrix is singular");
+    MTP_CHECK(!(f[3] & 8), MTP_E_INVAL, "an atom type is outside 0..n_types-1");
+    MTP_CHECK(!(f[3] & 2), MTP_E_INVAL, "an image shift exceeds +-127 cells (atoms far outside the cell)");
+    MTP_CHECK(!f[0], MTP_E_CAPACITY,
+              "a neighborhood has " + std::to_string(f[1]) + " atoms, more than max_nbrs = " + std::to_string(max_nbrs));
+    MTP_CHECK(!(f[3] & 4), MTP_E_INVAL, "internal: a reverse pair was not found");
+    MTP_CHECK(!f[2], MTP_E_OVERLAP, "two atoms are closer than 1e-6 Angstrom");
+}
+}  // namespace
+}  // namespace mtp
+
+int mtp_md_run(const mtp_model *m, const mtp_system *s, mtp_nbrs *nb, int32_t max_nbrs, double *pos, double *vel,
+               const double *masses, double dt, int32_t n_steps, mtp_precision p, mtp_grade_mode g,
+               double gamma_save, double gamma_break, double *gamma_hist, int32_t *saved, int32_t *n_saved,
+               int32_t *steps_done, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m && s && nb && pos && vel && masses && n_saved && steps_done, MTP_E_INVAL, "NULL argument");
+    check_system(m, s);
+    MTP_CHECK(s->n_cfg == 1, MTP_E_INVAL, "the MD driver runs one configuration");
+    MTP_CHECK(pos == s->pos, MTP_E_INVAL, "pos must be the system's position array");
+    MTP_CHECK(g == MTP_GRADE_FULL || g == MTP_GRADE_LINEAR, MTP_E_INVAL, "neighborhood grade mode expected");
+    MTP_CHECK(m->act[g].valid, MTP_E_INVAL, "no active set for this grade mode");
+    MTP_CHECK(n_steps >= 0 && dt > 0 && std::isfinite(dt), MTP_E_INVAL, "need n_steps >= 0 and dt > 0");
+    for (int t = 0; t < m->n_types; ++t) MTP_CHECK(masses[t] > 0, MTP_E_INVAL, "masses must be positive");
+    MTP_HIP(hipSetDevice(m->device));
+    hipStream_t st = S(stream);
+    const int64_t n = s->n_atoms;
+    m->md_f.ensure(sizeof(double) * 3 * (size_t)std::max<int64_t>(1, n));
+    m->md_g.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, n));
+    m->md_invm.ensure(sizeof(double) * m->n_types);
+    m->md_scal.ensure(64);
+    std::vector<double> invm(m->n_types);
+    for (int t = 0; t < m->n_types; ++t) invm[t] = 1.0 / masses[t];
+    MTP_HIP(hipMemcpyAsync(m->md_invm.ptr, invm.data(), sizeof(double) * invm.size(), hipMemcpyHostToDevice, st));
+    double *F = m->md_f.as<double>(), *gam = m->md_g.as<double>(), *gmax = m->md_scal.as<double>();
+    const double h = 0.5 * dt * EV_A_AMU;
+    // one step's grading: neighbor lists, forces and grades, gamma(cfg) = max_i gamma_i
+    auto grade = [&]() -> double {
+        build_neighbors(m, s, max_nbrs, nb, st);
+        EvalOut o;
+        o.forces = F;
+        o.gamma = gam;
+        o.mode = g;
+        evaluate(m, s, nb, p, o, st);
+        launch_argmax(gam, n, gmax, nullptr, st);
+        int32_t f[4];
+        double gm = 0.0;
+        MTP_HIP(hipMemcpyAsync(f, nb->flags.ptr, sizeof(f), hipMemcpyDeviceToHost, st));
+        MTP_HIP(hipMemcpyAsync(&gm, gmax, sizeof(double), hipMemcpyDeviceToHost, st));
+        MTP_HIP(hipStreamSynchronize(st));
+        throw_nbr_flags(f, max_nbrs);
+        return gm;
+    };
+    *n_saved = 0;
+    *steps_done = 0;
+    auto record = [&](int step, double gm) -> bool {   // false: stop
+        if (gamma_hist) gamma_hist[step] = gm;
+        if (gm > gamma_break) return false;
+        if (gm > gamma_save) {
+            if (saved) saved[*n_saved] = step;
+            ++*n_saved;
+        }
+        return true;
+    };
+    if (n == 0 || !record(0, grade())) return MTP_OK;
+    for (int step = 1; step <= n_steps; ++step) {
+        launch_md_step(0, n, pos, vel, F, s->type, m->md_invm.as<double>(), h, dt, st);
+        if (!record(step, grade())) break;
+        launch_md_step(1, n, pos, vel, F, s->type, m->md_invm.as<double>(), h, dt, st);
+        *steps_done = step;
+    }
+    MTP_HIP(hipStreamSynchronize(st));
+    API_END
+}
+
 int mtp_maxvol_update(mtp_model *m, mtp_grade_mode g, double *cand, int64_t n_cand, double threshold,
                       int32_t max_swaps, int32_t *swap_cand, int32_t *swap_col, int32_t *n_swaps, void *stream) {
     API_BEGIN

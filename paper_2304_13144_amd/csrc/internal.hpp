@@ -74,6 +74,7 @@ struct mtp_model {
     mutable mtp::DevBuf gbuf, virial, sitebuf, brow, gamma_ws, argmax_ws, work, sums, mbuf, dmbuf, tbuf, dtbuf, rows;
     mutable mtp::DevBuf selblk;     // per-block preselection counts written by the grade kernels
     mutable mtp::DevBuf cfgrows, cfgpart;   // configuration-mode rows and their chunk partials
+    mutable mtp::DevBuf md_f, md_g, md_invm, md_scal;   // MD driver: forces, grades, 1/mass, {gamma max, flags}
     // the configuration modes use the rows of their neighborhood mode (mode & 1)
     int m_of(int mode) const { return (mode & 1) == MTP_GRADE_FULL ? (int)kept.size() : n_types + basis.n_lin(); }
 };
@@ -187,6 +188,18 @@ void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *bl
 void run_maxvol(ActiveSet &as, double *cand, int64_t n_cand, double thr, int max_swaps, int32_t *swap_cand,
                 int32_t *swap_col, int32_t *n_swaps, hipStream_t st, DevBuf &work);
 void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision, void *dst, hipStream_t st);
+// extrapolation-controlled runs: largest value and its lowest index (one
+// block; either output may be NULL); velocity-Verlet half steps (half 0:
+// kick and drift, 1: kick); the spherical fragment around the largest
+// grade: argmax, candidate keys over atoms x image shifts, ordered
+// compaction, gather.  H: host cell (rows = lattice vectors), per: host pbc.
+void launch_argmax(const double *g, int64_t n, double *best, int32_t *where, hipStream_t st);
+void launch_md_step(int half, int64_t n, double *x, double *v, const double *F, const int32_t *type,
+                    const double *inv_m, double h, double dt, hipStream_t st);
+int64_t cut_fragment(const double *pos, const int32_t *type, int64_t n, const double *H, const int *per,
+                     const double *g, double cutoff, int32_t cap, double *pos_out, int32_t *type_out,
+                     int32_t *src_out, int32_t *shift_out, int32_t *count_dev, int32_t *center_dev, hipStream_t st,
+                     DevBuf &keys, DevBuf &idx, DevBuf &work);
 // configuration-mode rows: out [n_cfg][ldb] FP64 = per-configuration sums of
 // the rows [n][ldb] (precision-typed); part: cfg_row_partials_bytes(n, ldb)
 size_t cfg_row_partials_bytes(int64_t n, int ldb);

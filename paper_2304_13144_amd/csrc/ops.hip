@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "device_util.hpp"
 #include "internal.hpp"
@@ -193,6 +194,111 @@ __global__ __launch_bounds__(256) void row_final(const T *rows, int ldb, const d
         }
         out[(int64_t)c * ldb + k] = acc;
     }
+}
+
+// ---- extrapolation-controlled runs ---------------------------------------
+// Largest value of g[0..n) and its lowest index (one block).
+constexpr int AMAX_T = 1024;
+__global__ __launch_bounds__(AMAX_T) void argmax_kernel(const double *g, int64_t n, double *best, int32_t *where) {
+    __shared__ double sv[AMAX_T];
+    __shared__ int64_t si[AMAX_T];
+    double bv = -HUGE_VAL;
+    int64_t bi = n;
+    for (int64_t i = threadIdx.x; i < n; i += AMAX_T) {
+        const double v = g[i];
+        if (v > bv) {   // strided ascending: the first of equal values is kept
+            bv = v;
+            bi = i;
+        }
+    }
+    sv[threadIdx.x] = bv;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int w = AMAX_T / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double ov = sv[threadIdx.x + w];
+            const int64_t oi = si[threadIdx.x + w];
+            if (ov > sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+                sv[threadIdx.x] = ov;
+                si[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (best) *best = sv[0];
+        if (where) *where = (int32_t)si[0];
+    }
+}
+
+// Candidates of the spherical fragment: atom j = t / S and image shift number
+// s = t % S.  The shift counts from the image of j nearest to the center c
+// (per periodic axis the rounded fractional offset w), so n = n' - w with
+// n' in [-K, K] per axis; key = cutoff^2 - |x_j + n H - x_c|^2 (> 0 inside).
+struct CutGeom {
+    double H[9], Hinv[9];   // rows: lattice vectors; Hinv: inverse of H
+    int K[3];               // shift range per axis (0 on non-periodic axes)
+    int per[3];
+};
+__device__ inline void cut_candidate(const CutGeom &G, const double *pos, int64_t j, int c, int64_t s, double r[3],
+                                     int n[3]) {
+    const double d[3] = {pos[3 * j] - pos[3 * c], pos[3 * j + 1] - pos[3 * c + 1], pos[3 * j + 2] - pos[3 * c + 2]};
+    const int w3 = 2 * G.K[2] + 1, w2 = 2 * G.K[1] + 1;
+    const int np[3] = {(int)(s / (w2 * w3)) - G.K[0], (int)((s / w3) % w2) - G.K[1], (int)(s % w3) - G.K[2]};
+    for (int k = 0; k < 3; ++k) {
+        const double f = d[0] * G.Hinv[k] + d[1] * G.Hinv[3 + k] + d[2] * G.Hinv[6 + k];   // fractional offset
+        const int w = G.per[k] ? (int)rint(f) : 0;
+        n[k] = np[k] - w;
+    }
+    for (int a = 0; a < 3; ++a) r[a] = d[a] + n[0] * G.H[a] + n[1] * G.H[3 + a] + n[2] * G.H[6 + a];
+}
+
+__global__ void cut_keys(int64_t n, int64_t S, CutGeom G, const double *pos, const int32_t *center, double cutoff,
+                         double *keys) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * S) return;
+    double r[3];
+    int sh[3];
+    cut_candidate(G, pos, t / S, *center, t % S, r, sh);
+    keys[t] = cutoff * cutoff - (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+}
+
+__global__ void cut_gather(int64_t S, CutGeom G, const double *pos, const int32_t *type, const int32_t *center,
+                           const int32_t *idx, const int32_t *count, double *pos_out, int32_t *type_out,
+                           int32_t *src_out, int32_t *shift_out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= *count) return;
+    const int64_t t = idx[k], j = t / S;
+    const int c = *center;
+    double r[3];
+    int sh[3];
+    cut_candidate(G, pos, j, c, t % S, r, sh);
+    for (int a = 0; a < 3; ++a) {
+        if (pos_out) pos_out[3 * k + a] = pos[3 * j + a] + sh[0] * G.H[a] + sh[1] * G.H[3 + a] + sh[2] * G.H[6 + a];
+        if (shift_out) shift_out[3 * k + a] = sh[a];
+    }
+    if (type_out) type_out[k] = type[j];
+    if (src_out) src_out[k] = (int32_t)j;
+}
+
+// velocity Verlet: v += h F / m (h = dt / 2 times the unit factor), then x += dt v
+__global__ void md_kick_drift(int64_t n, double *x, double *v, const double *F, const int32_t *type,
+                              const double *inv_m, double h, double dt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double im = inv_m[type[i]];
+    for (int a = 0; a < 3; ++a) {
+        const double vi = v[3 * i + a] + h * F[3 * i + a] * im;
+        v[3 * i + a] = vi;
+        x[3 * i + a] += dt * vi;
+    }
+}
+
+__global__ void md_kick(int64_t n, double *v, const double *F, const int32_t *type, const double *inv_m, double h) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double im = inv_m[type[i]];
+    for (int a = 0; a < 3; ++a) v[3 * i + a] += h * F[3 * i + a] * im;
 }
 
 template <typename T>
@@ -387,6 +493,64 @@ void launch_cfg_rows(const void *rows, int precision, int ldb, int64_t n, const 
         hipLaunchKernelGGL(row_final<float>, dim3((unsigned)s->n_cfg), dim3(256), 0, st, r, ldb, part, s->cfg_off,
                            out);
     }
+}
+
+void launch_argmax(const double *g, int64_t n, double *best, int32_t *where, hipStream_t st) {
+    hipLaunchKernelGGL(argmax_kernel, dim3(1), dim3(AMAX_T), 0, st, g, n, best, where);
+}
+
+void launch_md_step(int half, int64_t n, double *x, double *v, const double *F, const int32_t *type,
+                    const double *inv_m, double h, double dt, hipStream_t st) {
+    if (n == 0) return;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (half == 0)
+        hipLaunchKernelGGL(md_kick_drift, grid, dim3(256), 0, st, n, x, v, F, type, inv_m, h, dt);
+    else
+        hipLaunchKernelGGL(md_kick, grid, dim3(256), 0, st, n, v, F, type, inv_m, h);
+}
+
+int64_t cut_fragment(const double *pos, const int32_t *type, int64_t n, const double *H, const int *per,
+                     const double *g, double cutoff, int32_t cap, double *pos_out, int32_t *type_out,
+                     int32_t *src_out, int32_t *shift_out, int32_t *count_dev, int32_t *center_dev, hipStream_t st,
+                     DevBuf &keys, DevBuf &idx, DevBuf &work) {
+    CutGeom G{};
+    for (int k = 0; k < 9; ++k) G.H[k] = H[k];
+    const double det = H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                       H[2] * (H[3] * H[7] - H[4] * H[6]);
+    MTP_CHECK(std::fabs(det) > 1e-12, MTP_E_INVAL, "the cell matrix is singular");
+    // inverse by cofactors (Hinv[r][c] = cof(c, r) / det)
+    G.Hinv[0] = (H[4] * H[8] - H[5] * H[7]) / det;
+    G.Hinv[1] = (H[2] * H[7] - H[1] * H[8]) / det;
+    G.Hinv[2] = (H[1] * H[5] - H[2] * H[4]) / det;
+    G.Hinv[3] = (H[5] * H[6] - H[3] * H[8]) / det;
+    G.Hinv[4] = (H[0] * H[8] - H[2] * H[6]) / det;
+    G.Hinv[5] = (H[2] * H[3] - H[0] * H[5]) / det;
+    G.Hinv[6] = (H[3] * H[7] - H[4] * H[6]) / det;
+    G.Hinv[7] = (H[1] * H[6] - H[0] * H[7]) / det;
+    G.Hinv[8] = (H[0] * H[4] - H[1] * H[3]) / det;
+    int64_t S = 1;
+    for (int k = 0; k < 3; ++k) {
+        // height of the cell along axis k: volume / |a_l x a_m|
+        const double *a = H + 3 * ((k + 1) % 3), *b = H + 3 * ((k + 2) % 3);
+        const double cx = a[1] * b[2] - a[2] * b[1], cy = a[2] * b[0] - a[0] * b[2], cz = a[0] * b[1] - a[1] * b[0];
+        const double h = std::fabs(det) / std::sqrt(cx * cx + cy * cy + cz * cz);
+        G.per[k] = per[k];
+        G.K[k] = per[k] ? (int)std::floor(cutoff / h + 0.5) + 1 : 0;
+        MTP_CHECK(G.K[k] <= 64, MTP_E_INVAL, "the cutoff spans more than 64 cells");
+        S *= 2 * G.K[k] + 1;
+    }
+    const int64_t tot = n * S;
+    MTP_CHECK(tot < ((int64_t)1 << 31), MTP_E_INVAL, "atoms x image shifts must stay below 2^31");
+    keys.ensure(sizeof(double) * (size_t)tot);
+    idx.ensure(sizeof(int32_t) * (size_t)std::max<int32_t>(cap, 1));
+    launch_argmax(g, n, nullptr, center_dev, st);
+    hipLaunchKernelGGL(cut_keys, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, S, G, pos, center_dev,
+                       cutoff, keys.as<double>());
+    launch_select(keys.as<double>(), tot, 0.0, idx.as<int32_t>(), cap, count_dev, st, work);
+    if (cap > 0)
+        hipLaunchKernelGGL(cut_gather, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st, S, G, pos, type,
+                           center_dev, idx.as<int32_t>(), count_dev, pos_out, type_out, src_out, shift_out);
+    return tot;
 }
 
 void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *blk, int32_t *idx, int32_t cap,

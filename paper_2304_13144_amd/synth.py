@@ -194,6 +194,31 @@ def cfg_pool(wid, n_cfg, stream=0, n_min=8, n_max=54):
     return [_vacancy_config(r, kind, int(n), density, n_types, sigma, 0.03) for n in sizes]
 
 
+def fcc111_slab(nx=15, ny=9, layers=6, a=3.615, box_z=40.0, sigma=0.05, stream=0):
+    """FCC(111) slab, periodic along x and y only: a rectangular in-plane cell
+    of d x d sqrt(3) (d = a / sqrt 2, two atoms per layer), ABC stacking at
+    a / sqrt(3) per layer, nx x ny cells per layer, centred in a box of
+    height box_z; displacements N(0, sigma^2).  The defaults give 1,620 atoms
+    in 38.3 x 39.8 x 40 A (six layers of 270)."""
+    d = a / math.sqrt(2.0)
+    dy = d * math.sqrt(3.0)
+    dz = a / math.sqrt(3.0)
+    base = np.array([[0.0, 0.0], [0.5 * d, 0.5 * dy]])
+    pos = []
+    for l in range(layers):
+        off = np.array([0.0, (l % 3) * dy / 3.0])   # A, B, C positions
+        for i in range(nx):
+            for j in range(ny):
+                for b in base:
+                    xy = np.array([i * d, j * dy]) + b + off
+                    pos.append([xy[0], xy[1], 0.5 * box_z + (l - 0.5 * (layers - 1)) * dz])
+    pos = np.array(pos)
+    pos[:, 1] %= ny * dy
+    cell = np.diag([nx * d, ny * dy, box_z])
+    pos = pos + np.random.default_rng([SEED, 6, P_DISPLACE, stream]).normal(0.0, sigma, pos.shape)
+    return Config(pos, np.zeros(len(pos), np.int32), cell, (True, True, False))
+
+
 def workload3(n_cfg=512):
     w = Workload(3, 20, 3, 2.0, 5.5)
     sizes = rng(3, P_SIZES).integers(8, 257, n_cfg)
