@@ -410,6 +410,34 @@ def extra_workloads(timed):
             "configs_per_s": len(cfgs) / (ms * 1e-3), "atom_steps_per_s": bc.n_atoms / (ms * 1e-3),
             "gamma_max": float(g.max().item()),
             "step": "neighborhood rows, per-configuration sums, FP64 grade GEMM (neighbor lists built)"}
+    # extrapolation-controlled MD on the 1,620-atom FCC(111) slab with the
+    # one-species level-16 potential of workload 5 (LINEAR grades against its
+    # active set; gamma_break disabled so every step is timed)
+    slab = synth.fcc111_slab()
+    mp = api.Model.create(16, 1, 2.0, 5.0)
+    th = synth.theta_teacher(5, 1, 92, 4)
+    mp.set_params(th)
+    bs = api.Batch([slab])
+    nbs = api.Neighbors().build(mp, bs, max_nbrs=64)
+    # this teacher was scaled on BCC snapshots: on the FCC slab, scale xi (E is
+    # linear in xi; the LINEAR rows do not depend on it) to max |F| = 0.5 eV/A
+    fmax = float(api.energy_forces_stress(mp, bs, nbs)["forces"].abs().max().item())
+    th[:93] *= min(1.0, 0.5 / max(fmax, 1e-30))
+    mp.set_params(th)
+    mp.set_active_set("linear", np.load(os.path.join(ROOT, "tests", "golden", "active_w5_linear.npy")))
+    vel = torch.as_tensor(np.random.default_rng([230413144, 6, 1, 7]).normal(0.0, 0.002, slab.pos.shape)).cuda()
+    api.md_run(mp, bs, nbs, vel, [63.546], 1.0, 2, "fp64", "linear", 2.0, 1e300)   # warm-up
+    n_md = 50
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = api.md_run(mp, bs, nbs, vel, [63.546], 1.0, n_md, "fp64", "linear", 2.0, 1e300)
+    torch.cuda.synchronize()
+    dt_ms = (time.perf_counter() - t0) * 1e3 / n_md
+    res["md_fcc111_slab_level16_fp64"] = {
+        "atoms": slab.n, "steps": r["steps"], "ms_per_step": dt_ms, "atom_steps_per_s": slab.n / (dt_ms * 1e-3),
+        "teacher_xi_scale": min(1.0, 0.5 / max(fmax, 1e-30)),
+        "gamma_cfg_first_last": [float(r["gamma"][0]), float(r["gamma"][-1])], "saved_steps_gamma_gt_2": len(r["saved"]),
+        "step": "velocity Verlet (dt 1 fs): neighbor rebuild, E/F/S + LINEAR grades, gamma(cfg) to the host"}
     return res
 
 
