@@ -132,6 +132,9 @@ int mtp_info(const mtp_model *m, mtp_model_info *info /* host */);
  * `stream` (the gauge choice is made on the host). */
 int mtp_set_params(mtp_model *m, const double *theta, void *stream);
 
+/* Copies theta (FP64 [n_theta]) to host memory. */
+int mtp_get_params(const mtp_model *m, double *theta /* host */);
+
 /* Columns of theta kept in FULL mode, ascending (host [m_full]). */
 int mtp_kept_columns(const mtp_model *m, int32_t *cols /* host */);
 
@@ -269,6 +272,27 @@ int mtp_md_run(const mtp_model *m, const mtp_system *s, mtp_nbrs *nb, int32_t ma
                const double *masses /* host */, double dt, int32_t n_steps, mtp_precision p, mtp_grade_mode g,
                double gamma_save, double gamma_break, double *gamma_hist /* host */, int32_t *saved /* host */,
                int32_t *n_saved /* host */, int32_t *steps_done /* host */, void *stream);
+
+/* Fitting (Sec. II.B): minimizes the objective of eq. 7,
+ *   L = sum_k [w_e (E_k - E_k^t)^2 + w_f sum_i |F_ik - F_ik^t|^2 + w_s sum_ab (S_abk - S_abk^t)^2],
+ * over theta by BFGS on the inverse Hessian (FP64, host side; the energies,
+ * forces, stresses and dL/dtheta on the device, as mtp_energy_forces_stress
+ * and mtp_efs_backward).  Starting from the model's theta: d = -H g; the
+ * step t is halved from t_0 until L(theta + t d) <= L + 1e-4 t g.d (at most
+ * 40 halvings, else stop); t_0 = min(1, 0.1 / max|g|) on the first
+ * iteration, 1 after; s = t d, y = g_new - g; when y.s > 0, H (I at first,
+ * rescaled to (y.s / y.y) I before the first update) becomes
+ * (I - rho s y^T) H (I - rho y s^T) + rho s s^T, rho = 1 / y.s.  Stops when
+ * max |g| <= gtol or after max_iter iterations.  Targets: device E_t
+ * [n_cfg], F_t [n_atoms*3], S_t [n_cfg*9] (NULL allowed where the weight
+ * is 0).  The neighbor lists must be built for s.  On return the model holds
+ * the last accepted theta (the FULL active sets are invalidated, as by
+ * mtp_set_params); loss_hist (host [max_iter+1] or NULL) receives L at
+ * every accepted iterate, *iters the number of iterations.  Synchronises
+ * `stream` at every evaluation. */
+int mtp_fit_bfgs(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, const double *E_t,
+                 const double *F_t, const double *S_t, double w_e, double w_f, double w_s, int32_t max_iter,
+                 double gtol, double *loss_hist /* host */, int32_t *iters /* host */, void *stream);
 
 /* Gradient of the fitting objective (eq. 7) with respect to theta, given
  * the upstream gradients dL/dE [n_cfg], dL/dF [n_atoms*3], dL/dS [n_cfg*9]

@@ -82,6 +82,11 @@ class Model:
         i = self.info
         return i["m_full"] if _mode(mode) in (MTP_GRADE_FULL, MTP_GRADE_FULL_CFG) else i["m_linear"]
 
+    def theta(self):
+        out = np.zeros(self.info["n_theta"])
+        check(_lib.lib().mtp_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
     def set_params(self, theta):
         t = torch.as_tensor(theta, dtype=torch.float64).to(self.device).contiguous()
         assert t.numel() == self.info["n_theta"]
@@ -322,6 +327,26 @@ def md_run(model, batch, nbrs, vel, masses, dt, n_steps, precision="fp64", mode=
     return {"gamma": hist[:graded], "saved": saved[:ns.value].tolist(), "steps": done.value}
 
 
+def fit_bfgs(model, batch, nbrs, E_t=None, F_t=None, S_t=None, w_e=1.0, w_f=0.01, w_s=0.001, max_iter=50,
+             gtol=1e-10, precision="fp64"):
+    """BFGS on the objective of eq. 7 from the model's theta (which holds the
+    result on return); targets E_t [n_cfg], F_t [n_atoms, 3], S_t [n_cfg, 3, 3].
+    Returns (theta, loss history)."""
+    def prep(t, shape):
+        if t is None:
+            return None
+        return torch.as_tensor(t, dtype=torch.float64).to(batch.device).reshape(shape).contiguous()
+    E_, F_, S_ = prep(E_t, (batch.n_cfg,)), prep(F_t, (batch.n_atoms, 3)), prep(S_t, (batch.n_cfg, 3, 3))
+    hist = np.zeros(max_iter + 1)
+    it = ctypes.c_int32()
+    s = batch.system()
+    check(_lib.lib().mtp_fit_bfgs(model._h, ctypes.byref(s), nbrs._h, _prec(precision), _p(E_), _p(F_), _p(S_),
+                                  float(w_e if E_ is not None else 0.0), float(w_f if F_ is not None else 0.0),
+                                  float(w_s if S_ is not None else 0.0), max_iter, float(gtol),
+                                  hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(it), _stream()))
+    return model.theta(), hist[:it.value + 1]
+
+
 def maxvol_update(model, mode, cand, threshold=1.001, max_swaps=None):
     """Swaps candidate rows (FP64 device [n, m], modified in place) into the active set."""
     m = model.m(mode)
@@ -392,7 +417,7 @@ def compiled_levels():
 
 
 __all__ = ["Model", "Batch", "Neighbors", "energy_forces_stress", "grade", "grade_cfg", "cfg_rows", "evaluate",
-           "b_rows", "select", "cut_neighborhood", "md_run",
+           "b_rows", "select", "cut_neighborhood", "md_run", "fit_bfgs",
            "maxvol_update", "efs_backward", "MTPEnergy", "tune", "CapturedStep", "basis_describe", "compiled_levels", "MtpError"]
 
 

@@ -491,6 +491,13 @@ int mtp_set_params(mtp_model *m, const double *theta, void *stream) {
     API_END
 }
 
+int mtp_get_params(const mtp_model *m, double *theta) {
+    API_BEGIN
+    MTP_CHECK(m && theta, MTP_E_INVAL, "NULL argument");
+    std::copy(m->theta_host.begin(), m->theta_host.end(), theta);
+    API_END
+}
+
 int mtp_kept_columns(const mtp_model *m, int32_t *cols) {
     API_BEGIN
     MTP_CHECK(m && cols, MTP_E_INVAL, "NULL argument");
@@ -866,6 +873,146 @@ int mtp_md_run(const mtp_model *m, const mtp_system *s, mtp_nbrs *nb, int32_t ma
         *steps_done = step;
     }
     MTP_HIP(hipStreamSynchronize(st));
+    API_END
+}
+
+int mtp_fit_bfgs(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, const double *E_t,
+                 const double *F_t, const double *S_t, double w_e, double w_f, double w_s, int32_t max_iter,
+                 double gtol, double *loss_hist, int32_t *iters, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m && s && nb && iters, MTP_E_INVAL, "NULL argument");
+    check_system(m, s);
+    check_nbrs(m, s, nb);
+    MTP_CHECK(p == MTP_FP64 || p == MTP_MIXED, MTP_E_INVAL, "bad precision");
+    MTP_CHECK(w_e >= 0 && w_f >= 0 && w_s >= 0, MTP_E_INVAL, "weights must be non-negative");
+    MTP_CHECK((w_e == 0 || E_t) && (w_f == 0 || F_t) && (w_s == 0 || S_t), MTP_E_INVAL,
+              "a target with a positive weight is NULL");
+    MTP_CHECK(max_iter >= 0, MTP_E_INVAL, "negative max_iter");
+    MTP_HIP(hipSetDevice(m->device));
+    hipStream_t st = S(stream);
+    const int64_t nE = s->n_cfg, nF = 3 * s->n_atoms, nS = 9 * (int64_t)s->n_cfg;
+    const int nth = m->n_theta;
+    m->fit_y.ensure(sizeof(double) * (size_t)(nE + nF + nS));
+    m->fit_g.ensure(sizeof(double) * (size_t)(nE + nF + nS));
+    m->fit_part.ensure(sizeof(double) * (size_t)((nE + 255) / 256 + (nF + 255) / 256 + (nS + 255) / 256 + 3));
+    m->fit_th.ensure(sizeof(double) * nth);
+    double *y = m->fit_y.as<double>(), *gy = m->fit_g.as<double>(), *part = m->fit_part.as<double>();
+    auto set_theta = [&](const std::vector<double> &th) {
+        for (double v : th) MTP_CHECK(std::isfinite(v), MTP_E_INVAL, "theta became NaN or Inf");
+        m->theta_host = th;
+        choose_gauge(m);
+        upload_params(m);
+        m->act[MTP_GRADE_FULL].valid = false;   // FULL rows depend on theta
+        m->act[MTP_GRADE_FULL_CFG].valid = false;
+    };
+    // eq. 7 at theta (forward only); leaves dL/dE, dL/dF, dL/dS on the device
+    auto loss = [&](const std::vector<double> &th) -> double {
+        set_theta(th);
+        EvalOut o;
+        o.energy = y;
+        o.forces = y + nE;
+        o.stress = y + nE + nF;
+        evaluate(m, s, nb, p, o, st);
+        int64_t np = 0;
+        const double *tg[3] = {E_t, F_t, S_t};
+        const double w[3] = {w_e, w_f, w_s};
+        const int64_t off[3] = {0, nE, nE + nF}, len[3] = {nE, nF, nS};
+        for (int k = 0; k < 3; ++k) {
+            if (w[k] > 0)
+                np += launch_fit_residual(len[k], y + off[k], tg[k], w[k], gy + off[k], part + np, st);
+            else
+                launch_zero(gy + off[k], sizeof(double) * (size_t)len[k], st);
+        }
+        std::vector<double> h((size_t)np);
+        if (np) MTP_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+        MTP_HIP(hipStreamSynchronize(st));
+        double f = 0.0;
+        for (double v : h) f += v;
+        return f;
+    };
+    auto grad = [&]() -> std::vector<double> {   // at the theta of the last loss()
+        const int e = mtp_efs_backward(m, s, nb, p, gy, gy + nE, gy + nE + nF, m->fit_th.as<double>(), stream);
+        MTP_CHECK(e == MTP_OK, e, std::string("backward: ") + mtp_last_error());
+        std::vector<double> g(nth);
+        MTP_HIP(hipMemcpyAsync(g.data(), m->fit_th.ptr, sizeof(double) * nth, hipMemcpyDeviceToHost, st));
+        MTP_HIP(hipStreamSynchronize(st));
+        return g;
+    };
+    auto dot = [](const std::vector<double> &a, const std::vector<double> &b) {
+        double r = 0.0;
+        for (size_t k = 0; k < a.size(); ++k) r += a[k] * b[k];
+        return r;
+    };
+    auto amax = [](const std::vector<double> &a) {
+        double r = 0.0;
+        for (double v : a) r = std::max(r, std::fabs(v));
+        return r;
+    };
+    // BFGS on the inverse Hessian with Armijo backtracking (the steps are
+    // described in include/mtp.h)
+    std::vector<double> x = m->theta_host;
+    double f = loss(x);
+    std::vector<double> g = grad();
+    if (loss_hist) loss_hist[0] = f;
+    std::vector<double> H((size_t)nth * nth, 0.0), d(nth), xn(nth), sv(nth), yv(nth), Hy(nth);
+    for (int k = 0; k < nth; ++k) H[(size_t)k * nth + k] = 1.0;
+    bool first = true;
+    int it = 0;
+    for (; it < max_iter; ++it) {
+        if (amax(g) <= gtol) break;
+        for (int r = 0; r < nth; ++r) {
+            double acc = 0.0;
+            for (int c = 0; c < nth; ++c) acc += H[(size_t)r * nth + c] * g[c];
+            d[r] = -acc;
+        }
+        const double slope = dot(g, d);
+        double t = first ? std::min(1.0, 0.1 / amax(g)) : 1.0, fn = 0.0;
+        bool ok = false;
+        for (int h = 0; h < 40; ++h) {
+            for (int k = 0; k < nth; ++k) xn[k] = x[k] + t * d[k];
+            fn = loss(xn);
+            if (fn <= f + 1e-4 * t * slope) {
+                ok = true;
+                break;
+            }
+            t *= 0.5;
+        }
+        if (!ok) break;
+        std::vector<double> gn = grad();
+        for (int k = 0; k < nth; ++k) {
+            sv[k] = xn[k] - x[k];
+            yv[k] = gn[k] - g[k];
+        }
+        const double ys = dot(yv, sv);
+        if (ys > 0) {
+            if (first) {
+                const double sc = ys / dot(yv, yv);
+                std::fill(H.begin(), H.end(), 0.0);
+                for (int k = 0; k < nth; ++k) H[(size_t)k * nth + k] = sc;
+            }
+            // H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T
+            //    = H - rho (s (H y)^T + (H y) s^T) + (rho^2 y.H.y + rho) s s^T   (H symmetric)
+            const double rho = 1.0 / ys;
+            for (int r = 0; r < nth; ++r) {
+                double acc = 0.0;
+                for (int c = 0; c < nth; ++c) acc += H[(size_t)r * nth + c] * yv[c];
+                Hy[r] = acc;
+            }
+            const double yHy = dot(yv, Hy);
+            const double cs = rho * rho * yHy + rho;
+            for (int r = 0; r < nth; ++r)
+                for (int c = 0; c < nth; ++c)
+                    H[(size_t)r * nth + c] += cs * sv[r] * sv[c] - rho * (sv[r] * Hy[c] + Hy[r] * sv[c]);
+            first = false;
+        }
+        x = xn;
+        f = fn;
+        g = gn;
+        if (loss_hist) loss_hist[it + 1] = f;
+    }
+    // the model keeps the last accepted theta
+    if (m->theta_host != x) set_theta(x);
+    *iters = it;
     API_END
 }
 

@@ -75,6 +75,7 @@ struct mtp_model {
     mutable mtp::DevBuf selblk;     // per-block preselection counts written by the grade kernels
     mutable mtp::DevBuf cfgrows, cfgpart;   // configuration-mode rows and their chunk partials
     mutable mtp::DevBuf md_f, md_g, md_invm, md_scal;   // MD driver: forces, grades, 1/mass, {gamma max, flags}
+    mutable mtp::DevBuf fit_y, fit_g, fit_part, fit_th;  // fitting: E/F/S, dL/d(E/F/S), loss partials, dL/dtheta
     // the configuration modes use the rows of their neighborhood mode (mode & 1)
     int m_of(int mode) const { return (mode & 1) == MTP_GRADE_FULL ? (int)kept.size() : n_types + basis.n_lin(); }
 };
@@ -200,6 +201,10 @@ int64_t cut_fragment(const double *pos, const int32_t *type, int64_t n, const do
                      const double *g, double cutoff, int32_t cap, double *pos_out, int32_t *type_out,
                      int32_t *src_out, int32_t *shift_out, int32_t *count_dev, int32_t *center_dev, hipStream_t st,
                      DevBuf &keys, DevBuf &idx, DevBuf &work);
+// fitting: g = 2 w (y - t) and per-256-entry partial sums of w (y - t)^2
+// (returns the number of partials)
+int64_t launch_fit_residual(int64_t n, const double *y, const double *t, double w, double *g, double *part,
+                            hipStream_t st);
 // configuration-mode rows: out [n_cfg][ldb] FP64 = per-configuration sums of
 // the rows [n][ldb] (precision-typed); part: cfg_row_partials_bytes(n, ldb)
 size_t cfg_row_partials_bytes(int64_t n, int ldb);

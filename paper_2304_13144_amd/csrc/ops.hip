@@ -301,6 +301,27 @@ __global__ void md_kick(int64_t n, double *v, const double *F, const int32_t *ty
     for (int a = 0; a < 3; ++a) v[3 * i + a] += h * F[3 * i + a] * im;
 }
 
+// Residual terms of eq. 7 for one kind of target: g = 2 w (y - t) (the
+// upstream gradient dL/dy) and, per block of 256 entries, the partial sum of
+// w (y - t)^2 (added in a fixed tree).
+__global__ __launch_bounds__(256) void fit_residual(int64_t n, const double *y, const double *t, double w, double *g,
+                                                    double *part) {
+    __shared__ double sp[256];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double r = 0.0;
+    if (i < n) {
+        r = y[i] - t[i];
+        g[i] = 2.0 * w * r;
+    }
+    sp[threadIdx.x] = w * r * r;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sp[threadIdx.x] += sp[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sp[0];
+}
+
 template <typename T>
 __global__ void copy_rows(const T *src, int ldb, int m, int64_t n, T *dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -551,6 +572,13 @@ int64_t cut_fragment(const double *pos, const int32_t *type, int64_t n, const do
         hipLaunchKernelGGL(cut_gather, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st, S, G, pos, type,
                            center_dev, idx.as<int32_t>(), count_dev, pos_out, type_out, src_out, shift_out);
     return tot;
+}
+
+int64_t launch_fit_residual(int64_t n, const double *y, const double *t, double w, double *g, double *part,
+                            hipStream_t st) {
+    const int64_t nb = (n + 255) / 256;
+    if (nb) hipLaunchKernelGGL(fit_residual, dim3((unsigned)nb), dim3(256), 0, st, n, y, t, w, g, part);
+    return nb;
 }
 
 void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *blk, int32_t *idx, int32_t cap,

@@ -545,6 +545,25 @@ def test_md_verlet_energy_error_is_second_order():
     assert 2.5 < e1 / e2 < 6.0
 
 
+# ----------------------------------------------------------- fitting -----
+def test_bfgs_minimizes_a_quadratic_and_rosenbrock():
+    from oracle import fit
+    r = np.random.default_rng(70)
+    Q = r.normal(size=(6, 6))
+    Q = Q @ Q.T + 6 * np.eye(6)
+    b = r.normal(size=6)
+    x, hist = fit.bfgs(lambda x: (0.5 * x @ Q @ x - b @ x, Q @ x - b), np.zeros(6), 100, gtol=1e-12)
+    assert np.allclose(x, np.linalg.solve(Q, b), rtol=0, atol=1e-9)
+    assert all(h1 <= h0 for h0, h1 in zip(hist, hist[1:]))
+
+    def rosen(x):
+        f = (1 - x[0]) ** 2 + 100 * (x[1] - x[0] ** 2) ** 2
+        g = np.array([-2 * (1 - x[0]) - 400 * x[0] * (x[1] - x[0] ** 2), 200 * (x[1] - x[0] ** 2)])
+        return f, g
+    x, hist = fit.bfgs(rosen, np.array([-1.2, 1.0]), 500, gtol=1e-10)
+    assert np.allclose(x, [1.0, 1.0], atol=1e-6) and hist[-1] < 1e-12
+
+
 # -------------------------------------------------------------- maxvol -----
 def test_maxvol_det_ratios_and_local_optimality_exhaustive():
     rng = np.random.default_rng(27)
