@@ -410,6 +410,24 @@ def extra_workloads(timed):
             "configs_per_s": len(cfgs) / (ms * 1e-3), "atom_steps_per_s": bc.n_atoms / (ms * 1e-3),
             "gamma_max": float(g.max().item()),
             "step": "neighborhood rows, per-configuration sums, FP64 grade GEMM (neighbor lists built)"}
+    # BFGS fitting of eq. 7 on workload 3 (level 20, 512 configurations):
+    # targets of the teacher from the library (a timing input), student =
+    # teacher perturbed by 1 %, five iterations
+    fit_th = theta * (1.0 + 0.01 * np.random.default_rng([230413144, 3, 2, 9]).normal(size=theta.shape))
+    m.set_params(theta)
+    tgt = api.energy_forces_stress(m, b, nb, "fp64", site_energies=False)
+    for prec in ("fp64", "mixed"):
+        m.set_params(fit_th)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, hist = api.fit_bfgs(m, b, nb, tgt["energy"], tgt["forces"], tgt["stress"], 1.0, 0.01, 0.001, max_iter=5,
+                               precision=prec)
+        torch.cuda.synchronize()
+        it_ms = (time.perf_counter() - t0) * 1e3 / max(1, len(hist) - 1)
+        res[f"fit_bfgs_level20_{prec}"] = {
+            "configs": len(w.configs), "atoms": b.n_atoms, "n_theta": len(theta), "iterations": len(hist) - 1,
+            "ms_per_iteration": it_ms, "loss_first_last": [float(hist[0]), float(hist[-1])],
+            "step": "one BFGS iteration: line-search forward evaluations + one backward, FP64 inverse-Hessian update"}
     # extrapolation-controlled MD on the 1,620-atom FCC(111) slab with the
     # one-species level-16 potential of workload 5 (LINEAR grades against its
     # active set; gamma_break disabled so every step is timed)
