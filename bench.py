@@ -412,8 +412,13 @@ def extra_workloads(timed):
             "step": "neighborhood rows, per-configuration sums, FP64 grade GEMM (neighbor lists built)"}
     # BFGS fitting of eq. 7 on workload 3 (level 20, 512 configurations):
     # targets of the teacher from the library (a timing input), student =
-    # teacher perturbed by 1 %, five iterations
+    # teacher perturbed by 1 %, five iterations; the teacher's own parameter
+    # sizes (0.1 for xi_0 and c, 0.1 lambda / s_alpha for xi_alpha, which span
+    # many decades) as the diagonal scale
     fit_th = theta * (1.0 + 0.01 * np.random.default_rng([230413144, 3, 2, 9]).normal(size=theta.shape))
+    s_alpha, lam = synth.teacher_scales(3)
+    fit_scale = np.concatenate([np.full(w.n_types, 0.1), 0.1 * lam / s_alpha, np.full(len(theta) - w.n_types - n_lin,
+                                                                                        0.1)])
     m.set_params(theta)
     tgt = api.energy_forces_stress(m, b, nb, "fp64", site_energies=False)
     for prec in ("fp64", "mixed"):
@@ -421,7 +426,7 @@ def extra_workloads(timed):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, hist = api.fit_bfgs(m, b, nb, tgt["energy"], tgt["forces"], tgt["stress"], 1.0, 0.01, 0.001, max_iter=5,
-                               precision=prec)
+                               precision=prec, scale=fit_scale)
         torch.cuda.synchronize()
         it_ms = (time.perf_counter() - t0) * 1e3 / max(1, len(hist) - 1)
         res[f"fit_bfgs_level20_{prec}"] = {

@@ -279,11 +279,12 @@ int mtp_md_run(const mtp_model *m, const mtp_system *s, mtp_nbrs *nb, int32_t ma
  * forces, stresses and dL/dtheta on the device, as mtp_energy_forces_stress
  * and mtp_efs_backward).  Starting from the model's theta: d = -H g; the
  * step t is halved from t_0 until L(theta + t d) <= L + 1e-4 t g.d (at most
- * 40 halvings, else stop); t_0 = min(1, 0.1 / max|g|) on the first
- * iteration, 1 after; s = t d, y = g_new - g; when y.s > 0, H (I at first,
- * rescaled to (y.s / y.y) I before the first update) becomes
- * (I - rho s y^T) H (I - rho y s^T) + rho s s^T, rho = 1 / y.s.  Stops when
- * max |g| <= gtol or after max_iter iterations.  Targets: device E_t
+ * 40 halvings, else stop); t_0 = min(1, 0.1 / max|D g|) on the first
+ * iteration, 1 after; s = t d, y = g_new - g; when y.s > 0, H (diag(D^2)
+ * at first, D = scale (host [n_theta], the typical size of each parameter)
+ * or 1 when scale is NULL, rescaled by y.s / y.H.y before the first update)
+ * becomes (I - rho s y^T) H (I - rho y s^T) + rho s s^T, rho = 1 / y.s.
+ * Stops when max |g| <= gtol or after max_iter iterations.  Targets: device E_t
  * [n_cfg], F_t [n_atoms*3], S_t [n_cfg*9] (NULL allowed where the weight
  * is 0).  The neighbor lists must be built for s.  On return the model holds
  * the last accepted theta (the FULL active sets are invalidated, as by
@@ -292,7 +293,8 @@ int mtp_md_run(const mtp_model *m, const mtp_system *s, mtp_nbrs *nb, int32_t ma
  * `stream` at every evaluation. */
 int mtp_fit_bfgs(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, const double *E_t,
                  const double *F_t, const double *S_t, double w_e, double w_f, double w_s, int32_t max_iter,
-                 double gtol, double *loss_hist /* host */, int32_t *iters /* host */, void *stream);
+                 double gtol, const double *scale /* host */, double *loss_hist /* host */,
+                 int32_t *iters /* host */, void *stream);
 
 /* Gradient of the fitting objective (eq. 7) with respect to theta, given
  * the upstream gradients dL/dE [n_cfg], dL/dF [n_atoms*3], dL/dS [n_cfg*9]

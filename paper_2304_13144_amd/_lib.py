@@ -89,7 +89,7 @@ def lib():
         "mtp_cut_neighborhood": [ctypes.POINTER(System), P, D, I32, P, P, P, P, ctypes.POINTER(I32),
                                  ctypes.POINTER(I32), P],
         "mtp_fit_bfgs": [P, ctypes.POINTER(System), P, ctypes.c_int, P, P, P, D, D, D, I32, D, ctypes.POINTER(D),
-                         ctypes.POINTER(I32), P],
+                         ctypes.POINTER(D), ctypes.POINTER(I32), P],
         "mtp_md_run": [P, ctypes.POINTER(System), P, I32, P, P, ctypes.POINTER(D), D, I32, ctypes.c_int, ctypes.c_int,
                        D, D, ctypes.POINTER(D), ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32), P],
         "mtp_efs_backward": [P, ctypes.POINTER(System), P, ctypes.c_int, P, P, P, P, P],

@@ -328,10 +328,12 @@ def md_run(model, batch, nbrs, vel, masses, dt, n_steps, precision="fp64", mode=
 
 
 def fit_bfgs(model, batch, nbrs, E_t=None, F_t=None, S_t=None, w_e=1.0, w_f=0.01, w_s=0.001, max_iter=50,
-             gtol=1e-10, precision="fp64"):
+             gtol=1e-10, precision="fp64", scale=None):
     """BFGS on the objective of eq. 7 from the model's theta (which holds the
-    result on return); targets E_t [n_cfg], F_t [n_atoms, 3], S_t [n_cfg, 3, 3].
+    result on return); targets E_t [n_cfg], F_t [n_atoms, 3], S_t [n_cfg, 3, 3];
+    scale: typical size of each parameter (diagonal preconditioner) or None.
     Returns (theta, loss history)."""
+    sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
     def prep(t, shape):
         if t is None:
             return None
@@ -343,6 +345,7 @@ def fit_bfgs(model, batch, nbrs, E_t=None, F_t=None, S_t=None, w_e=1.0, w_f=0.01
     check(_lib.lib().mtp_fit_bfgs(model._h, ctypes.byref(s), nbrs._h, _prec(precision), _p(E_), _p(F_), _p(S_),
                                   float(w_e if E_ is not None else 0.0), float(w_f if F_ is not None else 0.0),
                                   float(w_s if S_ is not None else 0.0), max_iter, float(gtol),
+                                  None if sc is None else sc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                   hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(it), _stream()))
     return model.theta(), hist[:it.value + 1]
 

@@ -878,7 +878,7 @@ int mtp_md_run(const mtp_model *m, const mtp_system *s, mtp_nbrs *nb, int32_t ma
 
 int mtp_fit_bfgs(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, const double *E_t,
                  const double *F_t, const double *S_t, double w_e, double w_f, double w_s, int32_t max_iter,
-                 double gtol, double *loss_hist, int32_t *iters, void *stream) {
+                 double gtol, const double *scale, double *loss_hist, int32_t *iters, void *stream) {
     API_BEGIN
     MTP_CHECK(m && s && nb && iters, MTP_E_INVAL, "NULL argument");
     check_system(m, s);
@@ -954,8 +954,13 @@ int mtp_fit_bfgs(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_prec
     double f = loss(x);
     std::vector<double> g = grad();
     if (loss_hist) loss_hist[0] = f;
-    std::vector<double> H((size_t)nth * nth, 0.0), d(nth), xn(nth), sv(nth), yv(nth), Hy(nth);
-    for (int k = 0; k < nth; ++k) H[(size_t)k * nth + k] = 1.0;
+    std::vector<double> H((size_t)nth * nth, 0.0), d(nth), xn(nth), sv(nth), yv(nth), Hy(nth), D(nth, 1.0);
+    if (scale)
+        for (int k = 0; k < nth; ++k) {
+            MTP_CHECK(scale[k] > 0 && std::isfinite(scale[k]), MTP_E_INVAL, "scale entries must be positive");
+            D[k] = scale[k];
+        }
+    for (int k = 0; k < nth; ++k) H[(size_t)k * nth + k] = D[k] * D[k];
     bool first = true;
     int it = 0;
     for (; it < max_iter; ++it) {
@@ -966,7 +971,12 @@ int mtp_fit_bfgs(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_prec
             d[r] = -acc;
         }
         const double slope = dot(g, d);
-        double t = first ? std::min(1.0, 0.1 / amax(g)) : 1.0, fn = 0.0;
+        double t = 1.0, fn = 0.0;
+        if (first) {
+            double dg = 0.0;
+            for (int k = 0; k < nth; ++k) dg = std::max(dg, std::fabs(D[k] * g[k]));
+            t = std::min(1.0, 0.1 / dg);
+        }
         bool ok = false;
         for (int h = 0; h < 40; ++h) {
             for (int k = 0; k < nth; ++k) xn[k] = x[k] + t * d[k];
@@ -985,19 +995,22 @@ int mtp_fit_bfgs(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_prec
         }
         const double ys = dot(yv, sv);
         if (ys > 0) {
-            if (first) {
-                const double sc = ys / dot(yv, yv);
-                std::fill(H.begin(), H.end(), 0.0);
-                for (int k = 0; k < nth; ++k) H[(size_t)k * nth + k] = sc;
+            auto hy = [&]() {
+                for (int r = 0; r < nth; ++r) {
+                    double acc = 0.0;
+                    for (int c = 0; c < nth; ++c) acc += H[(size_t)r * nth + c] * yv[c];
+                    Hy[r] = acc;
+                }
+            };
+            hy();
+            if (first) {   // the initial inverse Hessian rescaled by y.s / y.H.y
+                const double sc = ys / dot(yv, Hy);
+                for (double &v : H) v *= sc;
+                hy();
             }
             // H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T
             //    = H - rho (s (H y)^T + (H y) s^T) + (rho^2 y.H.y + rho) s s^T   (H symmetric)
             const double rho = 1.0 / ys;
-            for (int r = 0; r < nth; ++r) {
-                double acc = 0.0;
-                for (int c = 0; c < nth; ++c) acc += H[(size_t)r * nth + c] * yv[c];
-                Hy[r] = acc;
-            }
             const double yHy = dot(yv, Hy);
             const double cs = rho * rho * yHy + rho;
             for (int r = 0; r < nth; ++r)

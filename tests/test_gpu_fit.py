@@ -58,3 +58,21 @@ def test_fit_bfgs_matches_oracle():
     assert abs(hist[-1] - hist_or[-1]) <= 1e-3 * hist_or[-1]
     assert hist[-1] < 0.01 * hist[0]
     assert np.array_equal(m.theta(), th)
+
+
+def test_fit_bfgs_with_parameter_scale_matches_oracle():
+    """The same case with a diagonal scale (the parameters' typical sizes)."""
+    w, pot, cfgs, confs, targets, start = _case()
+    scale = np.abs(start) + 1e-3
+    th_or, hist_or = ofit.fit(pot, start, confs, targets, 1.0, 0.01, 0.001, 10, scale=scale)
+    m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
+    b = api.Batch(cfgs)
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    m.set_params(start)
+    th, hist = api.fit_bfgs(m, b, nb, np.array([t[0] for t in targets]), np.concatenate([t[1] for t in targets]),
+                            np.stack([t[2] for t in targets]), 1.0, 0.01, 0.001, max_iter=10, scale=scale)
+    print("loss gpu   ", np.array2string(hist, precision=8))
+    print("loss oracle", np.array2string(np.array(hist_or), precision=8))
+    assert len(hist) == len(hist_or)
+    assert np.allclose(hist[:6], hist_or[:6], rtol=1e-7, atol=0)
+    assert abs(hist[-1] - hist_or[-1]) <= 1e-3 * hist_or[-1]

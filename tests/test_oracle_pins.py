@@ -564,6 +564,26 @@ def test_bfgs_minimizes_a_quadratic_and_rosenbrock():
     assert np.allclose(x, [1.0, 1.0], atol=1e-6) and hist[-1] < 1e-12
 
 
+def test_bfgs_scale_is_a_change_of_variables():
+    # H_0 = diag(D^2) on x gives the iterates of H_0 = I on u = x / D
+    from oracle import fit
+    D = np.array([1e3, 1.0, 1e-3])
+    Q = np.array([[2.0, 0.3, 0.1], [0.3, 1.0, 0.2], [0.1, 0.2, 3.0]])
+    b = np.array([1.0, -2.0, 0.5])
+
+    def fu(u):   # the quadratic in u
+        return 0.5 * u @ Q @ u - b @ u, Q @ u - b
+
+    def fx(x):   # the same function of x = D u
+        u = x / D
+        f, gu = fu(u)
+        return f, gu / D
+    u, hu = fit.bfgs(fu, np.zeros(3), 8, gtol=0)
+    x, hx = fit.bfgs(fx, np.zeros(3), 8, gtol=0, scale=D)
+    assert np.allclose(hx, hu, rtol=1e-9, atol=1e-14)
+    assert np.allclose(x / D, u, rtol=1e-8, atol=1e-12)
+
+
 # -------------------------------------------------------------- maxvol -----
 def test_maxvol_det_ratios_and_local_optimality_exhaustive():
     rng = np.random.default_rng(27)
