@@ -173,7 +173,7 @@ def main():
         print(profile_summary(*a.profile_summary, kernels=TRAFFIC_KERNELS))
         return 0
     if a.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {a.gpus}); multi-GPU runs are not part of this build",
+        print(f"bench.py runs on exactly one GPU (asked for {a.gpus}); this benchmark measures one GPU only",
               file=sys.stderr)
         return 2
 

@@ -59,7 +59,7 @@ typedef enum {
     MTP_E_SINGULAR = -6,    /* active-set matrix not invertible */
     MTP_E_HIP = -7,         /* HIP runtime error */
     MTP_E_NOMEM = -8,       /* device allocation failed */
-    MTP_E_UNSUPPORTED = -9  /* level / type count not compiled into this build */
+    MTP_E_UNSUPPORTED = -9  /* level / type count not compiled into the library */
 } mtp_status;
 
 typedef enum { MTP_FP64 = 0, MTP_MIXED = 1 } mtp_precision;
@@ -321,7 +321,7 @@ int mtp_tune(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precisio
 /* Description of the basis of a level, one function per line (host). */
 int mtp_basis_describe(int32_t level, char *buf, size_t len, int32_t *n_lin);
 
-/* Levels compiled into this build (host [cap]); returns how many. */
+/* Levels compiled into the library (host [cap]); returns how many. */
 int mtp_compiled_levels(int32_t *levels, int32_t cap);
 
 const char *mtp_last_error(void);

@@ -117,7 +117,7 @@ mtp_model *new_model(int level, int n_types, double r_min, double r_cut, int dev
     MTP_CHECK(r_cut > r_min && r_min >= 0.0, MTP_E_INVAL, "need 0 <= r_min < r_cut");
     auto lv = compiled_levels();
     MTP_CHECK(std::find(lv.begin(), lv.end(), level) != lv.end(), MTP_E_UNSUPPORTED,
-              "level " + std::to_string(level) + " is not compiled into this build");
+              "level " + std::to_string(level) + " is not compiled into this library");
     int ndev = 0;
     MTP_HIP(hipGetDeviceCount(&ndev));
     MTP_CHECK(device >= 0 && device < ndev, MTP_E_INVAL, "bad hip_device");
