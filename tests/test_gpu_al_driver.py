@@ -116,3 +116,20 @@ def test_md_run_stops_above_gamma_break():
     assert want["steps"] == k - 1 and r["steps"] == k - 1
     assert len(r["gamma"]) == k + 1
     assert np.abs(pos - want["pos"]).max() <= 1e-9
+
+
+def test_md_run_without_steps_grades_the_start():
+    w, pot, theta, m, keep, A, cfg, vel = _md_setup()
+    r, pos, v = _gpu_md(m, cfg, vel, 0, 1e300, 1e300)
+    want = oal.md_verlet(pot, theta, cfg.pos, vel, cfg.types, cfg.cell, cfg.pbc, [63.546], 1.0, 0, A, "linear",
+                         keep, 1e300, 1e300)
+    assert r["steps"] == 0 and len(r["gamma"]) == 1
+    assert np.allclose(r["gamma"], want["gamma"], rtol=1e-9, atol=0)
+    assert np.array_equal(pos, cfg.pos) and np.array_equal(v, vel)
+
+
+def test_cut_neighborhood_zero_capacity():
+    cfg = synth.workload1().configs[0]
+    b = api.Batch([cfg])
+    out = api.cut_neighborhood(b, torch.zeros(cfg.n, dtype=torch.float64), 6.5, capacity=0)
+    assert len(out["src"]) == 0 and out["center"] == 0

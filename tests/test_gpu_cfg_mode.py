@@ -117,3 +117,22 @@ def test_cfg_mode_maxvol_matches_oracle():
     # the neighborhood-mode active set is a separate one
     with pytest.raises(api.MtpError):
         m.get_active_set("full")
+
+
+def test_cfg_rows_configurations_spanning_whole_chunks():
+    """Configurations longer than the 64-atom partial-sum chunks (the 128-atom
+    cells of workload 1) between short ones: rows in both modes."""
+    w = synth.workload1()
+    pot = potential(w)
+    theta = theta_for(1, pot)
+    m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
+    m.set_params(theta)
+    keep = m.kept_columns()
+    small = synth.cfg_pool(1, 3, stream=7)
+    cfgs = [small[0], w.configs[0], small[1], synth.workload1_training(2)[1], small[2]]
+    b = api.Batch(cfgs)
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    for mode in ("full", "linear"):
+        rows_or = om.cfg_rows(_oracle_rows(pot, theta, cfgs, mode, keep), [c.n for c in cfgs])
+        rows = api.cfg_rows(m, b, nb, "fp64", mode + "_cfg").cpu().numpy()
+        assert rel_err(rows, rows_or) <= 1e-10, mode
