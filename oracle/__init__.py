@@ -20,6 +20,13 @@ It computes the plain definitions of the paper, slowly and in float64:
 * ``neighbors``  -- the neighborhoods of Sec. II.A by brute force over all
                     atoms and all periodic images (a plain C triple loop with
                     a NumPy twin for tiny inputs).
+* ``al``         -- extrapolation-controlled runs (Sec. II.F, Sec. III.A):
+                    velocity-Verlet MD graded at every step and the
+                    spherical fragment around the atom of largest grade.
+* ``fit``        -- the BFGS minimization of eq. 7 (Sec. II.B).
+
+``mtp.cfg_rows`` gives the configuration-mode rows of Sec. II.C (sums of the
+neighborhood rows).
 
 Every function cites the passage it follows.  Readings of passages where the
 paper is silent are listed in the module docstrings.
