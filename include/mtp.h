@@ -273,6 +273,25 @@ int mtp_md_run(const mtp_model *m, const mtp_system *s, mtp_nbrs *nb, int32_t ma
                double gamma_save, double gamma_break, double *gamma_hist /* host */, int32_t *saved /* host */,
                int32_t *n_saved /* host */, int32_t *steps_done /* host */, void *stream);
 
+/* Structure relaxation with extrapolation control (Sec. III.A, the relax
+ * command): FIRE (Bitzek et al., Phys. Rev. Lett. 97, 170201 (2006); the
+ * paper names no minimizer).  Velocities start at zero; each step: stop if
+ * max_i |F_i| < fmax (eV/A); P = F.v over all 3N components; if P > 0,
+ * v <- (1 - alpha) v + alpha |v| F / |F| and, after more than 5 such steps
+ * in a row, dt <- min(1.1 dt, dt_max), alpha <- 0.99 alpha; else v <- 0,
+ * dt <- dt / 2, alpha <- 0.1 (alpha starts at 0.1, dt at dt0, fs); then
+ * v <- v + dt F / m, x <- x + dt v.  Every configuration, the initial one
+ * included, is graded before its forces are used, with the thresholds of
+ * mtp_md_run (record between gamma_save and gamma_break, stop above).  One
+ * configuration; pos must be s->pos (updated in place); masses host
+ * [n_types] amu.  gamma_hist / saved / n_saved / steps_done as for
+ * mtp_md_run; *converged (host) = 1 when the force tolerance was met. */
+int mtp_relax_fire(const mtp_model *m, const mtp_system *s, mtp_nbrs *nb, int32_t max_nbrs, double *pos,
+                   const double *masses /* host */, double dt0, double dt_max, double fmax, int32_t max_steps,
+                   mtp_precision p, mtp_grade_mode g, double gamma_save, double gamma_break,
+                   double *gamma_hist /* host */, int32_t *saved /* host */, int32_t *n_saved /* host */,
+                   int32_t *steps_done /* host */, int32_t *converged /* host */, void *stream);
+
 /* Fitting (Sec. II.B): minimizes the objective of eq. 7,
  *   L = sum_k [w_e (E_k - E_k^t)^2 + w_f sum_i |F_ik - F_ik^t|^2 + w_s sum_ab (S_abk - S_abk^t)^2],
  * over theta by BFGS on the inverse Hessian (FP64, host side; the energies,

@@ -21,7 +21,7 @@ STATUS = {0: "MTP_OK", -1: "MTP_E_INVAL", -2: "MTP_E_IO", -3: "MTP_E_PARSE", -4:
 EXPORTS = ("mtp_load", "mtp_save", "mtp_create", "mtp_free", "mtp_info", "mtp_set_params", "mtp_get_params", "mtp_kept_columns",
            "mtp_set_active_set", "mtp_get_active_set", "mtp_nbrs_create", "mtp_nbrs_free", "mtp_build_neighbors",
            "mtp_nbrs_status", "mtp_nbrs_export", "mtp_energy_forces_stress", "mtp_grade", "mtp_grade_cfg", "mtp_evaluate",
-           "mtp_evaluate_select", "mtp_b_rows", "mtp_select", "mtp_maxvol_update", "mtp_cut_neighborhood", "mtp_md_run", "mtp_fit_bfgs", "mtp_efs_backward", "mtp_basis_describe",
+           "mtp_evaluate_select", "mtp_b_rows", "mtp_select", "mtp_maxvol_update", "mtp_cut_neighborhood", "mtp_md_run", "mtp_relax_fire", "mtp_fit_bfgs", "mtp_efs_backward", "mtp_basis_describe",
            "mtp_compiled_levels", "mtp_last_error", "mtp_profile_enable", "mtp_profile_read", "mtp_tune")
 
 
@@ -90,6 +90,9 @@ def lib():
                                  ctypes.POINTER(I32), P],
         "mtp_fit_bfgs": [P, ctypes.POINTER(System), P, ctypes.c_int, P, P, P, D, D, D, I32, D, ctypes.POINTER(D),
                          ctypes.POINTER(D), ctypes.POINTER(I32), P],
+        "mtp_relax_fire": [P, ctypes.POINTER(System), P, I32, P, ctypes.POINTER(D), D, D, D, I32, ctypes.c_int,
+                           ctypes.c_int, D, D, ctypes.POINTER(D), ctypes.POINTER(I32), ctypes.POINTER(I32),
+                           ctypes.POINTER(I32), ctypes.POINTER(I32), P],
         "mtp_md_run": [P, ctypes.POINTER(System), P, I32, P, P, ctypes.POINTER(D), D, I32, ctypes.c_int, ctypes.c_int,
                        D, D, ctypes.POINTER(D), ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32), P],
         "mtp_efs_backward": [P, ctypes.POINTER(System), P, ctypes.c_int, P, P, P, P, P],

@@ -327,6 +327,27 @@ def md_run(model, batch, nbrs, vel, masses, dt, n_steps, precision="fp64", mode=
     return {"gamma": hist[:graded], "saved": saved[:ns.value].tolist(), "steps": done.value}
 
 
+def relax_fire(model, batch, nbrs, masses, dt0=1.0, dt_max=10.0, fmax=1e-3, max_steps=1000, precision="fp64",
+               mode="full", gamma_save=2.0, gamma_break=10.0, max_nbrs=64):
+    """FIRE relaxation with extrapolation control of a one-configuration
+    batch (batch.pos updated in place).  Returns gamma(cfg) per graded step,
+    the saved steps, the steps done and whether fmax was reached."""
+    m = np.ascontiguousarray(masses, dtype=np.float64)
+    hist = np.full(max_steps + 1, np.nan)
+    saved = np.zeros(max_steps + 1, dtype=np.int32)
+    ns, done, conv = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    s = batch.system()
+    check(_lib.lib().mtp_relax_fire(model._h, ctypes.byref(s), nbrs._h, max_nbrs, _p(batch.pos),
+                                    m.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(dt0), float(dt_max),
+                                    float(fmax), max_steps, _prec(precision), _mode(mode), float(gamma_save),
+                                    float(gamma_break), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    saved.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(ns),
+                                    ctypes.byref(done), ctypes.byref(conv), _stream()))
+    graded = int(np.count_nonzero(~np.isnan(hist)))
+    return {"gamma": hist[:graded], "saved": saved[:ns.value].tolist(), "steps": done.value,
+            "converged": bool(conv.value)}
+
+
 def fit_bfgs(model, batch, nbrs, E_t=None, F_t=None, S_t=None, w_e=1.0, w_f=0.01, w_s=0.001, max_iter=50,
              gtol=1e-10, precision="fp64", scale=None):
     """BFGS on the objective of eq. 7 from the model's theta (which holds the
@@ -420,7 +441,7 @@ def compiled_levels():
 
 
 __all__ = ["Model", "Batch", "Neighbors", "energy_forces_stress", "grade", "grade_cfg", "cfg_rows", "evaluate",
-           "b_rows", "select", "cut_neighborhood", "md_run", "fit_bfgs",
+           "b_rows", "select", "cut_neighborhood", "md_run", "relax_fire", "fit_bfgs",
            "maxvol_update", "efs_backward", "MTPEnergy", "tune", "CapturedStep", "basis_describe", "compiled_levels", "MtpError"]
 
 

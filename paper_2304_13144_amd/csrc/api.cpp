@@ -876,6 +876,105 @@ int mtp_md_run(const mtp_model *m, const mtp_system *s, mtp_nbrs *nb, int32_t ma
     API_END
 }
 
+int mtp_relax_fire(const mtp_model *m, const mtp_system *s, mtp_nbrs *nb, int32_t max_nbrs, double *pos,
+                   const double *masses, double dt0, double dt_max, double fmax, int32_t max_steps, mtp_precision p,
+                   mtp_grade_mode g, double gamma_save, double gamma_break, double *gamma_hist, int32_t *saved,
+                   int32_t *n_saved, int32_t *steps_done, int32_t *converged, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m && s && nb && pos && masses && n_saved && steps_done && converged, MTP_E_INVAL, "NULL argument");
+    check_system(m, s);
+    MTP_CHECK(s->n_cfg == 1, MTP_E_INVAL, "the relaxation runs one configuration");
+    MTP_CHECK(pos == s->pos, MTP_E_INVAL, "pos must be the system's position array");
+    MTP_CHECK(g == MTP_GRADE_FULL || g == MTP_GRADE_LINEAR, MTP_E_INVAL, "neighborhood grade mode expected");
+    MTP_CHECK(m->act[g].valid, MTP_E_INVAL, "no active set for this grade mode");
+    MTP_CHECK(max_steps >= 0 && dt0 > 0 && dt_max >= dt0 && std::isfinite(dt_max) && fmax >= 0, MTP_E_INVAL,
+              "need max_steps >= 0, 0 < dt0 <= dt_max and fmax >= 0");
+    for (int t = 0; t < m->n_types; ++t) MTP_CHECK(masses[t] > 0, MTP_E_INVAL, "masses must be positive");
+    MTP_HIP(hipSetDevice(m->device));
+    hipStream_t st = S(stream);
+    const int64_t n = s->n_atoms;
+    m->md_f.ensure(sizeof(double) * 3 * (size_t)std::max<int64_t>(1, n));
+    m->md_v.ensure(sizeof(double) * 3 * (size_t)std::max<int64_t>(1, n));
+    m->md_g.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, n));
+    m->md_invm.ensure(sizeof(double) * m->n_types);
+    m->md_scal.ensure(64);
+    std::vector<double> invm(m->n_types);
+    for (int t = 0; t < m->n_types; ++t) invm[t] = 1.0 / masses[t];
+    MTP_HIP(hipMemcpyAsync(m->md_invm.ptr, invm.data(), sizeof(double) * invm.size(), hipMemcpyHostToDevice, st));
+    double *F = m->md_f.as<double>(), *v = m->md_v.as<double>(), *gam = m->md_g.as<double>();
+    double *scal = m->md_scal.as<double>();   // [0] gamma max, [1..4] FIRE norms
+    launch_zero(v, sizeof(double) * 3 * (size_t)std::max<int64_t>(1, n), st);
+    double nrm[4] = {0, 0, 0, 0};
+    // grading of a configuration: neighbor lists, forces and grades, then
+    // gamma(cfg) and the FIRE norms of (F, v) in one read-back
+    auto grade = [&]() -> double {
+        build_neighbors(m, s, max_nbrs, nb, st);
+        EvalOut o;
+        o.forces = F;
+        o.gamma = gam;
+        o.mode = g;
+        evaluate(m, s, nb, p, o, st);
+        launch_argmax(gam, n, scal, nullptr, st);
+        launch_fire_norms(n, F, v, scal + 1, st);
+        int32_t f[4];
+        double h[5];
+        MTP_HIP(hipMemcpyAsync(f, nb->flags.ptr, sizeof(f), hipMemcpyDeviceToHost, st));
+        MTP_HIP(hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, st));
+        MTP_HIP(hipStreamSynchronize(st));
+        throw_nbr_flags(f, max_nbrs);
+        for (int k = 0; k < 4; ++k) nrm[k] = h[1 + k];
+        return h[0];
+    };
+    *n_saved = 0;
+    *steps_done = 0;
+    *converged = 0;
+    auto record = [&](int step, double gm) -> bool {   // false: stop
+        if (gamma_hist) gamma_hist[step] = gm;
+        if (gm > gamma_break) return false;
+        if (gm > gamma_save) {
+            if (saved) saved[*n_saved] = step;
+            ++*n_saved;
+        }
+        return true;
+    };
+    if (n == 0) {
+        *converged = 1;
+        return MTP_OK;
+    }
+    if (!record(0, grade())) return MTP_OK;
+    double dt = dt0, alpha = 0.1;
+    int n_pos = 0;
+    bool stopped = false;
+    for (int step = 1; step <= max_steps; ++step) {
+        if (std::sqrt(nrm[3]) < fmax) {
+            *converged = 1;
+            stopped = true;
+            break;
+        }
+        if (nrm[0] > 0) {   // F.v > 0: turn v towards F
+            launch_fire_mix(n, v, F, 1.0 - alpha, alpha * std::sqrt(nrm[2]) / std::sqrt(nrm[1]), st);
+            if (++n_pos > 5) {
+                dt = std::min(1.1 * dt, dt_max);
+                alpha *= 0.99;
+            }
+        } else {
+            launch_fire_mix(n, v, F, 0.0, 0.0, st);
+            dt *= 0.5;
+            alpha = 0.1;
+            n_pos = 0;
+        }
+        launch_md_step(0, n, pos, v, F, s->type, m->md_invm.as<double>(), dt * EV_A_AMU, dt, st);
+        if (!record(step, grade())) {
+            stopped = true;
+            break;
+        }
+        *steps_done = step;
+    }
+    if (!stopped) *converged = std::sqrt(nrm[3]) < fmax;
+    MTP_HIP(hipStreamSynchronize(st));
+    API_END
+}
+
 int mtp_fit_bfgs(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, const double *E_t,
                  const double *F_t, const double *S_t, double w_e, double w_f, double w_s, int32_t max_iter,
                  double gtol, const double *scale, double *loss_hist, int32_t *iters, void *stream) {

@@ -74,7 +74,8 @@ struct mtp_model {
     mutable mtp::DevBuf gbuf, virial, sitebuf, brow, gamma_ws, argmax_ws, work, sums, mbuf, dmbuf, tbuf, dtbuf, rows;
     mutable mtp::DevBuf selblk;     // per-block preselection counts written by the grade kernels
     mutable mtp::DevBuf cfgrows, cfgpart;   // configuration-mode rows and their chunk partials
-    mutable mtp::DevBuf md_f, md_g, md_invm, md_scal;   // MD driver: forces, grades, 1/mass, {gamma max, flags}
+    mutable mtp::DevBuf md_f, md_g, md_invm, md_scal;   // MD driver: forces, grades, 1/mass, {gamma max, norms}
+    mutable mtp::DevBuf md_v;                           // relaxation: FIRE velocities
     mutable mtp::DevBuf fit_y, fit_g, fit_part, fit_th;  // fitting: E/F/S, dL/d(E/F/S), loss partials, dL/dtheta
     // the configuration modes use the rows of their neighborhood mode (mode & 1)
     int m_of(int mode) const { return (mode & 1) == MTP_GRADE_FULL ? (int)kept.size() : n_types + basis.n_lin(); }
@@ -197,6 +198,9 @@ void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision,
 void launch_argmax(const double *g, int64_t n, double *best, int32_t *where, hipStream_t st);
 void launch_md_step(int half, int64_t n, double *x, double *v, const double *F, const int32_t *type,
                     const double *inv_m, double h, double dt, hipStream_t st);
+// FIRE: out [4] = {F.v, F.F, v.v, max_i |F_i|^2}; v <- a v + b F
+void launch_fire_norms(int64_t n, const double *F, const double *v, double *out, hipStream_t st);
+void launch_fire_mix(int64_t n, double *v, const double *F, double a, double b, hipStream_t st);
 int64_t cut_fragment(const double *pos, const int32_t *type, int64_t n, const double *H, const int *per,
                      const double *g, double cutoff, int32_t cap, double *pos_out, int32_t *type_out,
                      int32_t *src_out, int32_t *shift_out, int32_t *count_dev, int32_t *center_dev, hipStream_t st,

@@ -322,6 +322,45 @@ __global__ __launch_bounds__(256) void fit_residual(int64_t n, const double *y, 
     if (threadIdx.x == 0) part[blockIdx.x] = sp[0];
 }
 
+// FIRE relaxation: out = {F.v, F.F, v.v, max_i |F_i|^2} over all atoms (one
+// block, fixed reduction order), and the velocity mixing v <- a v + b F.
+constexpr int FIRE_T = 1024;
+__global__ __launch_bounds__(FIRE_T) void fire_norms(int64_t n, const double *F, const double *v, double *out) {
+    __shared__ double s[4][FIRE_T];
+    double p = 0.0, ff = 0.0, vv = 0.0, fm = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += FIRE_T) {
+        double fi = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double f = F[3 * i + a], u = v[3 * i + a];
+            p += f * u;
+            fi += f * f;
+            vv += u * u;
+        }
+        ff += fi;
+        fm = fmax(fm, fi);
+    }
+    s[0][threadIdx.x] = p;
+    s[1][threadIdx.x] = ff;
+    s[2][threadIdx.x] = vv;
+    s[3][threadIdx.x] = fm;
+    __syncthreads();
+    for (int w = FIRE_T / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s[0][threadIdx.x] += s[0][threadIdx.x + w];
+            s[1][threadIdx.x] += s[1][threadIdx.x + w];
+            s[2][threadIdx.x] += s[2][threadIdx.x + w];
+            s[3][threadIdx.x] = fmax(s[3][threadIdx.x], s[3][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void fire_mix(int64_t n3, double *v, const double *F, double a, double b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n3) v[i] = a * v[i] + b * F[i];
+}
+
 template <typename T>
 __global__ void copy_rows(const T *src, int ldb, int m, int64_t n, T *dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -579,6 +618,15 @@ int64_t launch_fit_residual(int64_t n, const double *y, const double *t, double 
     const int64_t nb = (n + 255) / 256;
     if (nb) hipLaunchKernelGGL(fit_residual, dim3((unsigned)nb), dim3(256), 0, st, n, y, t, w, g, part);
     return nb;
+}
+
+void launch_fire_norms(int64_t n, const double *F, const double *v, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(fire_norms, dim3(1), dim3(FIRE_T), 0, st, n, F, v, out);
+}
+
+void launch_fire_mix(int64_t n, double *v, const double *F, double a, double b, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(fire_mix, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0, st, 3 * n, v, F, a, b);
 }
 
 void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *blk, int32_t *idx, int32_t cap,

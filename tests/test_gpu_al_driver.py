@@ -133,3 +133,26 @@ def test_cut_neighborhood_zero_capacity():
     b = api.Batch([cfg])
     out = api.cut_neighborhood(b, torch.zeros(cfg.n, dtype=torch.float64), 6.5, capacity=0)
     assert len(out["src"]) == 0 and out["center"] == 0
+
+
+
+def test_relax_fire_matches_oracle():
+    """FIRE from a displaced workload-1 cell (xi scaled as in the MD tests):
+    the same positions after 25 steps (no convergence in that time, so both
+    sides take every step) and the same grades and saved steps."""
+    w, pot, theta, m, keep, A, cfg, _ = _md_setup()
+    start = cfg.pos + np.random.default_rng(63).normal(0.0, 0.03, cfg.pos.shape)
+    probe = oal.relax_fire(pot, theta, start, cfg.types, cfg.cell, cfg.pbc, [63.546], 1.0, 10.0, 0.0, 25, A, "linear",
+                           keep, 1e300, 1e300)
+    save = float(np.median(probe["gamma"]))
+    want = oal.relax_fire(pot, theta, start, cfg.types, cfg.cell, cfg.pbc, [63.546], 1.0, 10.0, 0.0, 25, A, "linear",
+                          keep, save, 1e300)
+    b = api.Batch([synth.Config(start, cfg.types, cfg.cell, cfg.pbc)])
+    r = api.relax_fire(m, b, api.Neighbors(), [63.546], 1.0, 10.0, 0.0, 25, "fp64", "linear", save, 1e300)
+    pos = b.pos.cpu().numpy()
+    print(f"gamma(cfg): {np.round(want['gamma'][:6], 4).tolist()} ..., saved {len(want['saved'])}, "
+          f"moved {np.abs(want['pos'] - start).max():.3g} A")
+    assert r["steps"] == want["steps"] == 25 and not r["converged"]
+    assert np.abs(pos - want["pos"]).max() <= 1e-9
+    assert np.allclose(r["gamma"], want["gamma"], rtol=1e-9, atol=0)
+    assert _same_saved(r["saved"], want["saved"], want["gamma"], save, 1e300)

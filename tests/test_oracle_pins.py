@@ -584,6 +584,28 @@ def test_bfgs_scale_is_a_change_of_variables():
     assert np.allclose(x / D, u, rtol=1e-8, atol=1e-12)
 
 
+def test_fire_finds_the_minimum_of_a_harmonic_well_and_stays_there():
+    # F = -k (x - x0) per atom (k in eV/A^2): FIRE must end at x0; started
+    # there, it takes no step
+    from oracle import al
+    r = np.random.default_rng(52)
+    x0 = r.normal(0, 3.0, (20, 3))
+    k = r.uniform(0.5, 5.0, 20)[:, None]
+    inv_m = 1.0 / r.uniform(1.0, 200.0, 20)
+    out = al.fire(x0 + r.normal(0, 0.3, x0.shape), inv_m, lambda x: -k * (x - x0), lambda x: 0.0, 1.0, 10.0, 1e-6,
+                  5000, 2.0, 10.0)
+    assert out["converged"] and np.abs(out["pos"] - x0).max() < 1e-6 / k.min()
+    again = al.fire(x0, inv_m, lambda x: -k * (x - x0), lambda x: 0.0, 1.0, 10.0, 1e-6, 10, 2.0, 10.0)
+    assert again["converged"] and again["steps"] == 0
+    # the grade hooks: every configuration graded, saved and stopped by the thresholds
+    grades = iter(np.linspace(0.5, 20.0, 100))
+    out = al.fire(x0 + 0.3, inv_m, lambda x: -k * (x - x0), lambda x: next(grades), 1.0, 10.0, 1e-12, 100, 2.0, 10.0)
+    g = np.linspace(0.5, 20.0, 100)
+    first_break = int(np.argmax(g > 10.0))
+    assert out["steps"] == first_break - 1 and len(out["gamma"]) == first_break + 1
+    assert out["saved"] == [k for k in range(first_break) if g[k] > 2.0]
+
+
 # -------------------------------------------------------------- maxvol -----
 def test_maxvol_det_ratios_and_local_optimality_exhaustive():
     rng = np.random.default_rng(27)
