@@ -461,6 +461,17 @@ def extra_workloads(timed):
         "teacher_xi_scale": min(1.0, 0.5 / max(fmax, 1e-30)),
         "gamma_cfg_first_last": [float(r["gamma"][0]), float(r["gamma"][-1])], "saved_steps_gamma_gt_2": len(r["saved"]),
         "step": "velocity Verlet (dt 1 fs): neighbor rebuild, E/F/S + LINEAR grades, gamma(cfg) to the host"}
+    # FIRE relaxation of the same slab from its displaced start (50 steps)
+    bs2 = api.Batch([slab])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = api.relax_fire(mp, bs2, api.Neighbors(), [63.546], 1.0, 10.0, 0.0, 50, "fp64", "linear", 2.0, 1e300)
+    torch.cuda.synchronize()
+    dt_ms = (time.perf_counter() - t0) * 1e3 / max(1, r["steps"])
+    res["relax_fire_fcc111_slab_level16_fp64"] = {
+        "atoms": slab.n, "steps": r["steps"], "ms_per_step": dt_ms, "atom_steps_per_s": slab.n / (dt_ms * 1e-3),
+        "step": "FIRE step: mixing, Euler step, neighbor rebuild, E/F/S + LINEAR grades, norms and gamma(cfg) to "
+                "the host"}
     return res
 
 
