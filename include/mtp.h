@@ -99,7 +99,8 @@ typedef struct {
     int64_t contraction_flops;  /* flops of the contraction program per neighborhood */
 } mtp_model_info;
 
-/* A batch of configurations (all pointers device memory). */
+/* A batch of configurations (all pointers device memory; pos and type may
+ * be NULL when n_atoms is 0). */
 typedef struct {
     int32_t n_cfg;
     int64_t n_atoms;

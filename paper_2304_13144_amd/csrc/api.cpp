@@ -152,7 +152,8 @@ void set_active(mtp_model *m, int mode, const double *A_dev, hipStream_t st) {
 void check_system(const mtp_model *m, const mtp_system *s) {
     MTP_CHECK(s, MTP_E_INVAL, "system is NULL");
     MTP_CHECK(s->n_cfg >= 1 && s->n_atoms >= 0, MTP_E_INVAL, "need n_cfg >= 1 and n_atoms >= 0");
-    MTP_CHECK(s->cfg_off && s->pos && s->type && s->cell, MTP_E_INVAL, "system arrays must not be NULL");
+    MTP_CHECK(s->cfg_off && s->cell, MTP_E_INVAL, "system arrays must not be NULL");
+    MTP_CHECK(s->n_atoms == 0 || (s->pos && s->type), MTP_E_INVAL, "positions and types must not be NULL");
     MTP_CHECK(s->n_atoms < (int64_t)1 << 31, MTP_E_INVAL, "at most 2^31-1 atoms per call");
     (void)m;
 }

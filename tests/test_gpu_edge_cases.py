@@ -1,0 +1,93 @@
+"""Degenerate inputs through the C ABI, against the oracle: a configuration
+without atoms inside a batch, a batch without atoms, a one-atom periodic
+cell (all neighbors are its own images), an isolated atom (no neighbors)
+and a non-periodic dimer.  FP64 bar 1e-10 relative (absolute where the
+oracle's value is zero)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mtp as om
+from oracle import neighbors as onb
+from paper_2304_13144_amd import api, synth
+from tests.helpers import active_rows, potential, theta_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _model():
+    w = synth.workload1()
+    pot = potential(w)
+    theta = theta_for(1, pot)
+    m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
+    m.set_params(theta)
+    m.set_active_set("linear", active_rows(1, "linear"))
+    return w, pot, theta, m
+
+
+def _oracle(pot, theta, c):
+    pairs = onb.neighbors(c.pos, c.cell, c.pbc, pot.r_cut)
+    E, F, S, V = om.energy_forces_stress(pot, theta, c.pos, c.types, c.cell, pairs)
+    rows = om.linear_rows(pot, theta, c.pos, c.types, c.cell, pairs)
+    return E, F, S, V, rows
+
+
+def _close(a, b, tol=1e-10):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    scale = max(np.abs(b).max() if b.size else 0.0, 1e-300)
+    return b.size == 0 or np.abs(a - b).max() <= tol * max(scale, 1.0)
+
+
+def _cases():
+    one = synth.Config(np.array([[0.3, 0.2, 0.1]]), np.array([0], np.int32), np.eye(3) * 2.9)
+    iso = synth.Config(np.array([[5.0, 5.0, 5.0]]), np.array([0], np.int32), np.eye(3) * 30.0, (False, False, False))
+    dimer = synth.Config(np.array([[4.0, 4.0, 4.0], [6.3, 4.1, 3.9]]), np.array([0, 0], np.int32), np.eye(3) * 20.0,
+                         (False, False, False))
+    return {"one_atom_periodic": one, "isolated_atom": iso, "dimer": dimer}
+
+
+@pytest.mark.parametrize("name", ["one_atom_periodic", "isolated_atom", "dimer"])
+def test_degenerate_cells_match_oracle(name):
+    w, pot, theta, m = _model()
+    c = _cases()[name]
+    E, F, S, V, rows = _oracle(pot, theta, c)
+    b = api.Batch([c])
+    nb = api.Neighbors().build(m, b, max_nbrs=96)
+    out = api.evaluate(m, b, nb, "fp64", "linear")
+    g = api.grade(m, b, nb, "fp64", "linear", rows=True)
+    assert _close(out["energy"].cpu().numpy()[0], E)
+    assert _close(out["site_e"].cpu().numpy(), V)
+    assert np.abs(out["forces"].cpu().numpy() - F).max() <= 1e-10 * max(1.0, np.abs(F).max())
+    assert np.abs(out["stress"].cpu().numpy()[0] - S).max() <= 1e-10 * max(1.0, np.abs(S).max())
+    assert _close(g["rows"].cpu().numpy(), rows)
+    gam = om.grades(rows, active_rows(1, "linear"))[0]
+    assert _close(g["gamma"].cpu().numpy(), gam, 1e-9)
+
+
+def test_batch_with_an_empty_configuration():
+    w, pot, theta, m = _model()
+    small = synth.cfg_pool(1, 2, stream=8)
+    empty = synth.Config(np.zeros((0, 3)), np.zeros(0, np.int32), np.eye(3) * 10.0)
+    cfgs = [small[0], empty, small[1]]
+    b = api.Batch(cfgs)
+    nb = api.Neighbors().build(m, b, max_nbrs=96)
+    out = api.evaluate(m, b, nb, "fp64", "linear")
+    E = out["energy"].cpu().numpy()
+    S = out["stress"].cpu().numpy()
+    assert E[1] == 0.0 and np.all(S[1] == 0.0)
+    for k in (0, 2):
+        Ek, Fk, Sk, _, _ = _oracle(pot, theta, cfgs[k])
+        assert _close(E[k], Ek)
+        assert np.abs(S[k] - Sk).max() <= 1e-10 * max(1.0, np.abs(Sk).max())
+    cg = api.cfg_rows(m, b, nb, "fp64", "linear_cfg").cpu().numpy()
+    assert np.all(cg[1] == 0.0)
+
+
+def test_batch_without_atoms():
+    w, pot, theta, m = _model()
+    empty = synth.Config(np.zeros((0, 3)), np.zeros(0, np.int32), np.eye(3) * 10.0)
+    b = api.Batch([empty, empty])
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    out = api.evaluate(m, b, nb, "fp64", "linear", gamma_save=2.0)
+    assert np.all(out["energy"].cpu().numpy() == 0.0) and np.all(out["stress"].cpu().numpy() == 0.0)
+    assert int(out["sel_count"].item()) == 0
