@@ -289,11 +289,11 @@ def main():
                            "tflops": gf * cfg.n / max(gus * 1e-6, 1e-12) / 1e12}
     dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"])
     d = per_kernel[dom]
-    rocprof_name = {"efs_moments": f"efs_moments<{'double' if prec == 'fp64' else 'float'}, {level}, {tuned[prec]}>",
+    rocprof_name = {"efs_moments": f"efs_moments<{'double' if prec == 'fp64' else 'float'}, {level}, {tuned[prec][0]}>",
                     "efs_moments_contract": f"efs_moments_contract<{'double' if prec == 'fp64' else 'float'}, {level}, "
                                             "true>",
                     "efs_contract": f"efs_contract<{'double' if prec == 'fp64' else 'float'}, {level}, true>",
-                    "efs_forces": f"efs_forces_rows<{'double' if prec == 'fp64' else 'float'}, {level}, {tuned[prec]}>",
+                    "efs_forces": f"efs_forces_rows<{'double' if prec == 'fp64' else 'float'}, {level}, {tuned[prec][1]}>",
                     "grade": "grade_f64" if prec == "fp64" else "grade_bf16<3>"}[dom]
     traffic = recorded_traffic(rocprof_name)
     out = {
@@ -315,7 +315,7 @@ def main():
                    "pairs_per_atom": pairs_per_atom,
                    "step": "evaluate(E, F, S, site energies, b rows, gamma, argmax) + preselection gamma > 2 (fused) "
                            "on a built neighbor list",
-                   "lanes_per_neighborhood": tuned[prec]},
+                   "lanes_per_neighborhood": {"moments_contraction": tuned[prec][0], "pair_gradients": tuned[prec][1]}},
         "with_rebuild": {"atom_steps_per_s": r["with_rebuild_atom_steps_per_s"],
                          "ms_per_step": r["with_rebuild_ms_per_step"],
                          "neighbor_build_us": r["kernels"]["neighbors"]["avg_us"]},

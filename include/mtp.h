@@ -331,10 +331,13 @@ int mtp_efs_backward(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb
 int mtp_profile_enable(int on);
 int mtp_profile_read(const char *kernel, double *total_ms /* host */, int64_t *launches /* host */);
 
-/* Autotuner: times the evaluation of this system with 2, 4 and 8 lanes per
- * neighborhood (HIP events, 3 repetitions after a warm-up), keeps the
- * fastest for this model, precision and size class (floor(log2 n_atoms)),
- * and returns it in *lanes (host).  Synchronises `stream`. */
+/* Autotuner: times the evaluation of this system under nine schedules --
+ * 2, 4 or 8 lanes per neighborhood for the moments / contraction (4: one
+ * fused launch) and, independently, for the pair gradients -- (HIP events,
+ * 3 repetitions after a warm-up), keeps the fastest for this model,
+ * precision and size class (floor(log2 n_atoms)) and returns it in *lanes
+ * (host) as 16 x (moments / contraction lanes) + (pair-gradient lanes).
+ * Synchronises `stream`. */
 int mtp_tune(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
              int32_t *lanes /* host */, void *stream);
 

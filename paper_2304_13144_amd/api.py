@@ -419,12 +419,13 @@ class MTPEnergy(torch.autograd.Function):
 
 
 def tune(model, batch, nbrs, precision="fp64", mode="full"):
-    """Runs the library's autotuner for this system; returns the chosen lanes per neighborhood."""
+    """Runs the library's autotuner for this system; returns the chosen lanes
+    per neighborhood as (moments / contraction, pair gradients)."""
     lanes = ctypes.c_int32()
     s = batch.system()
     check(_lib.lib().mtp_tune(model._h, ctypes.byref(s), nbrs._h, _prec(precision), _mode(mode), ctypes.byref(lanes),
                               _stream()))
-    return lanes.value
+    return lanes.value >> 4, lanes.value & 15
 
 
 def basis_describe(level):

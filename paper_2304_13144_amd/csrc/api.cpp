@@ -170,17 +170,18 @@ int size_bucket(int64_t n) {
     return b;
 }
 
+// schedule = 16 x (moments / contraction lanes) + (pair-gradient lanes)
 int lanes_for(const mtp_model *m, int64_t n, int prec) {
     if (m->force_lanes) return m->force_lanes;
     if (const char *e = std::getenv("MTP_LANES")) {
         int v = std::atoi(e);
-        if (v == 2 || v == 4 || v == 8) return v;
+        if (v == 2 || v == 4 || v == 8) return 17 * v;
     }
     if (int t = m->tuned_lanes[prec == MTP_FP64 ? 0 : 1][size_bucket(n)]) return t;
     // enough wavefronts for 256 CUs x 4 SIMDs, few lanes when the batch is large
-    if (n >= (int64_t)1 << 20) return 2;
-    if (n >= (int64_t)1 << 17) return 4;
-    return 8;
+    if (n >= (int64_t)1 << 20) return 17 * 2;
+    if (n >= (int64_t)1 << 17) return 17 * 4;
+    return 17 * 8;
 }
 
 struct EvalOut {
@@ -251,7 +252,9 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     a.colmap = m->colmap.as<int32_t>();
     a.m = mm;
     a.precision = prec;
-    a.lanes = lanes_for(m, n, prec);
+    const int sched = lanes_for(m, n, prec);
+    a.lanes = sched & 15;
+    a.lanes_mc = sched >> 4;
     a.stream = st;
     m->mbuf.ensure(tsz * m->basis.n_comp() * (size_t)n);
     m->dmbuf.ensure(tsz * m->basis.n_comp() * (size_t)n);
@@ -743,6 +746,7 @@ int mtp_b_rows(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_
     a.m = mm;
     a.precision = MTP_FP64;
     a.lanes = 4;
+    a.lanes_mc = 4;
     a.stream = S(stream);
     m->mbuf.ensure(sizeof(double) * m->basis.n_comp() * (size_t)n_idx);
     m->dmbuf.ensure(sizeof(double) * m->basis.n_comp() * (size_t)n_idx);
@@ -1188,6 +1192,7 @@ int mtp_efs_backward(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb
     a.c = th + tsz * (m->n_types + m->basis.n_lin());
     a.precision = p;
     a.lanes = 4;
+    a.lanes_mc = 4;
     a.stream = st;
     a.mbuf = m->mbuf.ptr;
     a.dmbuf = m->dmbuf.ptr;
@@ -1241,8 +1246,9 @@ int mtp_tune(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precisio
     int best = 0;
     float best_ms = 0.f;
     try {
-        for (int lanes : {2, 4, 8}) {
-            m->force_lanes = lanes;
+        for (int sched : {17 * 2, 17 * 4, 17 * 8, 16 * 4 + 2, 16 * 4 + 8, 16 * 2 + 4, 16 * 8 + 4, 16 * 2 + 8,
+                          16 * 8 + 2}) {
+            m->force_lanes = sched;
             evaluate(m, s, nb, p, o, st);   // warm-up (workspaces, caches)
             MTP_HIP(hipEventRecord(e0, st));
             for (int r = 0; r < 3; ++r) evaluate(m, s, nb, p, o, st);
@@ -1251,7 +1257,7 @@ int mtp_tune(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precisio
             float ms = 0.f;
             MTP_HIP(hipEventElapsedTime(&ms, e0, e1));
             if (!best || ms < best_ms) {
-                best = lanes;
+                best = sched;
                 best_ms = ms;
             }
         }

@@ -604,11 +604,10 @@ template <int L, typename T> int launch_efs_level_t(const EfsArgs &a);
 // instantiates the launchers of one level and one arithmetic type (each
 // (level, type) pair is a translation unit of its own, generated at build time)
 #define MTP_EFS_LEVEL_T(LEVEL, TT)                                                                       \
-    template <typename T, int K, bool WB> static void launch_efs_tk##LEVEL(const EfsArgs &a) {           \
-        const int per = 256 / K;                                                                         \
-        const unsigned grid = (unsigned)((a.n_atoms + per - 1) / per);                                   \
+    /* moments and contraction, K lanes per neighborhood (K = 4: one fused launch) */                    \
+    template <typename T, int K, bool WB> static void launch_mc##LEVEL(const EfsArgs &a) {               \
+        const unsigned grid = (unsigned)((a.n_atoms + 256 / K - 1) / (256 / K));                         \
         const unsigned grid1 = (unsigned)((a.n_atoms + 63) / 64);                                        \
-        if (grid == 0) return;                                                                           \
         if (K == 4) {                                                                                    \
             ProfScope ps("efs_moments", a.stream);                                                       \
             hipLaunchKernelGGL((efs_moments_contract<T, LEVEL, WB>), dim3(grid1), dim3(256), 0, a.stream, \
@@ -621,17 +620,25 @@ template <int L, typename T> int launch_efs_level_t(const EfsArgs &a);
             ProfScope ps("efs_contract", a.stream);                                                      \
             hipLaunchKernelGGL((efs_contract<T, LEVEL, WB>), dim3(grid1), dim3(256), 0, a.stream, a);    \
         }                                                                                                \
-        {                                                                                                \
-            ProfScope ps("efs_forces", a.stream);                                                        \
-            hipLaunchKernelGGL((efs_forces_rows<T, LEVEL, K>), dim3(WB ? 2 * grid : grid), dim3(256), 0,  \
-                               a.stream, a, (int64_t)grid);                                              \
-        }                                                                                                \
+    }                                                                                                    \
+    /* pair gradients and virial (+ the rest of the rows), K lanes per neighborhood */                   \
+    template <typename T, int K, bool WB> static void launch_fr##LEVEL(const EfsArgs &a) {               \
+        const unsigned grid = (unsigned)((a.n_atoms + 256 / K - 1) / (256 / K));                         \
+        ProfScope ps("efs_forces", a.stream);                                                            \
+        hipLaunchKernelGGL((efs_forces_rows<T, LEVEL, K>), dim3(WB ? 2 * grid : grid), dim3(256), 0,      \
+                           a.stream, a, (int64_t)grid);                                                  \
     }                                                                                                    \
     template <typename T, bool WB> static void launch_efs_t##LEVEL(const EfsArgs &a) {                   \
+        if (a.n_atoms == 0) return;                                                                      \
+        switch (a.lanes_mc) {                                                                            \
+            case 2: launch_mc##LEVEL<T, 2, WB>(a); break;                                                \
+            case 4: launch_mc##LEVEL<T, 4, WB>(a); break;                                                \
+            default: launch_mc##LEVEL<T, 8, WB>(a); break;                                               \
+        }                                                                                                \
         switch (a.lanes) {                                                                               \
-            case 2: launch_efs_tk##LEVEL<T, 2, WB>(a); break;                                            \
-            case 4: launch_efs_tk##LEVEL<T, 4, WB>(a); break;                                            \
-            default: launch_efs_tk##LEVEL<T, 8, WB>(a); break;                                           \
+            case 2: launch_fr##LEVEL<T, 2, WB>(a); break;                                                \
+            case 4: launch_fr##LEVEL<T, 4, WB>(a); break;                                                \
+            default: launch_fr##LEVEL<T, 8, WB>(a); break;                                               \
         }                                                                                                \
     }                                                                                                    \
     template <> int launch_efs_level_t<LEVEL, TT>(const EfsArgs &a) {                                    \

@@ -68,8 +68,9 @@ struct mtp_model {
     std::vector<int> colmap_host;   // full column -> kept column or -1
     mtp::DevBuf theta64, theta32, colmap;
     mtp::ActiveSet act[4];          // indexed by mtp_grade_mode: neighborhood and configuration modes
+    // schedules: 16 x (lanes of the moments / contraction) + (lanes of the pair gradients)
     int force_lanes = 0;            // set while the tuner times a schedule
-    int tuned_lanes[2][48] = {};    // [precision][floor(log2 n_atoms)] -> lanes per neighborhood, 0 = untuned
+    int tuned_lanes[2][48] = {};    // [precision][floor(log2 n_atoms)] -> schedule, 0 = untuned
     // scratch of the evaluation path
     mutable mtp::DevBuf gbuf, virial, sitebuf, brow, gamma_ws, argmax_ws, work, sums, mbuf, dmbuf, tbuf, dtbuf, rows;
     mutable mtp::DevBuf selblk;     // per-block preselection counts written by the grade kernels
@@ -124,7 +125,8 @@ struct EfsArgs {
     const int32_t *colmap;    // full column -> kept column or -1
     int m;                    // row length written (kept columns)
     int precision;
-    int lanes;                // lanes per neighborhood (2, 4, 8)
+    int lanes;                // lanes per neighborhood of the pair-gradient / row kernel (2, 4, 8)
+    int lanes_mc;             // lanes per neighborhood of the moments / contraction (2, 4, 8; 4 = one launch)
     void *mbuf, *dmbuf;       // [NC][n_atoms] T: moments and dV/dM between the kernels
     hipStream_t stream;
 };
