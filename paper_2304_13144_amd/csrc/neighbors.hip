@@ -393,6 +393,77 @@ __device__ inline unsigned test_window(const Window &W, int n, const Centre &c, 
     return in;
 }
 
+// One-window form of the test: the candidates' chunks are unrolled and the
+// per-species counts come from ballots (scalar popcounts), so no separate
+// counting pass is needed.  in / tb as for test_window.
+template <int NT>
+__device__ inline unsigned test_count(const Window &W, int n, const Centre &c, int lane, double d2max, unsigned &tb,
+                                      int (&cnt)[MAX_TYPES], Flags &fl) {
+    unsigned in = 0;
+    tb = 0;
+#pragma unroll
+    for (int cc = 0; cc < PS_CC; ++cc) {
+        if (cc * 64 < n) {   // wave-uniform
+            const int e = cc * 64 + lane;
+            bool ok = false;
+            unsigned t = 0;
+            if (e < n) {
+                const int o = W.lo[e];
+                const double r0 = (W.x[e] - c.y0) + W.qh[o][0], r1 = (W.y[e] - c.y1) + W.qh[o][1],
+                             r2 = (W.z[e] - c.y2) + W.qh[o][2];
+                const double d2 = r0 * r0 + r1 * r1 + r2 * r2;
+                t = (unsigned)W.qt[e] >> 30;
+                ok = d2 <= d2max && W.jq[e] != c.i;   // not the atom itself (same image)
+                if (ok && d2 < 1e-12) fl.overlap = true;
+            }
+            if (ok) {
+                in |= 1u << cc;
+                tb |= t << (2 * cc);
+            }
+#pragma unroll
+            for (int s = 0; s < NT; ++s) cnt[s] += __popcll(__ballot(ok && t == (unsigned)s));
+        }
+    }
+    return in;
+}
+
+// One-window neighborhoods: an accepted candidate of species t goes to list
+// offset base[t] + (accepted candidates of species t before it), kept if
+// below cap[t] (the rank within a chunk is mbcnt on the chunk's ballot of
+// species t); the list offset is below PS_WIN, so perm is indexed by it
+// directly (no compaction) and every offset below the capped total gets
+// exactly one candidate, in candidate order within each species group.
+template <int NT>
+__device__ inline void place_chunks(unsigned in, unsigned tb, int n, int lane, const int (&cap)[MAX_TYPES],
+                                    const int (&base)[MAX_TYPES], short *perm) {
+    int run[NT];
+#pragma unroll
+    for (int s = 0; s < NT; ++s) run[s] = 0;
+#pragma unroll
+    for (int cc = 0; cc < PS_CC; ++cc) {
+        if (cc * 64 < n) {   // wave-uniform
+            const bool a = (in >> cc) & 1u;
+            const int t = (tb >> (2 * cc)) & 3;
+            unsigned long long mk = 0ull;
+            int r = 0, cp = 0, bs = 0;
+#pragma unroll
+            for (int s = 0; s < NT; ++s) {
+                const unsigned long long m = __ballot(a && t == s);
+                if (t == s) {
+                    mk = m;
+                    r = run[s];
+                    cp = cap[s];
+                    bs = base[s];
+                }
+                run[s] += __popcll(m);
+            }
+            const int k = r + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
+            if (a && k < cp) perm[bs + k] = (short)(cc * 64 + lane);
+        }
+    }
+}
+
 // per-species counts of the accepted candidates (wave-uniform)
 __device__ inline void count_window(unsigned in, unsigned tb, int n, int n_types, int (&cnt)[MAX_TYPES]) {
     for (int cc = 0; cc * 64 < n; ++cc) {
@@ -452,36 +523,6 @@ __device__ inline void write_kept(const Window &W, const short *perm_e, const in
         jout[slot] = jq >= 0 ? jq : ~jq;
         if (sh0 < -127 || sh0 > 127 || sh1 < -127 || sh1 > 127 || sh2 < -127 || sh2 > 127) fl.wide = true;
         shout[slot] = (sh0 & 0xff) | ((sh1 & 0xff) << 8) | ((sh2 & 0xff) << 16) | (0xff << 24);
-    }
-}
-
-// One-window neighborhoods: the list offset base[t] + rank of an accepted
-// candidate is below PS_WIN, so perm is indexed by it directly (no
-// compaction): every offset below the capped total gets exactly one
-// candidate, in candidate order within each species group.
-__device__ inline void place_direct(unsigned in, unsigned tb, int n, int n_types, int lane,
-                                    const int (&cap)[MAX_TYPES], const int (&base)[MAX_TYPES], short *perm) {
-    const unsigned long long below = (1ull << lane) - 1ull;
-    int run[MAX_TYPES] = {0, 0, 0, 0};
-    for (int cc = 0; cc * 64 < n; ++cc) {
-        const bool a = (in >> cc) & 1u;
-        const int t = (tb >> (2 * cc)) & 3;
-        unsigned long long mine = 0ull;
-        int my_run = 0, my_cap = 0, my_base = 0;
-#pragma unroll
-        for (int s = 0; s < MAX_TYPES; ++s) {
-            if (s >= n_types) break;
-            const unsigned long long mk = __ballot(a && t == s);
-            if (t == s) {
-                mine = mk;
-                my_run = run[s];
-                my_cap = cap[s];
-                my_base = base[s];
-            }
-            run[s] += __popcll(mk);
-        }
-        const int k = my_run + __popcll(mine & below);
-        if (a && k < my_cap) perm[my_base + k] = (short)(cc * 64 + lane);
     }
 }
 
@@ -613,12 +654,11 @@ __global__ __launch_bounds__(256) void pair_search(const int32_t *nbins_dev, int
                 for (int k = 0; k < na; ++k) {
                     const Centre c = centre(k);
                     unsigned tb;
-                    const unsigned in = test_window(W, A0.total, c, lane, d2max, tb, fl);
                     int cnt[MAX_TYPES] = {0, 0, 0, 0}, cap[MAX_TYPES], base[MAX_TYPES];
+                    const unsigned in = test_count<NT>(W, A0.total, c, lane, d2max, tb, cnt, fl);
                     int tot;
-                    count_window(in, tb, A0.total, n_types, cnt);
                     list_layout(cnt, n_types, max_nbrs, cap, base, tot);
-                    place_direct(in, tb, A0.total, n_types, lane, cap, base, perm_e[wave]);
+                    place_chunks<NT>(in, tb, A0.total, lane, cap, base, perm_e[wave]);
                     const int kept = tot < max_nbrs ? tot : max_nbrs;
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
