@@ -211,8 +211,10 @@ int mtp_evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mt
  * threshold in ascending order and *count (device int32) their number, at
  * most `capacity`.  The grade kernel counts the selected rows of each block
  * of rows as it writes gamma, so only the placement remains (one launch
- * instead of mtp_select's two).  gamma may be NULL (grades kept internally);
- * needs the active set of `g`.  idx and count must not be NULL. */
+ * instead of mtp_select's two), and that launch also gathers the forces and
+ * finishes the per-configuration sums.  Results equal mtp_evaluate's bit for
+ * bit.  gamma may be NULL (grades kept internally); needs the active set of
+ * `g`.  idx and count must not be NULL. */
 int mtp_evaluate_select(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p,
                         mtp_grade_mode g, double *energy, double *forces, double *stress, double *site_e,
                         double *gamma, int32_t *argmax, double threshold, int32_t *idx, int32_t capacity,

@@ -260,23 +260,31 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     m->dmbuf.ensure(tsz * m->basis.n_comp() * (size_t)n);
     a.mbuf = m->mbuf.ptr;
     a.dmbuf = m->dmbuf.ptr;
+    // per-configuration sums: chunk partials, then one block per configuration.
+    // With forces and a preselection the force gather runs as extra blocks of
+    // the preselection's launch (one launch less per step) and the partials
+    // come from the pair-gradient kernel; otherwise the gather (or a kernel of
+    // their own) writes them.
+    const bool want_sums = o.energy || want_v;
+    const double *sum_e = o.energy ? site : nullptr;
+    const double *sum_v = want_v ? m->virial.as<double>() : nullptr;
+    if (want_sums) m->sums.ensure(cfg_partials_bytes(n));
+    const bool fuse_gather = want_f && want_sel;
+    if (fuse_gather && want_sums) {
+        a.part = m->sums.as<double>();
+        a.part_e = sum_e;
+    }
     int e;
     {
         ProfScope ps("efs", st);
         e = launch_efs(m->level, a);
     }
     MTP_CHECK(e == 0, MTP_E_HIP, std::string("efs kernel launch: ") + hipGetErrorString((hipError_t)e));
-    // per-configuration sums: chunk partials (in the force gather when forces
-    // are wanted), then one block per configuration
-    const bool want_sums = o.energy || want_v;
-    const double *sum_e = o.energy ? site : nullptr;
-    const double *sum_v = want_v ? m->virial.as<double>() : nullptr;
-    if (want_sums) m->sums.ensure(cfg_partials_bytes(n));
-    if (want_f) {
+    if (want_f && !fuse_gather) {
         ProfScope ps("force_gather", st);
         launch_force_gather(nb, m->gbuf.ptr, prec, o.forces, st, sum_e, sum_v,
                             want_sums ? m->sums.as<double>() : nullptr);
-    } else if (want_sums) {
+    } else if (want_sums && !fuse_gather) {
         launch_cfg_partials(n, sum_e, sum_v, m->sums.as<double>(), st);
     }
     // with a preselection the sums are finished by the preselection's launch
@@ -299,8 +307,9 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
         }
         if (want_sel) {
             ProfScope ps("select", st);
+            const GatherArgs ga = fuse_gather ? gather_args(nb, m->gbuf.ptr, prec, o.forces) : GatherArgs{};
             launch_select_write(gam, n, o.sel_thr, blk, o.sel_idx, o.sel_cap, o.sel_count, st,
-                                want_sums ? &sums : nullptr);
+                                want_sums ? &sums : nullptr, fuse_gather ? &ga : nullptr);
         }
     }
     if (o.b_rows) launch_copy_rows(m->brow.ptr, ldb, mm, n, prec, o.b_rows, st);

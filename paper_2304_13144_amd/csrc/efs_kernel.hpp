@@ -19,6 +19,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "device_util.hpp"
 #include "internal.hpp"
 
 namespace mtp {
@@ -593,10 +594,20 @@ template <typename T, int L, int K>
 __global__ __launch_bounds__(256) void efs_forces_rows(const EfsArgs a, int64_t nblk) {
     __shared__ T c_s[Level<L>::NRAD * MAX_TYPES * MAX_TYPES * NPOLY];
     __shared__ T s_dm[Level<L>::NC][256 / K];
-    if ((int64_t)blockIdx.x < nblk)
+    if ((int64_t)blockIdx.x < nblk) {
         efs_forces_body<T, L, K>(a, blockIdx.x, c_s, s_dm);
-    else
+        if (a.part) {   // uniform: the block's atoms are whole sum chunks (256 / K = 32, 64 or 128)
+            constexpr int PER = 256 / K / SUM_CHUNK;
+            static_assert(PER * SUM_CHUNK * K == 256, "chunks per block");
+            for (int q = 0; q < PER; ++q) {
+                const int64_t chunk = (int64_t)blockIdx.x * PER + q;
+                __syncthreads();   // the block's virials are written; sp of the previous chunk is read
+                if (chunk * SUM_CHUNK < a.n_atoms) chunk_partials(chunk, a.n_atoms, a.part_e, a.virial, a.part);
+            }
+        }
+    } else {
         efs_rows_body<T, L, K>(a, (int64_t)blockIdx.x - nblk, s_dm);
+    }
 }
 
 template <int L, typename T> int launch_efs_level_t(const EfsArgs &a);

@@ -128,6 +128,10 @@ struct EfsArgs {
     int lanes;                // lanes per neighborhood of the pair-gradient / row kernel (2, 4, 8)
     int lanes_mc;             // lanes per neighborhood of the moments / contraction (2, 4, 8; 4 = one launch)
     void *mbuf, *dmbuf;       // [NC][n_atoms] T: moments and dV/dM between the kernels
+    // optional (atom_list NULL only): the pair-gradient blocks also write the
+    // per-32-atom partial sums of part_e (V_i, nullable) and virial into part
+    double *part;
+    const double *part_e;
     hipStream_t stream;
 };
 int launch_efs(int level, const EfsArgs &a);
@@ -187,8 +191,21 @@ struct CfgSums {
     const double *site_e, *virial, *part;
     double *energy, *stress;
 };
+// the force gather as extra blocks of the same launch (forces from the pair
+// gradients; independent of the grade)
+struct GatherArgs {
+    int64_t n = 0;
+    int nt = 0, maxn = 0;
+    const int32_t *tcnt = nullptr, *rev = nullptr;
+    const void *g = nullptr;
+    int precision = 0;
+    double *F = nullptr;
+    int64_t blocks = 0;
+};
+GatherArgs gather_args(const mtp_nbrs *nb, const void *gbuf, int precision, double *forces);
 void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *blk, int32_t *idx, int32_t cap,
-                         int32_t *count, hipStream_t st, const CfgSums *sums = nullptr);
+                         int32_t *count, hipStream_t st, const CfgSums *sums = nullptr,
+                         const GatherArgs *gather = nullptr);
 void run_maxvol(ActiveSet &as, double *cand, int64_t n_cand, double thr, int max_swaps, int32_t *swap_cand,
                 int32_t *swap_col, int32_t *n_swaps, hipStream_t st, DevBuf &work);
 void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision, void *dst, hipStream_t st);

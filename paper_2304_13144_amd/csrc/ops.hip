@@ -16,38 +16,6 @@ __global__ void zero_kernel(uint32_t *p, size_t n_words) {
     if (i < n_words) p[i] = 0u;
 }
 
-// Partial sums of eq. 1 over chunks of SUM_CHUNK consecutive atoms:
-// part[chunk][0] = sum V_i, part[chunk][1 + k] = sum W_i,k (virial component
-// k), zero where the input is NULL.  Called by a whole block of 256 threads
-// for one chunk: wavefront w takes atoms 8 w .. 8 w + 7 of the chunk, lane l
-// atom l / 8 and the values l % 8 and 8 + l % 8; shuffles add the eight
-// atoms of a wavefront, then the four wavefronts are added in order.
-constexpr int SUM_CHUNK = 32;
-__device__ inline void chunk_partials(int64_t chunk, int64_t n, const double *site_e, const double *vir,
-                                      double *part) {
-    __shared__ double sp[4][10];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, s = lane & 7;
-    const int64_t i = chunk * SUM_CHUNK + 8 * w + (lane >> 3);
-    double v0 = 0.0, v1 = 0.0;   // value s and value 8 + s (0: V_i, 1 + k: W_i,k)
-    if (i < n) {
-        if (s == 0) v0 = site_e ? site_e[i] : 0.0;
-        else v0 = vir ? vir[9 * i + s - 1] : 0.0;
-        if (s < 2) v1 = vir ? vir[9 * i + 7 + s] : 0.0;
-    }
-#pragma unroll
-    for (int o = 8; o < 64; o <<= 1) {
-        v0 += __shfl_xor(v0, o, 64);
-        v1 += __shfl_xor(v1, o, 64);
-    }
-    if (lane < 8) sp[w][lane] = v0;
-    if (lane < 2) sp[w][8 + lane] = v1;
-    __syncthreads();
-    if (threadIdx.x < 10) {
-        const int t = threadIdx.x;
-        part[chunk * 10 + t] = ((sp[0][t] + sp[1][t]) + sp[2][t]) + sp[3][t];
-    }
-}
-
 // F_l = sum_{p in list(l)} (g_p - g_rev(p)): the first sum is -dV_l/dx_l, the
 // second collects dV_i/dx_l over every neighborhood i that holds l (or an
 // image of l).  FG_LANES lanes per atom, a fixed shuffle tree at the end, no
@@ -56,11 +24,10 @@ __device__ inline void chunk_partials(int64_t chunk, int64_t n, const double *si
 constexpr int FG_LANES = 8;
 static_assert(256 / FG_LANES == SUM_CHUNK, "one force_gather block per sum chunk");
 template <typename T>
-__global__ __launch_bounds__(256) void force_gather(int64_t n, int nt, int maxn, const int32_t *tcnt,
-                                                    const int32_t *rev, const T *g, double *F, const double *site_e,
-                                                    const double *vir, double *part) {
+__device__ inline void gather_block(int64_t blk, int64_t n, int nt, int maxn, const int32_t *tcnt,
+                                    const int32_t *rev, const T *g, double *F) {
     const int sub = threadIdx.x % FG_LANES;
-    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / FG_LANES;
+    const int64_t i = (blk * blockDim.x + threadIdx.x) / FG_LANES;
     const bool live = i < n;
     int tot = 0;
     if (live)
@@ -97,6 +64,13 @@ __global__ __launch_bounds__(256) void force_gather(int64_t n, int nt, int maxn,
         F[3 * i + 1] = fy;
         F[3 * i + 2] = fz;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void force_gather(int64_t n, int nt, int maxn, const int32_t *tcnt,
+                                                    const int32_t *rev, const T *g, double *F, const double *site_e,
+                                                    const double *vir, double *part) {
+    gather_block<T>(blockIdx.x, n, nt, maxn, tcnt, rev, g, F);
     if (part) chunk_partials(blockIdx.x, n, site_e, vir, part);   // uniform branch
 }
 
@@ -428,17 +402,30 @@ __device__ inline void select_write_wave(int64_t gb, int64_t nb, const double *g
 // four preselection blocks per block of 256 threads; with n_cfg > 0 the
 // first n_cfg blocks add the configuration sums instead (one launch for both
 // at the end of the evaluation)
+// blocks [0, n_cfg): configuration sums; [n_cfg, n_cfg + ga.blocks): the
+// force gather (GatherArgs; it waits for nothing the grade writes, and its
+// own launch would cost more than its blocks); the rest: one wavefront per
+// GRADE_ROWS rows of the preselection.
 template <bool SCANNED>
 __global__ __launch_bounds__(256) void select_write(const double *g, int64_t n, double thr, const int32_t *blk,
                                                     int32_t *idx, int32_t cap, int32_t *count, int n_cfg,
                                                     const int64_t *cfg_off, const double *site_e, const double *vir,
-                                                    const double *part, double *energy, double *stress) {
+                                                    const double *part, double *energy, double *stress,
+                                                    const GatherArgs ga) {
     if ((int)blockIdx.x < n_cfg) {
         cfg_final_block(blockIdx.x, cfg_off, site_e, vir, part, energy, stress);
         return;
     }
+    const int64_t b = (int64_t)blockIdx.x - n_cfg;
+    if (b < ga.blocks) {
+        if (ga.precision == MTP_FP64)
+            gather_block<double>(b, ga.n, ga.nt, ga.maxn, ga.tcnt, ga.rev, static_cast<const double *>(ga.g), ga.F);
+        else
+            gather_block<float>(b, ga.n, ga.nt, ga.maxn, ga.tcnt, ga.rev, static_cast<const float *>(ga.g), ga.F);
+        return;
+    }
     const int64_t nb = (n + GRADE_ROWS - 1) / GRADE_ROWS;
-    const int64_t gb = ((int64_t)blockIdx.x - n_cfg) * 4 + (threadIdx.x >> 6);
+    const int64_t gb = (b - ga.blocks) * 4 + (threadIdx.x >> 6);
     if (gb < nb) select_write_wave<SCANNED>(gb, nb, g, n, thr, blk, idx, cap, count);
 }
 
@@ -629,8 +616,23 @@ void launch_fire_mix(int64_t n, double *v, const double *F, double a, double b, 
     hipLaunchKernelGGL(fire_mix, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0, st, 3 * n, v, F, a, b);
 }
 
+GatherArgs gather_args(const mtp_nbrs *nb, const void *gbuf, int precision, double *forces) {
+    GatherArgs ga{};
+    ga.n = nb->n_atoms;
+    ga.nt = nb->n_types;
+    ga.maxn = nb->max_nbrs;
+    ga.tcnt = nb->tcnt.as<int32_t>();
+    ga.rev = nb->rev.as<int32_t>();
+    ga.g = gbuf;
+    ga.precision = precision;
+    ga.F = forces;
+    ga.blocks = (ga.n * FG_LANES + 255) / 256;
+    return ga;
+}
+
 void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *blk, int32_t *idx, int32_t cap,
-                         int32_t *count, hipStream_t st, const CfgSums *sums) {
+                         int32_t *count, hipStream_t st, const CfgSums *sums, const GatherArgs *gather) {
+    const GatherArgs ga = gather ? *gather : GatherArgs{};
     const int n_cfg = sums ? sums->s->n_cfg : 0;
     const int64_t *off = sums ? sums->s->cfg_off : nullptr;
     const double *se = sums ? sums->site_e : nullptr, *vir = sums ? sums->virial : nullptr;
@@ -642,14 +644,14 @@ void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *bl
         return;
     }
     const int64_t nb = (n + GRADE_ROWS - 1) / GRADE_ROWS;
-    const dim3 grid((unsigned)(n_cfg + (nb + 3) / 4));
+    const dim3 grid((unsigned)(n_cfg + ga.blocks + (nb + 3) / 4));
     if (nb <= SEL_DIRECT_BLOCKS) {
         hipLaunchKernelGGL(select_write<false>, grid, dim3(256), 0, st, gamma, n, thr, blk, idx, cap, count, n_cfg, off,
-                           se, vir, part, energy, stress);
+                           se, vir, part, energy, stress, ga);
     } else {
         hipLaunchKernelGGL(select_scan, dim3(1), dim3(SCAN_T), 0, st, blk, nb);
         hipLaunchKernelGGL(select_write<true>, grid, dim3(256), 0, st, gamma, n, thr, blk, idx, cap, count, n_cfg, off,
-                           se, vir, part, energy, stress);
+                           se, vir, part, energy, stress, ga);
     }
 }
 

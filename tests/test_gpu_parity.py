@@ -415,6 +415,30 @@ def test_evaluate_select_fused(precision, reps, q, cap):
     assert np.array_equal(out["sel_idx"][:k].cpu().numpy(), want[:k])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("lanes", [2, 4, 8])
+def test_evaluate_select_sums_bitwise(precision, lanes, monkeypatch):
+    """With a preselection the force gather runs as blocks of the
+    preselection's launch and the per-32-atom sum partials come from the
+    pair-gradient kernel (one, two or four chunks per block at eight, four or
+    two lanes per neighborhood): energies, forces, stresses, site energies and
+    grades equal the plain evaluation's bit for bit, on an uneven batch whose
+    configurations straddle the chunks."""
+    monkeypatch.setenv("MTP_LANES", str(lanes))
+    w = synth.workload2(reps=(5, 4, 3))
+    pot = potential(w)
+    theta = theta_for(2, pot)
+    m, _ = _model(w, theta, modes=("full",))
+    b = api.Batch([w.configs[0]] + list(synth.cfg_pool(2, 40, stream=3)))
+    assert b.n_atoms % 32 != 0
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    plain = api.evaluate(m, b, nb, precision, "full")
+    fused = api.evaluate(m, b, nb, precision, "full", gamma_save=1.0)
+    for k in ("energy", "forces", "stress", "site_e", "gamma", "argmax"):
+        assert torch.equal(plain[k], fused[k]), k
+    assert int(fused["sel_count"].item()) == int((plain["gamma"] > 1.0).sum().item())
+
+
 def test_singular_active_set_is_reported():
     w = synth.workload1()
     m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
