@@ -189,12 +189,13 @@ __global__ __launch_bounds__(256) void efs_moments(const EfsArgs a) {
 }
 
 // ---- kernel 2: contraction, site energy (eq. 2), dV/dM -------------------
-// One block holds 64 neighborhoods (one per lane) and four wavefronts; the
-// graphs of the contraction program are split into four parts at build time
-// (Level<L>::graph_part).  Wavefront w evaluates the graph values of part w,
-// all four exchange them through LDS, each runs the (short) trie walk for
-// V, B_alpha and dV/dg, and wavefront w runs the reverse pass of part w.  The
-// four partial dV/dM are added in LDS in a fixed order.
+// One block holds 64 neighborhoods (one per lane) and four (or eight)
+// wavefronts; the graphs of the contraction program are split into four and
+// into eight parts at build time (Level<L>::graph_part, graph_part8).
+// Wavefront w evaluates the graph values of part w, all exchange them through
+// LDS, each runs the (short) trie walk for V, B_alpha and dV/dg, and
+// wavefront w runs the reverse pass of part w.  The partial dV/dM are added
+// in LDS in a fixed order.
 template <typename T> struct ColLoad {   // component k of one neighborhood, [k][n] layout
     const T *p;
     int64_t s;
@@ -229,30 +230,43 @@ constexpr int STAGE_BYTES = 64 * 1024;
 template <typename T, int L> constexpr bool stage_rows() { return Level<L>::NLIN * 64 * sizeof(T) <= STAGE_BYTES; }
 template <typename T, int L> constexpr int stage_len() { return stage_rows<T, L>() ? Level<L>::NLIN : 1; }
 
-// The contraction of the 64 neighborhoods of block blk (a block of four
-// wavefronts), the moments read through M; sg, sdm: LDS scratch.
-template <typename T, int L, bool WB, typename MA>
+// The contraction of the 64 neighborhoods of block blk (a block of NW = 4
+// or 8 wavefronts), the moments read through M; sg, sdm: LDS scratch.
+template <typename T, int L, bool WB, typename MA, int NW = 4>
 __device__ inline void contract_body(const EfsArgs &a, int64_t blk, const MA &M,
                                      T (&sg)[Level<L>::NGRAPH][64], T (&sdm)[Level<L>::NC][64],
                                      T (&sB)[stage_len<T, L>()][64]) {
     using LV = Level<L>;
     constexpr int NC = LV::NC, NG = LV::NGRAPH;
-    static_assert(LV::NPART == 4, "contraction kernel expects four parts");
+    static_assert(LV::NPART == 4 && LV::NPART8 == 8 && (NW == 4 || NW == 8), "four or eight parts");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t slot = blk * 64 + lane;
     const bool live = slot < a.n_atoms;
     const int64_t sl = live ? slot : 0;
     {
         T g[NG];
-        switch (wave) {
-            case 0: LV::template graphs_part<0>(M, g); break;
-            case 1: LV::template graphs_part<1>(M, g); break;
-            case 2: LV::template graphs_part<2>(M, g); break;
-            default: LV::template graphs_part<3>(M, g); break;
+        if constexpr (NW == 4) {
+            switch (wave) {
+                case 0: LV::template graphs_part<0>(M, g); break;
+                case 1: LV::template graphs_part<1>(M, g); break;
+                case 2: LV::template graphs_part<2>(M, g); break;
+                default: LV::template graphs_part<3>(M, g); break;
+            }
+        } else {
+            switch (wave) {
+                case 0: LV::template graphs_part8<0>(M, g); break;
+                case 1: LV::template graphs_part8<1>(M, g); break;
+                case 2: LV::template graphs_part8<2>(M, g); break;
+                case 3: LV::template graphs_part8<3>(M, g); break;
+                case 4: LV::template graphs_part8<4>(M, g); break;
+                case 5: LV::template graphs_part8<5>(M, g); break;
+                case 6: LV::template graphs_part8<6>(M, g); break;
+                default: LV::template graphs_part8<7>(M, g); break;
+            }
         }
 #pragma unroll
         for (int G = 0; G < NG; ++G)
-            if (LV::graph_part[G] == wave) sg[G][lane] = g[G];
+            if ((NW == 4 ? LV::graph_part[G] : LV::graph_part8[G]) == wave) sg[G][lane] = g[G];
     }
     __syncthreads();
     T gin[NG], dg[NG];
@@ -272,13 +286,26 @@ __device__ inline void contract_body(const EfsArgs &a, int64_t blk, const MA &M,
         LV::template trie<T, false>(gin, xi, RowSink<T>{nullptr, false}, dg, V);
     }
     T dMp[NC];
-    switch (wave) {
-        case 0: LV::template reverse_part<0>(M, dg, dMp); break;
-        case 1: LV::template reverse_part<1>(M, dg, dMp); break;
-        case 2: LV::template reverse_part<2>(M, dg, dMp); break;
-        default: LV::template reverse_part<3>(M, dg, dMp); break;
+    if constexpr (NW == 4) {
+        switch (wave) {
+            case 0: LV::template reverse_part<0>(M, dg, dMp); break;
+            case 1: LV::template reverse_part<1>(M, dg, dMp); break;
+            case 2: LV::template reverse_part<2>(M, dg, dMp); break;
+            default: LV::template reverse_part<3>(M, dg, dMp); break;
+        }
+    } else {
+        switch (wave) {
+            case 0: LV::template reverse_part8<0>(M, dg, dMp); break;
+            case 1: LV::template reverse_part8<1>(M, dg, dMp); break;
+            case 2: LV::template reverse_part8<2>(M, dg, dMp); break;
+            case 3: LV::template reverse_part8<3>(M, dg, dMp); break;
+            case 4: LV::template reverse_part8<4>(M, dg, dMp); break;
+            case 5: LV::template reverse_part8<5>(M, dg, dMp); break;
+            case 6: LV::template reverse_part8<6>(M, dg, dMp); break;
+            default: LV::template reverse_part8<7>(M, dg, dMp); break;
+        }
     }
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < NW; ++w) {
         if (wave == w) {
 #pragma unroll
             for (int k = 0; k < NC; ++k) sdm[k][lane] = w == 0 ? dMp[k] : sdm[k][lane] + dMp[k];
@@ -289,14 +316,14 @@ __device__ inline void contract_body(const EfsArgs &a, int64_t blk, const MA &M,
         constexpr int NL = LV::NLIN;
         const int64_t nlive = a.n_atoms - blk * 64;
         T *rows = static_cast<T *>(a.brow) + blk * 64 * (int64_t)a.ldb + nt;
-        for (int e = threadIdx.x; e < 64 * NL; e += 256) {
+        for (int e = threadIdx.x; e < 64 * NL; e += 64 * NW) {
             const int r = e / NL, k = e % NL;
             if (r < nlive) rows[r * (int64_t)a.ldb + k] = sB[k][r];
         }
     }
     if (live) {
         T *dout = static_cast<T *>(a.dmbuf);
-        for (int k = wave; k < NC; k += 4) dout[(int64_t)k * a.n_atoms + slot] = sdm[k][lane];
+        for (int k = wave; k < NC; k += NW) dout[(int64_t)k * a.n_atoms + slot] = sdm[k][lane];
         if (wave == 0 && a.site_e) {
             const int64_t atom = a.atom_list ? (int64_t)a.atom_list[slot] : slot;
             int zi = a.type[atom];
@@ -345,6 +372,35 @@ __global__ __launch_bounds__(256) void efs_moments_contract(const EfsArgs a) {
     __syncthreads();
     contract_body<T, L, WB>(a, blockIdx.x, LdsCol<T>{&sM[0][threadIdx.x & 63]}, sg, sdm,
                             reinterpret_cast<T (&)[stage_len<T, L>()][64]>(sB));
+}
+
+// The same with eight wavefronts (512 threads, eight lanes per neighborhood
+// for the moments) and the eight-part contraction program: 64 neighborhoods
+// per block as before, but two wavefronts per SIMD instead of one while the
+// straight-line contraction runs.
+template <typename T, int L, bool WB>
+__global__ __launch_bounds__(512) void efs_moments_contract8(const EfsArgs a) {
+    using LV = Level<L>;
+    constexpr int K = 8, NC = LV::NC, NR = LV::NRAD;
+    constexpr int NCP = (NC + K - 1) / K * K;
+    __shared__ T c_s[NR * MAX_TYPES * MAX_TYPES * NPOLY];
+    __shared__ T sM[NCP][64];
+    __shared__ T sg[LV::NGRAPH][64];
+    __shared__ T sdm[NC][64];
+    __shared__ T sB[WB ? stage_len<T, L>() : 1][64];
+    load_coefs<T, NR>(a, c_s);
+    const int sub = threadIdx.x % K;
+    const AtomCtx c = atom_ctx<K>(a);
+    {
+        T M[NCP];
+        moments_scattered<T, L, K>(a, c, c_s, M);
+        const int la = threadIdx.x / K;
+#pragma unroll
+        for (int i = 0; i < NCP / K; ++i) sM[sub * (NCP / K) + i][la] = M[i];
+    }
+    __syncthreads();
+    contract_body<T, L, WB, LdsCol<T>, 8>(a, blockIdx.x, LdsCol<T>{&sM[0][threadIdx.x & 63]}, sg, sdm,
+                                          reinterpret_cast<T (&)[stage_len<T, L>()][64]>(sB));
 }
 
 // Chebyshev values (and derivatives) at u for the radial basis (eq. 4)
@@ -615,7 +671,7 @@ template <int L, typename T> int launch_efs_level_t(const EfsArgs &a);
 // instantiates the launchers of one level and one arithmetic type (each
 // (level, type) pair is a translation unit of its own, generated at build time)
 #define MTP_EFS_LEVEL_T(LEVEL, TT)                                                                       \
-    /* moments and contraction, K lanes per neighborhood (K = 4: one fused launch) */                    \
+    /* moments and contraction, K lanes per neighborhood (K = 4, 8: one launch; K = 2: two) */         \
     template <typename T, int K, bool WB> static void launch_mc##LEVEL(const EfsArgs &a) {               \
         const unsigned grid = (unsigned)((a.n_atoms + 256 / K - 1) / (256 / K));                         \
         const unsigned grid1 = (unsigned)((a.n_atoms + 63) / 64);                                        \
@@ -623,6 +679,10 @@ template <int L, typename T> int launch_efs_level_t(const EfsArgs &a);
             ProfScope ps("efs_moments", a.stream);                                                       \
             hipLaunchKernelGGL((efs_moments_contract<T, LEVEL, WB>), dim3(grid1), dim3(256), 0, a.stream, \
                                a);                                                                       \
+        } else if (K == 8) {                                                                             \
+            ProfScope ps("efs_moments", a.stream);                                                       \
+            hipLaunchKernelGGL((efs_moments_contract8<T, LEVEL, WB>), dim3(grid1), dim3(512), 0,          \
+                               a.stream, a);                                                             \
         } else {                                                                                         \
             {                                                                                            \
                 ProfScope ps("efs_moments", a.stream);                                                   \

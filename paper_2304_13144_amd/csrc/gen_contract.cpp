@@ -270,11 +270,17 @@ void write_level(const std::string &dir, int level) {
     std::string rev = em.os.str();
     const Counter cf = em.fwd, ct = em.trie_count, cr = em.rev;
 
-    // Split of the graphs over NPART wavefronts (largest first onto the
-    // least loaded part; cost = monomial terms x degree).
-    const int NPART = 4;
-    std::vector<int> part(B.graphs.size(), 0);
-    {
+    // Split of the graphs over np wavefronts (largest first onto the least
+    // loaded part; cost = monomial terms x degree): the four-part program of
+    // the four-wavefront kernels and the eight-part one of the eight-wavefront
+    // kernel.
+    struct Split {
+        std::vector<int> part;
+        std::vector<std::string> pf, pr;
+    };
+    auto split = [&](int np) {
+        Split sp;
+        sp.part.assign(B.graphs.size(), 0);
         std::vector<std::pair<long, int>> cost;
         for (size_t G = 0; G < B.graphs.size(); ++G) {
             long c = 0;
@@ -282,27 +288,31 @@ void write_level(const std::string &dir, int level) {
             cost.push_back({c, (int)G});
         }
         std::sort(cost.begin(), cost.end(), [](auto &a, auto &b) { return a.first > b.first || (a.first == b.first && a.second < b.second); });
-        std::vector<long> load(NPART, 0);
+        std::vector<long> load(np, 0);
         for (auto &c : cost) {
             int best = 0;
-            for (int q = 1; q < NPART; ++q)
+            for (int q = 1; q < np; ++q)
                 if (load[q] < load[best]) best = q;
-            part[c.second] = best;
+            sp.part[c.second] = best;
             load[best] += c.first;
         }
-    }
-    std::vector<std::string> pf(NPART), pr(NPART);
-    for (int q = 0; q < NPART; ++q) {
-        std::vector<int> gl;
-        for (size_t G = 0; G < B.graphs.size(); ++G)
-            if (part[G] == q) gl.push_back((int)G);
-        em.os.str("");
-        em.graphs_forward(gl, true);
-        pf[q] = em.os.str();
-        em.os.str("");
-        em.graphs_reverse(gl, true);
-        pr[q] = em.os.str();
-    }
+        sp.pf.resize(np);
+        sp.pr.resize(np);
+        for (int q = 0; q < np; ++q) {
+            std::vector<int> gl;
+            for (size_t G = 0; G < B.graphs.size(); ++G)
+                if (sp.part[G] == q) gl.push_back((int)G);
+            em.os.str("");
+            em.graphs_forward(gl, true);
+            sp.pf[q] = em.os.str();
+            em.os.str("");
+            em.graphs_reverse(gl, true);
+            sp.pr[q] = em.os.str();
+        }
+        return sp;
+    };
+    const int NPART = 4, NPART8 = 8;
+    const Split s4 = split(NPART), s8 = split(NPART8);
     em.os.str("");
     em.trie_walk(true);
     std::string walk_arrays = em.os.str();
@@ -327,7 +337,11 @@ void write_level(const std::string &dir, int level) {
     h << "  static constexpr long FLOPS_REVERSE = " << cr.flops() << ";\n";
     h << "  static constexpr int NPART = " << NPART << ";\n";
     h << "  static constexpr int graph_part[" << B.graphs.size() << "] = {";
-    for (size_t G = 0; G < B.graphs.size(); ++G) h << (G ? "," : "") << part[G];
+    for (size_t G = 0; G < B.graphs.size(); ++G) h << (G ? "," : "") << s4.part[G];
+    h << "};\n";
+    h << "  static constexpr int NPART8 = " << NPART8 << ";\n";
+    h << "  static constexpr int graph_part8[" << B.graphs.size() << "] = {";
+    for (size_t G = 0; G < B.graphs.size(); ++G) h << (G ? "," : "") << s8.part[G];
     h << "};\n";
     auto arr = [&](const char *name, auto f) {
         h << "  static constexpr int " << name << "[" << NC << "] = {";
@@ -356,19 +370,21 @@ void write_level(const std::string &dir, int level) {
     h << "  }\n";
     // the same program in parts: graph values of part P, the trie walk from
     // all graph values, and the reverse pass of part P (dM zero elsewhere)
-    h << "\n  template <int P, typename T, typename MP>\n";
-    h << "  __device__ __forceinline__ static void graphs_part(MP M, T *gout) {\n";
-    for (int q = 0; q < NPART; ++q)
-        h << "  " << (q ? "else " : "") << "if constexpr (P == " << q << ") {\n" << pf[q] << "  }\n";
-    h << "  }\n";
+    auto parts = [&](const char *name, const char *sig, const std::vector<std::string> &body) {
+        h << "\n  template <int P, typename T, typename MP>\n";
+        h << "  __device__ __forceinline__ static void " << name << sig << " {\n";
+        for (size_t q = 0; q < body.size(); ++q)
+            h << "  " << (q ? "else " : "") << "if constexpr (P == " << q << ") {\n" << body[q] << "  }\n";
+        h << "  }\n";
+    };
+    parts("graphs_part", "(MP M, T *gout)", s4.pf);
+    parts("graphs_part8", "(MP M, T *gout)", s8.pf);
     h << "\n  template <typename T, bool WB, typename XP, typename BP>\n";
     h << "  __device__ __forceinline__ static void trie(const T *gin, XP xi, BP Bout, T *dgout, T &V) {\n";
     h << walk_arrays << "  }\n";
-    h << "\n  template <int P, typename T, typename MP>\n";
-    h << "  __device__ __forceinline__ static void reverse_part(MP M, const T *dgin, T (&dM)[NC]) {\n";
-    for (int q = 0; q < NPART; ++q)
-        h << "  " << (q ? "else " : "") << "if constexpr (P == " << q << ") {\n" << pr[q] << "  }\n";
-    h << "  }\n};\n";
+    parts("reverse_part", "(MP M, const T *dgin, T (&dM)[NC])", s4.pr);
+    parts("reverse_part8", "(MP M, const T *dgin, T (&dM)[NC])", s8.pr);
+    h << "};\n";
     std::ofstream out(dir + "/mtp_level" + std::to_string(level) + ".inc");
     out << h.str();
     std::cout << "level " << level << ": graphs " << B.graphs.size() << " basis " << B.n_lin() << " comps " << NC
