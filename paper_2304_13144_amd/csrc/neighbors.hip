@@ -775,34 +775,41 @@ __global__ void reverse_pairs(int64_t n, int n_types, int max_nbrs, const int32_
     if (slot >= n * max_nbrs) return;
     const int64_t i = slot / max_nbrs;
     const int p = (int)(slot % max_nbrs);
-    int tot = 0;
-    for (int t = 0; t < n_types; ++t) tot += tcnt[i * n_types + t];
-    if (p >= tot) return;
-    const int zi = type[i];
-    if (zi < 0 || zi >= n_types) return;
+    // Each level of dependent loads is issued at once: the slot's own entry,
+    // i's species and counts (the entry is stale and unused past the count) ...
     const int j = jl[slot];
     const int s = sh[slot];
+    const int zi = type[i];
+    int tot = 0;
+#pragma unroll
+    for (int t = 0; t < MAX_TYPES; ++t) tot += t < n_types ? tcnt[i * n_types + t] : 0;
+    __asm__ volatile("" ::"v"(j), "v"(s), "v"(zi));   // keeps the loads above the branch
+    if (p >= tot) return;
+    if (zi < 0 || zi >= n_types) return;
     const int want = ((-sx8(s)) & 0xff) | ((-sx8(s >> 8)) & 0xff) << 8 | ((-sx8(s >> 16)) & 0xff) << 16;
     const int orev = (s >> 24) & 0xff;
-    int start = 0;
-    for (int t = 0; t < zi; ++t) start += tcnt[(int64_t)j * n_types + t];
-    const int cnt = tcnt[(int64_t)j * n_types + zi];
-    int lo = 0, hi = cnt;
-    if (orev != 0xff) {
-        const uint16_t *pj = pre + ((int64_t)j * n_types + zi) * 64;
-        const int a = pj[orev];
-        if (a != 0xffff) {
-            lo = a < cnt ? a : cnt;
-            if (orev + 1 < 64) {
-                const int b = pj[orev + 1];
-                hi = b < cnt ? b : cnt;
-            }
-        }
+    // ... then j's counts and both offset-table entries of the opposite bin offset ...
+    int start = 0, cnt = 0;
+#pragma unroll
+    for (int t = 0; t < MAX_TYPES; ++t) {
+        const int c = t < n_types ? tcnt[(int64_t)j * n_types + t] : 0;
+        if (t < zi) start += c;
+        if (t == zi) cnt = c;
     }
+    const uint16_t *pj = pre + ((int64_t)j * n_types + zi) * 64;
+    const int oa = orev != 0xff ? orev : 0;
+    const int a = pj[oa], b = pj[oa + 1 < 64 ? oa + 1 : 63];
+    int lo = 0, hi = cnt;
+    if (orev != 0xff && a != 0xffff) {   // without a table entry the whole group is scanned
+        lo = a < cnt ? a : cnt;
+        if (orev + 1 < 64) hi = b < cnt ? b : cnt;
+    }
+    // ... then the run (usually one to three entries), both words of an entry together
     int found = -1;
     for (int q = start + lo; q < start + hi; ++q) {
         const int64_t s2 = (int64_t)j * max_nbrs + q;
-        if (jl[s2] == (int)i && (sh[s2] & 0xffffff) == want) {
+        const int j2 = jl[s2], sh2 = sh[s2];
+        if ((j2 == (int)i) & ((sh2 & 0xffffff) == want)) {
             found = (int)s2;
             break;
         }
