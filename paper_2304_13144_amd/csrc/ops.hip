@@ -29,27 +29,44 @@ __device__ inline void gather_block(int64_t blk, int64_t n, int nt, int maxn, co
     const int sub = threadIdx.x % FG_LANES;
     const int64_t i = (blk * blockDim.x + threadIdx.x) / FG_LANES;
     const bool live = i < n;
+    const int64_t ic = live ? i : 0;
     int tot = 0;
-    if (live)
-        for (int t = 0; t < nt; ++t) tot += tcnt[i * nt + t];
+#pragma unroll
+    for (int t = 0; t < MAX_TYPES; ++t) tot += t < nt ? tcnt[ic * nt + t] : 0;
+    if (!live) tot = 0;
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    // FG_DEPTH pairs per lane at a time: their reverse indices, then their
-    // gradients, are all in flight together (the loads form a dependent chain)
+    // FG_DEPTH pairs per lane at a time, every load unconditional so that the
+    // reverse indices, then the gradients, are all in flight together (the
+    // loads form a dependent chain): a slot past the count reads its own
+    // (in-bounds) entry instead of a stale index and adds nothing.
     constexpr int FG_DEPTH = 4;
     for (int p0 = sub; p0 < tot; p0 += FG_DEPTH * FG_LANES) {
-        int64_t q[FG_DEPTH];
+        int64_t sl[FG_DEPTH], q[FG_DEPTH];
+        int r[FG_DEPTH];
 #pragma unroll
         for (int d = 0; d < FG_DEPTH; ++d) {
             const int p = p0 + d * FG_LANES;
-            q[d] = p < tot ? (int64_t)rev[i * maxn + p] : -1;
+            sl[d] = ic * maxn + (p < maxn ? p : maxn - 1);
+            r[d] = rev[sl[d]];
         }
+        static_assert(FG_DEPTH == 4, "the asm below names four loads");
+        __asm__ volatile("" ::"v"(r[0]), "v"(r[1]), "v"(r[2]), "v"(r[3]));   // keeps them unconditional
+#pragma unroll
+        for (int d = 0; d < FG_DEPTH; ++d) q[d] = p0 + d * FG_LANES < tot ? (int64_t)r[d] : sl[d];
+        T gs[FG_DEPTH][3], gq[FG_DEPTH][3];
+#pragma unroll
+        for (int d = 0; d < FG_DEPTH; ++d)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                gs[d][k] = g[3 * sl[d] + k];
+                gq[d][k] = g[3 * q[d] + k];
+            }
 #pragma unroll
         for (int d = 0; d < FG_DEPTH; ++d) {
-            if (q[d] >= 0) {
-                const int64_t s = i * maxn + p0 + d * FG_LANES;
-                fx += double(g[3 * s]) - double(g[3 * q[d]]);
-                fy += double(g[3 * s + 1]) - double(g[3 * q[d] + 1]);
-                fz += double(g[3 * s + 2]) - double(g[3 * q[d] + 2]);
+            if (p0 + d * FG_LANES < tot) {
+                fx += double(gs[d][0]) - double(gq[d][0]);
+                fy += double(gs[d][1]) - double(gq[d][1]);
+                fz += double(gs[d][2]) - double(gq[d][2]);
             }
         }
     }
