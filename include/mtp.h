@@ -336,8 +336,9 @@ int mtp_profile_read(const char *kernel, double *total_ms /* host */, int64_t *l
 /* Autotuner: times the evaluation of this system under nine schedules --
  * 2, 4 or 8 lanes per neighborhood for the moments / contraction (4 and 8:
  * one fused launch of four or eight wavefronts per 64 neighborhoods; 2: two
- * launches) and, independently, for the pair gradients -- (HIP events,
- * 3 repetitions after a warm-up), keeps the fastest for this model,
+ * launches) and, independently, for the pair gradients -- (HIP events:
+ * after a warm-up, five interleaved rounds of three evaluations per
+ * schedule, each schedule's minimum), keeps the fastest for this model,
  * precision and size class (floor(log2 n_atoms)) and returns it in *lanes
  * (host) as 16 x (moments / contraction lanes) + (pair-gradient lanes).
  * Synchronises `stream`. */

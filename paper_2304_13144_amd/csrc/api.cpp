@@ -1252,24 +1252,34 @@ int mtp_tune(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precisio
     hipEvent_t e0, e1;
     MTP_HIP(hipEventCreate(&e0));
     MTP_HIP(hipEventCreate(&e1));
+    // Schedules whose times differ by a few percent are told apart by
+    // interleaved rounds (clock and cache drift hit every schedule alike) and
+    // the minimum of each schedule over the rounds (a stray slow round is
+    // dropped); ties go to the earlier schedule of the list.
+    constexpr int SCHED[9] = {17 * 2, 17 * 4, 17 * 8, 16 * 4 + 2, 16 * 4 + 8, 16 * 2 + 4, 16 * 8 + 4, 16 * 2 + 8,
+                              16 * 8 + 2};
+    constexpr int ROUNDS = 5, REPS = 3;
+    float tmin[9];
     int best = 0;
-    float best_ms = 0.f;
     try {
-        for (int sched : {17 * 2, 17 * 4, 17 * 8, 16 * 4 + 2, 16 * 4 + 8, 16 * 2 + 4, 16 * 8 + 4, 16 * 2 + 8,
-                          16 * 8 + 2}) {
-            m->force_lanes = sched;
-            evaluate(m, s, nb, p, o, st);   // warm-up (workspaces, caches)
-            MTP_HIP(hipEventRecord(e0, st));
-            for (int r = 0; r < 3; ++r) evaluate(m, s, nb, p, o, st);
-            MTP_HIP(hipEventRecord(e1, st));
-            MTP_HIP(hipEventSynchronize(e1));
-            float ms = 0.f;
-            MTP_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (!best || ms < best_ms) {
-                best = sched;
-                best_ms = ms;
-            }
+        for (int k = 0; k < 9; ++k) {   // warm-up (workspaces, caches)
+            m->force_lanes = SCHED[k];
+            evaluate(m, s, nb, p, o, st);
         }
+        for (int rd = 0; rd < ROUNDS; ++rd)
+            for (int k = 0; k < 9; ++k) {
+                m->force_lanes = SCHED[k];
+                MTP_HIP(hipEventRecord(e0, st));
+                for (int r = 0; r < REPS; ++r) evaluate(m, s, nb, p, o, st);
+                MTP_HIP(hipEventRecord(e1, st));
+                MTP_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                MTP_HIP(hipEventElapsedTime(&ms, e0, e1));
+                tmin[k] = rd == 0 ? ms : std::min(tmin[k], ms);
+            }
+        for (int k = 1; k < 9; ++k)
+            if (tmin[k] < tmin[best]) best = k;
+        best = SCHED[best];
     } catch (...) {
         m->force_lanes = 0;
         (void)hipEventDestroy(e0);
