@@ -91,3 +91,25 @@ def test_batch_without_atoms():
     out = api.evaluate(m, b, nb, "fp64", "linear", gamma_save=2.0)
     assert np.all(out["energy"].cpu().numpy() == 0.0) and np.all(out["stress"].cpu().numpy() == 0.0)
     assert int(out["sel_count"].item()) == 0
+
+
+@pytest.mark.parametrize("name", ["one_atom_periodic", "isolated_atom", "dimer", "with_empty_configuration"])
+def test_preselecting_evaluation_equals_plain(name):
+    """The preselecting evaluation (force gather in the preselection's launch,
+    sum partials written by the pair-gradient kernel) equals the plain one bit
+    for bit on the degenerate cases, including a batch whose middle
+    configuration has no atoms."""
+    w, pot, theta, m = _model()
+    if name == "with_empty_configuration":
+        small = synth.cfg_pool(1, 2, stream=8)
+        empty = synth.Config(np.zeros((0, 3)), np.zeros(0, np.int32), np.eye(3) * 10.0)
+        cfgs = [small[0], empty, small[1]]
+    else:
+        cfgs = [_cases()[name]]
+    b = api.Batch(cfgs)
+    nb = api.Neighbors().build(m, b, max_nbrs=96)
+    plain = api.evaluate(m, b, nb, "fp64", "linear")
+    fused = api.evaluate(m, b, nb, "fp64", "linear", gamma_save=0.5)
+    for k in ("energy", "forces", "stress", "site_e", "gamma", "argmax"):
+        assert torch.equal(plain[k], fused[k]), k
+    assert int(fused["sel_count"].item()) == int((plain["gamma"] > 0.5).sum().item())
