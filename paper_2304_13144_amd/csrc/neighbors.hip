@@ -433,17 +433,25 @@ __device__ inline unsigned test_count(const Window &W, int n, const Centre &c, i
 // species t); the list offset is below PS_WIN, so perm is indexed by it
 // directly (no compaction) and every offset below the capped total gets
 // exactly one candidate, in candidate order within each species group.
+// The same chunk ballots also give, for this lane's candidate index x (the
+// first candidate of its bin offset), how many accepted candidates of each
+// species come before x: pre[s], clamped to cap[s] on return (where that
+// bin offset's run starts in the species group).
 template <int NT>
 __device__ inline void place_chunks(unsigned in, unsigned tb, int n, int lane, const int (&cap)[MAX_TYPES],
-                                    const int (&base)[MAX_TYPES], short *perm) {
+                                    const int (&base)[MAX_TYPES], short *perm, int x, int (&pre)[MAX_TYPES]) {
     int run[NT];
 #pragma unroll
     for (int s = 0; s < NT; ++s) run[s] = 0;
+    const int xc = x >> 6;
+    const unsigned long long xbelow = (1ull << (x & 63)) - 1ull;
+    bool xset = false;
 #pragma unroll
     for (int cc = 0; cc < PS_CC; ++cc) {
         if (cc * 64 < n) {   // wave-uniform
             const bool a = (in >> cc) & 1u;
             const int t = (tb >> (2 * cc)) & 3;
+            const bool here = xc == cc;
             unsigned long long mk = 0ull;
             int r = 0, cp = 0, bs = 0;
 #pragma unroll
@@ -455,12 +463,19 @@ __device__ inline void place_chunks(unsigned in, unsigned tb, int n, int lane, c
                     cp = cap[s];
                     bs = base[s];
                 }
+                if (here) pre[s] = run[s] + __popcll(m & xbelow);
                 run[s] += __popcll(m);
             }
+            xset = xset || here;
             const int k = r + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
             if (a && k < cp) perm[bs + k] = (short)(cc * 64 + lane);
         }
+    }
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+        const int v = xset ? pre[s] : run[s];   // x at or past the last candidate: all of them
+        pre[s] = v < cap[s] ? v : cap[s];
     }
 }
 
@@ -524,16 +539,6 @@ __device__ inline void write_kept(const Window &W, const short *perm_e, const in
         if (sh0 < -127 || sh0 > 127 || sh1 < -127 || sh1 > 127 || sh2 < -127 || sh2 > 127) fl.wide = true;
         shout[slot] = (sh0 & 0xff) | ((sh1 & 0xff) << 8) | ((sh2 & 0xff) << 16) | (0xff << 24);
     }
-}
-
-// entries of perm[0 .. n) (ascending) below key
-__device__ inline int count_below(const short *p, int n, int key) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (p[mid] < key) lo = mid + 1; else hi = mid;
-    }
-    return lo;
 }
 
 // consecutive lanes write list slots 0 .. tot - 1 from perm
@@ -658,7 +663,8 @@ __global__ __launch_bounds__(256) void pair_search(const int32_t *nbins_dev, int
                     const unsigned in = test_count<NT>(W, A0.total, c, lane, d2max, tb, cnt, fl);
                     int tot;
                     list_layout(cnt, n_types, max_nbrs, cap, base, tot);
-                    place_chunks<NT>(in, tb, A0.total, lane, cap, base, perm_e[wave]);
+                    int pre[MAX_TYPES] = {0, 0, 0, 0};
+                    place_chunks<NT>(in, tb, A0.total, lane, cap, base, perm_e[wave], A0.excl, pre);
                     const int kept = tot < max_nbrs ? tot : max_nbrs;
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
@@ -666,8 +672,7 @@ __global__ __launch_bounds__(256) void pair_search(const int32_t *nbins_dev, int
                     // lane o: where the run of bin offset o starts in each species group
 #pragma unroll
                     for (int t = 0; t < n_types; ++t)
-                        pre_out[((int64_t)c.i * n_types + t) * 64 + lane] =
-                            (uint16_t)count_below(perm_e[wave] + base[t], cap[t], A0.excl);
+                        pre_out[((int64_t)c.i * n_types + t) * 64 + lane] = (uint16_t)pre[t];
                     write_direct(W, perm_e[wave], kept, c, lane, max_nbrs, n_off, rout, jout, shout, fl);
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
