@@ -10,8 +10,10 @@
 //
 // Steps: geometry per configuration -> bin every atom (counting sort, then
 // each bin sorted by atom index so the result is deterministic) -> per atom
-// a counting pass and a filling pass over the 27 (or more) nearby bins,
-// grouped by neighbor species -> reverse-pair index for the atomic-free
+// the distance tests against the 27 (or more) nearby bins, whose ballots give
+// the per-species counts and every pair's place in the list, grouped by
+// neighbor species (bins whose surroundings exceed one LDS window: a counting
+// sweep, then a filling sweep) -> reverse-pair index for the atomic-free
 // force gather.
 #include <hip/hip_runtime.h>
 
