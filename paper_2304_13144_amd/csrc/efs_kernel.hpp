@@ -558,14 +558,21 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
 // both modes: the species one-hot (dV_i/dxi0) and zero padding.  The
 // xi part (B_alpha) comes from kernel 2.
 template <typename T, int L, int K>
-__device__ inline void efs_rows_body(const EfsArgs &a, int64_t blk, T (&s_dm)[Level<L>::NC][256 / K]) {
+__device__ inline void efs_rows_body(const EfsArgs &a, int64_t blk, T (&s_dm)[Level<L>::NC][256 / K],
+                                     int32_t *s_col) {
     using LV = Level<L>;
     constexpr int NC = LV::NC, NR = LV::NRAD, NL = LV::NLIN;
     const int nt = a.n_types;
     const int sub = threadIdx.x % K;
     const AtomCtx c = atom_ctx<K>(a, blk);
     const bool full_rows = a.grade_mode == MTP_GRADE_FULL;
-    if (full_rows) load_dm<T, NC, K>(a, c, sub, s_dm);
+    if (full_rows) {
+        // the kept columns of the c part, once per block in LDS: read from
+        // global memory beside the row stores, each would wait for the store
+        // before it (the two may alias)
+        for (int k = threadIdx.x; k < NR * nt * nt * NPOLY; k += blockDim.x) s_col[k] = a.colmap[nt + NL + k];
+        load_dm<T, NC, K>(a, c, sub, s_dm);   // (its barrier also covers s_col)
+    }
     const int la = threadIdx.x / K;
     T *brow = c.live ? static_cast<T *>(a.brow) + c.slot * (int64_t)a.ldb : nullptr;
     const T rc = T(a.r_cut);
@@ -616,11 +623,10 @@ __device__ inline void efs_rows_body(const EfsArgs &a, int64_t blk, T (&s_dm)[Le
             }
             efs::reduce_scatter<T, ND, K>(dc, sub);
             if (brow) {
-                const int base = nt + NL;
 #pragma unroll
                 for (int i = 0; i < ND / K; ++i) {
                     const int k = sub * (ND / K) + i, mu = k / NPOLY, b = k % NPOLY;
-                    const int col = a.colmap[base + ((mu * nt + c.zi) * nt + t) * NPOLY + b];
+                    const int col = s_col[((mu * nt + c.zi) * nt + t) * NPOLY + b];
                     if (col >= 0) brow[col] = dc[i];
                 }
             }
@@ -631,12 +637,11 @@ __device__ inline void efs_rows_body(const EfsArgs &a, int64_t blk, T (&s_dm)[Le
         // species one-hot, zero c blocks of the other central species, zero padding
         for (int k = sub; k < nt; k += K) brow[k] = T(k == c.zi ? 1 : 0);
         if (full_rows) {
-            const int base = nt + NL;
             const int nblk = NR * nt * nt * NPOLY;
             for (int k = sub; k < nblk; k += K) {
                 const int zz = (k / (nt * NPOLY)) % nt;
                 if (zz == c.zi) continue;
-                const int col = a.colmap[base + k];
+                const int col = s_col[k];
                 if (col >= 0) brow[col] = T(0);
             }
         }
@@ -650,6 +655,7 @@ template <typename T, int L, int K>
 __global__ __launch_bounds__(256) void efs_forces_rows(const EfsArgs a, int64_t nblk) {
     __shared__ T c_s[Level<L>::NRAD * MAX_TYPES * MAX_TYPES * NPOLY];
     __shared__ T s_dm[Level<L>::NC][256 / K];
+    __shared__ int32_t s_col[Level<L>::NRAD * MAX_TYPES * MAX_TYPES * NPOLY];
     if ((int64_t)blockIdx.x < nblk) {
         efs_forces_body<T, L, K>(a, blockIdx.x, c_s, s_dm);
         if (a.part) {   // uniform: the block's atoms are whole sum chunks (256 / K = 32, 64 or 128)
@@ -662,7 +668,7 @@ __global__ __launch_bounds__(256) void efs_forces_rows(const EfsArgs a, int64_t 
             }
         }
     } else {
-        efs_rows_body<T, L, K>(a, (int64_t)blockIdx.x - nblk, s_dm);
+        efs_rows_body<T, L, K>(a, (int64_t)blockIdx.x - nblk, s_dm, s_col);
     }
 }
 
