@@ -433,8 +433,10 @@ __device__ inline void load_dm(const EfsArgs &a, const AtomCtx &c, int sub, T (&
 // ---- kernel 3: pair gradients and virial; LANES per atom ------------------
 // g_ij = dE_i/dr_ij = sum_mu [f_mu'(r) P_mu r_ij / r + f_mu(r) grad P_mu] with
 // P_mu = sum_nu dE/dM_{mu,nu} (r_ij)^{(x)nu} (the moment tensors contracted
-// with dE/dM), written per pair; virial S_ab = -sum_j g_a r_b per atom.
-template <typename T, int L, int K>
+// with dE/dM), written per pair (G: gradients wanted, decided at compile time
+// so that the stores in the pair loop are unconditional); virial
+// S_ab = -sum_j g_a r_b per atom.
+template <typename T, int L, int K, bool G>
 __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T (&s_dm)[Level<L>::NC][256 / K]) {
     using LV = Level<L>;
     constexpr int NC = LV::NC, NR = LV::NRAD;
@@ -454,21 +456,22 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
     int gstart = 0;
     for (int t = 0; t < nt; ++t) {
         const int tc = tcount(a, c, t);
-        // the next pair vector is loaded while the current one is used
-        double nx = 0.0, ny = 0.0, nz = 0.0;
-        if (sub < tc) {
-            nx = c.rp[3 * (gstart + sub)];
-            ny = c.rp[3 * (gstart + sub) + 1];
-            nz = c.rp[3 * (gstart + sub) + 2];
-        }
+        // the next pair vector is loaded while the current one is used; the
+        // loads are unconditional (past the last pair the current one is read
+        // again, in bounds and unused), so that the wait for them leaves the
+        // gradient stores of the pair before in flight
+        const int p0 = gstart + sub < a.max_nbrs ? gstart + sub : a.max_nbrs - 1;
+        double nx = c.rp[3 * p0], ny = c.rp[3 * p0 + 1], nz = c.rp[3 * p0 + 2];
+        // waited for here, once, so that the loop head does not wait for
+        // every outstanding access (the stores included) on each pair
+        __asm__ volatile("" ::"v"(nx), "v"(ny), "v"(nz));
         for (int q = sub; q < tc; q += K) {
             const int p = gstart + q;
             const T x = T(nx), y = T(ny), z = T(nz);
-            if (q + K < tc) {
-                nx = c.rp[3 * (p + K)];
-                ny = c.rp[3 * (p + K) + 1];
-                nz = c.rp[3 * (p + K) + 2];
-            }
+            const int pn = q + K < tc ? p + K : p;
+            nx = c.rp[3 * pn];
+            ny = c.rp[3 * pn + 1];
+            nz = c.rp[3 * pn + 2];
             const T r = sqrt(x * x + y * y + z * z);
             T g0 = T(0), g1 = T(0), g2 = T(0);
             if (r < rc) {
@@ -528,7 +531,7 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
                 vir[3] -= g1 * x; vir[4] -= g1 * y; vir[5] -= g1 * z;
                 vir[6] -= g2 * x; vir[7] -= g2 * y; vir[8] -= g2 * z;
             }
-            if (gout) {
+            if constexpr (G) {
                 const int64_t s3 = (c.atom * (int64_t)a.max_nbrs + p) * 3;
                 gout[s3] = g0;
                 gout[s3 + 1] = g1;
@@ -657,7 +660,10 @@ __global__ __launch_bounds__(256) void efs_forces_rows(const EfsArgs a, int64_t 
     __shared__ T s_dm[Level<L>::NC][256 / K];
     __shared__ int32_t s_col[Level<L>::NRAD * MAX_TYPES * MAX_TYPES * NPOLY];
     if ((int64_t)blockIdx.x < nblk) {
-        efs_forces_body<T, L, K>(a, blockIdx.x, c_s, s_dm);
+        if (a.gbuf)
+            efs_forces_body<T, L, K, true>(a, blockIdx.x, c_s, s_dm);
+        else
+            efs_forces_body<T, L, K, false>(a, blockIdx.x, c_s, s_dm);
         if (a.part) {   // uniform: the block's atoms are whole sum chunks (256 / K = 32, 64 or 128)
             constexpr int PER = 256 / K / SUM_CHUNK;
             static_assert(PER * SUM_CHUNK * K == 256, "chunks per block");
