@@ -76,10 +76,12 @@ struct AtomCtx {
     const double *rp;
 };
 
-template <int K> __device__ inline AtomCtx atom_ctx(const EfsArgs &a, int64_t blk = -1) {
+// BS: the launch's block size, a compile-time constant (blockDim.x is read
+// from the dispatch packet: one more dependent load before the first real one)
+template <int K, int BS = 256> __device__ inline AtomCtx atom_ctx(const EfsArgs &a, int64_t blk = -1) {
     AtomCtx c;
     const int nt = a.n_types;
-    c.slot = (blk < 0 ? (int64_t)blockIdx.x : blk) * (blockDim.x / K) + threadIdx.x / K;
+    c.slot = (blk < 0 ? (int64_t)blockIdx.x : blk) * (BS / K) + threadIdx.x / K;
     c.live = c.slot < a.n_atoms;
     c.atom = c.live ? (a.atom_list ? (int64_t)a.atom_list[c.slot] : c.slot) : 0;
     int zi = c.live ? a.type[c.atom] : 0;
@@ -100,10 +102,10 @@ template <typename A> __device__ inline int tcount(const A &a, const AtomCtx &c,
     return c.live ? a.tcnt[c.atom * a.n_types + t] : 0;
 }
 
-template <typename T, int NR> __device__ inline void load_coefs(const EfsArgs &a, T *c_s) {
+template <typename T, int NR, int BS = 256> __device__ inline void load_coefs(const EfsArgs &a, T *c_s) {
     const T *cg = static_cast<const T *>(a.c);
     const int ncoef = NR * a.n_types * a.n_types * NPOLY;
-    for (int k = threadIdx.x; k < ncoef; k += blockDim.x) c_s[k] = cg[k];
+    for (int k = threadIdx.x; k < ncoef; k += BS) c_s[k] = cg[k];
     __syncthreads();
 }
 
@@ -388,9 +390,9 @@ __global__ __launch_bounds__(512) void efs_moments_contract8(const EfsArgs a) {
     __shared__ T sg[LV::NGRAPH][64];
     __shared__ T sdm[NC][64];
     __shared__ T sB[WB ? stage_len<T, L>() : 1][64];
-    load_coefs<T, NR>(a, c_s);
+    load_coefs<T, NR, 512>(a, c_s);
     const int sub = threadIdx.x % K;
-    const AtomCtx c = atom_ctx<K>(a);
+    const AtomCtx c = atom_ctx<K, 512>(a);
     {
         T M[NCP];
         moments_scattered<T, L, K>(a, c, c_s, M);
@@ -573,7 +575,7 @@ __device__ inline void efs_rows_body(const EfsArgs &a, int64_t blk, T (&s_dm)[Le
         // the kept columns of the c part, once per block in LDS: read from
         // global memory beside the row stores, each would wait for the store
         // before it (the two may alias)
-        for (int k = threadIdx.x; k < NR * nt * nt * NPOLY; k += blockDim.x) s_col[k] = a.colmap[nt + NL + k];
+        for (int k = threadIdx.x; k < NR * nt * nt * NPOLY; k += 256) s_col[k] = a.colmap[nt + NL + k];
         load_dm<T, NC, K>(a, c, sub, s_dm);   // (its barrier also covers s_col)
     }
     const int la = threadIdx.x / K;

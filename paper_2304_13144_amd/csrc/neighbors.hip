@@ -775,10 +775,10 @@ __device__ inline int sx8(int v) { return (int)(signed char)(v & 0xff); }
 // (from j's bin to i's); j's offset table gives where that offset's run
 // starts in j's species-z_i group, so only the run (ascending atom index) is
 // scanned.  Without a table entry the whole group is scanned.
-__global__ void reverse_pairs(int64_t n, int n_types, int max_nbrs, const int32_t *type, const int32_t *tcnt,
+__global__ __launch_bounds__(256) void reverse_pairs(int64_t n, int n_types, int max_nbrs, const int32_t *type, const int32_t *tcnt,
                               const int32_t *jl, const int32_t *sh, const uint16_t *pre, int32_t *rev,
                               int32_t *flags) {
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;   // blocks of 256 threads
     if (slot >= n * max_nbrs) return;
     const int64_t i = slot / max_nbrs;
     const int p = (int)(slot % max_nbrs);

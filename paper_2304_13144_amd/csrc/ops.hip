@@ -27,7 +27,7 @@ template <typename T>
 __device__ inline void gather_block(int64_t blk, int64_t n, int nt, int maxn, const int32_t *tcnt,
                                     const int32_t *rev, const T *g, double *F) {
     const int sub = threadIdx.x % FG_LANES;
-    const int64_t i = (blk * blockDim.x + threadIdx.x) / FG_LANES;
+    const int64_t i = (blk * 256 + threadIdx.x) / FG_LANES;   // blocks of 256 threads
     const bool live = i < n;
     const int64_t ic = live ? i : 0;
     int tot = 0;
