@@ -189,7 +189,7 @@ def main():
     theta = synth.theta_teacher(2, n_types, info["n_lin"], info["n_rad"])
     model.set_params(theta)
     keep = model.kept_columns()
-    A_full = np.load(os.path.join(ROOT, "tests", "golden", "active_w2_full.npy"))[:, keep]
+    A_full = synth.active_set(2, "full")[:, keep]
     model.set_active_set("full", A_full)
     batch = api.Batch([cfg])
     nbrs = api.Neighbors().build(model, batch, max_nbrs=64)
@@ -372,8 +372,8 @@ def extra_workloads(timed):
     m5 = api.Model.create(w5.level, w5.n_types, w5.r_min, w5.r_cut)
     m5.set_params(synth.theta_teacher(5, w5.n_types, 92, 4))
     keep = m5.kept_columns()
-    m5.set_active_set("full", np.load(os.path.join(ROOT, "tests", "golden", "active_w5_full.npy"))[:, keep])
-    m5.set_active_set("linear", np.load(os.path.join(ROOT, "tests", "golden", "active_w5_linear.npy")))
+    m5.set_active_set("full", synth.active_set(5, "full")[:, keep])
+    m5.set_active_set("linear", synth.active_set(5, "linear"))
     for k in (0, 19):
         cfg = synth.workload5_snapshot(k)
         b5 = api.Batch([cfg])
@@ -447,7 +447,7 @@ def extra_workloads(timed):
     fmax = float(api.energy_forces_stress(mp, bs, nbs)["forces"].abs().max().item())
     th[:93] *= min(1.0, 0.5 / max(fmax, 1e-30))
     mp.set_params(th)
-    mp.set_active_set("linear", np.load(os.path.join(ROOT, "tests", "golden", "active_w5_linear.npy")))
+    mp.set_active_set("linear", synth.active_set(5, "linear"))
     vel = torch.as_tensor(np.random.default_rng([230413144, 6, 1, 7]).normal(0.0, 0.002, slab.pos.shape)).cuda()
     api.md_run(mp, bs, nbs, vel, [63.546], 1.0, 2, "fp64", "linear", 2.0, 1e300)   # warm-up
     n_md = 50

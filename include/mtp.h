@@ -113,9 +113,16 @@ typedef struct {
 
 /* --- model ------------------------------------------------------------ */
 
-/* Reads a model file (the library's own text format, written by
- * mtp_save) and uploads it to `hip_device`.  The file holds level, species
- * count, R_min, R_cut, N_polyn, theta and optionally the active sets. */
+/* Reads a potential file and uploads it to `hip_device` (paper Sec. III.A:
+ * the potential file carries the trained parameters together with the
+ * active set, so that grades can be computed from the file alone).  The
+ * format is the library's own text format, written by mtp_save, not the
+ * paper's: level, species count, R_min, R_cut, N_polyn, theta (Sec. II.B
+ * order: xi_0 per species, xi_alpha, c) and optionally the active sets.
+ * Errors: MTP_E_INVAL (NULL argument), MTP_E_IO (unreadable file),
+ * MTP_E_PARSE (malformed or inconsistent content), MTP_E_UNSUPPORTED
+ * (level, species count or N_polyn not compiled in), MTP_E_HIP; *out is
+ * untouched on error.  The caller frees the model with mtp_free. */
 int mtp_load(const char *path, int hip_device, mtp_model **out);
 
 /* Writes the model (host-side copy of theta and active sets) to `path`. */

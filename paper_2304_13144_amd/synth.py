@@ -31,6 +31,9 @@ import numpy as np
 
 SEED = 230413144
 _HERE = os.path.dirname(os.path.abspath(__file__))
+# seeded inputs written by the oracle-side scripts next to the tests (teacher
+# scales, active sets): inputs of both the library and its checks
+DATA = os.path.join(_HERE, "data")
 
 # purposes of the random streams
 P_LATTICE, P_DISPLACE, P_THETA, P_TRAIN, P_STRAIN, P_SIZES, P_VACANCY = 0, 1, 2, 3, 4, 5, 6
@@ -280,10 +283,16 @@ def theta_raw(wid, n_types, n_lin, n_rad, n_polyn=8, std=0.1):
 
 def teacher_scales(wid):
     """Stored per-workload scales (s_alpha, force factor) of the teacher."""
-    path = os.path.join(os.path.dirname(_HERE), "tests", "golden", "teacher_scales.json")
+    path = os.path.join(DATA, "teacher_scales.json")
     with open(path) as fh:
         d = json.load(fh)[str(wid)]
     return np.asarray(d["s_alpha"], dtype=np.float64), float(d["force_factor"])
+
+
+def active_set(wid, mode):
+    """Stored active set of a workload (rows of A): FULL over all theta columns,
+    LINEAR over (onehot, B_alpha)."""
+    return np.load(os.path.join(DATA, f"active_w{wid}_{mode}.npy"))
 
 
 def theta_teacher(wid, n_types, n_lin, n_rad, n_polyn=8):

@@ -59,9 +59,9 @@ def main():
         idx = [int(np.argmin(np.abs(full[:, keep] - r).max(axis=1))) for r in Ak]
         A_full = full[idx]
         assert np.array_equal(A_full[:, keep], Ak)
-        np.save(os.path.join(HERE, f"active_w{wid}_full.npy"), A_full)
+        np.save(os.path.join(synth.DATA, f"active_w{wid}_full.npy"), A_full)
         Al, nsl = select(lin)
-        np.save(os.path.join(HERE, f"active_w{wid}_linear.npy"), Al)
+        np.save(os.path.join(synth.DATA, f"active_w{wid}_linear.npy"), Al)
         print(f"workload {wid}: pool {len(full)} rows, FULL m={Ak.shape[0]} ({nsw} swaps, "
               f"cond {np.linalg.cond(Ak):.3g}), LINEAR m={Al.shape[0]} ({nsl} swaps, cond {np.linalg.cond(Al):.3g}) "
               f"in {time.time() - t:.1f}s", flush=True)

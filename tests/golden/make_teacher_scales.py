@@ -53,7 +53,7 @@ def main():
         out[str(wid)] = {"level": level, "n_types": nt, "r_cut": rc, "n_ref_atoms": int(cfg.n),
                          "s_alpha": s.tolist(), "force_factor": float(lam)}
         print(wid, level, nt, cfg.n, "s range", s.min(), s.max(), "lam", lam, flush=True)
-    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "teacher_scales.json"), "w") as fh:
+    with open(os.path.join(synth.DATA, "teacher_scales.json"), "w") as fh:
         json.dump(out, fh, indent=1)
 
 

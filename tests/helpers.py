@@ -22,8 +22,9 @@ def theta_for(wid, pot):
 
 def active_rows(wid, mode):
     """Oracle-built active set of a workload: rows in the full theta column space
-    (FULL) or (onehot, B) columns (LINEAR); written by tests/golden/make_active_sets.py."""
-    return np.load(os.path.join(GOLDEN, f"active_w{wid}_{mode}.npy"))
+    (FULL) or (onehot, B) columns (LINEAR); written by tests/golden/make_active_sets.py
+    into the package data folder."""
+    return synth.active_set(wid, mode)
 
 
 def oracle_pairs(cfg, rc, atoms=None):
@@ -44,3 +45,14 @@ def rel_err(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def kappa_eq(A):
+    """Condition number of A with its columns scaled to unit max-abs (column-equilibrated)."""
+    A = np.asarray(A, dtype=np.float64)
+    return float(np.linalg.cond(A / np.abs(A).max(axis=0)))
+
+
+def fp64_gamma_tol(A):
+    """FP64 bar for grades: 1e-10, relaxed to kappa(A) 1e-15 on an ill-conditioned active set."""
+    return max(1e-10, kappa_eq(A) * 1e-15)

@@ -11,7 +11,7 @@ import torch
 from oracle import mtp as om
 from oracle import neighbors as onb
 from paper_2304_13144_amd import api, synth
-from tests.helpers import active_rows, oracle_local_forces, potential, rel_err, theta_for
+from tests.helpers import active_rows, fp64_gamma_tol, kappa_eq, oracle_local_forces, potential, rel_err, theta_for
 
 pytestmark = pytest.mark.gpu
 
@@ -296,7 +296,9 @@ def test_grade_fp64_workload1(mode):
         A = active_rows(1, "linear")
     assert rel_err(g["rows"], rows) <= FP64_TOL
     gam, am, _ = om.grades(rows, A)
-    assert rel_err(g["gamma"], gam) <= 1e-9
+    tol = fp64_gamma_tol(A)
+    print(f"{mode}: kappa {kappa_eq(A):.3g}, gamma rel err {rel_err(g['gamma'], gam):.3g}, tol {tol:.3g}")
+    assert rel_err(g["gamma"], gam) <= tol
     clear = np.sort(np.abs(_c(rows, A)), axis=1)
     unique = clear[:, -1] - clear[:, -2] > 1e-8 * clear[:, -1]
     assert np.array_equal(g["argmax"][unique], am[unique])
@@ -334,7 +336,9 @@ def test_grade_level16_two_species_small(precision, mode):
           f"gamma range {gam.min():.3g}..{gam.max():.3g}")
     if precision == "fp64":
         assert rel_err(g["rows"], rows) <= FP64_TOL
-        assert err.max() <= 1e-8
+        tol = fp64_gamma_tol(A)
+        print(f"kappa {kappa_eq(A):.3g}, norm-wise gamma rel err {rel_err(g['gamma'], gam):.3g}, tol {tol:.3g}")
+        assert rel_err(g["gamma"], gam) <= tol
     else:
         # FP32 rows cannot do better than their own rounding, amplified by the
         # conditioning of A (the emulation); the GPU rows carry a few more

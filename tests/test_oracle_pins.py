@@ -158,6 +158,102 @@ def test_closed_forms():
     assert torch.allclose(om.graph_value(g222, M), torch.trace(M02[0] @ M02[0] @ M02[0]), rtol=1e-12)
 
 
+# ------------------------------------------------------------- moments -----
+def _cheb_closed(x, k):
+    """T_k(x) from its trigonometric / hyperbolic closed form (no recurrence)."""
+    if abs(x) <= 1.0:
+        return math.cos(k * math.acos(x))
+    return math.cosh(k * math.acosh(abs(x))) * (math.copysign(1.0, x) ** k)
+
+
+def _radial_by_hand(c, r, zi, zj, r_min=2.0, r_cut=5.0):
+    """f_mu(r) = sum_beta c[mu, zi, zj, beta] T_beta(x) (R_cut - r)^2 (eq. 4), written out."""
+    x = (2.0 * r - r_min - r_cut) / (r_cut - r_min)
+    return [sum(c[mu, zi, zj, b] * _cheb_closed(x, b) for b in range(c.shape[3])) * (r_cut - r) ** 2
+            for mu in range(c.shape[0])]
+
+
+def _tiny_neighborhoods(seed, n_atoms=3, n_nbrs=(3, 4, 2)):
+    """Free pairs (no lattice): n_nbrs[i] neighbors of atom i at random directions, 2.1-4.9 A."""
+    rng = np.random.default_rng(seed)
+    rv, ii, jj = [], [], []
+    for i in range(n_atoms):
+        for _ in range(n_nbrs[i]):
+            d = rng.normal(size=3)
+            rv.append(d / np.linalg.norm(d) * rng.uniform(2.1, 4.9))
+            ii.append(i)
+            jj.append(int(rng.integers(0, n_atoms)))
+    return np.array(rv), np.array(ii), np.array(jj)
+
+
+def test_moments_equal_explicit_monomial_loops():
+    """M_{mu,nu}[a1..anu] = sum_j f_mu(|r_ij|) r_ij[a1] ... r_ij[anu] (eq. 3) by plain loops over
+    neighbors and index tuples, for every (mu, nu) of level 16 with two species (mu <= 3, nu <= 3)."""
+    pot = om.Potential(16, 2, 2.0, 5.0)
+    rng = np.random.default_rng(11)
+    c = rng.normal(size=(pot.n_rad, 2, 2, 8))
+    types = np.array([0, 1, 1])
+    rv, ii, jj = _tiny_neighborhoods(12)
+    M = om.moments(pot, torch.as_tensor(c), torch.as_tensor(rv), torch.as_tensor(ii),
+                   torch.as_tensor(types[ii]), torch.as_tensor(types[jj]), 3)
+    assert {nu for _, nu in pot.moments} == {0, 1, 2, 3} and {mu for mu, _ in pot.moments} == {0, 1, 2, 3}
+    for mu, nu in pot.moments:
+        got = M[(mu, nu)].numpy()
+        for i in range(3):
+            for idx in itertools.product(range(3), repeat=nu):
+                want = 0.0
+                for p in np.where(ii == i)[0]:
+                    f = _radial_by_hand(c, float(np.linalg.norm(rv[p])), types[i], types[jj[p]])[mu]
+                    term = f
+                    for a in idx:
+                        term *= rv[p][a]
+                    want += term
+                assert abs(got[(i,) + idx] - want) <= 1e-12 * max(1.0, abs(want)), (mu, nu, i, idx)
+
+
+def test_moments_single_neighbor_closed_form():
+    """One neighbor at (d, 0, 0): M_{mu,1} = f_mu(d) d e_x, M_{mu,2} = f_mu(d) d^2 e_x e_x,
+    M_{mu,3}[0,0,0] = f_mu(d) d^3 and every other entry zero."""
+    pot = om.Potential(16, 1, 2.0, 5.0)
+    c = np.random.default_rng(13).normal(size=(pot.n_rad, 1, 1, 8))
+    for d in (2.3, 3.7, 4.6):
+        M = om.moments(pot, torch.as_tensor(c), torch.tensor([[d, 0.0, 0.0]], dtype=torch.float64),
+                       torch.tensor([0]), torch.tensor([0]), torch.tensor([0]), 1)
+        f = _radial_by_hand(c, d, 0, 0)
+        for mu, nu in pot.moments:
+            want = np.zeros((3,) * nu)
+            want[(0,) * nu] = f[mu] * d ** nu
+            assert np.allclose(M[(mu, nu)].numpy()[0], want, rtol=1e-13, atol=1e-13 * abs(f[mu]) * d ** nu)
+
+
+def test_site_energies_equal_pair_sum_basis():
+    """V_i = xi_0[z_i] + sum_alpha xi_alpha prod_{G in alpha} val(G) (eq. 2) with every graph value
+    written as the pair sum over one neighbor per node of prod f_mu(|r_j|) prod (r_p . r_q)^e:
+    raw r_ij (not unit vectors) and a hand-written radial, through om.site_energies."""
+    pot = om.Potential(12, 2, 2.0, 5.0)
+    rng = np.random.default_rng(14)
+    theta = rng.normal(0, 0.3, pot.n_theta)
+    xi0, xi, c = theta[:2], theta[2:2 + pot.n_lin], theta[2 + pot.n_lin:].reshape(pot.n_rad, 2, 2, 8)
+    types = np.array([1, 0, 1])
+    rv, ii, jj = _tiny_neighborhoods(15, n_nbrs=(3, 2, 4))
+    V, _ = om.site_energies(pot, torch.as_tensor(theta), torch.as_tensor(rv), torch.as_tensor(ii),
+                            torch.as_tensor(jj), types, 3)
+    for i in range(3):
+        ps = np.where(ii == i)[0]
+        R = rv[ps]
+        f = np.array([_radial_by_hand(c, float(np.linalg.norm(r)), types[i], types[jj[p]]) for r, p in zip(R, ps)])
+        gv = {}
+        want = xi0[types[i]]
+        for a, bf in enumerate(pot.basis):
+            v = 1.0
+            for g in bf.factors:
+                if g not in gv:
+                    gv[g] = _pair_sum_value(g, f, R)
+                v *= gv[g]
+            want += xi[a] * v
+        assert abs(float(V[i]) - want) <= 1e-11 * max(1.0, abs(want)), (i, float(V[i]), want)
+
+
 # -------------------------------------------------------------- energy -----
 def _nbrs(pos, cell, pbc=(1, 1, 1), rc=5.0):
     return onb.neighbors(pos, cell, pbc, rc)
