@@ -32,17 +32,17 @@ sys.path.insert(0, ROOT)
 
 PEAK_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, FP64 and non-packed FP32
 PEAK_MFMA_F64_TFLOPS = 78.6
-PEAK_MFMA_BF16_TFLOPS = 2500.0
+PEAK_MFMA_I8_TOPS = 5000.0
+GRADE_I8_PRODUCTS = 19     # int8 digit products of the mixed grade (levels s + t <= 5 of 5 x 5 slices)
 PEAK_HBM_GBS = 8000.0
 KERNELS = ("neighbors", "efs", "efs_moments", "efs_contract", "efs_forces", "force_gather", "cfg_sums", "grade",
            "select")
 # kernels whose HBM traffic the profile summary records (rocprof name substrings)
-TRAFFIC_KERNELS = ("efs_moments_contract<double, 16, true>", "efs_moments_contract<float, 16, true>",
-                   "efs_moments<double, 16, 8>", "efs_moments<float, 16, 8>",
-                   "efs_contract<double, 16, true>", "efs_contract<float, 16, true>",
-                   "efs_forces_rows<double, 16, 4>", "efs_forces_rows<double, 16, 8>",
-                   "efs_forces_rows<float, 16, 4>", "efs_forces_rows<float, 16, 8>",
-                   "grade_f64", "grade_bf16<3>", "pair_search<false, 2>", "reverse_pairs")
+TRAFFIC_KERNELS = ("efs_moments_contract<double, 16, true>", "efs_moments_contract8<double, 16, true>",
+                   "efs_moments<double, 16, 8>", "efs_contract<double, 16, true>",
+                   "efs_forces_rows<double, double, 16, 4>", "efs_forces_rows<double, double, 16, 8>",
+                   "efs_forces_rows<float, double, 16, 4>", "efs_forces_rows<float, double, 16, 8>",
+                   "grade_f64", "grade_i8<4>", "pair_search<false, 2>", "reverse_pairs")
 
 
 def log(msg):
@@ -268,7 +268,8 @@ def main():
     mix = {k: v.cpu().numpy() for k, v in outs["mixed"].items()}
     mixed_vs_fp64 = {"forces_max_abs_eVA": float(np.abs(mix["forces"] - f64["forces"]).max()),
                      "gamma_max_rel": float((np.abs(mix["gamma"] - f64["gamma"]) / np.maximum(1, f64["gamma"])).max()),
-                     "energy_abs_eV": float(abs(mix["energy"][0] - f64["energy"][0]))}
+                     "energy_abs_eV": float(abs(mix["energy"][0] - f64["energy"][0])),
+                     "stress_max_abs_eV": float(np.abs(mix["stress"] - f64["stress"]).max())}
 
     # roofline of the dominant kernel of the evaluation (largest average launch time)
     prec = a.precision
@@ -282,19 +283,23 @@ def main():
         us = r["kernels"]["efs_moments" if k == "efs_moments_contract" else k]["avg_us"]
         per_kernel[k] = {"avg_us": us, "flops_per_atom": f, "bound": "alu", "peak_tflops": PEAK_VALU_TFLOPS,
                          "tflops": f * cfg.n / max(us * 1e-6, 1e-12) / 1e12}
-    gf = 2.0 * m * m * (1 if prec == "fp64" else 6)
+    # grade: 2 m^2 FP64 flops per row, or 19 int8 digit products of 2 m^2 ops each
+    gf = 2.0 * m * m * (1 if prec == "fp64" else GRADE_I8_PRODUCTS)
     gus = r["kernels"]["grade"]["avg_us"]
     per_kernel["grade"] = {"avg_us": gus, "flops_per_atom": gf, "bound": "mfma",
-                           "peak_tflops": PEAK_MFMA_F64_TFLOPS if prec == "fp64" else PEAK_MFMA_BF16_TFLOPS,
+                           "peak_tflops": PEAK_MFMA_F64_TFLOPS if prec == "fp64" else PEAK_MFMA_I8_TOPS,
+                           "unit": "TFLOP/s" if prec == "fp64" else "TOP/s (int8)",
                            "tflops": gf * cfg.n / max(gus * 1e-6, 1e-12) / 1e12}
     dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"])
     d = per_kernel[dom]
-    rocprof_name = {"efs_moments": f"efs_moments<{'double' if prec == 'fp64' else 'float'}, {level}, {tuned[prec][0]}>",
-                    "efs_moments_contract": f"efs_moments_contract<{'double' if prec == 'fp64' else 'float'}, {level}, "
-                                            "true>",
-                    "efs_contract": f"efs_contract<{'double' if prec == 'fp64' else 'float'}, {level}, true>",
-                    "efs_forces": f"efs_forces_rows<{'double' if prec == 'fp64' else 'float'}, {level}, {tuned[prec][1]}>",
-                    "grade": "grade_f64" if prec == "fp64" else "grade_bf16<3>"}[dom]
+    # with grades the moments and contraction run in FP64 in both forms (FP64 rows)
+    mc8 = "8" if tuned[prec][0] == 8 else ""
+    rocprof_name = {"efs_moments": f"efs_moments<double, {level}, {tuned[prec][0]}>",
+                    "efs_moments_contract": f"efs_moments_contract{mc8}<double, {level}, true>",
+                    "efs_contract": f"efs_contract<double, {level}, true>",
+                    "efs_forces": f"efs_forces_rows<{'double' if prec == 'fp64' else 'float'}, double, {level}, "
+                                  f"{tuned[prec][1]}>",
+                    "grade": "grade_f64" if prec == "fp64" else f"grade_i8<{(m + 63) // 64}>"}[dom]
     traffic = recorded_traffic(rocprof_name)
     out = {
         "metric": "atom-steps/s (E+F+stress+grade), level-16 MTP",
@@ -308,7 +313,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == "fp64" else "f32+bf16x3",
+        "dtype": "f64" if prec == "fp64" else "f64 rows + f32 pair gradients + i8 slice MFMA",
         "data": "synthetic (seeded FCC alloy, seeded teacher potential)",
         "config": {"workload": "fcc-alloy-16x16x16-level16-2species", "atoms": cfg.n, "level": level,
                    "n_types": n_types, "r_cut": w.r_cut, "grade_mode": "full", "m": m,
@@ -319,7 +324,8 @@ def main():
         "with_rebuild": {"atom_steps_per_s": r["with_rebuild_atom_steps_per_s"],
                          "ms_per_step": r["with_rebuild_ms_per_step"],
                          "neighbor_build_us": r["kernels"]["neighbors"]["avg_us"]},
-        "roofline": {"bound": d["bound"], "achieved": d["tflops"], "peak": d["peak_tflops"], "unit": "TFLOP/s",
+        "roofline": {"bound": d["bound"], "achieved": d["tflops"], "peak": d["peak_tflops"],
+                     "unit": d.get("unit", "TFLOP/s"),
                      "frac": d["tflops"] / d["peak_tflops"], "traffic": traffic, "kernel": rocprof_name,
                      "flops_per_atom": d["flops_per_atom"], "atoms_per_launch": cfg.n, "avg_us": d["avg_us"]},
         "evaluation_kernels": per_kernel,
@@ -478,38 +484,64 @@ def extra_workloads(timed):
 def cpu_baseline(cfg, w, theta, keep, A_full, f64, mix, n_centers):
     """The FP64 oracle on a bounded sample of the same configuration: the
     first n_centers atoms and all their neighbors get site energies, pair
-    gradients (forces / stress contributions), rows b_i and grades; also the
-    GPU-vs-oracle errors on those atoms (forces on the centers, whose
-    neighborhoods are complete)."""
+    gradients (forces / stress contributions), rows b_i and grades, on all
+    host threads; the same on an eighth of the centers on one thread.  Also
+    the GPU-vs-oracle errors: grades and site energies on the sample, and
+    energy, forces and stress of the whole configuration (oracle run outside
+    the timed sample)."""
     import torch
 
     from oracle import mtp as om
     from oracle import neighbors as onb
 
     pot = om.Potential(w.level, w.n_types, w.r_min, w.r_cut)
-    centers = np.arange(max(1, min(n_centers, cfg.n)))
-    around = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, w.r_cut, atoms=centers)
-    atoms = np.unique(np.concatenate([centers, around.j]))
-    pairs = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, w.r_cut, atoms=atoms)
-    t = time.perf_counter()
-    _, F, _, V = om.energy_forces_stress(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs)
-    rows = om.b_rows(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs, atoms=atoms)[:, keep]
-    gam = om.grades(rows, A_full)[0]
-    dt = time.perf_counter() - t
+
+    def sample(n_c):
+        centers = np.arange(max(1, min(n_c, cfg.n)))
+        around = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, w.r_cut, atoms=centers)
+        atoms = np.unique(np.concatenate([centers, around.j]))
+        pairs = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, w.r_cut, atoms=atoms)
+        t = time.perf_counter()
+        _, F, _, V = om.energy_forces_stress(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs)
+        rows = om.b_rows(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs, atoms=atoms)[:, keep]
+        gam = om.grades(rows, A_full)[0]
+        return time.perf_counter() - t, centers, atoms, V, rows, gam
+
+    threads = torch.get_num_threads()
+    dt, centers, atoms, V, rows, gam = sample(n_centers)
+    torch.set_num_threads(1)
+    try:
+        dt1, _, atoms1, _, _, _ = sample(max(1, n_centers // 8))
+    finally:
+        torch.set_num_threads(threads)
+    log(f"[bench] oracle sample: {len(atoms)} neighborhoods in {dt:.1f} s on {threads} threads, "
+        f"{len(atoms1)} in {dt1:.1f} s on one thread")
+    # whole-configuration energy, forces and stress (not timed)
+    pairs_all = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, w.r_cut)
+    E, F, S, _ = om.energy_forces_stress(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs_all)
     errs = {}
     for name, g in (("fp64", f64), ("mixed", mix)):
         errs[name] = {"site_e_max_abs": float(np.abs(g["site_e"][atoms] - V[atoms]).max()),
                       "gamma_max_rel": float((np.abs(g["gamma"][atoms] - gam) / np.maximum(1, gam)).max()),
-                      "forces_max_abs_eVA": float(np.abs(g["forces"][centers] - F[centers]).max())}
-    # what the FP32 rows alone force on the mixed grade: the oracle's rows rounded
-    # to FP32, graded in FP64; and the conditioning of A that amplifies it
+                      "gamma_normwise_rel": float(np.abs(g["gamma"][atoms] - gam).max() / np.abs(gam).max()),
+                      "gamma_sample_atoms": int(len(atoms)),
+                      "energy_rel": float(abs(g["energy"][0] - E) / abs(E)),
+                      "forces_max_abs_eVA": float(np.abs(g["forces"] - F).max()),
+                      "forces_normwise_rel": float(np.abs(g["forces"] - F).max() / np.abs(F).max()),
+                      "stress_max_abs_eV": float(np.abs(g["stress"][0] - S).max()),
+                      "stress_normwise_rel": float(np.abs(g["stress"][0] - S).max() / np.abs(S).max())}
+    # what FP32 rows alone would force on a grade: the oracle's rows rounded to
+    # FP32, graded in FP64; and the conditioning of A that amplifies it
     g32 = om.grades(rows.astype(np.float32).astype(np.float64), A_full)[0]
-    errs["mixed_gamma_predicted_from_fp32_rows"] = float((np.abs(g32 - gam) / np.maximum(1, gam)).max())
+    errs["gamma_from_fp32_rows_predicted"] = float((np.abs(g32 - gam) / np.maximum(1, gam)).max())
     errs["kappa_A_column_equilibrated"] = float(np.linalg.cond(A_full / np.abs(A_full).max(axis=0)))
-    base = {"value": len(atoms) / dt, "unit": "atom-steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
+    base = {"value": len(atoms) / dt, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(atoms)} neighborhoods ({len(centers)} atoms and all their neighbors) of the same "
                       f"16,384-atom configuration: site energies, pair gradients, rows b_i and grades "
-                      f"(neighbor search excluded)", "seconds": dt}
+                      f"(neighbor search excluded)", "seconds": dt,
+            "single_core": {"value": len(atoms1) / dt1, "unit": "atom-steps/s", "cores": 1,
+                            "sample": f"{len(atoms1)} neighborhoods ({max(1, n_centers // 8)} atoms and all their "
+                                      f"neighbors), the same steps", "seconds": dt1}}
     return base, errs
 
 

@@ -64,9 +64,14 @@ typedef enum {
 
 typedef enum { MTP_FP64 = 0, MTP_MIXED = 1 } mtp_precision;
 /* MTP_FP64: every step in double precision.
- * MTP_MIXED: radial functions, moments, contractions, pair gradients and b
- *   rows in FP32; grade product on MFMA with BF16 split operands and FP32
- *   accumulation; energy, force and stress sums, A^-1 and MaxVol in FP64. */
+ * MTP_MIXED: pair gradients (the force and stress terms) in FP32 with FP64
+ *   sums; energies, forces and stress only: radial functions, moments and
+ *   contractions in FP32 too.  When grades or rows are asked for, the
+ *   moments, contractions and rows run in FP64 (the grade amplifies row
+ *   errors by the conditioning of A: FP32 rows miss gamma to 1e-5 on a
+ *   level-16 active set) and the grade product is an int8 slice product
+ *   on MFMA with exact int32 accumulation (m <= 320; FP64 MFMA beyond).
+ *   A^-1 and MaxVol in FP64 in both forms. */
 
 typedef enum {
     MTP_GRADE_FULL = 0,
@@ -192,14 +197,13 @@ int mtp_energy_forces_stress(const mtp_model *m, const mtp_system *s, const mtp_
 /* Grades gamma_i = max_p |(b_i A^-1)_p| of every neighborhood (Sec. II.D)
  * and the argmax p (lowest on ties).  gamma [n_atoms] FP64, argmax
  * [n_atoms] int32 or NULL; b_rows (optional) receives the rows, [n_atoms*m]
- * row-major, FP64 for MTP_FP64 and FP32 for MTP_MIXED.  Needs the mode's
- * active set. */
+ * row-major FP64 (both precisions).  Needs the mode's active set. */
 int mtp_grade(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
               double *gamma, int32_t *argmax, void *b_rows, void *stream);
 
 /* Configuration grades (Sec. II.C): gamma(cfg) = max_p |(b(cfg) A^-1)_p|
- * with b(cfg) = sum of the rows b_i of the configuration's atoms (summed in
- * FP64; the b_i in FP64 for MTP_FP64, FP32 for MTP_MIXED) and A the active
+ * with b(cfg) = sum of the rows b_i of the configuration's atoms (FP64 rows
+ * and sums in both precisions) and A the active
  * set of mode g (MTP_GRADE_FULL_CFG or MTP_GRADE_LINEAR_CFG; the product in
  * FP64 in both precisions).  gamma [n_cfg] FP64 and argmax [n_cfg] int32
  * (lowest p on ties) may be NULL when b_cfg is given; b_cfg [n_cfg*m] FP64

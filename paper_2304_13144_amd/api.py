@@ -201,9 +201,8 @@ def grade(model, batch, nbrs, precision="fp64", mode="full", rows=False):
     g = _out(batch.n_atoms, torch.float64, d)
     am = _out(batch.n_atoms, torch.int32, d)
     b = None
-    if rows:
-        dt = torch.float64 if _prec(precision) == MTP_FP64 else torch.float32
-        b = _out(None, dt, d, (batch.n_atoms, model.m(mode)))
+    if rows:   # FP64 in both forms
+        b = _out(None, torch.float64, d, (batch.n_atoms, model.m(mode)))
     s = batch.system()
     check(_lib.lib().mtp_grade(model._h, ctypes.byref(s), nbrs._h, _prec(precision), _mode(mode), _p(g), _p(am),
                                _p(b), _stream()))

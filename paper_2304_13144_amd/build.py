@@ -65,18 +65,28 @@ def generate(levels):
                        f'#include "mtp_level{L}.inc"\n{macro}({L}, {T})\n}}  // namespace mtp\n')
                 _write_if_changed(path, src)
                 units.append(path)
-    decl = "".join(f"template <> int launch_efs_level_t<{L}, {T}>(const EfsArgs &a);\n"
+    decl = "".join(f"template <> int launch_mc_level_t<{L}, {T}>(const EfsArgs &a);\n"
+                   f"template <> int launch_fr_level_t<{L}, {T}, {T}>(const EfsArgs &a);\n"
                    f"template <> int launch_backward_level_t<{L}, {T}>(const BwdArgs &b);\n"
                    for L in levels for T in ("double", "float"))
-    cases = "".join(f"        case {L}: return f64 ? launch_efs_level_t<{L}, double>(a) : launch_efs_level_t<{L}, float>(a);\n"
-                    for L in levels)
+    decl += "".join(f"template <> int launch_fr_level_t<{L}, float, double>(const EfsArgs &a);\n" for L in levels)
+    # moments / contraction in FP64 for the FP64 form and for the mixed form when
+    # it writes rows (rows are FP64); pair gradients in the form's own type
+    mc = "".join(f"        case {L}: e = mc64 ? launch_mc_level_t<{L}, double>(a) : launch_mc_level_t<{L}, float>(a); break;\n"
+                 for L in levels)
+    fr = "".join(f"        case {L}: return f64 ? launch_fr_level_t<{L}, double, double>(a)\n"
+                 f"                     : (mc64 ? launch_fr_level_t<{L}, float, double>(a) : launch_fr_level_t<{L}, float, float>(a));\n"
+                 for L in levels)
     bcases = "".join(f"        case {L}: return f64 ? launch_backward_level_t<{L}, double>(b) : "
                      f"launch_backward_level_t<{L}, float>(b);\n" for L in levels)
     disp = ('#include "internal.hpp"\nnamespace mtp {\n'
-            + "template <int L, typename T> int launch_efs_level_t(const EfsArgs &a);\n"
+            + "template <int L, typename T> int launch_mc_level_t(const EfsArgs &a);\n"
+            + "template <int L, typename TF, typename TD> int launch_fr_level_t(const EfsArgs &a);\n"
             + "template <int L, typename T> int launch_backward_level_t(const BwdArgs &b);\n"
             + decl + "int launch_efs(int level, const EfsArgs &a) {\n    const bool f64 = a.precision == MTP_FP64;\n"
-            + "    switch (level) {\n" + cases
+            + "    const bool mc64 = f64 || a.brow != nullptr;\n    int e = 0;\n"
+            + "    switch (level) {\n" + mc + "        default: return -1;\n    }\n    if (e) return e;\n"
+            + "    switch (level) {\n" + fr
             + "        default: return -1;\n    }\n}\n"
             + "int launch_backward(int level, const BwdArgs &b) {\n    const bool f64 = b.e.precision == MTP_FP64;\n"
             + "    switch (level) {\n" + bcases

@@ -209,7 +209,10 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     if (want_grade) MTP_CHECK(m->act[o.mode].valid, MTP_E_INVAL, "no active set for this grade mode");
     MTP_HIP(hipSetDevice(m->device));
     const int64_t n = s->n_atoms;
+    // tsz: the pair gradients' type; msz: the moments' and dE/dM's (FP64 in
+    // the mixed form too when rows are wanted: rows are always FP64)
     const size_t tsz = prec == MTP_FP64 ? sizeof(double) : sizeof(float);
+    const size_t msz = (prec == MTP_FP64 || want_rows) ? sizeof(double) : sizeof(float);
     const bool want_f = o.forces != nullptr;
     const bool want_v = o.stress != nullptr;
     const bool want_e = o.energy || o.site_e;
@@ -222,7 +225,7 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
         m->sitebuf.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, n));
         site = m->sitebuf.as<double>();
     }
-    if (want_rows) m->brow.ensure(tsz * (size_t)ldb * (size_t)std::max<int64_t>(1, n));
+    if (want_rows) m->brow.ensure(sizeof(double) * (size_t)ldb * (size_t)std::max<int64_t>(1, n));
     if (n == 0) {
         if (o.energy) launch_zero(o.energy, sizeof(double) * s->n_cfg, st);
         if (o.stress) launch_zero(o.stress, sizeof(double) * 9 * s->n_cfg, st);
@@ -239,14 +242,14 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     a.type = s->type;
     a.r_min = m->r_min;
     a.r_cut = m->r_cut;
-    const char *th = prec == MTP_FP64 ? static_cast<const char *>(m->theta64.ptr) : static_cast<const char *>(m->theta32.ptr);
-    a.xi0 = th;
-    a.xi = th + tsz * m->n_types;
-    a.c = th + tsz * (m->n_types + m->basis.n_lin());
+    a.th64 = m->theta64.as<double>();
+    a.th32 = m->theta32.as<float>();
+    a.n_lin = m->basis.n_lin();
     a.site_e = want_e ? site : nullptr;
     a.gbuf = want_f ? m->gbuf.ptr : nullptr;
     a.virial = want_v ? m->virial.as<double>() : nullptr;
-    a.brow = want_rows ? m->brow.ptr : nullptr;
+    a.brow = want_rows ? m->brow.as<double>() : nullptr;
+    a.ldn = n;
     a.ldb = ldb;
     a.grade_mode = o.mode;
     a.colmap = m->colmap.as<int32_t>();
@@ -256,8 +259,8 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     a.lanes = sched & 15;
     a.lanes_mc = sched >> 4;
     a.stream = st;
-    m->mbuf.ensure(tsz * m->basis.n_comp() * (size_t)n);
-    m->dmbuf.ensure(tsz * m->basis.n_comp() * (size_t)n);
+    m->mbuf.ensure(msz * m->basis.n_comp() * (size_t)n);
+    m->dmbuf.ensure(msz * m->basis.n_comp() * (size_t)n);
     a.mbuf = m->mbuf.ptr;
     a.dmbuf = m->dmbuf.ptr;
     // per-configuration sums: chunk partials, then one block per configuration.
@@ -303,7 +306,7 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
         }
         {
             ProfScope ps("grade", st);
-            launch_grade(m->act[o.mode], prec, m->brow.ptr, ldb, n, gam, o.argmax, st, o.sel_thr, blk);
+            launch_grade(m->act[o.mode], prec, m->brow.as<double>(), ldb, n, n, gam, o.argmax, st, o.sel_thr, blk);
         }
         if (want_sel) {
             ProfScope ps("select", st);
@@ -312,7 +315,7 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
                                 want_sums ? &sums : nullptr, fuse_gather ? &ga : nullptr);
         }
     }
-    if (o.b_rows) launch_copy_rows(m->brow.ptr, ldb, mm, n, prec, o.b_rows, st);
+    if (o.b_rows) launch_copy_rows(m->brow.as<double>(), n, mm, n, static_cast<double *>(o.b_rows), st);
     MTP_HIP(hipGetLastError());
 }
 
@@ -655,7 +658,7 @@ int mtp_grade_cfg(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, m
     const bool want_grade = gamma || argmax;
     if (want_grade) MTP_CHECK(m->act[g].valid, MTP_E_INVAL, "no active set for this grade mode");
     hipStream_t st = S(stream);
-    // the neighborhood rows of every atom (FP64 or FP32), left in m->brow
+    // the neighborhood rows of every atom (FP64, column-major), left in m->brow
     EvalOut o;
     o.mode = g & 1;
     o.keep_rows = true;
@@ -668,15 +671,15 @@ int mtp_grade_cfg(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, m
         launch_zero(m->cfgrows.ptr, sizeof(double) * (size_t)ldb * s->n_cfg, st);
     } else {
         ProfScope ps("cfg_rows", st);
-        launch_cfg_rows(m->brow.ptr, p, ldb, n, s, m->cfgpart.as<double>(), m->cfgrows.as<double>(), st);
+        launch_cfg_rows(m->brow.as<double>(), ldb, n, s, m->cfgpart.as<double>(), m->cfgrows.as<double>(), st);
     }
     if (want_grade) {
         m->gamma_ws.ensure(sizeof(double) * s->n_cfg);
         ProfScope ps("grade", st);
-        launch_grade(m->act[g], MTP_FP64, m->cfgrows.ptr, ldb, s->n_cfg, gamma ? gamma : m->gamma_ws.as<double>(),
-                     argmax, st);
+        launch_grade(m->act[g], MTP_FP64, m->cfgrows.as<double>(), ldb, s->n_cfg, s->n_cfg,
+                     gamma ? gamma : m->gamma_ws.as<double>(), argmax, st);
     }
-    if (b_cfg) launch_copy_rows(m->cfgrows.ptr, ldb, mm, s->n_cfg, MTP_FP64, b_cfg, st);
+    if (b_cfg) launch_copy_rows(m->cfgrows.as<double>(), s->n_cfg, mm, s->n_cfg, b_cfg, st);
     MTP_HIP(hipGetLastError());
     API_END
 }
@@ -744,11 +747,11 @@ int mtp_b_rows(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_
     a.type = s->type;
     a.r_min = m->r_min;
     a.r_cut = m->r_cut;
-    const char *th = static_cast<const char *>(m->theta64.ptr);
-    a.xi0 = th;
-    a.xi = th + sizeof(double) * m->n_types;
-    a.c = th + sizeof(double) * (m->n_types + m->basis.n_lin());
-    a.brow = m->brow.ptr;
+    a.th64 = m->theta64.as<double>();
+    a.th32 = m->theta32.as<float>();
+    a.n_lin = m->basis.n_lin();
+    a.brow = m->brow.as<double>();
+    a.ldn = n_idx;
     a.ldb = ldb;
     a.grade_mode = g;
     a.colmap = m->colmap.as<int32_t>();
@@ -763,7 +766,7 @@ int mtp_b_rows(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_
     a.dmbuf = m->dmbuf.ptr;
     int e = launch_efs(m->level, a);
     MTP_CHECK(e == 0, MTP_E_HIP, std::string("efs kernel launch: ") + hipGetErrorString((hipError_t)e));
-    launch_copy_rows(m->brow.ptr, ldb, mm, n_idx, MTP_FP64, rows, S(stream));
+    launch_copy_rows(m->brow.as<double>(), n_idx, mm, n_idx, rows, S(stream));
     API_END
 }
 
@@ -1195,10 +1198,9 @@ int mtp_efs_backward(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb
     a.type = s->type;
     a.r_min = m->r_min;
     a.r_cut = m->r_cut;
-    const char *th = p == MTP_FP64 ? static_cast<const char *>(m->theta64.ptr) : static_cast<const char *>(m->theta32.ptr);
-    a.xi0 = th;
-    a.xi = th + tsz * m->n_types;
-    a.c = th + tsz * (m->n_types + m->basis.n_lin());
+    a.th64 = m->theta64.as<double>();
+    a.th32 = m->theta32.as<float>();
+    a.n_lin = m->basis.n_lin();
     a.precision = p;
     a.lanes = 4;
     a.lanes_mc = 4;

@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void bwd_contract(const BwdArgs b) {
     const T gE = b.gE ? T(b.gE[b.atom_cfg[slot]]) : T(0);
     T *row = static_cast<T *>(b.rows) + slot * (int64_t)b.n_theta;
     for (int t = 0; t < nt; ++t) row[t] = t == zi ? gE : T(0);
-    LV::template contract<Dual<T>, true>(M, XiConst<T>{static_cast<const T *>(a.xi)}, GradSink<T>{row + nt, gE}, dM,
+    LV::template contract<Dual<T>, true>(M, XiConst<T>{xi_of<T>(a)}, GradSink<T>{row + nt, gE}, dM,
                                          V);
     T *dv = static_cast<T *>(a.dmbuf);
     T *dt = static_cast<T *>(b.dtbuf);

@@ -15,6 +15,10 @@
 //   P_mu(r) = sum_{k in mu} (dV/dM_k) x^a y^b z^c  (k = component (mu; a,b,c)).
 // b-row entries of c (eq. 4): dV_i/dc^(beta)_{mu,z_i,z} = sum_{j: z_j = z} Q_beta(r_ij) P_mu(r_ij),
 // Q_beta = T_beta(x) (R_cut - r)^2.
+//
+// Rows are FP64 in every form and stored column-major: entry (i, k) at
+// brow[k * ldn + i], so that the lanes of a wavefront (consecutive
+// neighborhoods) write consecutive words of one column.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -62,6 +66,16 @@ template <typename T> __device__ inline void monomials(T x, T y, T z, T (&m)[20]
 
 }  // namespace efs
 
+// theta = [xi_0 (n_types) | xi_alpha (n_lin) | c] in the arithmetic type T
+template <typename T> __device__ inline const T *theta_of(const EfsArgs &a);
+template <> __device__ inline const double *theta_of<double>(const EfsArgs &a) { return a.th64; }
+template <> __device__ inline const float *theta_of<float>(const EfsArgs &a) { return a.th32; }
+template <typename T> __device__ inline const T *xi0_of(const EfsArgs &a) { return theta_of<T>(a); }
+template <typename T> __device__ inline const T *xi_of(const EfsArgs &a) { return theta_of<T>(a) + a.n_types; }
+template <typename T> __device__ inline const T *coef_of(const EfsArgs &a) {
+    return theta_of<T>(a) + a.n_types + a.n_lin;
+}
+
 template <typename T> struct XiPtr {      // xi_alpha, read where the program needs it
     const T *p;
     __device__ T operator[](int k) const { return p[k]; }
@@ -103,7 +117,7 @@ template <typename A> __device__ inline int tcount(const A &a, const AtomCtx &c,
 }
 
 template <typename T, int NR, int BS = 256> __device__ inline void load_coefs(const EfsArgs &a, T *c_s) {
-    const T *cg = static_cast<const T *>(a.c);
+    const T *cg = coef_of<T>(a);
     const int ncoef = NR * a.n_types * a.n_types * NPOLY;
     for (int k = threadIdx.x; k < ncoef; k += BS) c_s[k] = cg[k];
     __syncthreads();
@@ -203,44 +217,65 @@ template <typename T> struct ColLoad {   // component k of one neighborhood, [k]
     int64_t s;
     __device__ T operator[](int k) const { return p[k * s]; }
 };
-template <typename T> struct RowSink {   // receives B_alpha when enabled
+template <typename T> struct LdsSink {   // receives B_alpha into [alpha][64] in LDS
     T *p;
+    __device__ T &operator[](int k) const { return p[k * 64]; }
+};
+// receives B_alpha straight into column c0 + alpha of the FP64 rows (when
+// staging them would not fit in LDS): a uniform column base plus the lane's
+// row index, consecutive lanes writing consecutive words
+struct ColSink {
+    double *p;
+    int64_t s;
+    int c0;
+    uint32_t row;
     bool on;
     struct Ref {
-        T *q;
+        double *col;
+        uint32_t row;
         bool on;
-        __device__ void operator=(const T &v) const {
-            if (on) *q = v;
+        __device__ void operator=(const double &v) const {
+            if (on) col[row] = v;
         }
     };
-    __device__ Ref operator[](int k) const { return Ref{p + k, on}; }
+    __device__ Ref operator[](int k) const { return Ref{p + (int64_t)(c0 + k) * s, row, on}; }
+};
+struct NoSink {
+    struct Ref {
+        template <typename V> __device__ void operator=(const V &) const {}
+    };
+    __device__ Ref operator[](int) const { return Ref{}; }
 };
 
 template <typename T> struct LdsCol {   // component k of one neighborhood, [k][64] in LDS
     const T *p;
     __device__ T operator[](int k) const { return p[k * 64]; }
 };
-template <typename T> struct LdsSink {   // receives B_alpha into [alpha][64] in LDS
-    T *p;
-    __device__ T &operator[](int k) const { return p[k * 64]; }
-};
 
-// B_alpha of a block's 64 neighborhoods are staged in LDS ([NLIN][64]) and
-// written as whole rows when that fits in STAGE_BYTES; otherwise each lane
-// writes its own row entries (strided by the row length)
+// Rows of graph values / B_alpha staged in LDS: the graph values, and with
+// rows wanted (WB) B_alpha in the same place once the graph values are read,
+// when that fits in STAGE_BYTES (else B_alpha goes straight to memory).
 constexpr int STAGE_BYTES = 64 * 1024;
-template <typename T, int L> constexpr bool stage_rows() { return Level<L>::NLIN * 64 * sizeof(T) <= STAGE_BYTES; }
-template <typename T, int L> constexpr int stage_len() { return stage_rows<T, L>() ? Level<L>::NLIN : 1; }
+template <typename T, int L, bool WB> constexpr bool stage_b() {
+    return WB && Level<L>::NLIN * 64 * (int)sizeof(T) <= STAGE_BYTES;
+}
+template <typename T, int L, bool WB> constexpr int sg_rows() {
+    return stage_b<T, L, WB>() && Level<L>::NLIN > Level<L>::NGRAPH ? Level<L>::NLIN : Level<L>::NGRAPH;
+}
 
 // The contraction of the 64 neighborhoods of block blk (a block of NW = 4
 // or 8 wavefronts), the moments read through M; sg, sdm: LDS scratch.
-template <typename T, int L, bool WB, typename MA, int NW = 4>
+// ALIAS: sdm shares its storage with the moments M (they are dead once every
+// wavefront has finished its reverse part, which a barrier makes sure of).
+// WB: B_alpha goes into the rows (FP64 only: rows are always FP64), staged
+// in sg and written column by column (64 consecutive rows per store).
+template <typename T, int L, bool WB, typename MA, int NW = 4, bool ALIAS = false>
 __device__ inline void contract_body(const EfsArgs &a, int64_t blk, const MA &M,
-                                     T (&sg)[Level<L>::NGRAPH][64], T (&sdm)[Level<L>::NC][64],
-                                     T (&sB)[stage_len<T, L>()][64]) {
+                                     T (&sg)[sg_rows<T, L, WB>()][64], T (&sdm)[Level<L>::NC][64]) {
     using LV = Level<L>;
     constexpr int NC = LV::NC, NG = LV::NGRAPH;
     static_assert(LV::NPART == 4 && LV::NPART8 == 8 && (NW == 4 || NW == 8), "four or eight parts");
+    static_assert(!WB || sizeof(T) == sizeof(double), "rows are FP64");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t slot = blk * 64 + lane;
     const bool live = slot < a.n_atoms;
@@ -276,16 +311,22 @@ __device__ inline void contract_body(const EfsArgs &a, int64_t blk, const MA &M,
     for (int G = 0; G < NG; ++G) gin[G] = sg[G][lane];
     T V = T(0);
     const int nt = a.n_types;
-    const XiPtr<T> xi{static_cast<const T *>(a.xi)};
-    if (WB && wave == 0) {
-        if constexpr (stage_rows<T, L>()) {
-            LV::template trie<T, true>(gin, xi, LdsSink<T>{&sB[0][lane]}, dg, V);
+    const XiPtr<T> xi{xi_of<T>(a)};
+    if constexpr (stage_b<T, L, WB>()) {
+        __syncthreads();   // every wavefront has read the graph values: sg takes B_alpha
+        if (wave == 0) {
+            LV::template trie<T, true>(gin, xi, LdsSink<T>{&sg[0][lane]}, dg, V);
         } else {
-            T *row = static_cast<T *>(a.brow) + sl * (int64_t)a.ldb + nt;
-            LV::template trie<T, true>(gin, xi, RowSink<T>{row, live}, dg, V);
+            LV::template trie<T, false>(gin, xi, NoSink{}, dg, V);
+        }
+    } else if constexpr (WB) {
+        if (wave == 0) {
+            LV::template trie<T, true>(gin, xi, ColSink{a.brow, a.ldn, nt, (uint32_t)sl, live}, dg, V);
+        } else {
+            LV::template trie<T, false>(gin, xi, NoSink{}, dg, V);
         }
     } else {
-        LV::template trie<T, false>(gin, xi, RowSink<T>{nullptr, false}, dg, V);
+        LV::template trie<T, false>(gin, xi, NoSink{}, dg, V);
     }
     T dMp[NC];
     if constexpr (NW == 4) {
@@ -307,6 +348,7 @@ __device__ inline void contract_body(const EfsArgs &a, int64_t blk, const MA &M,
             default: LV::template reverse_part8<7>(M, dg, dMp); break;
         }
     }
+    if constexpr (ALIAS) __syncthreads();   // every reverse part has read M
     for (int w = 0; w < NW; ++w) {
         if (wave == w) {
 #pragma unroll
@@ -314,14 +356,10 @@ __device__ inline void contract_body(const EfsArgs &a, int64_t blk, const MA &M,
         }
         __syncthreads();
     }
-    if (WB && stage_rows<T, L>()) {   // B_alpha rows: consecutive threads, consecutive columns
-        constexpr int NL = LV::NLIN;
-        const int64_t nlive = a.n_atoms - blk * 64;
-        T *rows = static_cast<T *>(a.brow) + blk * 64 * (int64_t)a.ldb + nt;
-        for (int e = threadIdx.x; e < 64 * NL; e += 64 * NW) {
-            const int r = e / NL, k = e % NL;
-            if (r < nlive) rows[r * (int64_t)a.ldb + k] = sB[k][r];
-        }
+    if constexpr (stage_b<T, L, WB>()) {   // B_alpha (written to sg by wavefront 0 before the barriers above)
+        double *col = a.brow + (int64_t)nt * a.ldn + sl;
+        if (live)
+            for (int k = wave; k < LV::NLIN; k += NW) col[(int64_t)k * a.ldn] = sg[k][lane];
     }
     if (live) {
         T *dout = static_cast<T *>(a.dmbuf);
@@ -330,7 +368,7 @@ __device__ inline void contract_body(const EfsArgs &a, int64_t blk, const MA &M,
             const int64_t atom = a.atom_list ? (int64_t)a.atom_list[slot] : slot;
             int zi = a.type[atom];
             zi = zi < 0 ? 0 : (zi >= nt ? nt - 1 : zi);
-            a.site_e[atom] = double(V) + double(static_cast<const T *>(a.xi0)[zi]);
+            a.site_e[atom] = double(V) + double(xi0_of<T>(a)[zi]);
         }
     }
 }
@@ -338,19 +376,20 @@ __device__ inline void contract_body(const EfsArgs &a, int64_t blk, const MA &M,
 template <typename T, int L, bool WB>
 __global__ __launch_bounds__(256) void efs_contract(const EfsArgs a) {
     using LV = Level<L>;
-    __shared__ T sg[LV::NGRAPH][64];
+    __shared__ T sg[sg_rows<T, L, WB>()][64];
     __shared__ T sdm[LV::NC][64];
-    __shared__ T sB[WB ? stage_len<T, L>() : 1][64];
     const int64_t slot = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
     const int64_t sl = slot < a.n_atoms ? slot : 0;
-    contract_body<T, L, WB>(a, blockIdx.x, ColLoad<T>{static_cast<const T *>(a.mbuf) + sl, a.n_atoms}, sg, sdm,
-                            reinterpret_cast<T (&)[stage_len<T, L>()][64]>(sB));
+    contract_body<T, L, WB>(a, blockIdx.x, ColLoad<T>{static_cast<const T *>(a.mbuf) + sl, a.n_atoms}, sg, sdm);
 }
 
 // Kernels 1 and 2 in one launch (four lanes per neighborhood: the 256
 // threads of a block hold the same 64 neighborhoods in both phases): the
 // reduce-scattered moments go to LDS instead of memory, and after one
-// barrier the contraction reads them there.
+// barrier the contraction reads them there.  dV/dM reuses the moments'
+// LDS and B_alpha the graph values', so a block holds the radial
+// coefficients, the moments and max(graph values, B_alpha) only (78 KB at
+// level 16 in FP64 with rows, 45 KB without: two blocks per CU).
 template <typename T, int L, bool WB>
 __global__ __launch_bounds__(256) void efs_moments_contract(const EfsArgs a) {
     using LV = Level<L>;
@@ -358,9 +397,7 @@ __global__ __launch_bounds__(256) void efs_moments_contract(const EfsArgs a) {
     constexpr int NCP = (NC + K - 1) / K * K;
     __shared__ T c_s[NR * MAX_TYPES * MAX_TYPES * NPOLY];
     __shared__ T sM[NCP][64];
-    __shared__ T sg[LV::NGRAPH][64];
-    __shared__ T sdm[NC][64];
-    __shared__ T sB[WB ? stage_len<T, L>() : 1][64];
+    __shared__ T sg[sg_rows<T, L, WB>()][64];
     load_coefs<T, NR>(a, c_s);
     const int sub = threadIdx.x % K;
     const AtomCtx c = atom_ctx<K>(a);
@@ -372,8 +409,8 @@ __global__ __launch_bounds__(256) void efs_moments_contract(const EfsArgs a) {
         for (int i = 0; i < NCP / K; ++i) sM[sub * (NCP / K) + i][la] = M[i];
     }
     __syncthreads();
-    contract_body<T, L, WB>(a, blockIdx.x, LdsCol<T>{&sM[0][threadIdx.x & 63]}, sg, sdm,
-                            reinterpret_cast<T (&)[stage_len<T, L>()][64]>(sB));
+    contract_body<T, L, WB, LdsCol<T>, 4, true>(a, blockIdx.x, LdsCol<T>{&sM[0][threadIdx.x & 63]}, sg,
+                                                 reinterpret_cast<T (&)[NC][64]>(sM));
 }
 
 // The same with eight wavefronts (512 threads, eight lanes per neighborhood
@@ -387,9 +424,7 @@ __global__ __launch_bounds__(512) void efs_moments_contract8(const EfsArgs a) {
     constexpr int NCP = (NC + K - 1) / K * K;
     __shared__ T c_s[NR * MAX_TYPES * MAX_TYPES * NPOLY];
     __shared__ T sM[NCP][64];
-    __shared__ T sg[LV::NGRAPH][64];
-    __shared__ T sdm[NC][64];
-    __shared__ T sB[WB ? stage_len<T, L>() : 1][64];
+    __shared__ T sg[sg_rows<T, L, WB>()][64];
     load_coefs<T, NR, 512>(a, c_s);
     const int sub = threadIdx.x % K;
     const AtomCtx c = atom_ctx<K, 512>(a);
@@ -401,8 +436,8 @@ __global__ __launch_bounds__(512) void efs_moments_contract8(const EfsArgs a) {
         for (int i = 0; i < NCP / K; ++i) sM[sub * (NCP / K) + i][la] = M[i];
     }
     __syncthreads();
-    contract_body<T, L, WB, LdsCol<T>, 8>(a, blockIdx.x, LdsCol<T>{&sM[0][threadIdx.x & 63]}, sg, sdm,
-                                          reinterpret_cast<T (&)[stage_len<T, L>()][64]>(sB));
+    contract_body<T, L, WB, LdsCol<T>, 8, true>(a, blockIdx.x, LdsCol<T>{&sM[0][threadIdx.x & 63]}, sg,
+                                                 reinterpret_cast<T (&)[NC][64]>(sM));
 }
 
 // Chebyshev values (and derivatives) at u for the radial basis (eq. 4)
@@ -423,12 +458,14 @@ __device__ inline void chebyshev(T u, T (&Tb)[NPOLY], T (&dT)[NPOLY]) {
 
 // dE/dM of the block's neighborhoods in LDS, [k][neighborhood in block]: the
 // K lanes of a neighborhood read the same word (broadcast); in registers
-// they would cost 2 NC VGPRs per lane.
-template <typename T, int NC, int K>
+// they would cost 2 NC VGPRs per lane.  TD: the type dV/dM was computed in
+// (FP64 when the FP32 pair gradients of the mixed form follow an FP64
+// contraction that also fed the rows).
+template <typename T, int NC, int K, typename TD = T>
 __device__ inline void load_dm(const EfsArgs &a, const AtomCtx &c, int sub, T (&s_dm)[NC][256 / K]) {
-    const T *din = static_cast<const T *>(a.dmbuf);
+    const TD *din = static_cast<const TD *>(a.dmbuf);
     const int la = threadIdx.x / K;
-    for (int k = sub; k < NC; k += K) s_dm[k][la] = c.live ? din[(int64_t)k * a.n_atoms + c.slot] : T(0);
+    for (int k = sub; k < NC; k += K) s_dm[k][la] = c.live ? T(din[(int64_t)k * a.n_atoms + c.slot]) : T(0);
     __syncthreads();
 }
 
@@ -438,7 +475,7 @@ __device__ inline void load_dm(const EfsArgs &a, const AtomCtx &c, int sub, T (&
 // with dE/dM), written per pair (G: gradients wanted, decided at compile time
 // so that the stores in the pair loop are unconditional); virial
 // S_ab = -sum_j g_a r_b per atom.
-template <typename T, int L, int K, bool G>
+template <typename T, int L, int K, bool G, typename TD = T>
 __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T (&s_dm)[Level<L>::NC][256 / K]) {
     using LV = Level<L>;
     constexpr int NC = LV::NC, NR = LV::NRAD;
@@ -446,7 +483,7 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
     const int nt = a.n_types;
     const int sub = threadIdx.x % K;
     const AtomCtx c = atom_ctx<K>(a, blk);
-    load_dm<T, NC, K>(a, c, sub, s_dm);
+    load_dm<T, NC, K, TD>(a, c, sub, s_dm);
     const int la = threadIdx.x / K;
     const T rc = T(a.r_cut);
     const T xs = T(2.0 / (a.r_cut - a.r_min));
@@ -565,6 +602,7 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
 template <typename T, int L, int K>
 __device__ inline void efs_rows_body(const EfsArgs &a, int64_t blk, T (&s_dm)[Level<L>::NC][256 / K],
                                      int32_t *s_col) {
+    static_assert(sizeof(T) == sizeof(double), "rows are FP64");
     using LV = Level<L>;
     constexpr int NC = LV::NC, NR = LV::NRAD, NL = LV::NLIN;
     const int nt = a.n_types;
@@ -579,7 +617,9 @@ __device__ inline void efs_rows_body(const EfsArgs &a, int64_t blk, T (&s_dm)[Le
         load_dm<T, NC, K>(a, c, sub, s_dm);   // (its barrier also covers s_col)
     }
     const int la = threadIdx.x / K;
-    T *brow = c.live ? static_cast<T *>(a.brow) + c.slot * (int64_t)a.ldb : nullptr;
+    // entry k of this neighborhood's row: brow[k * ldn] (column-major rows)
+    double *brow = c.live ? a.brow + c.slot : nullptr;
+    const int64_t ldn = a.ldn;
     const T rc = T(a.r_cut);
     const T xs = T(2.0 / (a.r_cut - a.r_min));
     const T x0 = T(-(a.r_min + a.r_cut) / (a.r_cut - a.r_min));
@@ -632,7 +672,7 @@ __device__ inline void efs_rows_body(const EfsArgs &a, int64_t blk, T (&s_dm)[Le
                 for (int i = 0; i < ND / K; ++i) {
                     const int k = sub * (ND / K) + i, mu = k / NPOLY, b = k % NPOLY;
                     const int col = s_col[((mu * nt + c.zi) * nt + t) * NPOLY + b];
-                    if (col >= 0) brow[col] = dc[i];
+                    if (col >= 0) brow[col * ldn] = dc[i];
                 }
             }
             gstart += tc;
@@ -640,32 +680,41 @@ __device__ inline void efs_rows_body(const EfsArgs &a, int64_t blk, T (&s_dm)[Le
     }
     if (brow) {
         // species one-hot, zero c blocks of the other central species, zero padding
-        for (int k = sub; k < nt; k += K) brow[k] = T(k == c.zi ? 1 : 0);
+        for (int k = sub; k < nt; k += K) brow[k * ldn] = k == c.zi ? 1.0 : 0.0;
         if (full_rows) {
             const int nblk = NR * nt * nt * NPOLY;
             for (int k = sub; k < nblk; k += K) {
                 const int zz = (k / (nt * NPOLY)) % nt;
                 if (zz == c.zi) continue;
                 const int col = s_col[k];
-                if (col >= 0) brow[col] = T(0);
+                if (col >= 0) brow[col * ldn] = 0.0;
             }
         }
-        for (int k = a.m + sub; k < a.ldb; k += K) brow[k] = T(0);
+        for (int k = a.m + sub; k < a.ldb; k += K) brow[k * ldn] = 0.0;
     }
 }
 
 // Kernels 3 and 4 in one launch: blocks [0, nblk) take kernel 3, blocks
 // [nblk, 2 nblk) kernel 4 (when rows are wanted); both only read dE/dM.
-template <typename T, int L, int K>
+// TF: arithmetic of the pair gradients; TD: type of dE/dM, and of the rows
+// (rows exist only when TD is FP64: the FP64 form, or the mixed form whose
+// contraction ran in FP64 because the grade needs FP64 rows).
+template <typename TF, typename TD, int L, int K>
 __global__ __launch_bounds__(256) void efs_forces_rows(const EfsArgs a, int64_t nblk) {
-    __shared__ T c_s[Level<L>::NRAD * MAX_TYPES * MAX_TYPES * NPOLY];
-    __shared__ T s_dm[Level<L>::NC][256 / K];
-    __shared__ int32_t s_col[Level<L>::NRAD * MAX_TYPES * MAX_TYPES * NPOLY];
+    using LV = Level<L>;
+    constexpr int NCF = LV::NRAD * MAX_TYPES * MAX_TYPES * NPOLY;
+    constexpr size_t FBYTES = sizeof(TF) * (NCF + LV::NC * (256 / K));
+    constexpr size_t RBYTES = sizeof(double) * LV::NC * (256 / K) + sizeof(int32_t) * NCF;
+    constexpr bool ROWS = sizeof(TD) == sizeof(double);
+    // one LDS area: a block takes either the gradient or the row part
+    __shared__ __attribute__((aligned(16))) char smem[FBYTES > RBYTES ? FBYTES : RBYTES];
     if ((int64_t)blockIdx.x < nblk) {
+        TF *c_s = reinterpret_cast<TF *>(smem);
+        auto &s_dm = *reinterpret_cast<TF (*)[LV::NC][256 / K]>(c_s + NCF);
         if (a.gbuf)
-            efs_forces_body<T, L, K, true>(a, blockIdx.x, c_s, s_dm);
+            efs_forces_body<TF, L, K, true, TD>(a, blockIdx.x, c_s, s_dm);
         else
-            efs_forces_body<T, L, K, false>(a, blockIdx.x, c_s, s_dm);
+            efs_forces_body<TF, L, K, false, TD>(a, blockIdx.x, c_s, s_dm);
         if (a.part) {   // uniform: the block's atoms are whole sum chunks (256 / K = 32, 64 or 128)
             constexpr int PER = 256 / K / SUM_CHUNK;
             static_assert(PER * SUM_CHUNK * K == 256, "chunks per block");
@@ -675,15 +724,21 @@ __global__ __launch_bounds__(256) void efs_forces_rows(const EfsArgs a, int64_t 
                 if (chunk * SUM_CHUNK < a.n_atoms) chunk_partials(chunk, a.n_atoms, a.part_e, a.virial, a.part);
             }
         }
-    } else {
-        efs_rows_body<T, L, K>(a, (int64_t)blockIdx.x - nblk, s_dm, s_col);
+    } else if constexpr (ROWS) {
+        auto &s_dm = *reinterpret_cast<double (*)[LV::NC][256 / K]>(smem);
+        int32_t *s_col = reinterpret_cast<int32_t *>(smem + sizeof(double) * LV::NC * (256 / K));
+        efs_rows_body<double, L, K>(a, (int64_t)blockIdx.x - nblk, s_dm, s_col);
     }
 }
 
-template <int L, typename T> int launch_efs_level_t(const EfsArgs &a);
+template <int L, typename T> int launch_mc_level_t(const EfsArgs &a);
+template <int L, typename TF, typename TD> int launch_fr_level_t(const EfsArgs &a);
 
 // instantiates the launchers of one level and one arithmetic type (each
-// (level, type) pair is a translation unit of its own, generated at build time)
+// (level, type) pair is a translation unit of its own, generated at build
+// time): the moments / contraction in TT (rows only when TT is FP64), the
+// pair gradients in TT with dE/dM in TT, and for TT = float also with dE/dM
+// in FP64 (the mixed form with FP64 rows)
 #define MTP_EFS_LEVEL_T(LEVEL, TT)                                                                       \
     /* moments and contraction, K lanes per neighborhood (K = 4, 8: one launch; K = 2: two) */         \
     template <typename T, int K, bool WB> static void launch_mc##LEVEL(const EfsArgs &a) {               \
@@ -707,28 +762,47 @@ template <int L, typename T> int launch_efs_level_t(const EfsArgs &a);
         }                                                                                                \
     }                                                                                                    \
     /* pair gradients and virial (+ the rest of the rows), K lanes per neighborhood */                   \
-    template <typename T, int K, bool WB> static void launch_fr##LEVEL(const EfsArgs &a) {               \
+    template <typename TF, typename TD, int K> static void launch_fr##LEVEL(const EfsArgs &a) {          \
         const unsigned grid = (unsigned)((a.n_atoms + 256 / K - 1) / (256 / K));                         \
+        const bool rows = sizeof(TD) == sizeof(double) && a.brow != nullptr;                             \
         ProfScope ps("efs_forces", a.stream);                                                            \
-        hipLaunchKernelGGL((efs_forces_rows<T, LEVEL, K>), dim3(WB ? 2 * grid : grid), dim3(256), 0,      \
-                           a.stream, a, (int64_t)grid);                                                  \
+        hipLaunchKernelGGL((efs_forces_rows<TF, TD, LEVEL, K>), dim3(rows ? 2 * grid : grid), dim3(256),  \
+                           0, a.stream, a, (int64_t)grid);                                               \
     }                                                                                                    \
-    template <typename T, bool WB> static void launch_efs_t##LEVEL(const EfsArgs &a) {                   \
-        if (a.n_atoms == 0) return;                                                                      \
-        switch (a.lanes_mc) {                                                                            \
-            case 2: launch_mc##LEVEL<T, 2, WB>(a); break;                                                \
-            case 4: launch_mc##LEVEL<T, 4, WB>(a); break;                                                \
-            default: launch_mc##LEVEL<T, 8, WB>(a); break;                                               \
+    template <> int launch_mc_level_t<LEVEL, TT>(const EfsArgs &a) {                                     \
+        if (a.n_atoms == 0) return 0;                                                                    \
+        constexpr bool F64 = sizeof(TT) == sizeof(double);                                               \
+        if (F64 && a.brow != nullptr) {                                                                  \
+            switch (a.lanes_mc) {                                                                        \
+                case 2: launch_mc##LEVEL<TT, 2, F64>(a); break;                                          \
+                case 4: launch_mc##LEVEL<TT, 4, F64>(a); break;                                          \
+                default: launch_mc##LEVEL<TT, 8, F64>(a); break;                                         \
+            }                                                                                            \
+        } else {                                                                                         \
+            switch (a.lanes_mc) {                                                                        \
+                case 2: launch_mc##LEVEL<TT, 2, false>(a); break;                                        \
+                case 4: launch_mc##LEVEL<TT, 4, false>(a); break;                                        \
+                default: launch_mc##LEVEL<TT, 8, false>(a); break;                                       \
+            }                                                                                            \
         }                                                                                                \
-        switch (a.lanes) {                                                                               \
-            case 2: launch_fr##LEVEL<T, 2, WB>(a); break;                                                \
-            case 4: launch_fr##LEVEL<T, 4, WB>(a); break;                                                \
-            default: launch_fr##LEVEL<T, 8, WB>(a); break;                                               \
-        }                                                                                                \
-    }                                                                                                    \
-    template <> int launch_efs_level_t<LEVEL, TT>(const EfsArgs &a) {                                    \
-        if (a.brow != nullptr) launch_efs_t##LEVEL<TT, true>(a); else launch_efs_t##LEVEL<TT, false>(a); \
         return (int)hipGetLastError();                                                                   \
+    }                                                                                                    \
+    template <typename TD> static int launch_fr_td##LEVEL(const EfsArgs &a) {                            \
+        if (a.n_atoms == 0) return 0;                                                                    \
+        switch (a.lanes) {                                                                               \
+            case 2: launch_fr##LEVEL<TT, TD, 2>(a); break;                                               \
+            case 4: launch_fr##LEVEL<TT, TD, 4>(a); break;                                               \
+            default: launch_fr##LEVEL<TT, TD, 8>(a); break;                                              \
+        }                                                                                                \
+        return (int)hipGetLastError();                                                                   \
+    }                                                                                                    \
+    template <> int launch_fr_level_t<LEVEL, TT, TT>(const EfsArgs &a) { return launch_fr_td##LEVEL<TT>(a); } \
+    MTP_EFS_HYBRID_##TT(LEVEL)
+
+#define MTP_EFS_HYBRID_double(LEVEL)
+#define MTP_EFS_HYBRID_float(LEVEL)                                                                      \
+    template <> int launch_fr_level_t<LEVEL, float, double>(const EfsArgs &a) {                          \
+        return launch_fr_td##LEVEL<double>(a);                                                           \
     }
 
 }  // namespace mtp

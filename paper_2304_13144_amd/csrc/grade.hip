@@ -2,14 +2,29 @@
 //
 //   gamma_i = max_p |(b_i A^-1)_p|, argmax p (lowest index on ties)
 //
-// FP64 form: v_mfma_f64_16x16x4 tiles.  Mixed form: the FP32 rows b and the
-// FP64 A^-1 are split into sums of BF16 terms (x = x_0 + x_1 + x_2, each term
-// the BF16 rounding of what is left), and C = sum_{s+t < NS} b_s A_t on
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.
+// The rows b (FP64 in both forms) are column-major: entry (i, k) at
+// brow[k * ldn + i].
 //
-// A block of 512 threads owns 64 rows of C; each wavefront 16 rows and half
-// of each pass of 224 columns.  The block keeps a running max / argmax per
-// row, so C is never written.  A^-1 (<= m^2 x 8 B) stays L2-resident.
+// FP64 form: v_mfma_f64_16x16x4 tiles.  A block of 512 threads owns 64 rows
+// of C; each wavefront 16 rows and half of each pass of 224 columns.  The
+// block keeps a running max / argmax per row, so C is never written.  A^-1
+// (<= m^2 x 8 B) stays L2-resident.
+//
+// Mixed form: an int8 slice product with exact int32 accumulation (the
+// scheme of Ozaki et al. for accurate matrix products from low-precision
+// units).  Columns are equilibrated by powers of two, D_k = 2^-round(log2
+// max_i |A_ik|), so that b D and D^-1 A^-1 have entries of like size; each
+// row of b D and each column of D^-1 A^-1 is scaled by a power of two into
+// (-1, 1) and cut into NSL signed 7-bit digits (round to nearest: the first
+// digit of x 2^6, then of the remainder times 2^7), so x = 2^e sum_t d_t
+// 2^-(6 + 7t) up to 2^-(6 + 7 NSL) of the row (column) maximum.  Products of
+// digits of levels s + t <= NSL are summed on v_mfma_i32_16x16x64_i8 with no
+// rounding at all (|sum| < 2^31), and C = 2^(e_i + f_c) sum_q acc_q
+// 2^-(12 + 7q) in FP64.  FP32 rows or FP32 accumulation cannot hold gamma
+// to 1e-5 on the level-16 alloy's active set (column-equilibrated
+// condition number ~2e5, cancellation in b A^-1 of ~4e3); this product
+// keeps ~34 bits of each operand and rounds nothing until the final FP64
+// sum.
 //
 // Also here: A^-1 by Gauss-Jordan elimination (FP64, partial pivoting) and
 // the MaxVol swap loop with Sherman-Morrison updates (FP64 only).
@@ -21,9 +36,6 @@ namespace mtp {
 namespace {
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned u32x4 __attribute__((ext_vector_type(4)));   // a 16-byte piece, kept in registers
 
 __device__ inline void better(double v, int c, double &bv, int &bc) {
     if (v > bv || (v == bv && c < bc)) {
@@ -33,8 +45,8 @@ __device__ inline void better(double v, int c, double &bv, int &bc) {
 }
 
 // Result layouts of the two MFMAs (16x16 tile, lane l, register r):
-//   f64 16x16x4:       row (l/16) + 4 r, column l % 16
-//   f32 16x16x32 bf16: row 4 (l/16) + r, column l % 16
+//   f64 16x16x4:      row (l/16) + 4 r, column l % 16
+//   i32 16x16x64 i8:  row 4 (l/16) + r, column l % 16
 
 // FP64: a block of eight wavefronts owns 64 rows; wave w takes rows
 // 16 (w % 4) .. + 16 and one half (w / 4) of each pass of CT = 32 HALF
@@ -54,7 +66,7 @@ __device__ inline void better(double v, int c, double &bv, int &bc) {
 // m on the host (the smallest padding of m to passes of 32 HALF columns).
 constexpr int GF_ROWS = 64, GF_KC = 16, GF_NBUF = 3;
 template <int HALF>
-__global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow, int ldb, int64_t n,
+__global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow, int64_t ldn, int64_t n,
                                                  const double *__restrict__ Ainv, int m, double *gamma,
                                                  int32_t *argmax, double thr, int32_t *sel_blk) {
     constexpr int CT = 32 * HALF;
@@ -86,10 +98,10 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
         auto fetch = [&](Regs &R, int ch) {
             const int k0 = ch * GF_KC;
 #pragma unroll
-            for (int q = 0; q < RA; ++q) {
+            for (int q = 0; q < RA; ++q) {   // 64 consecutive rows of one column per wavefront
                 const int e = tid + 512 * q;
-                const int r = e / GF_KC, k = k0 + e % GF_KC;   // k < ldb: the rows are padded with zeros
-                R.a[q] = brow[min(row0 + r, n - 1) * ldb + k];
+                const int r = e % GF_ROWS, k = k0 + e / GF_ROWS;   // k < ldb: the rows are padded with zeros
+                R.a[q] = brow[(int64_t)k * ldn + min(row0 + r, n - 1)];
             }
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
@@ -102,7 +114,7 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
 #pragma unroll
             for (int q = 0; q < RA; ++q) {
                 const int e = tid + 512 * q;
-                sA[buf][e / GF_KC][e % GF_KC] = R.a[q];
+                sA[buf][e % GF_ROWS][e / GF_ROWS] = R.a[q];
             }
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
@@ -176,117 +188,129 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
     }
 }
 
-// split of x into NS BF16 terms (round to nearest even at every step)
-template <int NS> __device__ inline void split_f32(float x, __bf16 (&t)[NS]) {
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        t[s] = (__bf16)x;
-        x -= (float)t[s];
-    }
-}
+// ---- mixed form: int8 slice product ----------------------------------------
+// Block of 256 threads = four independent wavefronts of 16 rows (64 rows,
+// one preselection count per block).  A wavefront holds its rows' digits in
+// registers in the MFMA operand layout for the whole product (lane l: row
+// l % 16, k = 64 s + 16 (l / 16) .. + 16 of k step s; KS steps, m <= 64 KS),
+// then sweeps the columns 16 at a time, reading the digits of D^-1 A^-1 (one
+// 16-byte load per slice and k step, L2-resident, shared through L1 by the
+// block's wavefronts) one column tile ahead.  No LDS and no barrier in the
+// main loop.  Result layout of the 16x16 i32 tile: row 4 (l / 16) + r,
+// column l % 16.
+constexpr int GI_SL = 5;                  // digits per operand
+constexpr int GI_LEV = GI_SL + 1;         // levels s + t = 0 .. GI_SL summed
+constexpr int GI_KS_MAX = 5;              // k steps of 64 held in registers: m <= 320
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 
-// Ainv split layout: S[term][col][kp] (kp = k padded to KP, col padded to CP),
-// so that 8 consecutive k of one column are one 16-byte load.
-//
-// Block of eight wavefronts, 64 rows; wave w takes rows 16 (w % 4) .. + 16
-// and half w / 4 of each pass of 32 HALF columns.  k runs in chunks of 32
-// (one MFMA k step) through two LDS buffers: the rows' FP32 chunk is split
-// into its BF16 terms as it is stored, the split A^-1 chunk is copied as is.
-// Branch-free inner loop as in grade_f64 (clamped loads; the split A^-1 is
-// zero past m in k, columns past m are never compared).
-constexpr int GB_KC = 32, GB_KPAD = GB_KC + 8;   // +8 bf16: 80-byte rows spread the LDS banks
-template <int NS, int HALF>
-__global__ __launch_bounds__(512) void grade_bf16(const float *__restrict__ brow, int ldb, int64_t n,
-                                                  const __bf16 *__restrict__ S, int m, int KP, int CP, double *gamma,
-                                                  int32_t *argmax, double thr, int32_t *sel_blk) {
-    constexpr int CT = 32 * HALF;
-    __shared__ __attribute__((aligned(16))) __bf16 sA[2][NS][GF_ROWS][GB_KPAD];
-    __shared__ __attribute__((aligned(16))) __bf16 sB[2][NS][CT][GB_KPAD];
-    __shared__ double s_best[2][GF_ROWS];
-    __shared__ int s_idx[2][GF_ROWS];
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int rg = wave & 3, half = wave >> 2;
+template <int KS>
+__global__ __launch_bounds__(256) void grade_i8(const double *__restrict__ brow, int ldb, int64_t ldn, int64_t n,
+                                                const int8_t *__restrict__ S, const int32_t *__restrict__ fexp,
+                                                const double *__restrict__ dsc, int m, int CP, double *gamma,
+                                                int32_t *argmax, double thr, int32_t *sel_blk) {
+    constexpr int KP = 64 * KS;
+    __shared__ int s_cnt[4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
-    const int64_t row0 = (int64_t)blockIdx.x * GF_ROWS;
-    const int64_t term = (int64_t)CP * KP;
-    const int nchunk = KP / GB_KC;
-    // global -> register staging: A, one float4 per thread (row tid / 8, k 4 (tid % 8));
-    // B, 16-byte pieces e = tid + 512 q of (term, column, k group of 8)
-    constexpr int NBP = NS * CT * (GB_KC / 8);
-    constexpr int RB = (NBP + 511) / 512;
+    const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int64_t arow = min(row0 + lr, n - 1);   // rows past n: clamped, never written
+    const double *bp = brow + arow;
+    // the row's largest |b_k D_k| (D_k = 0 past m; k clamped into the rows)
+    double mx = 0.0;
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int k = 64 * s + 16 * lk + j;
+            mx = fmax(mx, fabs(bp[(int64_t)min(k, ldb - 1) * ldn] * dsc[k]));
+            if (j == 15) __builtin_amdgcn_sched_barrier(0);
+        }
+    mx = fmax(mx, __shfl_xor(mx, 16, 64));
+    mx = fmax(mx, __shfl_xor(mx, 32, 64));
+    // read the row again below (L1 / L2) rather than keep 4 KS x 16 values of
+    // b and D in registers from the pass above
+    __asm__ volatile("" ::: "memory");
+    int erow;
+    (void)frexp(mx, &erow);   // mx = f 2^erow, f in [0.5, 1); 0 for a zero row
+    const double sc = ldexp(1.0, 6 - erow);
+    // digits, four per register
+    i32x4 A[GI_SL][KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        unsigned w[GI_SL][4];
+#pragma unroll
+        for (int t = 0; t < GI_SL; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) w[t][q] = 0u;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int k = 64 * s + 16 * lk + j;
+            double r = bp[(int64_t)min(k, ldb - 1) * ldn] * dsc[k] * sc;   // |r| < 64, exact
+#pragma unroll
+            for (int t = 0; t < GI_SL; ++t) {
+                const double d = rint(r);
+                r = (r - d) * 128.0;
+                w[t][j >> 2] |= ((unsigned)(int)d & 0xffu) << (8 * (j & 3));
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < GI_SL; ++t) A[t][s] = i32x4{(int)w[t][0], (int)w[t][1], (int)w[t][2], (int)w[t][3]};
+        // one k step's loads in flight at a time: hoisting all of them would
+        // hold 2 KS x 16 registers beside the digits
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // 2^erow of the four result rows of this lane (row 4 lk + r is held by lane 4 lk + r)
+    double rsc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rsc[r] = ldexp(1.0, __shfl(erow, 4 * lk + r, 64) - 12);
     double best[4] = {-1.0, -1.0, -1.0, -1.0};
     int bidx[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
-    for (int ct0 = 0; ct0 < m; ct0 += CT) {
-        const int cb0 = half * HALF;
-        floatx4 acc[HALF];
+    const int64_t term = (int64_t)CP * KP;
+    const int ntile = (m + 15) / 16;
+    // the digits of D^-1 A^-1 for one k step of one column tile (20 registers),
+    // double-buffered across the steps; tiles go in pairs so that the buffer
+    // parity of every step is known at compile time (a tile past the last
+    // one, when their count is odd, reads the last tile again and compares
+    // nothing: its columns are >= m)
+    auto fetch = [&](i32x4 (&B)[GI_SL], int tile, int s) {
+        tile = tile < ntile ? tile : ntile - 1;
+        const int8_t *src = S + (int64_t)(16 * tile + lr) * KP + 16 * lk + 64 * s;
 #pragma unroll
-        for (int c = 0; c < HALF; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
-        float4 ra;
-        u32x4 rb[RB];
-        auto fetch = [&](int ch) {
-            const int k0 = ch * GB_KC;
-            const int r = tid >> 3, k = k0 + 4 * (tid & 7);
-            ra = *reinterpret_cast<const float4 *>(brow + min(row0 + r, n - 1) * ldb + k);
+        for (int t = 0; t < GI_SL; ++t) B[t] = *reinterpret_cast<const i32x4 *>(src + t * term);
+    };
+    i32x4 Bb[2][GI_SL];
+    i32x4 acc[GI_LEV];
+    fetch(Bb[0], 0, 0);
+    for (int t0 = 0; t0 < ntile; t0 += 2) {
 #pragma unroll
-            for (int q = 0; q < RB; ++q) {
-                const int e = tid + 512 * q;
-                const int t = e / (CT * 4), rem = e % (CT * 4), c = rem >> 2, kg = rem & 3;
-                const int col = min(ct0 + c, CP - 1);
-                if (q < RB - 1 || e < NBP)
-                    rb[q] = *reinterpret_cast<const u32x4 *>(S + t * term + (int64_t)col * KP + k0 + 8 * kg);
-            }
-        };
-        auto store = [&](int buf) {
-            const int r = tid >> 3, k = 4 * (tid & 7);
-            const float v[4] = {ra.x, ra.y, ra.z, ra.w};
+        for (int u = 0; u < 2 * KS; ++u) {
+            const int tile = t0 + u / KS, s = u % KS;
+            if (s == 0)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                __bf16 t[NS];
-                split_f32<NS>(v[e], t);
+                for (int q = 0; q < GI_LEV; ++q) acc[q] = i32x4{0, 0, 0, 0};
+            if (u + 1 < 2 * KS) fetch(Bb[(u + 1) & 1], t0 + (u + 1) / KS, (u + 1) % KS);
+            else fetch(Bb[(u + 1) & 1], t0 + 2, 0);
 #pragma unroll
-                for (int s2 = 0; s2 < NS; ++s2) sA[buf][s2][r][k + e] = t[s2];
-            }
+            for (int a = 0; a < GI_SL; ++a)
 #pragma unroll
-            for (int q = 0; q < RB; ++q) {
-                const int e = tid + 512 * q;
-                if (q < RB - 1 || e < NBP) {
-                    const int t = e / (CT * 4), rem = e % (CT * 4), c = rem >> 2, kg = rem & 3;
-                    *reinterpret_cast<u32x4 *>(&sB[buf][t][c][8 * kg]) = rb[q];
+                for (int b = 0; a + b <= GI_SL && b < GI_SL; ++b)
+                    acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[a][s], Bb[u & 1][b], acc[a + b], 0, 0, 0);
+            if (s == KS - 1) {
+                const int col = 16 * tile + lr;
+                const double cs = ldexp(1.0, fexp[col < CP ? col : CP - 1]);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int q = GI_LEV - 1; q >= 0; --q) v = fma(v, 0x1p-7, (double)acc[q][r]);
+                    if (col < m) better(fabs(v * rsc[r] * cs), col, best[r], bidx[r]);
                 }
             }
-        };
-        __syncthreads();
-        fetch(0);
-        store(0);
-        __syncthreads();
-        for (int ch = 0; ch < nchunk; ++ch) {
-            const int buf = ch & 1;
-            if (ch + 1 < nchunk) fetch(ch + 1);
-            bf16x8 A[NS];
-#pragma unroll
-            for (int s2 = 0; s2 < NS; ++s2) A[s2] = *reinterpret_cast<const bf16x8 *>(&sA[buf][s2][rg * 16 + lr][8 * lk]);
-#pragma unroll
-            for (int c = 0; c < HALF; ++c) {
-#pragma unroll
-                for (int t = 0; t < NS; ++t) {
-                    const bf16x8 B = *reinterpret_cast<const bf16x8 *>(&sB[buf][t][(cb0 + c) * 16 + lr][8 * lk]);
-#pragma unroll
-                    for (int s2 = 0; s2 + t < NS; ++s2)
-                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s2], B, acc[c], 0, 0, 0);
-                }
-            }
-            if (ch + 1 < nchunk) store(buf ^ 1);
-            __syncthreads();
-        }
-#pragma unroll
-        for (int c = 0; c < HALF; ++c) {
-            const int col = ct0 + (cb0 + c) * 16 + lr;
-            if (col < m)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) better((double)fabsf(acc[c][r]), col, best[r], bidx[r]);
+            // loads of one step ahead only (registers)
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
+    // the 16 lanes of a row group (columns), then one lane per row
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1)
 #pragma unroll
@@ -295,38 +319,67 @@ __global__ __launch_bounds__(512) void grade_bf16(const float *__restrict__ brow
             const int oc = __shfl_xor(bidx[r], o, 64);
             better(ov, oc, best[r], bidx[r]);
         }
-    if (lr == 0)   // bf16 layout: row 4 (lane / 16) + r
+    // lane l (< 16 used): row 4 (l / 4) + l % 4 of the wave, from lane 16 (l / 4)
+    const int src = 16 * (lr >> 2), rr = lr & 3;
+    double bv = 0.0;
+    int bc = 0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            s_best[half][rg * 16 + 4 * lk + r] = best[r];
-            s_idx[half][rg * 16 + 4 * lk + r] = bidx[r];
+    for (int r = 0; r < 4; ++r) {
+        const double v = __shfl(best[r], src, 64);
+        const int c = __shfl(bidx[r], src, 64);
+        if (r == rr) {
+            bv = v;
+            bc = c;
         }
-    __syncthreads();
-    if (tid < GF_ROWS) {   // wavefront 0: one row per lane
-        double bv = s_best[0][tid];
-        int bc = s_idx[0][tid];
-        better(s_best[1][tid], s_idx[1][tid], bv, bc);
-        const bool live = row0 + tid < n;
-        if (live) {
-            gamma[row0 + tid] = bv;
-            if (argmax) argmax[row0 + tid] = bc;
-        }
-        // preselection counts (gamma > thr) of this block, for select_write
-        const unsigned long long sel = __ballot(live && bv > thr);
-        if (sel_blk && tid == 0) sel_blk[blockIdx.x] = __popcll(sel);
     }
+    const int64_t row = row0 + lr;
+    const bool live = lane < 16 && row < n;
+    if (live) {
+        gamma[row] = bv;
+        if (argmax) argmax[row] = bc;
+    }
+    const unsigned long long sel = __ballot(live && bv > thr);
+    if (lane == 0) s_cnt[wave] = __popcll(sel);
+    __syncthreads();
+    if (sel_blk && threadIdx.x == 0) sel_blk[blockIdx.x] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
 }
 
-__global__ void split_ainv(const double *Ainv, int m, int KP, int CP, int NS, __bf16 *S) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)CP * KP) return;
-    const int col = (int)(idx / KP), k = (int)(idx % KP);
-    double x = (col < m && k < m) ? Ainv[(int64_t)k * m + col] : 0.0;
+// D_k = 2^-round(log2 max_i |A_ik|) (0 past m, and for an all-zero column)
+__global__ void i8_colscale(const double *A, int m, int KP, double *dsc) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= KP) return;
+    double mx = 0.0;
+    if (k < m)
+        for (int i = 0; i < m; ++i) mx = fmax(mx, fabs(A[(int64_t)i * m + k]));
+    dsc[k] = mx > 0.0 ? ldexp(1.0, -(int)rint(log2(mx))) : 0.0;
+}
+
+// digits of column c of D^-1 A^-1: one block per column (padded columns: zero)
+__global__ __launch_bounds__(256) void i8_slice_ainv(const double *Ainv, int m, int KP, int CP, const double *dsc,
+                                                     int8_t *S, int32_t *fexp) {
+    __shared__ double sm[256];
+    const int c = blockIdx.x;
+    double mx = 0.0;
+    for (int k = threadIdx.x; k < m; k += 256)
+        if (c < m && dsc[k] > 0.0) mx = fmax(mx, fabs(Ainv[(int64_t)k * m + c] / dsc[k]));
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+        __syncthreads();
+    }
+    int e;
+    (void)frexp(sm[0], &e);
+    if (threadIdx.x == 0) fexp[c] = e;
+    const double sc = ldexp(1.0, 6 - e);
     const int64_t term = (int64_t)CP * KP;
-    for (int s = 0; s < NS; ++s) {
-        const __bf16 t = (__bf16)(float)x;
-        S[s * term + idx] = t;
-        x -= (double)(float)t;
+    for (int k = threadIdx.x; k < KP; k += 256) {
+        double r = (c < m && k < m && dsc[k] > 0.0) ? Ainv[(int64_t)k * m + c] / dsc[k] * sc : 0.0;
+        for (int t = 0; t < GI_SL; ++t) {
+            const double d = rint(r);
+            r = (r - d) * 128.0;
+            S[t * term + (int64_t)c * KP + k] = (int8_t)(int)d;
+        }
     }
 }
 
@@ -540,17 +593,21 @@ __global__ void mv_init(MVState *st) {
 
 }  // namespace
 
-int split_terms() { return 3; }
-
+// digits of D^-1 A^-1 for the mixed product, after any change of A^-1
 void prepare_split(ActiveSet &as, hipStream_t st) {
     const int m = as.m;
-    const int KP = (m + 31) / 32 * 32, CP = (m + 15) / 16 * 16;
-    const int NS = split_terms();
-    as.Ainv32.ensure(sizeof(__bf16) * (size_t)NS * CP * KP);
-    const int64_t tot = (int64_t)CP * KP;
-    hipLaunchKernelGGL(split_ainv, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, as.Ainv.as<double>(), m, KP,
-                       CP, NS, as.Ainv32.as<__bf16>());
+    as.KP8 = (m + 63) / 64 * 64;
+    as.CP8 = (m + 15) / 16 * 16;
+    as.s8.ensure((size_t)GI_SL * as.CP8 * as.KP8);
+    as.fexp.ensure(sizeof(int32_t) * as.CP8);
+    as.dsc.ensure(sizeof(double) * as.KP8);
+    hipLaunchKernelGGL(i8_colscale, dim3((unsigned)((as.KP8 + 255) / 256)), dim3(256), 0, st, as.A.as<double>(), m,
+                       as.KP8, as.dsc.as<double>());
+    hipLaunchKernelGGL(i8_slice_ainv, dim3((unsigned)as.CP8), dim3(256), 0, st, as.Ainv.as<double>(), m, as.KP8,
+                       as.CP8, as.dsc.as<double>(), as.s8.as<int8_t>(), as.fexp.as<int32_t>());
 }
+
+bool slice_product_fits(int m) { return m <= 64 * GI_KS_MAX; }
 
 // column blocks per wave (HALF): the pass width 32 HALF that pads m the
 // least, the widest on ties
@@ -567,32 +624,47 @@ static int grade_half(int m) {
 }
 
 template <int HALF>
-static void launch_grade_h(const ActiveSet &as, int precision, const void *brow, int ldb, int64_t n, double *gamma,
-                           int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
+static void launch_grade_f64(const ActiveSet &as, const double *brow, int64_t ldn, int64_t n, double *gamma,
+                             int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
     const dim3 grid((unsigned)((n + GF_ROWS - 1) / GF_ROWS));
-    if (precision == MTP_FP64) {
-        hipLaunchKernelGGL(grade_f64<HALF>, grid, dim3(512), 0, st, static_cast<const double *>(brow), ldb, n,
-                           as.Ainv.as<double>(), as.m, gamma, argmax, thr, sel_blk);
-    } else {
-        const int KP = (as.m + 31) / 32 * 32, CP = (as.m + 15) / 16 * 16;
-        hipLaunchKernelGGL((grade_bf16<3, HALF>), grid, dim3(512), 0, st, static_cast<const float *>(brow), ldb, n,
-                           as.Ainv32.as<__bf16>(), as.m, KP, CP, gamma, argmax, thr, sel_blk);
-    }
+    hipLaunchKernelGGL(grade_f64<HALF>, grid, dim3(512), 0, st, brow, ldn, n, as.Ainv.as<double>(), as.m, gamma,
+                       argmax, thr, sel_blk);
 }
 
-void launch_grade(const ActiveSet &as, int precision, const void *brow, int ldb, int64_t n, double *gamma,
-                  int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
+template <int KS>
+static void launch_grade_i8(const ActiveSet &as, const double *brow, int ldb, int64_t ldn, int64_t n, double *gamma,
+                            int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
+    const dim3 grid((unsigned)((n + 63) / 64));
+    hipLaunchKernelGGL(grade_i8<KS>, grid, dim3(256), 0, st, brow, ldb, ldn, n, as.s8.as<int8_t>(),
+                       as.fexp.as<int32_t>(), as.dsc.as<double>(), as.m, as.CP8, gamma, argmax, thr, sel_blk);
+}
+
+void launch_grade(const ActiveSet &as, int precision, const double *brow, int ldb, int64_t ldn, int64_t n,
+                  double *gamma, int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
     static_assert(GRADE_ROWS == GF_ROWS, "preselection blocks are grade blocks");
     if (n == 0) return;
-    MTP_CHECK(ldb >= (as.m + 31) / 32 * 32, MTP_E_INVAL, "grade: row stride below the padded row length");
+    MTP_CHECK(ldb >= (as.m + 31) / 32 * 32, MTP_E_INVAL, "grade: row length below the padded row length");
+    MTP_CHECK(ldn >= n, MTP_E_INVAL, "grade: column stride below the row count");
+    if (precision == MTP_MIXED && slice_product_fits(as.m)) {
+        MTP_CHECK(as.KP8 == (as.m + 63) / 64 * 64 && as.s8.ptr, MTP_E_INVAL, "grade: digits of A^-1 not prepared");
+        switch (as.KP8 / 64) {
+            case 1: launch_grade_i8<1>(as, brow, ldb, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 2: launch_grade_i8<2>(as, brow, ldb, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 3: launch_grade_i8<3>(as, brow, ldb, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 4: launch_grade_i8<4>(as, brow, ldb, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            default: launch_grade_i8<5>(as, brow, ldb, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        }
+        return;
+    }
+    // FP64 form, and the mixed form past m = 320 (the digits would not fit in registers)
     switch (grade_half(as.m)) {
-        case 1: launch_grade_h<1>(as, precision, brow, ldb, n, gamma, argmax, st, thr, sel_blk); break;
-        case 2: launch_grade_h<2>(as, precision, brow, ldb, n, gamma, argmax, st, thr, sel_blk); break;
-        case 3: launch_grade_h<3>(as, precision, brow, ldb, n, gamma, argmax, st, thr, sel_blk); break;
-        case 4: launch_grade_h<4>(as, precision, brow, ldb, n, gamma, argmax, st, thr, sel_blk); break;
-        case 5: launch_grade_h<5>(as, precision, brow, ldb, n, gamma, argmax, st, thr, sel_blk); break;
-        case 6: launch_grade_h<6>(as, precision, brow, ldb, n, gamma, argmax, st, thr, sel_blk); break;
-        default: launch_grade_h<7>(as, precision, brow, ldb, n, gamma, argmax, st, thr, sel_blk); break;
+        case 1: launch_grade_f64<1>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        case 2: launch_grade_f64<2>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        case 3: launch_grade_f64<3>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        case 4: launch_grade_f64<4>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        case 5: launch_grade_f64<5>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        case 6: launch_grade_f64<6>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        default: launch_grade_f64<7>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
     }
 }
 

@@ -52,7 +52,10 @@ struct ActiveSet {
     bool valid = false;
     DevBuf A;        // m*m FP64 rows
     DevBuf Ainv;     // m*m FP64
-    DevBuf Ainv32;   // split copies for the mixed grade product (see grade.hip)
+    // mixed-form product (see grade.hip): int8 digits of D^-1 A^-1
+    // [GI_SL][CP8][KP8], their column exponents [CP8], the column scales D [KP8]
+    DevBuf s8, fexp, dsc;
+    int KP8 = 0, CP8 = 0;
 };
 
 }  // namespace mtp
@@ -114,13 +117,16 @@ struct EfsArgs {
     const int32_t *tcnt;
     const int32_t *type;
     double r_min, r_cut;
-    const void *xi0, *xi, *c; // precision-typed parameter arrays
+    const double *th64;       // theta = [xi_0 | xi_alpha | c] in FP64
+    const float *th32;        // and rounded to FP32
+    int n_lin;
     // outputs (nullable)
     double *site_e;           // [n_atoms]
     void *gbuf;               // [N*maxn*3] T  (pair gradients dV_i/dr_ij)
     double *virial;           // [n_atoms*9]
-    void *brow;               // [n_atoms*ldb] T
-    int ldb;
+    double *brow;             // rows b_i, FP64, column-major: entry (i, k) at brow[k * ldn + i]
+    int64_t ldn;              // column stride of brow (>= n_atoms)
+    int ldb;                  // columns written: m, then zeros up to ldb
     int grade_mode;           // rows layout: FULL (with colmap) or LINEAR
     const int32_t *colmap;    // full column -> kept column or -1
     int m;                    // row length written (kept columns)
@@ -172,14 +178,16 @@ void launch_cfg_partials(int64_t n, const double *site_e, const double *virial, 
 void launch_cfg_final(const mtp_system *s, const double *site_e, const double *virial, const double *part,
                       double *energy, double *stress, hipStream_t st);
 
-// grade: C = brow * Ainv (ld ldb), gamma/argmax per row
-// thr / sel_blk (nullable): the grade also writes, per block of GRADE_ROWS
-// rows, how many have gamma > thr (input of launch_select_write)
+// grade: C = b Ainv, gamma/argmax per row; b FP64 column-major (entry (i, k)
+// at brow[k * ldn + i], ldb >= m columns, zero past m).  FP64 MFMA for the
+// FP64 form, the exact int8 slice product for the mixed form (m <= 320;
+// beyond, FP64).  thr / sel_blk (nullable): the grade also writes, per block
+// of GRADE_ROWS rows, how many have gamma > thr (input of launch_select_write)
 constexpr int GRADE_ROWS = 64;
-void launch_grade(const ActiveSet &as, int precision, const void *brow, int ldb, int64_t n, double *gamma,
-                  int32_t *argmax, hipStream_t st, double thr = 0.0, int32_t *sel_blk = nullptr);
+void launch_grade(const ActiveSet &as, int precision, const double *brow, int ldb, int64_t ldn, int64_t n,
+                  double *gamma, int32_t *argmax, hipStream_t st, double thr = 0.0, int32_t *sel_blk = nullptr);
 void prepare_split(ActiveSet &as, hipStream_t st);
-int split_terms();
+bool slice_product_fits(int m);
 void launch_invert(ActiveSet &as, const double *A, hipStream_t st, DevBuf &work, int *singular_host);
 void launch_select(const double *gamma, int64_t n, double thr, int32_t *idx, int32_t cap, int32_t *count,
                    hipStream_t st, DevBuf &work);
@@ -208,7 +216,8 @@ void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *bl
                          const GatherArgs *gather = nullptr);
 void run_maxvol(ActiveSet &as, double *cand, int64_t n_cand, double thr, int max_swaps, int32_t *swap_cand,
                 int32_t *swap_col, int32_t *n_swaps, hipStream_t st, DevBuf &work);
-void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision, void *dst, hipStream_t st);
+// column-major rows (entry (i, k) at src[k * ldn + i]) -> row-major dst [n][m]
+void launch_copy_rows(const double *src, int64_t ldn, int m, int64_t n, double *dst, hipStream_t st);
 // extrapolation-controlled runs: largest value and its lowest index (one
 // block; either output may be NULL); velocity-Verlet half steps (half 0:
 // kick and drift, 1: kick); the spherical fragment around the largest
@@ -228,11 +237,12 @@ int64_t cut_fragment(const double *pos, const int32_t *type, int64_t n, const do
 // (returns the number of partials)
 int64_t launch_fit_residual(int64_t n, const double *y, const double *t, double w, double *g, double *part,
                             hipStream_t st);
-// configuration-mode rows: out [n_cfg][ldb] FP64 = per-configuration sums of
-// the rows [n][ldb] (precision-typed); part: cfg_row_partials_bytes(n, ldb)
+// configuration-mode rows: out (column-major, entry (c, k) at out[k * n_cfg + c])
+// = per-configuration sums of the column-major FP64 rows (entry (i, k) at
+// rows[k * n + i], ldb columns); part: cfg_row_partials_bytes(n, ldb)
 size_t cfg_row_partials_bytes(int64_t n, int ldb);
-void launch_cfg_rows(const void *rows, int precision, int ldb, int64_t n, const mtp_system *s, double *part,
-                     double *out, hipStream_t st);
+void launch_cfg_rows(const double *rows, int ldb, int64_t n, const mtp_system *s, double *part, double *out,
+                     hipStream_t st);
 void launch_zero(void *p, size_t bytes, hipStream_t st);
 
 }  // namespace mtp

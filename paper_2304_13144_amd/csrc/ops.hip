@@ -151,39 +151,40 @@ __global__ __launch_bounds__(256) void cfg_final(const int64_t *cfg_off, const d
 }
 
 // Configuration-mode rows b(cfg) = sum_i b_i over the atoms of each
-// configuration, in FP64 whatever the rows' type, in two steps like the
-// energy sums: partial sums over chunks of ROW_CHUNK atoms (thread t of a
-// block adds column t, t + 256, ... of its chunk's rows in atom order), then
-// one block per configuration adds the partials of its whole chunks and the
-// rows of the chunks it shares with its neighbors.  Fixed order throughout.
+// configuration, in FP64, in two steps like the energy sums: partial sums
+// over chunks of ROW_CHUNK atoms (thread t of a block adds column t, t + 256,
+// ... of its chunk's rows in atom order), then one block per configuration
+// adds the partials of its whole chunks and the rows of the chunks it shares
+// with its neighbors.  Fixed order throughout.  Rows and results are
+// column-major (entry (i, k) at rows[k * n + i]).
 constexpr int ROW_CHUNK = 64;
-template <typename T>
-__global__ __launch_bounds__(256) void row_partials(const T *rows, int ldb, int64_t n, double *part) {
+__global__ __launch_bounds__(256) void row_partials(const double *rows, int ldb, int64_t n, double *part) {
     const int64_t a0 = (int64_t)blockIdx.x * ROW_CHUNK;
     const int64_t a1 = a0 + ROW_CHUNK < n ? a0 + ROW_CHUNK : n;
     for (int k = threadIdx.x; k < ldb; k += 256) {
+        const double *col = rows + (int64_t)k * n;
         double acc = 0.0;
-        for (int64_t i = a0; i < a1; ++i) acc += double(rows[i * ldb + k]);
+        for (int64_t i = a0; i < a1; ++i) acc += col[i];
         part[(int64_t)blockIdx.x * ldb + k] = acc;
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void row_final(const T *rows, int ldb, const double *part, const int64_t *cfg_off,
-                                                 double *out) {
+__global__ __launch_bounds__(256) void row_final(const double *rows, int ldb, int64_t n, const double *part,
+                                                 const int64_t *cfg_off, int n_cfg, double *out) {
     const int c = blockIdx.x;
     const int64_t b = cfg_off[c], e = cfg_off[c + 1];
     const int64_t cb = (b + ROW_CHUNK - 1) / ROW_CHUNK, ce = e / ROW_CHUNK;   // whole chunks [cb, ce)
     for (int k = threadIdx.x; k < ldb; k += 256) {
+        const double *col = rows + (int64_t)k * n;
         double acc = 0.0;
         if (cb < ce) {
-            for (int64_t i = b; i < cb * ROW_CHUNK; ++i) acc += double(rows[i * ldb + k]);
+            for (int64_t i = b; i < cb * ROW_CHUNK; ++i) acc += col[i];
             for (int64_t q = cb; q < ce; ++q) acc += part[q * ldb + k];
-            for (int64_t i = ce * ROW_CHUNK; i < e; ++i) acc += double(rows[i * ldb + k]);
+            for (int64_t i = ce * ROW_CHUNK; i < e; ++i) acc += col[i];
         } else {
-            for (int64_t i = b; i < e; ++i) acc += double(rows[i * ldb + k]);
+            for (int64_t i = b; i < e; ++i) acc += col[i];
         }
-        out[(int64_t)c * ldb + k] = acc;
+        out[(int64_t)k * n_cfg + c] = acc;
     }
 }
 
@@ -352,12 +353,24 @@ __global__ void fire_mix(int64_t n3, double *v, const double *F, double a, doubl
     if (i < n3) v[i] = a * v[i] + b * F[i];
 }
 
-template <typename T>
-__global__ void copy_rows(const T *src, int ldb, int m, int64_t n, T *dst) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * m) return;
-    const int64_t r = i / m, c = i % m;
-    dst[i] = src[r * ldb + c];
+// column-major rows -> row-major [n][m] (through a 32 x 32 LDS tile: both
+// the reads and the writes are consecutive words)
+__global__ __launch_bounds__(256) void copy_rows(const double *src, int64_t ldn, int m, int64_t n, double *dst) {
+    __shared__ double t[32][33];
+    const int64_t r0 = (int64_t)blockIdx.x * 32;
+    const int c0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int q = ty; q < 32; q += 8) {
+        const int c = c0 + q;
+        const int64_t r = r0 + tx;
+        t[q][tx] = (c < m && r < n) ? src[(int64_t)c * ldn + r] : 0.0;
+    }
+    __syncthreads();
+    for (int q = ty; q < 32; q += 8) {
+        const int64_t r = r0 + q;
+        const int c = c0 + tx;
+        if (r < n && c < m) dst[r * m + c] = t[tx][q];
+    }
 }
 
 // Preselection: indices with gamma > thr in ascending order.  Blocks of
@@ -526,37 +539,23 @@ void launch_cfg_final(const mtp_system *s, const double *site_e, const double *v
                        energy, stress);
 }
 
-void launch_copy_rows(const void *src, int ldb, int m, int64_t n, int precision, void *dst, hipStream_t st) {
-    const int64_t tot = n * m;
-    if (!tot) return;
-    const dim3 grid((unsigned)((tot + 255) / 256));
-    if (precision == MTP_FP64)
-        hipLaunchKernelGGL(copy_rows<double>, grid, dim3(256), 0, st, static_cast<const double *>(src), ldb, m, n,
-                           static_cast<double *>(dst));
-    else
-        hipLaunchKernelGGL(copy_rows<float>, grid, dim3(256), 0, st, static_cast<const float *>(src), ldb, m, n,
-                           static_cast<float *>(dst));
+void launch_copy_rows(const double *src, int64_t ldn, int m, int64_t n, double *dst, hipStream_t st) {
+    if (n == 0 || m == 0) return;
+    const dim3 grid((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32));
+    hipLaunchKernelGGL(copy_rows, grid, dim3(256), 0, st, src, ldn, m, n, dst);
 }
 
 size_t cfg_row_partials_bytes(int64_t n, int ldb) {
     return sizeof(double) * (size_t)ldb * (size_t)std::max<int64_t>(1, (n + ROW_CHUNK - 1) / ROW_CHUNK);
 }
 
-void launch_cfg_rows(const void *rows, int precision, int ldb, int64_t n, const mtp_system *s, double *part,
-                     double *out, hipStream_t st) {
+void launch_cfg_rows(const double *rows, int ldb, int64_t n, const mtp_system *s, double *part, double *out,
+                     hipStream_t st) {
     if (s->n_cfg <= 0) return;
     const unsigned nch = (unsigned)((n + ROW_CHUNK - 1) / ROW_CHUNK);
-    if (precision == MTP_FP64) {
-        const double *r = static_cast<const double *>(rows);
-        if (nch) hipLaunchKernelGGL(row_partials<double>, dim3(nch), dim3(256), 0, st, r, ldb, n, part);
-        hipLaunchKernelGGL(row_final<double>, dim3((unsigned)s->n_cfg), dim3(256), 0, st, r, ldb, part, s->cfg_off,
-                           out);
-    } else {
-        const float *r = static_cast<const float *>(rows);
-        if (nch) hipLaunchKernelGGL(row_partials<float>, dim3(nch), dim3(256), 0, st, r, ldb, n, part);
-        hipLaunchKernelGGL(row_final<float>, dim3((unsigned)s->n_cfg), dim3(256), 0, st, r, ldb, part, s->cfg_off,
-                           out);
-    }
+    if (nch) hipLaunchKernelGGL(row_partials, dim3(nch), dim3(256), 0, st, rows, ldb, n, part);
+    hipLaunchKernelGGL(row_final, dim3((unsigned)s->n_cfg), dim3(256), 0, st, rows, ldb, n, part, s->cfg_off,
+                       s->n_cfg, out);
 }
 
 void launch_argmax(const double *g, int64_t n, double *best, int32_t *where, hipStream_t st) {
