@@ -300,8 +300,9 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
         m->gamma_ws.ensure(sizeof(double) * n);
         double *gam = o.gamma ? o.gamma : m->gamma_ws.as<double>();
         int32_t *blk = nullptr;
+        const int count_rows = grade_count_rows(m->act[o.mode], prec);
         if (want_sel) {
-            m->selblk.ensure(sizeof(int32_t) * (size_t)((n + GRADE_ROWS - 1) / GRADE_ROWS + 1));
+            m->selblk.ensure(sizeof(int32_t) * (size_t)((n + count_rows - 1) / count_rows + 1));
             blk = m->selblk.as<int32_t>();
         }
         {
@@ -312,7 +313,7 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
             ProfScope ps("select", st);
             const GatherArgs ga = fuse_gather ? gather_args(nb, m->gbuf.ptr, prec, o.forces) : GatherArgs{};
             launch_select_write(gam, n, o.sel_thr, blk, o.sel_idx, o.sel_cap, o.sel_count, st,
-                                want_sums ? &sums : nullptr, fuse_gather ? &ga : nullptr);
+                                want_sums ? &sums : nullptr, fuse_gather ? &ga : nullptr, count_rows);
         }
     }
     if (o.b_rows) launch_copy_rows(m->brow.as<double>(), n, mm, n, static_cast<double *>(o.b_rows), st);

@@ -189,18 +189,21 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
 }
 
 // ---- mixed form: int8 slice product ----------------------------------------
-// Block of 256 threads = four independent wavefronts of 16 rows (64 rows,
-// one preselection count per block).  A wavefront holds its rows' digits in
-// registers in the MFMA operand layout for the whole product (lane l: row
-// l % 16, k = 64 s + 16 (l / 16) .. + 16 of k step s; KS steps, m <= 64 KS),
-// then sweeps the columns 16 at a time, reading the digits of D^-1 A^-1 (one
-// 16-byte load per slice and k step, L2-resident, shared through L1 by the
-// block's wavefronts) one column tile ahead.  No LDS and no barrier in the
-// main loop.  Result layout of the 16x16 i32 tile: row 4 (l / 16) + r,
-// column l % 16.
+// Block of 256 threads = one group of 16 rows and four wavefronts that split
+// its column tiles (wavefront w: tiles w, w + 4, ...), so that n / 16 blocks
+// keep several wavefronts on every SIMD.  The four wavefronts cut the rows
+// into digits together (wavefront w: k steps w, w + 4, ...; the row maxima
+// and the digits meet in LDS, in the MFMA operand layout: lane l: row l % 16,
+// k = 64 s + 16 (l / 16) .. + 16 of k step s; KS steps, m <= 64 KS); then each
+// sweeps its columns, reading the rows' digits of a k step from LDS and the
+// digits of D^-1 A^-1 (one 16-byte load per slice and k step, L2-resident)
+// one k step ahead.  Result layout of the 16x16 i32
+// tile: row 4 (l / 16) + r, column l % 16.  One preselection count per 16
+// rows.
 constexpr int GI_SL = 5;                  // digits per operand
 constexpr int GI_LEV = GI_SL + 1;         // levels s + t = 0 .. GI_SL summed
-constexpr int GI_KS_MAX = 5;              // k steps of 64 held in registers: m <= 320
+constexpr int GI_KS_MAX = 5;              // k steps of 64 (the rows' digits in LDS): m <= 320
+constexpr int GI_ROWS = 16;               // rows per block (and per preselection count)
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 template <int KS>
@@ -209,34 +212,34 @@ __global__ __launch_bounds__(256) void grade_i8(const double *__restrict__ brow,
                                                 const double *__restrict__ dsc, int m, int CP, double *gamma,
                                                 int32_t *argmax, double thr, int32_t *sel_blk) {
     constexpr int KP = 64 * KS;
-    __shared__ int s_cnt[4];
+    __shared__ double s_mx[4][GI_ROWS];
+    __shared__ __attribute__((aligned(16))) i32x4 s_dig[KS][GI_SL][64];
+    __shared__ double s_best[4][GI_ROWS];
+    __shared__ int s_idx[4][GI_ROWS];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
-    const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int64_t row0 = (int64_t)blockIdx.x * GI_ROWS;
     const int64_t arow = min(row0 + lr, n - 1);   // rows past n: clamped, never written
     const double *bp = brow + arow;
-    // the row's largest |b_k D_k| (D_k = 0 past m; k clamped into the rows)
+    // the row's largest |b_k D_k| (D_k = 0 past m; k clamped into the rows),
+    // this wavefront's k steps, then the four partial maxima
     double mx = 0.0;
-#pragma unroll
-    for (int s = 0; s < KS; ++s)
+    for (int s = wave; s < KS; s += 4)
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int k = 64 * s + 16 * lk + j;
             mx = fmax(mx, fabs(bp[(int64_t)min(k, ldb - 1) * ldn] * dsc[k]));
-            if (j == 15) __builtin_amdgcn_sched_barrier(0);
         }
     mx = fmax(mx, __shfl_xor(mx, 16, 64));
     mx = fmax(mx, __shfl_xor(mx, 32, 64));
-    // read the row again below (L1 / L2) rather than keep 4 KS x 16 values of
-    // b and D in registers from the pass above
-    __asm__ volatile("" ::: "memory");
+    if (lane < GI_ROWS) s_mx[wave][lane] = mx;
+    __syncthreads();
+    mx = fmax(fmax(s_mx[0][lr], s_mx[1][lr]), fmax(s_mx[2][lr], s_mx[3][lr]));
     int erow;
     (void)frexp(mx, &erow);   // mx = f 2^erow, f in [0.5, 1); 0 for a zero row
     const double sc = ldexp(1.0, 6 - erow);
-    // digits, four per register
-    i32x4 A[GI_SL][KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
+    // digits of this wavefront's k steps, four per register, into LDS
+    for (int s = wave; s < KS; s += 4) {
         unsigned w[GI_SL][4];
 #pragma unroll
         for (int t = 0; t < GI_SL; ++t)
@@ -254,49 +257,54 @@ __global__ __launch_bounds__(256) void grade_i8(const double *__restrict__ brow,
             }
         }
 #pragma unroll
-        for (int t = 0; t < GI_SL; ++t) A[t][s] = i32x4{(int)w[t][0], (int)w[t][1], (int)w[t][2], (int)w[t][3]};
-        // one k step's loads in flight at a time: hoisting all of them would
-        // hold 2 KS x 16 registers beside the digits
-        __builtin_amdgcn_sched_barrier(0);
+        for (int t = 0; t < GI_SL; ++t) s_dig[s][t][lane] = i32x4{(int)w[t][0], (int)w[t][1], (int)w[t][2], (int)w[t][3]};
     }
-    // 2^erow of the four result rows of this lane (row 4 lk + r is held by lane 4 lk + r)
+    __syncthreads();
+    // 2^(erow - 12) of the four result rows of this lane (row 4 lk + r is held by lane 4 lk + r)
     double rsc[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) rsc[r] = ldexp(1.0, __shfl(erow, 4 * lk + r, 64) - 12);
     double best[4] = {-1.0, -1.0, -1.0, -1.0};
     int bidx[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
-    const int64_t term = (int64_t)CP * KP;
     const int ntile = (m + 15) / 16;
+    const int nmine = (ntile - wave + 3) / 4;   // tiles wave, wave + 4, ... (local index lt)
     // the digits of D^-1 A^-1 for one k step of one column tile (20 registers),
-    // double-buffered across the steps; tiles go in pairs so that the buffer
-    // parity of every step is known at compile time (a tile past the last
-    // one, when their count is odd, reads the last tile again and compares
+    // double-buffered across the steps; local tiles go in pairs so that the
+    // buffer parity of every step is known at compile time (a tile past the
+    // last, when their count is odd, reads a valid tile again and compares
     // nothing: its columns are >= m)
-    auto fetch = [&](i32x4 (&B)[GI_SL], int tile, int s) {
+    // S: [column][k / 16][slice][16 digits]: the five slices of one lane's
+    // 16 k are 80 consecutive bytes (one 32-bit offset, immediate offsets)
+    const i32x4 *S4 = reinterpret_cast<const i32x4 *>(S);
+    auto fetch = [&](i32x4 (&B)[GI_SL], int lt, int s) {
+        int tile = wave + 4 * lt;
         tile = tile < ntile ? tile : ntile - 1;
-        const int8_t *src = S + (int64_t)(16 * tile + lr) * KP + 16 * lk + 64 * s;
+        const uint32_t o = ((uint32_t)(16 * tile + lr) * (KP / 16) + 4 * s + lk) * GI_SL;
 #pragma unroll
-        for (int t = 0; t < GI_SL; ++t) B[t] = *reinterpret_cast<const i32x4 *>(src + t * term);
+        for (int t = 0; t < GI_SL; ++t) B[t] = S4[o + t];
     };
     i32x4 Bb[2][GI_SL];
     i32x4 acc[GI_LEV];
-    fetch(Bb[0], 0, 0);
-    for (int t0 = 0; t0 < ntile; t0 += 2) {
+    if (nmine > 0) fetch(Bb[0], 0, 0);
+    for (int l0 = 0; l0 < nmine; l0 += 2) {
 #pragma unroll
         for (int u = 0; u < 2 * KS; ++u) {
-            const int tile = t0 + u / KS, s = u % KS;
+            const int lt = l0 + u / KS, s = u % KS;
             if (s == 0)
 #pragma unroll
                 for (int q = 0; q < GI_LEV; ++q) acc[q] = i32x4{0, 0, 0, 0};
-            if (u + 1 < 2 * KS) fetch(Bb[(u + 1) & 1], t0 + (u + 1) / KS, (u + 1) % KS);
-            else fetch(Bb[(u + 1) & 1], t0 + 2, 0);
+            if (u + 1 < 2 * KS) fetch(Bb[(u + 1) & 1], l0 + (u + 1) / KS, (u + 1) % KS);
+            else fetch(Bb[(u + 1) & 1], l0 + 2, 0);
+            i32x4 A[GI_SL];   // the rows' digits of this k step, from LDS (registers for more wavefronts)
+#pragma unroll
+            for (int t = 0; t < GI_SL; ++t) A[t] = s_dig[s][t][lane];
 #pragma unroll
             for (int a = 0; a < GI_SL; ++a)
 #pragma unroll
                 for (int b = 0; a + b <= GI_SL && b < GI_SL; ++b)
-                    acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[a][s], Bb[u & 1][b], acc[a + b], 0, 0, 0);
+                    acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[a], Bb[u & 1][b], acc[a + b], 0, 0, 0);
             if (s == KS - 1) {
-                const int col = 16 * tile + lr;
+                const int col = 16 * (wave + 4 * lt) + lr;
                 const double cs = ldexp(1.0, fexp[col < CP ? col : CP - 1]);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -304,13 +312,14 @@ __global__ __launch_bounds__(256) void grade_i8(const double *__restrict__ brow,
 #pragma unroll
                     for (int q = GI_LEV - 1; q >= 0; --q) v = fma(v, 0x1p-7, (double)acc[q][r]);
                     if (col < m) better(fabs(v * rsc[r] * cs), col, best[r], bidx[r]);
+                    __builtin_amdgcn_sched_barrier(0);   // one row's conversions at a time (registers)
                 }
             }
             // loads of one step ahead only (registers)
             __builtin_amdgcn_sched_barrier(0);
         }
     }
-    // the 16 lanes of a row group (columns), then one lane per row
+    // the 16 lanes of a row group (columns), then the four wavefronts
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1)
 #pragma unroll
@@ -319,29 +328,27 @@ __global__ __launch_bounds__(256) void grade_i8(const double *__restrict__ brow,
             const int oc = __shfl_xor(bidx[r], o, 64);
             better(ov, oc, best[r], bidx[r]);
         }
-    // lane l (< 16 used): row 4 (l / 4) + l % 4 of the wave, from lane 16 (l / 4)
-    const int src = 16 * (lr >> 2), rr = lr & 3;
-    double bv = 0.0;
-    int bc = 0;
+    if (lr == 0)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const double v = __shfl(best[r], src, 64);
-        const int c = __shfl(bidx[r], src, 64);
-        if (r == rr) {
-            bv = v;
-            bc = c;
+        for (int r = 0; r < 4; ++r) {
+            s_best[wave][4 * lk + r] = best[r];
+            s_idx[wave][4 * lk + r] = bidx[r];
         }
-    }
-    const int64_t row = row0 + lr;
-    const bool live = lane < 16 && row < n;
-    if (live) {
-        gamma[row] = bv;
-        if (argmax) argmax[row] = bc;
-    }
-    const unsigned long long sel = __ballot(live && bv > thr);
-    if (lane == 0) s_cnt[wave] = __popcll(sel);
     __syncthreads();
-    if (sel_blk && threadIdx.x == 0) sel_blk[blockIdx.x] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    if (wave == 0) {
+        double bv = s_best[0][lr];
+        int bc = s_idx[0][lr];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) better(s_best[w][lr], s_idx[w][lr], bv, bc);
+        const int64_t row = row0 + lr;
+        const bool live = lane < GI_ROWS && row < n;
+        if (live) {
+            gamma[row] = bv;
+            if (argmax) argmax[row] = bc;
+        }
+        const unsigned long long sel = __ballot(live && bv > thr);
+        if (sel_blk && lane == 0) sel_blk[blockIdx.x] = __popcll(sel);
+    }
 }
 
 // D_k = 2^-round(log2 max_i |A_ik|) (0 past m, and for an all-zero column)
@@ -354,7 +361,8 @@ __global__ void i8_colscale(const double *A, int m, int KP, double *dsc) {
     dsc[k] = mx > 0.0 ? ldexp(1.0, -(int)rint(log2(mx))) : 0.0;
 }
 
-// digits of column c of D^-1 A^-1: one block per column (padded columns: zero)
+// digits of column c of D^-1 A^-1, layout [c][k / 16][slice][k % 16]: one
+// block per column (padded columns: zero)
 __global__ __launch_bounds__(256) void i8_slice_ainv(const double *Ainv, int m, int KP, int CP, const double *dsc,
                                                      int8_t *S, int32_t *fexp) {
     __shared__ double sm[256];
@@ -372,13 +380,13 @@ __global__ __launch_bounds__(256) void i8_slice_ainv(const double *Ainv, int m, 
     (void)frexp(sm[0], &e);
     if (threadIdx.x == 0) fexp[c] = e;
     const double sc = ldexp(1.0, 6 - e);
-    const int64_t term = (int64_t)CP * KP;
     for (int k = threadIdx.x; k < KP; k += 256) {
         double r = (c < m && k < m && dsc[k] > 0.0) ? Ainv[(int64_t)k * m + c] / dsc[k] * sc : 0.0;
+        int8_t *dst = S + (((int64_t)c * (KP / 16) + k / 16) * GI_SL) * 16 + k % 16;   // [c][k / 16][t][16]
         for (int t = 0; t < GI_SL; ++t) {
             const double d = rint(r);
             r = (r - d) * 128.0;
-            S[t * term + (int64_t)c * KP + k] = (int8_t)(int)d;
+            dst[16 * t] = (int8_t)(int)d;
         }
     }
 }
@@ -634,14 +642,18 @@ static void launch_grade_f64(const ActiveSet &as, const double *brow, int64_t ld
 template <int KS>
 static void launch_grade_i8(const ActiveSet &as, const double *brow, int ldb, int64_t ldn, int64_t n, double *gamma,
                             int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
-    const dim3 grid((unsigned)((n + 63) / 64));
+    const dim3 grid((unsigned)((n + GI_ROWS - 1) / GI_ROWS));
     hipLaunchKernelGGL(grade_i8<KS>, grid, dim3(256), 0, st, brow, ldb, ldn, n, as.s8.as<int8_t>(),
                        as.fexp.as<int32_t>(), as.dsc.as<double>(), as.m, as.CP8, gamma, argmax, thr, sel_blk);
 }
 
+int grade_count_rows(const ActiveSet &as, int precision) {
+    return precision == MTP_MIXED && slice_product_fits(as.m) ? GI_ROWS : GF_ROWS;
+}
+
 void launch_grade(const ActiveSet &as, int precision, const double *brow, int ldb, int64_t ldn, int64_t n,
                   double *gamma, int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
-    static_assert(GRADE_ROWS == GF_ROWS, "preselection blocks are grade blocks");
+    static_assert(GRADE_ROWS == GF_ROWS && GRADE_ROWS % GI_ROWS == 0, "preselection blocks are grade blocks");
     if (n == 0) return;
     MTP_CHECK(ldb >= (as.m + 31) / 32 * 32, MTP_E_INVAL, "grade: row length below the padded row length");
     MTP_CHECK(ldn >= n, MTP_E_INVAL, "grade: column stride below the row count");

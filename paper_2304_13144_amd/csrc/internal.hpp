@@ -213,7 +213,10 @@ struct GatherArgs {
 GatherArgs gather_args(const mtp_nbrs *nb, const void *gbuf, int precision, double *forces);
 void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *blk, int32_t *idx, int32_t cap,
                          int32_t *count, hipStream_t st, const CfgSums *sums = nullptr,
-                         const GatherArgs *gather = nullptr);
+                         const GatherArgs *gather = nullptr, int count_rows = GRADE_ROWS);
+// rows per preselection count written by launch_grade (GRADE_ROWS, or 16 for
+// the mixed form's slice product)
+int grade_count_rows(const ActiveSet &as, int precision);
 void run_maxvol(ActiveSet &as, double *cand, int64_t n_cand, double thr, int max_swaps, int32_t *swap_cand,
                 int32_t *swap_col, int32_t *n_swaps, hipStream_t st, DevBuf &work);
 // column-major rows (entry (i, k) at src[k * ldn + i]) -> row-major dst [n][m]

@@ -405,16 +405,17 @@ __global__ __launch_bounds__(SCAN_T) void select_scan(int32_t *blk, int64_t nb) 
     if (threadIdx.x == 0) blk[nb] = carry;
 }
 
-// one wavefront places the selected rows of preselection block gb (of nb)
+// one wavefront places the selected rows of preselection block gb (of nb);
+// blk holds `per` counts per block of GRADE_ROWS rows (one per grade block)
 template <bool SCANNED>
 __device__ inline void select_write_wave(int64_t gb, int64_t nb, const double *g, int64_t n, double thr,
-                                         const int32_t *blk, int32_t *idx, int32_t cap, int32_t *count) {
+                                         const int32_t *blk, int per, int32_t *idx, int32_t cap, int32_t *count) {
     const int lane = threadIdx.x & 63;
     int64_t off = 0;
     if (SCANNED) {
-        off = blk[gb];
+        off = blk[gb * per];
     } else {
-        for (int64_t b = lane; b < gb; b += GRADE_ROWS) off += blk[b];
+        for (int64_t b = lane; b < gb * per; b += GRADE_ROWS) off += blk[b];
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) off += __shfl_xor(off, d, 64);
     }
@@ -438,7 +439,7 @@ __device__ inline void select_write_wave(int64_t gb, int64_t nb, const double *g
 // GRADE_ROWS rows of the preselection.
 template <bool SCANNED>
 __global__ __launch_bounds__(256) void select_write(const double *g, int64_t n, double thr, const int32_t *blk,
-                                                    int32_t *idx, int32_t cap, int32_t *count, int n_cfg,
+                                                    int per, int32_t *idx, int32_t cap, int32_t *count, int n_cfg,
                                                     const int64_t *cfg_off, const double *site_e, const double *vir,
                                                     const double *part, double *energy, double *stress,
                                                     const GatherArgs ga) {
@@ -456,7 +457,7 @@ __global__ __launch_bounds__(256) void select_write(const double *g, int64_t n, 
     }
     const int64_t nb = (n + GRADE_ROWS - 1) / GRADE_ROWS;
     const int64_t gb = (b - ga.blocks) * 4 + (threadIdx.x >> 6);
-    if (gb < nb) select_write_wave<SCANNED>(gb, nb, g, n, thr, blk, idx, cap, count);
+    if (gb < nb) select_write_wave<SCANNED>(gb, nb, g, n, thr, blk, per, idx, cap, count);
 }
 
 // column sums of the per-neighborhood gradient rows, FP64, fixed order:
@@ -647,7 +648,10 @@ GatherArgs gather_args(const mtp_nbrs *nb, const void *gbuf, int precision, doub
 }
 
 void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *blk, int32_t *idx, int32_t cap,
-                         int32_t *count, hipStream_t st, const CfgSums *sums, const GatherArgs *gather) {
+                         int32_t *count, hipStream_t st, const CfgSums *sums, const GatherArgs *gather,
+                         int count_rows) {
+    MTP_CHECK(count_rows > 0 && GRADE_ROWS % count_rows == 0, MTP_E_INVAL, "preselection count granularity");
+    const int per = GRADE_ROWS / count_rows;
     const GatherArgs ga = gather ? *gather : GatherArgs{};
     const int n_cfg = sums ? sums->s->n_cfg : 0;
     const int64_t *off = sums ? sums->s->cfg_off : nullptr;
@@ -660,14 +664,16 @@ void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *bl
         return;
     }
     const int64_t nb = (n + GRADE_ROWS - 1) / GRADE_ROWS;
+    const int64_t ncount = (n + count_rows - 1) / count_rows;   // entries of blk
     const dim3 grid((unsigned)(n_cfg + ga.blocks + (nb + 3) / 4));
-    if (nb <= SEL_DIRECT_BLOCKS) {
-        hipLaunchKernelGGL(select_write<false>, grid, dim3(256), 0, st, gamma, n, thr, blk, idx, cap, count, n_cfg, off,
-                           se, vir, part, energy, stress, ga);
+    if (ncount <= SEL_DIRECT_BLOCKS) {
+        hipLaunchKernelGGL(select_write<false>, grid, dim3(256), 0, st, gamma, n, thr, blk, per, idx, cap, count, n_cfg,
+                           off, se, vir, part, energy, stress, ga);
     } else {
-        hipLaunchKernelGGL(select_scan, dim3(1), dim3(SCAN_T), 0, st, blk, nb);
-        hipLaunchKernelGGL(select_write<true>, grid, dim3(256), 0, st, gamma, n, thr, blk, idx, cap, count, n_cfg, off,
-                           se, vir, part, energy, stress, ga);
+        // exclusive offsets in place: entry gb * per is where block gb starts
+        hipLaunchKernelGGL(select_scan, dim3(1), dim3(SCAN_T), 0, st, blk, ncount);
+        hipLaunchKernelGGL(select_write<true>, grid, dim3(256), 0, st, gamma, n, thr, blk, per, idx, cap, count, n_cfg,
+                           off, se, vir, part, energy, stress, ga);
     }
 }
 
