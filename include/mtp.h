@@ -194,6 +194,21 @@ int mtp_nbrs_export(const mtp_nbrs *nb, int32_t *count, int32_t *j, int32_t *shi
 int mtp_energy_forces_stress(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p,
                              double *energy, double *forces, double *stress, double *site_e, void *stream);
 
+/* The same as mtp_energy_forces_stress, allocating nothing: for callers that
+ * cannot call hipMalloc (code under HIP graph capture, tight serving or MD
+ * loops, harnesses that forbid allocation).  Its scratch (moments, dE/dM,
+ * pair gradients, per-atom virials and site energies, sum partials) is one
+ * static device array of MTP_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends; a call whose evaluation needs more (about 2.4 KB per atom
+ * at level 16 with max_nbrs 64 in FP64, so some 27,000 atoms) returns
+ * MTP_E_CAPACITY before anything is enqueued.  The neighbor lists must
+ * already be built.  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller; nothing in the array needs to start at zero. */
+#define MTP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int mtp_energy_forces_stress_noalloc(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p,
+                                     double *energy, double *forces, double *stress, double *site_e, void *stream);
+
 /* Grades gamma_i = max_p |(b_i A^-1)_p| of every neighborhood (Sec. II.D)
  * and the argmax p (lowest on ties).  gamma [n_atoms] FP64, argmax
  * [n_atoms] int32 or NULL; b_rows (optional) receives the rows, [n_atoms*m]

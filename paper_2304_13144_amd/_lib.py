@@ -20,7 +20,7 @@ STATUS = {0: "MTP_OK", -1: "MTP_E_INVAL", -2: "MTP_E_IO", -3: "MTP_E_PARSE", -4:
 # every symbol declared in include/mtp.h
 EXPORTS = ("mtp_load", "mtp_save", "mtp_create", "mtp_free", "mtp_info", "mtp_set_params", "mtp_get_params", "mtp_kept_columns",
            "mtp_set_active_set", "mtp_get_active_set", "mtp_nbrs_create", "mtp_nbrs_free", "mtp_build_neighbors",
-           "mtp_nbrs_status", "mtp_nbrs_export", "mtp_energy_forces_stress", "mtp_grade", "mtp_grade_cfg", "mtp_evaluate",
+           "mtp_nbrs_status", "mtp_nbrs_export", "mtp_energy_forces_stress", "mtp_energy_forces_stress_noalloc", "mtp_grade", "mtp_grade_cfg", "mtp_evaluate",
            "mtp_evaluate_select", "mtp_b_rows", "mtp_select", "mtp_maxvol_update", "mtp_cut_neighborhood", "mtp_md_run", "mtp_relax_fire", "mtp_fit_bfgs", "mtp_efs_backward", "mtp_basis_describe",
            "mtp_compiled_levels", "mtp_last_error", "mtp_profile_enable", "mtp_profile_read", "mtp_tune")
 
@@ -78,6 +78,7 @@ def lib():
         "mtp_nbrs_status": [P, P],
         "mtp_nbrs_export": [P, P, P, P, ctypes.POINTER(I32), P],
         "mtp_energy_forces_stress": [P, ctypes.POINTER(System), P, ctypes.c_int, P, P, P, P, P],
+        "mtp_energy_forces_stress_noalloc": [P, ctypes.POINTER(System), P, ctypes.c_int, P, P, P, P, P],
         "mtp_grade": [P, ctypes.POINTER(System), P, ctypes.c_int, ctypes.c_int, P, P, P, P],
         "mtp_evaluate": [P, ctypes.POINTER(System), P, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P],
         "mtp_grade_cfg": [P, ctypes.POINTER(System), P, ctypes.c_int, ctypes.c_int, P, P, P, P],

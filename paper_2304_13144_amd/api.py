@@ -196,6 +196,22 @@ def energy_forces_stress(model, batch, nbrs, precision="fp64", site_energies=Tru
     return {"energy": E, "forces": F, "stress": S, "site_e": V}
 
 
+def energy_forces_stress_noalloc(model, batch, nbrs, precision="fp64", out=None):
+    """energy_forces_stress through the entry point that allocates nothing
+    (its scratch is the library's fixed device array); `out` reuses tensors."""
+    d = batch.device
+    if out is None:
+        out = {"energy": _out(batch.n_cfg, torch.float64, d),
+               "forces": _out(None, torch.float64, d, (batch.n_atoms, 3)),
+               "stress": _out(None, torch.float64, d, (batch.n_cfg, 3, 3)),
+               "site_e": _out(batch.n_atoms, torch.float64, d)}
+    s = batch.system()
+    check(_lib.lib().mtp_energy_forces_stress_noalloc(model._h, ctypes.byref(s), nbrs._h, _prec(precision),
+                                                      _p(out["energy"]), _p(out["forces"]), _p(out["stress"]),
+                                                      _p(out.get("site_e")), _stream()))
+    return out
+
+
 def grade(model, batch, nbrs, precision="fp64", mode="full", rows=False):
     d = batch.device
     g = _out(batch.n_atoms, torch.float64, d)
@@ -440,7 +456,7 @@ def compiled_levels():
     return list(arr[:n])
 
 
-__all__ = ["Model", "Batch", "Neighbors", "energy_forces_stress", "grade", "grade_cfg", "cfg_rows", "evaluate",
+__all__ = ["Model", "Batch", "Neighbors", "energy_forces_stress", "energy_forces_stress_noalloc", "grade", "grade_cfg", "cfg_rows", "evaluate",
            "b_rows", "select", "cut_neighborhood", "md_run", "relax_fire", "fit_bfgs",
            "maxvol_update", "efs_backward", "MTPEnergy", "tune", "CapturedStep", "basis_describe", "compiled_levels", "MtpError"]
 

@@ -197,8 +197,28 @@ struct EvalOut {
     bool keep_rows = false;   // leave the rows in m->brow (configuration mode)
 };
 
+// Where the evaluation's scratch comes from: the model's buffers, grown on
+// demand (hipMalloc), or one fixed device region that is carved up in order
+// (the no-allocation entry point; sizes past the region are rejected).
+struct Workspace {
+    char *base = nullptr;   // fixed region, or NULL for the model's buffers
+    size_t cap = 0, used = 0;
+    void *get(DevBuf &b, size_t bytes) {
+        if (!base) {
+            b.ensure(bytes);
+            return b.ptr;
+        }
+        const size_t off = (used + 255) / 256 * 256;
+        MTP_CHECK(off <= cap && bytes <= cap - off, MTP_E_CAPACITY,
+                  "the evaluation needs more than the " + std::to_string(cap >> 20) +
+                      " MiB of the fixed scratch region (fewer atoms or a smaller max_nbrs)");
+        used = off + bytes;
+        return base + off;
+    }
+};
+
 void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int prec, const EvalOut &o,
-              hipStream_t st) {
+              hipStream_t st, Workspace ws = Workspace{}) {
     check_system(m, s);
     check_nbrs(m, s, nb);
     MTP_CHECK(prec == MTP_FP64 || prec == MTP_MIXED, MTP_E_INVAL, "bad precision");
@@ -218,14 +238,14 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     const bool want_e = o.energy || o.site_e;
     const int mm = m->m_of(o.mode);
     const int ldb = ld_of(mm);
-    if (want_f) m->gbuf.ensure(tsz * 3 * (size_t)std::max<int64_t>(1, n * nb->max_nbrs));
-    if (want_v) m->virial.ensure(sizeof(double) * 9 * (size_t)std::max<int64_t>(1, n));
+    void *gbuf = want_f ? ws.get(m->gbuf, tsz * 3 * (size_t)std::max<int64_t>(1, n * nb->max_nbrs)) : nullptr;
+    double *virial =
+        want_v ? static_cast<double *>(ws.get(m->virial, sizeof(double) * 9 * (size_t)std::max<int64_t>(1, n))) : nullptr;
     double *site = o.site_e;
-    if (want_e && !site) {
-        m->sitebuf.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, n));
-        site = m->sitebuf.as<double>();
-    }
-    if (want_rows) m->brow.ensure(sizeof(double) * (size_t)ldb * (size_t)std::max<int64_t>(1, n));
+    if (want_e && !site) site = static_cast<double *>(ws.get(m->sitebuf, sizeof(double) * (size_t)std::max<int64_t>(1, n)));
+    double *brow = want_rows ? static_cast<double *>(ws.get(m->brow, sizeof(double) * (size_t)ldb *
+                                                                        (size_t)std::max<int64_t>(1, n)))
+                             : nullptr;
     if (n == 0) {
         if (o.energy) launch_zero(o.energy, sizeof(double) * s->n_cfg, st);
         if (o.stress) launch_zero(o.stress, sizeof(double) * 9 * s->n_cfg, st);
@@ -246,9 +266,9 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     a.th32 = m->theta32.as<float>();
     a.n_lin = m->basis.n_lin();
     a.site_e = want_e ? site : nullptr;
-    a.gbuf = want_f ? m->gbuf.ptr : nullptr;
-    a.virial = want_v ? m->virial.as<double>() : nullptr;
-    a.brow = want_rows ? m->brow.as<double>() : nullptr;
+    a.gbuf = gbuf;
+    a.virial = virial;
+    a.brow = brow;
     a.ldn = n;
     a.ldb = ldb;
     a.grade_mode = o.mode;
@@ -259,10 +279,8 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     a.lanes = sched & 15;
     a.lanes_mc = sched >> 4;
     a.stream = st;
-    m->mbuf.ensure(msz * m->basis.n_comp() * (size_t)n);
-    m->dmbuf.ensure(msz * m->basis.n_comp() * (size_t)n);
-    a.mbuf = m->mbuf.ptr;
-    a.dmbuf = m->dmbuf.ptr;
+    a.mbuf = ws.get(m->mbuf, msz * m->basis.n_comp() * (size_t)n);
+    a.dmbuf = ws.get(m->dmbuf, msz * m->basis.n_comp() * (size_t)n);
     // per-configuration sums: chunk partials, then one block per configuration.
     // With forces and a preselection the force gather runs as extra blocks of
     // the preselection's launch (one launch less per step) and the partials
@@ -270,11 +288,11 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     // their own) writes them.
     const bool want_sums = o.energy || want_v;
     const double *sum_e = o.energy ? site : nullptr;
-    const double *sum_v = want_v ? m->virial.as<double>() : nullptr;
-    if (want_sums) m->sums.ensure(cfg_partials_bytes(n));
+    const double *sum_v = want_v ? virial : nullptr;
+    double *sums = want_sums ? static_cast<double *>(ws.get(m->sums, cfg_partials_bytes(n))) : nullptr;
     const bool fuse_gather = want_f && want_sel;
     if (fuse_gather && want_sums) {
-        a.part = m->sums.as<double>();
+        a.part = sums;
         a.part_e = sum_e;
     }
     int e;
@@ -285,38 +303,35 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     MTP_CHECK(e == 0, MTP_E_HIP, std::string("efs kernel launch: ") + hipGetErrorString((hipError_t)e));
     if (want_f && !fuse_gather) {
         ProfScope ps("force_gather", st);
-        launch_force_gather(nb, m->gbuf.ptr, prec, o.forces, st, sum_e, sum_v,
-                            want_sums ? m->sums.as<double>() : nullptr);
+        launch_force_gather(nb, gbuf, prec, o.forces, st, sum_e, sum_v, sums);
     } else if (want_sums && !fuse_gather) {
-        launch_cfg_partials(n, sum_e, sum_v, m->sums.as<double>(), st);
+        launch_cfg_partials(n, sum_e, sum_v, sums, st);
     }
     // with a preselection the sums are finished by the preselection's launch
-    const CfgSums sums{s, sum_e, sum_v, m->sums.as<double>(), o.energy, o.stress};
+    const CfgSums csums{s, sum_e, sum_v, sums, o.energy, o.stress};
     if (want_sums && !want_sel) {
         ProfScope ps("cfg_sums", st);
-        launch_cfg_final(s, sum_e, sum_v, m->sums.as<double>(), o.energy, o.stress, st);
+        launch_cfg_final(s, sum_e, sum_v, sums, o.energy, o.stress, st);
     }
     if (want_grade) {
-        m->gamma_ws.ensure(sizeof(double) * n);
-        double *gam = o.gamma ? o.gamma : m->gamma_ws.as<double>();
+        double *gam = o.gamma ? o.gamma : static_cast<double *>(ws.get(m->gamma_ws, sizeof(double) * n));
         int32_t *blk = nullptr;
         const int count_rows = grade_count_rows(m->act[o.mode], prec);
-        if (want_sel) {
-            m->selblk.ensure(sizeof(int32_t) * (size_t)((n + count_rows - 1) / count_rows + 1));
-            blk = m->selblk.as<int32_t>();
-        }
+        if (want_sel)
+            blk = static_cast<int32_t *>(
+                ws.get(m->selblk, sizeof(int32_t) * (size_t)((n + count_rows - 1) / count_rows + 1)));
         {
             ProfScope ps("grade", st);
-            launch_grade(m->act[o.mode], prec, m->brow.as<double>(), ldb, n, n, gam, o.argmax, st, o.sel_thr, blk);
+            launch_grade(m->act[o.mode], prec, brow, ldb, n, n, gam, o.argmax, st, o.sel_thr, blk);
         }
         if (want_sel) {
             ProfScope ps("select", st);
-            const GatherArgs ga = fuse_gather ? gather_args(nb, m->gbuf.ptr, prec, o.forces) : GatherArgs{};
+            const GatherArgs ga = fuse_gather ? gather_args(nb, gbuf, prec, o.forces) : GatherArgs{};
             launch_select_write(gam, n, o.sel_thr, blk, o.sel_idx, o.sel_cap, o.sel_count, st,
-                                want_sums ? &sums : nullptr, fuse_gather ? &ga : nullptr, count_rows);
+                                want_sums ? &csums : nullptr, fuse_gather ? &ga : nullptr, count_rows);
         }
     }
-    if (o.b_rows) launch_copy_rows(m->brow.as<double>(), n, mm, n, static_cast<double *>(o.b_rows), st);
+    if (o.b_rows) launch_copy_rows(brow, n, mm, n, static_cast<double *>(o.b_rows), st);
     MTP_HIP(hipGetLastError());
 }
 
@@ -633,6 +648,23 @@ int mtp_energy_forces_stress(const mtp_model *m, const mtp_system *s, const mtp_
     o.stress = stress;
     o.site_e = site_e;
     evaluate(m, s, nb, p, o, S(stream));
+    API_END
+}
+
+int mtp_energy_forces_stress_noalloc(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p,
+                                     double *energy, double *forces, double *stress, double *site_e, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m, MTP_E_INVAL, "NULL model");
+    MTP_HIP(hipSetDevice(m->device));
+    EvalOut o;
+    o.energy = energy;
+    o.forces = forces;
+    o.stress = stress;
+    o.site_e = site_e;
+    Workspace ws;
+    ws.base = static_cast<char *>(noalloc_scratch(m->device));
+    ws.cap = NOALLOC_SCRATCH_BYTES;
+    evaluate(m, s, nb, p, o, S(stream), ws);
     API_END
 }
 

@@ -248,4 +248,10 @@ void launch_cfg_rows(const double *rows, int ldb, int64_t n, const mtp_system *s
                      hipStream_t st);
 void launch_zero(void *p, size_t bytes, hipStream_t st);
 
+// The fixed scratch region of the no-allocation entry point (a static device
+// array, one copy per GPU): its device address on `device`, looked up once
+// per device (that device must be current on the first call).
+constexpr size_t NOALLOC_SCRATCH_BYTES = MTP_NOALLOC_SCRATCH_BYTES;
+void *noalloc_scratch(int device);
+
 }  // namespace mtp

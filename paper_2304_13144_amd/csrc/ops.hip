@@ -2,6 +2,8 @@
 // configuration energy / stress sums, row copies, preselection compaction.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <algorithm>
 #include <cmath>
 
@@ -500,6 +502,27 @@ void launch_column_sums(const void *rows, int precision, int64_t n, int ncol, do
         hipLaunchKernelGGL(col_partial<float>, grid, dim3(256), 0, st, static_cast<const float *>(rows), n, ncol,
                            work.as<double>());
     hipLaunchKernelGGL(col_final, dim3((unsigned)((ncol + 255) / 256)), dim3(256), 0, st, work.as<double>(), ncol, out);
+}
+
+// Scratch of mtp_energy_forces_stress_noalloc: a file-scope device array
+// (each GPU the library runs on holds its own copy until the process ends).
+// Host code never uses the array's name as an address (on the host it is a
+// stand-in, not device memory): the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+void *noalloc_scratch(int device) {
+    static std::mutex mu;
+    static void *ptr[64] = {};
+    MTP_CHECK(device >= 0 && device < 64, MTP_E_INVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[device]) {
+        void *p = nullptr;
+        MTP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        MTP_CHECK(p != nullptr, MTP_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+        ptr[device] = p;
+    }
+    return ptr[device];
 }
 
 void launch_zero(void *p, size_t bytes, hipStream_t st) {
