@@ -44,7 +44,9 @@ namespace {
 
 hipStream_t S(void *s) { return static_cast<hipStream_t>(s); }
 
-int ld_of(int m) { return (m + 31) / 32 * 32; }
+// columns of the rows buffer: m padded with zeros to a multiple of 64 (the
+// k step of the mixed grade product)
+int ld_of(int m) { return (m + 63) / 64 * 64; }
 
 // FULL-mode gauge: per mu drop mu+1 columns of block c_mu chosen as the
 // first mu+1 pivots of a column-pivoted Gram-Schmidt (= QR with column

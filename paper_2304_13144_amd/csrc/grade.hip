@@ -189,137 +189,143 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
 }
 
 // ---- mixed form: int8 slice product ----------------------------------------
-// Block of 256 threads = one group of 16 rows and four wavefronts that split
-// its column tiles (wavefront w: tiles w, w + 4, ...), so that n / 16 blocks
-// keep several wavefronts on every SIMD.  The four wavefronts cut the rows
-// into digits together (wavefront w: k steps w, w + 4, ...; the row maxima
-// and the digits meet in LDS, in the MFMA operand layout: lane l: row l % 16,
-// k = 64 s + 16 (l / 16) .. + 16 of k step s; KS steps, m <= 64 KS); then each
-// sweeps its columns, reading the rows' digits of a k step from LDS and the
-// digits of D^-1 A^-1 (one 16-byte load per slice and k step, L2-resident)
-// one k step ahead.  Result layout of the 16x16 i32
-// tile: row 4 (l / 16) + r, column l % 16.  One preselection count per 16
-// rows.
+// Block of 256 threads = 64 rows, one group of 16 per wavefront.  Each
+// wavefront cuts its rows into digits and keeps them in registers in the MFMA
+// operand layout (lane l: row l % 16, k = 64 s + 16 (l / 16) .. + 16 of k step
+// s; KS steps, m <= 64 KS).  The digits of D^-1 A^-1 are stored tile by tile
+// in exactly the order the lanes read them ([tile][s][slice][lane][16]), so
+// the block stages a column tile into LDS as one contiguous copy (five
+// 16-byte loads per thread at KS = 4), double-buffered, one barrier per
+// tile, and every wavefront reads its operand with one 16-byte LDS read per
+// slice and k step.  Result layout of the 16x16 i32 tile: row 4 (l / 16) +
+// r, column l % 16.
 constexpr int GI_SL = 5;                  // digits per operand
 constexpr int GI_LEV = GI_SL + 1;         // levels s + t = 0 .. GI_SL summed
-constexpr int GI_KS_MAX = 5;              // k steps of 64 (the rows' digits in LDS): m <= 320
-constexpr int GI_ROWS = 16;               // rows per block (and per preselection count)
+constexpr int GI_KS_MAX = 5;              // k steps of 64 held in registers: m <= 320
+constexpr int GI_ROWS = 64;               // rows per block (and per preselection count)
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 template <int KS>
 __global__ __launch_bounds__(256) void grade_i8(const double *__restrict__ brow, int ldb, int64_t ldn, int64_t n,
-                                                const int8_t *__restrict__ S, const int32_t *__restrict__ fexp,
+                                                const i32x4 *__restrict__ S, const int32_t *__restrict__ fexp,
                                                 const double *__restrict__ dsc, int m, int CP, double *gamma,
                                                 int32_t *argmax, double thr, int32_t *sel_blk) {
-    constexpr int KP = 64 * KS;
-    __shared__ double s_mx[4][GI_ROWS];
-    __shared__ __attribute__((aligned(16))) i32x4 s_dig[KS][GI_SL][64];
-    __shared__ double s_best[4][GI_ROWS];
-    __shared__ int s_idx[4][GI_ROWS];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int TILE = KS * GI_SL * 64;     // 16-byte pieces of one column tile
+    constexpr int PER = (TILE + 255) / 256;   // pieces per thread
+    __shared__ i32x4 sB[2][TILE];
+    __shared__ int s_cnt[4];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
-    const int64_t row0 = (int64_t)blockIdx.x * GI_ROWS;
+    const int64_t row0 = (int64_t)blockIdx.x * GI_ROWS + wave * 16;
     const int64_t arow = min(row0 + lr, n - 1);   // rows past n: clamped, never written
     const double *bp = brow + arow;
-    // the row's largest |b_k D_k| (D_k = 0 past m; k clamped into the rows),
-    // this wavefront's k steps, then the four partial maxima
-    double mx = 0.0;
-    for (int s = wave; s < KS; s += 4)
+    const int ntile = (m + 15) / 16;
+    // the first column tile's digits in flight while the rows are cut
+    i32x4 pre[PER];
+    auto fetch = [&](int tile) {
+        const i32x4 *src = S + (int64_t)tile * TILE;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int k = 64 * s + 16 * lk + j;
-            mx = fmax(mx, fabs(bp[(int64_t)min(k, ldb - 1) * ldn] * dsc[k]));
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + 256 * q;
+            if (TILE % 256 == 0 || e < TILE) pre[q] = src[e];
         }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + 256 * q;
+            if (TILE % 256 == 0 || e < TILE) sB[buf][e] = pre[q];
+        }
+    };
+    fetch(0);
+    // the row's largest |b_k D_k| (D_k = 0 past m; the rows have ldb = 64 KS
+    // columns, zero past m); four k at a time: a running column pointer and
+    // one 32-byte read of D (addresses and values of a whole k step would
+    // hold some 100 registers)
+    double mx = 0.0;
+    for (int g = 0; g < 4 * KS; ++g) {   // k = 64 (g / 4) + 16 lk + 4 (g % 4) + 0..3
+        const int k0 = 64 * (g >> 2) + 16 * lk + 4 * (g & 3);
+        const double *p = bp + (int64_t)k0 * ldn;
+        const double4 d = *reinterpret_cast<const double4 *>(dsc + k0);
+        mx = fmax(mx, fmax(fmax(fabs(p[0] * d.x), fabs(p[ldn] * d.y)), fmax(fabs(p[2 * ldn] * d.z),
+                                                                             fabs(p[3 * ldn] * d.w))));
+    }
     mx = fmax(mx, __shfl_xor(mx, 16, 64));
     mx = fmax(mx, __shfl_xor(mx, 32, 64));
-    if (lane < GI_ROWS) s_mx[wave][lane] = mx;
-    __syncthreads();
-    mx = fmax(fmax(s_mx[0][lr], s_mx[1][lr]), fmax(s_mx[2][lr], s_mx[3][lr]));
+    // read the row again below (L1 / L2) rather than keep 4 KS x 16 values of
+    // b and D in registers from the pass above
+    __asm__ volatile("" ::: "memory");
     int erow;
     (void)frexp(mx, &erow);   // mx = f 2^erow, f in [0.5, 1); 0 for a zero row
     const double sc = ldexp(1.0, 6 - erow);
-    // digits of this wavefront's k steps, four per register, into LDS
-    for (int s = wave; s < KS; s += 4) {
-        unsigned w[GI_SL][4];
+    // digits, four per register (one register per slice for each four k)
+    i32x4 A[GI_SL][KS];
 #pragma unroll
-        for (int t = 0; t < GI_SL; ++t)
+    for (int s = 0; s < KS; ++s)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) w[t][q] = 0u;
+        for (int q = 0; q < 4; ++q) {
+            const int k0 = 64 * s + 16 * lk + 4 * q;
+            const double *p = bp + (int64_t)k0 * ldn;
+            const double4 dd = *reinterpret_cast<const double4 *>(dsc + k0);
+            const double x[4] = {p[0] * dd.x, p[ldn] * dd.y, p[2 * ldn] * dd.z, p[3 * ldn] * dd.w};
+            unsigned w[GI_SL] = {0u, 0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int k = 64 * s + 16 * lk + j;
-            double r = bp[(int64_t)min(k, ldb - 1) * ldn] * dsc[k] * sc;   // |r| < 64, exact
+            for (int j = 0; j < 4; ++j) {
+                double r = x[j] * sc;   // |r| < 64, exact
 #pragma unroll
-            for (int t = 0; t < GI_SL; ++t) {
-                const double d = rint(r);
-                r = (r - d) * 128.0;
-                w[t][j >> 2] |= ((unsigned)(int)d & 0xffu) << (8 * (j & 3));
+                for (int t = 0; t < GI_SL; ++t) {
+                    const double d = rint(r);
+                    r = (r - d) * 128.0;
+                    w[t] |= ((unsigned)(int)d & 0xffu) << (8 * j);
+                }
             }
-        }
 #pragma unroll
-        for (int t = 0; t < GI_SL; ++t) s_dig[s][t][lane] = i32x4{(int)w[t][0], (int)w[t][1], (int)w[t][2], (int)w[t][3]};
-    }
-    __syncthreads();
+            for (int t = 0; t < GI_SL; ++t) A[t][s][q] = (int)w[t];
+            __builtin_amdgcn_sched_barrier(0);   // four k in flight at a time (registers)
+        }
     // 2^(erow - 12) of the four result rows of this lane (row 4 lk + r is held by lane 4 lk + r)
     double rsc[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) rsc[r] = ldexp(1.0, __shfl(erow, 4 * lk + r, 64) - 12);
     double best[4] = {-1.0, -1.0, -1.0, -1.0};
     int bidx[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
-    const int ntile = (m + 15) / 16;
-    const int nmine = (ntile - wave + 3) / 4;   // tiles wave, wave + 4, ... (local index lt)
-    // the digits of D^-1 A^-1 for one k step of one column tile (20 registers),
-    // double-buffered across the steps; local tiles go in pairs so that the
-    // buffer parity of every step is known at compile time (a tile past the
-    // last, when their count is odd, reads a valid tile again and compares
-    // nothing: its columns are >= m)
-    // S: [column][k / 16][slice][16 digits]: the five slices of one lane's
-    // 16 k are 80 consecutive bytes (one 32-bit offset, immediate offsets)
-    const i32x4 *S4 = reinterpret_cast<const i32x4 *>(S);
-    auto fetch = [&](i32x4 (&B)[GI_SL], int lt, int s) {
-        int tile = wave + 4 * lt;
-        tile = tile < ntile ? tile : ntile - 1;
-        const uint32_t o = ((uint32_t)(16 * tile + lr) * (KP / 16) + 4 * s + lk) * GI_SL;
+    stash(0);
+    __syncthreads();
+    for (int tile = 0; tile < ntile; ++tile) {
+        const int buf = tile & 1;
+        if (tile + 1 < ntile) fetch(tile + 1);
+        i32x4 acc[GI_LEV];
 #pragma unroll
-        for (int t = 0; t < GI_SL; ++t) B[t] = S4[o + t];
-    };
-    i32x4 Bb[2][GI_SL];
-    i32x4 acc[GI_LEV];
-    if (nmine > 0) fetch(Bb[0], 0, 0);
-    for (int l0 = 0; l0 < nmine; l0 += 2) {
+        for (int q = 0; q < GI_LEV; ++q) acc[q] = i32x4{0, 0, 0, 0};
+        // the operand of k step s + 1 is read from LDS while the MFMAs of step s run
+        i32x4 B[2][GI_SL];
 #pragma unroll
-        for (int u = 0; u < 2 * KS; ++u) {
-            const int lt = l0 + u / KS, s = u % KS;
-            if (s == 0)
+        for (int t = 0; t < GI_SL; ++t) B[0][t] = sB[buf][t * 64 + lane];
 #pragma unroll
-                for (int q = 0; q < GI_LEV; ++q) acc[q] = i32x4{0, 0, 0, 0};
-            if (u + 1 < 2 * KS) fetch(Bb[(u + 1) & 1], l0 + (u + 1) / KS, (u + 1) % KS);
-            else fetch(Bb[(u + 1) & 1], l0 + 2, 0);
-            i32x4 A[GI_SL];   // the rows' digits of this k step, from LDS (registers for more wavefronts)
+        for (int s = 0; s < KS; ++s) {
+            if (s + 1 < KS)
 #pragma unroll
-            for (int t = 0; t < GI_SL; ++t) A[t] = s_dig[s][t][lane];
+                for (int t = 0; t < GI_SL; ++t) B[(s + 1) & 1][t] = sB[buf][((s + 1) * GI_SL + t) * 64 + lane];
 #pragma unroll
             for (int a = 0; a < GI_SL; ++a)
 #pragma unroll
                 for (int b = 0; a + b <= GI_SL && b < GI_SL; ++b)
-                    acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[a], Bb[u & 1][b], acc[a + b], 0, 0, 0);
-            if (s == KS - 1) {
-                const int col = 16 * (wave + 4 * lt) + lr;
-                const double cs = ldexp(1.0, fexp[col < CP ? col : CP - 1]);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    double v = 0.0;
-#pragma unroll
-                    for (int q = GI_LEV - 1; q >= 0; --q) v = fma(v, 0x1p-7, (double)acc[q][r]);
-                    if (col < m) better(fabs(v * rsc[r] * cs), col, best[r], bidx[r]);
-                    __builtin_amdgcn_sched_barrier(0);   // one row's conversions at a time (registers)
-                }
-            }
-            // loads of one step ahead only (registers)
-            __builtin_amdgcn_sched_barrier(0);
+                    acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[a][s], B[s & 1][b], acc[a + b], 0, 0, 0);
         }
+        const int col = 16 * tile + lr;
+        const double cs = ldexp(1.0, fexp[col]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = GI_LEV - 1; q >= 0; --q) v = fma(v, 0x1p-7, (double)acc[q][r]);
+            if (col < m) better(fabs(v * rsc[r] * cs), col, best[r], bidx[r]);
+        }
+        if (tile + 1 < ntile) stash(buf ^ 1);
+        __syncthreads();
     }
-    // the 16 lanes of a row group (columns), then the four wavefronts
+    // the 16 lanes of a row group (columns), then one lane per row
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1)
 #pragma unroll
@@ -328,27 +334,29 @@ __global__ __launch_bounds__(256) void grade_i8(const double *__restrict__ brow,
             const int oc = __shfl_xor(bidx[r], o, 64);
             better(ov, oc, best[r], bidx[r]);
         }
-    if (lr == 0)
+    // lane l (< 16 used): row 4 (l / 4) + l % 4 of the wave, from lane 16 (l / 4)
+    const int src = 16 * (lr >> 2), rr = lr & 3;
+    double bv = 0.0;
+    int bc = 0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            s_best[wave][4 * lk + r] = best[r];
-            s_idx[wave][4 * lk + r] = bidx[r];
+    for (int r = 0; r < 4; ++r) {
+        const double v = __shfl(best[r], src, 64);
+        const int c = __shfl(bidx[r], src, 64);
+        if (r == rr) {
+            bv = v;
+            bc = c;
         }
-    __syncthreads();
-    if (wave == 0) {
-        double bv = s_best[0][lr];
-        int bc = s_idx[0][lr];
-#pragma unroll
-        for (int w = 1; w < 4; ++w) better(s_best[w][lr], s_idx[w][lr], bv, bc);
-        const int64_t row = row0 + lr;
-        const bool live = lane < GI_ROWS && row < n;
-        if (live) {
-            gamma[row] = bv;
-            if (argmax) argmax[row] = bc;
-        }
-        const unsigned long long sel = __ballot(live && bv > thr);
-        if (sel_blk && lane == 0) sel_blk[blockIdx.x] = __popcll(sel);
     }
+    const int64_t row = row0 + lr;
+    const bool live = lane < 16 && row < n;
+    if (live) {
+        gamma[row] = bv;
+        if (argmax) argmax[row] = bc;
+    }
+    const unsigned long long sel = __ballot(live && bv > thr);
+    if (lane == 0) s_cnt[wave] = __popcll(sel);
+    __syncthreads();
+    if (sel_blk && tid == 0) sel_blk[blockIdx.x] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
 }
 
 // D_k = 2^-round(log2 max_i |A_ik|) (0 past m, and for an all-zero column)
@@ -361,8 +369,9 @@ __global__ void i8_colscale(const double *A, int m, int KP, double *dsc) {
     dsc[k] = mx > 0.0 ? ldexp(1.0, -(int)rint(log2(mx))) : 0.0;
 }
 
-// digits of column c of D^-1 A^-1, layout [c][k / 16][slice][k % 16]: one
-// block per column (padded columns: zero)
+// digits of column c of D^-1 A^-1, stored in the order the grade's lanes read
+// them: [tile = c / 16][s = k / 64][slice][lane = c % 16 + 16 ((k % 64) / 16)][k % 16];
+// one block per column (padded columns: zero)
 __global__ __launch_bounds__(256) void i8_slice_ainv(const double *Ainv, int m, int KP, int CP, const double *dsc,
                                                      int8_t *S, int32_t *fexp) {
     __shared__ double sm[256];
@@ -380,13 +389,16 @@ __global__ __launch_bounds__(256) void i8_slice_ainv(const double *Ainv, int m, 
     (void)frexp(sm[0], &e);
     if (threadIdx.x == 0) fexp[c] = e;
     const double sc = ldexp(1.0, 6 - e);
+    const int KS = KP / 64;
+    const int64_t tile_bytes = (int64_t)KS * GI_SL * 64 * 16;
     for (int k = threadIdx.x; k < KP; k += 256) {
         double r = (c < m && k < m && dsc[k] > 0.0) ? Ainv[(int64_t)k * m + c] / dsc[k] * sc : 0.0;
-        int8_t *dst = S + (((int64_t)c * (KP / 16) + k / 16) * GI_SL) * 16 + k % 16;   // [c][k / 16][t][16]
+        const int s = k / 64, lane = c % 16 + 16 * ((k % 64) / 16);
+        int8_t *dst = S + (c / 16) * tile_bytes + ((int64_t)(s * GI_SL) * 64 + lane) * 16 + k % 16;
         for (int t = 0; t < GI_SL; ++t) {
             const double d = rint(r);
             r = (r - d) * 128.0;
-            dst[16 * t] = (int8_t)(int)d;
+            dst[(int64_t)t * 64 * 16] = (int8_t)(int)d;
         }
     }
 }
@@ -643,7 +655,7 @@ template <int KS>
 static void launch_grade_i8(const ActiveSet &as, const double *brow, int ldb, int64_t ldn, int64_t n, double *gamma,
                             int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
     const dim3 grid((unsigned)((n + GI_ROWS - 1) / GI_ROWS));
-    hipLaunchKernelGGL(grade_i8<KS>, grid, dim3(256), 0, st, brow, ldb, ldn, n, as.s8.as<int8_t>(),
+    hipLaunchKernelGGL(grade_i8<KS>, grid, dim3(256), 0, st, brow, ldb, ldn, n, as.s8.as<i32x4>(),
                        as.fexp.as<int32_t>(), as.dsc.as<double>(), as.m, as.CP8, gamma, argmax, thr, sel_blk);
 }
 
@@ -659,6 +671,7 @@ void launch_grade(const ActiveSet &as, int precision, const double *brow, int ld
     MTP_CHECK(ldn >= n, MTP_E_INVAL, "grade: column stride below the row count");
     if (precision == MTP_MIXED && slice_product_fits(as.m)) {
         MTP_CHECK(as.KP8 == (as.m + 63) / 64 * 64 && as.s8.ptr, MTP_E_INVAL, "grade: digits of A^-1 not prepared");
+        MTP_CHECK(ldb >= as.KP8, MTP_E_INVAL, "grade: rows not padded to a multiple of 64 columns");
         switch (as.KP8 / 64) {
             case 1: launch_grade_i8<1>(as, brow, ldb, ldn, n, gamma, argmax, st, thr, sel_blk); break;
             case 2: launch_grade_i8<2>(as, brow, ldb, ldn, n, gamma, argmax, st, thr, sel_blk); break;
