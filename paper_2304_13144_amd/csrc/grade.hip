@@ -36,6 +36,7 @@ namespace mtp {
 namespace {
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef double doublex2 __attribute__((ext_vector_type(2)));   // (HIP's double2 is a struct: arrays of it end up in scratch)
 
 __device__ inline void better(double v, int c, double &bv, int &bc) {
     if (v > bv || (v == bv && c < bc)) {
@@ -66,7 +67,7 @@ __device__ inline void better(double v, int c, double &bv, int &bc) {
 // m on the host (the smallest padding of m to passes of 32 HALF columns).
 constexpr int GF_ROWS = 64, GF_KC = 16, GF_NBUF = 3;
 template <int HALF>
-__global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow, int64_t ldn, int64_t n,
+__global__ __launch_bounds__(512) void grade_f64_wide(const double *__restrict__ brow, int64_t ldn, int64_t n,
                                                  const double *__restrict__ Ainv, int m, double *gamma,
                                                  int32_t *argmax, double thr, int32_t *sel_blk) {
     constexpr int CT = 32 * HALF;
@@ -188,16 +189,132 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
     }
 }
 
+// FP64, m <= 32 GR_NK_MAX (288): a block of 512 threads = 64 rows x two halves of
+// the column tiles (wavefront w: row group w % 4, half w / 4, tiles h, h + 2,
+// ...), so that every SIMD runs two wavefronts.  A wavefront holds its 16 rows
+// in registers for the whole product in the MFMA operand layout (lane l: row
+// l % 16, k = 4 s + l / 16 of k step s; 8 NK steps of four).  A^-1 is stored
+// column tile by column tile in the order the lanes read it ([tile][s][lane]:
+// k = 4 s + l / 16, column 16 tile + l % 16, zero past m), so each half stages
+// its tile into LDS as one contiguous copy (double-buffered, the next tile's
+// loads in flight during the MFMAs, one barrier per tile) and a wavefront
+// reads its operand with one 8-byte LDS read per k step.  Even and odd k
+// steps go to two accumulators (two independent MFMA chains), added at the
+// end of the tile; the two halves' maxima meet in LDS at the end.
+constexpr int GR_NK_MAX = 9;   // 32-k chunks: m <= 288 (two halves x two buffers of a tile in LDS)
+template <int NK>
+__global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow, int64_t ldn, int64_t n,
+                                                 const double *__restrict__ L, int m, double *gamma,
+                                                 int32_t *argmax, double thr, int32_t *sel_blk) {
+    constexpr int KS = 8 * NK;                 // k steps of four
+    constexpr int TILE = KS * 64;              // doubles of one column tile
+    constexpr int PER = TILE / 2 / 256;        // 16-byte pieces per thread of a half (NK)
+    static_assert(PER * 512 == TILE, "tile staging");
+    __shared__ doublex2 sB[2][2][TILE / 2];    // [half][buffer]
+    __shared__ double s_best[2][GF_ROWS];
+    __shared__ int s_idx[2][GF_ROWS];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int rg = wave & 3, half = wave >> 2, ht = tid & 255;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int64_t row0 = (int64_t)blockIdx.x * GF_ROWS + rg * 16;
+    const int ntile = (m + 15) / 16;
+    const int nstep = (ntile + 1) / 2;         // tiles per half, rounded up (both halves pass every barrier)
+    doublex2 pre[PER];
+    auto fetch = [&](int tile) {
+        tile = tile < ntile ? tile : ntile - 1;   // past the last tile: an in-bounds tile, never compared
+        const doublex2 *src = reinterpret_cast<const doublex2 *>(L + (int64_t)tile * TILE);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) pre[q] = src[ht + 256 * q];
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) sB[half][buf][ht + 256 * q] = pre[q];
+    };
+    fetch(half);
+    // this lane's row, k = 4 s + lk (the rows are zero past m up to ldb >= 32 NK)
+    double a[KS];
+    {
+        const double *bp = brow + min(row0 + lr, n - 1) + (int64_t)lk * ldn;   // rows past n: clamped, never written
+#pragma unroll
+        for (int s = 0; s < KS; ++s) a[s] = bp[(int64_t)(4 * s) * ldn];
+    }
+    double best[4] = {-1.0, -1.0, -1.0, -1.0};
+    int bidx[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
+    stash(0);
+    __syncthreads();
+    for (int st = 0; st < nstep; ++st) {
+        const int buf = st & 1, tile = 2 * st + half;
+        if (st + 1 < nstep) fetch(tile + 2);
+        doublex4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+        const double *b = reinterpret_cast<const double *>(sB[half][buf]) + lane;
+#pragma unroll
+        for (int s = 0; s < KS; s += 2) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[64 * s], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s + 1], b[64 * (s + 1)], acc1, 0, 0, 0);
+        }
+        const int col = 16 * tile + lr;
+        if (col < m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) better(fabs(acc0[r] + acc1[r]), col, best[r], bidx[r]);
+        if (st + 1 < nstep) stash(buf ^ 1);
+        __syncthreads();
+    }
+    // the 16 lanes of a row (columns), then the two halves
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double ov = __shfl_xor(best[r], o, 64);
+            const int oc = __shfl_xor(bidx[r], o, 64);
+            better(ov, oc, best[r], bidx[r]);
+        }
+    if (lr == 0)   // f64 layout: lane l, register r -> row l / 16 + 4 r
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            s_best[half][rg * 16 + lk + 4 * r] = best[r];
+            s_idx[half][rg * 16 + lk + 4 * r] = bidx[r];
+        }
+    __syncthreads();
+    if (tid < GF_ROWS) {   // wavefront 0: one row per lane
+        double bv = s_best[0][tid];
+        int bc = s_idx[0][tid];
+        better(s_best[1][tid], s_idx[1][tid], bv, bc);
+        const int64_t row = (int64_t)blockIdx.x * GF_ROWS + tid;
+        const bool live = row < n;
+        if (live) {
+            gamma[row] = bv;
+            if (argmax) argmax[row] = bc;
+        }
+        const unsigned long long sel = __ballot(live && bv > thr);
+        if (sel_blk && tid == 0) sel_blk[blockIdx.x] = __popcll(sel);
+    }
+}
+
+// A^-1 in the lane order of grade_f64: out[(tile * 8 NK + s) * 64 + l] =
+// A^-1[4 s + l / 16][16 tile + l % 16], zero past m
+__global__ void f64_stage_ainv(const double *Ainv, int m, int NK, int ntile, double *out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)ntile * 8 * NK * 64;
+    if (e >= tot) return;
+    const int l = (int)(e % 64);
+    const int64_t ts = e / 64;
+    const int s = (int)(ts % (8 * NK)), tile = (int)(ts / (8 * NK));
+    const int k = 4 * s + l / 16, c = 16 * tile + l % 16;
+    out[e] = (k < m && c < m) ? Ainv[(int64_t)k * m + c] : 0.0;
+}
+
 // ---- mixed form: int8 slice product ----------------------------------------
-// Block of 256 threads = 64 rows, one group of 16 per wavefront.  Each
-// wavefront cuts its rows into digits and keeps them in registers in the MFMA
-// operand layout (lane l: row l % 16, k = 64 s + 16 (l / 16) .. + 16 of k step
+// Block of 512 threads = 64 rows x two halves of the column tiles (wavefront
+// w: row group w % 4, half w / 4, tiles h, h + 2, ...: two wavefronts per
+// SIMD).  Each wavefront cuts its rows into digits and keeps them in
+// registers in the MFMA operand layout (lane l: row l % 16, k = 64 s + 16 (l / 16) .. + 16 of k step
 // s; KS steps, m <= 64 KS).  The digits of D^-1 A^-1 are stored tile by tile
 // in exactly the order the lanes read them ([tile][s][slice][lane][16]), so
-// the block stages a column tile into LDS as one contiguous copy (five
+// each half stages its column tile into LDS as one contiguous copy (five
 // 16-byte loads per thread at KS = 4), double-buffered, one barrier per
 // tile, and every wavefront reads its operand with one 16-byte LDS read per
-// slice and k step.  Result layout of the 16x16 i32 tile: row 4 (l / 16) +
+// slice and k step; the halves' maxima meet in LDS at the end.  Result layout of the 16x16 i32 tile: row 4 (l / 16) +
 // r, column l % 16.
 constexpr int GI_SL = 5;                  // digits per operand
 constexpr int GI_LEV = GI_SL + 1;         // levels s + t = 0 .. GI_SL summed
@@ -206,63 +323,70 @@ constexpr int GI_ROWS = 64;               // rows per block (and per preselectio
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 template <int KS>
-__global__ __launch_bounds__(256) void grade_i8(const double *__restrict__ brow, int ldb, int64_t ldn, int64_t n,
+__global__ __launch_bounds__(512) void grade_i8(const double *__restrict__ brow, int ldb, int64_t ldn, int64_t n,
                                                 const i32x4 *__restrict__ S, const int32_t *__restrict__ fexp,
                                                 const double *__restrict__ dsc, int m, int CP, double *gamma,
                                                 int32_t *argmax, double thr, int32_t *sel_blk) {
     constexpr int TILE = KS * GI_SL * 64;     // 16-byte pieces of one column tile
-    constexpr int PER = (TILE + 255) / 256;   // pieces per thread
-    __shared__ i32x4 sB[2][TILE];
-    __shared__ int s_cnt[4];
+    constexpr int PER = (TILE + 255) / 256;   // pieces per thread of a half
+    // one LDS area: first the rows' digits [row group][s][slice][lane], then
+    // the column tiles [half][buffer][TILE] (the same size)
+    __shared__ i32x4 sm[4 * TILE];
+    __shared__ double s_mx[2][GI_ROWS];
+    __shared__ double s_best[2][GI_ROWS];
+    __shared__ int s_idx[2][GI_ROWS];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
+    const int rg = wave & 3, half = wave >> 2, ht = tid & 255;
     const int lr = lane & 15, lk = lane >> 4;
-    const int64_t row0 = (int64_t)blockIdx.x * GI_ROWS + wave * 16;
+    const int64_t row0 = (int64_t)blockIdx.x * GI_ROWS + rg * 16;
     const int64_t arow = min(row0 + lr, n - 1);   // rows past n: clamped, never written
     const double *bp = brow + arow;
     const int ntile = (m + 15) / 16;
+    const int nstep = (ntile + 1) / 2;   // tiles per half, rounded up (both halves pass every barrier)
     // the first column tile's digits in flight while the rows are cut
     i32x4 pre[PER];
     auto fetch = [&](int tile) {
+        tile = tile < ntile ? tile : ntile - 1;   // past the last tile: an in-bounds tile, never compared
         const i32x4 *src = S + (int64_t)tile * TILE;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int e = tid + 256 * q;
+            const int e = ht + 256 * q;
             if (TILE % 256 == 0 || e < TILE) pre[q] = src[e];
         }
     };
     auto stash = [&](int buf) {
+        i32x4 *dst = sm + (2 * half + buf) * TILE;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int e = tid + 256 * q;
-            if (TILE % 256 == 0 || e < TILE) sB[buf][e] = pre[q];
+            const int e = ht + 256 * q;
+            if (TILE % 256 == 0 || e < TILE) dst[e] = pre[q];
         }
     };
-    fetch(0);
-    // the row's largest |b_k D_k| (D_k = 0 past m; the rows have ldb = 64 KS
-    // columns, zero past m); four k at a time: a running column pointer and
-    // one 32-byte read of D (addresses and values of a whole k step would
-    // hold some 100 registers)
+    fetch(half);
+    // the two halves' wavefronts of a row group cut it together: k steps
+    // s = half, half + 2, ...; first the row's largest |b_k D_k| (D_k = 0 past
+    // m; the rows have ldb >= 64 KS columns, zero past m), four k at a time
     double mx = 0.0;
-    for (int g = 0; g < 4 * KS; ++g) {   // k = 64 (g / 4) + 16 lk + 4 (g % 4) + 0..3
-        const int k0 = 64 * (g >> 2) + 16 * lk + 4 * (g & 3);
-        const double *p = bp + (int64_t)k0 * ldn;
-        const double4 d = *reinterpret_cast<const double4 *>(dsc + k0);
-        mx = fmax(mx, fmax(fmax(fabs(p[0] * d.x), fabs(p[ldn] * d.y)), fmax(fabs(p[2 * ldn] * d.z),
-                                                                             fabs(p[3 * ldn] * d.w))));
-    }
+    for (int s = half; s < KS; s += 2)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k0 = 64 * s + 16 * lk + 4 * q;
+            const double *p = bp + (int64_t)k0 * ldn;
+            const double4 d = *reinterpret_cast<const double4 *>(dsc + k0);
+            mx = fmax(mx, fmax(fmax(fabs(p[0] * d.x), fabs(p[ldn] * d.y)), fmax(fabs(p[2 * ldn] * d.z),
+                                                                                 fabs(p[3 * ldn] * d.w))));
+        }
     mx = fmax(mx, __shfl_xor(mx, 16, 64));
     mx = fmax(mx, __shfl_xor(mx, 32, 64));
-    // read the row again below (L1 / L2) rather than keep 4 KS x 16 values of
-    // b and D in registers from the pass above
-    __asm__ volatile("" ::: "memory");
+    if (lane < 16) s_mx[half][rg * 16 + lane] = mx;
+    __syncthreads();
+    mx = fmax(s_mx[0][rg * 16 + lr], s_mx[1][rg * 16 + lr]);
     int erow;
     (void)frexp(mx, &erow);   // mx = f 2^erow, f in [0.5, 1); 0 for a zero row
     const double sc = ldexp(1.0, 6 - erow);
-    // digits, four per register (one register per slice for each four k)
-    i32x4 A[GI_SL][KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s)
+    // digits of this wavefront's k steps into LDS, one register per slice for each four k
+    for (int s = half; s < KS; s += 2)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int k0 = 64 * s + 16 * lk + 4 * q;
@@ -280,33 +404,42 @@ __global__ __launch_bounds__(256) void grade_i8(const double *__restrict__ brow,
                     w[t] |= ((unsigned)(int)d & 0xffu) << (8 * j);
                 }
             }
+            int *dig = reinterpret_cast<int *>(sm + ((rg * KS + s) * GI_SL) * 64 + lane) + q;
 #pragma unroll
-            for (int t = 0; t < GI_SL; ++t) A[t][s][q] = (int)w[t];
-            __builtin_amdgcn_sched_barrier(0);   // four k in flight at a time (registers)
+            for (int t = 0; t < GI_SL; ++t) dig[t * 64 * 4] = (int)w[t];
         }
-    // 2^(erow - 12) of the four result rows of this lane (row 4 lk + r is held by lane 4 lk + r)
+    __syncthreads();
+    i32x4 A[GI_SL][KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int t = 0; t < GI_SL; ++t) A[t][s] = sm[((rg * KS + s) * GI_SL + t) * 64 + lane];
+    // 2^(erow - 19) of the four result rows of this lane (row 4 lk + r is held by
+    // lane 4 lk + r): level 1 (weight 2^-19) is the unit of the combined sums below
     double rsc[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) rsc[r] = ldexp(1.0, __shfl(erow, 4 * lk + r, 64) - 12);
+    for (int r = 0; r < 4; ++r) rsc[r] = ldexp(1.0, __shfl(erow, 4 * lk + r, 64) - 19);
     double best[4] = {-1.0, -1.0, -1.0, -1.0};
     int bidx[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
+    __syncthreads();   // every wavefront holds its digits: the area takes the column tiles
     stash(0);
     __syncthreads();
-    for (int tile = 0; tile < ntile; ++tile) {
-        const int buf = tile & 1;
-        if (tile + 1 < ntile) fetch(tile + 1);
+    for (int st = 0; st < nstep; ++st) {
+        const int buf = st & 1, tile = 2 * st + half;
+        if (st + 1 < nstep) fetch(tile + 2);
+        const i32x4 *sB = sm + (2 * half + buf) * TILE;
         i32x4 acc[GI_LEV];
 #pragma unroll
         for (int q = 0; q < GI_LEV; ++q) acc[q] = i32x4{0, 0, 0, 0};
         // the operand of k step s + 1 is read from LDS while the MFMAs of step s run
         i32x4 B[2][GI_SL];
 #pragma unroll
-        for (int t = 0; t < GI_SL; ++t) B[0][t] = sB[buf][t * 64 + lane];
+        for (int t = 0; t < GI_SL; ++t) B[0][t] = sB[t * 64 + lane];
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             if (s + 1 < KS)
 #pragma unroll
-                for (int t = 0; t < GI_SL; ++t) B[(s + 1) & 1][t] = sB[buf][((s + 1) * GI_SL + t) * 64 + lane];
+                for (int t = 0; t < GI_SL; ++t) B[(s + 1) & 1][t] = sB[((s + 1) * GI_SL + t) * 64 + lane];
 #pragma unroll
             for (int a = 0; a < GI_SL; ++a)
 #pragma unroll
@@ -314,18 +447,21 @@ __global__ __launch_bounds__(256) void grade_i8(const double *__restrict__ brow,
                     acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[a][s], B[s & 1][b], acc[a + b], 0, 0, 0);
         }
         const int col = 16 * tile + lr;
-        const double cs = ldexp(1.0, fexp[col]);
+        const double cs = ldexp(1.0, fexp[col < CP ? col : CP - 1]);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            double v = 0.0;
-#pragma unroll
-            for (int q = GI_LEV - 1; q >= 0; --q) v = fma(v, 0x1p-7, (double)acc[q][r]);
+            // levels 0 + 1, 2 + 3, 4 + 5 exactly in int32 (|acc_q| < 2^23), then FP64:
+            // C = 2^(erow + fexp - 19) (c01 + 2^-14 (c23 + 2^-14 c45))
+            const int c01 = acc[0][r] * 128 + acc[1][r];
+            const int c23 = acc[2][r] * 128 + acc[3][r];
+            const int c45 = acc[4][r] * 128 + acc[5][r];
+            const double v = fma(fma((double)c45, 0x1p-14, (double)c23), 0x1p-14, (double)c01);
             if (col < m) better(fabs(v * rsc[r] * cs), col, best[r], bidx[r]);
         }
-        if (tile + 1 < ntile) stash(buf ^ 1);
+        if (st + 1 < nstep) stash(buf ^ 1);
         __syncthreads();
     }
-    // the 16 lanes of a row group (columns), then one lane per row
+    // the 16 lanes of a row group (columns), then the two halves
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1)
 #pragma unroll
@@ -334,29 +470,26 @@ __global__ __launch_bounds__(256) void grade_i8(const double *__restrict__ brow,
             const int oc = __shfl_xor(bidx[r], o, 64);
             better(ov, oc, best[r], bidx[r]);
         }
-    // lane l (< 16 used): row 4 (l / 4) + l % 4 of the wave, from lane 16 (l / 4)
-    const int src = 16 * (lr >> 2), rr = lr & 3;
-    double bv = 0.0;
-    int bc = 0;
+    if (lr == 0)   // i32 layout: lane l, register r -> row 4 (l / 16) + r
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const double v = __shfl(best[r], src, 64);
-        const int c = __shfl(bidx[r], src, 64);
-        if (r == rr) {
-            bv = v;
-            bc = c;
+        for (int r = 0; r < 4; ++r) {
+            s_best[half][rg * 16 + 4 * lk + r] = best[r];
+            s_idx[half][rg * 16 + 4 * lk + r] = bidx[r];
         }
-    }
-    const int64_t row = row0 + lr;
-    const bool live = lane < 16 && row < n;
-    if (live) {
-        gamma[row] = bv;
-        if (argmax) argmax[row] = bc;
-    }
-    const unsigned long long sel = __ballot(live && bv > thr);
-    if (lane == 0) s_cnt[wave] = __popcll(sel);
     __syncthreads();
-    if (sel_blk && tid == 0) sel_blk[blockIdx.x] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    if (tid < GI_ROWS) {   // wavefront 0: one row per lane
+        double bv = s_best[0][tid];
+        int bc = s_idx[0][tid];
+        better(s_best[1][tid], s_idx[1][tid], bv, bc);
+        const int64_t row = (int64_t)blockIdx.x * GI_ROWS + tid;
+        const bool live = row < n;
+        if (live) {
+            gamma[row] = bv;
+            if (argmax) argmax[row] = bc;
+        }
+        const unsigned long long sel = __ballot(live && bv > thr);
+        if (sel_blk && tid == 0) sel_blk[blockIdx.x] = __popcll(sel);
+    }
 }
 
 // D_k = 2^-round(log2 max_i |A_ik|) (0 past m, and for an all-zero column)
@@ -625,6 +758,14 @@ void prepare_split(ActiveSet &as, hipStream_t st) {
                        as.KP8, as.dsc.as<double>());
     hipLaunchKernelGGL(i8_slice_ainv, dim3((unsigned)as.CP8), dim3(256), 0, st, as.Ainv.as<double>(), m, as.KP8,
                        as.CP8, as.dsc.as<double>(), as.s8.as<int8_t>(), as.fexp.as<int32_t>());
+    if (m <= 32 * GR_NK_MAX) {   // A^-1 in the lane order of the FP64 product
+        as.NK64 = (m + 31) / 32;
+        const int ntile = (m + 15) / 16;
+        const int64_t tot = (int64_t)ntile * 8 * as.NK64 * 64;
+        as.lane64.ensure(sizeof(double) * (size_t)tot);
+        hipLaunchKernelGGL(f64_stage_ainv, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, as.Ainv.as<double>(),
+                           m, as.NK64, ntile, as.lane64.as<double>());
+    }
 }
 
 bool slice_product_fits(int m) { return m <= 64 * GI_KS_MAX; }
@@ -644,10 +785,18 @@ static int grade_half(int m) {
 }
 
 template <int HALF>
+static void launch_grade_f64_wide(const ActiveSet &as, const double *brow, int64_t ldn, int64_t n, double *gamma,
+                                  int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
+    const dim3 grid((unsigned)((n + GF_ROWS - 1) / GF_ROWS));
+    hipLaunchKernelGGL(grade_f64_wide<HALF>, grid, dim3(512), 0, st, brow, ldn, n, as.Ainv.as<double>(), as.m, gamma,
+                       argmax, thr, sel_blk);
+}
+
+template <int NK>
 static void launch_grade_f64(const ActiveSet &as, const double *brow, int64_t ldn, int64_t n, double *gamma,
                              int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
     const dim3 grid((unsigned)((n + GF_ROWS - 1) / GF_ROWS));
-    hipLaunchKernelGGL(grade_f64<HALF>, grid, dim3(512), 0, st, brow, ldn, n, as.Ainv.as<double>(), as.m, gamma,
+    hipLaunchKernelGGL(grade_f64<NK>, grid, dim3(512), 0, st, brow, ldn, n, as.lane64.as<double>(), as.m, gamma,
                        argmax, thr, sel_blk);
 }
 
@@ -655,7 +804,7 @@ template <int KS>
 static void launch_grade_i8(const ActiveSet &as, const double *brow, int ldb, int64_t ldn, int64_t n, double *gamma,
                             int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
     const dim3 grid((unsigned)((n + GI_ROWS - 1) / GI_ROWS));
-    hipLaunchKernelGGL(grade_i8<KS>, grid, dim3(256), 0, st, brow, ldb, ldn, n, as.s8.as<i32x4>(),
+    hipLaunchKernelGGL(grade_i8<KS>, grid, dim3(512), 0, st, brow, ldb, ldn, n, as.s8.as<i32x4>(),
                        as.fexp.as<int32_t>(), as.dsc.as<double>(), as.m, as.CP8, gamma, argmax, thr, sel_blk);
 }
 
@@ -682,14 +831,30 @@ void launch_grade(const ActiveSet &as, int precision, const double *brow, int ld
         return;
     }
     // FP64 form, and the mixed form past m = 320 (the digits would not fit in registers)
+    if (as.m <= 32 * GR_NK_MAX) {
+        MTP_CHECK(as.NK64 == (as.m + 31) / 32 && as.lane64.ptr, MTP_E_INVAL, "grade: A^-1 not staged");
+        MTP_CHECK(ldb >= 32 * as.NK64, MTP_E_INVAL, "grade: rows not padded to a multiple of 32 columns");
+        switch (as.NK64) {
+            case 1: launch_grade_f64<1>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 2: launch_grade_f64<2>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 3: launch_grade_f64<3>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 4: launch_grade_f64<4>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 5: launch_grade_f64<5>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 6: launch_grade_f64<6>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 7: launch_grade_f64<7>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 8: launch_grade_f64<8>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            default: launch_grade_f64<9>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        }
+        return;
+    }
     switch (grade_half(as.m)) {
-        case 1: launch_grade_f64<1>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
-        case 2: launch_grade_f64<2>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
-        case 3: launch_grade_f64<3>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
-        case 4: launch_grade_f64<4>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
-        case 5: launch_grade_f64<5>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
-        case 6: launch_grade_f64<6>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
-        default: launch_grade_f64<7>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        case 1: launch_grade_f64_wide<1>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        case 2: launch_grade_f64_wide<2>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        case 3: launch_grade_f64_wide<3>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        case 4: launch_grade_f64_wide<4>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        case 5: launch_grade_f64_wide<5>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        case 6: launch_grade_f64_wide<6>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        default: launch_grade_f64_wide<7>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
     }
 }
 

@@ -56,6 +56,9 @@ struct ActiveSet {
     // [GI_SL][CP8][KP8], their column exponents [CP8], the column scales D [KP8]
     DevBuf s8, fexp, dsc;
     int KP8 = 0, CP8 = 0;
+    // FP64 product (m <= 320): A^-1 in the lane order of the grade kernel
+    DevBuf lane64;
+    int NK64 = 0;
 };
 
 }  // namespace mtp
