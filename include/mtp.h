@@ -175,7 +175,9 @@ int mtp_nbrs_free(mtp_nbrs *nb);
 int mtp_build_neighbors(const mtp_model *m, const mtp_system *s, int32_t max_nbrs, mtp_nbrs *nb, void *stream);
 
 /* Synchronises `stream`; returns MTP_OK, MTP_E_CAPACITY (with the largest
- * count in the message) or MTP_E_OVERLAP for the last build. */
+ * count in the message), MTP_E_OVERLAP, or MTP_E_INVAL (a position that is
+ * not finite, a singular cell, a species out of range, an image shift past
+ * +-127 cells) for the last build. */
 int mtp_nbrs_status(const mtp_nbrs *nb, void *stream);
 
 /* Copies the lists out: count [n_atoms] (int32), j [n_atoms*max_nbrs]

@@ -147,6 +147,7 @@ class Batch:
 class Neighbors:
     def __init__(self):
         self._h = ctypes.c_void_p()
+        self.generation = 0   # counts builds (a backward checks that its lists were not rebuilt)
         check(_lib.lib().mtp_nbrs_create(ctypes.byref(self._h)))
 
     def __del__(self):
@@ -162,6 +163,7 @@ class Neighbors:
         s = batch.system()
         check(_lib.lib().mtp_build_neighbors(model._h, ctypes.byref(s), max_nbrs, self._h, _stream()))
         self.max_nbrs = max_nbrs
+        self.generation += 1
         if check_status:
             self.status()
         return self
@@ -418,17 +420,28 @@ class MTPEnergy(torch.autograd.Function):
 
     Forward evaluates energies [n_cfg], forces [n_atoms, 3] and stresses
     [n_cfg, 3, 3] with theta loaded into the model; backward returns
-    dL/dtheta from the library's backward kernels (moments recomputed)."""
+    dL/dtheta from the library's backward kernels (moments recomputed) at the
+    theta of its own forward: the model is loaded with that theta again if
+    another forward or set_params changed it in between.  A backward after
+    the neighbor lists were rebuilt raises (its positions are gone)."""
 
     @staticmethod
     def forward(ctx, theta, model, batch, nbrs, precision="fp64"):
         model.set_params(theta.detach())
         out = energy_forces_stress(model, batch, nbrs, precision, site_energies=False)
+        ctx.save_for_backward(theta.detach().clone())
         ctx.model, ctx.batch, ctx.nbrs, ctx.precision = model, batch, nbrs, precision
+        ctx.generation = nbrs.generation
         return out["energy"], out["forces"], out["stress"]
 
     @staticmethod
     def backward(ctx, gE, gF, gS):
+        (theta,) = ctx.saved_tensors
+        if ctx.nbrs.generation != ctx.generation:
+            raise RuntimeError("MTPEnergy.backward: the neighbor lists were rebuilt after this forward")
+        th = theta.cpu().numpy()
+        if not np.array_equal(ctx.model.theta, th):
+            ctx.model.set_params(th)
         g = efs_backward(ctx.model, ctx.batch, ctx.nbrs, gE, gF, gS, ctx.precision)
         return g, None, None, None, None
 
@@ -489,6 +502,17 @@ class CapturedStep:
         evaluate(self.model, self.batch, self.nbrs, precision, mode, out=self.out, gamma_save=gamma_save)
         self.sel = (self.out["sel_idx"], self.out["sel_count"])
 
-    def replay(self):
+    def replay(self, check=True):
+        """Replays the step.  With `check` (the default) it waits for the step
+        and raises MtpError if the neighbor build of this replay flagged a
+        capacity overflow, an overlap or a non-finite position (the status
+        words are written on the device by every replayed build); without it
+        the replay is only enqueued, and status() checks later."""
         self.graph.replay()
+        if check and self.rebuild:
+            self.status()
         return self.out
+
+    def status(self):
+        """Raises MtpError for what the last replayed neighbor build flagged (synchronises)."""
+        self.nbrs.status()

@@ -30,6 +30,8 @@ HIP_FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wno-unuse
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", CSRC, "-I", GEN]
 HOST_SOURCES = ["api.cpp", "basis.cpp", "prof.cpp"]
+# what the generated per-level units include (besides their level's program)
+KERNEL_HEADERS = ["efs_kernel.hpp", "backward_kernel.hpp", "kernel_args.hpp", "device_util.hpp"]
 HIP_SOURCES = ["neighbors.hip", "ops.hip", "grade.hip"]
 
 
@@ -115,16 +117,24 @@ def build(levels=DEFAULT_LEVELS, jobs=None, verbose=True, force=True):
     header / generated program (development loop); the default rebuilds all."""
     t0 = time.time()
     units, dispatch = generate(levels)
+    mt = os.path.getmtime
+    # the per-level units see only the kernel headers and their level's program
+    kernel_deps = [os.path.join(CSRC, f) for f in KERNEL_HEADERS] + [os.path.abspath(__file__)]
+    kernel_mtime = max(mt(d) for d in kernel_deps)
     deps = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
-    deps += [os.path.join(GEN, f) for f in os.listdir(GEN) if f.endswith(".inc")]
     deps += [os.path.join(os.path.dirname(HERE), "include", "mtp.h"), os.path.abspath(__file__)]
-    deps_mtime = max(os.path.getmtime(d) for d in deps)
+    host_mtime = max(mt(d) for d in deps)
     objs = []
     jobs_list = []
     for src in [os.path.join(CSRC, s) for s in HOST_SOURCES + HIP_SOURCES] + [dispatch] + units:
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
         objs.append(obj)
-        if force or _stale(src, obj, deps_mtime):
+        if src in units:
+            level = "".join(ch for ch in os.path.basename(src).split("_")[1] if ch.isdigit())
+            dm = max(kernel_mtime, mt(os.path.join(GEN, f"mtp_level{level}.inc")))
+        else:
+            dm = host_mtime
+        if force or _stale(src, obj, dm):
             jobs_list.append([HIPCC] + HIP_FLAGS + ["-c", src, "-o", obj])
     n = jobs or min(8, os.cpu_count() or 4)
     # longest units first (the backward units of the highest levels)

@@ -597,6 +597,7 @@ int mtp_nbrs_status(const mtp_nbrs *nb, void *stream) {
     int32_t f[4] = {0, 0, 0, 0};
     MTP_HIP(hipMemcpyAsync(f, nb->flags.ptr, sizeof(f), hipMemcpyDeviceToHost, S(stream)));
     MTP_HIP(hipStreamSynchronize(S(stream)));
+    MTP_CHECK(!(f[3] & 16), MTP_E_INVAL, "a position is not finite (NaN or Inf)");
     MTP_CHECK(!(f[3] & 1), MTP_E_INVAL, "a cell matrix is singular");
     MTP_CHECK(!(f[3] & 8), MTP_E_INVAL, "an atom type is outside 0..n_types-1");
     MTP_CHECK(!(f[3] & 2), MTP_E_INVAL, "an image shift exceeds +-127 cells (atoms far outside the cell)");
@@ -853,6 +854,7 @@ namespace {
 constexpr double EV_A_AMU = 1.602176634e-19 / 1e-10 / 1.66053906660e-27 * 1e-20;
 
 void throw_nbr_flags(const int32_t *f, int max_nbrs) {
+    MTP_CHECK(!(f[3] & 16), MTP_E_INVAL, "a position is not finite (NaN or Inf)");
     MTP_CHECK(!(f[3] & 1), MTP_E_INVAL, "a cell matrix is singular");
     MTP_CHECK(!(f[3] & 8), MTP_E_INVAL, "an atom type is outside 0..n_types-1");
     MTP_CHECK(!(f[3] & 2), MTP_E_INVAL, "an image shift exceeds +-127 cells (atoms far outside the cell)");

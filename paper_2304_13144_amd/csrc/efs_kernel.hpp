@@ -24,7 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_util.hpp"
-#include "internal.hpp"
+#include "kernel_args.hpp"
 
 namespace mtp {
 
@@ -608,7 +608,7 @@ __device__ inline void efs_rows_body(const EfsArgs &a, int64_t blk, T (&s_dm)[Le
     const int nt = a.n_types;
     const int sub = threadIdx.x % K;
     const AtomCtx c = atom_ctx<K>(a, blk);
-    const bool full_rows = a.grade_mode == MTP_GRADE_FULL;
+    const bool full_rows = a.grade_mode == GRADE_FULL;
     if (full_rows) {
         // the kept columns of the c part, once per block in LDS: read from
         // global memory beside the row stores, each would wait for the store

@@ -365,18 +365,33 @@ __global__ __launch_bounds__(512) void grade_i8(const double *__restrict__ brow,
     };
     fetch(half);
     // the two halves' wavefronts of a row group cut it together: k steps
-    // s = half, half + 2, ...; first the row's largest |b_k D_k| (D_k = 0 past
-    // m; the rows have ldb >= 64 KS columns, zero past m), four k at a time
-    double mx = 0.0;
-    for (int s = half; s < KS; s += 2)
+    // s = half, half + 2, ...  All of this wavefront's values of b D are
+    // loaded in one batch (one memory latency, not one per group of loads);
+    // the rows have ldb >= 64 KS columns, zero past m, and D_k = 0 past m
+    constexpr int NH = (KS + 1) / 2;   // k steps per half (the second half has one less for odd KS)
+    double x[NH][16];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k0 = 64 * s + 16 * lk + 4 * q;
-            const double *p = bp + (int64_t)k0 * ldn;
-            const double4 d = *reinterpret_cast<const double4 *>(dsc + k0);
-            mx = fmax(mx, fmax(fmax(fabs(p[0] * d.x), fabs(p[ldn] * d.y)), fmax(fabs(p[2 * ldn] * d.z),
-                                                                                 fabs(p[3 * ldn] * d.w))));
+    for (int i = 0; i < NH; ++i) {
+        const int s = half + 2 * i;
+        const int k0 = 64 * (s < KS ? s : KS - 1) + 16 * lk;   // a step past KS: read again, not used
+        const double *p = bp + (int64_t)k0 * ldn;
+#pragma unroll
+        for (int j = 0; j < 16; j += 4) {
+            const double4 d = *reinterpret_cast<const double4 *>(dsc + k0 + j);
+            x[i][j] = p[(int64_t)j * ldn] * d.x;
+            x[i][j + 1] = p[(int64_t)(j + 1) * ldn] * d.y;
+            x[i][j + 2] = p[(int64_t)(j + 2) * ldn] * d.z;
+            x[i][j + 3] = p[(int64_t)(j + 3) * ldn] * d.w;
         }
+    }
+    // the row's largest |b_k D_k|: this wavefront's steps, the four lanes of the
+    // row, then the two halves
+    double mx = 0.0;
+#pragma unroll
+    for (int i = 0; i < NH; ++i)
+        if (half + 2 * i < KS)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) mx = fmax(mx, fabs(x[i][j]));
     mx = fmax(mx, __shfl_xor(mx, 16, 64));
     mx = fmax(mx, __shfl_xor(mx, 32, 64));
     if (lane < 16) s_mx[half][rg * 16 + lane] = mx;
@@ -386,28 +401,28 @@ __global__ __launch_bounds__(512) void grade_i8(const double *__restrict__ brow,
     (void)frexp(mx, &erow);   // mx = f 2^erow, f in [0.5, 1); 0 for a zero row
     const double sc = ldexp(1.0, 6 - erow);
     // digits of this wavefront's k steps into LDS, one register per slice for each four k
-    for (int s = half; s < KS; s += 2)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k0 = 64 * s + 16 * lk + 4 * q;
-            const double *p = bp + (int64_t)k0 * ldn;
-            const double4 dd = *reinterpret_cast<const double4 *>(dsc + k0);
-            const double x[4] = {p[0] * dd.x, p[ldn] * dd.y, p[2 * ldn] * dd.z, p[3 * ldn] * dd.w};
-            unsigned w[GI_SL] = {0u, 0u, 0u, 0u, 0u};
+    for (int i = 0; i < NH; ++i) {
+        const int s = half + 2 * i;
+        if (s < KS)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                double r = x[j] * sc;   // |r| < 64, exact
+            for (int q = 0; q < 4; ++q) {
+                unsigned w[GI_SL] = {0u, 0u, 0u, 0u, 0u};
 #pragma unroll
-                for (int t = 0; t < GI_SL; ++t) {
-                    const double d = rint(r);
-                    r = (r - d) * 128.0;
-                    w[t] |= ((unsigned)(int)d & 0xffu) << (8 * j);
+                for (int j = 0; j < 4; ++j) {
+                    double r = x[i][4 * q + j] * sc;   // |r| < 64, exact
+#pragma unroll
+                    for (int t = 0; t < GI_SL; ++t) {
+                        const double d = rint(r);
+                        r = (r - d) * 128.0;
+                        w[t] |= ((unsigned)(int)d & 0xffu) << (8 * j);
+                    }
                 }
-            }
-            int *dig = reinterpret_cast<int *>(sm + ((rg * KS + s) * GI_SL) * 64 + lane) + q;
+                int *dig = reinterpret_cast<int *>(sm + ((rg * KS + s) * GI_SL) * 64 + lane) + q;
 #pragma unroll
-            for (int t = 0; t < GI_SL; ++t) dig[t * 64 * 4] = (int)w[t];
-        }
+                for (int t = 0; t < GI_SL; ++t) dig[t * 64 * 4] = (int)w[t];
+            }
+    }
     __syncthreads();
     i32x4 A[GI_SL][KS];
 #pragma unroll

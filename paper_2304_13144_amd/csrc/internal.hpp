@@ -9,6 +9,7 @@
 
 #include "../../include/mtp.h"
 #include "basis.hpp"
+#include "kernel_args.hpp"
 
 namespace mtp {
 
@@ -44,8 +45,6 @@ struct DevBuf {
 
 void launch_zero(void *p, size_t bytes, hipStream_t st);
 
-constexpr int NPOLY = 8;     // Chebyshev polynomials per radial function
-constexpr int MAX_TYPES = 4;
 
 struct ActiveSet {
     int m = 0;
@@ -60,6 +59,9 @@ struct ActiveSet {
     DevBuf lane64;
     int NK64 = 0;
 };
+
+// the kernels' copies of the ABI's enum values
+static_assert(GRADE_FULL == MTP_GRADE_FULL && PREC_FP64 == MTP_FP64, "enum values");
 
 }  // namespace mtp
 
@@ -111,63 +113,14 @@ struct mtp_nbrs {
 
 namespace mtp {
 
-// ---- launchers ------------------------------------------------------------
-struct EfsArgs {
-    int64_t n_atoms;          // atoms processed (= list length if atom_list)
-    const int32_t *atom_list; // optional: process these atoms
-    int n_types, max_nbrs;
-    const double *r;          // pair vectors
-    const int32_t *tcnt;
-    const int32_t *type;
-    double r_min, r_cut;
-    const double *th64;       // theta = [xi_0 | xi_alpha | c] in FP64
-    const float *th32;        // and rounded to FP32
-    int n_lin;
-    // outputs (nullable)
-    double *site_e;           // [n_atoms]
-    void *gbuf;               // [N*maxn*3] T  (pair gradients dV_i/dr_ij)
-    double *virial;           // [n_atoms*9]
-    double *brow;             // rows b_i, FP64, column-major: entry (i, k) at brow[k * ldn + i]
-    int64_t ldn;              // column stride of brow (>= n_atoms)
-    int ldb;                  // columns written: m, then zeros up to ldb
-    int grade_mode;           // rows layout: FULL (with colmap) or LINEAR
-    const int32_t *colmap;    // full column -> kept column or -1
-    int m;                    // row length written (kept columns)
-    int precision;
-    int lanes;                // lanes per neighborhood of the pair-gradient / row kernel (2, 4, 8)
-    int lanes_mc;             // lanes per neighborhood of the moments / contraction (2, 4, 8; 4 = one launch)
-    void *mbuf, *dmbuf;       // [NC][n_atoms] T: moments and dV/dM between the kernels
-    // optional (atom_list NULL only): the pair-gradient blocks also write the
-    // per-32-atom partial sums of part_e (V_i, nullable) and virial into part
-    double *part;
-    const double *part_e;
-    hipStream_t stream;
-};
+// ---- launchers (argument blocks in kernel_args.hpp) ------------------------
 int launch_efs(int level, const EfsArgs &a);
 
-struct BwdArgs {
-    EfsArgs e;                // neighbors, parameters, mbuf (moments), dmbuf (dV/dM)
-    const double *gE, *gF, *gS;
-    const int32_t *atom_cfg;
-    const int32_t *nbr_j;
-    void *tbuf, *dtbuf;       // [NC][n] tangent moments and H Mdot
-    void *rows;               // [n][n_theta] T: per-neighborhood gradient contributions
-    int n_theta;
-};
 int launch_backward(int level, const BwdArgs &b);
 void launch_column_sums(const void *rows, int precision, int64_t n, int ncol, double *out, hipStream_t st,
                         DevBuf &work);
 std::vector<int> compiled_levels();
 long contraction_flops(int level);   // per neighborhood, from the generated program
-
-// Optional timing of library kernels with HIP events (see mtp_profile_enable).
-void prof_mark(const char *name, bool begin, hipStream_t st);
-struct ProfScope {
-    const char *name;
-    hipStream_t st;
-    ProfScope(const char *n, hipStream_t s) : name(n), st(s) { prof_mark(name, true, st); }
-    ~ProfScope() { prof_mark(name, false, st); }
-};
 
 void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_nbrs *nb, hipStream_t st);
 

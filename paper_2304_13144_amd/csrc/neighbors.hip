@@ -92,8 +92,12 @@ __global__ void nbr_prepare(int n_cfg, const int64_t *cfg_off, const double *cel
     flags[4] = (int)off;   // bins in use (<= the host-side capacity n_atoms + n_cfg)
 }
 
+// A position that is not finite (NaN, Inf) sets bit 16 of flags[3] and is
+// binned at the origin of its cell (it then fails every distance test): the
+// status check reports MTP_E_INVAL instead of an empty neighborhood.
 __global__ void bin_kernel(int64_t n, int n_cfg, const int64_t *cfg_off, const double *pos, const CfgGeo *geo,
-                           int32_t *atom_cfg, int32_t *atom_bin, int32_t *atom_wrap, int32_t *bin_count) {
+                           int32_t *atom_cfg, int32_t *atom_bin, int32_t *atom_wrap, int32_t *bin_count,
+                           int32_t *flags) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     // configuration of atom i: last c with cfg_off[c] <= i
@@ -104,6 +108,10 @@ __global__ void bin_kernel(int64_t n, int n_cfg, const int64_t *cfg_off, const d
     }
     const CfgGeo &g = geo[lo];
     double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+    if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) {
+        atomicOr(&flags[3], 16);
+        x[0] = x[1] = x[2] = 0.0;
+    }
     int b[3], w[3];
     for (int k = 0; k < 3; ++k) {
         double s = x[0] * g.Hi[k] + x[1] * g.Hi[3 + k] + x[2] * g.Hi[6 + k];
@@ -870,7 +878,7 @@ void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_
     const dim3 ga((unsigned)((n + TB - 1) / TB));
     hipLaunchKernelGGL(bin_kernel, ga, dim3(TB), 0, st, n, s->n_cfg, s->cfg_off, s->pos, geo,
                        nb->atom_cfg.as<int32_t>(), nb->atom_bin.as<int32_t>(), nb->atom_wrap.as<int32_t>(),
-                       nb->bin_count.as<int32_t>());
+                       nb->bin_count.as<int32_t>(), flags);
     hipLaunchKernelGGL(scan_bins, dim3(1), dim3(SCAN_T), 0, st, nb->bin_count.as<int32_t>(),
                        nb->bin_start.as<int32_t>(), flags + 4);
     const BinStart bstart{nb->bin_start.as<int32_t>()};

@@ -83,3 +83,78 @@ def test_backward_parts_energy_only_equals_sum_of_rows():
         rows.append(om.b_rows(pot, theta_s, c.pos, c.types, c.cell, pairs))
     want = np.concatenate(rows).sum(axis=0)
     assert rel_err(g, want) <= 1e-10
+
+
+def test_backward_uses_the_theta_of_its_own_forward():
+    """Two forwards at different theta, then the backward of the first: the
+    gradient is the first theta's (the model is loaded with it again), equal
+    to a single forward + backward at that theta."""
+    pot, cfgs, theta_t, theta_s = _case(8, 2, 3, seed=81)
+    m = api.Model.create(8, 2, pot.r_min, pot.r_cut)
+    b = api.Batch(cfgs)
+    m.set_params(theta_s)
+    nb = api.Neighbors().build(m, b, max_nbrs=128)
+
+    def loss_of(E, F, S):
+        return (E ** 2).sum() + W_F * (F ** 2).sum() + W_S * (S ** 2).sum()
+
+    t1 = torch.tensor(theta_s, dtype=torch.float64, device="cuda", requires_grad=True)
+    ref = loss_of(*api.MTPEnergy.apply(t1, m, b, nb, "fp64"))
+    ref.backward()
+    want = t1.grad.clone()
+    t1.grad = None
+    l1 = loss_of(*api.MTPEnergy.apply(t1, m, b, nb, "fp64"))
+    t2 = torch.tensor(theta_t, dtype=torch.float64, device="cuda", requires_grad=True)
+    l2 = loss_of(*api.MTPEnergy.apply(t2, m, b, nb, "fp64"))
+    l1.backward()
+    assert torch.equal(t1.grad, want)
+    l2.backward()
+    assert not torch.equal(t2.grad, want)
+    # a rebuild between forward and backward is refused
+    l3 = loss_of(*api.MTPEnergy.apply(t1, m, b, nb, "fp64"))
+    nb.build(m, b, max_nbrs=128)
+    with pytest.raises(RuntimeError):
+        l3.backward()
+
+
+@pytest.mark.skipif(20 not in api.compiled_levels(), reason="level 20 not compiled into libmtp.so")
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_training_batch_gradient_on_sampled_configs(precision):
+    """The level-20 training batch at full size (512 configurations of 8-256
+    atoms, 3 species), in the launch configuration the benchmark times: the
+    loss holds terms of six sampled configurations only (the upstream
+    gradients of the others are zero), so the oracle computes it on those six."""
+    w = synth.workload3()
+    pot = om.Potential(w.level, w.n_types, w.r_min, w.r_cut)
+    theta_t = synth.theta_teacher(3, w.n_types, pot.n_lin, pot.n_rad)
+    theta_s = theta_t * (1.0 + 0.05 * np.random.default_rng(3).normal(size=theta_t.shape))
+    pick = np.sort(np.random.default_rng(5).choice(len(w.configs), 6, replace=False))
+    sub = [w.configs[k] for k in pick]
+    targets, geo = _oracle_targets(pot, sub, theta_t)
+    L_or, g_or = om.loss_and_grad(pot, theta_s, geo, targets, W_E, W_F, W_S)
+    m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
+    m.set_params(theta_s)
+    b = api.Batch(w.configs)
+    nb = api.Neighbors().build(m, b, max_nbrs=96)
+    theta = torch.tensor(theta_s, dtype=torch.float64, device="cuda", requires_grad=True)
+    E, F, S = api.MTPEnergy.apply(theta, m, b, nb, precision)
+    off = b.cfg_off_host
+    mask_c = torch.zeros(len(w.configs), dtype=torch.float64, device="cuda")
+    mask_c[torch.as_tensor(pick)] = 1.0
+    mask_a = torch.zeros(b.n_atoms, dtype=torch.float64, device="cuda")
+    Et = torch.zeros(len(w.configs), dtype=torch.float64, device="cuda")
+    Ft = torch.zeros((b.n_atoms, 3), dtype=torch.float64, device="cuda")
+    St = torch.zeros((len(w.configs), 3, 3), dtype=torch.float64, device="cuda")
+    for k, t in zip(pick, targets):
+        mask_a[off[k]:off[k + 1]] = 1.0
+        Et[k] = t[0]
+        Ft[off[k]:off[k + 1]] = torch.as_tensor(t[1])
+        St[k] = torch.as_tensor(t[2])
+    loss = (W_E * (mask_c * (E - Et) ** 2).sum() + W_F * (mask_a[:, None] * (F - Ft) ** 2).sum()
+            + W_S * (mask_c[:, None, None] * (S - St) ** 2).sum())
+    loss.backward()
+    g = theta.grad.cpu().numpy()
+    err = rel_err(g, g_or)
+    print(f"{precision}: configurations {list(pick)}, loss gpu {loss.item():.6g} oracle {L_or:.6g}, grad rel err {err:.3g}")
+    assert abs(loss.item() - L_or) <= (1e-10 if precision == "fp64" else 1e-4) * abs(L_or)
+    assert err <= (1e-9 if precision == "fp64" else 1e-3)

@@ -3,8 +3,9 @@
 * a batch of uneven configurations in one launch equals per-configuration runs;
 * a captured step replayed several times, with eager work in between, equals
   the eager step every time (bitwise in FP64);
-* the autotuner's choice gives bitwise the same FP64 results as every other
-  schedule."""
+* the autotuner's choice agrees with every other schedule to rounding (the
+  lanes change the summation order of the moments);
+* a checked replay raises when its neighbor build overflows."""
 import numpy as np
 import pytest
 import torch
@@ -72,7 +73,7 @@ def test_graph_replay_equals_eager(precision):
         assert np.isfinite(other["gamma"]).all()
 
 
-def test_autotuner_choice_is_bitwise_equivalent():
+def test_autotuner_choice_agrees_to_rounding():
     m = _model16()
     b = api.Batch([synth.workload2(reps=(8, 8, 8)).configs[0]])
     nb = api.Neighbors().build(m, b, max_nbrs=64)
@@ -89,3 +90,23 @@ def test_autotuner_choice_is_bitwise_equivalent():
         # lanes change the summation tree of the moments: equal to rounding
         assert np.allclose(other["forces"], tuned["forces"], rtol=0, atol=1e-10 * np.abs(tuned["forces"]).max())
         assert np.allclose(other["gamma"], tuned["gamma"], rtol=1e-9)
+
+
+def test_graph_replay_reports_neighbor_overflow_after_atoms_move():
+    """The captured step rebuilds the lists on every replay; when the atoms of
+    the captured positions are squeezed so that a neighborhood exceeds
+    max_nbrs, the replay raises MTP_E_CAPACITY (the build's status words are
+    read after every checked replay)."""
+    m = _model16()
+    cfg = synth.workload2(reps=(4, 4, 4)).configs[0]
+    b = api.Batch([cfg])
+    nb = api.Neighbors().build(m, b, max_nbrs=48)
+    step = api.CapturedStep(m, b, nb, "fp64", "full", max_nbrs=48)
+    step.replay()                              # 28-38 neighbors: fine
+    with torch.no_grad():
+        b.pos.mul_(0.8)                        # positions move in place (same buffer as captured)
+        b.cells.mul_(0.8)
+    torch.cuda.synchronize()
+    with pytest.raises(api.MtpError) as e:
+        step.replay()
+    assert e.value.status == "MTP_E_CAPACITY"

@@ -113,3 +113,18 @@ def test_preselecting_evaluation_equals_plain(name):
     for k in ("energy", "forces", "stress", "site_e", "gamma", "argmax"):
         assert torch.equal(plain[k], fused[k]), k
     assert int(fused["sel_count"].item()) == int((plain["gamma"] > 0.5).sum().item())
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_non_finite_position_is_reported(bad):
+    """A NaN or Inf coordinate is flagged by the neighbor build (MTP_E_INVAL),
+    not turned into an empty neighborhood."""
+    w = synth.workload1()
+    cfg = w.configs[0]
+    pos = cfg.pos.copy()
+    pos[17, 1] = bad
+    m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
+    b = api.Batch([synth.Config(pos, cfg.types, cfg.cell)])
+    with pytest.raises(api.MtpError) as e:
+        api.Neighbors().build(m, b, max_nbrs=64)
+    assert e.value.status == "MTP_E_INVAL" and "finite" in str(e.value)
