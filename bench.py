@@ -42,7 +42,7 @@ TRAFFIC_KERNELS = ("efs_moments_contract<double, 16, true>", "efs_moments_contra
                    "efs_moments<double, 16, 8>", "efs_contract<double, 16, true>",
                    "efs_forces_rows<double, double, 16, 4>", "efs_forces_rows<double, double, 16, 8>",
                    "efs_forces_rows<float, double, 16, 4>", "efs_forces_rows<float, double, 16, 8>",
-                   "grade_f64", "grade_i8<4>", "pair_search<false, 2>", "reverse_pairs")
+                   "grade_f64<", "grade_f64_wide<", "grade_i8<4>", "pair_search<false, 2>", "reverse_pairs")
 
 
 def log(msg):
@@ -196,9 +196,9 @@ def main():
     count, _, _ = nbrs.export(batch)
     pairs_per_atom = float(count.double().mean().item())
     outs = {p: api.evaluate(model, batch, nbrs, p, "full", gamma_save=2.0) for p in ("fp64", "mixed")}
-    tuned = {p: api.tune(model, batch, nbrs, p, "full") for p in ("fp64", "mixed")}
+    tuned = {p: api.tune(model, batch, nbrs, p, "full", with_grade=True) for p in ("fp64", "mixed")}
     torch.cuda.synchronize()
-    log(f"[bench] autotuned lanes per neighborhood: {tuned}")
+    log(f"[bench] autotuned (moments lanes, pair-gradient lanes, grade form): {tuned}")
     if a.copy_calibration:
         src = torch.ones(256 * 1024 * 1024 // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -217,16 +217,20 @@ def main():
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
 
-    def timed(fn):
-        for _ in range(a.warmup):
+    def timed(fn, per_call=1):
+        """ms per step of fn, which runs per_call steps: a.steps steps timed."""
+        for _ in range(max(1, a.warmup // per_call)):
             fn()
         torch.cuda.synchronize()
         t0.record()
-        for _ in range(a.steps):
+        for _ in range(a.steps // per_call):
             fn()
         t1.record()
         torch.cuda.synchronize()
         return t0.elapsed_time(t1) / a.steps
+
+    # passes per graph replay: the largest divisor of the step count up to 10
+    passes = max(d for d in range(1, 11) if a.steps % d == 0)
 
     results = {}
     for prec in ("fp64", "mixed"):
@@ -246,20 +250,33 @@ def main():
         # plain eager and HIP-graph replays: evaluation alone and with the rebuild
         eager_eval = timed(lambda: eval_step(prec))
         eager_full = timed(lambda: full_step(prec))
+        # one pass per replay, and `passes` passes per replay (the K timed steps
+        # are K / passes replays); status words of the rebuilds checked after timing
         cap_eval = api.CapturedStep(model, batch, nbrs, prec, "full", max_nbrs=64, rebuild=False)
         graph_eval = timed(cap_eval.replay)
+        capk_eval = api.CapturedStep(model, batch, nbrs, prec, "full", max_nbrs=64, rebuild=False,
+                                     passes=passes)
+        graphk_eval = timed(lambda: capk_eval.replay(check=False), passes)
         cap_full = api.CapturedStep(model, batch, nbrs, prec, "full", max_nbrs=64, rebuild=True)
-        graph_full = timed(cap_full.replay)
-        outs[prec] = {k: v.clone() for k, v in cap_full.out.items()}
-        ms_eval, ms_full = min(eager_eval, graph_eval), min(eager_full, graph_full)
+        graph_full = timed(lambda: cap_full.replay(check=False))
+        cap_full.status()
+        capk_full = api.CapturedStep(model, batch, nbrs, prec, "full", max_nbrs=64, rebuild=True, passes=passes)
+        graphk_full = timed(lambda: capk_full.replay(check=False), passes)
+        capk_full.status()
+        outs[prec] = {k: v.clone() for k, v in capk_full.out.items()}
+        ms_eval = min(eager_eval, graph_eval, graphk_eval)
+        ms_full = min(eager_full, graph_full, graphk_full)
         results[prec] = {"ms_per_step": ms_eval, "atom_steps_per_s": cfg.n / (ms_eval * 1e-3),
                          "with_rebuild_ms_per_step": ms_full,
                          "with_rebuild_atom_steps_per_s": cfg.n / (ms_full * 1e-3),
                          "eager_ms_per_step": eager_eval, "graph_ms_per_step": graph_eval,
+                         "graph_passes": passes, "graph_multi_pass_ms_per_step": graphk_eval,
                          "eager_with_rebuild_ms": eager_full, "graph_with_rebuild_ms": graph_full,
+                         "graph_multi_pass_with_rebuild_ms": graphk_full,
                          "profiled_with_rebuild_ms": prof_ms, "kernels": kern}
         log(f"[bench] {prec}: evaluation {ms_eval:.4f} ms/step ({cfg.n / (ms_eval * 1e-3):.4g} atom-steps/s; "
-            f"eager {eager_eval:.4f}, graph {graph_eval:.4f}); with neighbor rebuild {ms_full:.4f} ms/step "
+            f"eager {eager_eval:.4f}, graph {graph_eval:.4f}, graph x{passes} {graphk_eval:.4f}); "
+            f"with neighbor rebuild {ms_full:.4f} ms/step "
             f"({cfg.n / (ms_full * 1e-3):.4g}); kernels (us): "
             + ", ".join(f"{k} {v['avg_us']:.1f}" for k, v in kern.items()))
 
@@ -284,11 +301,13 @@ def main():
         per_kernel[k] = {"avg_us": us, "flops_per_atom": f, "bound": "alu", "peak_tflops": PEAK_VALU_TFLOPS,
                          "tflops": f * cfg.n / max(us * 1e-6, 1e-12) / 1e12}
     # grade: 2 m^2 FP64 flops per row, or 19 int8 digit products of 2 m^2 ops each
-    gf = 2.0 * m * m * (1 if prec == "fp64" else GRADE_I8_PRODUCTS)
+    gform = tuned[prec][2]
+    i8 = gform == "int8-slices"
+    gf = 2.0 * m * m * (GRADE_I8_PRODUCTS if i8 else 1)
     gus = r["kernels"]["grade"]["avg_us"]
-    per_kernel["grade"] = {"avg_us": gus, "flops_per_atom": gf, "bound": "mfma",
-                           "peak_tflops": PEAK_MFMA_F64_TFLOPS if prec == "fp64" else PEAK_MFMA_I8_TOPS,
-                           "unit": "TFLOP/s" if prec == "fp64" else "TOP/s (int8)",
+    per_kernel["grade"] = {"avg_us": gus, "flops_per_atom": gf, "bound": "mfma", "form": gform,
+                           "peak_tflops": PEAK_MFMA_I8_TOPS if i8 else PEAK_MFMA_F64_TFLOPS,
+                           "unit": "TOP/s (int8)" if i8 else "TFLOP/s",
                            "tflops": gf * cfg.n / max(gus * 1e-6, 1e-12) / 1e12}
     dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"])
     d = per_kernel[dom]
@@ -299,7 +318,8 @@ def main():
                     "efs_contract": f"efs_contract<double, {level}, true>",
                     "efs_forces": f"efs_forces_rows<{'double' if prec == 'fp64' else 'float'}, double, {level}, "
                                   f"{tuned[prec][1]}>",
-                    "grade": "grade_f64" if prec == "fp64" else f"grade_i8<{(m + 63) // 64}>"}[dom]
+                    "grade": {"int8-slices": f"grade_i8<{(m + 63) // 64}>", "fp64-registers": "grade_f64<",
+                              "fp64-lds": "grade_f64_wide<"}[gform]}[dom]
     traffic = recorded_traffic(rocprof_name)
     out = {
         "metric": "atom-steps/s (E+F+stress+grade), level-16 MTP",
@@ -309,7 +329,9 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": r["ms_per_step"],
-        "launch": "hip-graph replay" if r["graph_ms_per_step"] <= r["eager_ms_per_step"] else "eager",
+        "launch": {r["eager_ms_per_step"]: "eager", r["graph_ms_per_step"]: "hip-graph replay, one pass",
+                   r["graph_multi_pass_ms_per_step"]: f"hip-graph replay, {r['graph_passes']} passes per replay"}[
+                       r["ms_per_step"]],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -320,7 +342,8 @@ def main():
                    "pairs_per_atom": pairs_per_atom,
                    "step": "evaluate(E, F, S, site energies, b rows, gamma, argmax) + preselection gamma > 2 (fused) "
                            "on a built neighbor list",
-                   "lanes_per_neighborhood": {"moments_contraction": tuned[prec][0], "pair_gradients": tuned[prec][1]}},
+                   "lanes_per_neighborhood": {"moments_contraction": tuned[prec][0], "pair_gradients": tuned[prec][1]},
+                   "grade_form": tuned[prec][2]},
         "with_rebuild": {"atom_steps_per_s": r["with_rebuild_atom_steps_per_s"],
                          "ms_per_step": r["with_rebuild_ms_per_step"],
                          "neighbor_build_us": r["kernels"]["neighbors"]["avg_us"]},

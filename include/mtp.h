@@ -369,9 +369,16 @@ int mtp_profile_read(const char *kernel, double *total_ms /* host */, int64_t *l
  * schedule, each schedule's minimum), keeps the fastest for this model,
  * precision and size class (floor(log2 n_atoms)) and returns it in *lanes
  * (host) as 16 x (moments / contraction lanes) + (pair-gradient lanes).
- * Synchronises `stream`. */
+ * Then, when the grade mode has an active set, it times the kernel forms of
+ * the grade product the same way under the chosen lanes -- 1: FP64 MFMA with
+ * each wavefront's rows in registers (m <= 288); 2: FP64 MFMA with the rows
+ * staged through LDS (any m); 3: the int8 slice product (MTP_MIXED, m <=
+ * 320) -- keeps the fastest for this model, precision, grade mode and size
+ * class and returns it in *grade (host, nullable; 0 when no grade was
+ * timed).  Every form meets the precision's error bound; they differ in
+ * speed only.  Synchronises `stream`. */
 int mtp_tune(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
-             int32_t *lanes /* host */, void *stream);
+             int32_t *lanes /* host */, int32_t *grade /* host, nullable */, void *stream);
 
 /* Description of the basis of a level, one function per line (host). */
 int mtp_basis_describe(int32_t level, char *buf, size_t len, int32_t *n_lin);

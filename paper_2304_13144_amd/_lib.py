@@ -100,7 +100,8 @@ def lib():
         "mtp_basis_describe": [I32, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(I32)],
         "mtp_compiled_levels": [ctypes.POINTER(I32), I32],
         "mtp_profile_enable": [ctypes.c_int],
-        "mtp_tune": [P, ctypes.POINTER(System), P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(I32), P],
+        "mtp_tune": [P, ctypes.POINTER(System), P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(I32),
+                     ctypes.POINTER(I32), P],
         "mtp_profile_read": [ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I64)],
     }
     for name, args in sig.items():

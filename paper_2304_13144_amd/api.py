@@ -446,13 +446,21 @@ class MTPEnergy(torch.autograd.Function):
         return g, None, None, None, None
 
 
-def tune(model, batch, nbrs, precision="fp64", mode="full"):
+GRADE_FORMS = {0: "none", 1: "fp64-registers", 2: "fp64-lds", 3: "int8-slices"}
+
+
+def tune(model, batch, nbrs, precision="fp64", mode="full", with_grade=False):
     """Runs the library's autotuner for this system; returns the chosen lanes
-    per neighborhood as (moments / contraction, pair gradients)."""
+    per neighborhood as (moments / contraction, pair gradients), and with
+    `with_grade` also the chosen kernel form of the grade product (a name
+    from GRADE_FORMS; "none" when the mode has no active set)."""
     lanes = ctypes.c_int32()
+    grade = ctypes.c_int32()
     s = batch.system()
     check(_lib.lib().mtp_tune(model._h, ctypes.byref(s), nbrs._h, _prec(precision), _mode(mode), ctypes.byref(lanes),
-                              _stream()))
+                              ctypes.byref(grade), _stream()))
+    if with_grade:
+        return lanes.value >> 4, lanes.value & 15, GRADE_FORMS[grade.value]
     return lanes.value >> 4, lanes.value & 15
 
 
@@ -478,21 +486,31 @@ class CapturedStep:
     """One hot-path step (neighbor build if `rebuild`, fused evaluation,
     preselection) captured once in a HIP graph and replayed.
 
+    `passes` > 1 captures that many passes of the step, one after the other,
+    in the same graph: every replay then runs the step `passes` times over
+    the same inputs (each pass rebuilds and re-evaluates in full).  A graph
+    replay has a fixed start-up cost of its own, which several passes per
+    replay share.
+
     The step must have run eagerly at least once at the same sizes so that
     every library workspace exists (nothing is allocated during capture).
-    Outputs live in `self.out` and are overwritten by every replay."""
+    Outputs live in `self.out` and are overwritten by every pass."""
 
     def __init__(self, model, batch, nbrs, precision="fp64", mode="full", max_nbrs=64, gamma_save=2.0,
-                 rebuild=True):
+                 rebuild=True, passes=1):
+        if passes < 1:
+            raise ValueError("passes must be at least 1")
         self.model, self.batch, self.nbrs = model, batch, nbrs
         self.args = (precision, mode, max_nbrs, gamma_save)
         self.rebuild = rebuild
+        self.passes = passes
         self.out = evaluate(model, batch, nbrs, precision, mode, gamma_save=gamma_save)
         self._step()                      # eager warm-up: workspaces at their final size
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            self._step()
+            for _ in range(passes):
+                self._step()
         torch.cuda.synchronize()
 
     def _step(self):

@@ -186,6 +186,17 @@ int lanes_for(const mtp_model *m, int64_t n, int prec) {
     return 17 * 8;
 }
 
+// grade schedule: the tuner's choice for this size class, else GRADE_AUTO
+int grade_sched_for(const mtp_model *m, int64_t n, int prec, int mode) {
+    if (m->force_grade) return m->force_grade;
+    if (const char *e = std::getenv("MTP_GRADE_FORM")) {   // 1, 2 or 3 (GRADE_*), where available
+        const int v = std::atoi(e);
+        if (v >= GRADE_F64_REG && v <= GRADE_I8 && grade_sched_valid(m->act[mode & 1], prec, v)) return v;
+    }
+    const int t = m->tuned_grade[prec == MTP_FP64 ? 0 : 1][mode & 1][size_bucket(n)];
+    return t && grade_sched_valid(m->act[mode & 1], prec, t) ? t : GRADE_AUTO;
+}
+
 struct EvalOut {
     double *energy = nullptr, *forces = nullptr, *stress = nullptr, *site_e = nullptr;
     double *gamma = nullptr;
@@ -318,13 +329,14 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     if (want_grade) {
         double *gam = o.gamma ? o.gamma : static_cast<double *>(ws.get(m->gamma_ws, sizeof(double) * n));
         int32_t *blk = nullptr;
-        const int count_rows = grade_count_rows(m->act[o.mode], prec);
+        const int count_rows = GRADE_ROWS;
         if (want_sel)
             blk = static_cast<int32_t *>(
                 ws.get(m->selblk, sizeof(int32_t) * (size_t)((n + count_rows - 1) / count_rows + 1)));
         {
             ProfScope ps("grade", st);
-            launch_grade(m->act[o.mode], prec, brow, ldb, n, n, gam, o.argmax, st, o.sel_thr, blk);
+            launch_grade(m->act[o.mode], prec, brow, ldb, n, n, gam, o.argmax, st, o.sel_thr, blk,
+                         grade_sched_for(m, n, prec, o.mode));
         }
         if (want_sel) {
             ProfScope ps("select", st);
@@ -1268,7 +1280,7 @@ int mtp_efs_backward(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb
 }
 
 int mtp_tune(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
-             int32_t *lanes_out, void *stream) {
+             int32_t *lanes_out, int32_t *grade_out, void *stream) {
     API_BEGIN
     MTP_CHECK(m && lanes_out, MTP_E_INVAL, "NULL argument");
     check_system(m, s);
@@ -1326,10 +1338,47 @@ int mtp_tune(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precisio
         throw;
     }
     m->force_lanes = 0;
+    m->tuned_lanes[p == MTP_FP64 ? 0 : 1][size_bucket(n)] = best;
+    // the grade's kernel form, timed the same way under the chosen lanes
+    int gbest = GRADE_AUTO;
+    if (o.gamma) {
+        std::vector<int> cand;
+        for (int sc : {GRADE_F64_REG, GRADE_F64_LDS, GRADE_I8})
+            if (grade_sched_valid(m->act[g], p, sc)) cand.push_back(sc);
+        std::vector<float> gmin(cand.size());
+        try {
+            for (int sc : cand) {
+                m->force_grade = sc;
+                evaluate(m, s, nb, p, o, st);
+            }
+            for (int rd = 0; rd < ROUNDS; ++rd)
+                for (size_t k = 0; k < cand.size(); ++k) {
+                    m->force_grade = cand[k];
+                    MTP_HIP(hipEventRecord(e0, st));
+                    for (int r = 0; r < REPS; ++r) evaluate(m, s, nb, p, o, st);
+                    MTP_HIP(hipEventRecord(e1, st));
+                    MTP_HIP(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    MTP_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    gmin[k] = rd == 0 ? ms : std::min(gmin[k], ms);
+                }
+        } catch (...) {
+            m->force_grade = 0;
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            throw;
+        }
+        m->force_grade = 0;
+        size_t kb = 0;
+        for (size_t k = 1; k < cand.size(); ++k)
+            if (gmin[k] < gmin[kb]) kb = k;
+        gbest = cand[kb];
+        m->tuned_grade[p == MTP_FP64 ? 0 : 1][g][size_bucket(n)] = gbest;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    m->tuned_lanes[p == MTP_FP64 ? 0 : 1][size_bucket(n)] = best;
     *lanes_out = best;
+    if (grade_out) *grade_out = gbest;
     API_END
 }
 

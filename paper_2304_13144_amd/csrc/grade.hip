@@ -551,67 +551,71 @@ __global__ __launch_bounds__(256) void i8_slice_ainv(const double *Ainv, int m, 
     }
 }
 
-// ---- Gauss-Jordan inverse (one block) ----------------------------------------
-constexpr int GJ_T = 1024;
-__global__ __launch_bounds__(GJ_T) void gauss_jordan(double *W, int m, int32_t *singular) {
-    // W is m x 2m: [A | I] -> [I | A^-1]
-    __shared__ double sv[GJ_T];
-    __shared__ int si[GJ_T];
-    __shared__ int piv;
-    const int n2 = 2 * m;
-    for (int c = 0; c < m; ++c) {
-        double bv = -1.0;
-        int bi = m;
-        for (int r = c + threadIdx.x; r < m; r += GJ_T) {
-            const double v = fabs(W[(int64_t)r * n2 + c]);
-            if (v > bv) {
-                bv = v;
-                bi = r;
-            }
+// ---- Gauss-Jordan inverse ---------------------------------------------------
+// W = [A | I] (m x 2m, row-major) becomes [I | A^-1] by m elimination steps
+// with partial pivoting (largest |W[r][c]| over r >= c, the lowest row on
+// ties).  One launch per step c, one block per row r: every block finds the
+// pivot p itself (the same search over column c in every block, so no
+// grid-wide exchange is needed) and writes row r of the next W from the
+// current one (two buffers: no block reads what another writes):
+//   next[c] = cur[p] / cur[p][c]
+//   next[p] = cur[c] - cur[c][c] next[c]          (p != c)
+//   next[r] = cur[r] - cur[r][c] next[c]          (other rows)
+// with column c set to the unit vector e_c exactly.  A pivot below 1e-300
+// sets *singular, and every later step returns at once.
+constexpr int GJ_T = 256;
+__global__ __launch_bounds__(GJ_T) void gj_step(const double *__restrict__ cur, double *__restrict__ next, int m,
+                                                int c, int32_t *singular) {
+    __shared__ double sv[GJ_T / 64];
+    __shared__ int si[GJ_T / 64];
+    if (*singular) return;   // uniform: the flag was written by an earlier launch
+    const int n2 = 2 * m, r = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double bv = -1.0;
+    int bi = m;
+    for (int q = c + tid; q < m; q += GJ_T) {
+        const double v = fabs(cur[(int64_t)q * n2 + c]);
+        if (v > bv) {   // rows visited in increasing order: the first maximum is kept
+            bv = v;
+            bi = q;
         }
-        sv[threadIdx.x] = bv;
-        si[threadIdx.x] = bi;
-        __syncthreads();
-        for (int w = GJ_T / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) {
-                const double ov = sv[threadIdx.x + w];
-                const int oi = si[threadIdx.x + w];
-                if (ov > sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi < si[threadIdx.x])) {
-                    sv[threadIdx.x] = ov;
-                    si[threadIdx.x] = oi;
-                }
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            piv = si[0];
-            if (!(sv[0] > 1e-300)) *singular = 1;
-        }
-        __syncthreads();
-        if (*singular) return;   // uniform: every thread sees the same flag
-        const int p = piv;
-        if (p != c)
-            for (int k = threadIdx.x; k < n2; k += GJ_T) {
-                const double t = W[(int64_t)p * n2 + k];
-                W[(int64_t)p * n2 + k] = W[(int64_t)c * n2 + k];
-                W[(int64_t)c * n2 + k] = t;
-            }
-        __syncthreads();
-        const double inv = 1.0 / W[(int64_t)c * n2 + c];
-        __syncthreads();
-        for (int k = threadIdx.x; k < n2; k += GJ_T) W[(int64_t)c * n2 + k] *= inv;
-        __syncthreads();
-        for (int64_t e = threadIdx.x; e < (int64_t)m * n2; e += GJ_T) {
-            const int r = (int)(e / n2), k = (int)(e % n2);
-            if (r == c || k == c) continue;
-            const double f = W[(int64_t)r * n2 + c];
-            if (f != 0.0) W[e] -= f * W[(int64_t)c * n2 + k];
-        }
-        __syncthreads();
-        for (int r = threadIdx.x; r < m; r += GJ_T)
-            if (r != c) W[(int64_t)r * n2 + c] = 0.0;
-        __syncthreads();
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+        }
+    }
+    if (lane == 0) {
+        sv[wave] = bv;
+        si[wave] = bi;
+    }
+    __syncthreads();
+    bv = sv[0];
+    bi = si[0];
+    for (int w = 1; w < GJ_T / 64; ++w)
+        if (sv[w] > bv || (sv[w] == bv && si[w] < bi)) {
+            bv = sv[w];
+            bi = si[w];
+        }
+    if (!(bv > 1e-300)) {
+        if (r == 0 && tid == 0) *singular = 1;
+        return;   // uniform over the block
+    }
+    const int p = bi;
+    const double *prow = cur + (int64_t)p * n2;
+    const double inv = 1.0 / prow[c];
+    double *out = next + (int64_t)r * n2;
+    if (r == c) {
+        for (int k = tid; k < n2; k += GJ_T) out[k] = k == c ? 1.0 : prow[k] * inv;
+        return;
+    }
+    const double *src = cur + (int64_t)(r == p ? c : r) * n2;
+    const double f = src[c];
+    for (int k = tid; k < n2; k += GJ_T) out[k] = k == c ? 0.0 : fma(-f, prow[k] * inv, src[k]);
 }
 
 __global__ void gj_setup(const double *A, int m, double *W) {
@@ -823,17 +827,32 @@ static void launch_grade_i8(const ActiveSet &as, const double *brow, int ldb, in
                        as.fexp.as<int32_t>(), as.dsc.as<double>(), as.m, as.CP8, gamma, argmax, thr, sel_blk);
 }
 
-int grade_count_rows(const ActiveSet &as, int precision) {
-    return precision == MTP_MIXED && slice_product_fits(as.m) ? GI_ROWS : GF_ROWS;
+bool grade_sched_valid(const ActiveSet &as, int precision, int sched) {
+    switch (sched) {
+        case GRADE_AUTO: return true;
+        case GRADE_F64_REG: return as.m <= 32 * GR_NK_MAX;
+        case GRADE_F64_LDS: return true;
+        case GRADE_I8: return precision == MTP_MIXED && slice_product_fits(as.m);
+        default: return false;
+    }
+}
+
+static int grade_sched_resolve(const ActiveSet &as, int precision, int sched) {
+    if (sched != GRADE_AUTO) return sched;
+    if (precision == MTP_MIXED && slice_product_fits(as.m)) return GRADE_I8;
+    return as.m <= 32 * GR_NK_MAX ? GRADE_F64_REG : GRADE_F64_LDS;
 }
 
 void launch_grade(const ActiveSet &as, int precision, const double *brow, int ldb, int64_t ldn, int64_t n,
-                  double *gamma, int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
-    static_assert(GRADE_ROWS == GF_ROWS && GRADE_ROWS % GI_ROWS == 0, "preselection blocks are grade blocks");
+                  double *gamma, int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk, int sched) {
+    // every form counts the preselection per block of the same 64 rows
+    static_assert(GRADE_ROWS == GF_ROWS && GRADE_ROWS == GI_ROWS, "preselection blocks are grade blocks");
+    MTP_CHECK(grade_sched_valid(as, precision, sched), MTP_E_INVAL, "grade: schedule not available for this m / precision");
     if (n == 0) return;
     MTP_CHECK(ldb >= (as.m + 31) / 32 * 32, MTP_E_INVAL, "grade: row length below the padded row length");
     MTP_CHECK(ldn >= n, MTP_E_INVAL, "grade: column stride below the row count");
-    if (precision == MTP_MIXED && slice_product_fits(as.m)) {
+    sched = grade_sched_resolve(as, precision, sched);
+    if (sched == GRADE_I8) {
         MTP_CHECK(as.KP8 == (as.m + 63) / 64 * 64 && as.s8.ptr, MTP_E_INVAL, "grade: digits of A^-1 not prepared");
         MTP_CHECK(ldb >= as.KP8, MTP_E_INVAL, "grade: rows not padded to a multiple of 64 columns");
         switch (as.KP8 / 64) {
@@ -845,8 +864,7 @@ void launch_grade(const ActiveSet &as, int precision, const double *brow, int ld
         }
         return;
     }
-    // FP64 form, and the mixed form past m = 320 (the digits would not fit in registers)
-    if (as.m <= 32 * GR_NK_MAX) {
+    if (sched == GRADE_F64_REG) {
         MTP_CHECK(as.NK64 == (as.m + 31) / 32 && as.lane64.ptr, MTP_E_INVAL, "grade: A^-1 not staged");
         MTP_CHECK(ldb >= 32 * as.NK64, MTP_E_INVAL, "grade: rows not padded to a multiple of 32 columns");
         switch (as.NK64) {
@@ -875,14 +893,16 @@ void launch_grade(const ActiveSet &as, int precision, const double *brow, int ld
 
 void launch_invert(ActiveSet &as, const double *A, hipStream_t st, DevBuf &work, int *singular_host) {
     const int m = as.m;
-    work.ensure(sizeof(double) * (size_t)2 * m * m + 64);
-    double *W = work.as<double>();
-    int32_t *flag = reinterpret_cast<int32_t *>(W + (size_t)2 * m * m);
+    const size_t wsz = (size_t)2 * m * m;
+    work.ensure(sizeof(double) * 2 * wsz + 64);
+    double *W[2] = {work.as<double>(), work.as<double>() + wsz};
+    int32_t *flag = reinterpret_cast<int32_t *>(W[1] + wsz);
     launch_zero(flag, sizeof(int32_t), st);
-    const int64_t tot = (int64_t)2 * m * m;
-    hipLaunchKernelGGL(gj_setup, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, A, m, W);
-    hipLaunchKernelGGL(gauss_jordan, dim3(1), dim3(GJ_T), 0, st, W, m, flag);
-    hipLaunchKernelGGL(gj_extract, dim3((unsigned)(((int64_t)m * m + 255) / 256)), dim3(256), 0, st, W, m,
+    const int64_t tot = (int64_t)wsz;
+    hipLaunchKernelGGL(gj_setup, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, A, m, W[0]);
+    for (int c = 0; c < m; ++c)
+        hipLaunchKernelGGL(gj_step, dim3((unsigned)m), dim3(GJ_T), 0, st, W[c & 1], W[(c + 1) & 1], m, c, flag);
+    hipLaunchKernelGGL(gj_extract, dim3((unsigned)(((int64_t)m * m + 255) / 256)), dim3(256), 0, st, W[m & 1], m,
                        as.Ainv.as<double>());
     int32_t h = 0;
     MTP_HIP(hipMemcpyAsync(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));

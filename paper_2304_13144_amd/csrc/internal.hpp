@@ -79,6 +79,8 @@ struct mtp_model {
     // schedules: 16 x (lanes of the moments / contraction) + (lanes of the pair gradients)
     int force_lanes = 0;            // set while the tuner times a schedule
     int tuned_lanes[2][48] = {};    // [precision][floor(log2 n_atoms)] -> schedule, 0 = untuned
+    int force_grade = 0;            // set while the tuner times a grade schedule
+    int tuned_grade[2][2][48] = {}; // [precision][grade mode][floor(log2 n_atoms)] -> GRADE_*, 0 = untuned
     // scratch of the evaluation path
     mutable mtp::DevBuf gbuf, virial, sitebuf, brow, gamma_ws, argmax_ws, work, sums, mbuf, dmbuf, tbuf, dtbuf, rows;
     mutable mtp::DevBuf selblk;     // per-block preselection counts written by the grade kernels
@@ -140,8 +142,15 @@ void launch_cfg_final(const mtp_system *s, const double *site_e, const double *v
 // beyond, FP64).  thr / sel_blk (nullable): the grade also writes, per block
 // of GRADE_ROWS rows, how many have gamma > thr (input of launch_select_write)
 constexpr int GRADE_ROWS = 64;
+// grade schedules (kernel forms): GRADE_AUTO picks by precision and m;
+// GRADE_F64_REG: FP64 MFMA with the rows in registers (m <= 288);
+// GRADE_F64_LDS: FP64 MFMA with the rows staged through LDS (any m);
+// GRADE_I8: the int8 slice product (mixed form, m <= 320)
+enum { GRADE_AUTO = 0, GRADE_F64_REG = 1, GRADE_F64_LDS = 2, GRADE_I8 = 3 };
+bool grade_sched_valid(const ActiveSet &as, int precision, int sched);
 void launch_grade(const ActiveSet &as, int precision, const double *brow, int ldb, int64_t ldn, int64_t n,
-                  double *gamma, int32_t *argmax, hipStream_t st, double thr = 0.0, int32_t *sel_blk = nullptr);
+                  double *gamma, int32_t *argmax, hipStream_t st, double thr = 0.0, int32_t *sel_blk = nullptr,
+                  int sched = GRADE_AUTO);
 void prepare_split(ActiveSet &as, hipStream_t st);
 bool slice_product_fits(int m);
 void launch_invert(ActiveSet &as, const double *A, hipStream_t st, DevBuf &work, int *singular_host);
@@ -170,9 +179,6 @@ GatherArgs gather_args(const mtp_nbrs *nb, const void *gbuf, int precision, doub
 void launch_select_write(const double *gamma, int64_t n, double thr, int32_t *blk, int32_t *idx, int32_t cap,
                          int32_t *count, hipStream_t st, const CfgSums *sums = nullptr,
                          const GatherArgs *gather = nullptr, int count_rows = GRADE_ROWS);
-// rows per preselection count written by launch_grade (GRADE_ROWS, or 16 for
-// the mixed form's slice product)
-int grade_count_rows(const ActiveSet &as, int precision);
 void run_maxvol(ActiveSet &as, double *cand, int64_t n_cand, double thr, int max_swaps, int32_t *swap_cand,
                 int32_t *swap_col, int32_t *n_swaps, hipStream_t st, DevBuf &work);
 // column-major rows (entry (i, k) at src[k * ldn + i]) -> row-major dst [n][m]

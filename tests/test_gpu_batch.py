@@ -55,13 +55,13 @@ def test_uneven_batch_equals_single_configs():
         assert np.allclose(together["stress"][k], one["stress"][0], rtol=1e-12, atol=1e-12)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_graph_replay_equals_eager(precision):
+@pytest.mark.parametrize("precision,passes", [("fp64", 1), ("mixed", 1), ("fp64", 3)])
+def test_graph_replay_equals_eager(precision, passes):
     m = _model16()
     b = api.Batch(_uneven_configs(8, seed=91))
     nb = api.Neighbors().build(m, b, max_nbrs=96)
     eager = _np(api.evaluate(m, b, nb, precision, "full"))
-    step = api.CapturedStep(m, b, nb, precision, "full", max_nbrs=96)
+    step = api.CapturedStep(m, b, nb, precision, "full", max_nbrs=96, passes=passes)
     for rep in range(3):
         # eager work and a synchronisation between replays
         other = _np(api.evaluate(m, b, nb, precision, "linear"))
@@ -90,6 +90,32 @@ def test_autotuner_choice_agrees_to_rounding():
         # lanes change the summation tree of the moments: equal to rounding
         assert np.allclose(other["forces"], tuned["forces"], rtol=0, atol=1e-10 * np.abs(tuned["forces"]).max())
         assert np.allclose(other["gamma"], tuned["gamma"], rtol=1e-9)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_grade_forms_agree_and_tuner_picks_one(precision):
+    """Every kernel form of the grade product gives the same grades to the
+    precision's bound, and the tuner returns one of the forms."""
+    import os
+    m = _model16()
+    b = api.Batch([synth.workload2(reps=(6, 6, 6)).configs[0]])
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    forms = {"1": "fp64-registers", "2": "fp64-lds"} | ({"3": "int8-slices"} if precision == "mixed" else {})
+    lanes = api.tune(m, b, nb, precision, "full", with_grade=True)   # first: the lanes stay fixed below
+    assert lanes[2] in forms.values()
+    got = {}
+    for k in forms:
+        os.environ["MTP_GRADE_FORM"] = k
+        try:
+            got[k] = _np(api.evaluate(m, b, nb, precision, "full"))["gamma"]
+        finally:
+            del os.environ["MTP_GRADE_FORM"]
+    # the two FP64 products differ only in summation order
+    assert np.allclose(got["2"], got["1"], rtol=1e-12, atol=0)
+    if precision == "mixed":
+        assert np.all(np.abs(got["3"] - got["1"]) <= 1e-5 * np.maximum(1.0, got["1"]))
+    assert np.array_equal(_np(api.evaluate(m, b, nb, precision, "full"))["gamma"],
+                          got[{v: k for k, v in forms.items()}[lanes[2]]])
 
 
 def test_graph_replay_reports_neighbor_overflow_after_atoms_move():

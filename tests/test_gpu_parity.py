@@ -426,6 +426,39 @@ def test_maxvol_matches_oracle_swap_sequence():
     assert rel_err(Ainv.cpu().numpy() @ A_or, np.eye(A_or.shape[0])) <= 1e-6
 
 
+@pytest.mark.parametrize("case", ["workload2_full", "workload1_full", "pivoting", "singular"])
+def test_active_set_inverse_matches_oracle_lu(case):
+    """A^-1 by the multi-block Gauss-Jordan inverse against the oracle's LU
+    solve of I = C A (Sec. II.C: A is the active set's matrix), row by row
+    (row k of A^-1 carries 1 / (scale of column k of A)) within
+    kappa_eq(A) m 1e-15, kappa_eq the condition number of A with unit
+    max-abs columns; a singular A is refused."""
+    w = synth.workload2() if case == "workload2_full" else synth.workload1()
+    theta = theta_for(w.wid, potential(w))
+    m, keep = _model(w, theta, modes=())
+    if case in ("workload2_full", "workload1_full"):
+        A = active_rows(w.wid, "full")[:, keep]
+    else:
+        k = len(keep)
+        rng = np.random.default_rng(31)
+        A = rng.normal(size=(k, k))
+        A[np.arange(k), np.arange(k)] = 0.0          # every step has to pivot
+        A[: k // 2] *= 1e-3                           # rows of very different scale
+        if case == "singular":
+            A[5] = 0.0                                # exactly singular: the last pivot is 0
+    if case == "singular":
+        with pytest.raises(api.MtpError):
+            m.set_active_set("full", A)
+        return
+    m.set_active_set("full", A)
+    _, Ainv = m.get_active_set("full")
+    _, _, inv_or = om.grades(np.eye(A.shape[0]), A)
+    tol = kappa_eq(A) * 1e-15 * A.shape[0]
+    diff = np.abs(Ainv.cpu().numpy() - inv_or).max(axis=1) / np.abs(inv_or).max(axis=1)
+    print(f"{case}: m = {A.shape[0]}, kappa_eq {kappa_eq(A):.3g}, worst row rel err {diff.max():.3g} (bar {tol:.3g})")
+    assert diff.max() <= tol
+
+
 @pytest.mark.parametrize("n,shift,cap", [(100000, 0.0, None), (1048577, 5.0, None), (300000, 5.0, 1000),
                                          (7, 0.0, None)])
 def test_select_matches_numpy(n, shift, cap):
