@@ -359,7 +359,7 @@ def main():
         "mixed_vs_fp64": mixed_vs_fp64,
     }
     if a.extra_workloads:
-        out["extra_workloads"] = extra_workloads(timed)
+        out["extra_workloads"] = extra_workloads(timed, passes)
     if not a.no_cpu_baseline:
         out["cpu_baseline"], out["errors_vs_oracle"] = cpu_baseline(cfg, w, theta, keep, A_full, f64, mix,
                                                                    a.cpu_centers)
@@ -367,9 +367,11 @@ def main():
     return 0
 
 
-def extra_workloads(timed):
+def extra_workloads(timed, passes):
     """The training workload (level 20, 3 species, 512 uneven configurations:
-    loss forward + backward through MTPEnergy) and the active-learning
+    loss forward + backward through MTPEnergy), the batched uneven evaluation
+    at level 24 (1,024 configurations of 16-4096 atoms: E, F, S, site
+    energies, eager and HIP-graph replay, both forms), the active-learning
     snapshots (level 16, 1,048,576 atoms: grades + preselection gamma > 2, FULL
     and LINEAR) at their full sizes, and configuration-mode grades of 1,024
     small alloy cells."""
@@ -378,6 +380,35 @@ def extra_workloads(timed):
     from paper_2304_13144_amd import api, synth
 
     res = {}
+    if 24 in api.compiled_levels():
+        w4 = synth.workload4()
+        m4 = api.Model.create(w4.level, w4.n_types, w4.r_min, w4.r_cut)
+        inf4 = m4.info
+        m4.set_params(synth.theta_teacher(4, w4.n_types, inf4["n_lin"], inf4["n_rad"]))
+        b4 = api.Batch(w4.configs)
+        nb4 = api.Neighbors().build(m4, b4, max_nbrs=64)
+        for prec in ("fp64", "mixed"):
+            lanes = api.tune(m4, b4, nb4, prec, "full")
+            o4 = {"energy": torch.empty(b4.n_cfg, dtype=torch.float64, device=b4.device),
+                  "forces": torch.empty((b4.n_atoms, 3), dtype=torch.float64, device=b4.device),
+                  "stress": torch.empty((b4.n_cfg, 3, 3), dtype=torch.float64, device=b4.device),
+                  "site_e": torch.empty(b4.n_atoms, dtype=torch.float64, device=b4.device)}
+            eager = timed(lambda: api.evaluate(m4, b4, nb4, prec, "full", out=o4))
+            cap = api.CapturedStep(m4, b4, nb4, prec, "full", max_nbrs=64, rebuild=False, passes=passes,
+                                   grades=False)
+            graph = timed(lambda: cap.replay(check=False), passes)
+            ms = min(eager, graph)
+            res[f"batched_level24_{prec}"] = {
+                "configs": len(w4.configs), "atoms": b4.n_atoms, "ms_per_step": ms,
+                "atom_steps_per_s": b4.n_atoms / (ms * 1e-3), "eager_ms": eager,
+                "graph_ms_per_pass": graph, "graph_passes": passes,
+                "lanes_per_neighborhood": {"moments": lanes[0], "pair_gradients": lanes[1]},
+                "step": "E, F, S, site energies (staged contraction program, no grades)"}
+            log(f"[bench] level 24 batch {prec}: {ms:.3f} ms/step ({b4.n_atoms / (ms * 1e-3):.4g} atom-steps/s; "
+                f"eager {eager:.3f}, graph x{passes} {graph:.3f})")
+        res["batched_level24_mixed_speedup"] = (res["batched_level24_fp64"]["ms_per_step"]
+                                                / res["batched_level24_mixed"]["ms_per_step"])
+        del m4, b4, nb4
     w = synth.workload3()
     n_lin = {20: 293}[w.level]
     n_rad = {20: 5}[w.level]

@@ -497,14 +497,21 @@ class CapturedStep:
     Outputs live in `self.out` and are overwritten by every pass."""
 
     def __init__(self, model, batch, nbrs, precision="fp64", mode="full", max_nbrs=64, gamma_save=2.0,
-                 rebuild=True, passes=1):
+                 rebuild=True, passes=1, grades=True):
         if passes < 1:
             raise ValueError("passes must be at least 1")
         self.model, self.batch, self.nbrs = model, batch, nbrs
-        self.args = (precision, mode, max_nbrs, gamma_save)
+        self.args = (precision, mode, max_nbrs, gamma_save if grades else None)
         self.rebuild = rebuild
         self.passes = passes
-        self.out = evaluate(model, batch, nbrs, precision, mode, gamma_save=gamma_save)
+        out = None
+        if not grades:   # energy, forces, stress and site energies only (no active set needed)
+            d = batch.device
+            out = {"energy": _out(batch.n_cfg, torch.float64, d),
+                   "forces": _out(None, torch.float64, d, (batch.n_atoms, 3)),
+                   "stress": _out(None, torch.float64, d, (batch.n_cfg, 3, 3)),
+                   "site_e": _out(batch.n_atoms, torch.float64, d)}
+        self.out = evaluate(model, batch, nbrs, precision, mode, out=out, gamma_save=self.args[3])
         self._step()                      # eager warm-up: workspaces at their final size
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
@@ -518,7 +525,7 @@ class CapturedStep:
         if self.rebuild:
             self.nbrs.build(self.model, self.batch, max_nbrs=max_nbrs, check_status=False)
         evaluate(self.model, self.batch, self.nbrs, precision, mode, out=self.out, gamma_save=gamma_save)
-        self.sel = (self.out["sel_idx"], self.out["sel_count"])
+        self.sel = (self.out["sel_idx"], self.out["sel_count"]) if gamma_save is not None else None
 
     def replay(self, check=True):
         """Replays the step.  With `check` (the default) it waits for the step

@@ -22,7 +22,7 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 GEN = os.path.join(BUILD, "gen")
 LIB = os.path.join(HERE, "libmtp.so")
 
-DEFAULT_LEVELS = (2, 4, 6, 8, 12, 16, 20)
+DEFAULT_LEVELS = (2, 4, 6, 8, 12, 16, 20, 24)
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wno-unused-result",
@@ -31,7 +31,7 @@ HIP_FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wno-unuse
              "-I", CSRC, "-I", GEN]
 HOST_SOURCES = ["api.cpp", "basis.cpp", "prof.cpp"]
 # what the generated per-level units include (besides their level's program)
-KERNEL_HEADERS = ["efs_kernel.hpp", "backward_kernel.hpp", "kernel_args.hpp", "device_util.hpp"]
+KERNEL_HEADERS = ["efs_kernel.hpp", "efs_staged.hpp", "backward_kernel.hpp", "kernel_args.hpp", "device_util.hpp"]
 HIP_SOURCES = ["neighbors.hip", "ops.hip", "grade.hip"]
 
 
@@ -43,34 +43,68 @@ def _run(cmd):
     return time.time() - t
 
 
+STAGE_R_PER_UNIT = 4   # reverse parts per translation unit of a staged level
+
+
 def generate(levels):
     os.makedirs(GEN, exist_ok=True)
     gen_exe = os.path.join(BUILD, "gen_contract")
     _run(["g++", "-O2", "-std=c++17", "-o", gen_exe, os.path.join(CSRC, "gen_contract.cpp"),
           os.path.join(CSRC, "basis.cpp")])
     tmp = os.path.join(BUILD, "gen_tmp")
+    if os.path.isdir(tmp):
+        for f in os.listdir(tmp):
+            os.remove(os.path.join(tmp, f))
     os.makedirs(tmp, exist_ok=True)
     _run([gen_exe, tmp] + [str(L) for L in levels])
     for f in os.listdir(tmp):   # keep the mtime of unchanged programs (incremental builds)
         _write_if_changed(os.path.join(GEN, f), open(os.path.join(tmp, f)).read())
-    flops = {}
+    flops, staged = {}, {}
     for L in levels:
         txt = open(os.path.join(GEN, f"mtp_level{L}.inc")).read()
         flops[L] = sum(int(txt.split(f"FLOPS_{k} = ")[1].split(";")[0]) for k in ("GRAPHS", "TRIE", "REVERSE"))
+        if "STAGED = true" in txt:   # (graph parts, reverse parts, graphs)
+            staged[L] = (int(txt.split("STAGE_G = ")[1].split(",")[0]), int(txt.split("STAGE_R = ")[1].split(";")[0]),
+                         int(txt.split("NGRAPH = ")[1].split(";")[0]))
     units = []
-    for L in levels:   # one unit per (level, arithmetic type, forward / backward): they compile in parallel
+
+    def unit(name, body):
+        path = os.path.join(GEN, name)
+        _write_if_changed(path, body)
+        units.append(path)
+
+    for L in levels:   # units per (level, arithmetic type, forward / backward): they compile in parallel
         for T, tag in (("double", "f64"), ("float", "f32")):
-            for kind, macro, hdr in (("efs", "MTP_EFS_LEVEL_T", "efs_kernel.hpp"),
-                                     ("bwd", "MTP_BWD_LEVEL_T", "backward_kernel.hpp")):
-                path = os.path.join(GEN, f"{kind}_level{L}_{tag}.hip")
-                src = (f'#include "efs_kernel.hpp"\n#include "backward_kernel.hpp"\nnamespace mtp {{\n'
-                       f'#include "mtp_level{L}.inc"\n{macro}({L}, {T})\n}}  // namespace mtp\n')
-                _write_if_changed(path, src)
-                units.append(path)
+            if L not in staged:
+                for kind, macro in (("efs", "MTP_EFS_LEVEL_T"), ("bwd", "MTP_BWD_LEVEL_T")):
+                    unit(f"{kind}_level{L}_{tag}.hip",
+                         f'#include "efs_kernel.hpp"\n#include "backward_kernel.hpp"\nnamespace mtp {{\n'
+                         f'#include "mtp_level{L}.inc"\n{macro}({L}, {T})\n}}  // namespace mtp\n')
+                continue
+            ng, nr, _ = staged[L]
+            # the staged program: moments + trie walk + pair gradients in one unit, the graph
+            # parts in one, the reverse parts in units of STAGE_R_PER_UNIT
+            decl = "".join(f"template <> void launch_graphs_stage<{L}, {T}, {q}>(const EfsArgs &a);\n" for q in range(ng))
+            decl += "".join(f"template <> void launch_reverse_stage<{L}, {T}, {q}>(const EfsArgs &a);\n" for q in range(nr))
+            unit(f"efs_level{L}_{tag}.hip",
+                 f'#include "efs_staged.hpp"\nnamespace mtp {{\n#include "mtp_level{L}.inc"\n{decl}'
+                 f'MTP_EFS_STAGED_LEVEL_T({L}, {T})\nMTP_EFS_FR_LEVEL_T({L}, {T})\n}}  // namespace mtp\n')
+            unit(f"stg_level{L}_{tag}_g.hip",
+                 f'#include "efs_staged.hpp"\nnamespace mtp {{\n#include "mtp_level{L}.inc"\n'
+                 + "".join(f'#include "mtp_level{L}_g{q}.inc"\nMTP_STAGE_G_T({L}, {T}, {q})\n' for q in range(ng))
+                 + "}  // namespace mtp\n")
+            for u in range(0, nr, STAGE_R_PER_UNIT):
+                unit(f"stg_level{L}_{tag}_r{u // STAGE_R_PER_UNIT}.hip",
+                     f'#include "efs_staged.hpp"\nnamespace mtp {{\n#include "mtp_level{L}.inc"\n'
+                     + "".join(f'#include "mtp_level{L}_r{q}.inc"\nMTP_STAGE_R_T({L}, {T}, {q})\n'
+                               for q in range(u, min(nr, u + STAGE_R_PER_UNIT)))
+                     + "}  // namespace mtp\n")
+    plain = [L for L in levels if L not in staged]
     decl = "".join(f"template <> int launch_mc_level_t<{L}, {T}>(const EfsArgs &a);\n"
                    f"template <> int launch_fr_level_t<{L}, {T}, {T}>(const EfsArgs &a);\n"
-                   f"template <> int launch_backward_level_t<{L}, {T}>(const BwdArgs &b);\n"
                    for L in levels for T in ("double", "float"))
+    decl += "".join(f"template <> int launch_backward_level_t<{L}, {T}>(const BwdArgs &b);\n"
+                    for L in plain for T in ("double", "float"))
     decl += "".join(f"template <> int launch_fr_level_t<{L}, float, double>(const EfsArgs &a);\n" for L in levels)
     # moments / contraction in FP64 for the FP64 form and for the mixed form when
     # it writes rows (rows are FP64); pair gradients in the form's own type
@@ -80,7 +114,8 @@ def generate(levels):
                  f"                     : (mc64 ? launch_fr_level_t<{L}, float, double>(a) : launch_fr_level_t<{L}, float, float>(a));\n"
                  for L in levels)
     bcases = "".join(f"        case {L}: return f64 ? launch_backward_level_t<{L}, double>(b) : "
-                     f"launch_backward_level_t<{L}, float>(b);\n" for L in levels)
+                     f"launch_backward_level_t<{L}, float>(b);\n" for L in plain)
+    scases = "".join(f"        case {L}: return {staged[L][2]};\n" for L in staged)
     disp = ('#include "internal.hpp"\nnamespace mtp {\n'
             + "template <int L, typename T> int launch_mc_level_t(const EfsArgs &a);\n"
             + "template <int L, typename TF, typename TD> int launch_fr_level_t(const EfsArgs &a);\n"
@@ -92,7 +127,10 @@ def generate(levels):
             + "        default: return -1;\n    }\n}\n"
             + "int launch_backward(int level, const BwdArgs &b) {\n    const bool f64 = b.e.precision == MTP_FP64;\n"
             + "    switch (level) {\n" + bcases
-            + "        default: return -1;\n    }\n}\nstd::vector<int> compiled_levels() { return {"
+            + "        default: return -1;\n    }\n}\n"
+            + "int staged_graphs(int level) {\n    switch (level) {\n" + scases
+            + "        default: return 0;\n    }\n}\n"
+            + "std::vector<int> compiled_levels() { return {"
             + ", ".join(str(L) for L in levels) + "}; }\nlong contraction_flops(int level) {\n    switch (level) {\n"
             + "".join(f"        case {L}: return {flops[L]};\n" for L in levels)
             + "        default: return 0;\n    }\n}\n}  // namespace mtp\n")
@@ -131,7 +169,8 @@ def build(levels=DEFAULT_LEVELS, jobs=None, verbose=True, force=True):
         objs.append(obj)
         if src in units:
             level = "".join(ch for ch in os.path.basename(src).split("_")[1] if ch.isdigit())
-            dm = max(kernel_mtime, mt(os.path.join(GEN, f"mtp_level{level}.inc")))
+            progs = [f for f in os.listdir(GEN) if f == f"mtp_level{level}.inc" or f.startswith(f"mtp_level{level}_")]
+            dm = max([kernel_mtime] + [mt(os.path.join(GEN, f)) for f in progs])
         else:
             dm = host_mtime
         if force or _stale(src, obj, dm):

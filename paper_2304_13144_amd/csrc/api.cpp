@@ -294,6 +294,11 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     a.stream = st;
     a.mbuf = ws.get(m->mbuf, msz * m->basis.n_comp() * (size_t)n);
     a.dmbuf = ws.get(m->dmbuf, msz * m->basis.n_comp() * (size_t)n);
+    if (const int ngs = staged_graphs(m->level)) {   // tiles of 64 neighborhoods
+        const size_t bytes = msz * ngs * (size_t)((n + 63) / 64 * 64);
+        a.gval = ws.get(m->gval, bytes);
+        a.dgval = ws.get(m->dgval, bytes);
+    }
     // per-configuration sums: chunk partials, then one block per configuration.
     // With forces and a preselection the force gather runs as extra blocks of
     // the preselection's launch (one launch less per step) and the partials
@@ -812,6 +817,13 @@ int mtp_b_rows(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_
     m->dmbuf.ensure(sizeof(double) * m->basis.n_comp() * (size_t)n_idx);
     a.mbuf = m->mbuf.ptr;
     a.dmbuf = m->dmbuf.ptr;
+    if (const int ngs = staged_graphs(m->level)) {
+        const size_t bytes = sizeof(double) * ngs * (size_t)((n_idx + 63) / 64 * 64);
+        m->gval.ensure(bytes);
+        m->dgval.ensure(bytes);
+        a.gval = m->gval.ptr;
+        a.dgval = m->dgval.ptr;
+    }
     int e = launch_efs(m->level, a);
     MTP_CHECK(e == 0, MTP_E_HIP, std::string("efs kernel launch: ") + hipGetErrorString((hipError_t)e));
     launch_copy_rows(m->brow.as<double>(), n_idx, mm, n_idx, rows, S(stream));
@@ -1222,6 +1234,9 @@ int mtp_efs_backward(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb
     check_system(m, s);
     check_nbrs(m, s, nb);
     MTP_CHECK(p == MTP_FP64 || p == MTP_MIXED, MTP_E_INVAL, "bad precision");
+    MTP_CHECK(!staged_graphs(m->level), MTP_E_UNSUPPORTED,
+              "level " + std::to_string(m->level) + " is compiled as a staged program, which evaluates energies, "
+              "forces, stresses and rows; its backward pass is not built");
     MTP_HIP(hipSetDevice(m->device));
     hipStream_t st = S(stream);
     const int64_t n = s->n_atoms;

@@ -739,7 +739,9 @@ template <int L, typename TF, typename TD> int launch_fr_level_t(const EfsArgs &
 // time): the moments / contraction in TT (rows only when TT is FP64), the
 // pair gradients in TT with dE/dM in TT, and for TT = float also with dE/dM
 // in FP64 (the mixed form with FP64 rows)
-#define MTP_EFS_LEVEL_T(LEVEL, TT)                                                                       \
+#define MTP_EFS_LEVEL_T(LEVEL, TT) MTP_EFS_MC_LEVEL_T(LEVEL, TT) MTP_EFS_FR_LEVEL_T(LEVEL, TT)
+
+#define MTP_EFS_MC_LEVEL_T(LEVEL, TT)                                                                    \
     /* moments and contraction, K lanes per neighborhood (K = 4, 8: one launch; K = 2: two) */         \
     template <typename T, int K, bool WB> static void launch_mc##LEVEL(const EfsArgs &a) {               \
         const unsigned grid = (unsigned)((a.n_atoms + 256 / K - 1) / (256 / K));                         \
@@ -761,14 +763,6 @@ template <int L, typename TF, typename TD> int launch_fr_level_t(const EfsArgs &
             hipLaunchKernelGGL((efs_contract<T, LEVEL, WB>), dim3(grid1), dim3(256), 0, a.stream, a);    \
         }                                                                                                \
     }                                                                                                    \
-    /* pair gradients and virial (+ the rest of the rows), K lanes per neighborhood */                   \
-    template <typename TF, typename TD, int K> static void launch_fr##LEVEL(const EfsArgs &a) {          \
-        const unsigned grid = (unsigned)((a.n_atoms + 256 / K - 1) / (256 / K));                         \
-        const bool rows = sizeof(TD) == sizeof(double) && a.brow != nullptr;                             \
-        ProfScope ps("efs_forces", a.stream);                                                            \
-        hipLaunchKernelGGL((efs_forces_rows<TF, TD, LEVEL, K>), dim3(rows ? 2 * grid : grid), dim3(256),  \
-                           0, a.stream, a, (int64_t)grid);                                               \
-    }                                                                                                    \
     template <> int launch_mc_level_t<LEVEL, TT>(const EfsArgs &a) {                                     \
         if (a.n_atoms == 0) return 0;                                                                    \
         constexpr bool F64 = sizeof(TT) == sizeof(double);                                               \
@@ -786,6 +780,16 @@ template <int L, typename TF, typename TD> int launch_fr_level_t(const EfsArgs &
             }                                                                                            \
         }                                                                                                \
         return (int)hipGetLastError();                                                                   \
+    }
+
+#define MTP_EFS_FR_LEVEL_T(LEVEL, TT)                                                                    \
+    /* pair gradients and virial (+ the rest of the rows), K lanes per neighborhood */                   \
+    template <typename TF, typename TD, int K> static void launch_fr##LEVEL(const EfsArgs &a) {          \
+        const unsigned grid = (unsigned)((a.n_atoms + 256 / K - 1) / (256 / K));                         \
+        const bool rows = sizeof(TD) == sizeof(double) && a.brow != nullptr;                             \
+        ProfScope ps("efs_forces", a.stream);                                                            \
+        hipLaunchKernelGGL((efs_forces_rows<TF, TD, LEVEL, K>), dim3(rows ? 2 * grid : grid), dim3(256),  \
+                           0, a.stream, a, (int64_t)grid);                                               \
     }                                                                                                    \
     template <typename TD> static int launch_fr_td##LEVEL(const EfsArgs &a) {                            \
         if (a.n_atoms == 0) return 0;                                                                    \

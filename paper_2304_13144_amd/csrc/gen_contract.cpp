@@ -143,13 +143,15 @@ struct Emitter {
     }
 
     std::vector<bool> dg_set;
+    bool stream = false;   // graph values read from gin[] at each use, dV/dg accumulated in dgout[]
 
     void visit(int node, int depth, const std::string &ind) {
         for (auto &kv : trie[node].child) {
             const int G = kv.first, c = kv.second;
             const std::string bd = "b" + std::to_string(depth), bd1 = "b" + std::to_string(depth + 1);
             const std::string wd = "w" + std::to_string(depth), wd1 = "w" + std::to_string(depth + 1);
-            const std::string g = "g" + std::to_string(G), dg = "dg" + std::to_string(G);
+            const std::string g = stream ? "gin[" + std::to_string(G) + "]" : "g" + std::to_string(G);
+            const std::string dg = stream ? "dgout[" + std::to_string(G) + "]" : "dg" + std::to_string(G);
             os << ind << "{\n";
             const std::string in2 = ind + "  ";
             if (depth == 0) os << in2 << "const T " << bd1 << " = " << g << ";\n";
@@ -168,6 +170,9 @@ struct Emitter {
             os << in2 << wd << " = fma(" << g << ", " << wd1 << ", " << wd << ");\n";
             trie_count.fma++;
             os << ind << "}\n";
+            // streamed walk: dV/dg goes back to memory after each node
+            // (and the parent's sum is formed here, not deferred to its use)
+            if (stream) os << ind << "MTP_STAGE_SYNC(" << wd << ");\n";
         }
     }
     Counter trie_count;
@@ -187,6 +192,126 @@ struct Emitter {
             if (!dg_set[G]) os << "  dg" << G << " = T(0);\n";
         if (arrays)
             for (size_t G = 0; G < B.graphs.size(); ++G) os << "  dgout[" << G << "] = dg" << G << ";\n";
+    }
+
+    // Horner form of one graph polynomial over the tree of its monomials'
+    // factor prefixes: S(n) = coef(n) + sum over children c of M[k_c] S(c), so
+    // that g = S(root) and, with q(n) = dV/dg x the product of the factors
+    // on the path to n, dV/dM[k_c] gets q(parent c) S(c) at every node c.  The
+    // walk is depth first: only one S and one q per depth are live (the
+    // prefix-product form holds every prefix of the graph at once).
+    struct HTree {
+        std::vector<int> k;
+        std::vector<long> coef;
+        std::vector<std::vector<int>> ch;
+        std::vector<int> roots;
+    };
+    static HTree htree(const std::vector<Monomial> &poly) {
+        HTree t;
+        std::map<std::vector<int>, int> memo;
+        for (auto &m : poly) {
+            std::vector<int> pre;
+            int cur = -1;
+            for (int k : m.comp) {
+                pre.push_back(k);
+                auto it = memo.find(pre);
+                if (it != memo.end()) {
+                    cur = it->second;
+                    continue;
+                }
+                const int n = (int)t.k.size();
+                t.k.push_back(k);
+                t.coef.push_back(0);
+                t.ch.emplace_back();
+                (cur < 0 ? t.roots : t.ch[cur]).push_back(n);
+                memo[pre] = n;
+                cur = n;
+            }
+            t.coef[cur] += m.coef;
+        }
+        return t;
+    }
+    std::vector<bool> hdm_set;
+    void h_dm(int k, const std::string &a, long c, Counter &cnt) {   // dM[k] += a (c = 1) or a * c
+        const std::string term = c == 1 ? a : lit(c) + " * " + a;
+        if (!hdm_set[k]) {
+            os << "dM[" << k << "] = " << term << ";\n";
+            if (c != 1) cnt.mul++;
+            hdm_set[k] = true;
+        } else if (c == 1) {
+            os << "dM[" << k << "] += " << a << ";\n";
+            cnt.add++;
+        } else {
+            os << "dM[" << k << "] = fma(" << lit(c) << ", " << a << ", dM[" << k << "]);\n";
+            cnt.fma++;
+        }
+    }
+    // emits the accumulation of the children `kids` of a node into a<d> (and
+    // with rev the dV/dM terms, q: the name of q(node))
+    void h_children(const HTree &t, const std::vector<int> &kids, int d, bool rev, const std::string &q, Counter &cnt) {
+        const std::string ad = "a" + std::to_string(d);
+        for (int c : kids) {
+            const std::string Mk = "M[" + std::to_string(t.k[c]) + "]";
+            if (t.ch[c].empty()) {   // leaf: S(c) = coef(c)
+                const long cf = t.coef[c];
+                if (cf == 1) { os << ad << " += " << Mk << ";\n"; cnt.add++; }
+                else { os << ad << " = fma(" << lit(cf) << ", " << Mk << ", " << ad << ");\n"; cnt.fma++; }
+                if (rev) h_dm(t.k[c], q, cf, cnt);
+                continue;
+            }
+            const std::string a1 = "a" + std::to_string(d + 1), q1 = "q" + std::to_string(d + 1);
+            os << "{\n";
+            if (rev) { os << "const T " << q1 << " = " << q << " * " << Mk << ";\n"; cnt.mul++; }
+            os << "T " << a1 << " = " << (t.coef[c] ? lit(t.coef[c]) : std::string("T(0)")) << ";\n";
+            h_children(t, t.ch[c], d + 1, rev, q1, cnt);
+            if (rev) h_dm(t.k[c], q + " * " + a1, 1, cnt), cnt.mul++;
+            os << ad << " = fma(" << Mk << ", " << a1 << ", " << ad << ");\n";
+            cnt.fma++;
+            os << "}\nMTP_STAGE_KEEP(" << ad << ");\n";
+        }
+    }
+    // graph values of `gl` in Horner form, written to gout[G]
+    void graphs_forward_horner(const std::vector<int> &gl) {
+        os << "  // graph values (Horner form over the factor-prefix tree)\n";
+        for (int G : gl) {
+            const HTree t = htree(B.polys[G]);
+            os << "  {  // " << B.graphs[G].str() << ", " << B.polys[G].size() << " monomials\n";
+            os << "T a0 = T(0);\n";
+            h_children(t, t.roots, 0, false, "", fwd);
+            os << "gout[" << G << "] = a0;\n  }\n  MTP_STAGE_BARRIER();\n";
+        }
+    }
+    // dV/dM of the graphs `gl` in Horner form (dg from dgin[G]); a compiler
+    // barrier between graphs keeps the moments from being held across them
+    void graphs_reverse_horner(const std::vector<int> &gl) {
+        os << "  // dV/dM by reverse accumulation (Horner form over the factor-prefix tree)\n";
+        hdm_set.assign(B.n_comp(), false);
+        for (int G : gl) {
+            const HTree t = htree(B.polys[G]);
+            os << "  {  // " << B.graphs[G].str() << "\n";
+            os << "const T q0 = dgin[" << G << "];\nT a0 = T(0);\n";
+            h_children(t, t.roots, 0, true, "q0", rev);
+            os << "(void)a0;\n  }\n  MTP_STAGE_BARRIER();\n";
+        }
+        for (int k = 0; k < B.n_comp(); ++k)
+            if (!hdm_set[k]) os << "  dM[" << k << "] = T(0);\n";
+    }
+
+    // The trie walk with every graph value read where it is used and dV/dg
+    // accumulated in place (gin, dgout: accessors), so that neither the 2 x
+    // NGRAPH values nor anything but the walk's path is held in registers.
+    void trie_walk_stream() {
+        build_trie();
+        os << "  // basis values, site energy and dV/dg by a walk over the factor trie\n";
+        dg_set.assign(B.graphs.size(), false);
+        trie_count = Counter{};
+        stream = true;
+        os << "  T w0 = T(0);\n";
+        visit(0, 0, "  ");
+        stream = false;
+        os << "  V = w0;\n";
+        for (size_t G = 0; G < B.graphs.size(); ++G)
+            if (!dg_set[G]) os << "  dgout[" << G << "] = T(0);\n";
     }
 
     void graphs_reverse(const std::vector<int> &gl, bool dg_array) {
@@ -255,8 +380,136 @@ struct Emitter {
     }
 };
 
+// Levels with more connected graphs than this get the staged program: graph
+// values, trie walk and reverse pass as separate kernels (graph values and
+// dV/dg pass through memory), each split into parts that compile apart.
+constexpr int STAGED_GRAPHS = 128;
+constexpr int STAGE_G = 8, STAGE_R = 16;
+
+// Split of the graphs over np parts (largest first onto the least loaded
+// part; cost = monomial terms x degree).
+std::vector<int> split_graphs(const Basis &B, int np) {
+    std::vector<int> part(B.graphs.size(), 0);
+    std::vector<std::pair<long, int>> cost;
+    for (size_t G = 0; G < B.graphs.size(); ++G) {
+        long c = 0;
+        for (auto &t : B.polys[G]) c += (long)t.comp.size();
+        cost.push_back({c, (int)G});
+    }
+    std::sort(cost.begin(), cost.end(),
+              [](auto &a, auto &b) { return a.first > b.first || (a.first == b.first && a.second < b.second); });
+    std::vector<long> load(np, 0);
+    for (auto &c : cost) {
+        int best = 0;
+        for (int q = 1; q < np; ++q)
+            if (load[q] < load[best]) best = q;
+        part[c.second] = best;
+        load[best] += c.first;
+    }
+    return part;
+}
+
+void write_common(std::ostringstream &h, const Basis &B, int level) {
+    const int NC = B.n_comp();
+    h << "  static constexpr int NC = " << NC << ";\n";
+    h << "  static constexpr int NLIN = " << B.n_lin() << ";\n";
+    h << "  static constexpr int NRAD = " << B.n_rad << ";\n";
+    h << "  static constexpr int NGRAPH = " << B.graphs.size() << ";\n";
+    int maxnu = 0;
+    for (auto &c : B.comps) maxnu = std::max(maxnu, c.nu);
+    h << "  static constexpr int MAXNU = " << maxnu << ";\n";
+    auto arr = [&](const char *name, auto f) {
+        h << "  static constexpr int " << name << "[" << NC << "] = {";
+        for (int k = 0; k < NC; ++k) h << (k ? "," : "") << f(B.comps[k]);
+        h << "};\n";
+    };
+    arr("comp_mu", [](const Component &c) { return c.mu; });
+    arr("comp_nu", [](const Component &c) { return c.nu; });
+    arr("comp_mono", [](const Component &c) { return monomial_index(c.e[0], c.e[1], c.e[2]); });
+    for (int ax = 0; ax < 3; ++ax) {
+        std::string nm = std::string("comp_dmono") + "xyz"[ax];
+        arr(nm.c_str(), [ax](const Component &c) {
+            if (c.e[ax] == 0) return -1;
+            int e[3] = {c.e[0], c.e[1], c.e[2]};
+            e[ax]--;
+            return monomial_index(e[0], e[1], e[2]);
+        });
+        std::string nf = std::string("comp_dfac") + "xyz"[ax];
+        arr(nf.c_str(), [ax](const Component &c) { return c.e[ax]; });
+    }
+}
+
+// The staged program of a large level: mtp_level<L>.inc holds the constants
+// and the trie walk; mtp_level<L>_g<P>.inc the graph values of part P
+// (LevelGraphs<L, P>::run) and mtp_level<L>_r<P>.inc the reverse pass of part
+// P (LevelReverse<L, P>::run), each included by its own translation unit.
+void write_level_staged(const std::string &dir, int level, const Basis &B) {
+    Emitter em(B);
+    const std::vector<int> pg = split_graphs(B, STAGE_G), pr = split_graphs(B, STAGE_R);
+    auto graphs_of = [&](const std::vector<int> &part, int q) {
+        std::vector<int> gl;
+        for (size_t G = 0; G < B.graphs.size(); ++G)
+            if (part[G] == q) gl.push_back((int)G);
+        return gl;
+    };
+    const std::string L = std::to_string(level);
+    for (int q = 0; q < STAGE_G; ++q) {
+        em.os.str("");
+        em.graphs_forward_horner(graphs_of(pg, q));
+        std::ofstream out(dir + "/mtp_level" + L + "_g" + std::to_string(q) + ".inc");
+        out << "// generated by gen_contract for MTP level " << level << ", graph values of part " << q
+            << "; do not edit.\n#pragma once\n\n";
+        out << "template <> struct LevelGraphs<" << level << ", " << q << "> {\n";
+        out << "  template <typename T, typename MP, typename GP>\n";
+        out << "  __device__ __forceinline__ static void run(MP M, GP gout) {\n" << em.os.str() << "  }\n};\n";
+    }
+    for (int q = 0; q < STAGE_R; ++q) {
+        em.os.str("");
+        em.graphs_reverse_horner(graphs_of(pr, q));
+        std::ofstream out(dir + "/mtp_level" + L + "_r" + std::to_string(q) + ".inc");
+        out << "// generated by gen_contract for MTP level " << level << ", reverse pass of part " << q
+            << "; do not edit.\n#pragma once\n\n";
+        out << "template <> struct LevelReverse<" << level << ", " << q << "> {\n";
+        out << "  template <typename T, typename MP, typename DP>\n";
+        out << "  __device__ __forceinline__ static void run(MP M, DP dgin, T (&dM)[" << B.n_comp() << "]) {\n"
+            << em.os.str() << "  }\n};\n";
+    }
+    em.os.str("");
+    em.trie_walk_stream();
+    const std::string walk = em.os.str();
+    // flops of the whole program (the parts are disjoint)
+    const Counter cf = em.fwd, cr = em.rev;   // every graph once in each (the parts are disjoint)
+    std::ostringstream h;
+    h << "// generated by gen_contract for MTP level " << level << "; do not edit.\n";
+    h << "// " << B.graphs.size() << " connected graphs, " << B.n_lin() << " basis functions, " << B.n_comp()
+      << " moment components, " << B.n_rad << " radial functions; staged program.\n";
+    h << "#pragma once\n\n";
+    h << "template <> struct Level<" << level << "> {\n";
+    write_common(h, B, level);
+    h << "  // flops of the contraction program per neighborhood (mul/add = 1, fma = 2)\n";
+    h << "  static constexpr long FLOPS_GRAPHS = " << cf.flops() << ";\n";
+    h << "  static constexpr long FLOPS_TRIE = " << em.trie_count.flops() << ";\n";
+    h << "  static constexpr long FLOPS_REVERSE = " << cr.flops() << ";\n";
+    h << "  static constexpr bool STAGED = true;\n";
+    h << "  static constexpr int STAGE_G = " << STAGE_G << ", STAGE_R = " << STAGE_R << ";\n";
+    h << "\n  template <typename T, bool WB, typename GP, typename XP, typename BP, typename DP>\n";
+    h << "  __device__ __forceinline__ static void trie(GP gin, XP xi, BP Bout, DP dgout, T &V) {\n"
+      << walk << "  }\n";
+    h << "};\n";
+    std::ofstream out(dir + "/mtp_level" + L + ".inc");
+    out << h.str();
+    std::cout << "level " << level << ": graphs " << B.graphs.size() << " basis " << B.n_lin() << " comps "
+              << B.n_comp() << " flops graphs " << cf.flops() << " trie " << em.trie_count.flops() << " reverse "
+              << cr.flops() << " (staged: " << STAGE_G << " graph parts, " << STAGE_R << " reverse parts)\n";
+}
+
+bool force_staged = false;   // --staged: every level as a staged program (for checking the two forms)
+bool force_single = false;   // --single: every level as one program
+
 void write_level(const std::string &dir, int level) {
     Basis B = build_basis(level);
+    if (force_staged || (!force_single && (int)B.graphs.size() > STAGED_GRAPHS))
+        return write_level_staged(dir, level, B);
     Emitter em(B);
     std::vector<int> all(B.graphs.size());
     for (size_t G = 0; G < all.size(); ++G) all[G] = (int)G;
@@ -335,6 +588,7 @@ void write_level(const std::string &dir, int level) {
     h << "  static constexpr long FLOPS_GRAPHS = " << cf.flops() << ";\n";
     h << "  static constexpr long FLOPS_TRIE = " << ct.flops() << ";\n";
     h << "  static constexpr long FLOPS_REVERSE = " << cr.flops() << ";\n";
+    h << "  static constexpr bool STAGED = false;\n";
     h << "  static constexpr int NPART = " << NPART << ";\n";
     h << "  static constexpr int graph_part[" << B.graphs.size() << "] = {";
     for (size_t G = 0; G < B.graphs.size(); ++G) h << (G ? "," : "") << s4.part[G];
@@ -398,6 +652,12 @@ int main(int argc, char **argv) {
         std::cerr << "usage: gen_contract <out_dir> <level>...\n";
         return 2;
     }
-    for (int i = 2; i < argc; ++i) write_level(argv[1], std::atoi(argv[i]));
+    for (int i = 2; i < argc; ++i) {
+        if (std::string(argv[i]) == "--staged" || std::string(argv[i]) == "--single") {
+            (argv[i][2] == 's' && argv[i][3] == 't' ? force_staged : force_single) = true;
+            continue;
+        }
+        write_level(argv[1], std::atoi(argv[i]));
+    }
     return 0;
 }

@@ -84,6 +84,7 @@ struct mtp_model {
     // scratch of the evaluation path
     mutable mtp::DevBuf gbuf, virial, sitebuf, brow, gamma_ws, argmax_ws, work, sums, mbuf, dmbuf, tbuf, dtbuf, rows;
     mutable mtp::DevBuf selblk;     // per-block preselection counts written by the grade kernels
+    mutable mtp::DevBuf gval, dgval;   // staged levels: graph values and dV/dg between the launches
     mutable mtp::DevBuf cfgrows, cfgpart;   // configuration-mode rows and their chunk partials
     mutable mtp::DevBuf md_f, md_g, md_invm, md_scal;   // MD driver: forces, grades, 1/mass, {gamma max, norms}
     mutable mtp::DevBuf md_v;                           // relaxation: FIRE velocities
@@ -123,6 +124,7 @@ void launch_column_sums(const void *rows, int precision, int64_t n, int ncol, do
                         DevBuf &work);
 std::vector<int> compiled_levels();
 long contraction_flops(int level);   // per neighborhood, from the generated program
+int staged_graphs(int level);        // connected graphs of a level compiled as a staged program, else 0
 
 void build_neighbors(const mtp_model *m, const mtp_system *s, int max_nbrs, mtp_nbrs *nb, hipStream_t st);
 

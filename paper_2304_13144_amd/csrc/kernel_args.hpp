@@ -40,6 +40,7 @@ struct EfsArgs {
     int lanes;                // lanes per neighborhood of the pair-gradient / row kernel (2, 4, 8)
     int lanes_mc;             // lanes per neighborhood of the moments / contraction (2, 4, 8; 4 = one launch)
     void *mbuf, *dmbuf;       // [NC][n_atoms] T: moments and dV/dM between the kernels
+    void *gval, *dgval;       // staged levels only: [NGRAPH][n_atoms] T graph values and dV/dg
     // optional (atom_list NULL only): the pair-gradient blocks also write the
     // per-32-atom partial sums of part_e (V_i, nullable) and virial into part
     double *part;
