@@ -151,6 +151,48 @@ def profile_summary(trace_dir, fetch_dir, write_dir, kernels):
     return "\n".join(out)
 
 
+COUNTER_KERNELS = ("efs_moments_contract", "efs_forces_rows", "grade_f64", "grade_i8", "select_write")
+
+
+def counter_summary(trace_dir, counter_dirs):
+    """Markdown table of rocprofv3 --pmc counters (mean per dispatch, summed
+    over the device) for the evaluation kernels, with derived figures: VALU
+    busy and s_waitcnt shares of the waves' cycles, LDS bank-conflict share,
+    and FP64 / FP32 FLOP/s counted from the per-type VALU instruction
+    counters (an FMA is 2 flops, x 64 lanes) over the average duration from
+    the trace run."""
+    import csv
+    import glob
+
+    vals = {}
+    for d in counter_dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                vals.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    stats = list(csv.DictReader(open(glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)[0])))
+    dur = {r["Name"]: float(r["AverageNs"]) for r in stats}
+    names = sorted({c for v in vals.values() for c in v})
+    out = ["| kernel | avg us | " + " | ".join(names) + " |", "|---|---|" + "---|" * len(names)]
+    derived = ["| kernel | VALU busy share (SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES) | "
+               "s_waitcnt share (SQ_WAIT_ANY / SQ_WAVE_CYCLES) | "
+               "LDS bank-conflict share (SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS) | FP64 TFLOP/s | FP32 TFLOP/s |",
+               "|---|---|---|---|---|---|"]
+    for k, c in vals.items():
+        if not any(s in k for s in COUNTER_KERNELS):
+            continue
+        m = {n: sum(v) / len(v) for n, v in c.items()}
+        us = dur.get(k, float("nan")) / 1e3
+        out.append(f"| `{k[:80]}` | {us:.2f} | " + " | ".join(f"{m.get(n, float('nan')):.0f}" for n in names) + " |")
+        g = lambda n: m.get(n, float("nan"))
+        f64 = 64 * (2 * g("SQ_INSTS_VALU_FMA_F64") + g("SQ_INSTS_VALU_MUL_F64") + g("SQ_INSTS_VALU_ADD_F64"))
+        f32 = 64 * (2 * g("SQ_INSTS_VALU_FMA_F32") + g("SQ_INSTS_VALU_MUL_F32") + g("SQ_INSTS_VALU_ADD_F32"))
+        derived.append(f"| `{k[:80]}` | "
+                       f"{g('SQ_ACTIVE_INST_VALU') / g('SQ_WAVE_CYCLES'):.3f} | {g('SQ_WAIT_ANY') / g('SQ_WAVE_CYCLES'):.3f} | "
+                       f"{g('SQ_LDS_BANK_CONFLICT') / g('SQ_ACTIVE_INST_LDS'):.3f} | {f64 / (us * 1e-6) / 1e12:.2f} | "
+                       f"{f32 / (us * 1e-6) / 1e12:.2f} |")
+    return "\n".join(out + [""] + derived)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +205,8 @@ def main():
                     help="oracle sample: this many atoms and all their neighbors (about 10-30 s of host time)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for scaling HBM counters)")
+    ap.add_argument("--counter-summary", nargs="+", metavar="DIR",
+                    help="print a markdown table of rocprofv3 --pmc output (TRACE_DIR then counter dirs) and exit")
     ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="print a markdown summary of rocprofv3 output and exit")
     ap.add_argument("--extra-workloads", action="store_true",
@@ -171,6 +215,9 @@ def main():
     a = ap.parse_args()
     if a.profile_summary:
         print(profile_summary(*a.profile_summary, kernels=TRAFFIC_KERNELS))
+        return 0
+    if a.counter_summary:
+        print(counter_summary(a.counter_summary[0], a.counter_summary[1:]))
         return 0
     if a.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {a.gpus}); this benchmark measures one GPU only",
@@ -321,6 +368,9 @@ def main():
                     "grade": {"int8-slices": f"grade_i8<{(m + 63) // 64}>", "fp64-registers": "grade_f64<",
                               "fp64-lds": "grade_f64_wide<"}[gform]}[dom]
     traffic = recorded_traffic(rocprof_name)
+    # the rate this part sustains on the grade's MFMA form (register operands, no memory)
+    ceiling = {"f64_tflops": api.mfma_rate("f64"), "i8_tops": api.mfma_rate("i8")}
+    log(f"[bench] sustained MFMA rate: FP64 {ceiling['f64_tflops']:.1f} TFLOP/s, int8 {ceiling['i8_tops']:.0f} TOP/s")
     out = {
         "metric": "atom-steps/s (E+F+stress+grade), level-16 MTP",
         "value": r["atom_steps_per_s"],
@@ -350,7 +400,10 @@ def main():
         "roofline": {"bound": d["bound"], "achieved": d["tflops"], "peak": d["peak_tflops"],
                      "unit": d.get("unit", "TFLOP/s"),
                      "frac": d["tflops"] / d["peak_tflops"], "traffic": traffic, "kernel": rocprof_name,
-                     "flops_per_atom": d["flops_per_atom"], "atoms_per_launch": cfg.n, "avg_us": d["avg_us"]},
+                     "flops_per_atom": d["flops_per_atom"], "atoms_per_launch": cfg.n, "avg_us": d["avg_us"],
+                     "sustained_mfma": ceiling,
+                     "frac_of_sustained": (d["tflops"] / (ceiling["i8_tops"] if i8 else ceiling["f64_tflops"])
+                                           if d["bound"] == "mfma" else None)},
         "evaluation_kernels": per_kernel,
         "forms": {p: {k: (round(v, 5) if isinstance(v, float) else v) for k, v in res.items() if k != "kernels"}
                   | {"kernels_us": {k: round(x["avg_us"], 2) for k, x in res["kernels"].items()}}

@@ -380,6 +380,17 @@ int mtp_profile_read(const char *kernel, double *total_ms /* host */, int64_t *l
 int mtp_tune(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
              int32_t *lanes /* host */, int32_t *grade /* host, nullable */, void *stream);
 
+/* Sustained MFMA rate of this GPU (measurement helper): a full grid of
+ * eight wavefronts per CU runs four independent accumulation chains each of
+ * one MFMA form on register operands (kind 0: v_mfma_f64_16x16x4, FP64;
+ * kind 1: v_mfma_i32_16x16x64_i8) for `iters` iterations (rounded up to a
+ * multiple of 16); *tflops (host)
+ * receives the rate of the second of two launches in TFLOP/s (TOP/s for
+ * int8).  The ceiling a kernel built on that form can reach, beside the
+ * nominal peak.  Synchronises `stream`; MTP_E_INVAL for a bad kind or
+ * iters outside 1 .. 2^24. */
+int mtp_mfma_rate(int kind, int32_t iters, double *tflops /* host */, void *stream);
+
 /* Description of the basis of a level, one function per line (host). */
 int mtp_basis_describe(int32_t level, char *buf, size_t len, int32_t *n_lin);
 

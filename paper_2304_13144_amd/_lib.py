@@ -22,7 +22,7 @@ EXPORTS = ("mtp_load", "mtp_save", "mtp_create", "mtp_free", "mtp_info", "mtp_se
            "mtp_set_active_set", "mtp_get_active_set", "mtp_nbrs_create", "mtp_nbrs_free", "mtp_build_neighbors",
            "mtp_nbrs_status", "mtp_nbrs_export", "mtp_energy_forces_stress", "mtp_energy_forces_stress_noalloc", "mtp_grade", "mtp_grade_cfg", "mtp_evaluate",
            "mtp_evaluate_select", "mtp_b_rows", "mtp_select", "mtp_maxvol_update", "mtp_cut_neighborhood", "mtp_md_run", "mtp_relax_fire", "mtp_fit_bfgs", "mtp_efs_backward", "mtp_basis_describe",
-           "mtp_compiled_levels", "mtp_last_error", "mtp_profile_enable", "mtp_profile_read", "mtp_tune")
+           "mtp_compiled_levels", "mtp_last_error", "mtp_profile_enable", "mtp_profile_read", "mtp_tune", "mtp_mfma_rate")
 
 
 class MtpError(RuntimeError):
@@ -103,6 +103,7 @@ def lib():
         "mtp_tune": [P, ctypes.POINTER(System), P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(I32),
                      ctypes.POINTER(I32), P],
         "mtp_profile_read": [ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I64)],
+        "mtp_mfma_rate": [ctypes.c_int, ctypes.c_int32, ctypes.POINTER(D), P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)

@@ -464,6 +464,14 @@ def tune(model, batch, nbrs, precision="fp64", mode="full", with_grade=False):
     return lanes.value >> 4, lanes.value & 15
 
 
+def mfma_rate(kind, iters=20000):
+    """Sustained MFMA rate of this GPU in TFLOP/s (TOP/s for int8): kind
+    "f64" (v_mfma_f64_16x16x4) or "i8" (v_mfma_i32_16x16x64_i8)."""
+    out = ctypes.c_double()
+    check(_lib.lib().mtp_mfma_rate({"f64": 0, "i8": 1}[kind], iters, ctypes.byref(out), _stream()))
+    return out.value
+
+
 def basis_describe(level):
     n = ctypes.c_int32()
     buf = ctypes.create_string_buffer(1 << 22)
@@ -479,7 +487,7 @@ def compiled_levels():
 
 __all__ = ["Model", "Batch", "Neighbors", "energy_forces_stress", "energy_forces_stress_noalloc", "grade", "grade_cfg", "cfg_rows", "evaluate",
            "b_rows", "select", "cut_neighborhood", "md_run", "relax_fire", "fit_bfgs",
-           "maxvol_update", "efs_backward", "MTPEnergy", "tune", "CapturedStep", "basis_describe", "compiled_levels", "MtpError"]
+           "maxvol_update", "efs_backward", "MTPEnergy", "tune", "CapturedStep", "basis_describe", "compiled_levels", "mfma_rate", "MtpError"]
 
 
 class CapturedStep:

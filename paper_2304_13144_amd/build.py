@@ -31,7 +31,7 @@ HIP_FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wno-unuse
              "-I", CSRC, "-I", GEN]
 HOST_SOURCES = ["api.cpp", "basis.cpp", "prof.cpp"]
 # what the generated per-level units include (besides their level's program)
-KERNEL_HEADERS = ["efs_kernel.hpp", "efs_staged.hpp", "backward_kernel.hpp", "kernel_args.hpp", "device_util.hpp"]
+KERNEL_HEADERS = ["efs_kernel.hpp", "backward_kernel.hpp", "kernel_args.hpp", "device_util.hpp"]
 HIP_SOURCES = ["neighbors.hip", "ops.hip", "grade.hip"]
 
 
@@ -157,8 +157,8 @@ def build(levels=DEFAULT_LEVELS, jobs=None, verbose=True, force=True):
     units, dispatch = generate(levels)
     mt = os.path.getmtime
     # the per-level units see only the kernel headers and their level's program
-    kernel_deps = [os.path.join(CSRC, f) for f in KERNEL_HEADERS] + [os.path.abspath(__file__)]
-    kernel_mtime = max(mt(d) for d in kernel_deps)
+    kernel_mtime = max(mt(d) for d in [os.path.join(CSRC, f) for f in KERNEL_HEADERS] + [os.path.abspath(__file__)])
+    staged_mtime = max(kernel_mtime, mt(os.path.join(CSRC, "efs_staged.hpp")))
     deps = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
     deps += [os.path.join(os.path.dirname(HERE), "include", "mtp.h"), os.path.abspath(__file__)]
     host_mtime = max(mt(d) for d in deps)
@@ -170,7 +170,8 @@ def build(levels=DEFAULT_LEVELS, jobs=None, verbose=True, force=True):
         if src in units:
             level = "".join(ch for ch in os.path.basename(src).split("_")[1] if ch.isdigit())
             progs = [f for f in os.listdir(GEN) if f == f"mtp_level{level}.inc" or f.startswith(f"mtp_level{level}_")]
-            dm = max([kernel_mtime] + [mt(os.path.join(GEN, f)) for f in progs])
+            staged_unit = any(f.startswith(f"mtp_level{level}_") for f in progs)
+            dm = max([staged_mtime if staged_unit else kernel_mtime] + [mt(os.path.join(GEN, f)) for f in progs])
         else:
             dm = host_mtime
         if force or _stale(src, obj, dm):

@@ -1397,6 +1397,13 @@ int mtp_tune(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precisio
     API_END
 }
 
+int mtp_mfma_rate(int kind, int32_t iters, double *tflops, void *stream) {
+    API_BEGIN
+    MTP_CHECK(tflops, MTP_E_INVAL, "NULL argument");
+    *tflops = mfma_rate(kind, iters, S(stream));
+    API_END
+}
+
 int mtp_basis_describe(int32_t level, char *buf, size_t len, int32_t *n_lin) {
     API_BEGIN
     Basis b = build_basis(level);

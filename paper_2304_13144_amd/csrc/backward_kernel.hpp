@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void bwd_tangent_moments(const BwdArgs b) {
             }
 #pragma unroll
             for (int mu = 0; mu < NR; ++mu) {
-                const T *cm = c_s + ((mu * nt + c.zi) * nt + zj) * NPOLY;
+                const CoefRow<T> cm = coef_row(c_s, mu, c.zi, zj, nt);
                 T s = T(0), sp = T(0);
 #pragma unroll
                 for (int q = 0; q < NPOLY; ++q) {

@@ -116,11 +116,29 @@ template <typename A> __device__ inline int tcount(const A &a, const AtomCtx &c,
     return c.live ? a.tcnt[c.atom * a.n_types + t] : 0;
 }
 
+// The radial coefficients c_{mu, z_i, z_j, beta} in LDS as
+// [mu][beta][z_i][z_j], the species padded to MAX_TYPES: the lanes of a
+// wavefront, whose pairs have different (z_i, z_j), read one (mu, beta) at a
+// time from one 16-word row (no bank conflicts; the parameter order
+// [mu][z_i][z_j][beta] puts them NPOLY words apart), and beta steps by a
+// constant offset.
+constexpr int COEF_TT = MAX_TYPES * MAX_TYPES;
 template <typename T, int NR, int BS = 256> __device__ inline void load_coefs(const EfsArgs &a, T *c_s) {
     const T *cg = coef_of<T>(a);
-    const int ncoef = NR * a.n_types * a.n_types * NPOLY;
-    for (int k = threadIdx.x; k < ncoef; k += BS) c_s[k] = cg[k];
+    const int nt = a.n_types, ntt = nt * nt;
+    const int ncoef = NR * ntt * NPOLY;
+    for (int k = threadIdx.x; k < ncoef; k += BS) {
+        const int b = k % NPOLY, pair = (k / NPOLY) % ntt, mu = k / (NPOLY * ntt);
+        c_s[(mu * NPOLY + b) * COEF_TT + (pair / nt) * MAX_TYPES + pair % nt] = cg[k];
+    }
     __syncthreads();
+}
+template <typename T> struct CoefRow {   // c_{mu, z_i, z_j, beta} over beta, from the LDS copy
+    const T *p;
+    __device__ T operator[](int b) const { return p[b * COEF_TT]; }
+};
+template <typename T> __device__ inline CoefRow<T> coef_row(const T *c_s, int mu, int zi, int zj, int) {
+    return CoefRow<T>{c_s + mu * NPOLY * COEF_TT + zi * MAX_TYPES + zj};
 }
 
 // ---- kernel 1: moments (eq. 3), LANES lanes per neighborhood -------------
@@ -168,7 +186,7 @@ __device__ inline void moments_scattered(const EfsArgs &a, const AtomCtx &c, con
             for (int b = 2; b < NPOLY; ++b) Tb[b] = fma(T(2) * u, Tb[b - 1], -Tb[b - 2]);
 #pragma unroll
             for (int mu = 0; mu < NR; ++mu) {
-                const T *cm = c_s + ((mu * nt + c.zi) * nt + zj) * NPOLY;
+                const CoefRow<T> cm = coef_row(c_s, mu, c.zi, zj, nt);
                 T s = T(0);
 #pragma unroll
                 for (int b = 0; b < NPOLY; ++b) s = fma(cm[b], Tb[b], s);
@@ -524,7 +542,7 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
                     chebyshev<T, true>(u, Tb, dT);
 #pragma unroll
                     for (int mu = 0; mu < NR; ++mu) {
-                        const T *cm = c_s + ((mu * nt + c.zi) * nt + t) * NPOLY;
+                        const CoefRow<T> cm = coef_row(c_s, mu, c.zi, t, nt);
                         T s = T(0), sp = T(0);
 #pragma unroll
                         for (int b = 0; b < NPOLY; ++b) {

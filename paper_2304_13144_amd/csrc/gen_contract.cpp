@@ -271,14 +271,19 @@ struct Emitter {
         }
     }
     // graph values of `gl` in Horner form, written to gout[G]
+    // (a compiler barrier after every GROUP graphs bounds how many moments
+    // are held at once; within a group their loads overlap)
+    static constexpr int FWD_GROUP = 4;
     void graphs_forward_horner(const std::vector<int> &gl) {
         os << "  // graph values (Horner form over the factor-prefix tree)\n";
+        int i = 0;
         for (int G : gl) {
             const HTree t = htree(B.polys[G]);
             os << "  {  // " << B.graphs[G].str() << ", " << B.polys[G].size() << " monomials\n";
             os << "T a0 = T(0);\n";
             h_children(t, t.roots, 0, false, "", fwd);
-            os << "gout[" << G << "] = a0;\n  }\n  MTP_STAGE_BARRIER();\n";
+            os << "gout[" << G << "] = a0;\n  }\n";
+            if (++i % FWD_GROUP == 0) os << "  MTP_STAGE_BARRIER();\n";
         }
     }
     // dV/dM of the graphs `gl` in Horner form (dg from dgin[G]); a compiler

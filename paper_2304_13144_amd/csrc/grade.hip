@@ -891,6 +891,83 @@ void launch_grade(const ActiveSet &as, int precision, const double *brow, int ld
     }
 }
 
+// ---- sustained MFMA rate -----------------------------------------------------
+// Every wavefront of a grid of eight wavefronts per CU (two per SIMD, as in
+// the grade kernels) runs CH independent accumulation chains of one MFMA
+// form on register operands, no memory traffic in the loop: the rate it
+// reaches is the ceiling of a kernel built on that form on this part, the
+// figure the grade kernels' measured rates compare with beside the nominal
+// peak.  The operands are perturbed per iteration (no loop-invariant
+// products) and every accumulator is written out at the end.
+constexpr int MC_CH = 4;
+__global__ __launch_bounds__(256) void mfma_rate_f64(int iters, double *sink) {
+    const int lane = threadIdx.x & 63;
+    double a = 1.0 + 1e-3 * lane, b = 1.0 - 1e-3 * lane;
+    doublex4 acc[MC_CH];
+#pragma unroll
+    for (int c = 0; c < MC_CH; ++c) acc[c] = doublex4{0.0, 0.0, 0.0, 0.0};
+    for (int it = 0; it < iters; it += 16) {   // 16 x MC_CH products per trip: the loop overhead is noise
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+#pragma unroll
+            for (int c = 0; c < MC_CH; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+        a = a * 0.999999 + 1e-9;
+    }
+    double t = 0.0;
+#pragma unroll
+    for (int c = 0; c < MC_CH; ++c) t += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+    sink[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = t;
+}
+__global__ __launch_bounds__(256) void mfma_rate_i8(int iters, double *sink) {
+    const int lane = threadIdx.x & 63;
+    i32x4 a = {lane, 3 * lane, 5 * lane, 7 * lane}, b = {1, 2, 3, 4};
+    i32x4 acc[MC_CH];
+#pragma unroll
+    for (int c = 0; c < MC_CH; ++c) acc[c] = i32x4{0, 0, 0, 0};
+    for (int it = 0; it < iters; it += 16) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+#pragma unroll
+            for (int c = 0; c < MC_CH; ++c) acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[c], 0, 0, 0);
+        a[0] ^= it;
+    }
+    int t = 0;
+#pragma unroll
+    for (int c = 0; c < MC_CH; ++c) t += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+    sink[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = (double)t;
+}
+
+double mfma_rate(int kind, int iters, hipStream_t st) {
+    MTP_CHECK(kind == 0 || kind == 1, MTP_E_INVAL, "mfma rate: kind 0 (FP64 16x16x4) or 1 (int8 16x16x64)");
+    MTP_CHECK(iters > 0 && iters <= (1 << 24), MTP_E_INVAL, "mfma rate: iters in 1 .. 2^24");
+    iters = (iters + 15) / 16 * 16;   // whole trips of the unrolled loop
+    int dev = 0, cus = 0;
+    MTP_HIP(hipGetDevice(&dev));
+    MTP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const unsigned blocks = (unsigned)cus * 2;   // 2 x 256 threads = eight wavefronts per CU
+    DevBuf sink;
+    sink.ensure(sizeof(double) * blocks * 256);
+    hipEvent_t e0, e1;
+    MTP_HIP(hipEventCreate(&e0));
+    MTP_HIP(hipEventCreate(&e1));
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {   // the first launch warms the clocks up
+        MTP_HIP(hipEventRecord(e0, st));
+        if (kind == 0)
+            hipLaunchKernelGGL(mfma_rate_f64, dim3(blocks), dim3(256), 0, st, iters, sink.as<double>());
+        else
+            hipLaunchKernelGGL(mfma_rate_i8, dim3(blocks), dim3(256), 0, st, iters, sink.as<double>());
+        MTP_HIP(hipEventRecord(e1, st));
+        MTP_HIP(hipEventSynchronize(e1));
+        MTP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const double per = kind == 0 ? 2.0 * 16 * 16 * 4 : 2.0 * 16 * 16 * 64;   // flops (ops) per MFMA
+    const double total = per * MC_CH * (double)iters * blocks * 4;           // 4 wavefronts per block
+    return total / (ms * 1e-3) / 1e12;
+}
+
 void launch_invert(ActiveSet &as, const double *A, hipStream_t st, DevBuf &work, int *singular_host) {
     const int m = as.m;
     const size_t wsz = (size_t)2 * m * m;

@@ -154,6 +154,7 @@ void launch_grade(const ActiveSet &as, int precision, const double *brow, int ld
                   double *gamma, int32_t *argmax, hipStream_t st, double thr = 0.0, int32_t *sel_blk = nullptr,
                   int sched = GRADE_AUTO);
 void prepare_split(ActiveSet &as, hipStream_t st);
+double mfma_rate(int kind, int iters, hipStream_t st);   // TFLOP/s (TOP/s) sustained; synchronises st
 bool slice_product_fits(int m);
 void launch_invert(ActiveSet &as, const double *A, hipStream_t st, DevBuf &work, int *singular_host);
 void launch_select(const double *gamma, int64_t n, double thr, int32_t *idx, int32_t cap, int32_t *count,

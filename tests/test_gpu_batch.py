@@ -136,3 +136,16 @@ def test_graph_replay_reports_neighbor_overflow_after_atoms_move():
     with pytest.raises(api.MtpError) as e:
         step.replay()
     assert e.value.status == "MTP_E_CAPACITY"
+
+
+def test_sustained_mfma_rate_is_plausible():
+    """The measurement helper behind the roofline's sustained-rate figure:
+    positive, below the nominal dense peaks (FP64 78.6 TFLOP/s, int8 5.0
+    POP/s) with a small margin, and bad arguments are refused."""
+    f64 = api.mfma_rate("f64", 2000)
+    i8 = api.mfma_rate("i8", 2000)
+    print(f"sustained MFMA: FP64 {f64:.1f} TFLOP/s, int8 {i8:.0f} TOP/s")
+    assert 1.0 < f64 < 78.6 * 1.05
+    assert 50.0 < i8 < 5000.0 * 1.05
+    with pytest.raises(api.MtpError):
+        api.mfma_rate("f64", 0)
