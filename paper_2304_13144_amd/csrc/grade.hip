@@ -198,9 +198,9 @@ __global__ __launch_bounds__(512) void grade_f64_wide(const double *__restrict__
 // k = 4 s + l / 16, column 16 tile + l % 16, zero past m), so each half stages
 // its tile into LDS as one contiguous copy (double-buffered, the next tile's
 // loads in flight during the MFMAs, one barrier per tile) and a wavefront
-// reads its operand with one 8-byte LDS read per k step.  Even and odd k
-// steps go to two accumulators (two independent MFMA chains), added at the
-// end of the tile; the two halves' maxima meet in LDS at the end.
+// reads its operand with one 8-byte LDS read per k step.  The k steps go
+// round-robin to four accumulators (four independent MFMA chains), added at
+// the end of the tile; the two halves' maxima meet in LDS at the end.
 constexpr int GR_NK_MAX = 9;   // 32-k chunks: m <= 288 (two halves x two buffers of a tile in LDS)
 template <int NK>
 __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow, int64_t ldn, int64_t n,
@@ -242,21 +242,29 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
     double best[4] = {-1.0, -1.0, -1.0, -1.0};
     int bidx[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
     stash(0);
+    // the rows are waited for here, once: with their loads still counted at
+    // the loop's entry, every tile's products would also wait for the next
+    // tile's prefetch (the load counter is in order), exposing its latency
+#pragma unroll
+    for (int s = 0; s < KS; ++s) __asm__ volatile("" ::"v"(a[s]));
     __syncthreads();
     for (int st = 0; st < nstep; ++st) {
         const int buf = st & 1, tile = 2 * st + half;
         if (st + 1 < nstep) fetch(tile + 2);
-        doublex4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+        doublex4 acc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = doublex4{0.0, 0.0, 0.0, 0.0};
         const double *b = reinterpret_cast<const double *>(sB[half][buf]) + lane;
 #pragma unroll
-        for (int s = 0; s < KS; s += 2) {
-            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[64 * s], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s + 1], b[64 * (s + 1)], acc1, 0, 0, 0);
-        }
+        for (int s = 0; s < KS; s += 4)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s + c], b[64 * (s + c)], acc[c], 0, 0, 0);
         const int col = 16 * tile + lr;
         if (col < m)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) better(fabs(acc0[r] + acc1[r]), col, best[r], bidx[r]);
+            for (int r = 0; r < 4; ++r)
+                better(fabs((acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r])), col, best[r], bidx[r]);
         if (st + 1 < nstep) stash(buf ^ 1);
         __syncthreads();
     }
@@ -282,6 +290,102 @@ __global__ __launch_bounds__(512) void grade_f64(const double *__restrict__ brow
         better(s_best[1][tid], s_idx[1][tid], bv, bc);
         const int64_t row = (int64_t)blockIdx.x * GF_ROWS + tid;
         const bool live = row < n;
+        if (live) {
+            gamma[row] = bv;
+            if (argmax) argmax[row] = bc;
+        }
+        const unsigned long long sel = __ballot(live && bv > thr);
+        if (sel_blk && tid == 0) sel_blk[blockIdx.x] = __popcll(sel);
+    }
+}
+
+// The same product in blocks of 256 threads = 32 rows x two halves of the
+// column tiles, one LDS buffer per half (57 KB at m = 212), so that two
+// blocks share a CU: one block's barriers, tile staging and epilogues then
+// overlap the other's MFMAs (with one block per CU every wavefront of the CU
+// meets the same barrier at the same time, and the MFMA units idle through
+// it).  Per tile: barrier (every wavefront has read the buffer), the next
+// tile's pieces from registers into LDS, barrier, the next-but-one tile's
+// loads issued, the products.  Counts of gamma > thr per 32 rows.
+constexpr int GF2_ROWS = 32;
+template <int NK>
+__global__ __launch_bounds__(256, 2) void grade_f64_pair(const double *__restrict__ brow, int64_t ldn, int64_t n,
+                                                         const double *__restrict__ L, int m, double *gamma,
+                                                         int32_t *argmax, double thr, int32_t *sel_blk) {
+    constexpr int KS = 8 * NK;                 // k steps of four
+    constexpr int TILE = KS * 64;              // doubles of one column tile
+    constexpr int PER = TILE / 2 / 128;        // 16-byte pieces per thread of a half
+    static_assert(PER * 256 == TILE, "tile staging");
+    __shared__ doublex2 sB[2][TILE / 2];       // [half]
+    __shared__ double s_best[2][GF2_ROWS];
+    __shared__ int s_idx[2][GF2_ROWS];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int rg = wave & 1, half = wave >> 1, ht = tid & 127;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int64_t row0 = (int64_t)blockIdx.x * GF2_ROWS + rg * 16;
+    const int ntile = (m + 15) / 16;
+    const int nstep = (ntile + 1) / 2;         // tiles per half, rounded up (both halves pass every barrier)
+    doublex2 pre[PER];
+    auto fetch = [&](int tile) {               // unconditional: past the last tile, an in-bounds tile
+        tile = tile < ntile ? tile : ntile - 1;
+        const doublex2 *src = reinterpret_cast<const doublex2 *>(L + (int64_t)tile * TILE);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) pre[q] = src[ht + 128 * q];
+    };
+    fetch(half);
+    double a[KS];
+    {
+        const double *bp = brow + min(row0 + lr, n - 1) + (int64_t)lk * ldn;   // rows past n: clamped, never written
+#pragma unroll
+        for (int s = 0; s < KS; ++s) a[s] = bp[(int64_t)(4 * s) * ldn];
+    }
+    double best[4] = {-1.0, -1.0, -1.0, -1.0};
+    int bidx[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
+    for (int st = 0; st < nstep; ++st) {
+        const int tile = 2 * st + half;
+        __syncthreads();   // every wavefront has read the buffer (and, at st = 0, nothing has)
+#pragma unroll
+        for (int q = 0; q < PER; ++q) sB[half][ht + 128 * q] = pre[q];
+        __syncthreads();
+        fetch(tile + 2);
+        doublex4 acc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = doublex4{0.0, 0.0, 0.0, 0.0};
+        const double *b = reinterpret_cast<const double *>(sB[half]) + lane;
+#pragma unroll
+        for (int s = 0; s < KS; s += 4)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s + c], b[64 * (s + c)], acc[c], 0, 0, 0);
+        const int col = 16 * tile + lr;
+        if (col < m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                better(fabs((acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r])), col, best[r], bidx[r]);
+    }
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double ov = __shfl_xor(best[r], o, 64);
+            const int oc = __shfl_xor(bidx[r], o, 64);
+            better(ov, oc, best[r], bidx[r]);
+        }
+    if (lr == 0)   // f64 layout: lane l, register r -> row l / 16 + 4 r
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            s_best[half][rg * 16 + lk + 4 * r] = best[r];
+            s_idx[half][rg * 16 + lk + 4 * r] = bidx[r];
+        }
+    __syncthreads();
+    if (tid < 64) {   // wavefront 0: one row per lane (32 rows)
+        const int q = tid < GF2_ROWS ? tid : 0;
+        double bv = s_best[0][q];
+        int bc = s_idx[0][q];
+        better(s_best[1][q], s_idx[1][q], bv, bc);
+        const int64_t row = (int64_t)blockIdx.x * GF2_ROWS + tid;
+        const bool live = tid < GF2_ROWS && row < n;
         if (live) {
             gamma[row] = bv;
             if (argmax) argmax[row] = bc;
@@ -441,7 +545,12 @@ __global__ __launch_bounds__(512) void grade_i8(const double *__restrict__ brow,
     __syncthreads();
     for (int st = 0; st < nstep; ++st) {
         const int buf = st & 1, tile = 2 * st + half;
-        if (st + 1 < nstep) fetch(tile + 2);
+        // this tile's column scales before the next tile's prefetch: waiting
+        // for them then leaves the prefetch in flight (the load counter is in
+        // order, and the prefetch is issued on every path)
+        const int col = 16 * tile + lr;
+        const int fe = fexp[col < CP ? col : CP - 1];
+        fetch(tile + 2);   // unconditional (clamped to a valid tile at the end), so that the wait count is known
         const i32x4 *sB = sm + (2 * half + buf) * TILE;
         i32x4 acc[GI_LEV];
 #pragma unroll
@@ -461,8 +570,7 @@ __global__ __launch_bounds__(512) void grade_i8(const double *__restrict__ brow,
                 for (int b = 0; a + b <= GI_SL && b < GI_SL; ++b)
                     acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[a][s], B[s & 1][b], acc[a + b], 0, 0, 0);
         }
-        const int col = 16 * tile + lr;
-        const double cs = ldexp(1.0, fexp[col < CP ? col : CP - 1]);
+        const double cs = ldexp(1.0, fe);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             // levels 0 + 1, 2 + 3, 4 + 5 exactly in int32 (|acc_q| < 2^23), then FP64:
@@ -819,6 +927,14 @@ static void launch_grade_f64(const ActiveSet &as, const double *brow, int64_t ld
                        argmax, thr, sel_blk);
 }
 
+template <int NK>
+static void launch_grade_f64_pair(const ActiveSet &as, const double *brow, int64_t ldn, int64_t n, double *gamma,
+                                  int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
+    const dim3 grid((unsigned)((n + GF2_ROWS - 1) / GF2_ROWS));
+    hipLaunchKernelGGL(grade_f64_pair<NK>, grid, dim3(256), 0, st, brow, ldn, n, as.lane64.as<double>(), as.m, gamma,
+                       argmax, thr, sel_blk);
+}
+
 template <int KS>
 static void launch_grade_i8(const ActiveSet &as, const double *brow, int ldb, int64_t ldn, int64_t n, double *gamma,
                             int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
@@ -831,6 +947,7 @@ bool grade_sched_valid(const ActiveSet &as, int precision, int sched) {
     switch (sched) {
         case GRADE_AUTO: return true;
         case GRADE_F64_REG: return as.m <= 32 * GR_NK_MAX;
+        case GRADE_F64_PAIR: return as.m <= 32 * GR_NK_MAX;
         case GRADE_F64_LDS: return true;
         case GRADE_I8: return precision == MTP_MIXED && slice_product_fits(as.m);
         default: return false;
@@ -843,10 +960,15 @@ static int grade_sched_resolve(const ActiveSet &as, int precision, int sched) {
     return as.m <= 32 * GR_NK_MAX ? GRADE_F64_REG : GRADE_F64_LDS;
 }
 
+int grade_count_rows(const ActiveSet &as, int precision, int sched) {
+    return grade_sched_resolve(as, precision, sched) == GRADE_F64_PAIR ? GF2_ROWS : GRADE_ROWS;
+}
+
 void launch_grade(const ActiveSet &as, int precision, const double *brow, int ldb, int64_t ldn, int64_t n,
                   double *gamma, int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk, int sched) {
     // every form counts the preselection per block of the same 64 rows
     static_assert(GRADE_ROWS == GF_ROWS && GRADE_ROWS == GI_ROWS, "preselection blocks are grade blocks");
+    static_assert(GRADE_ROWS % GF2_ROWS == 0, "preselection blocks");
     MTP_CHECK(grade_sched_valid(as, precision, sched), MTP_E_INVAL, "grade: schedule not available for this m / precision");
     if (n == 0) return;
     MTP_CHECK(ldb >= (as.m + 31) / 32 * 32, MTP_E_INVAL, "grade: row length below the padded row length");
@@ -861,6 +983,22 @@ void launch_grade(const ActiveSet &as, int precision, const double *brow, int ld
             case 3: launch_grade_i8<3>(as, brow, ldb, ldn, n, gamma, argmax, st, thr, sel_blk); break;
             case 4: launch_grade_i8<4>(as, brow, ldb, ldn, n, gamma, argmax, st, thr, sel_blk); break;
             default: launch_grade_i8<5>(as, brow, ldb, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+        }
+        return;
+    }
+    if (sched == GRADE_F64_PAIR) {
+        MTP_CHECK(as.NK64 == (as.m + 31) / 32 && as.lane64.ptr, MTP_E_INVAL, "grade: A^-1 not staged");
+        MTP_CHECK(ldb >= 32 * as.NK64, MTP_E_INVAL, "grade: rows not padded to a multiple of 32 columns");
+        switch (as.NK64) {
+            case 1: launch_grade_f64_pair<1>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 2: launch_grade_f64_pair<2>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 3: launch_grade_f64_pair<3>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 4: launch_grade_f64_pair<4>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 5: launch_grade_f64_pair<5>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 6: launch_grade_f64_pair<6>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 7: launch_grade_f64_pair<7>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            case 8: launch_grade_f64_pair<8>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
+            default: launch_grade_f64_pair<9>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); break;
         }
         return;
     }

@@ -147,9 +147,12 @@ constexpr int GRADE_ROWS = 64;
 // grade schedules (kernel forms): GRADE_AUTO picks by precision and m;
 // GRADE_F64_REG: FP64 MFMA with the rows in registers (m <= 288);
 // GRADE_F64_LDS: FP64 MFMA with the rows staged through LDS (any m);
-// GRADE_I8: the int8 slice product (mixed form, m <= 320)
-enum { GRADE_AUTO = 0, GRADE_F64_REG = 1, GRADE_F64_LDS = 2, GRADE_I8 = 3 };
+// GRADE_I8: the int8 slice product (mixed form, m <= 320);
+// GRADE_F64_PAIR: as GRADE_F64_REG in blocks of 32 rows, two blocks per CU
+enum { GRADE_AUTO = 0, GRADE_F64_REG = 1, GRADE_F64_LDS = 2, GRADE_I8 = 3, GRADE_F64_PAIR = 4 };
 bool grade_sched_valid(const ActiveSet &as, int precision, int sched);
+// rows per preselection count the grade writes under a schedule (divides GRADE_ROWS)
+int grade_count_rows(const ActiveSet &as, int precision, int sched);
 void launch_grade(const ActiveSet &as, int precision, const double *brow, int ldb, int64_t ldn, int64_t n,
                   double *gamma, int32_t *argmax, hipStream_t st, double thr = 0.0, int32_t *sel_blk = nullptr,
                   int sched = GRADE_AUTO);

@@ -100,7 +100,8 @@ def test_grade_forms_agree_and_tuner_picks_one(precision):
     m = _model16()
     b = api.Batch([synth.workload2(reps=(6, 6, 6)).configs[0]])
     nb = api.Neighbors().build(m, b, max_nbrs=64)
-    forms = {"1": "fp64-registers", "2": "fp64-lds"} | ({"3": "int8-slices"} if precision == "mixed" else {})
+    forms = {"1": "fp64-registers", "2": "fp64-lds", "4": "fp64-registers-32-row-blocks"} | \
+        ({"3": "int8-slices"} if precision == "mixed" else {})
     lanes = api.tune(m, b, nb, precision, "full", with_grade=True)   # first: the lanes stay fixed below
     assert lanes[2] in forms.values()
     got = {}
@@ -110,8 +111,9 @@ def test_grade_forms_agree_and_tuner_picks_one(precision):
             got[k] = _np(api.evaluate(m, b, nb, precision, "full"))["gamma"]
         finally:
             del os.environ["MTP_GRADE_FORM"]
-    # the two FP64 products differ only in summation order
+    # the FP64 products differ only in summation order
     assert np.allclose(got["2"], got["1"], rtol=1e-12, atol=0)
+    assert np.allclose(got["4"], got["1"], rtol=1e-12, atol=0)
     if precision == "mixed":
         assert np.all(np.abs(got["3"] - got["1"]) <= 1e-5 * np.maximum(1.0, got["1"]))
     assert np.array_equal(_np(api.evaluate(m, b, nb, precision, "full"))["gamma"],
