@@ -24,14 +24,18 @@
 
 namespace mtp {
 
-// between the graphs of a reverse part: the moments are read again (from
-// cache) for each graph instead of all being held in registers
-#define MTP_STAGE_BARRIER() asm volatile("" ::: "memory")
-// the same in the trie walk, also pinning the running sum w of the parent
-// node (else its products are deferred to the end, every factor held until then)
+// in the trie walk, after every node: dV/dg goes back to memory and the
+// graph values are read again (a compiler barrier), and the running sum w of
+// the parent node is formed there (else its products are deferred to the
+// end, every factor held until then)
 #define MTP_STAGE_SYNC(w) asm volatile("" : "+v"(w) : : "memory")
 // a Horner sum formed where it is written (not deferred)
 #define MTP_STAGE_KEEP(a) asm volatile("" : "+v"(a))
+
+// between the graphs of a part: no instruction is scheduled across, so that
+// the graphs are not interleaved (which would hold the temporaries of many at
+// once on top of the part's moments and dV/dM)
+#define MTP_STAGE_SCHED() __builtin_amdgcn_sched_barrier(0)
 
 template <int L, int P> struct LevelGraphs;
 template <int L, int P> struct LevelReverse;
@@ -50,13 +54,23 @@ template <typename T, int NG> __device__ inline TileCol<T> tile_of(T *arr, int64
     return TileCol<T>{arr + tile * (int64_t)NG * 64, (uint32_t)(slot & 63)};
 }
 
+// the moment components a part uses, from memory into registers (the
+// others are never read)
+template <typename T, typename PART, int NC>
+__device__ inline void load_part_moments(const EfsArgs &a, int64_t slot, T (&M)[NC]) {
+    const T *mb = static_cast<const T *>(a.mbuf) + slot;
+#pragma unroll
+    for (int i = 0; i < PART::NM; ++i) M[PART::mcomp[i]] = mb[(int64_t)PART::mcomp[i] * a.n_atoms];
+}
+
 template <typename T, int L, int P>
 __global__ __launch_bounds__(256) void efs_graphs_stage(const EfsArgs a) {
     using LV = Level<L>;
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= a.n_atoms) return;
-    LevelGraphs<L, P>::template run<T>(ColLoad<T>{static_cast<const T *>(a.mbuf) + slot, a.n_atoms},
-                                       tile_of<T, LV::NGRAPH>(static_cast<T *>(a.gval), slot));
+    T M[LV::NC];
+    load_part_moments<T, LevelGraphs<L, P>>(a, slot, M);
+    LevelGraphs<L, P>::template run<T>(M, tile_of<T, LV::NGRAPH>(static_cast<T *>(a.gval), slot));
 }
 
 template <typename T, int L, bool WB>
@@ -87,14 +101,20 @@ __global__ __launch_bounds__(256) void efs_reverse_stage(const EfsArgs a) {
     using LV = Level<L>;
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= a.n_atoms) return;
-    T dM[LV::NC];
-    LevelReverse<L, P>::template run<T>(ColLoad<T>{static_cast<const T *>(a.mbuf) + slot, a.n_atoms},
-                                        tile_of<const T, LV::NGRAPH>(static_cast<const T *>(a.dgval), slot), dM);
+    using PART = LevelReverse<L, P>;
+    T M[LV::NC], dM[LV::NC];
+    load_part_moments<T, PART>(a, slot, M);
+    PART::template run<T>(M, tile_of<const T, LV::NGRAPH>(static_cast<const T *>(a.dgval), slot), dM);
     T *out = static_cast<T *>(a.dmbuf) + slot;
+    if constexpr (P == 0) {   // part 0 writes every component (zero where it adds nothing)
 #pragma unroll
-    for (int k = 0; k < LV::NC; ++k) {   // parts add in a fixed order: deterministic
-        const int64_t o = (int64_t)k * a.n_atoms;
-        out[o] = P == 0 ? dM[k] : out[o] + dM[k];
+        for (int k = 0; k < LV::NC; ++k) out[(int64_t)k * a.n_atoms] = dM[k];
+    } else {                  // the others add to theirs, in part order: deterministic
+#pragma unroll
+        for (int i = 0; i < PART::NM; ++i) {
+            const int64_t o = (int64_t)PART::mcomp[i] * a.n_atoms;
+            out[o] = out[o] + dM[PART::mcomp[i]];
+        }
     }
 }
 

@@ -19,6 +19,7 @@
 #include <functional>
 #include <iostream>
 #include <map>
+#include <set>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -271,23 +272,17 @@ struct Emitter {
         }
     }
     // graph values of `gl` in Horner form, written to gout[G]
-    // (a compiler barrier after every GROUP graphs bounds how many moments
-    // are held at once; within a group their loads overlap)
-    static constexpr int FWD_GROUP = 4;
     void graphs_forward_horner(const std::vector<int> &gl) {
         os << "  // graph values (Horner form over the factor-prefix tree)\n";
-        int i = 0;
         for (int G : gl) {
             const HTree t = htree(B.polys[G]);
             os << "  {  // " << B.graphs[G].str() << ", " << B.polys[G].size() << " monomials\n";
             os << "T a0 = T(0);\n";
             h_children(t, t.roots, 0, false, "", fwd);
-            os << "gout[" << G << "] = a0;\n  }\n";
-            if (++i % FWD_GROUP == 0) os << "  MTP_STAGE_BARRIER();\n";
+            os << "gout[" << G << "] = a0;\n  }\n  MTP_STAGE_SCHED();\n";
         }
     }
-    // dV/dM of the graphs `gl` in Horner form (dg from dgin[G]); a compiler
-    // barrier between graphs keeps the moments from being held across them
+    // dV/dM of the graphs `gl` in Horner form (dg from dgin[G])
     void graphs_reverse_horner(const std::vector<int> &gl) {
         os << "  // dV/dM by reverse accumulation (Horner form over the factor-prefix tree)\n";
         hdm_set.assign(B.n_comp(), false);
@@ -296,7 +291,7 @@ struct Emitter {
             os << "  {  // " << B.graphs[G].str() << "\n";
             os << "const T q0 = dgin[" << G << "];\nT a0 = T(0);\n";
             h_children(t, t.roots, 0, true, "q0", rev);
-            os << "(void)a0;\n  }\n  MTP_STAGE_BARRIER();\n";
+            os << "(void)a0;\n  }\n  MTP_STAGE_SCHED();\n";
         }
         for (int k = 0; k < B.n_comp(); ++k)
             if (!hdm_set[k]) os << "  dM[" << k << "] = T(0);\n";
@@ -391,27 +386,54 @@ struct Emitter {
 constexpr int STAGED_GRAPHS = 128;
 constexpr int STAGE_G = 8, STAGE_R = 16;
 
-// Split of the graphs over np parts (largest first onto the least loaded
-// part; cost = monomial terms x degree).
-std::vector<int> split_graphs(const Basis &B, int np) {
-    std::vector<int> part(B.graphs.size(), 0);
-    std::vector<std::pair<long, int>> cost;
-    for (size_t G = 0; G < B.graphs.size(); ++G) {
-        long c = 0;
-        for (auto &t : B.polys[G]) c += (long)t.comp.size();
-        cost.push_back({c, (int)G});
+// Split for the staged program: graphs (largest first) go to the part whose
+// set of moment components grows least, among the parts whose cost stays
+// within 15 % of the mean (else the least loaded part): a part then reads
+// and writes few components (level 24: at most 44 of 91 in 8 parts, 38 in
+// 16), which its kernel holds in registers.
+std::vector<int> cluster_graphs(const Basis &B, int np) {
+    const size_t ng = B.graphs.size();
+    std::vector<std::set<int>> comp(ng);
+    std::vector<long> cost(ng, 0);
+    long total = 0;
+    for (size_t G = 0; G < ng; ++G) {
+        for (auto &t : B.polys[G]) {
+            comp[G].insert(t.comp.begin(), t.comp.end());
+            cost[G] += (long)t.comp.size();
+        }
+        total += cost[G];
     }
-    std::sort(cost.begin(), cost.end(),
-              [](auto &a, auto &b) { return a.first > b.first || (a.first == b.first && a.second < b.second); });
+    const double cap = 1.15 * (double)total / np;
+    std::vector<int> order(ng), part(ng, 0);
+    for (size_t G = 0; G < ng; ++G) order[G] = (int)G;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<std::set<int>> uni(np);
     std::vector<long> load(np, 0);
-    for (auto &c : cost) {
-        int best = 0;
-        for (int q = 1; q < np; ++q)
-            if (load[q] < load[best]) best = q;
-        part[c.second] = best;
-        load[best] += c.first;
+    for (int G : order) {
+        int best = -1;
+        size_t bu = 0;
+        for (int q = 0; q < np; ++q) {
+            if (load[q] > 0 && load[q] + cost[G] > cap) continue;
+            size_t u = uni[q].size();
+            for (int k : comp[G]) u += uni[q].count(k) ? 0 : 1;
+            if (best < 0 || u < bu || (u == bu && load[q] < load[best])) {
+                best = q;
+                bu = u;
+            }
+        }
+        if (best < 0) best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        part[G] = best;
+        uni[best].insert(comp[G].begin(), comp[G].end());
+        load[best] += cost[G];
     }
     return part;
+}
+
+std::vector<int> part_components(const Basis &B, const std::vector<int> &gl) {
+    std::set<int> u;
+    for (int G : gl)
+        for (auto &t : B.polys[G]) u.insert(t.comp.begin(), t.comp.end());
+    return std::vector<int>(u.begin(), u.end());
 }
 
 void write_common(std::ostringstream &h, const Basis &B, int level) {
@@ -450,7 +472,7 @@ void write_common(std::ostringstream &h, const Basis &B, int level) {
 // P (LevelReverse<L, P>::run), each included by its own translation unit.
 void write_level_staged(const std::string &dir, int level, const Basis &B) {
     Emitter em(B);
-    const std::vector<int> pg = split_graphs(B, STAGE_G), pr = split_graphs(B, STAGE_R);
+    const std::vector<int> pg = cluster_graphs(B, STAGE_G), pr = cluster_graphs(B, STAGE_R);
     auto graphs_of = [&](const std::vector<int> &part, int q) {
         std::vector<int> gl;
         for (size_t G = 0; G < B.graphs.size(); ++G)
@@ -464,7 +486,13 @@ void write_level_staged(const std::string &dir, int level, const Basis &B) {
         std::ofstream out(dir + "/mtp_level" + L + "_g" + std::to_string(q) + ".inc");
         out << "// generated by gen_contract for MTP level " << level << ", graph values of part " << q
             << "; do not edit.\n#pragma once\n\n";
+        const std::vector<int> mc = part_components(B, graphs_of(pg, q));
         out << "template <> struct LevelGraphs<" << level << ", " << q << "> {\n";
+        out << "  // the moment components this part reads\n";
+        out << "  static constexpr int NM = " << mc.size() << ";\n  static constexpr int mcomp[" << std::max<size_t>(1, mc.size()) << "] = {";
+        for (size_t i = 0; i < mc.size(); ++i) out << (i ? "," : "") << mc[i];
+        if (mc.empty()) out << "0";
+        out << "};\n";
         out << "  template <typename T, typename MP, typename GP>\n";
         out << "  __device__ __forceinline__ static void run(MP M, GP gout) {\n" << em.os.str() << "  }\n};\n";
     }
@@ -474,7 +502,13 @@ void write_level_staged(const std::string &dir, int level, const Basis &B) {
         std::ofstream out(dir + "/mtp_level" + L + "_r" + std::to_string(q) + ".inc");
         out << "// generated by gen_contract for MTP level " << level << ", reverse pass of part " << q
             << "; do not edit.\n#pragma once\n\n";
+        const std::vector<int> mc = part_components(B, graphs_of(pr, q));
         out << "template <> struct LevelReverse<" << level << ", " << q << "> {\n";
+        out << "  // the moment components this part reads and whose dV/dM it adds to (the others stay zero)\n";
+        out << "  static constexpr int NM = " << mc.size() << ";\n  static constexpr int mcomp[" << std::max<size_t>(1, mc.size()) << "] = {";
+        for (size_t i = 0; i < mc.size(); ++i) out << (i ? "," : "") << mc[i];
+        if (mc.empty()) out << "0";
+        out << "};\n";
         out << "  template <typename T, typename MP, typename DP>\n";
         out << "  __device__ __forceinline__ static void run(MP M, DP dgin, T (&dM)[" << B.n_comp() << "]) {\n"
             << em.os.str() << "  }\n};\n";

@@ -8,8 +8,8 @@
 #include <random>
 #define __device__
 #define __forceinline__ inline
-#define MTP_STAGE_BARRIER()
 #define MTP_STAGE_SYNC(w)
+#define MTP_STAGE_SCHED()
 #define MTP_STAGE_KEEP(a)
 using std::fma;
 namespace A {
