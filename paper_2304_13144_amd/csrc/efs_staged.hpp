@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void efs_trie_stage(const EfsArgs a) {
 }
 
 template <typename T, int L, int P>
-__global__ __launch_bounds__(256) void efs_reverse_stage(const EfsArgs a) {
+__global__ __launch_bounds__(256, 2) void efs_reverse_stage(const EfsArgs a) {
     using LV = Level<L>;
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= a.n_atoms) return;
