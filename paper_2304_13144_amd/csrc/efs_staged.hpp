@@ -74,12 +74,13 @@ __global__ __launch_bounds__(256) void efs_graphs_stage(const EfsArgs a) {
 }
 
 template <typename T, int L, bool WB>
-__global__ __launch_bounds__(256) void efs_trie_stage(const EfsArgs a) {
+__global__ __launch_bounds__(256) void efs_trie_stage(const EfsArgs a, const T *__restrict__ gval,
+                                                     T *__restrict__ dgval) {
     using LV = Level<L>;
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= a.n_atoms) return;
-    const TileCol<const T> gin = tile_of<const T, LV::NGRAPH>(static_cast<const T *>(a.gval), slot);
-    const TileCol<T> dg = tile_of<T, LV::NGRAPH>(static_cast<T *>(a.dgval), slot);
+    const TileCol<const T> gin = tile_of<const T, LV::NGRAPH>(gval, slot);
+    const TileCol<T> dg = tile_of<T, LV::NGRAPH>(dgval, slot);
     const XiPtr<T> xi{xi_of<T>(a)};
     T V = T(0);
     if constexpr (WB) {
@@ -162,10 +163,14 @@ static void launch_stages(const EfsArgs &a, std::integer_sequence<int, P...>, bo
         }                                                                                                \
         ProfScope ps("efs_contract", a.stream);                                                          \
         launch_stages<LEVEL, TT>(a, std::make_integer_sequence<int, LV::STAGE_G>{}, true);               \
+        const TT *gv = static_cast<const TT *>(a.gval);                                                   \
+        TT *dgv = static_cast<TT *>(a.dgval);                                                            \
         if (F64 && a.brow != nullptr)                                                                    \
-            hipLaunchKernelGGL((efs_trie_stage<TT, LEVEL, F64>), dim3(g256), dim3(256), 0, a.stream, a); \
+            hipLaunchKernelGGL((efs_trie_stage<TT, LEVEL, F64>), dim3(g256), dim3(256), 0, a.stream, a, gv, \
+                               dgv);                                                                     \
         else                                                                                             \
-            hipLaunchKernelGGL((efs_trie_stage<TT, LEVEL, false>), dim3(g256), dim3(256), 0, a.stream, a); \
+            hipLaunchKernelGGL((efs_trie_stage<TT, LEVEL, false>), dim3(g256), dim3(256), 0, a.stream, a, gv, \
+                               dgv);                                                                     \
         launch_stages<LEVEL, TT>(a, std::make_integer_sequence<int, LV::STAGE_R>{}, false);              \
         return (int)hipGetLastError();                                                                   \
     }

@@ -173,7 +173,7 @@ struct Emitter {
             os << ind << "}\n";
             // streamed walk: dV/dg goes back to memory after each node
             // (and the parent's sum is formed here, not deferred to its use)
-            if (stream) os << ind << "MTP_STAGE_SYNC(" << wd << ");\n";
+            if (stream) os << ind << (depth <= 1 ? "MTP_STAGE_SYNC(" : "MTP_STAGE_KEEP(") << wd << ");\n";
         }
     }
     Counter trie_count;
