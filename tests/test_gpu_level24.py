@@ -125,3 +125,34 @@ def test_backward_is_refused(w24):
     E, F, S = api.MTPEnergy.apply(th, m, b, nb, "fp64")
     with pytest.raises(api.MtpError):
         E.sum().backward()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_grades_at_m_1114_match_oracle(w24, precision):
+    """Grades of level-24 rows against a seeded well-conditioned active-set
+    matrix of full size (m = 1114, beyond the register and int8 forms: the
+    FP64 product with rows staged through LDS grades both forms), oracle rows
+    solved by LU (Sec. II.D) for a few atoms; the preselection of the same
+    call counts the atoms above 2 exactly as the oracle's grades do."""
+    w, pot, theta, m = w24
+    keep = m.kept_columns()
+    mm = len(keep)
+    assert mm == m.m("full") == 1114
+    rng = np.random.default_rng(1114)
+    A = np.eye(mm) * 4.0 + rng.normal(size=(mm, mm)) / np.sqrt(mm)   # kappa ~ 10
+    A *= np.exp(rng.uniform(-3, 3, size=mm))[None, :]                 # columns of very different scale
+    m.set_active_set("full", A)
+    c = sorted(w.configs, key=lambda c: c.n)[2]
+    b = api.Batch([c])
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    out = api.evaluate(m, b, nb, precision, "full", gamma_save=2.0)
+    atoms = [0, c.n // 2, c.n - 1]
+    pairs = onb.neighbors(c.pos, c.cell, c.pbc, pot.r_cut)
+    rows = om.b_rows(pot, theta, c.pos, c.types, c.cell, pairs, atoms=atoms)[:, keep]
+    g_or, am_or, _ = om.grades(rows, A)
+    g = _np(out["gamma"])[atoms]
+    am = _np(out["argmax"])[atoms]
+    print(f"{precision}: gamma {g} vs {g_or}")
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert np.all(np.abs(g - g_or) <= tol * np.maximum(1.0, g_or))
+    assert np.array_equal(am, am_or)
