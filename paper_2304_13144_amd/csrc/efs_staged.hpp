@@ -4,30 +4,31 @@
 // value and dV/dg of a neighborhood in registers and exchanges the graph
 // values of 64 neighborhoods through LDS; at this level that is 2 x 218
 // values per lane and 111 KB of LDS (FP64), beyond a CU.  Here the program
-// runs as separate launches that pass per-neighborhood state through memory
-// ([k][n_atoms] columns: consecutive lanes, consecutive addresses):
+// runs as separate launches that pass per-neighborhood state through memory:
 //
 //   moments (efs_moments)          -> M      [NC][n]
-//   graph values, part P of 8      -> g      (reads M)
-//   trie walk                      -> dV/dg, V, B_alpha rows
+//   graph values, part P of 8      -> g      tiles of 64 neighborhoods (reads M)
+//   trie walk                      -> dV/dg  tiles; V; B_alpha rows
 //   reverse pass, part P of 16     -> dV/dM  [NC][n]       (reads M, dV/dg;
 //                                     part P adds its share to parts 0..P-1)
 //
 // followed by the pair-gradient kernel as at every level.  One neighborhood
-// per lane throughout; each part is its own translation unit, so the
-// program compiles in pieces.  The state is about 2.5 KB per neighborhood
-// (FP64): a few GB of HBM traffic per 10^6 atoms, small against the program's
-// arithmetic.
+// per lane throughout.  The graphs of a part are chosen so that they use few
+// moment components (the generator clusters them), which the part holds in
+// registers; each part is its own translation unit, so the program compiles
+// in pieces.  The state is about 4 KB per neighborhood (FP64): a few GB of
+// HBM traffic per 10^6 atoms.
 #pragma once
 
 #include "efs_kernel.hpp"
 
 namespace mtp {
 
-// in the trie walk, after every node: dV/dg goes back to memory and the
-// graph values are read again (a compiler barrier), and the running sum w of
-// the parent node is formed there (else its products are deferred to the
-// end, every factor held until then)
+// in the trie walk, after the nodes of the first two depths: dV/dg goes back
+// to memory and the graph values are read again (a compiler barrier), and
+// the running sum w of the parent node is formed there (else its products
+// are deferred to the end, every factor held until then); deeper nodes only
+// pin w (MTP_STAGE_KEEP)
 #define MTP_STAGE_SYNC(w) asm volatile("" : "+v"(w) : : "memory")
 // a Horner sum formed where it is written (not deferred)
 #define MTP_STAGE_KEEP(a) asm volatile("" : "+v"(a))

@@ -171,8 +171,9 @@ struct Emitter {
             os << in2 << wd << " = fma(" << g << ", " << wd1 << ", " << wd << ");\n";
             trie_count.fma++;
             os << ind << "}\n";
-            // streamed walk: dV/dg goes back to memory after each node
-            // (and the parent's sum is formed here, not deferred to its use)
+            // streamed walk: after each node of the first two depths, dV/dg
+            // goes back to memory; after every node the parent's sum is
+            // formed here, not deferred to its use
             if (stream) os << ind << (depth <= 1 ? "MTP_STAGE_SYNC(" : "MTP_STAGE_KEEP(") << wd << ");\n";
         }
     }
@@ -298,8 +299,8 @@ struct Emitter {
     }
 
     // The trie walk with every graph value read where it is used and dV/dg
-    // accumulated in place (gin, dgout: accessors), so that neither the 2 x
-    // NGRAPH values nor anything but the walk's path is held in registers.
+    // accumulated in place (gin, dgout: accessors into memory), so that the
+    // 2 x NGRAPH values are not all held in registers.
     void trie_walk_stream() {
         build_trie();
         os << "  // basis values, site energy and dV/dg by a walk over the factor trie\n";
