@@ -373,9 +373,11 @@ int mtp_profile_read(const char *kernel, double *total_ms /* host */, int64_t *l
  * the grade product the same way under the chosen lanes -- 1: FP64 MFMA with
  * each wavefront's rows in registers (m <= 288); 2: FP64 MFMA with the rows
  * staged through LDS (any m); 3: the int8 slice product (MTP_MIXED, m <=
- * 320); 4: as 1 in blocks of 32 rows, two blocks per CU (m <= 288) -- keeps
- * the fastest for this model, precision, grade mode and size
- * class and returns it in *grade (host, nullable; 0 when no grade was
+ * 320); 4: as 1 in blocks of 32 rows, two blocks per CU (m <= 288); 5: FP64
+ * MFMA with k outermost, the rows streamed in chunks of eight k steps beside
+ * the products (m <= 288); 6: as 5 in chunks of two k steps, two blocks per
+ * CU (m <= 288) -- keeps the fastest for this model, precision, grade mode
+ * and size class and returns it in *grade (host, nullable; 0 when no grade was
  * timed).  Every form meets the precision's error bound; they differ in
  * speed only.  Synchronises `stream`. */
 int mtp_tune(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,

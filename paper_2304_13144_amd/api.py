@@ -446,7 +446,8 @@ class MTPEnergy(torch.autograd.Function):
         return g, None, None, None, None
 
 
-GRADE_FORMS = {0: "none", 1: "fp64-registers", 2: "fp64-lds", 3: "int8-slices", 4: "fp64-registers-32-row-blocks"}
+GRADE_FORMS = {0: "none", 1: "fp64-registers", 2: "fp64-lds", 3: "int8-slices", 4: "fp64-registers-32-row-blocks",
+               5: "fp64-k-outer", 6: "fp64-k-outer-2-step-chunks"}
 
 
 def tune(model, batch, nbrs, precision="fp64", mode="full", with_grade=False):

@@ -189,9 +189,9 @@ int lanes_for(const mtp_model *m, int64_t n, int prec) {
 // grade schedule: the tuner's choice for this size class, else GRADE_AUTO
 int grade_sched_for(const mtp_model *m, int64_t n, int prec, int mode) {
     if (m->force_grade) return m->force_grade;
-    if (const char *e = std::getenv("MTP_GRADE_FORM")) {   // 1 .. 4 (GRADE_*), where available
+    if (const char *e = std::getenv("MTP_GRADE_FORM")) {   // 1 .. 6 (GRADE_*), where available
         const int v = std::atoi(e);
-        if (v >= GRADE_F64_REG && v <= GRADE_F64_PAIR && grade_sched_valid(m->act[mode & 1], prec, v)) return v;
+        if (v >= GRADE_F64_REG && v <= GRADE_F64_KOUTER2 && grade_sched_valid(m->act[mode & 1], prec, v)) return v;
     }
     const int t = m->tuned_grade[prec == MTP_FP64 ? 0 : 1][mode & 1][size_bucket(n)];
     return t && grade_sched_valid(m->act[mode & 1], prec, t) ? t : GRADE_AUTO;
@@ -1358,7 +1358,7 @@ int mtp_tune(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precisio
     int gbest = GRADE_AUTO;
     if (o.gamma) {
         std::vector<int> cand;
-        for (int sc : {GRADE_F64_REG, GRADE_F64_LDS, GRADE_I8, GRADE_F64_PAIR})
+        for (int sc : {GRADE_F64_REG, GRADE_F64_LDS, GRADE_I8, GRADE_F64_PAIR, GRADE_F64_KOUTER, GRADE_F64_KOUTER2})
             if (grade_sched_valid(m->act[g], p, sc)) cand.push_back(sc);
         std::vector<float> gmin(cand.size());
         try {

@@ -395,6 +395,137 @@ __global__ __launch_bounds__(256, 2) void grade_f64_pair(const double *__restric
     }
 }
 
+// FP64 with k outermost: a block of 512 threads owns 64 rows (row group w %
+// 4 of wavefront w, half w / 4 of the column tiles: tiles h NK .. h NK + NK -
+// 1).  A wavefront keeps the accumulators of all NK of its tiles (8 NK
+// registers) and runs k in chunks of KC k steps: per chunk, KC values of its
+// rows (loaded two chunks ahead) times the chunk's operands of its NK tiles,
+// KC NK independent MFMAs.  The rows are never held whole, so their loads
+// spread over the product instead of all arriving before the first MFMA.
+// Each half's chunk of A^-1 (NK pieces of KC x 512 bytes, one per tile, in
+// the lane order of f64_stage_ainv) is loaded DIST chunks ahead into
+// registers and stored to LDS one chunk ahead, double-buffered: one barrier
+// per chunk.  The 64 rows of a block share every staged chunk, so A^-1
+// crosses from L2 once per 64 rows.  The chunk loop is unrolled in full
+// (2 NK x 4 / KC chunks), so every wait count is exact.  KC = 8, DIST = 1:
+// 112 KB of LDS at m = 224, one block per CU (the fewest barriers, for
+// launches of about one block per CU); KC = 2, DIST = 2: 28 KB and fewer
+// registers, two blocks per CU (for larger launches).
+template <int NK, int KC, int DIST>
+__global__ __launch_bounds__(512) void grade_f64_kouter(const double *__restrict__ brow, int64_t ldn, int64_t n,
+                                                        const double *__restrict__ L, int m, double *gamma,
+                                                        int32_t *argmax, double thr, int32_t *sel_blk) {
+    constexpr int KS = 8 * NK;                 // k steps of four
+    constexpr int NCH = KS / KC;               // chunks
+    static_assert(NCH * KC == KS, "chunks tile the k steps");
+    constexpr int CH = KC * NK * 64;           // doubles of one half's chunk in LDS: [step][tile][lane]
+    constexpr int PIECES = NK * KC * 32;       // its 16-byte pieces: [tile][step][32]
+    constexpr int PER = (PIECES + 255) / 256;  // per thread of the half
+    __shared__ double sB[2][2][CH];            // [half][buffer]
+    __shared__ double s_best[2][GF_ROWS];
+    __shared__ int s_idx[2][GF_ROWS];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int rg = wave & 3, half = wave >> 2, ht = tid & 255;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int64_t row0 = (int64_t)blockIdx.x * GF_ROWS + rg * 16;
+    const int ntile = (m + 15) / 16;
+    doublex2 pre[DIST][PER];
+    auto fetch = [&](int c) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = ht + 256 * q;
+            if (PIECES % 256 == 0 || e < PIECES) {
+                const int j = e / (KC * 32), p = e % (KC * 32);
+                const int t = min(half * NK + j, ntile - 1);   // past the last tile: an in-bounds tile, never compared
+                pre[c % DIST][q] = reinterpret_cast<const doublex2 *>(L + ((int64_t)t * KS + KC * c) * 64)[p];
+            }
+        }
+    };
+    auto stash = [&](int buf, int c) {   // piece p of tile j: step p / 32, lanes 2 (p % 32) and 2 (p % 32) + 1
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = ht + 256 * q;
+            if (PIECES % 256 == 0 || e < PIECES) {
+                const int j = e / (KC * 32), p = e % (KC * 32);
+                *reinterpret_cast<doublex2 *>(&sB[half][buf][((p >> 5) * NK + j) * 64 + 2 * (p & 31)]) =
+                    pre[c % DIST][q];
+            }
+        }
+    };
+    // this lane's row at k = 4 s + lk (zero past m up to ldb >= 32 NK); rows past n: clamped, never written
+    const double *bp = brow + min(row0 + lr, n - 1) + (int64_t)lk * ldn;
+    double a[NCH][KC];
+    auto load_rows = [&](int c) {
+#pragma unroll
+        for (int s = 0; s < KC; ++s) a[c][s] = bp[(int64_t)(4 * (KC * c + s)) * ldn];
+    };
+    fetch(0);
+    load_rows(0);
+    if (NCH > 1) load_rows(1);
+    stash(0, 0);
+#pragma unroll
+    for (int d = 1; d <= DIST; ++d)
+        if (d < NCH) fetch(d);
+    __syncthreads();
+    double best[4] = {-1.0, -1.0, -1.0, -1.0};
+    int bidx[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
+    doublex4 acc[NK];
+#pragma unroll
+    for (int j = 0; j < NK; ++j) acc[j] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        if (c + 2 < NCH) load_rows(c + 2);
+        const double *b = sB[half][c & 1] + lane;
+#pragma unroll
+        for (int s = 0; s < KC; ++s)
+#pragma unroll
+            for (int j = 0; j < NK; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][s], b[(s * NK + j) * 64], acc[j], 0, 0, 0);
+        if (c + 1 < NCH) {
+            stash((c + 1) & 1, c + 1);   // its last readers passed the previous barrier
+            if (c + 1 + DIST < NCH) fetch(c + 1 + DIST);
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+        const int col = 16 * (half * NK + j) + lr;
+        if (col < m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) better(fabs(acc[j][r]), col, best[r], bidx[r]);
+    }
+    // the 16 lanes of a row (columns), then the two halves
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double ov = __shfl_xor(best[r], o, 64);
+            const int oc = __shfl_xor(bidx[r], o, 64);
+            better(ov, oc, best[r], bidx[r]);
+        }
+    if (lr == 0)   // f64 layout: lane l, register r -> row l / 16 + 4 r
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            s_best[half][rg * 16 + lk + 4 * r] = best[r];
+            s_idx[half][rg * 16 + lk + 4 * r] = bidx[r];
+        }
+    __syncthreads();
+    if (tid < GF_ROWS) {   // wavefront 0: one row per lane
+        double bv = s_best[0][tid];
+        int bc = s_idx[0][tid];
+        better(s_best[1][tid], s_idx[1][tid], bv, bc);
+        const int64_t row = (int64_t)blockIdx.x * GF_ROWS + tid;
+        const bool live = row < n;
+        if (live) {
+            gamma[row] = bv;
+            if (argmax) argmax[row] = bc;
+        }
+        const unsigned long long sel = __ballot(live && bv > thr);
+        if (sel_blk && tid == 0) sel_blk[blockIdx.x] = __popcll(sel);
+    }
+}
+
 // A^-1 in the lane order of grade_f64: out[(tile * 8 NK + s) * 64 + l] =
 // A^-1[4 s + l / 16][16 tile + l % 16], zero past m
 __global__ void f64_stage_ainv(const double *Ainv, int m, int NK, int ntile, double *out) {
@@ -935,6 +1066,14 @@ static void launch_grade_f64_pair(const ActiveSet &as, const double *brow, int64
                        argmax, thr, sel_blk);
 }
 
+template <int NK, int KC, int DIST>
+static void launch_grade_f64_kouter(const ActiveSet &as, const double *brow, int64_t ldn, int64_t n, double *gamma,
+                                    int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
+    const dim3 grid((unsigned)((n + GF_ROWS - 1) / GF_ROWS));
+    hipLaunchKernelGGL((grade_f64_kouter<NK, KC, DIST>), grid, dim3(512), 0, st, brow, ldn, n, as.lane64.as<double>(),
+                       as.m, gamma, argmax, thr, sel_blk);
+}
+
 template <int KS>
 static void launch_grade_i8(const ActiveSet &as, const double *brow, int ldb, int64_t ldn, int64_t n, double *gamma,
                             int32_t *argmax, hipStream_t st, double thr, int32_t *sel_blk) {
@@ -947,7 +1086,9 @@ bool grade_sched_valid(const ActiveSet &as, int precision, int sched) {
     switch (sched) {
         case GRADE_AUTO: return true;
         case GRADE_F64_REG: return as.m <= 32 * GR_NK_MAX;
-        case GRADE_F64_PAIR: return as.m <= 32 * GR_NK_MAX;
+        case GRADE_F64_PAIR:
+        case GRADE_F64_KOUTER:
+        case GRADE_F64_KOUTER2: return as.m <= 32 * GR_NK_MAX;
         case GRADE_F64_LDS: return true;
         case GRADE_I8: return precision == MTP_MIXED && slice_product_fits(as.m);
         default: return false;
@@ -984,6 +1125,32 @@ void launch_grade(const ActiveSet &as, int precision, const double *brow, int ld
             case 4: launch_grade_i8<4>(as, brow, ldb, ldn, n, gamma, argmax, st, thr, sel_blk); break;
             default: launch_grade_i8<5>(as, brow, ldb, ldn, n, gamma, argmax, st, thr, sel_blk); break;
         }
+        return;
+    }
+    if (sched == GRADE_F64_KOUTER || sched == GRADE_F64_KOUTER2) {
+        MTP_CHECK(as.NK64 == (as.m + 31) / 32 && as.lane64.ptr, MTP_E_INVAL, "grade: A^-1 not staged");
+        MTP_CHECK(ldb >= 32 * as.NK64, MTP_E_INVAL, "grade: rows not padded to a multiple of 32 columns");
+        const bool big = sched == GRADE_F64_KOUTER;   // eight k steps per chunk, else two, two chunks ahead
+#define MTP_KOUTER_CASE(K)                                                                  \
+    case K:                                                                                 \
+        if (big)                                                                            \
+            launch_grade_f64_kouter<K, 8, 1>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); \
+        else                                                                                \
+            launch_grade_f64_kouter<K, 2, 2>(as, brow, ldn, n, gamma, argmax, st, thr, sel_blk); \
+        break;
+        switch (as.NK64) {
+            MTP_KOUTER_CASE(1)
+            MTP_KOUTER_CASE(2)
+            MTP_KOUTER_CASE(3)
+            MTP_KOUTER_CASE(4)
+            MTP_KOUTER_CASE(5)
+            MTP_KOUTER_CASE(6)
+            MTP_KOUTER_CASE(7)
+            MTP_KOUTER_CASE(8)
+            default:
+                MTP_KOUTER_CASE(9)
+        }
+#undef MTP_KOUTER_CASE
         return;
     }
     if (sched == GRADE_F64_PAIR) {

@@ -148,8 +148,19 @@ constexpr int GRADE_ROWS = 64;
 // GRADE_F64_REG: FP64 MFMA with the rows in registers (m <= 288);
 // GRADE_F64_LDS: FP64 MFMA with the rows staged through LDS (any m);
 // GRADE_I8: the int8 slice product (mixed form, m <= 320);
-// GRADE_F64_PAIR: as GRADE_F64_REG in blocks of 32 rows, two blocks per CU
-enum { GRADE_AUTO = 0, GRADE_F64_REG = 1, GRADE_F64_LDS = 2, GRADE_I8 = 3, GRADE_F64_PAIR = 4 };
+// GRADE_F64_PAIR: as GRADE_F64_REG in blocks of 32 rows, two blocks per CU;
+// GRADE_F64_KOUTER: FP64 MFMA with k outermost, the rows streamed in chunks
+// of eight k steps (m <= 288; one block per CU); GRADE_F64_KOUTER2: the same
+// in chunks of two k steps (two blocks per CU)
+enum {
+    GRADE_AUTO = 0,
+    GRADE_F64_REG = 1,
+    GRADE_F64_LDS = 2,
+    GRADE_I8 = 3,
+    GRADE_F64_PAIR = 4,
+    GRADE_F64_KOUTER = 5,
+    GRADE_F64_KOUTER2 = 6
+};
 bool grade_sched_valid(const ActiveSet &as, int precision, int sched);
 // rows per preselection count the grade writes under a schedule (divides GRADE_ROWS)
 int grade_count_rows(const ActiveSet &as, int precision, int sched);

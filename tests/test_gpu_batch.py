@@ -100,7 +100,8 @@ def test_grade_forms_agree_and_tuner_picks_one(precision):
     m = _model16()
     b = api.Batch([synth.workload2(reps=(6, 6, 6)).configs[0]])
     nb = api.Neighbors().build(m, b, max_nbrs=64)
-    forms = {"1": "fp64-registers", "2": "fp64-lds", "4": "fp64-registers-32-row-blocks"} | \
+    forms = {"1": "fp64-registers", "2": "fp64-lds", "4": "fp64-registers-32-row-blocks", "5": "fp64-k-outer",
+             "6": "fp64-k-outer-2-step-chunks"} | \
         ({"3": "int8-slices"} if precision == "mixed" else {})
     lanes = api.tune(m, b, nb, precision, "full", with_grade=True)   # first: the lanes stay fixed below
     assert lanes[2] in forms.values()
@@ -114,6 +115,8 @@ def test_grade_forms_agree_and_tuner_picks_one(precision):
     # the FP64 products differ only in summation order
     assert np.allclose(got["2"], got["1"], rtol=1e-12, atol=0)
     assert np.allclose(got["4"], got["1"], rtol=1e-12, atol=0)
+    assert np.allclose(got["5"], got["1"], rtol=1e-12, atol=0)
+    assert np.array_equal(got["6"], got["5"])   # the same products in the same order
     if precision == "mixed":
         assert np.all(np.abs(got["3"] - got["1"]) <= 1e-5 * np.maximum(1.0, got["1"]))
     assert np.array_equal(_np(api.evaluate(m, b, nb, precision, "full"))["gamma"],

@@ -4,6 +4,8 @@ Bars (written per test): FP64 form within 1e-10 relative (norm-wise: max
 |diff| / max |oracle|); mixed form with forces within 1e-4 eV/A and gamma
 within 1e-5 max(1, gamma); neighbor lists bit-exact as sets.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -272,23 +274,33 @@ def test_batched_equals_single_configs():
 
 
 # --------------------------------------------------------------- grades ----
-def _grade_case(wid, w, cfg, precision, mode):
+def _grade_case(wid, w, cfg, precision, mode, form=None):
+    """form: a kernel form of the grade product (MTP_GRADE_FORM), else the
+    library's choice"""
     pot = potential(w)
     theta = theta_for(wid, pot)
     m, keep = _model(w, theta)
     b = api.Batch([cfg])
     nb = api.Neighbors().build(m, b, max_nbrs=64)
-    out = api.grade(m, b, nb, precision, mode, rows=True)
+    if form is not None:
+        os.environ["MTP_GRADE_FORM"] = form
+    try:
+        out = api.grade(m, b, nb, precision, mode, rows=True)
+    finally:
+        os.environ.pop("MTP_GRADE_FORM", None)
     torch.cuda.synchronize()
     return pot, theta, keep, {k: v.cpu().numpy() for k, v in out.items()}
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+# the library's form for each precision, and the other FP64 forms (4: rows in
+# registers in blocks of 32 rows, 5 and 6: k outermost)
+@pytest.mark.parametrize("precision,form", [("fp64", None), ("mixed", None), ("fp64", "4"), ("fp64", "5"),
+                                            ("fp64", "6")])
 @pytest.mark.parametrize("mode", ["full", "linear"])
-def test_grade_workload1(mode, precision):
+def test_grade_workload1(mode, precision, form):
     w = synth.workload1()
     cfg = w.configs[0]
-    pot, theta, keep, g = _grade_case(1, w, cfg, precision, mode)
+    pot, theta, keep, g = _grade_case(1, w, cfg, precision, mode, form)
     pairs = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, w.r_cut)
     if mode == "full":
         assert list(keep) == om.kept_columns(pot, theta)
@@ -324,12 +336,14 @@ def _fp32_row_emulation(rows, A):
     return float((np.abs(g1 - g0) / np.maximum(1.0, g0)).max())
 
 
-@pytest.mark.parametrize("precision,mode", [("fp64", "full"), ("fp64", "linear"), ("mixed", "full"),
-                                            ("mixed", "linear")])
-def test_grade_level16_two_species_small(precision, mode):
+@pytest.mark.parametrize("precision,mode,form", [("fp64", "full", None), ("fp64", "linear", None),
+                                                 ("mixed", "full", None), ("mixed", "linear", None),
+                                                 ("fp64", "full", "5"), ("fp64", "linear", "5"),
+                                                 ("fp64", "full", "6"), ("fp64", "linear", "6")])
+def test_grade_level16_two_species_small(precision, mode, form):
     w = synth.workload2(reps=(4, 4, 4))
     cfg = w.configs[0]
-    pot, theta, keep, g = _grade_case(2, w, cfg, precision, mode)
+    pot, theta, keep, g = _grade_case(2, w, cfg, precision, mode, form)
     pairs = onb.neighbors(cfg.pos, cfg.cell, cfg.pbc, w.r_cut)
     if mode == "full":
         rows = om.b_rows(pot, theta, cfg.pos, cfg.types, cfg.cell, pairs)[:, keep]
