@@ -42,7 +42,8 @@ TRAFFIC_KERNELS = ("efs_moments_contract<double, 16, true>", "efs_moments_contra
                    "efs_moments<double, 16, 8>", "efs_contract<double, 16, true>",
                    "efs_forces_rows<double, double, 16, 4>", "efs_forces_rows<double, double, 16, 8>",
                    "efs_forces_rows<float, double, 16, 4>", "efs_forces_rows<float, double, 16, 8>",
-                   "grade_f64<", "grade_f64_wide<", "grade_f64_pair<", "grade_f64_kouter<", "grade_i8<4>", "pair_search<false, 2>",
+                   "grade_f64<", "grade_f64_wide<", "grade_f64_pair<", "grade_f64_kouter<7, 8, 1>",
+                   "grade_f64_kouter<7, 2, 2>", "grade_i8<4>", "pair_search<false, 2>",
                    "reverse_pairs")
 
 
@@ -368,7 +369,8 @@ def main():
                                   f"{tuned[prec][1]}>",
                     "grade": {"int8-slices": f"grade_i8<{(m + 63) // 64}>", "fp64-registers": "grade_f64<",
                               "fp64-lds": "grade_f64_wide<", "fp64-registers-32-row-blocks": "grade_f64_pair<",
-                              "fp64-k-outer": "grade_f64_kouter<", "fp64-k-outer-2-step-chunks": "grade_f64_kouter<"}[gform]}[dom]
+                              "fp64-k-outer": f"grade_f64_kouter<{(m + 31) // 32}, 8, 1>",
+                              "fp64-k-outer-2-step-chunks": f"grade_f64_kouter<{(m + 31) // 32}, 2, 2>"}[gform]}[dom]
     traffic = recorded_traffic(rocprof_name)
     # the rate this part sustains on the grade's MFMA form (register operands, no memory)
     ceiling = {"f64_tflops": api.mfma_rate("f64"), "i8_tops": api.mfma_rate("i8")}
