@@ -493,15 +493,31 @@ __device__ inline void load_dm(const EfsArgs &a, const AtomCtx &c, int sub, T (&
 // with dE/dM), written per pair (G: gradients wanted, decided at compile time
 // so that the stores in the pair loop are unconditional); virial
 // S_ab = -sum_j g_a r_b per atom.
-template <typename T, int L, int K, bool G, typename TD = T>
-__device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T (&s_dm)[Level<L>::NC][256 / K]) {
+//
+// R > 0 (FP64 only): the rest of the b row in the same pass (kernel 4's
+// work, Sec. II.C) -- R = 2 (FULL) the radial-coefficient part
+// dV_i/dc_{mu, z_i, z_j, beta} = sum_j T_beta(r_ij) (R_cut - r_ij)^2 P_mu(r_ij)
+// from the P_mu and Chebyshev values the gradient already has (32 more FMAs
+// per pair at N_rad = 4), then for R = 1 and 2 the species one-hot and the
+// zero padding.  The same sums in the same order as kernel 4 at the same
+// lanes, so the rows are the same bit for bit.  s_col: the kept-column map
+// (R = 2).
+template <typename T, int L, int K, bool G, typename TD = T, int R = 0>
+__device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T (&s_dm)[Level<L>::NC][256 / K],
+                                       int32_t *s_col = nullptr) {
     using LV = Level<L>;
-    constexpr int NC = LV::NC, NR = LV::NRAD;
+    constexpr int NC = LV::NC, NR = LV::NRAD, NL = LV::NLIN;
+    constexpr int ND = NR * NPOLY;   // radial-coefficient sums per species (a multiple of K)
+    static_assert(R == 0 || sizeof(T) == sizeof(double), "rows are FP64");
     load_coefs<T, NR>(a, c_s);
     const int nt = a.n_types;
+    if constexpr (R == 2)   // before load_dm's barrier, which covers it
+        for (int k = threadIdx.x; k < NR * nt * nt * NPOLY; k += 256) s_col[k] = a.colmap[nt + NL + k];
     const int sub = threadIdx.x % K;
     const AtomCtx c = atom_ctx<K>(a, blk);
     load_dm<T, NC, K, TD>(a, c, sub, s_dm);
+    double *brow = R > 0 && c.live ? a.brow + c.slot : nullptr;   // entry k at brow[k * ldn]
+    const int64_t ldn = a.ldn;
     const int la = threadIdx.x / K;
     const T rc = T(a.r_cut);
     const T xs = T(2.0 / (a.r_cut - a.r_min));
@@ -513,6 +529,10 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
     int gstart = 0;
     for (int t = 0; t < nt; ++t) {
         const int tc = tcount(a, c, t);
+        T dc[R == 2 ? ND : 1];
+        if constexpr (R == 2)
+#pragma unroll
+            for (int k = 0; k < ND; ++k) dc[k] = T(0);
         // the next pair vector is loaded while the current one is used; the
         // loads are unconditional (past the last pair the current one is read
         // again, in bounds and unused), so that the wait for them leaves the
@@ -533,6 +553,7 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
             T g0 = T(0), g1 = T(0), g2 = T(0);
             if (r < rc) {
                 T f[NR], fp[NR];
+                T qb[R == 2 ? NPOLY : 1];   // T_beta (R_cut - r)^2, for the row's c part
                 {
                     const T u = fma(r, xs, x0);
                     const T d = rc - r;
@@ -540,6 +561,9 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
                     const T dcut = T(-2) * d;
                     T Tb[NPOLY], dT[NPOLY];
                     chebyshev<T, true>(u, Tb, dT);
+                    if constexpr (R == 2)
+#pragma unroll
+                        for (int b = 0; b < NPOLY; ++b) qb[b] = Tb[b] * cut;
 #pragma unroll
                     for (int mu = 0; mu < NR; ++mu) {
                         const CoefRow<T> cm = coef_row(c_s, mu, c.zi, t, nt);
@@ -570,6 +594,11 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
                     if (LV::comp_dmonoz[k] >= 0)
                         Gz[mu] = fma(dmk * T(LV::comp_dfacz[k]), mono[LV::comp_dmonoz[k] < 0 ? 0 : LV::comp_dmonoz[k]], Gz[mu]);
                 }
+                if constexpr (R == 2)
+#pragma unroll
+                    for (int b = 0; b < NPOLY; ++b)
+#pragma unroll
+                        for (int mu = 0; mu < NR; ++mu) dc[mu * NPOLY + b] = fma(qb[b], P[mu], dc[mu * NPOLY + b]);
                 const T rinv = T(1) / r;
                 T radial_part = T(0);
 #pragma unroll
@@ -595,7 +624,33 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
                 gout[s3 + 2] = g2;
             }
         }
+        if constexpr (R == 2) {
+            efs::reduce_scatter<T, ND, K>(dc, sub);
+            if (brow) {
+#pragma unroll
+                for (int i = 0; i < ND / K; ++i) {
+                    const int k = sub * (ND / K) + i, mu = k / NPOLY, b = k % NPOLY;
+                    const int col = s_col[((mu * nt + c.zi) * nt + t) * NPOLY + b];
+                    if (col >= 0) brow[col * ldn] = dc[i];
+                }
+            }
+        }
         gstart += tc;
+    }
+    if constexpr (R > 0) {
+        if (brow) {   // species one-hot, zero c blocks of the other central species, zero padding
+            for (int k = sub; k < nt; k += K) brow[k * ldn] = k == c.zi ? 1.0 : 0.0;
+            if constexpr (R == 2) {
+                const int nblk = NR * nt * nt * NPOLY;
+                for (int k = sub; k < nblk; k += K) {
+                    const int zz = (k / (nt * NPOLY)) % nt;
+                    if (zz == c.zi) continue;
+                    const int col = s_col[k];
+                    if (col >= 0) brow[col * ldn] = 0.0;
+                }
+            }
+            for (int k = a.m + sub; k < a.ldb; k += K) brow[k * ldn] = 0.0;
+        }
     }
     constexpr int NV = (9 + K - 1) / K * K;
     T vp[NV];
@@ -749,6 +804,28 @@ __global__ __launch_bounds__(256) void efs_forces_rows(const EfsArgs a, int64_t 
     }
 }
 
+// FP64 form with forces and rows: kernels 3 and 4 in one pass over the pairs
+// (R = 1 LINEAR, 2 FULL rows); no row blocks
+template <typename T, int L, int K, int R>
+__global__ __launch_bounds__(256) void efs_forces_fused(const EfsArgs a) {
+    using LV = Level<L>;
+    constexpr int NCF = LV::NRAD * MAX_TYPES * MAX_TYPES * NPOLY;
+    __shared__ __attribute__((aligned(16))) char smem[sizeof(T) * (NCF + LV::NC * (256 / K)) + sizeof(int32_t) * NCF];
+    T *c_s = reinterpret_cast<T *>(smem);
+    auto &s_dm = *reinterpret_cast<T (*)[LV::NC][256 / K]>(c_s + NCF);
+    int32_t *s_col = reinterpret_cast<int32_t *>(smem + sizeof(T) * (NCF + LV::NC * (256 / K)));
+    efs_forces_body<T, L, K, true, T, R>(a, blockIdx.x, c_s, s_dm, s_col);
+    if (a.part) {   // uniform: the block's atoms are whole sum chunks
+        constexpr int PER = 256 / K / SUM_CHUNK;
+        static_assert(PER * SUM_CHUNK * K == 256, "chunks per block");
+        for (int q = 0; q < PER; ++q) {
+            const int64_t chunk = (int64_t)blockIdx.x * PER + q;
+            __syncthreads();
+            if (chunk * SUM_CHUNK < a.n_atoms) chunk_partials(chunk, a.n_atoms, a.part_e, a.virial, a.part);
+        }
+    }
+}
+
 template <int L, typename T> int launch_mc_level_t(const EfsArgs &a);
 template <int L, typename TF, typename TD> int launch_fr_level_t(const EfsArgs &a);
 
@@ -806,6 +883,17 @@ template <int L, typename TF, typename TD> int launch_fr_level_t(const EfsArgs &
         const unsigned grid = (unsigned)((a.n_atoms + 256 / K - 1) / (256 / K));                         \
         const bool rows = sizeof(TD) == sizeof(double) && a.brow != nullptr;                             \
         ProfScope ps("efs_forces", a.stream);                                                            \
+        if constexpr (sizeof(TF) == sizeof(double)) {                                                    \
+            if (rows && a.gbuf) { /* FP64 with forces: rows in the same pass */                          \
+                if (a.grade_mode == GRADE_FULL)                                                          \
+                    hipLaunchKernelGGL((efs_forces_fused<TF, LEVEL, K, 2>), dim3(grid), dim3(256), 0,     \
+                                       a.stream, a);                                                     \
+                else                                                                                     \
+                    hipLaunchKernelGGL((efs_forces_fused<TF, LEVEL, K, 1>), dim3(grid), dim3(256), 0,     \
+                                       a.stream, a);                                                     \
+                return;                                                                                  \
+            }                                                                                            \
+        }                                                                                                \
         hipLaunchKernelGGL((efs_forces_rows<TF, TD, LEVEL, K>), dim3(rows ? 2 * grid : grid), dim3(256),  \
                            0, a.stream, a, (int64_t)grid);                                               \
     }                                                                                                    \

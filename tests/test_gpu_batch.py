@@ -154,3 +154,29 @@ def test_sustained_mfma_rate_is_plausible():
     assert 50.0 < i8 < 5000.0 * 1.05
     with pytest.raises(api.MtpError):
         api.mfma_rate("f64", 0)
+
+
+@pytest.mark.parametrize("lanes", ["2", "4", "8"])
+@pytest.mark.parametrize("mode", ["full", "linear"])
+def test_fp64_rows_in_the_pair_pass_equal_the_row_blocks(mode, lanes):
+    """An FP64 evaluation with forces computes the rows' remaining parts in the
+    pair-gradient pass itself; mtp_grade (no forces) computes them in row
+    blocks of their own.  Same sums in the same order: the grades are bitwise
+    equal, and the forces are bitwise those of the launch without rows."""
+    import os
+    m = _model16()
+    if mode == "linear":
+        m.set_active_set("linear", active_rows(2, "linear"))
+    b = api.Batch([synth.workload2(reps=(6, 6, 6)).configs[0]])
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    os.environ["MTP_LANES"] = lanes
+    try:
+        fused = _np(api.evaluate(m, b, nb, "fp64", mode))
+        sep = _np(api.grade(m, b, nb, "fp64", mode, rows=True))
+        plain = _np(api.energy_forces_stress(m, b, nb, "fp64"))
+    finally:
+        del os.environ["MTP_LANES"]
+    assert np.array_equal(fused["gamma"], sep["gamma"])
+    assert np.array_equal(fused["argmax"], sep["argmax"])
+    for key in ("forces", "energy", "stress"):
+        assert np.array_equal(fused[key], plain[key]), key
