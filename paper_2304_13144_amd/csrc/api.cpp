@@ -44,9 +44,10 @@ namespace {
 
 hipStream_t S(void *s) { return static_cast<hipStream_t>(s); }
 
-// columns of the rows buffer: m padded with zeros to a multiple of 64 (the
-// k step of the mixed grade product)
-int ld_of(int m) { return (m + 63) / 64 * 64; }
+// columns of the rows buffer: m padded with zeros to a multiple of 64 for the
+// mixed form (the k step of its int8 product), of 32 for the FP64 form (the
+// k chunk of the FP64 products, which never read further)
+int ld_of(int m, int prec) { return prec == MTP_MIXED ? (m + 63) / 64 * 64 : (m + 31) / 32 * 32; }
 
 // FULL-mode gauge: per mu drop mu+1 columns of block c_mu chosen as the
 // first mu+1 pivots of a column-pivoted Gram-Schmidt (= QR with column
@@ -250,7 +251,7 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     const bool want_v = o.stress != nullptr;
     const bool want_e = o.energy || o.site_e;
     const int mm = m->m_of(o.mode);
-    const int ldb = ld_of(mm);
+    const int ldb = ld_of(mm, prec);
     void *gbuf = want_f ? ws.get(m->gbuf, tsz * 3 * (size_t)std::max<int64_t>(1, n * nb->max_nbrs)) : nullptr;
     double *virial =
         want_v ? static_cast<double *>(ws.get(m->virial, sizeof(double) * 9 * (size_t)std::max<int64_t>(1, n))) : nullptr;
@@ -716,7 +717,7 @@ int mtp_grade_cfg(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, m
     o.mode = g & 1;
     o.keep_rows = true;
     evaluate(m, s, nb, p, o, st);
-    const int mm = m->m_of(g), ldb = ld_of(mm);
+    const int mm = m->m_of(g), ldb = ld_of(mm, p);   // as the evaluation above left the rows
     const int64_t n = s->n_atoms;
     m->cfgrows.ensure(sizeof(double) * (size_t)ldb * s->n_cfg);
     m->cfgpart.ensure(cfg_row_partials_bytes(n, ldb));
@@ -788,7 +789,7 @@ int mtp_b_rows(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_
     if (n_idx == 0) return MTP_OK;
     MTP_HIP(hipSetDevice(m->device));
     const int mm = m->m_of(g);
-    const int ldb = ld_of(mm);
+    const int ldb = ld_of(mm, MTP_FP64);
     m->brow.ensure(sizeof(double) * (size_t)ldb * n_idx);
     EfsArgs a{};
     a.n_atoms = n_idx;
