@@ -40,7 +40,7 @@ KERNELS = ("neighbors", "efs", "efs_moments", "efs_contract", "efs_forces", "for
 # kernels whose HBM traffic the profile summary records (rocprof name substrings)
 TRAFFIC_KERNELS = ("efs_moments_contract<double, 16, true>", "efs_moments_contract8<double, 16, true>",
                    "efs_moments<double, 16, 8>", "efs_contract<double, 16, true>",
-                   "efs_forces_rows<double, double, 16, 4>", "efs_forces_rows<double, double, 16, 8>",
+                   "efs_forces_fused<double, 16, 4, 2>", "efs_forces_fused<double, 16, 8, 2>",
                    "efs_forces_rows<float, double, 16, 4>", "efs_forces_rows<float, double, 16, 8>",
                    "grade_f64<", "grade_f64_wide<", "grade_f64_pair<", "grade_f64_kouter<7, 8, 1>",
                    "grade_f64_kouter<7, 2, 2>", "grade_i8<4>", "pair_search<false, 2>",
@@ -153,7 +153,7 @@ def profile_summary(trace_dir, fetch_dir, write_dir, kernels):
     return "\n".join(out)
 
 
-COUNTER_KERNELS = ("efs_moments_contract", "efs_forces_rows", "grade_f64", "grade_i8", "select_write")
+COUNTER_KERNELS = ("efs_moments_contract", "efs_forces_rows", "efs_forces_fused", "grade_f64", "grade_i8", "select_write")
 
 
 def counter_summary(trace_dir, counter_dirs):
@@ -365,8 +365,9 @@ def main():
     rocprof_name = {"efs_moments": f"efs_moments<double, {level}, {tuned[prec][0]}>",
                     "efs_moments_contract": f"efs_moments_contract{mc8}<double, {level}, true>",
                     "efs_contract": f"efs_contract<double, {level}, true>",
-                    "efs_forces": f"efs_forces_rows<{'double' if prec == 'fp64' else 'float'}, double, {level}, "
-                                  f"{tuned[prec][1]}>",
+                    # FP64 with forces and FULL rows: the pair pass carries the rows (R = 2)
+                    "efs_forces": (f"efs_forces_fused<double, {level}, {tuned[prec][1]}, 2>" if prec == "fp64" else
+                                   f"efs_forces_rows<float, double, {level}, {tuned[prec][1]}>"),
                     "grade": {"int8-slices": f"grade_i8<{(m + 63) // 64}>", "fp64-registers": "grade_f64<",
                               "fp64-lds": "grade_f64_wide<", "fp64-registers-32-row-blocks": "grade_f64_pair<",
                               "fp64-k-outer": f"grade_f64_kouter<{(m + 31) // 32}, 8, 1>",
