@@ -51,19 +51,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def efs_flops_per_atom(n_pairs_per_atom, nc, nr, contraction_flops, with_rows):
+def efs_flops_per_atom(n_pairs_per_atom, nc, nr, contraction_flops, with_rows, fused_rows=True):
     """Algorithmic flops per neighborhood of the evaluation kernels.
 
     efs_moments, per pair:  r (6) + T_0..T_7 (12) + f_mu (16 nr + 2) + monomials (16) + moments (2 nc)
     efs_contract:           the generated contraction program (graph values, trie walk, reverse)
-    efs_forces (one launch, two block ranges), per pair:
+    efs_forces, per pair:
       pair gradients:       r (6) + T, T' (30) + f, f' (32 nr + 4 nr + 3) + monomials (16)
                             + P and grad P (8 nc) + g assembly (8 nr + 7) + virial (18)
-      b-row c part:         r (6) + T (12) + cutoff (3) + monomials (16) + P (2 nc) + 2 nr NPOLY + NPOLY
+      b-row c part, in the same pass (FP64, fused_rows): T_beta cut (NPOLY) + 2 nr NPOLY --
+                            P and the Chebyshev values are the gradient's;
+      in row blocks of their own (the mixed form, whose rows are FP64 and its
+      pair gradients FP32): r (6) + T (12) + cutoff (3) + monomials (16) + P (2 nc)
+                            + 2 nr NPOLY + NPOLY
     """
     p1 = 6 + 12 + 16 * nr + 2 + 16 + 2 * nc
     p3 = 6 + 30 + 36 * nr + 3 + 16 + 8 * nc + 8 * nr + 7 + 18
-    p4 = 6 + 12 + 3 + 16 + 2 * nc + 2 * nr * 8 + 8
+    p4 = 8 + 2 * nr * 8 if fused_rows else 6 + 12 + 3 + 16 + 2 * nc + 2 * nr * 8 + 8
     return {"efs_moments": n_pairs_per_atom * p1, "efs_contract": float(contraction_flops),
             "efs_forces": n_pairs_per_atom * (p3 + (p4 if with_rows else 0))}
 
@@ -341,7 +345,8 @@ def main():
     prec = a.precision
     r = results[prec]
     m = info["m_full"]
-    fl = efs_flops_per_atom(pairs_per_atom, info["n_comp"], info["n_rad"], info["contraction_flops"], True)
+    fl = efs_flops_per_atom(pairs_per_atom, info["n_comp"], info["n_rad"], info["contraction_flops"], True,
+                            fused_rows=prec == "fp64")
     if r["kernels"]["efs_contract"]["launches"] == 0:   # four lanes: moments and contraction in one launch
         fl = {"efs_moments_contract": fl["efs_moments"] + fl["efs_contract"], "efs_forces": fl["efs_forces"]}
     per_kernel = {}
