@@ -281,6 +281,8 @@ void evaluate(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, int p
     a.n_lin = m->basis.n_lin();
     a.site_e = want_e ? site : nullptr;
     a.gbuf = gbuf;
+    a.rev = nb->rev.as<int32_t>();
+    a.F = o.forces;
     a.virial = virial;
     a.brow = brow;
     a.ldn = n;

@@ -490,9 +490,13 @@ __device__ inline void load_dm(const EfsArgs &a, const AtomCtx &c, int sub, T (&
 // ---- kernel 3: pair gradients and virial; LANES per atom ------------------
 // g_ij = dE_i/dr_ij = sum_mu [f_mu'(r) P_mu r_ij / r + f_mu(r) grad P_mu] with
 // P_mu = sum_nu dE/dM_{mu,nu} (r_ij)^{(x)nu} (the moment tensors contracted
-// with dE/dM), written per pair (G: gradients wanted, decided at compile time
-// so that the stores in the pair loop are unconditional); virial
-// S_ab = -sum_j g_a r_b per atom.
+// with dE/dM); virial S_ab = -sum_j g_a r_b per atom.  G (gradients wanted,
+// decided at compile time so that the stores in the pair loop are
+// unconditional): the force's own part F_i = sum_j g_ij (FP64, lanes summed
+// in a fixed order) is written per atom, and each g_ij is stored at the slot
+// of the reverse pair (j, i) -- the gather then subtracts, for every atom,
+// the gradients its neighbors hold of it as one contiguous run of its own
+// slots, instead of following the reverse index pair by pair.
 //
 // R > 0 (FP64 only): the rest of the b row in the same pass (kernel 4's
 // work, Sec. II.C) -- R = 2 (FULL) the radial-coefficient part
@@ -525,7 +529,9 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
     T vir[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) vir[k] = T(0);
+    double fo[3] = {0.0, 0.0, 0.0};   // sum_j g_ij of this lane's pairs
     T *gout = static_cast<T *>(a.gbuf);
+    const int32_t *rslot = a.rev + c.atom * (int64_t)a.max_nbrs;
     int gstart = 0;
     for (int t = 0; t < nt; ++t) {
         const int tc = tcount(a, c, t);
@@ -539,16 +545,20 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
         // gradient stores of the pair before in flight
         const int p0 = gstart + sub < a.max_nbrs ? gstart + sub : a.max_nbrs - 1;
         double nx = c.rp[3 * p0], ny = c.rp[3 * p0 + 1], nz = c.rp[3 * p0 + 2];
+        // the reverse slot of the next pair likewise (its store waits for it)
+        int nrv = G ? rslot[p0] : 0;
         // waited for here, once, so that the loop head does not wait for
         // every outstanding access (the stores included) on each pair
-        __asm__ volatile("" ::"v"(nx), "v"(ny), "v"(nz));
+        __asm__ volatile("" ::"v"(nx), "v"(ny), "v"(nz), "v"(nrv));
         for (int q = sub; q < tc; q += K) {
             const int p = gstart + q;
             const T x = T(nx), y = T(ny), z = T(nz);
+            const int rv = nrv;
             const int pn = q + K < tc ? p + K : p;
             nx = c.rp[3 * pn];
             ny = c.rp[3 * pn + 1];
             nz = c.rp[3 * pn + 2];
+            if constexpr (G) nrv = rslot[pn];
             const T r = sqrt(x * x + y * y + z * z);
             T g0 = T(0), g1 = T(0), g2 = T(0);
             if (r < rc) {
@@ -618,10 +628,13 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
                 vir[6] -= g2 * x; vir[7] -= g2 * y; vir[8] -= g2 * z;
             }
             if constexpr (G) {
-                const int64_t s3 = (c.atom * (int64_t)a.max_nbrs + p) * 3;
+                const int64_t s3 = (int64_t)rv * 3;   // the reverse pair's slot
                 gout[s3] = g0;
                 gout[s3 + 1] = g1;
                 gout[s3 + 2] = g2;
+                fo[0] += double(g0);
+                fo[1] += double(g1);
+                fo[2] += double(g2);
             }
         }
         if constexpr (R == 2) {
@@ -651,6 +664,15 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
             }
             for (int k = a.m + sub; k < a.ldb; k += K) brow[k * ldn] = 0.0;
         }
+    }
+    if constexpr (G) {
+#pragma unroll
+        for (int o = K / 2; o > 0; o >>= 1)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) fo[d] += __shfl_xor(fo[d], o, 64);
+        if (c.live && sub == 0)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) a.F[c.atom * 3 + d] = fo[d];
     }
     constexpr int NV = (9 + K - 1) / K * K;
     T vp[NV];

@@ -186,7 +186,7 @@ struct CfgSums {
 struct GatherArgs {
     int64_t n = 0;
     int nt = 0, maxn = 0;
-    const int32_t *tcnt = nullptr, *rev = nullptr;
+    const int32_t *tcnt = nullptr;
     const void *g = nullptr;
     int precision = 0;
     double *F = nullptr;

@@ -28,7 +28,9 @@ struct EfsArgs {
     int n_lin;
     // outputs (nullable)
     double *site_e;           // [n_atoms]
-    void *gbuf;               // [N*maxn*3] T  (pair gradients dV_i/dr_ij)
+    void *gbuf;               // [N*maxn*3] T: pair gradient dV_i/dr_ij stored at the reverse pair's slot
+    const int32_t *rev;       // [N*maxn] the reverse pair's slot (with gbuf)
+    double *F;                // [N*3] with gbuf: sum_j dV_i/dr_ij per atom (the gather subtracts the rest)
     double *virial;           // [n_atoms*9]
     double *brow;             // rows b_i, FP64, column-major: entry (i, k) at brow[k * ldn + i]
     int64_t ldn;              // column stride of brow (>= n_atoms)

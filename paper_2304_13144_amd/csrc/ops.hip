@@ -20,14 +20,17 @@ __global__ void zero_kernel(uint32_t *p, size_t n_words) {
 
 // F_l = sum_{p in list(l)} (g_p - g_rev(p)): the first sum is -dV_l/dx_l, the
 // second collects dV_i/dx_l over every neighborhood i that holds l (or an
-// image of l).  FG_LANES lanes per atom, a fixed shuffle tree at the end, no
-// atomics: results are bitwise reproducible.  A block holds SUM_CHUNK atoms;
-// with `part` it also writes that chunk's partial energy / virial sums.
+// image of l).  The pair kernel wrote the first sum per atom into F and each
+// g_p at the slot rev(p), so the second is the sum over l's own slots:
+// F_l -= sum_{p in list(l)} h_p.  FG_LANES lanes per atom, a fixed shuffle
+// tree at the end, no atomics: results are bitwise reproducible.  A block
+// holds SUM_CHUNK atoms; with `part` it also writes that chunk's partial
+// energy / virial sums.
 constexpr int FG_LANES = 8;
 static_assert(256 / FG_LANES == SUM_CHUNK, "one force_gather block per sum chunk");
 template <typename T>
-__device__ inline void gather_block(int64_t blk, int64_t n, int nt, int maxn, const int32_t *tcnt,
-                                    const int32_t *rev, const T *g, double *F) {
+__device__ inline void gather_block(int64_t blk, int64_t n, int nt, int maxn, const int32_t *tcnt, const T *h,
+                                    double *F) {
     const int sub = threadIdx.x % FG_LANES;
     const int64_t i = (blk * 256 + threadIdx.x) / FG_LANES;   // blocks of 256 threads
     const bool live = i < n;
@@ -37,38 +40,25 @@ __device__ inline void gather_block(int64_t blk, int64_t n, int nt, int maxn, co
     for (int t = 0; t < MAX_TYPES; ++t) tot += t < nt ? tcnt[ic * nt + t] : 0;
     if (!live) tot = 0;
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    // FG_DEPTH pairs per lane at a time, every load unconditional so that the
-    // reverse indices, then the gradients, are all in flight together (the
-    // loads form a dependent chain): a slot past the count reads its own
-    // (in-bounds) entry instead of a stale index and adds nothing.
+    // FG_DEPTH pairs per lane at a time, every load unconditional so that they
+    // are all in flight together: a slot past the count reads the atom's
+    // last slot (in bounds) and adds nothing
     constexpr int FG_DEPTH = 4;
+    const T *hi = h + ic * (int64_t)maxn * 3;
     for (int p0 = sub; p0 < tot; p0 += FG_DEPTH * FG_LANES) {
-        int64_t sl[FG_DEPTH], q[FG_DEPTH];
-        int r[FG_DEPTH];
+        T hq[FG_DEPTH][3];
 #pragma unroll
         for (int d = 0; d < FG_DEPTH; ++d) {
-            const int p = p0 + d * FG_LANES;
-            sl[d] = ic * maxn + (p < maxn ? p : maxn - 1);
-            r[d] = rev[sl[d]];
+            const int p = p0 + d * FG_LANES < maxn ? p0 + d * FG_LANES : maxn - 1;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) hq[d][k] = hi[3 * p + k];
         }
-        static_assert(FG_DEPTH == 4, "the asm below names four loads");
-        __asm__ volatile("" ::"v"(r[0]), "v"(r[1]), "v"(r[2]), "v"(r[3]));   // keeps them unconditional
-#pragma unroll
-        for (int d = 0; d < FG_DEPTH; ++d) q[d] = p0 + d * FG_LANES < tot ? (int64_t)r[d] : sl[d];
-        T gs[FG_DEPTH][3], gq[FG_DEPTH][3];
-#pragma unroll
-        for (int d = 0; d < FG_DEPTH; ++d)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                gs[d][k] = g[3 * sl[d] + k];
-                gq[d][k] = g[3 * q[d] + k];
-            }
 #pragma unroll
         for (int d = 0; d < FG_DEPTH; ++d) {
             if (p0 + d * FG_LANES < tot) {
-                fx += double(gs[d][0]) - double(gq[d][0]);
-                fy += double(gs[d][1]) - double(gq[d][1]);
-                fz += double(gs[d][2]) - double(gq[d][2]);
+                fx += double(hq[d][0]);
+                fy += double(hq[d][1]);
+                fz += double(hq[d][2]);
             }
         }
     }
@@ -79,17 +69,16 @@ __device__ inline void gather_block(int64_t blk, int64_t n, int nt, int maxn, co
         fz += __shfl_xor(fz, o, 64);
     }
     if (live && sub == 0) {
-        F[3 * i] = fx;
-        F[3 * i + 1] = fy;
-        F[3 * i + 2] = fz;
+        F[3 * i] -= fx;
+        F[3 * i + 1] -= fy;
+        F[3 * i + 2] -= fz;
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void force_gather(int64_t n, int nt, int maxn, const int32_t *tcnt,
-                                                    const int32_t *rev, const T *g, double *F, const double *site_e,
-                                                    const double *vir, double *part) {
-    gather_block<T>(blockIdx.x, n, nt, maxn, tcnt, rev, g, F);
+__global__ __launch_bounds__(256) void force_gather(int64_t n, int nt, int maxn, const int32_t *tcnt, const T *g,
+                                                    double *F, const double *site_e, const double *vir, double *part) {
+    gather_block<T>(blockIdx.x, n, nt, maxn, tcnt, g, F);
     if (part) chunk_partials(blockIdx.x, n, site_e, vir, part);   // uniform branch
 }
 
@@ -452,9 +441,9 @@ __global__ __launch_bounds__(256) void select_write(const double *g, int64_t n, 
     const int64_t b = (int64_t)blockIdx.x - n_cfg;
     if (b < ga.blocks) {
         if (ga.precision == MTP_FP64)
-            gather_block<double>(b, ga.n, ga.nt, ga.maxn, ga.tcnt, ga.rev, static_cast<const double *>(ga.g), ga.F);
+            gather_block<double>(b, ga.n, ga.nt, ga.maxn, ga.tcnt, static_cast<const double *>(ga.g), ga.F);
         else
-            gather_block<float>(b, ga.n, ga.nt, ga.maxn, ga.tcnt, ga.rev, static_cast<const float *>(ga.g), ga.F);
+            gather_block<float>(b, ga.n, ga.nt, ga.maxn, ga.tcnt, static_cast<const float *>(ga.g), ga.F);
         return;
     }
     const int64_t nb = (n + GRADE_ROWS - 1) / GRADE_ROWS;
@@ -538,12 +527,10 @@ void launch_force_gather(const mtp_nbrs *nb, const void *gbuf, int precision, do
     const dim3 grid((unsigned)((n * FG_LANES + 255) / 256));
     if (precision == MTP_FP64)
         hipLaunchKernelGGL(force_gather<double>, grid, dim3(256), 0, st, n, nb->n_types, nb->max_nbrs,
-                           nb->tcnt.as<int32_t>(), nb->rev.as<int32_t>(), static_cast<const double *>(gbuf), forces,
-                           site_e, virial, part);
+                           nb->tcnt.as<int32_t>(), static_cast<const double *>(gbuf), forces, site_e, virial, part);
     else
         hipLaunchKernelGGL(force_gather<float>, grid, dim3(256), 0, st, n, nb->n_types, nb->max_nbrs,
-                           nb->tcnt.as<int32_t>(), nb->rev.as<int32_t>(), static_cast<const float *>(gbuf), forces,
-                           site_e, virial, part);
+                           nb->tcnt.as<int32_t>(), static_cast<const float *>(gbuf), forces, site_e, virial, part);
 }
 
 size_t cfg_partials_bytes(int64_t n) {
@@ -662,7 +649,6 @@ GatherArgs gather_args(const mtp_nbrs *nb, const void *gbuf, int precision, doub
     ga.nt = nb->n_types;
     ga.maxn = nb->max_nbrs;
     ga.tcnt = nb->tcnt.as<int32_t>();
-    ga.rev = nb->rev.as<int32_t>();
     ga.g = gbuf;
     ga.precision = precision;
     ga.F = forces;
