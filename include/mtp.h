@@ -218,6 +218,19 @@ int mtp_energy_forces_stress_noalloc(const mtp_model *m, const mtp_system *s, co
 int mtp_grade(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
               double *gamma, int32_t *argmax, void *b_rows, void *stream);
 
+/* Grades of rows the caller holds (Sec. II.D): gamma_i = max_p |(b_i A^-1)_p|
+ * and the argmax p (lowest on ties) for n rows b_i against the active set of
+ * mode g (MTP_GRADE_FULL or MTP_GRADE_LINEAR), by the kernels and the tuned
+ * kernel form of the fused evaluation.  rows (device, FP64, read only): the
+ * evaluation's own column-major layout, entry (i, k) at rows[k * ld + i] with
+ * ld >= n, for k < ldb, where ldb >= m rounded up to a multiple of 32
+ * (MTP_FP64) or 64 (MTP_MIXED, whose int8 product steps k by 64) and the
+ * columns m <= k < ldb hold zeros.  gamma [n] FP64 and argmax [n] int32 (or
+ * NULL) on the device.  MTP_E_INVAL for a bad mode or precision, ld < n, a
+ * short ldb or a mode without an active set. */
+int mtp_grade_rows(const mtp_model *m, mtp_precision p, mtp_grade_mode g, const double *rows, int64_t n, int64_t ld,
+                   int32_t ldb, double *gamma, int32_t *argmax, void *stream);
+
 /* Configuration grades (Sec. II.C): gamma(cfg) = max_p |(b(cfg) A^-1)_p|
  * with b(cfg) = sum of the rows b_i of the configuration's atoms (FP64 rows
  * and sums in both precisions) and A the active

@@ -20,7 +20,7 @@ STATUS = {0: "MTP_OK", -1: "MTP_E_INVAL", -2: "MTP_E_IO", -3: "MTP_E_PARSE", -4:
 # every symbol declared in include/mtp.h
 EXPORTS = ("mtp_load", "mtp_save", "mtp_create", "mtp_free", "mtp_info", "mtp_set_params", "mtp_get_params", "mtp_kept_columns",
            "mtp_set_active_set", "mtp_get_active_set", "mtp_nbrs_create", "mtp_nbrs_free", "mtp_build_neighbors",
-           "mtp_nbrs_status", "mtp_nbrs_export", "mtp_energy_forces_stress", "mtp_energy_forces_stress_noalloc", "mtp_grade", "mtp_grade_cfg", "mtp_evaluate",
+           "mtp_nbrs_status", "mtp_nbrs_export", "mtp_energy_forces_stress", "mtp_energy_forces_stress_noalloc", "mtp_grade", "mtp_grade_rows", "mtp_grade_cfg", "mtp_evaluate",
            "mtp_evaluate_select", "mtp_b_rows", "mtp_select", "mtp_maxvol_update", "mtp_cut_neighborhood", "mtp_md_run", "mtp_relax_fire", "mtp_fit_bfgs", "mtp_efs_backward", "mtp_basis_describe",
            "mtp_compiled_levels", "mtp_last_error", "mtp_profile_enable", "mtp_profile_read", "mtp_tune", "mtp_mfma_rate")
 
@@ -82,6 +82,7 @@ def lib():
         "mtp_grade": [P, ctypes.POINTER(System), P, ctypes.c_int, ctypes.c_int, P, P, P, P],
         "mtp_evaluate": [P, ctypes.POINTER(System), P, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P],
         "mtp_grade_cfg": [P, ctypes.POINTER(System), P, ctypes.c_int, ctypes.c_int, P, P, P, P],
+        "mtp_grade_rows": [P, ctypes.c_int, ctypes.c_int, P, I64, I64, I32, P, P, P],
         "mtp_evaluate_select": [P, ctypes.POINTER(System), P, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, D, P, I32,
                                 P, P],
         "mtp_b_rows": [P, ctypes.POINTER(System), P, ctypes.c_int, P, I32, P, P],

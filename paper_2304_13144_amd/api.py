@@ -227,6 +227,26 @@ def grade(model, batch, nbrs, precision="fp64", mode="full", rows=False):
     return {"gamma": g, "argmax": am, "rows": b}
 
 
+def row_stride(m, precision="fp64"):
+    """Columns of the column-major row layout the grade kernels read: m
+    padded with zeros to a multiple of 32 (FP64) or 64 (mixed)."""
+    q = 32 if precision == "fp64" else 64
+    return (m + q - 1) // q * q
+
+
+def grade_rows(model, rows_cm, precision="fp64", mode="full", out=None):
+    """Grades of rows the caller holds: rows_cm is a contiguous FP64 device
+    tensor [ldb, n] (column k of every row at rows_cm[k]; ldb >=
+    row_stride(m), zeros past m), as the evaluation lays them out; `out`
+    reuses a previous call's gamma / argmax tensors."""
+    ldb, n = rows_cm.shape
+    g = out["gamma"] if out else _out(n, torch.float64, rows_cm.device)
+    am = out["argmax"] if out else _out(n, torch.int32, rows_cm.device)
+    check(_lib.lib().mtp_grade_rows(model._h, _prec(precision), _mode(mode), _p(rows_cm), n, n, ldb, _p(g), _p(am),
+                                    _stream()))
+    return {"gamma": g, "argmax": am}
+
+
 def grade_cfg(model, batch, nbrs, precision="fp64", mode="full_cfg", rows=False):
     """Configuration grades (mode "full_cfg" / "linear_cfg"): gamma [n_cfg],
     argmax [n_cfg] and, with rows=True, b(cfg) [n_cfg, m] FP64."""
@@ -488,7 +508,8 @@ def compiled_levels():
 
 __all__ = ["Model", "Batch", "Neighbors", "energy_forces_stress", "energy_forces_stress_noalloc", "grade", "grade_cfg", "cfg_rows", "evaluate",
            "b_rows", "select", "cut_neighborhood", "md_run", "relax_fire", "fit_bfgs",
-           "maxvol_update", "efs_backward", "MTPEnergy", "tune", "CapturedStep", "basis_describe", "compiled_levels", "mfma_rate", "MtpError"]
+           "maxvol_update", "efs_backward", "MTPEnergy", "tune", "CapturedStep", "basis_describe", "compiled_levels", "mfma_rate", "MtpError",
+           "grade_rows", "row_stride"]
 
 
 class CapturedStep:

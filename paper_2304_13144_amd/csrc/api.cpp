@@ -704,6 +704,26 @@ int mtp_grade(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_p
     API_END
 }
 
+int mtp_grade_rows(const mtp_model *m, mtp_precision p, mtp_grade_mode g, const double *rows, int64_t n, int64_t ld,
+                   int32_t ldb, double *gamma, int32_t *argmax, void *stream) {
+    API_BEGIN
+    MTP_CHECK(m && gamma && (rows || n == 0), MTP_E_INVAL, "NULL argument");
+    MTP_CHECK(p == MTP_FP64 || p == MTP_MIXED, MTP_E_INVAL, "bad precision");
+    MTP_CHECK(g == MTP_GRADE_FULL || g == MTP_GRADE_LINEAR, MTP_E_INVAL, "bad grade mode");
+    MTP_CHECK(n >= 0 && ld >= n, MTP_E_INVAL, "need n >= 0 and ld >= n");
+    MTP_CHECK(m->act[g].valid, MTP_E_INVAL, "no active set for this grade mode");
+    const int mm = m->m_of(g);
+    MTP_CHECK(ldb >= ld_of(mm, p), MTP_E_INVAL, "rows: fewer columns than the padded row length");
+    if (n == 0) return MTP_OK;
+    MTP_HIP(hipSetDevice(m->device));
+    hipStream_t st = S(stream);
+    const int sched = grade_sched_for(m, n, p, g);
+    ProfScope ps("grade", st);
+    launch_grade(m->act[g], p, rows, ldb, ld, n, gamma, argmax, st, 0.0, nullptr, sched);
+    MTP_HIP(hipGetLastError());
+    API_END
+}
+
 int mtp_grade_cfg(const mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precision p, mtp_grade_mode g,
                   double *gamma, int32_t *argmax, double *b_cfg, void *stream) {
     API_BEGIN

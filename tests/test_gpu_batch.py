@@ -180,3 +180,29 @@ def test_fp64_rows_in_the_pair_pass_equal_the_row_blocks(mode, lanes):
     assert np.array_equal(fused["argmax"], sep["argmax"])
     for key in ("forces", "energy", "stress"):
         assert np.array_equal(fused[key], plain[key]), key
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("mode", ["full", "linear"])
+def test_grade_rows_equals_the_evaluation(precision, mode):
+    """mtp_grade_rows on the evaluation's own rows (laid out column-major and
+    zero-padded as the evaluation does) runs the same kernel form: the grades
+    and argmax are bitwise those of the fused evaluation.  A row stride short
+    of the padded length is refused."""
+    m = _model16()
+    if mode == "linear":
+        m.set_active_set("linear", active_rows(2, "linear"))
+    b = api.Batch([synth.workload2(reps=(6, 6, 6)).configs[0]])
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    g = api.grade(m, b, nb, precision, mode, rows=True)
+    rows = g["rows"]
+    n, mm = rows.shape
+    ldb = api.row_stride(mm, precision)
+    cm = torch.zeros(ldb, n, dtype=torch.float64, device=rows.device)
+    cm[:mm] = rows.t()
+    out = api.grade_rows(m, cm.contiguous(), precision, mode)
+    torch.cuda.synchronize()
+    assert np.array_equal(out["gamma"].cpu().numpy(), g["gamma"].cpu().numpy())
+    assert np.array_equal(out["argmax"].cpu().numpy(), g["argmax"].cpu().numpy())
+    with pytest.raises(api.MtpError):
+        api.grade_rows(m, cm[: mm // 32 * 32].contiguous(), precision, mode)
