@@ -430,6 +430,10 @@ __global__ __launch_bounds__(512) void grade_f64_kouter(const double *__restrict
     const int lr = lane & 15, lk = lane >> 4;
     const int64_t row0 = (int64_t)blockIdx.x * GF_ROWS + rg * 16;
     const int ntile = (m + 15) / 16;
+    // k steps that reach a column below m: the later ones multiply the rows'
+    // zero padding, and are skipped (m > 32 (NK - 1), so every step up to
+    // 8 (NK - 1) is needed and the test folds away for all but the last few)
+    const int ksn = (m + 3) / 4;
     doublex2 pre[DIST][PER];
     auto fetch = [&](int c) {
 #pragma unroll
@@ -479,9 +483,10 @@ __global__ __launch_bounds__(512) void grade_f64_kouter(const double *__restrict
         const double *b = sB[half][c & 1] + lane;
 #pragma unroll
         for (int s = 0; s < KC; ++s)
+            if (KC * c + s <= 8 * (NK - 1) || KC * c + s < ksn)   // uniform
 #pragma unroll
-            for (int j = 0; j < NK; ++j)
-                acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][s], b[(s * NK + j) * 64], acc[j], 0, 0, 0);
+                for (int j = 0; j < NK; ++j)
+                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][s], b[(s * NK + j) * 64], acc[j], 0, 0, 0);
         if (c + 1 < NCH) {
             stash((c + 1) & 1, c + 1);   // its last readers passed the previous barrier
             if (c + 1 + DIST < NCH) fetch(c + 1 + DIST);
