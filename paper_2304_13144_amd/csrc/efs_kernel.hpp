@@ -531,7 +531,7 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
     for (int k = 0; k < 9; ++k) vir[k] = T(0);
     double fo[3] = {0.0, 0.0, 0.0};   // sum_j g_ij of this lane's pairs
     T *gout = static_cast<T *>(a.gbuf);
-    const int32_t *rslot = a.rev + c.atom * (int64_t)a.max_nbrs;
+    const int32_t *rslot = G ? a.rev + c.atom * (int64_t)a.max_nbrs : nullptr;   // set only with gradients
     int gstart = 0;
     for (int t = 0; t < nt; ++t) {
         const int tc = tcount(a, c, t);
