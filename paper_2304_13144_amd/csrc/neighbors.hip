@@ -800,7 +800,10 @@ __global__ __launch_bounds__(256) void reverse_pairs(int64_t n, int n_types, int
     for (int t = 0; t < MAX_TYPES; ++t) tot += t < n_types ? tcnt[i * n_types + t] : 0;
     __asm__ volatile("" ::"v"(j), "v"(s), "v"(zi));   // keeps the loads above the branch
     if (p >= tot) return;
-    if (zi < 0 || zi >= n_types) return;
+    if (zi < 0 || zi >= n_types) {   // flagged when the atom was staged; the slot names itself (in bounds)
+        rev[slot] = (int)slot;
+        return;
+    }
     const int want = ((-sx8(s)) & 0xff) | ((-sx8(s >> 8)) & 0xff) << 8 | ((-sx8(s >> 16)) & 0xff) << 16;
     const int orev = (s >> 24) & 0xff;
     // ... then j's counts and both offset-table entries of the opposite bin offset ...

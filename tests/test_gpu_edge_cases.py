@@ -128,3 +128,19 @@ def test_non_finite_position_is_reported(bad):
     with pytest.raises(api.MtpError) as e:
         api.Neighbors().build(m, b, max_nbrs=64)
     assert e.value.status == "MTP_E_INVAL" and "finite" in str(e.value)
+
+
+def test_out_of_range_species_is_reported():
+    """An atom type outside 0..n_types-1 is flagged by the neighbor build
+    (MTP_E_INVAL); the build's kernels keep every index in range meanwhile
+    (the atom is staged as species 0 and its reverse-pair slots name
+    themselves)."""
+    w = synth.workload1()
+    cfg = w.configs[0]
+    types = cfg.types.copy()
+    types[5] = w.n_types + 3
+    m = api.Model.create(w.level, w.n_types, w.r_min, w.r_cut)
+    b = api.Batch([synth.Config(cfg.pos, types, cfg.cell)])
+    with pytest.raises(api.MtpError) as e:
+        api.Neighbors().build(m, b, max_nbrs=64)
+    assert e.value.status == "MTP_E_INVAL" and "type" in str(e.value)
