@@ -156,3 +156,26 @@ def test_grades_at_m_1114_match_oracle(w24, precision):
     tol = 1e-10 if precision == "fp64" else 1e-5
     assert np.all(np.abs(g - g_or) <= tol * np.maximum(1.0, g_or))
     assert np.array_equal(am, am_or)
+
+
+def test_grade_rows_at_m_1114_equals_the_evaluation(w24):
+    """mtp_grade_rows at level 24 (m = 1114, rows staged through LDS): the
+    evaluation's own rows, laid out column-major with zero padding to a
+    multiple of 32 columns, grade bitwise as the evaluation does."""
+    import torch
+    w, pot, theta, m = w24
+    mm = m.m("full")
+    rng = np.random.default_rng(1115)
+    A = np.eye(mm) * 4.0 + rng.normal(size=(mm, mm)) / np.sqrt(mm)
+    m.set_active_set("full", A)
+    c = sorted(w.configs, key=lambda c: c.n)[1]
+    b = api.Batch([c])
+    nb = api.Neighbors().build(m, b, max_nbrs=64)
+    g = api.grade(m, b, nb, "fp64", "full", rows=True)
+    rows = g["rows"]
+    cm = torch.zeros(api.row_stride(mm, "fp64"), c.n, dtype=torch.float64, device=rows.device)
+    cm[:mm] = rows.t()
+    out = api.grade_rows(m, cm.contiguous(), "fp64", "full")
+    torch.cuda.synchronize()
+    assert np.array_equal(_np(out["gamma"]), _np(g["gamma"]))
+    assert np.array_equal(_np(out["argmax"]), _np(g["argmax"]))

@@ -59,3 +59,11 @@ def test_compiled_levels_cover_workloads():
     lv = api.compiled_levels()
     for L in (8, 16):
         assert L in lv
+
+
+def test_row_stride_pads_to_the_grade_step():
+    """The rows' column count the grade kernels read: m padded to a multiple
+    of 32 (FP64 k chunks) or 64 (the int8 product's k step)."""
+    from paper_2304_13144_amd import api
+    assert [api.row_stride(m, "fp64") for m in (1, 32, 33, 212, 1114)] == [32, 32, 64, 224, 1120]
+    assert [api.row_stride(m, "mixed") for m in (1, 64, 65, 212)] == [64, 64, 128, 256]
