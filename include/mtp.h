@@ -383,7 +383,8 @@ int mtp_profile_read(const char *kernel, double *total_ms /* host */, int64_t *l
  * precision and size class (floor(log2 n_atoms)) and returns it in *lanes
  * (host) as 16 x (moments / contraction lanes) + (pair-gradient lanes).
  * Then, when the grade mode has an active set, it times the kernel forms of
- * the grade product the same way under the chosen lanes -- 1: FP64 MFMA with
+ * the grade product (each form's launch alone, ten at a time, on the rows
+ * the evaluations left, in five interleaved rounds) -- 1: FP64 MFMA with
  * each wavefront's rows in registers (m <= 288); 2: FP64 MFMA with the rows
  * staged through LDS (any m); 3: the int8 slice product (MTP_MIXED, m <=
  * 320); 4: as 1 in blocks of 32 rows, two blocks per CU (m <= 288); 5: FP64

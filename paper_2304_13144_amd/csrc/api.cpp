@@ -1377,23 +1377,32 @@ int mtp_tune(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precisio
     }
     m->force_lanes = 0;
     m->tuned_lanes[p == MTP_FP64 ? 0 : 1][size_bucket(n)] = best;
-    // the grade's kernel form, timed the same way under the chosen lanes
+    // the grade's kernel form: each form's launch alone, on the rows the
+    // evaluations above left in the model's row buffer, with the
+    // preselection count the evaluation asks of it (the forms differ by about
+    // a microsecond, within the spread of whole evaluations)
     int gbest = GRADE_AUTO;
     if (o.gamma) {
         std::vector<int> cand;
         for (int sc : {GRADE_F64_REG, GRADE_F64_LDS, GRADE_I8, GRADE_F64_PAIR, GRADE_F64_KOUTER, GRADE_F64_KOUTER2})
             if (grade_sched_valid(m->act[g], p, sc)) cand.push_back(sc);
         std::vector<float> gmin(cand.size());
+        const int ldb = ld_of(m->m_of(g), p);
+        const double *rows = m->brow.as<double>();
+        int cr = GRADE_ROWS;   // the finest preselection count among the forms
+        for (int sc : cand) cr = std::min(cr, grade_count_rows(m->act[g], p, sc));
+        DevBuf blk;
+        blk.ensure(sizeof(int32_t) * (size_t)((n + cr - 1) / cr + 1));
+        constexpr int GREPS = 10;
         try {
-            for (int sc : cand) {
-                m->force_grade = sc;
-                evaluate(m, s, nb, p, o, st);
-            }
+            for (int sc : cand)
+                launch_grade(m->act[g], p, rows, ldb, n, n, o.gamma, nullptr, st, 2.0, blk.as<int32_t>(), sc);
             for (int rd = 0; rd < ROUNDS; ++rd)
                 for (size_t k = 0; k < cand.size(); ++k) {
-                    m->force_grade = cand[k];
                     MTP_HIP(hipEventRecord(e0, st));
-                    for (int r = 0; r < REPS; ++r) evaluate(m, s, nb, p, o, st);
+                    for (int r = 0; r < GREPS; ++r)
+                        launch_grade(m->act[g], p, rows, ldb, n, n, o.gamma, nullptr, st, 2.0, blk.as<int32_t>(),
+                                     cand[k]);
                     MTP_HIP(hipEventRecord(e1, st));
                     MTP_HIP(hipEventSynchronize(e1));
                     float ms = 0.f;
@@ -1401,12 +1410,10 @@ int mtp_tune(mtp_model *m, const mtp_system *s, const mtp_nbrs *nb, mtp_precisio
                     gmin[k] = rd == 0 ? ms : std::min(gmin[k], ms);
                 }
         } catch (...) {
-            m->force_grade = 0;
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             throw;
         }
-        m->force_grade = 0;
         size_t kb = 0;
         for (size_t k = 1; k < cand.size(); ++k)
             if (gmin[k] < gmin[kb]) kb = k;
