@@ -42,8 +42,10 @@ __device__ inline void gather_block(int64_t blk, int64_t n, int nt, int maxn, co
     double fx = 0.0, fy = 0.0, fz = 0.0;
     // FG_DEPTH pairs per lane at a time, every load unconditional so that they
     // are all in flight together: a slot past the count reads the atom's
-    // last slot (in bounds) and adds nothing
-    constexpr int FG_DEPTH = 4;
+    // last slot (in bounds) and adds nothing.  FG_LANES x FG_DEPTH = 40 pairs
+    // in one round covers a dense crystal's neighborhood at R_cut = 5 A
+    // (33 pairs) without a second memory round
+    constexpr int FG_DEPTH = 5;
     const T *hi = h + ic * (int64_t)maxn * 3;
     for (int p0 = sub; p0 < tot; p0 += FG_DEPTH * FG_LANES) {
         T hq[FG_DEPTH][3];
