@@ -29,6 +29,13 @@ HIP_FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wno-unuse
              # no packed FP32 instructions anywhere in the device code
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", CSRC, "-I", GEN]
+# units compiled with the machine scheduler's ILP strategy: the level-16 FP64
+# moments / contraction kernel runs one wavefront per SIMD and waits on LDS
+# results; scheduled for ILP it measured 21.4 -> 20.6 us per launch on the
+# 16,384-atom alloy, while the pair pass measured slower under it (29.3 -> 32.3
+# us) and keeps the default scheduler in a unit of its own
+ILP_UNITS = ("efs_level16_f64_mc.hip",)
+ILP_FLAGS = ["-mllvm", "--amdgpu-sched-strategy=max-ilp"]
 HOST_SOURCES = ["api.cpp", "basis.cpp", "prof.cpp"]
 # what the generated per-level units include (besides their level's program)
 KERNEL_HEADERS = ["efs_kernel.hpp", "backward_kernel.hpp", "kernel_args.hpp", "device_util.hpp"]
@@ -76,8 +83,12 @@ def generate(levels):
     for L in levels:   # units per (level, arithmetic type, forward / backward): they compile in parallel
         for T, tag in (("double", "f64"), ("float", "f32")):
             if L not in staged:
-                for kind, macro in (("efs", "MTP_EFS_LEVEL_T"), ("bwd", "MTP_BWD_LEVEL_T")):
-                    unit(f"{kind}_level{L}_{tag}.hip",
+                # moments / contraction and the pair pass in units of their own
+                # (ILP_UNITS compiles some of them differently), then the backward
+                for name, macro in ((f"efs_level{L}_{tag}_mc", "MTP_EFS_MC_LEVEL_T"),
+                                    (f"efs_level{L}_{tag}_fr", "MTP_EFS_FR_LEVEL_T"),
+                                    (f"bwd_level{L}_{tag}", "MTP_BWD_LEVEL_T")):
+                    unit(f"{name}.hip",
                          f'#include "efs_kernel.hpp"\n#include "backward_kernel.hpp"\nnamespace mtp {{\n'
                          f'#include "mtp_level{L}.inc"\n{macro}({L}, {T})\n}}  // namespace mtp\n')
                 continue
@@ -175,7 +186,8 @@ def build(levels=DEFAULT_LEVELS, jobs=None, verbose=True, force=True):
         else:
             dm = host_mtime
         if force or _stale(src, obj, dm):
-            jobs_list.append([HIPCC] + HIP_FLAGS + ["-c", src, "-o", obj])
+            extra = ILP_FLAGS if os.path.basename(src) in ILP_UNITS else []
+            jobs_list.append([HIPCC] + HIP_FLAGS + extra + ["-c", src, "-o", obj])
     n = jobs or min(8, os.cpu_count() or 4)
     # longest units first (the backward units of the highest levels)
     jobs_list.sort(key=lambda c: ("bwd_level" not in c[-3], -int(''.join(ch for ch in os.path.basename(c[-3]) if ch.isdigit()) or 0)))

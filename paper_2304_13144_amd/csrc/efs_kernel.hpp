@@ -856,8 +856,6 @@ template <int L, typename TF, typename TD> int launch_fr_level_t(const EfsArgs &
 // time): the moments / contraction in TT (rows only when TT is FP64), the
 // pair gradients in TT with dE/dM in TT, and for TT = float also with dE/dM
 // in FP64 (the mixed form with FP64 rows)
-#define MTP_EFS_LEVEL_T(LEVEL, TT) MTP_EFS_MC_LEVEL_T(LEVEL, TT) MTP_EFS_FR_LEVEL_T(LEVEL, TT)
-
 #define MTP_EFS_MC_LEVEL_T(LEVEL, TT)                                                                    \
     /* moments and contraction, K lanes per neighborhood (K = 4, 8: one launch; K = 2: two) */         \
     template <typename T, int K, bool WB> static void launch_mc##LEVEL(const EfsArgs &a) {               \
