@@ -33,9 +33,7 @@ HIP_FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wno-unuse
 # moments / contraction kernel runs one wavefront per SIMD and waits on LDS
 # results; scheduled for ILP it measured 21.4 -> 20.6 us per launch on the
 # 16,384-atom alloy, while the pair pass measured slower under it (29.3 -> 32.3
-# us) and keeps the default scheduler in a unit of its own; the level-20
-# moments / contraction unit and the level-24 staged program measured slower
-# under it too (not a rule for every level)
+# us) and keeps the default scheduler in a unit of its own
 ILP_UNITS = ("efs_level16_f64_mc.hip",)
 ILP_FLAGS = ["-mllvm", "--amdgpu-sched-strategy=max-ilp"]
 HOST_SOURCES = ["api.cpp", "basis.cpp", "prof.cpp"]
