@@ -298,6 +298,26 @@ __device__ inline void contract_body(const EfsArgs &a, int64_t blk, const MA &M,
     const int64_t slot = blk * 64 + lane;
     const bool live = slot < a.n_atoms;
     const int64_t sl = live ? slot : 0;
+    if constexpr (WB) {
+        // the rows' constant entries, in whole columns of 64 rows: the species
+        // one-hot, then zeros from column nt + NL on (the c part's blocks and
+        // the padding; the pair pass writes the neighborhood's own c block
+        // over them afterwards).  Issued first, so that they drain while the
+        // graph values are computed (no vector memory load follows that
+        // would wait for them)
+        if (live) {
+            const int ntp = a.n_types;
+            const int64_t atom = a.atom_list ? (int64_t)a.atom_list[slot] : slot;
+            int zi = a.type[atom];
+            zi = zi < 0 ? 0 : (zi >= ntp ? ntp - 1 : zi);
+            double *rowp = a.brow + sl;
+            const int c0 = ntp + LV::NLIN;
+            for (int k = wave; k < ntp + a.ldb - c0; k += NW) {
+                const int col = k < ntp ? k : c0 + (k - ntp);
+                rowp[(int64_t)col * a.ldn] = k == zi ? 1.0 : 0.0;
+            }
+        }
+    }
     {
         T g[NG];
         if constexpr (NW == 4) {
@@ -650,7 +670,7 @@ __device__ inline void efs_forces_body(const EfsArgs &a, int64_t blk, T *c_s, T 
         }
         gstart += tc;
     }
-    if constexpr (R > 0) {
+    if constexpr (R > 0 && LV::STAGED) {   // (the single-kernel contraction writes these for the other levels)
         if (brow) {   // species one-hot, zero c blocks of the other central species, zero padding
             for (int k = sub; k < nt; k += K) brow[k * ldn] = k == c.zi ? 1.0 : 0.0;
             if constexpr (R == 2) {
@@ -774,18 +794,22 @@ __device__ inline void efs_rows_body(const EfsArgs &a, int64_t blk, T (&s_dm)[Le
         }
     }
     if (brow) {
-        // species one-hot, zero c blocks of the other central species, zero padding
-        for (int k = sub; k < nt; k += K) brow[k * ldn] = k == c.zi ? 1.0 : 0.0;
-        if (full_rows) {
-            const int nblk = NR * nt * nt * NPOLY;
-            for (int k = sub; k < nblk; k += K) {
-                const int zz = (k / (nt * NPOLY)) % nt;
-                if (zz == c.zi) continue;
-                const int col = s_col[k];
-                if (col >= 0) brow[col * ldn] = 0.0;
+        // species one-hot, zero c blocks of the other central species, zero
+        // padding: written here for the staged levels only (the single-kernel
+        // contraction writes them for the others)
+        if constexpr (Level<L>::STAGED) {
+            for (int k = sub; k < nt; k += K) brow[k * ldn] = k == c.zi ? 1.0 : 0.0;
+            if (full_rows) {
+                const int nblk = NR * nt * nt * NPOLY;
+                for (int k = sub; k < nblk; k += K) {
+                    const int zz = (k / (nt * NPOLY)) % nt;
+                    if (zz == c.zi) continue;
+                    const int col = s_col[k];
+                    if (col >= 0) brow[col * ldn] = 0.0;
+                }
             }
+            for (int k = a.m + sub; k < a.ldb; k += K) brow[k * ldn] = 0.0;
         }
-        for (int k = a.m + sub; k < a.ldb; k += K) brow[k * ldn] = 0.0;
     }
 }
 
